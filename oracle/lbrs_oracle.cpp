@@ -1,0 +1,631 @@
+// LBRS oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, deliberately unoptimised FP64 CPU implementation of the
+// Lattice Boltzmann Relaxation Scheme (LBRS) of Raghurama Rao, Deshmukh and
+// Kotnala, "A Lattice Boltzmann Relaxation Scheme for Inviscid Compressible
+// Flows" (arXiv 1504.07034).  It exists so that the GPU library can be checked
+// against something that a reader can compare with the paper by eye.  Only the
+// test-suite, the smoke check and the CPU-baseline leg of the benchmark may load
+// it.  It shares no source, header, table or helper with the GPU library.
+//
+// Every time step is taken in the paper's order (Sec. II):
+//   moments U = sum_i f_i                      (eq. "moments", "moments_system")
+//   global lattice speed from U                (Sec. II.C lambda choice; Sec. II.D
+//                                               Bouchut bound for D2Q4)
+//   equilibria f_i^eq(U, G(U))                 (eq. "equilibrium", the D1Q2/D1Q3
+//                                               Euler equilibria, the D2Q4 f^eq)
+//   relaxation (1-omega) f + omega f^eq        (discrete LBRS update, Sec. II.A)
+//   exact hopping one node along each link     (same equation, lambda_i dt = dx)
+//   boundary populations                       (Sec. II.E specular wall; the
+//                                               transmissive and periodic sides are
+//                                               readings, not in the paper)
+//
+// Readings of points the paper leaves open (each listed in the design notes):
+//   * the lattice speed is one global value per step: lambda* = max over cells
+//     of the local bound, and the lattice speed is lambda_lat = dx/dt with
+//     dt = min(cfl*dx/lambda*, t_end - t)   (exact hopping needs one speed);
+//   * the 2D bound's garbled "sqrt(2a)" is read as sqrt(2)*a;
+//   * the D1Q3 model uses the same lambda formula as D1Q2;
+//   * 2D Euler: E = p/(rho(gamma-1)) + (u^2+v^2)/2 and the standard fluxes;
+//   * transmissive side: the ghost population equals the nearest interior
+//     post-collision population (index clamped per axis); periodic: wrap;
+//   * the wall sits on a node row (column); its incoming populations are set
+//     after streaming by specular reflection of the outgoing ones, with the
+//     normal momentum component negated (Sec. II.E, upper wall written out
+//     there; the other three sides by the same mirror rule);
+//   * f^0 = f^eq(U0) with the lattice speed lambda*(U0)/cfl (frozen / user
+//     modes: the fixed speed).
+//
+// The core is templated on the scalar so that a forward-mode dual number gives
+// exact directional derivatives (the reference for the adjoint).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#include <limits>
+
+namespace orc {
+
+// ----------------------------------------------------------------- parameters
+enum { D1Q2 = 0, D1Q3 = 1, D2Q4 = 2 };
+enum { FLUX_EULER = 0, FLUX_LINEAR = 1 };
+enum { SIDE_TRANSMISSIVE = 0, SIDE_PERIODIC = 1, SIDE_WALL = 2 };
+enum { LAM_PER_STEP = 0, LAM_FROZEN = 1, LAM_USER = 2 };
+enum { ST_OK = 0, ST_INVAL = -1, ST_NONPHYSICAL = -4 };
+
+// Mirrored field by field in oracle/__init__.py (ctypes).
+struct Problem {
+    int model;        // D1Q2, D1Q3, D2Q4
+    int flux;         // FLUX_EULER or FLUX_LINEAR (scalar test mode)
+    int nx, ny;       // ny = 1 in 1D
+    double x0, x1, y0, y1;
+    double gamma, omega, cfl;
+    int side[4];      // xlo, xhi, ylo, yhi
+    int lam_mode;
+    double lam_user;  // lattice speed for LAM_USER
+    double adv_x, adv_y;  // advection speed for FLUX_LINEAR
+};
+
+// ------------------------------------------------------------ dual numbers
+// Forward-mode AD: value and one directional derivative.
+struct Dual {
+    double v, d;
+    Dual() : v(0), d(0) {}
+    Dual(double a) : v(a), d(0) {}
+    Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+    return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+inline Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+inline Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+inline Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+inline Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+inline Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+inline Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+inline Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+inline Dual sqrt(Dual a) {
+    double s = std::sqrt(a.v);
+    return Dual(s, a.d / (2.0 * s));
+}
+inline Dual pow(Dual a, double e) {
+    double p = std::pow(a.v, e);
+    return Dual(p, e * std::pow(a.v, e - 1.0) * a.d);
+}
+inline double val(double a) { return a; }
+inline double val(const Dual& a) { return a.v; }
+using std::sqrt;
+using std::pow;
+
+// ------------------------------------------------------------ the lattices
+// Sign pattern s_i of each discrete velocity (c_i = lambda * s_i).
+//   D1Q2: Lambda = diag(-lambda, +lambda)                       (Sec. II.A)
+//   D1Q3: Lambda = diag(-lambda, 0, +lambda)                    (Sec. II.C)
+//   D2Q4: Lambda_1 = diag(-,+,+,-) lambda, Lambda_2 = diag(-,-,+,+) lambda
+//                                                               (Sec. II.D)
+inline int nq(int model) { return model == D1Q2 ? 2 : (model == D1Q3 ? 3 : 4); }
+inline int ndim(int model) { return model == D2Q4 ? 2 : 1; }
+inline int sx(int model, int i) {
+    static const int s12[2] = {-1, +1};
+    static const int s13[3] = {-1, 0, +1};
+    static const int s24[4] = {-1, +1, +1, -1};
+    return model == D1Q2 ? s12[i] : (model == D1Q3 ? s13[i] : s24[i]);
+}
+inline int sy(int model, int i) {
+    static const int s24[4] = {-1, -1, +1, +1};
+    return model == D2Q4 ? s24[i] : 0;
+}
+inline int ncomp(const Problem& P) {
+    if (P.flux == FLUX_LINEAR) return 1;
+    return ndim(P.model) == 1 ? 3 : 4;
+}
+
+// --------------------------------------------------------- Euler equations
+// 1D: U = (rho, rho u, rho E), G = (rho u, p + rho u^2, p u + rho u E),
+//     E = p/(rho(gamma-1)) + u^2/2                                (Sec. II.C)
+template <class T>
+void euler_flux_1d(const T* U, double gamma, T* G) {
+    T rho = U[0];
+    T u = U[1] / rho;
+    T E = U[2] / rho;
+    T p = (gamma - 1.0) * rho * (E - 0.5 * (u * u));
+    G[0] = rho * u;
+    G[1] = p + rho * u * u;
+    G[2] = p * u + rho * u * E;
+}
+
+// 2D: U = (rho, rho u, rho v, rho E), E = p/(rho(gamma-1)) + (u^2+v^2)/2,
+//     G1 = (rho u, p + rho u^2, rho u v, p u + rho u E),
+//     G2 = (rho v, rho v u, p + rho v^2, p v + rho v E).
+// The paper only names "the 2D Euler equations" (Sec. II.D); these are the
+// standard gamma-law fluxes.
+template <class T>
+void euler_flux_2d(const T* U, double gamma, T* G1, T* G2) {
+    T rho = U[0];
+    T u = U[1] / rho;
+    T v = U[2] / rho;
+    T E = U[3] / rho;
+    T p = (gamma - 1.0) * rho * (E - 0.5 * (u * u + v * v));
+    G1[0] = rho * u;
+    G1[1] = p + rho * u * u;
+    G1[2] = rho * u * v;
+    G1[3] = p * u + rho * u * E;
+    G2[0] = rho * v;
+    G2[1] = rho * v * u;
+    G2[2] = p + rho * v * v;
+    G2[3] = p * v + rho * v * E;
+}
+
+// Flux vectors of the conservation law being relaxed.  Gy is untouched in 1D.
+template <class T>
+void flux(const Problem& P, const T* U, T* Gx, T* Gy) {
+    if (P.flux == FLUX_LINEAR) {  // scalar test mode: g1 = cx u, g2 = cy u
+        Gx[0] = P.adv_x * U[0];
+        if (ndim(P.model) == 2) Gy[0] = P.adv_y * U[0];
+        return;
+    }
+    if (ndim(P.model) == 1)
+        euler_flux_1d(U, P.gamma, Gx);
+    else
+        euler_flux_2d(U, P.gamma, Gx, Gy);
+}
+
+// Pressure of an Euler state, from E = p/(rho(gamma-1)) + |u|^2/2.
+template <class T>
+T pressure(const Problem& P, const T* U) {
+    T rho = U[0];
+    if (ndim(P.model) == 1) {
+        T u = U[1] / rho, E = U[2] / rho;
+        return (P.gamma - 1.0) * rho * (E - 0.5 * (u * u));
+    }
+    T u = U[1] / rho, v = U[2] / rho, E = U[3] / rho;
+    return (P.gamma - 1.0) * rho * (E - 0.5 * (u * u + v * v));
+}
+
+// Local bound on the wave speeds.
+//  1D: lambda = max(|u - a|, |u|, |u + a|)        (Sec. II.C, Jin-Xin choice)
+//  2D: lambda = max(|u+v|, |u+v +- sqrt(2) a|, |u-v|, |u-v -+ sqrt(2) a|)
+//      (Sec. II.D, Bouchut's condition; "sqrt(2a)" read as sqrt(2)*a)
+//  linear advection: |c| in 1D, |cx| + |cy| in 2D (the sub-characteristic
+//  bound for the scalar D1Q2 model, Sec. II.A, and its D2Q4 analogue).
+inline double local_lambda(const Problem& P, const double* U) {
+    if (P.flux == FLUX_LINEAR)
+        return ndim(P.model) == 1 ? std::fabs(P.adv_x)
+                                  : std::fabs(P.adv_x) + std::fabs(P.adv_y);
+    double rho = U[0];
+    double p = pressure(P, U);
+    double a = std::sqrt(P.gamma * p / rho);
+    if (ndim(P.model) == 1) {
+        double u = U[1] / rho;
+        return std::max(std::max(std::fabs(u - a), std::fabs(u)), std::fabs(u + a));
+    }
+    double u = U[1] / rho, v = U[2] / rho;
+    double r2a = std::sqrt(2.0) * a;
+    double cands[6] = {std::fabs(u + v), std::fabs(u + v + r2a), std::fabs(u + v - r2a),
+                       std::fabs(u - v), std::fabs(u - v - r2a), std::fabs(u - v + r2a)};
+    double m = cands[0];
+    for (int j = 1; j < 6; ++j) m = std::max(m, cands[j]);
+    return m;
+}
+
+// Equilibria of the diagonal relaxation system for one conserved component.
+//  D1Q2: f1 = U/2 - G/(2 lambda),  f2 = U/2 + G/(2 lambda)
+//  D1Q3: f1 = U/3 - G/(2 lambda),  f2 = U/3,  f3 = U/3 + G/(2 lambda)
+//  D2Q4: f_i = U/4 + s_ix G1/(4 lambda) + s_iy G2/(4 lambda)
+// (Sec. II.A "equilibrium", Sec. II.C D1Q2/D1Q3 Euler equilibria, Sec. II.D.)
+template <class T>
+T equilibrium(int model, int i, const T& U, const T& Gx, const T& Gy, double lam) {
+    if (model == D1Q2) return U / 2.0 + sx(model, i) * (Gx / (2.0 * lam));
+    if (model == D1Q3) return U / 3.0 + sx(model, i) * (Gx / (2.0 * lam));
+    return U / 4.0 + sx(model, i) * (Gx / (4.0 * lam)) + sy(model, i) * (Gy / (4.0 * lam));
+}
+
+// Is an Euler state admissible (rho > 0, p > 0, all finite)?
+inline bool physical(const Problem& P, const double* U) {
+    int K = ncomp(P);
+    for (int k = 0; k < K; ++k)
+        if (!std::isfinite(U[k])) return false;
+    if (P.flux == FLUX_LINEAR) return true;
+    if (!(U[0] > 0.0)) return false;
+    double p = pressure(P, U);
+    return p > 0.0 && std::isfinite(p);
+}
+
+// ---------------------------------------------------------- the simulation
+template <class T>
+struct Sim {
+    Problem P;
+    int Q, K, D;
+    long ncell;
+    double dx;
+    std::vector<T> f, fs;  // f[(i*K + k)*ncell + y*nx + x]; fs = post-collision
+    std::vector<T> U;      // U[k*ncell + cell]
+
+    explicit Sim(const Problem& p) : P(p) {
+        Q = nq(P.model);
+        K = ncomp(P);
+        D = ndim(P.model);
+        ncell = (long)P.nx * P.ny;
+        dx = (P.x1 - P.x0) / P.nx;
+        f.assign((size_t)Q * K * ncell, T(0.0));
+        fs.assign((size_t)Q * K * ncell, T(0.0));
+        U.assign((size_t)K * ncell, T(0.0));
+    }
+    T& F(std::vector<T>& a, int i, int k, int x, int y) {
+        return a[((size_t)(i * K + k)) * ncell + (size_t)y * P.nx + x];
+    }
+
+    // U = sum_i f_i in every cell                      (eq. "moments_system")
+    void moments() {
+        for (int k = 0; k < K; ++k)
+            for (long c = 0; c < ncell; ++c) {
+                T s = T(0.0);
+                for (int i = 0; i < Q; ++i) s = s + f[((size_t)(i * K + k)) * ncell + c];
+                U[(size_t)k * ncell + c] = s;
+            }
+    }
+
+    double max_local_lambda() {
+        double m = 0.0;
+        std::vector<double> Uc(K);
+        for (long c = 0; c < ncell; ++c) {
+            for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
+            m = std::max(m, local_lambda(P, Uc.data()));
+        }
+        return m;
+    }
+
+    bool all_physical(long* bad) {
+        std::vector<double> Uc(K);
+        for (long c = 0; c < ncell; ++c) {
+            for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
+            if (!physical(P, Uc.data())) {
+                if (bad) *bad = c;
+                return false;
+            }
+        }
+        return true;
+    }
+
+    // f^0 = f^eq(U0) in every cell (Sec. II.A: the initial data are given to
+    // the populations through their equilibria).
+    void init_equilibrium(const T* U0, double lam) {
+        std::vector<T> Uc(K), Gx(K), Gy(K);
+        for (int y = 0; y < P.ny; ++y)
+            for (int x = 0; x < P.nx; ++x) {
+                long c = (long)y * P.nx + x;
+                for (int k = 0; k < K; ++k) Uc[k] = U0[(size_t)k * ncell + c];
+                flux(P, Uc.data(), Gx.data(), Gy.data());
+                for (int i = 0; i < Q; ++i)
+                    for (int k = 0; k < K; ++k)
+                        F(f, i, k, x, y) = equilibrium(P.model, i, Uc[k], Gx[k], Gy[k], lam);
+            }
+    }
+
+    // Collision: f* = (1 - omega) f + omega f^eq(U), with U from moments().
+    // (Discrete LBRS update with omega = dt/epsilon, Sec. II.A and II.D.)
+    void collide(double lam) {
+        std::vector<T> Uc(K), Gx(K), Gy(K);
+        for (int y = 0; y < P.ny; ++y)
+            for (int x = 0; x < P.nx; ++x) {
+                long c = (long)y * P.nx + x;
+                for (int k = 0; k < K; ++k) Uc[k] = U[(size_t)k * ncell + c];
+                flux(P, Uc.data(), Gx.data(), Gy.data());
+                for (int i = 0; i < Q; ++i)
+                    for (int k = 0; k < K; ++k) {
+                        T feq = equilibrium(P.model, i, Uc[k], Gx[k], Gy[k], lam);
+                        F(fs, i, k, x, y) = (1.0 - P.omega) * F(f, i, k, x, y) + P.omega * feq;
+                    }
+            }
+    }
+
+    // Source index along one axis for a pull from position j - s.  Returns -1
+    // when the source lies beyond a wall (the population is set by reflection).
+    int source(int j, int s, int n, int side_lo, int side_hi) {
+        int src = j - s;
+        if (src >= 0 && src < n) return src;
+        int side = src < 0 ? side_lo : side_hi;
+        if (side == SIDE_PERIODIC) return (src + n) % n;
+        if (side == SIDE_TRANSMISSIVE) return src < 0 ? 0 : n - 1;
+        return -1;  // wall
+    }
+
+    // Streaming with exact hopping: f_i(x + s_i, t + dt) = f*_i(x, t)   (Sec. II.A)
+    // written as a pull f_i^{n+1}(x) = f*_i(x - s_i), then the walls.
+    void stream() {
+        for (int i = 0; i < Q; ++i)
+            for (int y = 0; y < P.ny; ++y)
+                for (int x = 0; x < P.nx; ++x) {
+                    int xs = source(x, sx(P.model, i), P.nx, P.side[0], P.side[1]);
+                    int ys = D == 2 ? source(y, sy(P.model, i), P.ny, P.side[2], P.side[3]) : 0;
+                    for (int k = 0; k < K; ++k)
+                        F(f, i, k, x, y) = (xs < 0 || ys < 0) ? T(0.0) : F(fs, i, k, xs, ys);
+                }
+        apply_walls();
+    }
+
+    // Specular reflection at a wall node row/column (Sec. II.E).  The paper
+    // writes the upper wall: f1 = f4 and f2 = f3 for the mass, x-momentum and
+    // energy components, f1 = -f4 and f2 = -f3 for the y-momentum component.
+    // The other sides follow by the same mirror rule: the incoming population
+    // takes the value of its mirror image with the normal momentum negated.
+    void apply_walls() {
+        if (D != 2) return;
+        // component index of the momentum normal to a y-wall / an x-wall
+        const int ky = 2, kx = 1;
+        if (P.side[3] == SIDE_WALL) {  // upper wall, row ny-1: f1 <- f4, f2 <- f3
+            int y = P.ny - 1;
+            for (int x = 0; x < P.nx; ++x)
+                for (int k = 0; k < K; ++k) {
+                    double sgn = (k == ky) ? -1.0 : 1.0;
+                    F(f, 0, k, x, y) = sgn * F(f, 3, k, x, y);
+                    F(f, 1, k, x, y) = sgn * F(f, 2, k, x, y);
+                }
+        }
+        if (P.side[2] == SIDE_WALL) {  // lower wall, row 0: f4 <- f1, f3 <- f2
+            int y = 0;
+            for (int x = 0; x < P.nx; ++x)
+                for (int k = 0; k < K; ++k) {
+                    double sgn = (k == ky) ? -1.0 : 1.0;
+                    F(f, 3, k, x, y) = sgn * F(f, 0, k, x, y);
+                    F(f, 2, k, x, y) = sgn * F(f, 1, k, x, y);
+                }
+        }
+        if (P.side[0] == SIDE_WALL) {  // left wall, column 0: f2 <- f1, f3 <- f4
+            int x = 0;
+            for (int y = 0; y < P.ny; ++y)
+                for (int k = 0; k < K; ++k) {
+                    double sgn = (k == kx) ? -1.0 : 1.0;
+                    F(f, 1, k, x, y) = sgn * F(f, 0, k, x, y);
+                    F(f, 2, k, x, y) = sgn * F(f, 3, k, x, y);
+                }
+        }
+        if (P.side[1] == SIDE_WALL) {  // right wall, column nx-1: f1 <- f2, f4 <- f3
+            int x = P.nx - 1;
+            for (int y = 0; y < P.ny; ++y)
+                for (int k = 0; k < K; ++k) {
+                    double sgn = (k == kx) ? -1.0 : 1.0;
+                    F(f, 0, k, x, y) = sgn * F(f, 1, k, x, y);
+                    F(f, 3, k, x, y) = sgn * F(f, 2, k, x, y);
+                }
+        }
+    }
+};
+
+int validate(const Problem& P) {
+    if (P.model < D1Q2 || P.model > D2Q4) return ST_INVAL;
+    if (P.flux != FLUX_EULER && P.flux != FLUX_LINEAR) return ST_INVAL;
+    if (P.nx < 3 || P.ny < 1) return ST_INVAL;
+    if (ndim(P.model) == 1 && P.ny != 1) return ST_INVAL;
+    if (ndim(P.model) == 2 && P.ny < 3) return ST_INVAL;
+    if (!(P.omega > 0.0 && P.omega < 2.0)) return ST_INVAL;  // Chapman-Enskog, Sec. II.B
+    if (!(P.x1 > P.x0)) return ST_INVAL;
+    if (ndim(P.model) == 2) {
+        // diagonal hops need dx == dy
+        double dx = (P.x1 - P.x0) / P.nx, dy = (P.y1 - P.y0) / P.ny;
+        if (!(std::fabs(dx - dy) <= 1e-12 * dx)) return ST_INVAL;
+    }
+    for (int s = 0; s < 4; ++s)
+        if (P.side[s] < 0 || P.side[s] > 2) return ST_INVAL;
+    if ((P.side[0] == SIDE_PERIODIC) != (P.side[1] == SIDE_PERIODIC)) return ST_INVAL;
+    if (ndim(P.model) == 2 && (P.side[2] == SIDE_PERIODIC) != (P.side[3] == SIDE_PERIODIC))
+        return ST_INVAL;
+    if (ndim(P.model) == 1 && (P.side[0] == SIDE_WALL || P.side[1] == SIDE_WALL)) return ST_INVAL;
+    if (ndim(P.model) == 2) {  // walls meeting at a corner are not defined
+        bool xw = P.side[0] == SIDE_WALL || P.side[1] == SIDE_WALL;
+        bool yw = P.side[2] == SIDE_WALL || P.side[3] == SIDE_WALL;
+        if (xw && yw) return ST_INVAL;
+    }
+    if (P.lam_mode < LAM_PER_STEP || P.lam_mode > LAM_USER) return ST_INVAL;
+    if (P.lam_mode == LAM_USER && !(P.lam_user > 0.0)) return ST_INVAL;
+    if (P.lam_mode != LAM_USER && !(P.cfl > 0.0 && P.cfl <= 1.0)) return ST_INVAL;
+    return ST_OK;
+}
+
+}  // namespace orc
+
+using namespace orc;
+
+extern "C" {
+
+// Flux vectors of one state.  Gx, Gy: K values each (Gy unused in 1D).
+void orc_flux(const Problem* P, const double* U, double* Gx, double* Gy) {
+    flux(*P, U, Gx, Gy);
+}
+
+// Local wave-speed bound of one state.
+double orc_local_lambda(const Problem* P, const double* U) { return local_lambda(*P, U); }
+
+// Equilibria of one state at lattice speed lam.  feq: Q*K values, [i][k].
+void orc_equilibria(const Problem* P, const double* U, double lam, double* feq) {
+    int Q = nq(P->model), K = ncomp(*P);
+    std::vector<double> Gx(K), Gy(K, 0.0);
+    flux(*P, U, Gx.data(), Gy.data());
+    for (int i = 0; i < Q; ++i)
+        for (int k = 0; k < K; ++k)
+            feq[i * K + k] = equilibrium(P->model, i, U[k], Gx[k], Gy[k], lam);
+}
+
+// Primitive (rho, u, [v,] p) -> conserved (rho, rho u, [rho v,] rho E) per cell,
+// SoA planes of ncell values.  E = p/(rho(gamma-1)) + |u|^2/2.
+void orc_prim_to_cons(const Problem* P, const double* W, double* U) {
+    long n = (long)P->nx * P->ny;
+    int K = ncomp(*P);
+    if (P->flux == FLUX_LINEAR) {
+        std::memcpy(U, W, sizeof(double) * n);
+        return;
+    }
+    for (long c = 0; c < n; ++c) {
+        double rho = W[c];
+        if (K == 3) {
+            double u = W[n + c], p = W[2 * n + c];
+            double E = p / (rho * (P->gamma - 1.0)) + 0.5 * (u * u);
+            U[c] = rho;
+            U[n + c] = rho * u;
+            U[2 * n + c] = rho * E;
+        } else {
+            double u = W[n + c], v = W[2 * n + c], p = W[3 * n + c];
+            double E = p / (rho * (P->gamma - 1.0)) + 0.5 * (u * u + v * v);
+            U[c] = rho;
+            U[n + c] = rho * u;
+            U[2 * n + c] = rho * v;
+            U[3 * n + c] = rho * E;
+        }
+    }
+}
+
+// Lattice speed the run starts from: lambda*(U0)/cfl (per-step and frozen
+// modes) or the user's value.  Returns <= 0 on error.
+double orc_initial_lattice_speed(const Problem* P, const double* U0) {
+    if (validate(*P) != ST_OK) return -1.0;
+    if (P->lam_mode == LAM_USER) return P->lam_user;
+    Sim<double> S(*P);
+    std::memcpy(S.U.data(), U0, sizeof(double) * S.K * S.ncell);
+    if (!S.all_physical(nullptr)) return -1.0;
+    return S.max_local_lambda() / P->cfl;
+}
+
+// Run the scheme from U0 (SoA [K][ny][nx]) until t >= t_end or max_steps steps.
+// Outputs (each optional, may be null):
+//   U_out  [K][ny][nx]  moments of the final populations
+//   f_out  [Q][K][ny][nx] final populations
+//   dt_seq, lam_seq [max_steps]: dt_n and the lattice speed used at step n
+//   nsteps, t_final, fail_step (step whose result was non-physical, or -1)
+// Returns ST_OK, ST_INVAL or ST_NONPHYSICAL.
+int orc_run(const Problem* Pp, const double* U0, double t_end, long max_steps, double* U_out,
+            double* f_out, double* dt_seq, double* lam_seq, long* nsteps, double* t_final,
+            long* fail_step) {
+    const Problem& P = *Pp;
+    if (nsteps) *nsteps = 0;
+    if (t_final) *t_final = 0.0;
+    if (fail_step) *fail_step = -1;
+    int st = validate(P);
+    if (st != ST_OK) return st;
+    Sim<double> S(P);
+    std::memcpy(S.U.data(), U0, sizeof(double) * S.K * S.ncell);
+    if (!S.all_physical(nullptr)) {
+        if (fail_step) *fail_step = 0;
+        return ST_NONPHYSICAL;
+    }
+    double lam_fixed = P.lam_mode == LAM_USER ? P.lam_user : S.max_local_lambda() / P.cfl;
+    S.init_equilibrium(U0, lam_fixed);
+
+    double t = 0.0;
+    long n = 0;
+    int status = ST_OK;
+    while (n < max_steps && t < t_end) {
+        S.moments();
+        double dt, lam;
+        if (P.lam_mode == LAM_PER_STEP) {
+            // Global bound of step n from U^n, then exact hopping lam*dt = dx,
+            // with the last step clipped to land on t_end.
+            double lam_star = S.max_local_lambda();
+            dt = P.cfl * S.dx / lam_star;
+            double rem = t_end - t;
+            bool last = false;
+            if (dt >= rem) {
+                dt = rem;
+                last = true;
+            }
+            lam = S.dx / dt;
+            t = last ? t_end : t + dt;
+        } else {
+            lam = lam_fixed;
+            dt = S.dx / lam;
+            t = t + dt;
+        }
+        if (dt_seq) dt_seq[n] = dt;
+        if (lam_seq) lam_seq[n] = lam;
+        S.collide(lam);
+        S.stream();
+        ++n;
+        S.moments();
+        if (!S.all_physical(nullptr)) {
+            status = ST_NONPHYSICAL;
+            if (fail_step) *fail_step = n;
+            break;
+        }
+    }
+    S.moments();
+    if (U_out) std::memcpy(U_out, S.U.data(), sizeof(double) * S.K * S.ncell);
+    if (f_out) std::memcpy(f_out, S.f.data(), sizeof(double) * S.Q * S.K * S.ncell);
+    if (nsteps) *nsteps = n;
+    if (t_final) *t_final = t;
+    return status;
+}
+
+// One step at a fixed lattice speed lam, from given populations f (no lambda
+// reduction, no time bookkeeping), with its tangent: (f, df) -> (f', df').
+// df / df_out may be null for a plain step.
+int orc_step_fixed(const Problem* Pp, const double* f, const double* df, double lam,
+                   double* f_out, double* df_out) {
+    const Problem& P = *Pp;
+    int st = validate(P);
+    if (st != ST_OK) return st;
+    Sim<Dual> S(P);
+    size_t nf = (size_t)S.Q * S.K * S.ncell;
+    for (size_t j = 0; j < nf; ++j) S.f[j] = Dual(f[j], df ? df[j] : 0.0);
+    S.moments();
+    S.collide(lam);
+    S.stream();
+    for (size_t j = 0; j < nf; ++j) {
+        f_out[j] = S.f[j].v;
+        if (df_out) df_out[j] = S.f[j].d;
+    }
+    return ST_OK;
+}
+
+// Directional derivative of a whole fixed-speed run with respect to the initial
+// primitive state: W0 + eps*dW0 -> (U(T), dU(T)/deps), after nsteps steps at the
+// lattice speed lam (frozen or user mode).  W0/dW0: SoA primitive planes.
+// If isentropic != 0 the pressure plane is ignored and p = rho^gamma/gamma.
+int orc_run_tangent(const Problem* Pp, const double* W0, const double* dW0, int isentropic,
+                    double lam, long nsteps, double* U_out, double* dU_out) {
+    const Problem& P = *Pp;
+    int st = validate(P);
+    if (st != ST_OK) return st;
+    if (P.flux != FLUX_EULER) return ST_INVAL;
+    Sim<Dual> S(P);
+    long n = S.ncell;
+    std::vector<Dual> U0((size_t)S.K * n);
+    for (long c = 0; c < n; ++c) {
+        // conserved variables of the primitive state, differentiated
+        Dual rho(W0[c], dW0[c]);
+        if (S.K == 3) {
+            Dual u(W0[n + c], dW0[n + c]);
+            Dual p = isentropic ? pow(rho, P.gamma) / P.gamma : Dual(W0[2 * n + c], dW0[2 * n + c]);
+            Dual E = p / (rho * (P.gamma - 1.0)) + 0.5 * (u * u);
+            U0[c] = rho;
+            U0[n + c] = rho * u;
+            U0[2 * n + c] = rho * E;
+        } else {
+            Dual u(W0[n + c], dW0[n + c]), v(W0[2 * n + c], dW0[2 * n + c]);
+            Dual p = isentropic ? pow(rho, P.gamma) / P.gamma : Dual(W0[3 * n + c], dW0[3 * n + c]);
+            Dual E = p / (rho * (P.gamma - 1.0)) + 0.5 * (u * u + v * v);
+            U0[c] = rho;
+            U0[n + c] = rho * u;
+            U0[2 * n + c] = rho * v;
+            U0[3 * n + c] = rho * E;
+        }
+    }
+    S.init_equilibrium(U0.data(), lam);
+    for (long s = 0; s < nsteps; ++s) {
+        S.moments();
+        S.collide(lam);
+        S.stream();
+    }
+    S.moments();
+    for (size_t j = 0; j < (size_t)S.K * n; ++j) {
+        U_out[j] = S.U[j].v;
+        dU_out[j] = S.U[j].d;
+    }
+    return ST_OK;
+}
+
+}  // extern "C"

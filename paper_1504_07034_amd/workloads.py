@@ -1,0 +1,216 @@
+"""Seeded synthetic inputs for the LBRS hot path.
+
+This module holds input *data* only: grids, piecewise-constant states, smooth
+pulses and seeded random draws, as primitive variables W = (rho, u, [v,] p) in
+SoA planes ``[K][ny][nx]`` (float64, numpy).  It contains none of the scheme's
+arithmetic (no conversion to conserved variables, no fluxes, no equilibria), so
+both the GPU library's tests and the CPU oracle can start from the same arrays.
+
+Grids are cell-centred: x_j = x0 + (j + 1/2) dx with dx = (x1 - x0)/nx.  With
+an even cell count no centre lies on a mid-domain interface, so no tie-break
+is needed at the discontinuities below.
+
+Model ids: 0 = D1Q2, 1 = D1Q3, 2 = D2Q4.  Side ids: 0 transmissive,
+1 periodic, 2 wall; side order (x-low, x-high, y-low, y-high).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+D1Q2, D1Q3, D2Q4 = 0, 1, 2
+TRANSMISSIVE, PERIODIC, WALL = 0, 1, 2
+
+
+@dataclass
+class Workload:
+    name: str
+    model: int
+    nx: int
+    ny: int
+    domain: tuple            # (x0, x1, y0, y1)
+    W: np.ndarray            # primitive SoA [K][ny][nx]
+    gamma: float = 1.4
+    omega: float = 1.0
+    cfl: float = 0.5
+    sides: tuple = (TRANSMISSIVE,) * 4
+    t_end: float = math.inf
+    steps: int | None = None  # fixed step count (frozen lattice speed runs)
+    meta: dict = field(default_factory=dict)
+
+
+def centres(n: int, a: float, b: float) -> np.ndarray:
+    dx = (b - a) / n
+    return a + (np.arange(n) + 0.5) * dx
+
+
+def _tube(n, domain, xi, left, right, model=D1Q3):
+    x = centres(n, domain[0], domain[1])
+    W = np.empty((3, 1, n))
+    for k in range(3):
+        W[k, 0, :] = np.where(x < xi, left[k], right[k])
+    return W
+
+
+def sod(n: int = 400, model: int = D1Q3, omega: float = 1.0, cfl: float = 0.5,
+        t_end: float = 0.2) -> Workload:
+    """Sod shock tube on [0,1], interface 0.5: (rho,u,p) = (1,0,1) | (0.125,0,0.1)."""
+    W = _tube(n, (0.0, 1.0), 0.5, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    return Workload("sod", model, n, 1, (0.0, 1.0, 0.0, 1.0), W, omega=omega, cfl=cfl,
+                    t_end=t_end, meta={"left": (1.0, 0.0, 1.0), "right": (0.125, 0.0, 0.1),
+                                       "x_interface": 0.5})
+
+
+def sod_dimensional(model: int = D1Q3, omega: float = 1.0, cfl: float = 0.5) -> Workload:
+    """The paper's dimensional shock tube (Sec. III): [-10, 10], 50 cells,
+    (1 kg/m^3, 0, 1e5 Pa) | (0.125, 0, 1e4), t = 0.01 s."""
+    W = _tube(50, (-10.0, 10.0), 0.0, (1.0, 0.0, 1.0e5), (0.125, 0.0, 1.0e4))
+    return Workload("sod_dimensional", model, 50, 1, (-10.0, 10.0, 0.0, 1.0), W, omega=omega,
+                    cfl=cfl, t_end=0.01, meta={"left": (1.0, 0.0, 1.0e5),
+                                               "right": (0.125, 0.0, 1.0e4), "x_interface": 0.0})
+
+
+def steady_contact(n: int = 100, model: int = D1Q3, omega: float = 1.0,
+                   t_end: float = 2.0) -> Workload:
+    """Stationary contact (Sec. III): rho 1.4 | 1.0, u = 0, p = 1 on [0,1], split at 0.5."""
+    W = _tube(n, (0.0, 1.0), 0.5, (1.4, 0.0, 1.0), (1.0, 0.0, 1.0))
+    return Workload("steady_contact", model, n, 1, (0.0, 1.0, 0.0, 1.0), W, omega=omega,
+                    t_end=t_end)
+
+
+def riemann2d(n: int = 4096, states=None, t_end: float = 0.3, omega: float = 1.0,
+              cfl: float = 0.5) -> Workload:
+    """Four-quadrant 2D Riemann problem on [0,1]^2 split at x = y = 0.5.
+
+    Default quadrant states (rho, u, v, p):
+      NE (1.5, 0, 0, 1.5), NW (0.5323, 1.206, 0, 0.3),
+      SW (0.138, 1.206, 1.206, 0.029), SE (0.5323, 0, 1.206, 0.3)."""
+    if states is None:
+        states = {"NE": (1.5, 0.0, 0.0, 1.5), "NW": (0.5323, 1.206, 0.0, 0.3),
+                  "SW": (0.138, 1.206, 1.206, 0.029), "SE": (0.5323, 0.0, 1.206, 0.3)}
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")  # [y][x]
+    east, north = X > 0.5, Y > 0.5
+    W = np.empty((4, n, n))
+    for k in range(4):
+        W[k] = np.where(north, np.where(east, states["NE"][k], states["NW"][k]),
+                        np.where(east, states["SE"][k], states["SW"][k]))
+    return Workload("riemann2d", D2Q4, n, n, (0.0, 1.0, 0.0, 1.0), W, omega=omega, cfl=cfl,
+                    t_end=t_end, meta={"states": states})
+
+
+def riemann2d_paper(n: int = 400, t_end: float = 0.25) -> Workload:
+    """The paper's 2D Riemann case (Sec. III): quadrants split at the domain
+    centre (its garbled "x >= 0, y >= 0" read as x, y >= 0.5 on [0,1]^2)."""
+    states = {"NE": (1.1, 0.0, 0.0, 1.1), "NW": (0.5065, 0.8939, 0.0, 0.35),
+              "SW": (1.1, 0.8939, 0.8939, 1.1), "SE": (0.5065, 0.0, 0.8939, 0.35)}
+    w = riemann2d(n, states=states, t_end=t_end)
+    w.name = "riemann2d_paper"
+    return w
+
+
+def explosion(n: int = 400, t_end: float = 0.25, omega: float = 1.0) -> Workload:
+    """Explosion (Sec. III): [-1,1]^2, (1,0,0,1) for r < 0.4, (0.125,0,0,0.1) outside."""
+    x = centres(n, -1.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    inside = X * X + Y * Y < 0.4 * 0.4
+    W = np.empty((4, n, n))
+    W[0] = np.where(inside, 1.0, 0.125)
+    W[1] = 0.0
+    W[2] = 0.0
+    W[3] = np.where(inside, 1.0, 0.1)
+    return Workload("explosion", D2Q4, n, n, (-1.0, 1.0, -1.0, 1.0), W, omega=omega, t_end=t_end)
+
+
+def acoustic_pulse(n: int = 2048, steps: int = 2000, gamma: float = 1.4) -> Workload:
+    """Periodic [0,1]^2, rho = 1 + 0.01 exp(-r^2/0.05^2) about (0.5, 0.5), u = v = 0,
+    p = rho^gamma/gamma (isentropic), run for a fixed number of steps at a frozen
+    lattice speed; objective J = sum of rho^2 over cells centred in [0.7,0.8]^2."""
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2
+    W = np.empty((4, n, n))
+    W[0] = 1.0 + 0.01 * np.exp(-r2 / 0.05 ** 2)
+    W[1] = 0.0
+    W[2] = 0.0
+    W[3] = W[0] ** gamma / gamma
+    return Workload("acoustic_pulse", D2Q4, n, n, (0.0, 1.0, 0.0, 1.0), W, gamma=gamma,
+                    sides=(PERIODIC,) * 4, steps=steps,
+                    meta={"window": (0.7, 0.8), "isentropic": True})
+
+
+def window_mask(n: int, lo: float = 0.7, hi: float = 0.8) -> np.ndarray:
+    """Boolean [n][n] mask of cells whose centres lie in the closed square [lo,hi]^2."""
+    x = centres(n, 0.0, 1.0)
+    inx = (x >= lo) & (x <= hi)
+    return inx[:, None] & inx[None, :]
+
+
+def fourier_modes(n: int, seed: int, nmodes: int = 8, gamma: float = 1.4,
+                  steps: int = 1000) -> Workload:
+    """Random smooth periodic state: rho = 1 + 0.05 * sum of nmodes seeded modes,
+    u, v = 0.1 * seeded modes, p = rho^gamma/gamma.  Each mode is
+    cos(2 pi (kx x + ky y) + theta) with integer (kx, ky) in [-4,4]^2 \\ {0},
+    theta ~ U[0, 2 pi) and a random sign, normalised by nmodes."""
+    rng = np.random.default_rng(seed)
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+
+    def field():
+        acc = np.zeros((n, n))
+        for _ in range(nmodes):
+            while True:
+                kx, ky = rng.integers(-4, 5, size=2)
+                if kx != 0 or ky != 0:
+                    break
+            th = rng.uniform(0.0, 2.0 * math.pi)
+            sg = rng.choice([-1.0, 1.0])
+            acc += sg * np.cos(2.0 * math.pi * (kx * X + ky * Y) + th)
+        return acc / nmodes
+
+    W = np.empty((4, n, n))
+    W[0] = 1.0 + 0.05 * field()
+    W[1] = 0.1 * field()
+    W[2] = 0.1 * field()
+    W[3] = W[0] ** gamma / gamma
+    return Workload(f"fourier{seed}", D2Q4, n, n, (0.0, 1.0, 0.0, 1.0), W, gamma=gamma,
+                    sides=(PERIODIC,) * 4, steps=steps, meta={"seed": seed})
+
+
+def tube_batch(count: int = 1024, seed: int = 0, nmin: int = 200, nmax: int = 20000):
+    """Ragged batch of shock tubes: cell counts log-uniform in [nmin, nmax], left and
+    right states rho ~ U[0.1,1], u ~ U[-0.5,0.5], p ~ U[0.1,1], t_end ~ U[0.1,0.25];
+    domain [0,1], interface 0.5, D1Q3, omega = 1, cfl = 0.5, transmissive."""
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(math.log(nmin), math.log(nmax), size=count)).astype(np.int64)
+    ns += ns % 2  # even counts: no cell centre on the interface
+    tubes = []
+    for b in range(count):
+        left = (rng.uniform(0.1, 1.0), rng.uniform(-0.5, 0.5), rng.uniform(0.1, 1.0))
+        right = (rng.uniform(0.1, 1.0), rng.uniform(-0.5, 0.5), rng.uniform(0.1, 1.0))
+        t_end = rng.uniform(0.1, 0.25)
+        W = _tube(int(ns[b]), (0.0, 1.0), 0.5, left, right)
+        tubes.append(Workload(f"tube{b}", D1Q3, int(ns[b]), 1, (0.0, 1.0, 0.0, 1.0), W,
+                              t_end=t_end, meta={"left": left, "right": right,
+                                                 "x_interface": 0.5}))
+    return tubes
+
+
+def domain_batch(count: int = 128, seed: int = 0, sides=(256, 512, 1024, 2048),
+                 steps: int = 1000):
+    """Ragged batch of periodic 2D domains with side lengths drawn uniformly from
+    `sides`; domain b gets the random smooth state fourier_modes(n_b, seed*100000 + b)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sides), size=count)
+    return [fourier_modes(int(ns[b]), seed * 100000 + b, steps=steps) for b in range(count)]
+
+
+def random_states(count: int, seed: int, dim: int = 2):
+    """Random admissible primitive states (rho, u, [v,] p), one per row."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.1, 2.0, size=count)
+    p = rng.uniform(0.05, 3.0, size=count)
+    vel = rng.uniform(-2.0, 2.0, size=(count, dim))
+    return np.column_stack([rho, vel, p])
