@@ -1,0 +1,168 @@
+"""Benchmark of the LBRS hot path on one MI355X.
+
+Workload: the four-quadrant 2D Riemann problem, 4096 x 4096 cells on [0,1]^2,
+D2Q4, FP64, gamma = 1.4, omega = 1, CFL 0.5, transmissive sides, t_end = 0.3.
+One "step" is one fused collide-and-stream LBRS step over the whole grid
+(moments, flux, equilibria, relaxation, streaming, sides, next-step lambda*).
+
+Prints one JSON line: MLUPS (value), the HBM roofline of the step kernel
+(algorithmic 256 B per lattice update: 16 FP64 populations read + 16 written),
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = 256  # 16 FP64 populations in + 16 out per lattice update
+
+
+def cpu_baseline(nsteps: int = 2):
+    """The oracle on the same 4096^2 workload for a bounded number of steps
+    (single thread), init time excluded by differencing two runs."""
+    import oracle
+    from paper_1504_07034_amd import workloads as wl
+
+    w = wl.riemann2d(4096)
+    P = oracle.Problem(model=w.model, nx=w.nx, ny=w.ny, domain=w.domain, gamma=w.gamma,
+                       omega=w.omega, cfl=w.cfl, sides=w.sides)
+    U0 = oracle.prim_to_cons(P, w.W)
+    del w
+    t0 = time.perf_counter()
+    oracle.run(P, U0, t_end=0.3, max_steps=0, record=False)
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = oracle.run(P, U0, t_end=0.3, max_steps=nsteps, record=False)
+    t_run = time.perf_counter() - t0
+    secs = max(t_run - t_init, 1e-9)
+    lups = 4096 * 4096 * r.nsteps
+    return {"value": lups / secs / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"4096x4096 four-quadrant problem, {r.nsteps} steps from t=0 "
+                      f"({secs:.1f} s of stepping; init excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--rows", type=int, default=-1,
+                    help="rows per tile (0 = automatic); default: autotune")
+    ap.add_argument("--wpb", type=int, default=4)
+    ap.add_argument("--layout", type=int, default=1, help="0 planar, 1 row-interleaved")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, run one plain copy of the populations (lbrs_get_f: "
+                         "16 planes read and written) as a known-size reference for counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1504_07034_amd import autotune, lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    n = 4096
+    t_end = 0.3
+    w = wl.riemann2d(n, t_end=t_end)
+    sim = lbrs.Sim(w.model, n, n, domain=w.domain, gamma=w.gamma, omega=w.omega, cfl=w.cfl,
+                   bc=w.sides, layout=args.layout)
+    W = torch.from_numpy(w.W).cuda()
+    U0 = sim.prim_to_cons(W)
+    del W, w
+
+    shape = {"rows": args.rows, "wpb": args.wpb}
+
+    def fresh():
+        sim.init(U0)
+        if shape["rows"] >= 0:
+            sim.set_tile(shape["rows"], shape["wpb"])
+
+    if args.rows < 0:  # autotune the launch shape (untimed), then start over
+        sim.init(U0)
+        sim.step(20, t_end)
+        best = autotune.tune(sim, t_end, use_cache=False)
+        shape = {"rows": best["rows"], "wpb": best["wpb"]}
+        print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']}) {c['ms']:.3f} ms"
+                                       for c in best["candidates"]), file=sys.stderr, flush=True)
+
+    # The run reaches t_end after ~7.8k steps; time in segments that stay
+    # inside [0, t_end) so that every timed step does real work.
+    seg_cap = 6000
+    fresh()
+    sim.step(args.warmup, t_end)
+    done_in_seg = args.warmup
+    stream = torch.cuda.current_stream()
+    total_ms = 0.0
+    left = args.steps
+    while left > 0:
+        if done_in_seg >= seg_cap:
+            fresh()
+            done_in_seg = 0
+        k = min(left, seg_cap - done_in_seg)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(k, t_end)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        st = sim.state()
+        if st["rc"] != 0 or st["nsteps"] != done_in_seg + k:
+            raise RuntimeError(f"timed steps did not all run: {st}")
+        done_in_seg += k
+        left -= k
+
+    if args.calibrate_copy:
+        f_copy = sim.get_f()
+        torch.cuda.synchronize()
+        del f_copy
+
+    ms_per_step = total_ms / args.steps
+    cells = n * n
+    mlups = cells / (ms_per_step * 1e-3) / 1e6
+    achieved = BYTES_PER_LUP * cells / (ms_per_step * 1e-3) / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D four-quadrant Riemann problem, plain LBRS D2Q4",
+                   "nx": n, "ny": n, "domain": "[0,1]^2", "gamma": 1.4, "omega": 1.0,
+                   "cfl": 0.5, "sides": "transmissive", "t_end": t_end,
+                   "tile_rows": shape["rows"], "waves_per_block": shape["wpb"],
+                   "layout": "row-interleaved" if args.layout == 1 else "planar"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+    }
+    sim.close()
+    del U0
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * lbrs.h -- C ABI of the MI355X (gfx950) implementation of the Lattice
+ * Boltzmann Relaxation Scheme (LBRS) for the inviscid gamma-law Euler
+ * equations: S. V. Raghurama Rao, R. Deshmukh, S. Kotnala, "A Lattice
+ * Boltzmann Relaxation Scheme for Inviscid Compressible Flows",
+ * arXiv 1504.07034.
+ *
+ * The problem the calls solve is the paper's (Sec. II): evolve conserved
+ * initial data U0 with the discrete-velocity BGK model whose equilibria are
+ * algebraic in U and the flux G(U),
+ *     f_i(x + lambda_i dt, t + dt) = (1 - omega) f_i(x, t) + omega f_i^eq(x, t),
+ * with exact hopping (lambda dt = dx), then read back U = sum_i f_i.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * All arithmetic is IEEE FP64.  All large buffers are DEVICE pointers that
+ *    the caller allocates and owns; the library borrows them until
+ *    lbrs_destroy().  The library allocates only its small host-side context.
+ *  * Layouts (C order, x fastest):
+ *      U  (conserved)  : K planes [K][ny][nx]; K = 3 in 1D (rho, rho u, rho E),
+ *                        K = 4 in 2D (rho, rho u, rho v, rho E)
+ *      W  (primitive)  : [K][ny][nx] = (rho, u, p) or (rho, u, v, p)
+ *      f  (populations): Q*K planes p = i*K + k, velocity order as in the
+ *                        paper: D1Q2 (-,+), D1Q3 (-,0,+),
+ *                        D2Q4 (-,-), (+,-), (+,+), (-,+); element (p, y, x) at
+ *                          LBRS_LAYOUT_PLANAR: (p*ny + y)*nx + x   [Q][K][ny][nx]
+ *                          LBRS_LAYOUT_ROWS  : (y*Q*K + p)*nx + x  [ny][Q][K][nx]
+ *                        (the two coincide in 1D).  Population-shaped buffers
+ *                        of a context (f0, f1, lbrs_get_f/lbrs_set_f, the
+ *                        adjoint's fbar) all use the context's layout.
+ *    Pointers must be 8-byte aligned (hipMalloc / torch allocations are
+ *    256-byte aligned).
+ *  * Grid: cell-centred, dx = (x1-x0)/nx, dy = (y1-y0)/ny; 2D requires
+ *    dx == dy (the D2Q4 populations hop along cell diagonals).
+ *  * Every call that enqueues work does so on the context's HIP stream and
+ *    returns without synchronising, except lbrs_get_state() which waits for
+ *    the stream.
+ *  * Return codes: LBRS_OK (0) or a negative lbrs_status; lbrs_strerror()
+ *    names them.  An invalid argument is rejected before anything is
+ *    enqueued.  A non-physical state (rho <= 0, p <= 0 or a non-finite value)
+ *    met on the device stops the time loop at that step and is reported by
+ *    the next lbrs_get_state() as LBRS_E_NONPHYSICAL with the step index.
+ */
+#ifndef LBRS_H
+#define LBRS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbrs_ctx lbrs_ctx; /* opaque host-side handle */
+
+typedef enum {
+    LBRS_OK = 0,
+    LBRS_E_INVAL = -1,       /* bad parameter, size or pointer */
+    LBRS_E_NOMEM = -2,       /* host allocation failed */
+    LBRS_E_HIP = -3,         /* a HIP runtime call failed */
+    LBRS_E_NONPHYSICAL = -4, /* rho <= 0, p <= 0 or non-finite state met */
+    LBRS_E_STATE = -5        /* call not valid for this context's mode */
+} lbrs_status;
+
+/* Discrete-velocity models (Sec. II.A D1Q2, Sec. II.C D1Q3, Sec. II.D D2Q4). */
+enum { LBRS_D1Q2 = 0, LBRS_D1Q3 = 1, LBRS_D2Q4 = 2 };
+
+/* Side conditions, given per side in the order x-low, x-high, y-low, y-high.
+ * WALL is the paper's free-slip wall by specular reflection (Sec. II.E), with
+ * the wall on the first/last node row or column; walls on two perpendicular
+ * sides (a corner) are rejected.  TRANSMISSIVE (zero gradient of the
+ * post-collision populations) and PERIODIC are not in the paper.  PERIODIC
+ * must be set on both sides of an axis.  1D models accept TRANSMISSIVE and
+ * PERIODIC on x only. */
+enum { LBRS_BC_TRANSMISSIVE = 0, LBRS_BC_PERIODIC = 1, LBRS_BC_WALL = 2 };
+
+/* Lattice speed.  PER_STEP: every step takes the global bound
+ * lambda* = max over cells of the local bound (Sec. II.C Jin-Xin choice in 1D,
+ * Sec. II.D Bouchut condition in 2D), dt = min(cfl*dx/lambda*, t_end - t) and
+ * the lattice speed dx/dt.  FROZEN_INIT: the lattice speed lambda*(U0)/cfl is
+ * fixed at lbrs_init (dt = dx/lambda, no clipping at t_end) -- the mode the
+ * adjoint calls need.  USER: the fixed lattice speed lambda_user. */
+enum { LBRS_LAMBDA_PER_STEP = 0, LBRS_LAMBDA_FROZEN_INIT = 1, LBRS_LAMBDA_USER = 2 };
+
+/* Population layouts.  ROWS keeps the 16 D2Q4 population rows of a grid row
+ * in one contiguous block, so the 2D step touches two memory pages per row
+ * instead of 32. */
+enum { LBRS_LAYOUT_PLANAR = 0, LBRS_LAYOUT_ROWS = 1 };
+
+typedef struct {
+    int model;            /* LBRS_D1Q2, LBRS_D1Q3 or LBRS_D2Q4 */
+    int nx, ny;           /* cells; ny = 1 for 1D; nx >= 3 (and ny >= 3 in 2D) */
+    double x0, x1, y0, y1;/* domain; y0, y1 ignored in 1D */
+    double gamma;         /* ratio of specific heats, > 1 */
+    double omega;         /* relaxation parameter omega = dt/epsilon, in (0, 2) (Sec. II.B) */
+    double cfl;           /* in (0, 1]: lattice speed = (lambda star) / cfl */
+    int bc[4];            /* side conditions, x-low, x-high, y-low, y-high */
+    int lambda_mode;      /* LBRS_LAMBDA_* */
+    double lambda_user;   /* lattice speed for LBRS_LAMBDA_USER, > 0 */
+    int layout;           /* LBRS_LAYOUT_PLANAR (0) or LBRS_LAYOUT_ROWS (1) */
+} lbrs_params;
+
+/* Sizes in bytes of one population buffer (f0 or f1), of one conserved-state
+ * buffer (U, K planes) and of the device scratch area lbrs_init needs.
+ * Any output pointer may be NULL.  Returns LBRS_E_INVAL for invalid params. */
+int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes,
+                     size_t* scratch_bytes);
+
+/* Primitive -> conserved variables on the device: U = (rho, rho u, [rho v,]
+ * rho E) with E = p/(rho(gamma-1)) + |u|^2/2 (Sec. II.C).  d_W and d_U are
+ * [K][ny][nx]; they may not alias.  Enqueued on hip_stream (NULL = default). */
+int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void* hip_stream);
+
+/* Create a context and set the populations to equilibrium, f^0 = f^eq(U0)
+ * (Sec. II.A: the initial data are given to the populations through their
+ * equilibria), with the lattice speed lambda*(U0)/cfl (or lambda_user).
+ *   d_U0      [K][ny][nx] conserved initial state (read during this call's
+ *             kernels only)
+ *   d_f0,d_f1 two population buffers of f_bytes each (ping-pong; borrowed)
+ *   d_scratch scratch_bytes of device memory (borrowed; holds t, the step
+ *             count, the lambda* reduction slots and the status word)
+ *   hip_stream the stream every later call enqueues on (NULL = default)
+ * On success *out receives the context.  A non-physical U0 is reported by the
+ * next lbrs_get_state() with step index 0. */
+int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* d_f0,
+              double* d_f1, void* d_scratch, void* hip_stream);
+
+/* Enqueue max_steps fused collide-and-stream steps (Sec. II.A discrete LBRS
+ * update; Sec. II.D in 2D; walls Sec. II.E).  Each step reads the lattice
+ * speed from the device, forms U, the flux, the equilibria, relaxes, streams
+ * one node along every link, applies the side conditions and reduces the next
+ * step's lambda*.  A step whose start time is >= t_end, or that follows a
+ * non-physical step, does nothing, so the run stops exactly at t_end
+ * (PER_STEP mode clips the last dt).  Asynchronous. */
+int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
+
+/* Wait for the stream and report the current time, completed step count,
+ * the lattice speed of the last step taken (or of f^0 before any step) and
+ * the status.  *status is 0 or a bit mask (1 = non-physical); *fail_step is
+ * the index (1-based; 0 = the initial state) of the first non-physical state
+ * or -1.  Any output pointer may be NULL.  Returns LBRS_E_NONPHYSICAL when the
+ * status is set, LBRS_OK otherwise. */
+int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda,
+                   unsigned* status, long long* fail_step);
+
+/* Moments of the current populations, U = sum_i f_i (eq. "moments_system"),
+ * into d_U [K][ny][nx].  Asynchronous. */
+int lbrs_moments(lbrs_ctx* c, double* d_U);
+
+/* Copy the current populations to / from d_f [Q][K][ny][nx] (checkpoints).
+ * lbrs_set_f also sets the time t and step count n, clears the status, and
+ * (PER_STEP mode) re-reduces lambda* from the new populations. */
+int lbrs_get_f(lbrs_ctx* c, double* d_f);
+int lbrs_set_f(lbrs_ctx* c, const double* d_f, double t, long long n);
+
+/* Objective for the gradient calls (2D only): J = sum of rho^2 over the cells
+ * with i in [ix0, ix1) and j in [iy0, iy1), rho from the current populations.
+ * Writes J to *d_J (one device double) and the seed of the adjoint,
+ * dJ/df_{i,rho}(x) = 2 rho(x) inside the window and 0 elsewhere, to
+ * d_fbar [Q][K][ny][nx].  Asynchronous. */
+int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, double* d_J,
+                          double* d_fbar);
+
+/* Forward step that also stores the step's input moments U^n into
+ * d_Utape_n [K][ny][nx] (the tape the adjoint step reads).  FROZEN_INIT or
+ * USER mode only (else LBRS_E_STATE); otherwise identical to lbrs_step(c, 1,
+ * +inf). */
+int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n);
+
+/* Adjoint (vector-Jacobian product) of one fixed-speed step, D2Q4 with
+ * periodic sides: given fbar^{n+1} = dJ/df^{n+1} and the step's input moments
+ * U^n, write fbar^n = dJ/df^n:
+ *   fbar*_i(x) = fbar^{n+1}_i(x + s_i)                      (reverse stream)
+ *   Ubar(x)    = omega [ (1/4) sum_i fbar*_i
+ *                        + (A1(U^n)^T h_x + A2(U^n)^T h_y) / (4 lambda) ],
+ *                h_d = sum_i s_{i,d} fbar*_i,  A_d = dG_d/dU   (D2Q4 equilibria)
+ *   fbar^n_i   = (1 - omega) fbar*_i + Ubar                 (relaxation)
+ * All arrays are [Q][K][ny][nx] / [K][ny][nx]; d_fbar may not alias
+ * d_fbar_next.  FROZEN_INIT or USER mode only.  Asynchronous. */
+int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar_next,
+                      double* d_fbar);
+
+/* Adjoint of the initialisation f^0 = f^eq(U0): Ubar0 = sum_i (df_i^eq/dU)^T
+ * fbar0_i at U0.  d_fbar0 [Q][K][ny][nx], d_U0 and d_Ubar0 [K][ny][nx].
+ * FROZEN_INIT or USER mode only.  Asynchronous. */
+int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, double* d_Ubar0);
+
+/* Adjoint of lbrs_prim_to_cons: given W and Ubar = dJ/dU, write Wbar = dJ/dW.
+ * If isentropic != 0, the pressure is taken as p = rho^gamma/gamma and the
+ * result's density plane is the total derivative dJ/drho0 (the other planes
+ * are then zero).  Enqueued on hip_stream. */
+int lbrs_prim_to_cons_adjoint(const lbrs_params* p, const double* d_W, const double* d_Ubar,
+                              int isentropic, double* d_Wbar, void* hip_stream);
+
+/* Change the stream later calls enqueue on. */
+int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);
+
+/* Launch shape of the 2D step.  Each wavefront marches the rows of a tile:
+ * a strip of at most 62 columns by a segment of rows; waves loop over the tiles of a
+ * persistent grid of the resident workgroups.  rows_per_tile = 0 (the
+ * default) picks as many segments as make the tiles one balanced round of the
+ * resident waves; otherwise segments of about rows_per_tile rows (1..65536).
+ * waves_per_block is 1, 2, 4, 6, 8, 12 or 16: the waves of a workgroup march
+ * adjacent strips in lockstep.  Takes effect for later calls. */
+int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block);
+
+const char* lbrs_strerror(int code);
+void lbrs_destroy(lbrs_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBRS_H */

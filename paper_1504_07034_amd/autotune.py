@@ -1,0 +1,92 @@
+"""Autotuner for the launch shape of the 2D step kernel.
+
+Candidates are (rows_per_tile, waves_per_block) pairs; rows_per_tile = 0 is
+the library's automatic choice (one balanced round of the resident waves).
+Each candidate is timed with HIP events over a few steps that start from the
+same checkpoint of the populations (lbrs_get_f / lbrs_set_f), so tuning does
+not advance the caller's solution.  The best shape is applied to the context
+and cached per (device, model, nx, ny, side conditions) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import lbrs
+
+CACHE = os.environ.get("LBRS_TUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "lbrs_tune.json"))
+
+DEFAULT_ROWS = (0, 32, 64, 96, 128)
+DEFAULT_WPB = (4, 6, 8, 12, 16)
+
+
+def _key(sim: "lbrs.Sim") -> str:
+    p = sim.p
+    name = torch.cuda.get_device_name(sim.device)
+    return f"{name}|m{p.model}|{p.nx}x{p.ny}|bc{tuple(p.bc)}"
+
+
+def _load_cache() -> dict:
+    try:
+        with open(CACHE) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c: dict) -> None:
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        with open(CACHE, "w") as fh:
+            json.dump(c, fh, indent=1, sort_keys=True)
+    except OSError:
+        pass
+
+
+def time_shape(sim: "lbrs.Sim", rows: int, wpb: int, steps: int, f0: torch.Tensor,
+               t0: float, n0: int, t_end: float) -> float:
+    """Milliseconds per step of one launch shape, from the checkpoint (f0, t0, n0)."""
+    sim.set_tile(rows, wpb)
+    sim.set_f(f0, t0, n0)
+    sim.step(2, t_end)  # warm the shape
+    sim.set_f(f0, t0, n0)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps, t_end)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=DEFAULT_ROWS,
+         wpbs=DEFAULT_WPB, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Pick and apply the fastest 2D launch shape for `sim` (already initialised)."""
+    key = _key(sim)
+    cache = _load_cache() if use_cache else {}
+    if use_cache and key in cache:
+        best = cache[key]
+        sim.set_tile(best["rows"], best["wpb"])
+        return best
+    st = sim.state()
+    f0 = sim.get_f()
+    results = []
+    for w in wpbs:
+        for r in rows:
+            ms = time_shape(sim, r, w, steps, f0, st["t"], st["nsteps"], t_end)
+            results.append({"rows": r, "wpb": w, "ms": ms})
+            if verbose:
+                print(f"autotune rows={r} wpb={w}: {ms:.4f} ms/step", flush=True)
+    best = min(results, key=lambda d: d["ms"])
+    sim.set_f(f0, st["t"], st["nsteps"])
+    sim.set_tile(best["rows"], best["wpb"])
+    best = dict(best, candidates=results)
+    if use_cache:
+        cache[key] = best
+        _save_cache(cache)
+    return best

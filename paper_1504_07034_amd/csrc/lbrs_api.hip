@@ -1,0 +1,402 @@
+// C ABI of the LBRS library (declared in include/lbrs.h): parameter checks,
+// the context, and the launch sequence of every call.  No call allocates
+// device memory; all large buffers are the caller's.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "lbrs.h"
+#include "lbrs_launch.hpp"
+
+
+using namespace lbrs;
+
+struct lbrs_ctx {
+    lbrs_params P;
+    int Q, K, dim;
+    long long plane;
+    long long ps, rs;    // population offset p*ps + y*rs + x
+    double dx;
+    double* f0;
+    double* f1;
+    DevState* st;
+    hipStream_t stream;
+    long long launches;  // step launches since the last (re)initialisation
+    int rows_per_tile;   // 0: automatic (one balanced round of resident waves)
+    int waves_per_block;
+    int persistent_max;  // largest 1D domain run by the persistent kernel
+    int cu_count;
+    int bpc[17];         // resident step-kernel workgroups per CU, by waves per block
+};
+
+static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
+static int nk(int model) { return model == LBRS_D2Q4 ? 4 : 3; }
+
+static int check_params(const lbrs_params* p) {
+    if (!p) return LBRS_E_INVAL;
+    if (p->model < LBRS_D1Q2 || p->model > LBRS_D2Q4) return LBRS_E_INVAL;
+    const int dim = p->model == LBRS_D2Q4 ? 2 : 1;
+    if (p->nx < 3 || p->ny < 1) return LBRS_E_INVAL;
+    if (dim == 1 && p->ny != 1) return LBRS_E_INVAL;
+    if (dim == 2 && p->ny < 3) return LBRS_E_INVAL;
+    if ((long long)p->nx * p->ny > (1ll << 40)) return LBRS_E_INVAL;
+    if (!(p->x1 > p->x0) || !isfinite(p->x0) || !isfinite(p->x1)) return LBRS_E_INVAL;
+    if (!(p->gamma > 1.0) || !isfinite(p->gamma)) return LBRS_E_INVAL;
+    if (!(p->omega > 0.0 && p->omega < 2.0)) return LBRS_E_INVAL;
+    if (dim == 2) {
+        if (!(p->y1 > p->y0)) return LBRS_E_INVAL;
+        double dx = (p->x1 - p->x0) / p->nx, dy = (p->y1 - p->y0) / p->ny;
+        if (!(fabs(dx - dy) <= 1e-12 * dx)) return LBRS_E_INVAL;
+    }
+    for (int s = 0; s < 4; ++s)
+        if (p->bc[s] < LBRS_BC_TRANSMISSIVE || p->bc[s] > LBRS_BC_WALL) return LBRS_E_INVAL;
+    if ((p->bc[0] == LBRS_BC_PERIODIC) != (p->bc[1] == LBRS_BC_PERIODIC)) return LBRS_E_INVAL;
+    if (dim == 2 && (p->bc[2] == LBRS_BC_PERIODIC) != (p->bc[3] == LBRS_BC_PERIODIC))
+        return LBRS_E_INVAL;
+    if (dim == 1 && (p->bc[0] == LBRS_BC_WALL || p->bc[1] == LBRS_BC_WALL)) return LBRS_E_INVAL;
+    if (dim == 2) {
+        bool xw = p->bc[0] == LBRS_BC_WALL || p->bc[1] == LBRS_BC_WALL;
+        bool yw = p->bc[2] == LBRS_BC_WALL || p->bc[3] == LBRS_BC_WALL;
+        if (xw && yw) return LBRS_E_INVAL;
+    }
+    if (p->lambda_mode < LBRS_LAMBDA_PER_STEP || p->lambda_mode > LBRS_LAMBDA_USER)
+        return LBRS_E_INVAL;
+    if (p->lambda_mode == LBRS_LAMBDA_USER && !(p->lambda_user > 0.0 && isfinite(p->lambda_user)))
+        return LBRS_E_INVAL;
+    if (p->lambda_mode != LBRS_LAMBDA_USER && !(p->cfl > 0.0 && p->cfl <= 1.0)) return LBRS_E_INVAL;
+    if (p->layout != LBRS_LAYOUT_PLANAR && p->layout != LBRS_LAYOUT_ROWS) return LBRS_E_INVAL;
+    return LBRS_OK;
+}
+
+static CellArgs cell_args(const lbrs_ctx* c) {
+    CellArgs a;
+    a.plane = c->plane;
+    a.ps = c->ps;
+    a.rs = c->rs;
+    a.nx = c->P.nx;
+    a.ny = c->P.ny;
+    a.model = c->P.model;
+    a.gamma = c->P.gamma;
+    return a;
+}
+
+static int hip_status(hipError_t e) { return e == hipSuccess ? LBRS_OK : LBRS_E_HIP; }
+
+extern "C" {
+
+int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes, size_t* scratch_bytes) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    size_t cells = (size_t)p->nx * (size_t)p->ny;
+    if (f_bytes) *f_bytes = sizeof(double) * (size_t)nq(p->model) * nk(p->model) * cells;
+    if (u_bytes) *u_bytes = sizeof(double) * (size_t)nk(p->model) * cells;
+    if (scratch_bytes) *scratch_bytes = (sizeof(DevState) + 255) / 256 * 256;
+    return LBRS_OK;
+}
+
+int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void* hip_stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!d_W || !d_U || d_W == d_U) return LBRS_E_INVAL;
+    CellArgs a;
+    a.plane = (long long)p->nx * p->ny;
+    a.ps = a.plane;
+    a.rs = p->nx;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.model = p->model;
+    a.gamma = p->gamma;
+    return hip_status(launch_prim_to_cons(a, d_W, d_U, (hipStream_t)hip_stream));
+}
+
+int lbrs_prim_to_cons_adjoint(const lbrs_params* p, const double* d_W, const double* d_Ubar,
+                              int isentropic, double* d_Wbar, void* hip_stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!d_W || !d_Ubar || !d_Wbar || d_Wbar == d_W || d_Wbar == d_Ubar) return LBRS_E_INVAL;
+    CellArgs a;
+    a.plane = (long long)p->nx * p->ny;
+    a.ps = a.plane;
+    a.rs = p->nx;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.model = p->model;
+    a.gamma = p->gamma;
+    return hip_status(launch_prim_to_cons_adjoint(a, d_W, d_Ubar, isentropic, d_Wbar,
+                                                  (hipStream_t)hip_stream));
+}
+
+int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* d_f0, double* d_f1,
+              void* d_scratch, void* hip_stream) {
+    if (!out) return LBRS_E_INVAL;
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!d_U0 || !d_f0 || !d_f1 || !d_scratch || d_f0 == d_f1) return LBRS_E_INVAL;
+    if (((uintptr_t)d_scratch & 7u) != 0) return LBRS_E_INVAL;
+    lbrs_ctx* c = (lbrs_ctx*)calloc(1, sizeof(lbrs_ctx));
+    if (!c) return LBRS_E_NOMEM;
+    c->P = *p;
+    c->Q = nq(p->model);
+    c->K = nk(p->model);
+    c->dim = p->model == LBRS_D2Q4 ? 2 : 1;
+    c->plane = (long long)p->nx * p->ny;
+    if (p->layout == LBRS_LAYOUT_ROWS) {
+        c->ps = p->nx;
+        c->rs = (long long)c->Q * c->K * p->nx;
+    } else {
+        c->ps = c->plane;
+        c->rs = p->nx;
+    }
+    c->dx = (p->x1 - p->x0) / p->nx;
+    c->f0 = d_f0;
+    c->f1 = d_f1;
+    c->st = (DevState*)d_scratch;
+    c->stream = (hipStream_t)hip_stream;
+    c->launches = 0;
+    c->rows_per_tile = 0;
+    c->waves_per_block = 4;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        free(c);
+        return LBRS_E_HIP;
+    }
+    c->persistent_max = persistent1d_max_cells(c->Q, prop.sharedMemPerBlock);
+    c->cu_count = prop.multiProcessorCount;
+    CellArgs a = cell_args(c);
+    hipError_t e = launch_reset(c->st, c->stream);
+    if (e == hipSuccess)
+        e = launch_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl, c->stream);
+    if (e != hipSuccess) {
+        free(c);
+        return LBRS_E_HIP;
+    }
+    *out = c;
+    return LBRS_OK;
+}
+
+int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block) {
+    if (!c) return LBRS_E_INVAL;
+    if (rows_per_tile != 0 && (rows_per_tile < 1 || rows_per_tile > 65536)) return LBRS_E_INVAL;
+    if (!step2d_wpb_supported(waves_per_block)) return LBRS_E_INVAL;
+    c->rows_per_tile = rows_per_tile;
+    c->waves_per_block = waves_per_block;
+    return LBRS_OK;
+}
+
+int lbrs_set_stream(lbrs_ctx* c, void* hip_stream) {
+    if (!c) return LBRS_E_INVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return LBRS_OK;
+}
+
+// Row segments per strip.  Automatic: as many as make the tiles one balanced
+// round of the resident waves (at least 8 rows each); else ceil(ny / rows).
+static int blocks_per_cu(const lbrs_ctx* c) {
+    lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
+    int w = c->waves_per_block;
+    if (m->bpc[w] == 0) m->bpc[w] = step2d_blocks_per_cu(w);
+    return m->bpc[w];
+}
+
+static int step2d_segments(const lbrs_ctx* c, int nstrips) {
+    const int ny = c->P.ny;
+    long long nseg;
+    if (c->rows_per_tile > 0) {
+        nseg = (ny + c->rows_per_tile - 1) / c->rows_per_tile;
+    } else {
+        long long waves = (long long)c->cu_count * blocks_per_cu(c) * c->waves_per_block;
+        nseg = waves / nstrips;
+        long long cap = (ny + 7) / 8;  // at least 8 rows per segment
+        if (nseg > cap) nseg = cap;
+    }
+    if (nseg < 1) nseg = 1;
+    if (nseg > ny) nseg = ny;
+    return (int)nseg;
+}
+
+static int step2d_max_blocks(const lbrs_ctx* c) {
+    return c->cu_count * blocks_per_cu(c);
+}
+
+static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
+    Step2DArgs a;
+    a.f0 = c->f0;
+    a.f1 = c->f1;
+    a.st = c->st;
+    a.tape = tape;
+    a.plane = c->plane;
+    a.ps = c->ps;
+    a.rs = c->rs;
+    a.nx = c->P.nx;
+    a.ny = c->P.ny;
+    // strips of at most 62 columns, as many as a multiple of the waves per
+    // workgroup, with the columns spread evenly over them
+    const int wpb = c->waves_per_block;
+    a.nstrips = ((c->P.nx + 61) / 62 + wpb - 1) / wpb * wpb;
+    a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
+    a.nseg = step2d_segments(c, a.nstrips);
+    a.ntiles = a.nstrips * a.nseg;
+    a.launch = c->launches;
+    a.dx = c->dx;
+    a.cfl = c->P.cfl;
+    a.omega = c->P.omega;
+    a.gamma = c->P.gamma;
+    a.t_end = t_end;
+    a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
+    for (int s = 0; s < 4; ++s) a.bc[s] = c->P.bc[s];
+    return a;
+}
+
+static Step1DArgs step1d_args(const lbrs_ctx* c, double t_end, int max_steps) {
+    Step1DArgs a;
+    a.f0 = c->f0;
+    a.f1 = c->f1;
+    a.st = c->st;
+    a.plane = c->plane;
+    a.nx = c->P.nx;
+    a.launch = c->launches;
+    a.dx = c->dx;
+    a.cfl = c->P.cfl;
+    a.omega = c->P.omega;
+    a.gamma = c->P.gamma;
+    a.t_end = t_end;
+    a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
+    a.periodic = c->P.bc[0] == LBRS_BC_PERIODIC;
+    a.max_steps = max_steps;
+    return a;
+}
+
+int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
+    if (!c || max_steps < 0 || isnan(t_end)) return LBRS_E_INVAL;
+    if (max_steps == 0) return LBRS_OK;
+    if (c->dim == 2) {
+        for (int s = 0; s < max_steps; ++s) {
+            Step2DArgs a = step2d_args(c, t_end, nullptr);
+            hipError_t e = launch_step2d(a, c->waves_per_block, false, step2d_max_blocks(c), c->stream);
+            if (e != hipSuccess) return LBRS_E_HIP;
+            ++c->launches;
+        }
+        return LBRS_OK;
+    }
+    if (c->P.nx <= c->persistent_max) {
+        Step1DArgs a = step1d_args(c, t_end, max_steps);
+        hipError_t e = launch_run1d(a, c->Q, c->stream);
+        if (e != hipSuccess) return LBRS_E_HIP;
+        ++c->launches;
+        return LBRS_OK;
+    }
+    for (int s = 0; s < max_steps; ++s) {
+        Step1DArgs a = step1d_args(c, t_end, 1);
+        hipError_t e = launch_step1d(a, c->Q, c->stream);
+        if (e != hipSuccess) return LBRS_E_HIP;
+        ++c->launches;
+    }
+    return LBRS_OK;
+}
+
+int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n) {
+    if (!c || !d_Utape_n) return LBRS_E_INVAL;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP) return LBRS_E_STATE;
+    if (c->dim != 2) return LBRS_E_STATE;
+    Step2DArgs a = step2d_args(c, INFINITY, d_Utape_n);
+    hipError_t e = launch_step2d(a, c->waves_per_block, true, step2d_max_blocks(c), c->stream);
+    if (e != hipSuccess) return LBRS_E_HIP;
+    ++c->launches;
+    return LBRS_OK;
+}
+
+int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda, unsigned* status,
+                   long long* fail_step) {
+    if (!c) return LBRS_E_INVAL;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LBRS_E_HIP;
+    DevState h;
+    if (hipMemcpy(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost) != hipSuccess) return LBRS_E_HIP;
+    const Slot& s = h.s[c->launches & 1];
+    if (t) *t = s.t;
+    if (nsteps) *nsteps = s.n;
+    if (lambda) *lambda = s.lam_used;
+    if (status) *status = h.status;
+    if (fail_step) *fail_step = h.fail_step == ~0ull ? -1 : (long long)h.fail_step;
+    return h.status ? LBRS_E_NONPHYSICAL : LBRS_OK;
+}
+
+int lbrs_moments(lbrs_ctx* c, double* d_U) {
+    if (!c || !d_U) return LBRS_E_INVAL;
+    CellArgs a = cell_args(c);
+    return hip_status(launch_moments(a, c->f0, c->f1, c->st, (int)(c->launches & 1), d_U, c->stream));
+}
+
+int lbrs_get_f(lbrs_ctx* c, double* d_f) {
+    if (!c || !d_f || d_f == c->f0 || d_f == c->f1) return LBRS_E_INVAL;
+    CellArgs a = cell_args(c);
+    return hip_status(launch_get_f(a, c->f0, c->f1, c->st, (int)(c->launches & 1), d_f, c->stream));
+}
+
+int lbrs_set_f(lbrs_ctx* c, const double* d_f, double t, long long n) {
+    if (!c || !d_f || d_f == c->f0 || d_f == c->f1 || !isfinite(t) || n < 0) return LBRS_E_INVAL;
+    // the new state becomes launch 0: slot 0, buffer f0, bound in slot 0
+    c->launches = 0;
+    CellArgs a = cell_args(c);
+    return hip_status(launch_set_f(a, c->f0, c->f1, c->st, d_f, t, n, c->stream));
+}
+
+int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, double* d_J,
+                          double* d_fbar) {
+    if (!c || !d_J || !d_fbar) return LBRS_E_INVAL;
+    if (c->dim != 2) return LBRS_E_STATE;
+    if (ix0 < 0 || iy0 < 0 || ix1 > c->P.nx || iy1 > c->P.ny || ix0 > ix1 || iy0 > iy1)
+        return LBRS_E_INVAL;
+    CellArgs a = cell_args(c);
+    return hip_status(launch_window_objective(a, c->f0, c->f1, c->st, (int)(c->launches & 1), ix0,
+                                              ix1, iy0, iy1, d_J, d_fbar, c->stream));
+}
+
+int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar_next, double* d_fbar) {
+    if (!c || !d_Utape_n || !d_fbar_next || !d_fbar || d_fbar == d_fbar_next) return LBRS_E_INVAL;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    for (int s = 0; s < 4; ++s)
+        if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
+    AdjArgs a;
+    a.plane = c->plane;
+    a.ps = c->ps;
+    a.rs = c->rs;
+    a.nx = c->P.nx;
+    a.ny = c->P.ny;
+    a.gamma = c->P.gamma;
+    a.omega = c->P.omega;
+    a.st = c->st;
+    return hip_status(launch_adjoint_step(a, d_Utape_n, d_fbar_next, d_fbar, c->stream));
+}
+
+int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, double* d_Ubar0) {
+    if (!c || !d_fbar0 || !d_U0 || !d_Ubar0) return LBRS_E_INVAL;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    AdjArgs a;
+    a.plane = c->plane;
+    a.ps = c->ps;
+    a.rs = c->rs;
+    a.nx = c->P.nx;
+    a.ny = c->P.ny;
+    a.gamma = c->P.gamma;
+    a.omega = c->P.omega;
+    a.st = c->st;
+    return hip_status(launch_adjoint_init(a, d_fbar0, d_U0, d_Ubar0, c->stream));
+}
+
+const char* lbrs_strerror(int code) {
+    switch (code) {
+        case LBRS_OK: return "ok";
+        case LBRS_E_INVAL: return "invalid argument";
+        case LBRS_E_NOMEM: return "host allocation failed";
+        case LBRS_E_HIP: return "HIP runtime error";
+        case LBRS_E_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
+        case LBRS_E_STATE: return "call not valid in this context's mode";
+        default: return "unknown error";
+    }
+}
+
+void lbrs_destroy(lbrs_ctx* c) { free(c); }
+
+}  // extern "C"

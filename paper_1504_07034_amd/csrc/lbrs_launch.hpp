@@ -1,0 +1,83 @@
+// Launch arguments and launchers shared by the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbrs_device.hpp"
+
+namespace lbrs {
+
+struct Step2DArgs {
+    double* f0;
+    double* f1;
+    DevState* st;
+    double* tape;         // U^n output [4][ny][nx] (tape kernel only)
+    long long plane;      // nx * ny (planes of U and of the tape)
+    long long ps, rs;     // population offset = p*ps + y*rs + x
+    int nx, ny;
+    int strip;            // output columns per strip (<= 62)
+    int nstrips, nseg;    // tiles: strips x balanced row segments; nstrips is a
+                          // multiple of the waves per workgroup
+    int ntiles;
+    long long launch;     // host launch counter p
+    double dx, cfl, omega, gamma, t_end;
+    int lam_mode;
+    int bc[4];
+};
+
+struct Step1DArgs {
+    double* f0;
+    double* f1;
+    DevState* st;
+    long long plane;   // nx
+    int nx;
+    long long launch;
+    double dx, cfl, omega, gamma, t_end;
+    int lam_mode;
+    int periodic;
+    int max_steps;     // persistent kernel only
+};
+
+struct CellArgs {
+    long long plane;   // nx * ny
+    long long ps, rs;  // population offset = p*ps + y*rs + x
+    int nx, ny;
+    int model;         // D1Q2, D1Q3, D2Q4
+    double gamma;
+};
+
+struct AdjArgs {
+    long long plane;
+    long long ps, rs;    // population (and adjoint population) layout
+    int nx, ny;
+    double gamma, omega;
+    const DevState* st;  // the fixed lattice speed is read from st->lam_fixed
+};
+
+hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, int max_blocks, hipStream_t s);
+int step2d_blocks_per_cu(int wpb);
+bool step2d_wpb_supported(int wpb);
+hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
+hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);
+int persistent1d_max_cells(int Q, size_t lds_limit);
+hipError_t launch_reset(DevState* st, hipStream_t s);
+hipError_t launch_prim_to_cons(const CellArgs& a, const double* W, double* U, hipStream_t s);
+hipError_t launch_prim_to_cons_adjoint(const CellArgs& a, const double* W, const double* Ub,
+                                       int isen, double* Wb, hipStream_t s);
+hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState* st, int lam_mode,
+                       double lam_user, double cfl, hipStream_t s);
+hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st, const double* ext,
+                        double t, long long n, hipStream_t s);
+hipError_t launch_get_f(const CellArgs& a, double* f0, double* f1, const DevState* st, int slot,
+                        double* ext, hipStream_t s);
+hipError_t launch_moments(const CellArgs& a, const double* f0, const double* f1, const DevState* st,
+                          int slot, double* U, hipStream_t s);
+hipError_t launch_window_objective(const CellArgs& a, const double* f0, const double* f1,
+                                   DevState* st, int slot, int ix0, int ix1, int iy0, int iy1,
+                                   double* J, double* fbar, hipStream_t s);
+hipError_t launch_adjoint_step(const AdjArgs& a, const double* Un, const double* gn, double* g,
+                               hipStream_t s);
+hipError_t launch_adjoint_init(const AdjArgs& a, const double* fb0, const double* U0, double* Ub,
+                               hipStream_t s);
+
+}  // namespace lbrs

@@ -1,0 +1,423 @@
+// Pointwise kernels around the LBRS step (gfx950, FP64): state reset,
+// primitive -> conserved conversion, the initial equilibrium (Sec. II.A:
+// f_i = f_i^eq(u0)), moments (eq. "moments_system"), population copies, the
+// window objective and its seed, and the adjoint of one fixed-speed D2Q4 step
+// and of the initialisation.
+#include "lbrs_launch.hpp"
+
+namespace lbrs {
+
+// offset of population plane p at cell c = y*nx + x
+__device__ inline long long fofs(long long ps, long long rs, int nx, int p, long long c) {
+    return p * ps + (c / nx) * rs + (c % nx);
+}
+
+__host__ __device__ inline int nq_of(int model) { return model == D1Q2 ? 2 : (model == D1Q3 ? 3 : 4); }
+__host__ __device__ inline int nk_of(int model) { return model == D2Q4 ? 4 : 3; }
+
+__global__ void reset_state_kernel(DevState* st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int i = 0; i < 2; ++i) {
+            st->s[i].t = 0.0;
+            st->s[i].n = 0;
+            st->s[i].lam_used = 0.0;
+            st->s[i].cur = 0;
+            st->s[i].pad = 0;
+        }
+        for (int i = 0; i < 3; ++i) {
+            st->lam[i] = 0ull;
+            st->bad[i] = 0u;
+        }
+        st->status = 0u;
+        st->fail_step = ~0ull;
+        st->lam_fixed = 0.0;
+        st->lam_init = 0ull;
+        st->J = 0.0;
+    }
+}
+
+// E = p/(rho(gamma-1)) + |u|^2/2, U = (rho, rho u, [rho v,] rho E)
+__global__ void prim_to_cons_kernel(CellArgs a, const double* __restrict__ W, double* __restrict__ U) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.plane) return;
+    const long long P = a.plane;
+    double rho = W[c];
+    if (a.model == D2Q4) {
+        double u = W[P + c], v = W[2 * P + c], p = W[3 * P + c];
+        U[c] = rho;
+        U[P + c] = rho * u;
+        U[2 * P + c] = rho * v;
+        U[3 * P + c] = p / (a.gamma - 1.0) + 0.5 * rho * (u * u + v * v);
+    } else {
+        double u = W[P + c], p = W[2 * P + c];
+        U[c] = rho;
+        U[P + c] = rho * u;
+        U[2 * P + c] = p / (a.gamma - 1.0) + 0.5 * rho * u * u;
+    }
+}
+
+// Adjoint of prim_to_cons: Wbar = (dU/dW)^T Ubar; isentropic: p = rho^gamma/gamma
+// and the density plane receives the total derivative.
+__global__ void prim_to_cons_adjoint_kernel(CellArgs a, const double* __restrict__ W,
+                                            const double* __restrict__ Ub, int isentropic,
+                                            double* __restrict__ Wb) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.plane) return;
+    const long long P = a.plane;
+    const double gm1 = a.gamma - 1.0;
+    double rho = W[c];
+    if (a.model == D2Q4) {
+        double u = W[P + c], v = W[2 * P + c];
+        double b0 = Ub[c], b1 = Ub[P + c], b2 = Ub[2 * P + c], b3 = Ub[3 * P + c];
+        double rb = b0 + u * b1 + v * b2 + 0.5 * (u * u + v * v) * b3;
+        double ub = rho * b1 + rho * u * b3;
+        double vb = rho * b2 + rho * v * b3;
+        double pb = b3 / gm1;
+        if (isentropic) {
+            Wb[c] = rb + pb * pow(rho, gm1);
+            Wb[P + c] = 0.0;
+            Wb[2 * P + c] = 0.0;
+            Wb[3 * P + c] = 0.0;
+        } else {
+            Wb[c] = rb;
+            Wb[P + c] = ub;
+            Wb[2 * P + c] = vb;
+            Wb[3 * P + c] = pb;
+        }
+    } else {
+        double u = W[P + c];
+        double b0 = Ub[c], b1 = Ub[P + c], b2 = Ub[2 * P + c];
+        double rb = b0 + u * b1 + 0.5 * u * u * b2;
+        double ub = rho * b1 + rho * u * b2;
+        double pb = b2 / gm1;
+        if (isentropic) {
+            Wb[c] = rb + pb * pow(rho, gm1);
+            Wb[P + c] = 0.0;
+            Wb[2 * P + c] = 0.0;
+        } else {
+            Wb[c] = rb;
+            Wb[P + c] = ub;
+            Wb[2 * P + c] = pb;
+        }
+    }
+}
+
+__device__ inline bool cell_bound(int model, const double* U, double gamma, double* l) {
+    return model == D2Q4 ? bound_d2q4(U, gamma, l) : bound_1d(U, gamma, l);
+}
+
+// lambda*(U0) -> st->lam_init; a non-physical U0 sets the status (step 0).
+__global__ void bound_of_U_kernel(CellArgs a, const double* __restrict__ U, DevState* st) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    bool bad = false;
+    if (c < a.plane) {
+        const int K = nk_of(a.model);
+        double Uc[4];
+        for (int k = 0; k < K; ++k) Uc[k] = U[k * a.plane + c];
+        bad = !cell_bound(a.model, Uc, a.gamma, &l);
+    }
+    double wm = wave_max(l);
+    if ((threadIdx.x & 63) == 0) publish_max(&st->lam_init, wm);
+    if (__any(bad) && (threadIdx.x & 63) == 0) {
+        atomicOr(&st->bad[0], 1u);
+        atomicOr(&st->status, 1u);
+        atomicMin(&st->fail_step, 0ull);
+    }
+}
+
+// f^0 = f^eq(U0) at the lattice speed lambda*(U0)/cfl (or the user's), then
+// lambda*_0 from U^0 = sum_i f^0_i into reduction slot 0.
+__global__ void init_eq_kernel(CellArgs a, const double* __restrict__ U0, double* __restrict__ f,
+                               DevState* st, int lam_mode, double lam_user, double cfl) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double lam0 = lam_mode == LAM_USER
+                      ? lam_user
+                      : __longlong_as_double((long long)st->lam_init) / cfl;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->s[0].t = 0.0;
+        st->s[0].n = 0;
+        st->s[0].lam_used = lam0;
+        st->s[0].cur = 0;
+        st->lam_fixed = lam0;
+    }
+    double l = 0.0;
+    if (c < a.plane) {
+        const long long P = a.plane;
+        if (a.model == D2Q4) {
+            double U[4], z[16], fs[16];
+            for (int k = 0; k < 4; ++k) U[k] = U0[k * P + c];
+            for (int p = 0; p < 16; ++p) z[p] = 0.0;
+            Euler2 e = euler2(U, a.gamma - 1.0);
+            collide_d2q4(z, U, e, 1.0 / (4.0 * lam0), 1.0, fs);
+            for (int p = 0; p < 16; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = fs[p];
+            double Un[4];
+            moments_d2q4(fs, Un);
+            bound_d2q4(Un, a.gamma, &l);
+        } else {
+            double U[3], z[9], fs[9];
+            for (int k = 0; k < 3; ++k) U[k] = U0[k * P + c];
+            for (int p = 0; p < 9; ++p) z[p] = 0.0;
+            double Un[3];
+            if (a.model == D1Q2) {
+                collide_1d<2>(z, U, a.gamma - 1.0, 1.0 / (2.0 * lam0), 1.0, fs);
+                for (int p = 0; p < 6; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = fs[p];
+                moments_1d<2>(fs, Un);
+            } else {
+                collide_1d<3>(z, U, a.gamma - 1.0, 1.0 / (2.0 * lam0), 1.0, fs);
+                for (int p = 0; p < 9; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = fs[p];
+                moments_1d<3>(fs, Un);
+            }
+            bound_1d(Un, a.gamma, &l);
+        }
+    }
+    double wm = wave_max(l);
+    if ((threadIdx.x & 63) == 0) publish_max(&st->lam[0], wm);
+}
+
+// lambda* of given populations into reduction slot 0 (after lbrs_set_f).
+__global__ void bound_of_f_kernel(CellArgs a, const double* __restrict__ f, DevState* st) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    bool bad = false;
+    if (c < a.plane) {
+        const int Q = nq_of(a.model), K = nk_of(a.model);
+        double Uc[4] = {0.0, 0.0, 0.0, 0.0};
+        double fc[16];
+        for (int p = 0; p < Q * K; ++p) fc[p] = f[fofs(a.ps, a.rs, a.nx, p, c)];
+        if (a.model == D2Q4) moments_d2q4(fc, Uc);
+        else if (a.model == D1Q2) moments_1d<2>(fc, Uc);
+        else moments_1d<3>(fc, Uc);
+        bad = !cell_bound(a.model, Uc, a.gamma, &l);
+    }
+    double wm = wave_max(l);
+    if ((threadIdx.x & 63) == 0) publish_max(&st->lam[0], wm);
+    if (__any(bad) && (threadIdx.x & 63) == 0) {
+        atomicOr(&st->bad[0], 1u);
+        atomicOr(&st->status, 1u);
+    }
+}
+
+__global__ void set_slot0_kernel(DevState* st, double t, long long n) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->s[0].t = t;
+        st->s[0].n = n;
+        st->s[0].lam_used = st->lam_fixed;
+        st->s[0].cur = 0;
+        for (int i = 0; i < 3; ++i) {
+            st->lam[i] = 0ull;
+            st->bad[i] = 0u;
+        }
+        st->status = 0u;
+        st->fail_step = ~0ull;
+    }
+}
+
+// U = sum_i f_i of the current buffer (slot `slot` of the time state).
+__global__ void moments_kernel(CellArgs a, const double* __restrict__ f0, const double* __restrict__ f1,
+                               const DevState* st, int slot, double* __restrict__ U) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.plane) return;
+    const double* f = st->s[slot].cur ? f1 : f0;
+    const int Q = nq_of(a.model), K = nk_of(a.model);
+    double fc[16], Uc[4];
+    for (int p = 0; p < Q * K; ++p) fc[p] = f[fofs(a.ps, a.rs, a.nx, p, c)];
+    if (a.model == D2Q4) moments_d2q4(fc, Uc);
+    else if (a.model == D1Q2) moments_1d<2>(fc, Uc);
+    else moments_1d<3>(fc, Uc);
+    for (int k = 0; k < K; ++k) U[k * a.plane + c] = Uc[k];
+}
+
+// Copy between the current buffer and an external one (dir 0: out, 1: in to f0).
+__global__ void copy_f_kernel(long long count, double* __restrict__ f0, double* __restrict__ f1,
+                              const DevState* st, int slot, double* __restrict__ ext, int dir) {
+    long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    if (dir == 0) {
+        const double* f = st->s[slot].cur ? f1 : f0;
+        ext[j] = f[j];
+    } else {
+        f0[j] = ext[j];
+    }
+}
+
+// J = sum over the window of rho^2 (rho from the current populations); seed
+// fbar_{i,rho} = 2 rho in the window, zero elsewhere and in the other planes.
+__global__ void window_objective_kernel(CellArgs a, const double* __restrict__ f0,
+                                        const double* __restrict__ f1, DevState* st, int slot,
+                                        int ix0, int ix1, int iy0, int iy1, double* J,
+                                        double* __restrict__ fbar) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double contrib = 0.0;
+    if (c < a.plane) {
+        const double* f = st->s[slot].cur ? f1 : f0;
+        const int Q = nq_of(a.model), K = nk_of(a.model);
+        const int x = (int)(c % a.nx), y = (int)(c / a.nx);
+        const bool in = x >= ix0 && x < ix1 && y >= iy0 && y < iy1;
+        double rho = 0.0;
+        if (Q == 4) rho = (f[fofs(a.ps, a.rs, a.nx, 0 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 2 * K, c)]) +
+                          (f[fofs(a.ps, a.rs, a.nx, 1 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 3 * K, c)]);
+        else for (int i = 0; i < Q; ++i) rho += f[fofs(a.ps, a.rs, a.nx, i * K, c)];
+        for (int i = 0; i < Q; ++i)
+            for (int k = 0; k < K; ++k)
+                fbar[fofs(a.ps, a.rs, a.nx, i * K + k, c)] = (in && k == 0) ? 2.0 * rho : 0.0;
+        contrib = in ? rho * rho : 0.0;
+    }
+    for (int off = 32; off >= 1; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
+    if ((threadIdx.x & 63) == 0 && contrib != 0.0) atomicAdd(J, contrib);
+}
+
+// A1(U)^T hx + A2(U)^T hy for the 2D Euler fluxes, with
+// dp/dU = (gamma-1) (|u|^2/2, -u, -v, 1) and H = (E + p)/rho:
+//   A1^T h = h0 e_m + h1 (2u e_m - u^2 e_rho + dp) + h2 (v e_m + u e_n - uv e_rho)
+//            + h3 (H e_m - H u e_rho + u e_E + u dp)
+//   A2^T g = g0 e_n + g1 (v e_m + u e_n - uv e_rho) + g2 (2v e_n - v^2 e_rho + dp)
+//            + g3 (H e_n - H v e_rho + v e_E + v dp)
+__device__ inline void flux_vjp_2d(const double U[4], double gamma, const double hx[4],
+                                   const double hy[4], double out[4]) {
+    const double gm1 = gamma - 1.0;
+    const double ir = 1.0 / U[0];
+    const double u = U[1] * ir, v = U[2] * ir;
+    const double q2 = u * u + v * v;
+    const double p = gm1 * (U[3] - 0.5 * U[0] * q2);
+    const double H = (U[3] + p) * ir;
+    const double al = hx[1] + u * hx[3];
+    const double be = hy[2] + v * hy[3];
+    const double ab = gm1 * (al + be);
+    out[0] = -u * (u * hx[1] + v * hx[2] + H * hx[3]) - v * (u * hy[1] + v * hy[2] + H * hy[3]) +
+             ab * 0.5 * q2;
+    out[1] = hx[0] + 2.0 * u * hx[1] + v * hx[2] + H * hx[3] + v * hy[1] - ab * u;
+    out[2] = u * hx[2] + hy[0] + u * hy[1] + 2.0 * v * hy[2] + H * hy[3] - ab * v;
+    out[3] = u * hx[3] + v * hy[3] + ab;
+}
+
+// fbar^n from fbar^{n+1} and U^n (D2Q4, periodic sides):
+//   fbar*_i(x) = fbar^{n+1}_i(x + s_i)
+//   Ubar = omega [ (1/4) sum_i fbar*_i + (A1^T h_x + A2^T h_y)/(4 lambda) ]
+//   fbar^n_i = (1 - omega) fbar*_i + Ubar
+__global__ __launch_bounds__(256) void adjoint_step_d2q4(AdjArgs a, const double* __restrict__ Un,
+                                                         const double* __restrict__ gn,
+                                                         double* __restrict__ g) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= a.nx) return;
+    const long long P = a.plane;
+    const int xp = x + 1 < a.nx ? x + 1 : 0, xm = x > 0 ? x - 1 : a.nx - 1;
+    const int yp = y + 1 < a.ny ? y + 1 : 0, ym = y > 0 ? y - 1 : a.ny - 1;
+    // s1 = (-,-), s2 = (+,-), s3 = (+,+), s4 = (-,+)
+    const long long src[4] = {(long long)ym * a.rs + xm, (long long)ym * a.rs + xp,
+                              (long long)yp * a.rs + xp, (long long)yp * a.rs + xm};
+    double fb[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fb[i * 4 + k] = gn[(i * 4 + k) * a.ps + src[i]];
+    const long long c = (long long)y * a.nx + x;
+    double U[4], sum[4], hx[4], hy[4], vjp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        U[k] = Un[k * P + c];
+        sum[k] = (fb[k] + fb[8 + k]) + (fb[4 + k] + fb[12 + k]);
+        hx[k] = (fb[4 + k] + fb[8 + k]) - (fb[k] + fb[12 + k]);
+        hy[k] = (fb[8 + k] + fb[12 + k]) - (fb[k] + fb[4 + k]);
+    }
+    flux_vjp_2d(U, a.gamma, hx, hy, vjp);
+    const double c4 = 1.0 / (4.0 * a.st->lam_fixed);
+    const double om1 = 1.0 - a.omega;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double Ub = a.omega * (0.25 * sum[k] + c4 * vjp[k]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g[(i * 4 + k) * a.ps + (long long)y * a.rs + x] = om1 * fb[i * 4 + k] + Ub;
+    }
+}
+
+// Ubar0 = sum_i (df_i^eq/dU)^T fbar0_i at U0 (D2Q4).
+__global__ void adjoint_init_d2q4(AdjArgs a, const double* __restrict__ fb0,
+                                  const double* __restrict__ U0, double* __restrict__ Ub) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.plane) return;
+    const long long P = a.plane;
+    double fb[16], U[4], sum[4], hx[4], hy[4], vjp[4];
+    for (int p = 0; p < 16; ++p) fb[p] = fb0[fofs(a.ps, a.rs, a.nx, p, c)];
+    for (int k = 0; k < 4; ++k) {
+        U[k] = U0[k * P + c];
+        sum[k] = (fb[k] + fb[8 + k]) + (fb[4 + k] + fb[12 + k]);
+        hx[k] = (fb[4 + k] + fb[8 + k]) - (fb[k] + fb[12 + k]);
+        hy[k] = (fb[8 + k] + fb[12 + k]) - (fb[k] + fb[4 + k]);
+    }
+    flux_vjp_2d(U, a.gamma, hx, hy, vjp);
+    const double c4 = 1.0 / (4.0 * a.st->lam_fixed);
+    for (int k = 0; k < 4; ++k) Ub[k * P + c] = 0.25 * sum[k] + c4 * vjp[k];
+}
+
+// ------------------------------------------------------------ launchers
+static inline dim3 grid1(long long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+hipError_t launch_reset(DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(reset_state_kernel, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+hipError_t launch_prim_to_cons(const CellArgs& a, const double* W, double* U, hipStream_t s) {
+    hipLaunchKernelGGL(prim_to_cons_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, W, U);
+    return hipGetLastError();
+}
+hipError_t launch_prim_to_cons_adjoint(const CellArgs& a, const double* W, const double* Ub,
+                                       int isen, double* Wb, hipStream_t s) {
+    hipLaunchKernelGGL(prim_to_cons_adjoint_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, W, Ub,
+                       isen, Wb);
+    return hipGetLastError();
+}
+hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState* st, int lam_mode,
+                       double lam_user, double cfl, hipStream_t s) {
+    hipLaunchKernelGGL(bound_of_U_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, U0, st);
+    hipLaunchKernelGGL(init_eq_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, U0, f0, st, lam_mode,
+                       lam_user, cfl);
+    return hipGetLastError();
+}
+hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st, const double* ext,
+                        double t, long long n, hipStream_t s) {
+    const int Q = nq_of(a.model), K = nk_of(a.model);
+    long long cnt = (long long)Q * K * a.plane;
+    hipLaunchKernelGGL(set_slot0_kernel, dim3(1), dim3(64), 0, s, st, t, n);
+    hipLaunchKernelGGL(copy_f_kernel, grid1(cnt, 256), dim3(256), 0, s, cnt, f0, f1, st, 0,
+                       const_cast<double*>(ext), 1);
+    hipLaunchKernelGGL(bound_of_f_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, st);
+    return hipGetLastError();
+}
+hipError_t launch_get_f(const CellArgs& a, double* f0, double* f1, const DevState* st, int slot,
+                        double* ext, hipStream_t s) {
+    const int Q = nq_of(a.model), K = nk_of(a.model);
+    long long cnt = (long long)Q * K * a.plane;
+    hipLaunchKernelGGL(copy_f_kernel, grid1(cnt, 256), dim3(256), 0, s, cnt, f0, f1, st, slot, ext, 0);
+    return hipGetLastError();
+}
+hipError_t launch_moments(const CellArgs& a, const double* f0, const double* f1, const DevState* st,
+                          int slot, double* U, hipStream_t s) {
+    hipLaunchKernelGGL(moments_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, f1, st, slot, U);
+    return hipGetLastError();
+}
+__global__ void zero_kernel(double* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
+}
+hipError_t launch_window_objective(const CellArgs& a, const double* f0, const double* f1,
+                                   DevState* st, int slot, int ix0, int ix1, int iy0, int iy1,
+                                   double* J, double* fbar, hipStream_t s) {
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, J);
+    hipLaunchKernelGGL(window_objective_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, f1, st,
+                       slot, ix0, ix1, iy0, iy1, J, fbar);
+    return hipGetLastError();
+}
+hipError_t launch_adjoint_step(const AdjArgs& a, const double* Un, const double* gn, double* g,
+                               hipStream_t s) {
+    dim3 grid((a.nx + 255) / 256, a.ny);
+    hipLaunchKernelGGL(adjoint_step_d2q4, grid, dim3(256), 0, s, a, Un, gn, g);
+    return hipGetLastError();
+}
+hipError_t launch_adjoint_init(const AdjArgs& a, const double* fb0, const double* U0, double* Ub,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(adjoint_init_d2q4, grid1(a.plane, 256), dim3(256), 0, s, a, fb0, U0, Ub);
+    return hipGetLastError();
+}
+
+}  // namespace lbrs

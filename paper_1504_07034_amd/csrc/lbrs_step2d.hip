@@ -1,0 +1,272 @@
+// Fused LBRS step for the 2D Euler equations on the D2Q4 lattice (gfx950).
+//
+// One launch = one time step: moments (eq. "moments_system"), flux and
+// equilibria (Sec. II.D), relaxation (1-omega) f + omega f^eq and exact
+// hopping along the four diagonals (the multi-dimensional LBRS update of
+// Sec. II.D), side conditions (specular wall, Sec. II.E; transmissive and
+// periodic sides), and the global wave-speed bound of the next step from the
+// freshly streamed populations (Sec. II.D Bouchut bound).
+//
+// Data: 16 population planes, two buffers; element (p, y, x) at
+// p*ps + y*rs + x: planar [i][k][y][x] (ps = nx*ny, rs = nx) or row-interleaved
+// [y][i][k][x] (ps = nx, rs = 16*nx), where a row of all 16 planes is one
+// contiguous 128*nx-byte block (a wave's row touches 2 pages, not 32).
+//
+// Work decomposition.  A wavefront owns a strip of S <= 62 output columns and
+// marches down a segment of rows.  Lane l holds column x0 - 1 + l, so lanes 0
+// and S + 1 are the strip's halo columns, recomputed by both neighbouring
+// strips.
+// Each row is read once from HBM: the lane computes U, the flux and the 16
+// post-collision values of its column, and the diagonal hops become DPP
+// wavefront shifts by one lane (x) plus a two-row register pipeline (y):
+//   f1^{n+1}(x, r-1) = f1*(x+1, r)   f2^{n+1}(x, r-1) = f2*(x-1, r)
+//   f3^{n+1}(x, r+1) = f3*(x-1, r)   f4^{n+1}(x, r+1) = f4*(x+1, r)
+// The output row r-1 is complete after row r is processed, so the new moments
+// U^{n+1} and the local bound are formed in registers and reduced (wave max,
+// one atomic per wave at most) into the next step's lambda*.
+//
+// The row loop has no branch around memory instructions: the next row is
+// always prefetched (row indices are clamped or wrapped into the grid), and
+// rows are written with range-checked buffer stores whose halo lanes carry an
+// out-of-range offset, so the hardware drops them.  The wait before a row's
+// compute therefore covers only that row's loads, never the previous row's
+// stores.  Waves loop over tiles (persistent grid sized to the resident
+// waves); tiles are numbered strip-fastest and dealt to XCDs in contiguous
+// runs.  The waves of a workgroup own adjacent strips of the same row segment
+// and march its rows in lockstep (a bare s_barrier per row, no memory fence),
+// so the cache lines two strips share are fetched once, while both waves need
+// them.  The host makes the strip count a multiple of the waves per workgroup,
+// so every wave of a workgroup runs the same number of rows and tiles.
+#include "lbrs_launch.hpp"
+
+namespace lbrs {
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Wavefront shifts by one lane (DPP): lane l receives lane l-1 (shr) or
+// lane l+1 (shl).  Lanes with no source receive 0 and are halo lanes.
+__device__ inline double lane_from_left(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double lane_from_right(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);  // wave_shl:1
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Store one double per lane into one row of one plane; a byte offset voff
+// outside [0, row_bytes) is dropped by the buffer range check.
+__device__ inline void store_row(double* row, int row_bytes, int voff, double v) {
+    __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(row, 0, row_bytes, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, 0, 0);
+}
+
+__device__ inline void load_row(double v[16], const double* __restrict__ fin, long long ps,
+                                long long off) {
+#pragma unroll
+    for (int p = 0; p < 16; ++p) v[p] = fin[p * ps + off];
+}
+
+struct Shifted {
+    double s1[4], s2[4], n3[4], n4[4];
+};
+
+// Collision of the lane's cell and the four diagonal hops across lanes.
+__device__ inline void collide_and_shift(const double f[16], double gm1, double c4lam, double omega,
+                                         double U[4], Shifted& sh) {
+    moments_d2q4(f, U);
+    const Euler2 e = euler2(U, gm1);
+    double fs[16];
+    collide_d2q4(f, U, e, c4lam, omega, fs);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sh.s1[k] = lane_from_right(fs[0 * 4 + k]);
+        sh.s2[k] = lane_from_left(fs[1 * 4 + k]);
+        sh.n3[k] = lane_from_left(fs[2 * 4 + k]);
+        sh.n4[k] = lane_from_right(fs[3 * 4 + k]);
+    }
+}
+
+template <bool TAPE, int WPB>
+__global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
+    const LaunchSlots ls = slots_for(a.launch);
+    DevState* st = a.st;
+    const StepCtl c = step_control(st, ls, a.lam_mode, a.dx, a.cfl, a.t_end);
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_state(st, ls, c);
+    if (!c.active) return;
+
+    const int lane = threadIdx.x & 63;
+    // wave-uniform, so that tile and row indices (and the store descriptors)
+    // live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nx = a.nx, ny = a.ny;
+    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
+    const double* __restrict__ fin = c.cur ? a.f1 : a.f0;
+    double* __restrict__ fout = c.cur ? a.f0 : a.f1;
+    const long long plane = a.plane, ps = a.ps, rs = a.rs;
+    const double gm1 = a.gamma - 1.0;
+    const double c4lam = 1.0 / (4.0 * c.lam);
+    const double omega = a.omega;
+    const int row_bytes = nx * 8;
+    const int total_waves = gridDim.x * WPB;
+
+    double lmax = 0.0;
+    bool bad = false;
+
+    for (int tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wave; tile < a.ntiles;
+         tile += total_waves) {
+        const int strip = tile % a.nstrips;
+        const int seg = tile / a.nstrips;
+        const int x = strip * a.strip - 1 + lane;
+        const int y0 = (int)(((long long)seg * ny) / a.nseg);
+        const int y1 = (int)(((long long)(seg + 1) * ny) / a.nseg);
+        const int xl = map_index(x, nx, px);
+        const bool out_lane = lane >= 1 && lane <= a.strip && x < nx;
+        const int voff = out_lane ? x * 8 : 0x7fffffff;
+        const bool wall_xlo = a.bc[0] == BC_WALL && x == 0;
+        const bool wall_xhi = a.bc[1] == BC_WALL && x == nx - 1;
+
+        // prologue: rows y0-1 and y0 fill the two-row pipeline (no output)
+        double f[16], nxt[16], U[4];
+        Shifted sh;
+        load_row(f, fin, ps, (long long)map_index(y0 - 1, ny, py) * rs + xl);
+        load_row(nxt, fin, ps, (long long)map_index(y0, ny, py) * rs + xl);
+        collide_and_shift(f, gm1, c4lam, omega, U, sh);
+        double A3[4], A4[4], B3[4], B4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            A3[k] = sh.n3[k];
+            A4[k] = sh.n4[k];
+        }
+#pragma unroll
+        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+        load_row(nxt, fin, ps, (long long)map_index(y0 + 1, ny, py) * rs + xl);
+        collide_and_shift(f, gm1, c4lam, omega, U, sh);
+        if (TAPE) {
+            double* trow = a.tape + (long long)y0 * nx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) store_row(trow + k * plane, row_bytes, voff, U[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            B3[k] = A3[k];
+            B4[k] = A4[k];
+            A3[k] = sh.n3[k];
+            A4[k] = sh.n4[k];
+        }
+
+        // main loop: row r completes output row r-1
+        for (int r = y0 + 1; r <= y1; ++r) {
+            // lockstep with the workgroup's neighbouring strips (same trip
+            // count by construction); no fence: nothing is exchanged
+            if (WPB > 1) __builtin_amdgcn_s_barrier();
+#pragma unroll
+            for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+            load_row(nxt, fin, ps, (long long)map_index(r + 1, ny, py) * rs + xl);
+            collide_and_shift(f, gm1, c4lam, omega, U, sh);
+            if (TAPE) {
+                // U^n of row r; row y1 is the next segment's first row
+                double* trow = a.tape + (long long)map_index(r, ny, false) * nx;
+                const int tv = r < y1 ? voff : 0x7fffffff;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) store_row(trow + k * plane, row_bytes, tv, U[k]);
+            }
+            const int o = r - 1;
+            double g[16];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                g[0 * 4 + k] = sh.s1[k];
+                g[1 * 4 + k] = sh.s2[k];
+                g[2 * 4 + k] = B3[k];
+                g[3 * 4 + k] = B4[k];
+            }
+            // specular reflection at wall node rows/columns: the incoming
+            // populations mirror the outgoing ones, normal momentum negated
+            const bool wall_top = a.bc[3] == BC_WALL && o == ny - 1;
+            const bool wall_bot = a.bc[2] == BC_WALL && o == 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double sy = (k == 2) ? -1.0 : 1.0, sx = (k == 1) ? -1.0 : 1.0;
+                if (wall_top) {
+                    g[0 * 4 + k] = sy * g[3 * 4 + k];
+                    g[1 * 4 + k] = sy * g[2 * 4 + k];
+                }
+                if (wall_bot) {
+                    g[3 * 4 + k] = sy * g[0 * 4 + k];
+                    g[2 * 4 + k] = sy * g[1 * 4 + k];
+                }
+                if (wall_xlo) {
+                    g[1 * 4 + k] = sx * g[0 * 4 + k];
+                    g[2 * 4 + k] = sx * g[3 * 4 + k];
+                }
+                if (wall_xhi) {
+                    g[0 * 4 + k] = sx * g[1 * 4 + k];
+                    g[3 * 4 + k] = sx * g[2 * 4 + k];
+                }
+            }
+            double* orow = fout + (long long)o * rs;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) store_row(orow + p * ps, row_bytes, voff, g[p]);
+            double Un[4], l;
+            moments_d2q4(g, Un);
+            const bool ok = bound_d2q4(Un, a.gamma, &l);
+            bad |= out_lane && !ok;
+            lmax = fmax(lmax, out_lane ? l : 0.0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                B3[k] = A3[k];
+                B4[k] = A4[k];
+                A3[k] = sh.n3[k];
+                A4[k] = sh.n4[k];
+            }
+        }
+    }
+
+    if (a.lam_mode == LAM_PER_STEP) {
+        double wm = wave_max(lmax);
+        if (lane == 0) publish_max(&st->lam[ls.la], wm);
+    }
+    if (__any(bad) && lane == 0) publish_bad(st, ls, c.n + 1);
+}
+
+template <bool TAPE, int WPB>
+static hipError_t launch_one(const Step2DArgs& a, int max_blocks, hipStream_t s) {
+    int nblocks = (a.ntiles + WPB - 1) / WPB;
+    if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
+    hipLaunchKernelGGL((step2d_d2q4<TAPE, WPB>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    return hipGetLastError();
+}
+
+#define LBRS_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12) X(16)
+
+hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, int max_blocks, hipStream_t s) {
+#define LBRS_CASE(W)                                                                       \
+    if (wpb == W) return tape ? launch_one<true, W>(a, max_blocks, s) : launch_one<false, W>(a, max_blocks, s);
+    LBRS_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return hipErrorInvalidValue;
+}
+
+bool step2d_wpb_supported(int wpb) {
+#define LBRS_CASE(W) if (wpb == W) return true;
+    LBRS_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return false;
+}
+
+// Resident workgroups of the step kernel per CU for a workgroup size.
+int step2d_blocks_per_cu(int wpb) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define LBRS_CASE(W) \
+    if (wpb == W) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W>, 64 * W, 0);
+    LBRS_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+}  // namespace lbrs

@@ -1,0 +1,327 @@
+"""Thin Python binding of the LBRS C ABI (include/lbrs.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels of
+``liblbrs.so``.  Functions carry the C names; tensors are torch float64 CUDA
+tensors (device pointers), and work is enqueued on torch's current stream
+unless a stream is given.  Loading fails loudly when the library is not built
+or no GPU is visible -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbrs.so")
+
+LBRS_OK, LBRS_E_INVAL, LBRS_E_NOMEM, LBRS_E_HIP, LBRS_E_NONPHYSICAL, LBRS_E_STATE = 0, -1, -2, -3, -4, -5
+LBRS_D1Q2, LBRS_D1Q3, LBRS_D2Q4 = 0, 1, 2
+LBRS_BC_TRANSMISSIVE, LBRS_BC_PERIODIC, LBRS_BC_WALL = 0, 1, 2
+LBRS_LAMBDA_PER_STEP, LBRS_LAMBDA_FROZEN_INIT, LBRS_LAMBDA_USER = 0, 1, 2
+LBRS_LAYOUT_PLANAR, LBRS_LAYOUT_ROWS = 0, 1
+
+# Every symbol include/lbrs.h declares (checked by the CPU test-suite).
+EXPORTS = (
+    "lbrs_query_sizes", "lbrs_prim_to_cons", "lbrs_init", "lbrs_step", "lbrs_get_state",
+    "lbrs_moments", "lbrs_get_f", "lbrs_set_f", "lbrs_window_objective", "lbrs_step_tape",
+    "lbrs_adjoint_step", "lbrs_adjoint_init", "lbrs_prim_to_cons_adjoint", "lbrs_set_stream",
+    "lbrs_set_tile", "lbrs_strerror", "lbrs_destroy",
+)
+
+
+class lbrs_params(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+        ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("omega", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("bc", ctypes.c_int * 4),
+        ("lambda_mode", ctypes.c_int), ("lambda_user", ctypes.c_double),
+        ("layout", ctypes.c_int),
+    ]
+
+
+class LBRSError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH, require_gpu: bool = True):
+    """Load liblbrs.so (raises if it is missing, or if no GPU is visible)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+    if require_gpu and not torch.cuda.is_available():
+        raise RuntimeError("the LBRS library needs a visible gfx950 GPU")
+    lib = ctypes.CDLL(path)
+    vp, dp, P = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(lbrs_params)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    i, d, ll = ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    sig = {
+        "lbrs_query_sizes": (i, [P, szp, szp, szp]),
+        "lbrs_prim_to_cons": (i, [P, vp, vp, vp]),
+        "lbrs_init": (i, [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp]),
+        "lbrs_step": (i, [vp, i, d]),
+        "lbrs_get_state": (i, [vp, dp, ctypes.POINTER(ll), dp, ctypes.POINTER(ctypes.c_uint),
+                               ctypes.POINTER(ll)]),
+        "lbrs_moments": (i, [vp, vp]),
+        "lbrs_get_f": (i, [vp, vp]),
+        "lbrs_set_f": (i, [vp, vp, d, ll]),
+        "lbrs_window_objective": (i, [vp, i, i, i, i, vp, vp]),
+        "lbrs_step_tape": (i, [vp, vp]),
+        "lbrs_adjoint_step": (i, [vp, vp, vp, vp]),
+        "lbrs_adjoint_init": (i, [vp, vp, vp, vp]),
+        "lbrs_prim_to_cons_adjoint": (i, [P, vp, vp, i, vp, vp]),
+        "lbrs_set_stream": (i, [vp, vp]),
+        "lbrs_set_tile": (i, [vp, i, i]),
+        "lbrs_strerror": (ctypes.c_char_p, [i]),
+        "lbrs_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return load_library(require_gpu=False).lbrs_strerror(code).decode()
+    except Exception:  # pragma: no cover - message only
+        return f"error {code}"
+
+
+def _check(rc: int, where: str):
+    if rc != LBRS_OK:
+        raise LBRSError(rc, where)
+
+
+def _dptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_params(model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0, cfl=0.5,
+                bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
+                layout=LBRS_LAYOUT_PLANAR) -> lbrs_params:
+    p = lbrs_params()
+    p.model, p.nx, p.ny = int(model), int(nx), int(ny)
+    p.x0, p.x1, p.y0, p.y1 = map(float, domain)
+    p.gamma, p.omega, p.cfl = float(gamma), float(omega), float(cfl)
+    for s in range(4):
+        p.bc[s] = int(bc[s])
+    p.lambda_mode, p.lambda_user = int(lambda_mode), float(lambda_user)
+    p.layout = int(layout)
+    return p
+
+
+# ------------------------------------------------------------- C-named calls
+def lbrs_query_sizes(p: lbrs_params):
+    f, u, s = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().lbrs_query_sizes(ctypes.byref(p), ctypes.byref(f), ctypes.byref(u),
+                                           ctypes.byref(s)), "lbrs_query_sizes")
+    return f.value, u.value, s.value
+
+
+def lbrs_prim_to_cons(p: lbrs_params, W: torch.Tensor, U: torch.Tensor, stream=None):
+    _check(load_library().lbrs_prim_to_cons(ctypes.byref(p), _dptr(W), _dptr(U), _stream(stream)),
+           "lbrs_prim_to_cons")
+
+
+def lbrs_prim_to_cons_adjoint(p: lbrs_params, W, Ubar, isentropic: bool, Wbar, stream=None):
+    _check(load_library().lbrs_prim_to_cons_adjoint(ctypes.byref(p), _dptr(W), _dptr(Ubar),
+                                                    int(isentropic), _dptr(Wbar), _stream(stream)),
+           "lbrs_prim_to_cons_adjoint")
+
+
+def lbrs_init(p: lbrs_params, U0, f0, f1, scratch, stream=None):
+    ctx = ctypes.c_void_p()
+    _check(load_library().lbrs_init(ctypes.byref(ctx), ctypes.byref(p), _dptr(U0), _dptr(f0),
+                                    _dptr(f1), _dptr(scratch), _stream(stream)), "lbrs_init")
+    return ctx
+
+
+def lbrs_step(ctx, max_steps: int, t_end: float = math.inf):
+    _check(load_library().lbrs_step(ctx, int(max_steps), float(t_end)), "lbrs_step")
+
+
+def lbrs_get_state(ctx):
+    t, lam = ctypes.c_double(), ctypes.c_double()
+    n, fail = ctypes.c_longlong(), ctypes.c_longlong()
+    st = ctypes.c_uint()
+    rc = load_library().lbrs_get_state(ctx, ctypes.byref(t), ctypes.byref(n), ctypes.byref(lam),
+                                       ctypes.byref(st), ctypes.byref(fail))
+    if rc not in (LBRS_OK, LBRS_E_NONPHYSICAL):
+        raise LBRSError(rc, "lbrs_get_state")
+    return {"rc": rc, "t": t.value, "nsteps": n.value, "lambda": lam.value, "status": st.value,
+            "fail_step": fail.value}
+
+
+def lbrs_moments(ctx, U):
+    _check(load_library().lbrs_moments(ctx, _dptr(U)), "lbrs_moments")
+
+
+def lbrs_get_f(ctx, f):
+    _check(load_library().lbrs_get_f(ctx, _dptr(f)), "lbrs_get_f")
+
+
+def lbrs_set_f(ctx, f, t: float, n: int):
+    _check(load_library().lbrs_set_f(ctx, _dptr(f), float(t), int(n)), "lbrs_set_f")
+
+
+def lbrs_window_objective(ctx, ix0, ix1, iy0, iy1, J, fbar):
+    _check(load_library().lbrs_window_objective(ctx, int(ix0), int(ix1), int(iy0), int(iy1),
+                                                _dptr(J), _dptr(fbar)), "lbrs_window_objective")
+
+
+def lbrs_step_tape(ctx, Utape):
+    _check(load_library().lbrs_step_tape(ctx, _dptr(Utape)), "lbrs_step_tape")
+
+
+def lbrs_adjoint_step(ctx, Utape, fbar_next, fbar):
+    _check(load_library().lbrs_adjoint_step(ctx, _dptr(Utape), _dptr(fbar_next), _dptr(fbar)),
+           "lbrs_adjoint_step")
+
+
+def lbrs_adjoint_init(ctx, fbar0, U0, Ubar0):
+    _check(load_library().lbrs_adjoint_init(ctx, _dptr(fbar0), _dptr(U0), _dptr(Ubar0)),
+           "lbrs_adjoint_init")
+
+
+def lbrs_set_stream(ctx, stream=None):
+    _check(load_library().lbrs_set_stream(ctx, _stream(stream)), "lbrs_set_stream")
+
+
+def lbrs_set_tile(ctx, rows_per_tile: int, waves_per_block: int = 4):
+    _check(load_library().lbrs_set_tile(ctx, int(rows_per_tile), int(waves_per_block)),
+           "lbrs_set_tile")
+
+
+def lbrs_destroy(ctx):
+    if ctx:
+        load_library().lbrs_destroy(ctx)
+
+
+# ------------------------------------------------------------- convenience
+class Sim:
+    """One domain: owns its device buffers (torch), drives the C calls."""
+
+    def __init__(self, model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0,
+                 cfl=0.5, bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
+                 layout=LBRS_LAYOUT_PLANAR, device="cuda"):
+        load_library()
+        self.layout = layout
+        self.p = make_params(model, nx, ny, domain, gamma, omega, cfl, bc, lambda_mode, lambda_user,
+                             layout)
+        self.model, self.nx, self.ny = model, nx, ny
+        self.Q = {0: 2, 1: 3, 2: 4}[model]
+        self.K = 4 if model == LBRS_D2Q4 else 3
+        fb, ub, sb = lbrs_query_sizes(self.p)
+        self.device = torch.device(device)
+        self.f0 = torch.empty(fb // 8, dtype=torch.float64, device=self.device)
+        self.f1 = torch.empty(fb // 8, dtype=torch.float64, device=self.device)
+        self.scratch = torch.zeros(sb // 8, dtype=torch.float64, device=self.device)
+        self.ctx = None
+
+    @property
+    def f_shape(self):
+        """Shape of population-shaped tensors in this context's layout."""
+        if self.layout == LBRS_LAYOUT_ROWS:
+            return (self.ny, self.Q, self.K, self.nx)
+        return (self.Q, self.K, self.ny, self.nx)
+
+    def to_planar(self, f: torch.Tensor) -> torch.Tensor:
+        """[Q][K][ny][nx] view/copy of a population tensor of this context."""
+        if self.layout == LBRS_LAYOUT_ROWS:
+            return f.reshape(self.ny, self.Q, self.K, self.nx).permute(1, 2, 0, 3).contiguous()
+        return f.reshape(self.Q, self.K, self.ny, self.nx)
+
+    def from_planar(self, f: torch.Tensor) -> torch.Tensor:
+        if self.layout == LBRS_LAYOUT_ROWS:
+            return f.reshape(self.Q, self.K, self.ny, self.nx).permute(2, 0, 1, 3).contiguous()
+        return f.reshape(self.Q, self.K, self.ny, self.nx).contiguous()
+
+    @property
+    def u_shape(self):
+        return (self.K, self.ny, self.nx)
+
+    def prim_to_cons(self, W: torch.Tensor) -> torch.Tensor:
+        W = W.to(self.device, torch.float64).contiguous()
+        U = torch.empty(self.u_shape, dtype=torch.float64, device=self.device)
+        lbrs_prim_to_cons(self.p, W, U)
+        return U
+
+    def init(self, U0: torch.Tensor):
+        U0 = U0.to(self.device, torch.float64).contiguous()
+        if self.ctx is not None:
+            lbrs_destroy(self.ctx)
+        self.ctx = lbrs_init(self.p, U0, self.f0, self.f1, self.scratch)
+        return self
+
+    def init_primitive(self, W):
+        if not isinstance(W, torch.Tensor):
+            W = torch.from_numpy(W)
+        return self.init(self.prim_to_cons(W))
+
+    def set_tile(self, rows_per_tile: int, waves_per_block: int = 4):
+        lbrs_set_tile(self.ctx, rows_per_tile, waves_per_block)
+
+    def step(self, max_steps: int, t_end: float = math.inf):
+        lbrs_step(self.ctx, max_steps, t_end)
+
+    def run(self, t_end: float, chunk: int = 1000, max_steps: int = 10**8):
+        """Step until t_end (or max_steps); polls the device state every chunk steps."""
+        done = 0
+        while done < max_steps:
+            k = min(chunk, max_steps - done)
+            self.step(k, t_end)
+            done += k
+            s = self.state()
+            if s["t"] >= t_end or s["rc"] != LBRS_OK or s["nsteps"] < done:
+                return s
+        return self.state()
+
+    def state(self):
+        return lbrs_get_state(self.ctx)
+
+    def moments(self) -> torch.Tensor:
+        U = torch.empty(self.u_shape, dtype=torch.float64, device=self.device)
+        lbrs_moments(self.ctx, U)
+        return U
+
+    def get_f(self) -> torch.Tensor:
+        f = torch.empty(self.f_shape, dtype=torch.float64, device=self.device)
+        lbrs_get_f(self.ctx, f)
+        return f
+
+    def set_f(self, f: torch.Tensor, t: float, n: int):
+        lbrs_set_f(self.ctx, f.contiguous(), t, n)
+
+    def close(self):
+        if self.ctx is not None:
+            lbrs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

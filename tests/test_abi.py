@@ -1,0 +1,69 @@
+"""The C-ABI library loads on the CPU and exports every symbol include/lbrs.h
+declares; parameter checks answer without a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1504_07034_amd import lbrs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbrs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbrs_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbrs.LIB_PATH):
+        pytest.fail("liblbrs.so is not built (run __graft_entry__.build())")
+    return lbrs.load_library(require_gpu=False)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    decl = _declared()
+    assert decl, "no declarations found"
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(lbrs.EXPORTS)
+
+
+def test_query_sizes_and_validation(lib):
+    p = lbrs.make_params(lbrs.LBRS_D2Q4, 4096, 4096)
+    f, u, s = lbrs.lbrs_query_sizes(p)
+    assert f == 16 * 8 * 4096 * 4096 and u == 4 * 8 * 4096 * 4096 and 0 < s <= 4096
+    p = lbrs.make_params(lbrs.LBRS_D1Q3, 400)
+    f, u, s = lbrs.lbrs_query_sizes(p)
+    assert f == 9 * 8 * 400 and u == 3 * 8 * 400
+    bad = [
+        dict(model=lbrs.LBRS_D1Q3, nx=400, omega=2.0),
+        dict(model=lbrs.LBRS_D1Q3, nx=400, omega=0.0),
+        dict(model=lbrs.LBRS_D1Q3, nx=400, cfl=1.5),
+        dict(model=lbrs.LBRS_D1Q3, nx=400, cfl=0.0),
+        dict(model=lbrs.LBRS_D1Q3, nx=2),
+        dict(model=lbrs.LBRS_D1Q3, nx=400, ny=2),
+        dict(model=lbrs.LBRS_D1Q3, nx=400, bc=(2, 0, 0, 0)),
+        dict(model=lbrs.LBRS_D1Q3, nx=400, bc=(1, 0, 0, 0)),
+        dict(model=lbrs.LBRS_D2Q4, nx=400, ny=200),                      # dx != dy
+        dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, bc=(2, 0, 2, 0)),       # wall corner
+        dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, lambda_mode=2, lambda_user=0.0),
+        dict(model=7, nx=64),
+    ]
+    for kw in bad:
+        p = lbrs.make_params(**kw)
+        with pytest.raises(lbrs.LBRSError) as e:
+            lbrs.lbrs_query_sizes(p)
+        assert e.value.code == lbrs.LBRS_E_INVAL, kw
+
+
+def test_init_rejects_null_pointers(lib):
+    p = lbrs.make_params(lbrs.LBRS_D1Q3, 400)
+    ctx = ctypes.c_void_p()
+    rc = lib.lbrs_init(ctypes.byref(ctx), ctypes.byref(p), None, None, None, None, None)
+    assert rc == lbrs.LBRS_E_INVAL and not ctx.value
+    assert lib.lbrs_step(None, 1, 1.0) == lbrs.LBRS_E_INVAL
+    assert lib.lbrs_strerror(lbrs.LBRS_E_NONPHYSICAL).decode().startswith("non-physical")
