@@ -184,12 +184,40 @@ int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar
  * FROZEN_INIT or USER mode only.  Asynchronous. */
 int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, double* d_Ubar0);
 
-/* Adjoint of lbrs_prim_to_cons: given W and Ubar = dJ/dU, write Wbar = dJ/dW.
- * If isentropic != 0, the pressure is taken as p = rho^gamma/gamma and the
- * result's density plane is the total derivative dJ/drho0 (the other planes
- * are then zero).  Enqueued on hip_stream. */
+/* Adjoint of lbrs_prim_to_cons: given W and Ubar = dJ/dU, write Wbar = dJ/dW
+ * = (dU/dW)^T Ubar.  [K][ny][nx] each; d_Wbar may alias neither input.
+ * Enqueued on hip_stream. */
 int lbrs_prim_to_cons_adjoint(const lbrs_params* p, const double* d_W, const double* d_Ubar,
-                              int isentropic, double* d_Wbar, void* hip_stream);
+                              double* d_Wbar, void* hip_stream);
+
+/* Gas at rest with the isentropic pressure p = rho^gamma/gamma (the initial
+ * state of an acoustic pulse): U = (rho, 0, [0,] rho^gamma/(gamma(gamma-1))).
+ * d_rho [ny][nx], d_U [K][ny][nx].  Enqueued on hip_stream. */
+int lbrs_isentropic_to_cons(const lbrs_params* p, const double* d_rho, double* d_U,
+                            void* hip_stream);
+
+/* Its adjoint: rhobar = Ubar_rho + Ubar_E rho^(gamma-1)/(gamma-1) = dJ/drho0. */
+int lbrs_isentropic_to_cons_adjoint(const lbrs_params* p, const double* d_rho,
+                                    const double* d_Ubar, double* d_rhobar, void* hip_stream);
+
+/* Forward sweep of a checkpointed gradient (FROZEN_INIT or USER mode, 2D):
+ * from the current state take nsteps steps, first copying the populations
+ * before steps j*segment (j = 0 .. ceil(nsteps/segment)-1) into
+ * d_ckpt + j*Q*K*nx*ny.  With segment ~ sqrt(nsteps) the store holds
+ * ~sqrt(nsteps) population sets.  Asynchronous. */
+int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ckpt);
+
+/* Backward sweep (periodic D2Q4, FROZEN_INIT or USER mode): on entry d_fbar
+ * holds dJ/df after the nsteps steps of lbrs_forward_checkpointed (called
+ * last on this context, with the same nsteps, segment and d_ckpt); on return
+ * it holds dJ/df^0.  Segments are processed last to first: each is recomputed
+ * from its checkpoint with lbrs_step_tape, storing U^n in d_tape (segment
+ * planes sets of K*nx*ny doubles), then lbrs_adjoint_step runs backwards
+ * through it.  d_work is one population-sized buffer.  Waits once for the
+ * stream at entry; the rest is asynchronous.  Leaves the context at the end
+ * of the first segment. */
+int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const double* d_ckpt,
+                               double* d_tape, double* d_fbar, double* d_work);
 
 /* Change the stream later calls enqueue on. */
 int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);

@@ -89,6 +89,8 @@ def _load():
         lib.orc_run_tangent.argtypes = [P, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_long,
                                         dp, dp]
         lib.orc_run_tangent.restype = ctypes.c_int
+        lib.orc_init_tangent.argtypes = [P, dp, dp, ctypes.c_double, dp, dp]
+        lib.orc_init_tangent.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -239,3 +241,16 @@ def run_tangent(P: Problem, W0, dW0, lam: float, nsteps: int, isentropic: bool =
     if st != OK:
         raise ValueError(f"orc_run_tangent failed: {st}")
     return U, dU
+
+
+def init_tangent(P: Problem, U0, dU0, lam: float):
+    """f^0 = f^eq(U0) at lattice speed lam and its tangent along dU0."""
+    U0 = _arr(U0).reshape(P.K, P.ny, P.nx)
+    dU0 = _arr(dU0).reshape(P.K, P.ny, P.nx)
+    f0 = np.zeros((P.Q, P.K, P.ny, P.nx))
+    df0 = np.zeros_like(f0)
+    st = _load().orc_init_tangent(ctypes.byref(P.c()), _ptr(U0), _ptr(dU0), float(lam), _ptr(f0),
+                                  _ptr(df0))
+    if st != OK:
+        raise ValueError(f"orc_init_tangent failed: {st}")
+    return f0, df0

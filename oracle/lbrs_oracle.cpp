@@ -581,6 +581,24 @@ int orc_step_fixed(const Problem* Pp, const double* f, const double* df, double 
     return ST_OK;
 }
 
+// Tangent of the initialisation f^0 = f^eq(U0) at lattice speed lam along dU0
+// (both [K][ny][nx]); writes f0 and df0 ([Q][K][ny][nx]).
+int orc_init_tangent(const Problem* Pp, const double* U0, const double* dU0, double lam,
+                     double* f0, double* df0) {
+    const Problem& P = *Pp;
+    int st = validate(P);
+    if (st != ST_OK) return st;
+    Sim<Dual> S(P);
+    std::vector<Dual> U((size_t)S.K * S.ncell);
+    for (size_t j = 0; j < U.size(); ++j) U[j] = Dual(U0[j], dU0[j]);
+    S.init_equilibrium(U.data(), lam);
+    for (size_t j = 0; j < S.f.size(); ++j) {
+        f0[j] = S.f[j].v;
+        df0[j] = S.f[j].d;
+    }
+    return ST_OK;
+}
+
 // Directional derivative of a whole fixed-speed run with respect to the initial
 // primitive state: W0 + eps*dW0 -> (U(T), dU(T)/deps), after nsteps steps at the
 // lattice speed lam (frozen or user mode).  W0/dW0: SoA primitive planes.

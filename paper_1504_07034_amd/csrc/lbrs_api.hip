@@ -109,11 +109,7 @@ int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void
     return hip_status(launch_prim_to_cons(a, d_W, d_U, (hipStream_t)hip_stream));
 }
 
-int lbrs_prim_to_cons_adjoint(const lbrs_params* p, const double* d_W, const double* d_Ubar,
-                              int isentropic, double* d_Wbar, void* hip_stream) {
-    int rc = check_params(p);
-    if (rc) return rc;
-    if (!d_W || !d_Ubar || !d_Wbar || d_Wbar == d_W || d_Wbar == d_Ubar) return LBRS_E_INVAL;
+static CellArgs cell_args_of(const lbrs_params* p) {
     CellArgs a;
     a.plane = (long long)p->nx * p->ny;
     a.ps = a.plane;
@@ -122,8 +118,32 @@ int lbrs_prim_to_cons_adjoint(const lbrs_params* p, const double* d_W, const dou
     a.ny = p->ny;
     a.model = p->model;
     a.gamma = p->gamma;
-    return hip_status(launch_prim_to_cons_adjoint(a, d_W, d_Ubar, isentropic, d_Wbar,
+    return a;
+}
+
+int lbrs_prim_to_cons_adjoint(const lbrs_params* p, const double* d_W, const double* d_Ubar,
+                              double* d_Wbar, void* hip_stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!d_W || !d_Ubar || !d_Wbar || d_Wbar == d_W || d_Wbar == d_Ubar) return LBRS_E_INVAL;
+    return hip_status(launch_prim_to_cons_adjoint(cell_args_of(p), d_W, d_Ubar, d_Wbar,
                                                   (hipStream_t)hip_stream));
+}
+
+int lbrs_isentropic_to_cons(const lbrs_params* p, const double* d_rho, double* d_U, void* hip_stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!d_rho || !d_U || d_rho == d_U) return LBRS_E_INVAL;
+    return hip_status(launch_isentropic_to_cons(cell_args_of(p), d_rho, d_U, (hipStream_t)hip_stream));
+}
+
+int lbrs_isentropic_to_cons_adjoint(const lbrs_params* p, const double* d_rho, const double* d_Ubar,
+                                    double* d_rhobar, void* hip_stream) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!d_rho || !d_Ubar || !d_rhobar || d_rhobar == d_rho || d_rhobar == d_Ubar) return LBRS_E_INVAL;
+    return hip_status(launch_isentropic_to_cons_adjoint(cell_args_of(p), d_rho, d_Ubar, d_rhobar,
+                                                        (hipStream_t)hip_stream));
 }
 
 int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* d_f0, double* d_f1,
@@ -339,7 +359,8 @@ int lbrs_set_f(lbrs_ctx* c, const double* d_f, double t, long long n) {
     // the new state becomes launch 0: slot 0, buffer f0, bound in slot 0
     c->launches = 0;
     CellArgs a = cell_args(c);
-    return hip_status(launch_set_f(a, c->f0, c->f1, c->st, d_f, t, n, c->stream));
+    return hip_status(launch_set_f(a, c->f0, c->f1, c->st, d_f, t, n,
+                                   c->P.lambda_mode == LBRS_LAMBDA_PER_STEP, c->stream));
 }
 
 int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, double* d_J,
@@ -383,6 +404,67 @@ int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, do
     a.omega = c->P.omega;
     a.st = c->st;
     return hip_status(launch_adjoint_init(a, d_fbar0, d_U0, d_Ubar0, c->stream));
+}
+
+int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ckpt) {
+    if (!c || !d_ckpt || nsteps < 1 || segment < 1) return LBRS_E_INVAL;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    const long long fcount = (long long)c->Q * c->K * c->plane;
+    const int nckpt = (nsteps + segment - 1) / segment;
+    for (int j = 0; j < nckpt; ++j) {
+        int rc = lbrs_get_f(c, d_ckpt + j * fcount);
+        if (rc) return rc;
+        int len = nsteps - j * segment < segment ? nsteps - j * segment : segment;
+        rc = lbrs_step(c, len, INFINITY);
+        if (rc) return rc;
+    }
+    return LBRS_OK;
+}
+
+int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const double* d_ckpt,
+                               double* d_tape, double* d_fbar, double* d_work) {
+    if (!c || !d_ckpt || !d_tape || !d_fbar || !d_work || d_fbar == d_work || nsteps < 1 ||
+        segment < 1)
+        return LBRS_E_INVAL;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    for (int s = 0; s < 4; ++s)
+        if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
+    // time and step count of the first checkpoint (the state the forward
+    // sweep started from) and the fixed step size
+    DevState h;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LBRS_E_HIP;
+    if (hipMemcpy(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost) != hipSuccess) return LBRS_E_HIP;
+    const Slot& now = h.s[c->launches & 1];
+    const double dt = c->dx / h.lam_fixed;
+    const long long n0 = now.n - nsteps;
+    const double t0 = now.t - nsteps * dt;
+    const long long fcount = (long long)c->Q * c->K * c->plane;
+    const long long ucount = (long long)c->K * c->plane;
+    const int nckpt = (nsteps + segment - 1) / segment;
+    double* cur = d_fbar;
+    double* nxt = d_work;
+    for (int j = nckpt - 1; j >= 0; --j) {
+        int rc = lbrs_set_f(c, d_ckpt + j * fcount, t0 + (double)j * segment * dt, n0 + (long long)j * segment);
+        if (rc) return rc;
+        int len = nsteps - j * segment < segment ? nsteps - j * segment : segment;
+        for (int i = 0; i < len; ++i) {
+            rc = lbrs_step_tape(c, d_tape + i * ucount);
+            if (rc) return rc;
+        }
+        for (int i = len - 1; i >= 0; --i) {
+            rc = lbrs_adjoint_step(c, d_tape + i * ucount, cur, nxt);
+            if (rc) return rc;
+            double* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    }
+    if (cur != d_fbar) {
+        if (hipMemcpyAsync(d_fbar, cur, sizeof(double) * fcount, hipMemcpyDeviceToDevice, c->stream) !=
+            hipSuccess)
+            return LBRS_E_HIP;
+    }
+    return LBRS_OK;
 }
 
 const char* lbrs_strerror(int code) {

@@ -63,11 +63,14 @@ int persistent1d_max_cells(int Q, size_t lds_limit);
 hipError_t launch_reset(DevState* st, hipStream_t s);
 hipError_t launch_prim_to_cons(const CellArgs& a, const double* W, double* U, hipStream_t s);
 hipError_t launch_prim_to_cons_adjoint(const CellArgs& a, const double* W, const double* Ub,
-                                       int isen, double* Wb, hipStream_t s);
+                                       double* Wb, hipStream_t s);
+hipError_t launch_isentropic_to_cons(const CellArgs& a, const double* rho, double* U, hipStream_t s);
+hipError_t launch_isentropic_to_cons_adjoint(const CellArgs& a, const double* rho, const double* Ub,
+                                             double* rb, hipStream_t s);
 hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState* st, int lam_mode,
                        double lam_user, double cfl, hipStream_t s);
 hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st, const double* ext,
-                        double t, long long n, hipStream_t s);
+                        double t, long long n, bool per_step, hipStream_t s);
 hipError_t launch_get_f(const CellArgs& a, double* f0, double* f1, const DevState* st, int slot,
                         double* ext, hipStream_t s);
 hipError_t launch_moments(const CellArgs& a, const double* f0, const double* f1, const DevState* st,

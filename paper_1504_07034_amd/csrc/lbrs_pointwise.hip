@@ -56,11 +56,9 @@ __global__ void prim_to_cons_kernel(CellArgs a, const double* __restrict__ W, do
     }
 }
 
-// Adjoint of prim_to_cons: Wbar = (dU/dW)^T Ubar; isentropic: p = rho^gamma/gamma
-// and the density plane receives the total derivative.
+// Adjoint of prim_to_cons: Wbar = (dU/dW)^T Ubar.
 __global__ void prim_to_cons_adjoint_kernel(CellArgs a, const double* __restrict__ W,
-                                            const double* __restrict__ Ub, int isentropic,
-                                            double* __restrict__ Wb) {
+                                            const double* __restrict__ Ub, double* __restrict__ Wb) {
     long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.plane) return;
     const long long P = a.plane;
@@ -69,37 +67,41 @@ __global__ void prim_to_cons_adjoint_kernel(CellArgs a, const double* __restrict
     if (a.model == D2Q4) {
         double u = W[P + c], v = W[2 * P + c];
         double b0 = Ub[c], b1 = Ub[P + c], b2 = Ub[2 * P + c], b3 = Ub[3 * P + c];
-        double rb = b0 + u * b1 + v * b2 + 0.5 * (u * u + v * v) * b3;
-        double ub = rho * b1 + rho * u * b3;
-        double vb = rho * b2 + rho * v * b3;
-        double pb = b3 / gm1;
-        if (isentropic) {
-            Wb[c] = rb + pb * pow(rho, gm1);
-            Wb[P + c] = 0.0;
-            Wb[2 * P + c] = 0.0;
-            Wb[3 * P + c] = 0.0;
-        } else {
-            Wb[c] = rb;
-            Wb[P + c] = ub;
-            Wb[2 * P + c] = vb;
-            Wb[3 * P + c] = pb;
-        }
+        Wb[c] = b0 + u * b1 + v * b2 + 0.5 * (u * u + v * v) * b3;
+        Wb[P + c] = rho * b1 + rho * u * b3;
+        Wb[2 * P + c] = rho * b2 + rho * v * b3;
+        Wb[3 * P + c] = b3 / gm1;
     } else {
         double u = W[P + c];
         double b0 = Ub[c], b1 = Ub[P + c], b2 = Ub[2 * P + c];
-        double rb = b0 + u * b1 + 0.5 * u * u * b2;
-        double ub = rho * b1 + rho * u * b2;
-        double pb = b2 / gm1;
-        if (isentropic) {
-            Wb[c] = rb + pb * pow(rho, gm1);
-            Wb[P + c] = 0.0;
-            Wb[2 * P + c] = 0.0;
-        } else {
-            Wb[c] = rb;
-            Wb[P + c] = ub;
-            Wb[2 * P + c] = pb;
-        }
+        Wb[c] = b0 + u * b1 + 0.5 * u * u * b2;
+        Wb[P + c] = rho * b1 + rho * u * b2;
+        Wb[2 * P + c] = b2 / gm1;
     }
+}
+
+// Gas at rest with p = rho^gamma/gamma: U = (rho, 0, [0,] rho^gamma/(gamma(gamma-1))).
+__global__ void isentropic_to_cons_kernel(CellArgs a, const double* __restrict__ rho,
+                                          double* __restrict__ U) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.plane) return;
+    const long long P = a.plane;
+    const int K = nk_of(a.model);
+    double r = rho[c];
+    U[c] = r;
+    for (int k = 1; k < K - 1; ++k) U[k * P + c] = 0.0;
+    U[(K - 1) * P + c] = pow(r, a.gamma) / (a.gamma * (a.gamma - 1.0));
+}
+
+// Its adjoint: rhobar = Ubar_rho + Ubar_E rho^(gamma-1)/(gamma-1).
+__global__ void isentropic_to_cons_adjoint_kernel(CellArgs a, const double* __restrict__ rho,
+                                                  const double* __restrict__ Ub,
+                                                  double* __restrict__ rb) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.plane) return;
+    const int K = nk_of(a.model);
+    double r = rho[c];
+    rb[c] = Ub[c] + Ub[(K - 1) * a.plane + c] * pow(r, a.gamma - 1.0) / (a.gamma - 1.0);
 }
 
 __device__ inline bool cell_bound(int model, const double* U, double gamma, double* l) {
@@ -241,30 +243,56 @@ __global__ void copy_f_kernel(long long count, double* __restrict__ f0, double* 
     }
 }
 
-// J = sum over the window of rho^2 (rho from the current populations); seed
-// fbar_{i,rho} = 2 rho in the window, zero elsewhere and in the other planes.
-__global__ void window_objective_kernel(CellArgs a, const double* __restrict__ f0,
-                                        const double* __restrict__ f1, DevState* st, int slot,
-                                        int ix0, int ix1, int iy0, int iy1, double* J,
-                                        double* __restrict__ fbar) {
+// Density of the current populations at cell c.
+__device__ inline double density_at(const CellArgs& a, const double* f, long long c) {
+    const int Q = nq_of(a.model), K = nk_of(a.model);
+    if (Q == 4)
+        return (f[fofs(a.ps, a.rs, a.nx, 0 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 2 * K, c)]) +
+               (f[fofs(a.ps, a.rs, a.nx, 1 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 3 * K, c)]);
+    double rho = 0.0;
+    for (int i = 0; i < Q; ++i) rho += f[fofs(a.ps, a.rs, a.nx, i * K, c)];
+    return rho;
+}
+
+// Seed of the adjoint: fbar_{i,rho} = 2 rho inside the window, zero elsewhere
+// and in the other components (dJ/df for J = sum_window rho^2, rho = sum_i f_i).
+__global__ void window_seed_kernel(CellArgs a, const double* __restrict__ f0,
+                                   const double* __restrict__ f1, const DevState* st, int slot,
+                                   int ix0, int ix1, int iy0, int iy1, double* __restrict__ fbar) {
     long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double contrib = 0.0;
-    if (c < a.plane) {
-        const double* f = st->s[slot].cur ? f1 : f0;
-        const int Q = nq_of(a.model), K = nk_of(a.model);
-        const int x = (int)(c % a.nx), y = (int)(c / a.nx);
-        const bool in = x >= ix0 && x < ix1 && y >= iy0 && y < iy1;
-        double rho = 0.0;
-        if (Q == 4) rho = (f[fofs(a.ps, a.rs, a.nx, 0 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 2 * K, c)]) +
-                          (f[fofs(a.ps, a.rs, a.nx, 1 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 3 * K, c)]);
-        else for (int i = 0; i < Q; ++i) rho += f[fofs(a.ps, a.rs, a.nx, i * K, c)];
-        for (int i = 0; i < Q; ++i)
-            for (int k = 0; k < K; ++k)
-                fbar[fofs(a.ps, a.rs, a.nx, i * K + k, c)] = (in && k == 0) ? 2.0 * rho : 0.0;
-        contrib = in ? rho * rho : 0.0;
+    if (c >= a.plane) return;
+    const double* f = st->s[slot].cur ? f1 : f0;
+    const int Q = nq_of(a.model), K = nk_of(a.model);
+    const int x = (int)(c % a.nx), y = (int)(c / a.nx);
+    const bool in = x >= ix0 && x < ix1 && y >= iy0 && y < iy1;
+    const double g = in ? 2.0 * density_at(a, f, c) : 0.0;
+    for (int i = 0; i < Q; ++i)
+        for (int k = 0; k < K; ++k) fbar[fofs(a.ps, a.rs, a.nx, i * K + k, c)] = k == 0 ? g : 0.0;
+}
+
+// J = sum over the window of rho^2, by one workgroup in a fixed order (the
+// result is bitwise reproducible, which finite differences of J rely on).
+__global__ __launch_bounds__(1024) void window_sum_kernel(CellArgs a, const double* __restrict__ f0,
+                                                          const double* __restrict__ f1,
+                                                          const DevState* st, int slot, int ix0,
+                                                          int ix1, int iy0, int iy1, double* J) {
+    __shared__ double part[16];
+    const double* f = st->s[slot].cur ? f1 : f0;
+    const long long w = ix1 - ix0, cells = w * (long long)(iy1 - iy0);
+    double acc = 0.0;
+    for (long long j = threadIdx.x; j < cells; j += blockDim.x) {
+        long long c = (long long)(iy0 + j / w) * a.nx + (ix0 + j % w);
+        double rho = density_at(a, f, c);
+        acc += rho * rho;
     }
-    for (int off = 32; off >= 1; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
-    if ((threadIdx.x & 63) == 0 && contrib != 0.0) atomicAdd(J, contrib);
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += part[i];
+        *J = t;
+    }
 }
 
 // A1(U)^T hx + A2(U)^T hy for the 2D Euler fluxes, with
@@ -363,9 +391,18 @@ hipError_t launch_prim_to_cons(const CellArgs& a, const double* W, double* U, hi
     return hipGetLastError();
 }
 hipError_t launch_prim_to_cons_adjoint(const CellArgs& a, const double* W, const double* Ub,
-                                       int isen, double* Wb, hipStream_t s) {
-    hipLaunchKernelGGL(prim_to_cons_adjoint_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, W, Ub,
-                       isen, Wb);
+                                       double* Wb, hipStream_t s) {
+    hipLaunchKernelGGL(prim_to_cons_adjoint_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, W, Ub, Wb);
+    return hipGetLastError();
+}
+hipError_t launch_isentropic_to_cons(const CellArgs& a, const double* rho, double* U, hipStream_t s) {
+    hipLaunchKernelGGL(isentropic_to_cons_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, rho, U);
+    return hipGetLastError();
+}
+hipError_t launch_isentropic_to_cons_adjoint(const CellArgs& a, const double* rho, const double* Ub,
+                                             double* rb, hipStream_t s) {
+    hipLaunchKernelGGL(isentropic_to_cons_adjoint_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, rho,
+                       Ub, rb);
     return hipGetLastError();
 }
 hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState* st, int lam_mode,
@@ -376,13 +413,13 @@ hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState
     return hipGetLastError();
 }
 hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st, const double* ext,
-                        double t, long long n, hipStream_t s) {
+                        double t, long long n, bool per_step, hipStream_t s) {
     const int Q = nq_of(a.model), K = nk_of(a.model);
     long long cnt = (long long)Q * K * a.plane;
     hipLaunchKernelGGL(set_slot0_kernel, dim3(1), dim3(64), 0, s, st, t, n);
     hipLaunchKernelGGL(copy_f_kernel, grid1(cnt, 256), dim3(256), 0, s, cnt, f0, f1, st, 0,
                        const_cast<double*>(ext), 1);
-    hipLaunchKernelGGL(bound_of_f_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, st);
+    if (per_step) hipLaunchKernelGGL(bound_of_f_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, st);
     return hipGetLastError();
 }
 hipError_t launch_get_f(const CellArgs& a, double* f0, double* f1, const DevState* st, int slot,
@@ -397,15 +434,13 @@ hipError_t launch_moments(const CellArgs& a, const double* f0, const double* f1,
     hipLaunchKernelGGL(moments_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, f1, st, slot, U);
     return hipGetLastError();
 }
-__global__ void zero_kernel(double* p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
-}
 hipError_t launch_window_objective(const CellArgs& a, const double* f0, const double* f1,
                                    DevState* st, int slot, int ix0, int ix1, int iy0, int iy1,
                                    double* J, double* fbar, hipStream_t s) {
-    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, J);
-    hipLaunchKernelGGL(window_objective_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, f1, st,
-                       slot, ix0, ix1, iy0, iy1, J, fbar);
+    hipLaunchKernelGGL(window_sum_kernel, dim3(1), dim3(1024), 0, s, a, f0, f1, st, slot, ix0, ix1,
+                       iy0, iy1, J);
+    hipLaunchKernelGGL(window_seed_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, f1, st, slot,
+                       ix0, ix1, iy0, iy1, fbar);
     return hipGetLastError();
 }
 hipError_t launch_adjoint_step(const AdjArgs& a, const double* Un, const double* gn, double* g,

@@ -27,8 +27,10 @@ LBRS_LAYOUT_PLANAR, LBRS_LAYOUT_ROWS = 0, 1
 EXPORTS = (
     "lbrs_query_sizes", "lbrs_prim_to_cons", "lbrs_init", "lbrs_step", "lbrs_get_state",
     "lbrs_moments", "lbrs_get_f", "lbrs_set_f", "lbrs_window_objective", "lbrs_step_tape",
-    "lbrs_adjoint_step", "lbrs_adjoint_init", "lbrs_prim_to_cons_adjoint", "lbrs_set_stream",
-    "lbrs_set_tile", "lbrs_strerror", "lbrs_destroy",
+    "lbrs_adjoint_step", "lbrs_adjoint_init", "lbrs_prim_to_cons_adjoint",
+    "lbrs_isentropic_to_cons", "lbrs_isentropic_to_cons_adjoint", "lbrs_forward_checkpointed",
+    "lbrs_backward_checkpointed", "lbrs_set_stream", "lbrs_set_tile", "lbrs_strerror",
+    "lbrs_destroy",
 )
 
 
@@ -80,7 +82,11 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_step_tape": (i, [vp, vp]),
         "lbrs_adjoint_step": (i, [vp, vp, vp, vp]),
         "lbrs_adjoint_init": (i, [vp, vp, vp, vp]),
-        "lbrs_prim_to_cons_adjoint": (i, [P, vp, vp, i, vp, vp]),
+        "lbrs_prim_to_cons_adjoint": (i, [P, vp, vp, vp, vp]),
+        "lbrs_isentropic_to_cons": (i, [P, vp, vp, vp]),
+        "lbrs_isentropic_to_cons_adjoint": (i, [P, vp, vp, vp, vp]),
+        "lbrs_forward_checkpointed": (i, [vp, i, i, vp]),
+        "lbrs_backward_checkpointed": (i, [vp, i, i, vp, vp, vp, vp]),
         "lbrs_set_stream": (i, [vp, vp]),
         "lbrs_set_tile": (i, [vp, i, i]),
         "lbrs_strerror": (ctypes.c_char_p, [i]),
@@ -146,10 +152,32 @@ def lbrs_prim_to_cons(p: lbrs_params, W: torch.Tensor, U: torch.Tensor, stream=N
            "lbrs_prim_to_cons")
 
 
-def lbrs_prim_to_cons_adjoint(p: lbrs_params, W, Ubar, isentropic: bool, Wbar, stream=None):
+def lbrs_prim_to_cons_adjoint(p: lbrs_params, W, Ubar, Wbar, stream=None):
     _check(load_library().lbrs_prim_to_cons_adjoint(ctypes.byref(p), _dptr(W), _dptr(Ubar),
-                                                    int(isentropic), _dptr(Wbar), _stream(stream)),
+                                                    _dptr(Wbar), _stream(stream)),
            "lbrs_prim_to_cons_adjoint")
+
+
+def lbrs_isentropic_to_cons(p: lbrs_params, rho, U, stream=None):
+    _check(load_library().lbrs_isentropic_to_cons(ctypes.byref(p), _dptr(rho), _dptr(U),
+                                                  _stream(stream)), "lbrs_isentropic_to_cons")
+
+
+def lbrs_isentropic_to_cons_adjoint(p: lbrs_params, rho, Ubar, rhobar, stream=None):
+    _check(load_library().lbrs_isentropic_to_cons_adjoint(ctypes.byref(p), _dptr(rho), _dptr(Ubar),
+                                                          _dptr(rhobar), _stream(stream)),
+           "lbrs_isentropic_to_cons_adjoint")
+
+
+def lbrs_forward_checkpointed(ctx, nsteps: int, segment: int, ckpt):
+    _check(load_library().lbrs_forward_checkpointed(ctx, int(nsteps), int(segment), _dptr(ckpt)),
+           "lbrs_forward_checkpointed")
+
+
+def lbrs_backward_checkpointed(ctx, nsteps: int, segment: int, ckpt, tape, fbar, work):
+    _check(load_library().lbrs_backward_checkpointed(ctx, int(nsteps), int(segment), _dptr(ckpt),
+                                                     _dptr(tape), _dptr(fbar), _dptr(work)),
+           "lbrs_backward_checkpointed")
 
 
 def lbrs_init(p: lbrs_params, U0, f0, f1, scratch, stream=None):

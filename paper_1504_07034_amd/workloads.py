@@ -214,3 +214,22 @@ def random_states(count: int, seed: int, dim: int = 2):
     p = rng.uniform(0.05, 3.0, size=count)
     vel = rng.uniform(-2.0, 2.0, size=(count, dim))
     return np.column_stack([rho, vel, p])
+
+
+def bump_direction(n: int, seed: int, nbumps: int = 4, width: float = 0.05) -> np.ndarray:
+    """Smooth perturbation direction on the periodic [0,1]^2 grid: a sum of nbumps
+    Gaussian bumps of the given width with random centres and signs (periodic
+    distance), scaled so that max |d| = 1.  Shape [n][n]."""
+    rng = np.random.default_rng(seed)
+    x = centres(n, 0.0, 1.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    d = np.zeros((n, n))
+    for _ in range(nbumps):
+        cx, cy = rng.uniform(0.0, 1.0, size=2)
+        sg = rng.choice([-1.0, 1.0])
+        dx = np.abs(X - cx)
+        dy = np.abs(Y - cy)
+        dx = np.minimum(dx, 1.0 - dx)
+        dy = np.minimum(dy, 1.0 - dy)
+        d += sg * np.exp(-(dx * dx + dy * dy) / width ** 2)
+    return d / np.max(np.abs(d))

@@ -1,0 +1,176 @@
+"""GPU adjoint (hand-written VJP of the fixed-speed D2Q4 step) against the
+oracle's forward-mode dual numbers, and the checkpointed gradient against
+central finite differences at the full 2048^2 / 2000-step size."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1504_07034_amd import adjoint, lbrs
+from paper_1504_07034_amd import workloads as wl
+
+from helpers import report
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = [0, 1]
+
+
+def _sim(n, lam, layout, omega=1.0):
+    return lbrs.Sim(lbrs.LBRS_D2Q4, n, n, omega=omega, bc=(1, 1, 1, 1),
+                    lambda_mode=lbrs.LBRS_LAMBDA_USER, lambda_user=lam, layout=layout)
+
+
+def _oracle_problem(n, lam, omega=1.0):
+    return oracle.Problem(model=oracle.D2Q4, nx=n, ny=n, omega=omega, sides=(1, 1, 1, 1),
+                          lam_mode=oracle.LAM_USER, lam_user=lam)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("omega", [0.7, 1.0, 1.6])
+def test_adjoint_step_equals_bruteforce_transpose(omega, layout):
+    """Every entry of L^T fbar, L = d(step)/df at f^3, against the transpose built
+    column by column from the oracle's tangent (dual numbers) on a 6 x 6 grid."""
+    n, lam, steps = 6, 3.0, 3
+    w = wl.fourier_modes(n, seed=11)
+    P = _oracle_problem(n, lam, omega)
+    ref = oracle.run(P, oracle.prim_to_cons(P, w.W), max_steps=steps, want_f=True)
+    fbar = np.random.default_rng(5).standard_normal((4, 4, n, n))
+    expect = np.zeros(16 * n * n)
+    for j in range(16 * n * n):
+        e = np.zeros(16 * n * n)
+        e[j] = 1.0
+        _, col = oracle.step_fixed(P, ref.f, lam, df=e)
+        expect[j] = np.sum(col * fbar)
+    sim = _sim(n, lam, layout, omega)
+    sim.init_primitive(w.W)
+    sim.step(steps)
+    tape = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
+    lbrs.lbrs_step_tape(sim.ctx, tape)
+    gn = sim.from_planar(torch.from_numpy(fbar).cuda())
+    g = torch.empty_like(gn)
+    lbrs.lbrs_adjoint_step(sim.ctx, tape, gn, g)
+    got = sim.to_planar(g).cpu().numpy().ravel()
+    err = np.max(np.abs(got - expect)) / np.max(np.abs(expect))
+    report("adjoint bruteforce", omega=omega, layout=layout, rel=err)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_tape_equals_moments_and_dot_product(layout):
+    """130^2 periodic (three strips, ragged): the tape written by lbrs_step_tape is
+    U^n bit for bit, and <L df, fbar> (oracle tangent) = <df, L^T fbar> (GPU)."""
+    n, lam = 130, 2.9
+    w = wl.fourier_modes(n, seed=4)
+    sim = _sim(n, lam, layout, omega=1.3)
+    sim.init_primitive(w.W)
+    sim.step(7)
+    U7 = sim.moments().clone()
+    tape = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
+    lbrs.lbrs_step_tape(sim.ctx, tape)
+    assert torch.equal(tape, U7)
+    P = _oracle_problem(n, lam, omega=1.3)
+    ref = oracle.run(P, oracle.prim_to_cons(P, w.W), max_steps=7, want_f=True)
+    rng = np.random.default_rng(9)
+    df = rng.standard_normal((4, 4, n, n))
+    fbar = rng.standard_normal((4, 4, n, n))
+    _, Ldf = oracle.step_fixed(P, ref.f, lam, df=df)
+    lhs = float(np.sum(Ldf * fbar))
+    g = torch.empty(sim.f_shape, dtype=torch.float64, device="cuda")
+    lbrs.lbrs_adjoint_step(sim.ctx, tape, sim.from_planar(torch.from_numpy(fbar).cuda()), g)
+    rhs = float(np.sum(df * sim.to_planar(g).cpu().numpy()))
+    report("dot product", layout=layout, lhs=lhs, rhs=rhs)
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+def test_adjoint_init_dot_product():
+    """<d f^0, fbar0> with d f^0 = (df^eq/dU0) dU0 from the oracle's dual numbers
+    equals <dU0, Ubar0> from lbrs_adjoint_init."""
+    n, lam = 40, 3.1
+    w = wl.fourier_modes(n, seed=2)
+    P = _oracle_problem(n, lam)
+    U0 = oracle.prim_to_cons(P, w.W)
+    rng = np.random.default_rng(3)
+    dU0 = rng.standard_normal(U0.shape)
+    fbar0 = rng.standard_normal((4, 4, n, n))
+    _, df0 = oracle.init_tangent(P, U0, dU0, lam)
+    lhs = float(np.sum(df0 * fbar0))
+    sim = _sim(n, lam, 1)
+    Ug = torch.from_numpy(U0).cuda()
+    sim.init(Ug)
+    Ub = torch.empty_like(Ug)
+    lbrs.lbrs_adjoint_init(sim.ctx, sim.from_planar(torch.from_numpy(fbar0).cuda()), Ug, Ub)
+    rhs = float(np.sum(dU0 * Ub.cpu().numpy()))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def _oracle_dJ(n, steps, rho0, d, window):
+    """Directional derivative of J along d by the oracle's dual numbers (its own
+    frozen lattice speed of the unperturbed state)."""
+    W0 = np.zeros((4, n, n))
+    W0[0] = rho0
+    W0[3] = rho0 ** 1.4 / 1.4
+    Pf = oracle.Problem(model=oracle.D2Q4, nx=n, ny=n, sides=(1, 1, 1, 1),
+                        lam_mode=oracle.LAM_FROZEN)
+    lam = oracle.initial_lattice_speed(Pf, oracle.prim_to_cons(Pf, W0))
+    P = _oracle_problem(n, lam)
+    dW = np.zeros_like(W0)
+    dW[0] = d
+    U, dU = oracle.run_tangent(P, W0, dW, lam, steps, isentropic=True)
+    m = wl.window_mask(n, *window)
+    return float(np.sum(U[0][m] ** 2)), float(np.sum(2.0 * U[0][m] * dU[0][m]))
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_gradient_matches_oracle_dual_numbers(layout):
+    """Checkpointed gradient (48^2, 60 steps, segment 8) against the oracle's exact
+    directional derivatives along three smooth directions."""
+    n, steps = 48, 60
+    w = wl.acoustic_pulse(n, steps=steps)
+    rho0 = torch.from_numpy(w.W[0].copy()).cuda()
+    spec = adjoint.GradientSpec(n=n, steps=steps, layout=layout, segment=8)
+    run = adjoint.GradientRunner(spec, rho0)
+    r = rho0.clone().requires_grad_(True)
+    J = adjoint.LBRSFunction.apply(r, run)
+    J.backward()
+    grad = r.grad.cpu().numpy()
+    for k in range(3):
+        d = wl.bump_direction(n, seed=200 + k)
+        J_o, dJ_o = _oracle_dJ(n, steps, w.W[0], d, (0.7, 0.8))
+        dJ_g = float(np.sum(grad * d))
+        report("grad vs dual", k=k, layout=layout, J=J.item(), J_oracle=J_o, gpu=dJ_g, oracle=dJ_o)
+        assert abs(J.item() - J_o) <= 1e-12 * abs(J_o)
+        assert abs(dJ_g - dJ_o) <= 1e-9 * abs(dJ_o)
+    run.close()
+
+
+def test_gradient_finite_differences_full_size():
+    """Full size: 2048^2 periodic acoustic pulse, 2000 steps, sqrt(T) checkpoints;
+    the gradient dJ/drho0 against central differences (h = 1e-4) along 16 seeded
+    smooth directions, relative error <= 1e-5."""
+    n, steps = 2048, 2000
+    w = wl.acoustic_pulse(n, steps=steps)
+    rho0 = torch.from_numpy(w.W[0].copy()).cuda()
+    spec = adjoint.GradientSpec(n=n, steps=steps)
+    run = adjoint.GradientRunner(spec, rho0)
+    report("fd setup", lam=spec.lam, segment=spec.seg, window=run.win)
+    r = rho0.clone().requires_grad_(True)
+    J = adjoint.LBRSFunction.apply(r, run)
+    J.backward()
+    grad = r.grad
+    h = 1e-4
+    worst = 0.0
+    for k in range(16):
+        d = torch.from_numpy(wl.bump_direction(n, seed=100 + k)).cuda()
+        Jp = run.forward(rho0 + h * d, keep=False).item()
+        Jm = run.forward(rho0 - h * d, keep=False).item()
+        fd = (Jp - Jm) / (2 * h)
+        ad = float(torch.sum(grad * d))
+        rel = abs(fd - ad) / abs(ad)
+        worst = max(worst, rel)
+        report("fd", k=k, J=J.item(), fd=fd, adjoint=ad, rel=rel)
+        assert rel <= 1e-5
+    report("fd worst", rel=worst)
+    run.close()
