@@ -20,6 +20,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
+
+# HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (calibrated against a plain copy), valid for the kernel source they were taken
+# on (profiles/step2d_d2q4_riemann4096.md); null once the source changes.
+TRAFFIC_BYTES = 4.433e9
+TRAFFIC_SOURCE_HASH = "e4135b5d4352c596"
+TRAFFIC_SHAPE = {"rows": 0, "wpb": 16, "layout": 1}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1504_07034_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                   for f in ("lbrs_step2d.hip", "lbrs_device.hpp"))
+    return hashlib.sha256(src).hexdigest()[:16]
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = 256  # 16 FP64 populations in + 16 out per lattice update
 
@@ -48,6 +63,72 @@ def cpu_baseline(nsteps: int = 2):
                       f"({secs:.1f} s of stepping; init excluded)"}
 
 
+def batched_1d(chunks=(510, 1022, 2046), subset=32):
+    """Ragged 1D batch: 1024 seeded shock tubes (200..20000 cells, own t_end) in
+    one persistent launch (chunk autotuned), against sequential single-domain
+    runs of a seeded subset of the same tubes (the plain library path: one
+    persistent launch per tube of <= 2048 cells, one launch per step above)."""
+    import numpy as np
+    import torch
+
+    from paper_1504_07034_amd import lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    tubes = wl.tube_batch(1024, seed=0)
+
+    def make(sel, chunk):
+        units = [lbrs.make_params(t.model, t.nx, 1, t.domain, t.gamma, t.omega, t.cfl)
+                 for t in sel]
+        B = lbrs.Batch1D(units, [t.t_end for t in sel], chunk=chunk)
+        W = torch.from_numpy(np.concatenate([t.W[:, 0, :] for t in sel], axis=1)).cuda()
+        U0 = torch.empty_like(W)
+        lbrs.lbrs_prim_to_cons(lbrs.make_params(units[0].model, B.total, 1), W, U0)
+        return B, U0
+
+    def timed_batch(sel, chunk):
+        B, U0 = make(sel, chunk)
+        B.init(U0)
+        B.run(10**6)  # capture the graph and warm up
+        B.init(U0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.run(10**6)
+        e1.record()
+        st = B.state()
+        ms = e0.elapsed_time(e1)
+        lups = sum(n * t.nx for n, t in zip(st["nsteps"], sel))
+        assert st["rc"] == 0 and all(x == t.t_end for x, t in zip(st["t"], sel))
+        B.close()
+        return ms, lups
+
+    tuned = {}
+    for c in chunks:
+        try:
+            tuned[c] = timed_batch(tubes, c)
+        except lbrs.LBRSError:  # chunk too large for this device's LDS
+            pass
+    best = min(tuned, key=lambda c: tuned[c][0])
+    ms, lups = tuned[best]
+    rng = np.random.default_rng(1)
+    sub = [tubes[i] for i in sorted(rng.choice(len(tubes), size=subset, replace=False))]
+    ms_b, lups_b = timed_batch(sub, best)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in sub:
+        sim = lbrs.Sim(t.model, t.nx, 1, domain=t.domain, gamma=t.gamma, omega=t.omega, cfl=t.cfl)
+        sim.init_primitive(t.W)
+        sim.run(t.t_end, chunk=100000)
+        sim.close()
+    torch.cuda.synchronize()
+    ms_s = (time.perf_counter() - t0) * 1e3
+    return {"units": len(tubes), "cells": int(sum(t.nx for t in tubes)), "chunk": best,
+            "ms": round(ms, 2), "MLUPS": round(lups / ms / 1e3, 1),
+            "chunk_ms": {str(c): round(v[0], 2) for c, v in tuned.items()},
+            "subset": {"units": subset, "batched_ms": round(ms_b, 2),
+                       "sequential_ms": round(ms_s, 2), "speedup": round(ms_s / ms_b, 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +139,8 @@ def main():
     ap.add_argument("--wpb", type=int, default=4)
     ap.add_argument("--layout", type=int, default=1, help="0 planar, 1 row-interleaved")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and adjoint figures reported beside the main value")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain copy of the populations (lbrs_get_f: "
                          "16 planes read and written) as a known-size reference for counters")
@@ -154,11 +237,15 @@ def main():
                    "layout": "row-interleaved" if args.layout == 1 else "planar"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": (TRAFFIC_BYTES if kernel_source_hash() == TRAFFIC_SOURCE_HASH
+                                 and shape["wpb"] == TRAFFIC_SHAPE["wpb"]
+                                 and args.layout == TRAFFIC_SHAPE["layout"] else None)},
     }
     sim.close()
     del U0
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        rec["batched_1d"] = batched_1d()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec), flush=True)

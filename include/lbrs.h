@@ -231,6 +231,48 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);
  * adjacent strips in lockstep.  Takes effect for later calls. */
 int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block);
 
+/* ------------------------------------------------------------------------
+ * Ragged batch of independent 1D units (shock tubes) in one persistent launch.
+ * Every unit is a full problem of the paper's 1D scheme (Sec. II.A update,
+ * Sec. II.C equilibria and bound) with its own lbrs_params (model D1Q2 or
+ * D1Q3, the same for all units; nx, domain, gamma, omega, cfl, x sides and
+ * lambda mode) and its own t_end; the units' cells lie back to back in pools:
+ *   U pool  [3][total]     f pool  [Q*3][total]    (unit b at offsets[b])
+ * A unit of more than `chunk` cells is split over a team of workgroups that
+ * keep their chunk in LDS for the whole run and synchronise once per step.
+ * ------------------------------------------------------------------------ */
+typedef struct lbrs_batch lbrs_batch;
+
+/* Offsets of the units in the pools (offsets[nunits] = total cells; may be
+ * NULL) and the device scratch size for a chunk size (cells per workgroup,
+ * >= 3; at most what the LDS holds: 3*Q*(chunk+2) doubles).  A unit may span
+ * at most 64 workgroups (nx <= 64*chunk).  Needs the GPU (occupancy). */
+int lbrs_batch_query(int nunits, const lbrs_params* units, int chunk, long long* offsets,
+                     size_t* scratch_bytes);
+
+/* Plan the batch (member jobs on the persistent grid), upload it to
+ * d_scratch (256-byte aligned, lbrs_batch_query's size; borrowed), and set
+ * every unit to equilibrium f^0 = f^eq(U0) from d_U0.  t_end: host array of
+ * nunits end times (NULL: unbounded).  Waits for the stream once. */
+int lbrs_batch_init(lbrs_batch** out, int nunits, const lbrs_params* units, const double* t_end,
+                    int chunk, const double* d_U0, double* d_f, void* d_scratch, void* hip_stream);
+
+/* Advance every unit by up to max_steps steps (each stops at its t_end or at
+ * a non-physical state) in one persistent launch; the launch is captured in a
+ * hipGraph the first time and replayed after.  Asynchronous. */
+int lbrs_batch_run(lbrs_batch* b, int max_steps);
+
+/* Per-unit time, steps, last lattice speed, status (bit 0 non-physical,
+ * bit 1 team barrier gave up) and first non-physical step (or -1), into host
+ * arrays of nunits (each may be NULL).  Waits for the stream. */
+int lbrs_batch_get_state(lbrs_batch* b, double* t, long long* nsteps, double* lambda,
+                         unsigned* status, long long* fail_step);
+
+/* Moments U = sum_i f_i of the whole f pool into d_U [3][total]. */
+int lbrs_batch_moments(lbrs_batch* b, double* d_U);
+
+void lbrs_batch_destroy(lbrs_batch* b);
+
 const char* lbrs_strerror(int code);
 void lbrs_destroy(lbrs_ctx* c);
 

@@ -54,6 +54,63 @@ struct AdjArgs {
     const DevState* st;  // the fixed lattice speed is read from st->lam_fixed
 };
 
+// team arrival counters sit on separate 128-byte lines
+static constexpr int COUNTER_STRIDE = 32;
+// largest team (workgroups sharing one unit)
+static constexpr int MAXTEAM = 64;
+
+struct Unit1D {
+    long long off;     // first cell of the unit in the pools
+    int n;             // cells
+    int periodic;
+    int g;             // members
+    int lam_mode;
+    double dx, gamma, omega, cfl, t_end, lam_fixed;
+};
+
+struct UnitState1D {
+    double t;
+    long long nsteps;
+    double lam_used;
+    unsigned status;   // bit 0: non-physical; bit 1: team barrier timed out
+    unsigned pad;
+    long long fail_step;
+};
+
+struct Job1D {
+    int unit, member, c0, c1;  // cells [c0, c1) of the unit
+};
+
+// Team exchange slot of one member for one step parity.
+struct EdgeSlot {
+    double lam;
+    unsigned bad;
+    unsigned pad;
+    double first[9];   // f^{n+1} of the member's first cell
+    double last[9];    // f^{n+1} of the member's last cell
+};
+
+struct Batch1DArgs {
+    const Unit1D* units;
+    UnitState1D* states;
+    const Job1D* jobs;
+    const int* job_begin;      // [grid + 1]
+    unsigned* counters;        // per unit (stride COUNTER_STRIDE), team barrier arrivals
+    EdgeSlot* slots;           // per unit: [2][g] at slot_off[unit]
+    const long long* slot_off;
+    double* f;                 // pool [Q*3][total]
+    long long total;           // pool plane stride
+    int Q;
+    int max_steps;
+    unsigned spin_limit;
+};
+
+hipError_t launch_batch1d_init(const Unit1D* units, Unit1D* units_rw, int nunits, const double* U0,
+                               double* f, long long total, UnitState1D* states, int Q, hipStream_t s);
+hipError_t launch_zero_counters(unsigned* c, int n, hipStream_t s);
+hipError_t launch_batch1d(const Batch1DArgs& a, int grid, int threads, int chunk, hipStream_t s);
+int batch1d_blocks_per_cu(int Q, int threads, int chunk);
+
 hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, int max_blocks, hipStream_t s);
 int step2d_blocks_per_cu(int wpb);
 bool step2d_wpb_supported(int wpb);
@@ -78,6 +135,7 @@ hipError_t launch_moments(const CellArgs& a, const double* f0, const double* f1,
 hipError_t launch_window_objective(const CellArgs& a, const double* f0, const double* f1,
                                    DevState* st, int slot, int ix0, int ix1, int iy0, int iy1,
                                    double* J, double* fbar, hipStream_t s);
+hipError_t launch_pool_moments(const CellArgs& a, const double* f, double* U, hipStream_t s);
 hipError_t launch_adjoint_step(const AdjArgs& a, const double* Un, const double* gn, double* g,
                                hipStream_t s);
 hipError_t launch_adjoint_init(const AdjArgs& a, const double* fb0, const double* U0, double* Ub,

@@ -230,6 +230,19 @@ __global__ void moments_kernel(CellArgs a, const double* __restrict__ f0, const 
     for (int k = 0; k < K; ++k) U[k * a.plane + c] = Uc[k];
 }
 
+// U = sum_i f_i of a population pool (no time state: one buffer).
+__global__ void pool_moments_kernel(CellArgs a, const double* __restrict__ f, double* __restrict__ U) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.plane) return;
+    const int Q = nq_of(a.model), K = nk_of(a.model);
+    double fc[16], Uc[4];
+    for (int p = 0; p < Q * K; ++p) fc[p] = f[fofs(a.ps, a.rs, a.nx, p, c)];
+    if (a.model == D2Q4) moments_d2q4(fc, Uc);
+    else if (a.model == D1Q2) moments_1d<2>(fc, Uc);
+    else moments_1d<3>(fc, Uc);
+    for (int k = 0; k < K; ++k) U[k * a.plane + c] = Uc[k];
+}
+
 // Copy between the current buffer and an external one (dir 0: out, 1: in to f0).
 __global__ void copy_f_kernel(long long count, double* __restrict__ f0, double* __restrict__ f1,
                               const DevState* st, int slot, double* __restrict__ ext, int dir) {
@@ -441,6 +454,10 @@ hipError_t launch_window_objective(const CellArgs& a, const double* f0, const do
                        iy0, iy1, J);
     hipLaunchKernelGGL(window_seed_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, f1, st, slot,
                        ix0, ix1, iy0, iy1, fbar);
+    return hipGetLastError();
+}
+hipError_t launch_pool_moments(const CellArgs& a, const double* f, double* U, hipStream_t s) {
+    hipLaunchKernelGGL(pool_moments_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f, U);
     return hipGetLastError();
 }
 hipError_t launch_adjoint_step(const AdjArgs& a, const double* Un, const double* gn, double* g,

@@ -29,8 +29,9 @@ EXPORTS = (
     "lbrs_moments", "lbrs_get_f", "lbrs_set_f", "lbrs_window_objective", "lbrs_step_tape",
     "lbrs_adjoint_step", "lbrs_adjoint_init", "lbrs_prim_to_cons_adjoint",
     "lbrs_isentropic_to_cons", "lbrs_isentropic_to_cons_adjoint", "lbrs_forward_checkpointed",
-    "lbrs_backward_checkpointed", "lbrs_set_stream", "lbrs_set_tile", "lbrs_strerror",
-    "lbrs_destroy",
+    "lbrs_backward_checkpointed", "lbrs_set_stream", "lbrs_set_tile", "lbrs_batch_query",
+    "lbrs_batch_init", "lbrs_batch_run", "lbrs_batch_get_state", "lbrs_batch_moments",
+    "lbrs_batch_destroy", "lbrs_strerror", "lbrs_destroy",
 )
 
 
@@ -89,6 +90,13 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_backward_checkpointed": (i, [vp, i, i, vp, vp, vp, vp]),
         "lbrs_set_stream": (i, [vp, vp]),
         "lbrs_set_tile": (i, [vp, i, i]),
+        "lbrs_batch_query": (i, [i, P, i, ctypes.POINTER(ll), szp]),
+        "lbrs_batch_init": (i, [ctypes.POINTER(vp), i, P, dp, i, vp, vp, vp, vp]),
+        "lbrs_batch_run": (i, [vp, i]),
+        "lbrs_batch_get_state": (i, [vp, dp, ctypes.POINTER(ll), dp, ctypes.POINTER(ctypes.c_uint),
+                                     ctypes.POINTER(ll)]),
+        "lbrs_batch_moments": (i, [vp, vp]),
+        "lbrs_batch_destroy": (None, [vp]),
         "lbrs_strerror": (ctypes.c_char_p, [i]),
         "lbrs_destroy": (None, [vp]),
     }
@@ -347,6 +355,99 @@ class Sim:
         if self.ctx is not None:
             lbrs_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- 1D batch
+def lbrs_batch_query(units, chunk: int):
+    n = len(units)
+    arr = (lbrs_params * n)(*units)
+    offs = (ctypes.c_longlong * (n + 1))()
+    sb = ctypes.c_size_t()
+    _check(load_library().lbrs_batch_query(n, arr, int(chunk), offs, ctypes.byref(sb)),
+           "lbrs_batch_query")
+    return list(offs), sb.value
+
+
+def lbrs_batch_init(units, t_end, chunk, U0, f, scratch, stream=None):
+    n = len(units)
+    arr = (lbrs_params * n)(*units)
+    te = (ctypes.c_double * n)(*[float(x) for x in t_end]) if t_end is not None else None
+    b = ctypes.c_void_p()
+    _check(load_library().lbrs_batch_init(ctypes.byref(b), n, arr, te, int(chunk), _dptr(U0),
+                                          _dptr(f), ctypes.c_void_p(scratch.data_ptr()),
+                                          _stream(stream)), "lbrs_batch_init")
+    return b
+
+
+def lbrs_batch_run(b, max_steps: int):
+    _check(load_library().lbrs_batch_run(b, int(max_steps)), "lbrs_batch_run")
+
+
+def lbrs_batch_get_state(b, nunits: int):
+    t = (ctypes.c_double * nunits)()
+    lam = (ctypes.c_double * nunits)()
+    n = (ctypes.c_longlong * nunits)()
+    st = (ctypes.c_uint * nunits)()
+    fail = (ctypes.c_longlong * nunits)()
+    rc = load_library().lbrs_batch_get_state(b, t, n, lam, st, fail)
+    if rc not in (LBRS_OK, LBRS_E_NONPHYSICAL):
+        raise LBRSError(rc, "lbrs_batch_get_state")
+    return {"rc": rc, "t": list(t), "nsteps": list(n), "lambda": list(lam), "status": list(st),
+            "fail_step": list(fail)}
+
+
+def lbrs_batch_moments(b, U):
+    _check(load_library().lbrs_batch_moments(b, _dptr(U)), "lbrs_batch_moments")
+
+
+class Batch1D:
+    """A ragged batch of 1D units in one persistent launch (pools owned here)."""
+
+    def __init__(self, units, t_end=None, chunk: int = 1022, device="cuda"):
+        load_library()
+        self.units = list(units)
+        self.n = len(self.units)
+        self.Q = 2 if self.units[0].model == LBRS_D1Q2 else 3
+        self.chunk = chunk
+        self.offsets, sb = lbrs_batch_query(self.units, chunk)
+        self.total = self.offsets[-1]
+        self.device = torch.device(device)
+        self.f = torch.empty((self.Q * 3, self.total), dtype=torch.float64, device=self.device)
+        self.scratch = torch.zeros(max(sb, 256), dtype=torch.uint8, device=self.device)
+        self.t_end = t_end
+        self.b = None
+
+    def init(self, U0: torch.Tensor):
+        if self.b is not None:
+            load_library().lbrs_batch_destroy(self.b)
+        self.b = lbrs_batch_init(self.units, self.t_end, self.chunk, U0.contiguous(), self.f,
+                                 self.scratch)
+        return self
+
+    def run(self, max_steps: int):
+        lbrs_batch_run(self.b, max_steps)
+
+    def state(self):
+        return lbrs_batch_get_state(self.b, self.n)
+
+    def moments(self) -> torch.Tensor:
+        U = torch.empty((3, self.total), dtype=torch.float64, device=self.device)
+        lbrs_batch_moments(self.b, U)
+        return U
+
+    def unit_slice(self, b: int):
+        return slice(self.offsets[b], self.offsets[b + 1])
+
+    def close(self):
+        if self.b is not None:
+            load_library().lbrs_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:
