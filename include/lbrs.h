@@ -273,6 +273,80 @@ int lbrs_batch_moments(lbrs_batch* b, double* d_U);
 
 void lbrs_batch_destroy(lbrs_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Batch of independent 2D domains (D2Q4, fixed lattice speeds: FROZEN_INIT or
+ * USER mode per domain; PER_STEP is rejected).  Domain d occupies cells
+ * [off_d, off_d + nx_d*ny_d) of the moment pools ([4][total]) and the
+ * population block [16*off_d, 16*(off_d + nx_d*ny_d)) of the population pools,
+ * row-interleaved ([ny_d][16][nx_d]).  One launch advances every domain by
+ * one step (the same fused step as lbrs_step); the adjoint calls (periodic
+ * domains) mirror the single-domain ones.  All calls are asynchronous on the
+ * batch's stream except where noted.
+ * ------------------------------------------------------------------------ */
+typedef struct lbrs_batch2d lbrs_batch2d;
+
+/* Cell offsets (ndom + 1 values, may be NULL) and scratch bytes. */
+int lbrs_batch2d_query(int ndom, const lbrs_params* doms, long long* cell_offsets,
+                       size_t* scratch_bytes);
+
+/* Plan the tiles, upload the domain table to d_scratch (256-byte aligned,
+ * borrowed; waits for the stream once), and reset from d_U0 (see below).
+ * d_f0, d_f1: population pools of 16*total doubles each (borrowed). */
+int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, const double* d_U0,
+                      double* d_f0, double* d_f1, void* d_scratch, void* hip_stream);
+
+/* Every domain's lattice speed from U0 (FROZEN_INIT: lambda*(U0_d)/cfl_d),
+ * f^0 = f^eq(U0) per domain (Sec. II.A), step count 0. */
+int lbrs_batch2d_reset(lbrs_batch2d* b, const double* d_U0);
+
+/* nsteps fused steps of every domain (one launch each). */
+int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps);
+
+/* One step that also stores every domain's input moments U^n in d_Utape [4][total]. */
+int lbrs_batch2d_step_tape(lbrs_batch2d* b, double* d_Utape);
+
+/* Adjoint of one step for every domain (periodic domains only, else
+ * LBRS_E_STATE); same definition as lbrs_adjoint_step, pools as above. */
+int lbrs_batch2d_adjoint_step(lbrs_batch2d* b, const double* d_Utape, const double* d_fbar_next,
+                              double* d_fbar);
+
+/* Adjoint of f^0 = f^eq(U0) for every domain: d_Ubar0 [4][total]. */
+int lbrs_batch2d_adjoint_init(lbrs_batch2d* b, const double* d_fbar0, const double* d_U0,
+                              double* d_Ubar0);
+
+/* Window of the objective: cells whose centres (origin at the domain's lower
+ * left corner) lie in the closed square [lo, hi]^2.  Waits for the stream. */
+int lbrs_batch2d_set_window(lbrs_batch2d* b, double lo, double hi);
+
+/* J_d = sum over domain d's window of rho^2 into d_J [ndom] (each by one
+ * workgroup in a fixed order) and the seed dJ_d/df into d_fbar (pool). */
+int lbrs_batch2d_window_objective(lbrs_batch2d* b, double* d_J, double* d_fbar);
+
+/* Moments of the current populations into d_U [4][total]; population
+ * checkpoints to/from a pool-sized buffer (set_f also sets the step count). */
+int lbrs_batch2d_moments(lbrs_batch2d* b, double* d_U);
+int lbrs_batch2d_get_f(lbrs_batch2d* b, double* d_f);
+int lbrs_batch2d_set_f(lbrs_batch2d* b, const double* d_f, long long n);
+
+/* Gradients dJ_d/dU0 of every domain's window objective after nsteps steps:
+ * reset from d_U0, forward sweep with population checkpoints every `segment`
+ * steps (d_ckpt: ceil(nsteps/segment) pools), objective (d_J [ndom]),
+ * backward sweep (per segment: recompute with the moment tape d_tape,
+ * `segment` sets of [4][total], then reverse adjoint steps; d_fbar, d_work:
+ * pools), adjoint of the initialisation into d_Ubar0 [4][total].  With
+ * use_graph != 0 the whole sequence is captured in a hipGraph on the first
+ * call and replayed after (later calls must pass the same arguments).  No
+ * host synchronisation. */
+int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int segment,
+                          double* d_ckpt, double* d_tape, double* d_fbar, double* d_work,
+                          double* d_J, double* d_Ubar0, int use_graph);
+
+/* Step count, per-domain lattice speed and status (bit 0: a non-physical
+ * state met), host arrays of ndom (may be NULL).  Waits for the stream. */
+int lbrs_batch2d_get_state(lbrs_batch2d* b, long long* nsteps, double* lambda, unsigned* status);
+
+void lbrs_batch2d_destroy(lbrs_batch2d* b);
+
 const char* lbrs_strerror(int code);
 void lbrs_destroy(lbrs_ctx* c);
 

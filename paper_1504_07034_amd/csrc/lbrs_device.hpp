@@ -174,6 +174,70 @@ __device__ inline bool bound_d2q4(const double U[4], double gamma, double* lam) 
     return ok;
 }
 
+// A1(U)^T hx + A2(U)^T hy for the 2D Euler fluxes, with
+// dp/dU = (gamma-1) (|u|^2/2, -u, -v, 1) and H = (E + p)/rho:
+//   A1^T h = h0 e_m + h1 (2u e_m - u^2 e_rho + dp) + h2 (v e_m + u e_n - uv e_rho)
+//            + h3 (H e_m - H u e_rho + u e_E + u dp)
+//   A2^T g = g0 e_n + g1 (v e_m + u e_n - uv e_rho) + g2 (2v e_n - v^2 e_rho + dp)
+//            + g3 (H e_n - H v e_rho + v e_E + v dp)
+__device__ inline void flux_vjp_2d(const double U[4], double gamma, const double hx[4],
+                                   const double hy[4], double out[4]) {
+    const double gm1 = gamma - 1.0;
+    const double ir = 1.0 / U[0];
+    const double u = U[1] * ir, v = U[2] * ir;
+    const double q2 = u * u + v * v;
+    const double p = gm1 * (U[3] - 0.5 * U[0] * q2);
+    const double H = (U[3] + p) * ir;
+    const double al = hx[1] + u * hx[3];
+    const double be = hy[2] + v * hy[3];
+    const double ab = gm1 * (al + be);
+    out[0] = -u * (u * hx[1] + v * hx[2] + H * hx[3]) - v * (u * hy[1] + v * hy[2] + H * hy[3]) +
+             ab * 0.5 * q2;
+    out[1] = hx[0] + 2.0 * u * hx[1] + v * hx[2] + H * hx[3] + v * hy[1] - ab * u;
+    out[2] = u * hx[2] + hy[0] + u * hy[1] + 2.0 * v * hy[2] + H * hy[3] - ab * v;
+    out[3] = u * hx[3] + v * hy[3] + ab;
+}
+
+// fbar^n of one cell (D2Q4 fixed-speed step) from the reverse-streamed
+// fbar*_i = fbar^{n+1}_i(x + s_i) (fb, [i][k]) and the step's input U^n:
+//   Ubar = omega [ (1/4) sum_i fbar*_i + (A1^T h_x + A2^T h_y)/(4 lambda) ],
+//   h_d = sum_i s_{i,d} fbar*_i,   fbar^n_i = (1 - omega) fbar*_i + Ubar.
+__device__ inline void adjoint_cell_d2q4(const double fb[16], const double U[4], double gamma,
+                                         double omega, double lam, double out[16]) {
+    double sum[4], hx[4], hy[4], vjp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sum[k] = (fb[k] + fb[8 + k]) + (fb[4 + k] + fb[12 + k]);
+        hx[k] = (fb[4 + k] + fb[8 + k]) - (fb[k] + fb[12 + k]);
+        hy[k] = (fb[8 + k] + fb[12 + k]) - (fb[k] + fb[4 + k]);
+    }
+    flux_vjp_2d(U, gamma, hx, hy, vjp);
+    const double c4 = 1.0 / (4.0 * lam);
+    const double om1 = 1.0 - omega;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double Ub = omega * (0.25 * sum[k] + c4 * vjp[k]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i * 4 + k] = om1 * fb[i * 4 + k] + Ub;
+    }
+}
+
+// Ubar0 = sum_i (df_i^eq/dU)^T fbar0_i at U0 (adjoint of f^0 = f^eq(U0)).
+__device__ inline void adjoint_init_cell_d2q4(const double fb[16], const double U[4], double gamma,
+                                              double lam, double out[4]) {
+    double sum[4], hx[4], hy[4], vjp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sum[k] = (fb[k] + fb[8 + k]) + (fb[4 + k] + fb[12 + k]);
+        hx[k] = (fb[4 + k] + fb[8 + k]) - (fb[k] + fb[12 + k]);
+        hy[k] = (fb[8 + k] + fb[12 + k]) - (fb[k] + fb[4 + k]);
+    }
+    flux_vjp_2d(U, gamma, hx, hy, vjp);
+    const double c4 = 1.0 / (4.0 * lam);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = 0.25 * sum[k] + c4 * vjp[k];
+}
+
 // ----------------------------------------------------------- 1D Euler
 __device__ inline void euler1(const double U[3], double gm1, double* u, double* p, double* H) {
     double ir = 1.0 / U[0];

@@ -111,6 +111,36 @@ hipError_t launch_zero_counters(unsigned* c, int n, hipStream_t s);
 hipError_t launch_batch1d(const Batch1DArgs& a, int grid, int threads, int chunk, hipStream_t s);
 int batch1d_blocks_per_cu(int Q, int threads, int chunk);
 
+// One domain of a 2D batch (periodic or other sides, fixed lattice speed).
+// Its cells are [coff, coff + nx*ny) of the moment pools ([K][total]); its
+// populations the block of 16*nx*ny doubles at 16*coff of the population
+// pools, row-interleaved ([ny][16][nx]).
+struct Domain2D {
+    long long coff;
+    long long tile0;       // first tile of the domain in the batch's tile list
+    long long row0;        // first row of the domain among all domains' rows
+    int nx, ny;
+    int strip, nstrips, nseg;
+    int bc[4];
+    double dx, gamma, omega, cfl, lam;
+    int lam_mode;
+    int pad;
+};
+
+struct Batch2DArgs {
+    const Domain2D* doms;
+    int ndom;
+    long long ntiles;
+    long long total;       // cells of all domains
+    double* f0;
+    double* f1;
+    int cur;               // buffer holding f^n (host parity)
+    double* tape;          // [4][total] or null
+    unsigned* status;      // per domain
+};
+
+hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
+                               hipStream_t s);
 hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, int max_blocks, hipStream_t s);
 int step2d_blocks_per_cu(int wpb);
 bool step2d_wpb_supported(int wpb);

@@ -308,30 +308,6 @@ __global__ __launch_bounds__(1024) void window_sum_kernel(CellArgs a, const doub
     }
 }
 
-// A1(U)^T hx + A2(U)^T hy for the 2D Euler fluxes, with
-// dp/dU = (gamma-1) (|u|^2/2, -u, -v, 1) and H = (E + p)/rho:
-//   A1^T h = h0 e_m + h1 (2u e_m - u^2 e_rho + dp) + h2 (v e_m + u e_n - uv e_rho)
-//            + h3 (H e_m - H u e_rho + u e_E + u dp)
-//   A2^T g = g0 e_n + g1 (v e_m + u e_n - uv e_rho) + g2 (2v e_n - v^2 e_rho + dp)
-//            + g3 (H e_n - H v e_rho + v e_E + v dp)
-__device__ inline void flux_vjp_2d(const double U[4], double gamma, const double hx[4],
-                                   const double hy[4], double out[4]) {
-    const double gm1 = gamma - 1.0;
-    const double ir = 1.0 / U[0];
-    const double u = U[1] * ir, v = U[2] * ir;
-    const double q2 = u * u + v * v;
-    const double p = gm1 * (U[3] - 0.5 * U[0] * q2);
-    const double H = (U[3] + p) * ir;
-    const double al = hx[1] + u * hx[3];
-    const double be = hy[2] + v * hy[3];
-    const double ab = gm1 * (al + be);
-    out[0] = -u * (u * hx[1] + v * hx[2] + H * hx[3]) - v * (u * hy[1] + v * hy[2] + H * hy[3]) +
-             ab * 0.5 * q2;
-    out[1] = hx[0] + 2.0 * u * hx[1] + v * hx[2] + H * hx[3] + v * hy[1] - ab * u;
-    out[2] = u * hx[2] + hy[0] + u * hy[1] + 2.0 * v * hy[2] + H * hy[3] - ab * v;
-    out[3] = u * hx[3] + v * hy[3] + ab;
-}
-
 // fbar^n from fbar^{n+1} and U^n (D2Q4, periodic sides):
 //   fbar*_i(x) = fbar^{n+1}_i(x + s_i)
 //   Ubar = omega [ (1/4) sum_i fbar*_i + (A1^T h_x + A2^T h_y)/(4 lambda) ]
@@ -354,23 +330,14 @@ __global__ __launch_bounds__(256) void adjoint_step_d2q4(AdjArgs a, const double
 #pragma unroll
         for (int k = 0; k < 4; ++k) fb[i * 4 + k] = gn[(i * 4 + k) * a.ps + src[i]];
     const long long c = (long long)y * a.nx + x;
-    double U[4], sum[4], hx[4], hy[4], vjp[4];
+    double U[4], out[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        U[k] = Un[k * P + c];
-        sum[k] = (fb[k] + fb[8 + k]) + (fb[4 + k] + fb[12 + k]);
-        hx[k] = (fb[4 + k] + fb[8 + k]) - (fb[k] + fb[12 + k]);
-        hy[k] = (fb[8 + k] + fb[12 + k]) - (fb[k] + fb[4 + k]);
-    }
-    flux_vjp_2d(U, a.gamma, hx, hy, vjp);
-    const double c4 = 1.0 / (4.0 * a.st->lam_fixed);
-    const double om1 = 1.0 - a.omega;
+    for (int k = 0; k < 4; ++k) U[k] = Un[k * P + c];
+    adjoint_cell_d2q4(fb, U, a.gamma, a.omega, a.st->lam_fixed, out);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double Ub = a.omega * (0.25 * sum[k] + c4 * vjp[k]);
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) g[(i * 4 + k) * a.ps + (long long)y * a.rs + x] = om1 * fb[i * 4 + k] + Ub;
-    }
+        for (int i = 0; i < 4; ++i) g[(i * 4 + k) * a.ps + (long long)y * a.rs + x] = out[i * 4 + k];
 }
 
 // Ubar0 = sum_i (df_i^eq/dU)^T fbar0_i at U0 (D2Q4).
@@ -379,17 +346,11 @@ __global__ void adjoint_init_d2q4(AdjArgs a, const double* __restrict__ fb0,
     long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.plane) return;
     const long long P = a.plane;
-    double fb[16], U[4], sum[4], hx[4], hy[4], vjp[4];
+    double fb[16], U[4], out[4];
     for (int p = 0; p < 16; ++p) fb[p] = fb0[fofs(a.ps, a.rs, a.nx, p, c)];
-    for (int k = 0; k < 4; ++k) {
-        U[k] = U0[k * P + c];
-        sum[k] = (fb[k] + fb[8 + k]) + (fb[4 + k] + fb[12 + k]);
-        hx[k] = (fb[4 + k] + fb[8 + k]) - (fb[k] + fb[12 + k]);
-        hy[k] = (fb[8 + k] + fb[12 + k]) - (fb[k] + fb[4 + k]);
-    }
-    flux_vjp_2d(U, a.gamma, hx, hy, vjp);
-    const double c4 = 1.0 / (4.0 * a.st->lam_fixed);
-    for (int k = 0; k < 4; ++k) Ub[k * P + c] = 0.25 * sum[k] + c4 * vjp[k];
+    for (int k = 0; k < 4; ++k) U[k] = U0[k * P + c];
+    adjoint_init_cell_d2q4(fb, U, a.gamma, a.st->lam_fixed, out);
+    for (int k = 0; k < 4; ++k) Ub[k * P + c] = out[k];
 }
 
 // ------------------------------------------------------------ launchers

@@ -91,6 +91,141 @@ __device__ inline void collide_and_shift(const double f[16], double gm1, double 
     }
 }
 
+// Geometry and physics of the domain a tile belongs to.
+struct TileGeom {
+    const double* fin;
+    double* fout;
+    double* tape;       // U^n planes (TAPE), element (k, y, x) at k*tape_ps + y*nx + x
+    long long tape_ps;
+    long long ps, rs;   // population offset p*ps + y*rs + x
+    int nx, ny;
+    int strip, nstrips, nseg;
+    double c4lam, omega, gamma;
+    int bc[4];
+};
+
+// One tile: a strip of g.strip output columns (lanes 1..strip; lanes 0 and
+// strip+1 are its halo columns) over row segment `seg` of the domain,
+// marched row by row.  Accumulates the lane's bound of the new state and its
+// admissibility.
+template <bool TAPE, int WPB>
+__device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane, double& lmax,
+                                          bool& bad) {
+    const int nx = g.nx, ny = g.ny;
+    const bool px = g.bc[0] == BC_PERIODIC, py = g.bc[2] == BC_PERIODIC;
+    const double* __restrict__ fin = g.fin;
+    double* __restrict__ fout = g.fout;
+    const long long ps = g.ps, rs = g.rs;
+    const double gm1 = g.gamma - 1.0;
+    const double c4lam = g.c4lam, omega = g.omega;
+    const int row_bytes = nx * 8;
+    const int strip = tile % g.nstrips;
+    const int seg = tile / g.nstrips;
+    const int x = strip * g.strip - 1 + lane;
+    const int y0 = (int)(((long long)seg * ny) / g.nseg);
+    const int y1 = (int)(((long long)(seg + 1) * ny) / g.nseg);
+    const int xl = map_index(x, nx, px);
+    const bool out_lane = lane >= 1 && lane <= g.strip && x < nx;
+    const int voff = out_lane ? x * 8 : 0x7fffffff;
+    const bool wall_xlo = g.bc[0] == BC_WALL && x == 0;
+    const bool wall_xhi = g.bc[1] == BC_WALL && x == nx - 1;
+
+    // prologue: rows y0-1 and y0 fill the two-row pipeline (no output)
+    double f[16], nxt[16], U[4];
+    Shifted sh;
+    load_row(f, fin, ps, (long long)map_index(y0 - 1, ny, py) * rs + xl);
+    load_row(nxt, fin, ps, (long long)map_index(y0, ny, py) * rs + xl);
+    collide_and_shift(f, gm1, c4lam, omega, U, sh);
+    double A3[4], A4[4], B3[4], B4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        A3[k] = sh.n3[k];
+        A4[k] = sh.n4[k];
+    }
+#pragma unroll
+    for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+    load_row(nxt, fin, ps, (long long)map_index(y0 + 1, ny, py) * rs + xl);
+    collide_and_shift(f, gm1, c4lam, omega, U, sh);
+    if (TAPE) {
+        double* trow = g.tape + (long long)y0 * nx;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store_row(trow + k * g.tape_ps, row_bytes, voff, U[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        B3[k] = A3[k];
+        B4[k] = A4[k];
+        A3[k] = sh.n3[k];
+        A4[k] = sh.n4[k];
+    }
+
+    // main loop: row r completes output row r-1
+    for (int r = y0 + 1; r <= y1; ++r) {
+        // lockstep with the workgroup's neighbouring strips (same trip
+        // count by construction); no fence: nothing is exchanged
+        if (WPB > 1) __builtin_amdgcn_s_barrier();
+#pragma unroll
+        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+        load_row(nxt, fin, ps, (long long)map_index(r + 1, ny, py) * rs + xl);
+        collide_and_shift(f, gm1, c4lam, omega, U, sh);
+        if (TAPE) {
+            // U^n of row r; row y1 is the next segment's first row
+            double* trow = g.tape + (long long)map_index(r, ny, false) * nx;
+            const int tv = r < y1 ? voff : 0x7fffffff;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) store_row(trow + k * g.tape_ps, row_bytes, tv, U[k]);
+        }
+        const int o = r - 1;
+        double go[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            go[0 * 4 + k] = sh.s1[k];
+            go[1 * 4 + k] = sh.s2[k];
+            go[2 * 4 + k] = B3[k];
+            go[3 * 4 + k] = B4[k];
+        }
+        // specular reflection at wall node rows/columns: the incoming
+        // populations mirror the outgoing ones, normal momentum negated
+        const bool wall_top = g.bc[3] == BC_WALL && o == ny - 1;
+        const bool wall_bot = g.bc[2] == BC_WALL && o == 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double sy = (k == 2) ? -1.0 : 1.0, sx = (k == 1) ? -1.0 : 1.0;
+            if (wall_top) {
+                go[0 * 4 + k] = sy * go[3 * 4 + k];
+                go[1 * 4 + k] = sy * go[2 * 4 + k];
+            }
+            if (wall_bot) {
+                go[3 * 4 + k] = sy * go[0 * 4 + k];
+                go[2 * 4 + k] = sy * go[1 * 4 + k];
+            }
+            if (wall_xlo) {
+                go[1 * 4 + k] = sx * go[0 * 4 + k];
+                go[2 * 4 + k] = sx * go[3 * 4 + k];
+            }
+            if (wall_xhi) {
+                go[0 * 4 + k] = sx * go[1 * 4 + k];
+                go[3 * 4 + k] = sx * go[2 * 4 + k];
+            }
+        }
+        double* orow = fout + (long long)o * rs;
+#pragma unroll
+        for (int p = 0; p < 16; ++p) store_row(orow + p * ps, row_bytes, voff, go[p]);
+        double Un[4], l;
+        moments_d2q4(go, Un);
+        const bool ok = bound_d2q4(Un, g.gamma, &l);
+        bad |= out_lane && !ok;
+        lmax = fmax(lmax, out_lane ? l : 0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            B3[k] = A3[k];
+            B4[k] = A4[k];
+            A3[k] = sh.n3[k];
+            A4[k] = sh.n4[k];
+        }
+    }
+}
+
 template <bool TAPE, int WPB>
 __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
     const LaunchSlots ls = slots_for(a.launch);
@@ -103,134 +238,78 @@ __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
     // wave-uniform, so that tile and row indices (and the store descriptors)
     // live in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nx = a.nx, ny = a.ny;
-    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
-    const double* __restrict__ fin = c.cur ? a.f1 : a.f0;
-    double* __restrict__ fout = c.cur ? a.f0 : a.f1;
-    const long long plane = a.plane, ps = a.ps, rs = a.rs;
-    const double gm1 = a.gamma - 1.0;
-    const double c4lam = 1.0 / (4.0 * c.lam);
-    const double omega = a.omega;
-    const int row_bytes = nx * 8;
+    TileGeom g;
+    g.fin = c.cur ? a.f1 : a.f0;
+    g.fout = c.cur ? a.f0 : a.f1;
+    g.tape = a.tape;
+    g.tape_ps = a.plane;
+    g.ps = a.ps;
+    g.rs = a.rs;
+    g.nx = a.nx;
+    g.ny = a.ny;
+    g.strip = a.strip;
+    g.nstrips = a.nstrips;
+    g.nseg = a.nseg;
+    g.c4lam = 1.0 / (4.0 * c.lam);
+    g.omega = a.omega;
+    g.gamma = a.gamma;
+    for (int s = 0; s < 4; ++s) g.bc[s] = a.bc[s];
     const int total_waves = gridDim.x * WPB;
 
     double lmax = 0.0;
     bool bad = false;
-
     for (int tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wave; tile < a.ntiles;
-         tile += total_waves) {
-        const int strip = tile % a.nstrips;
-        const int seg = tile / a.nstrips;
-        const int x = strip * a.strip - 1 + lane;
-        const int y0 = (int)(((long long)seg * ny) / a.nseg);
-        const int y1 = (int)(((long long)(seg + 1) * ny) / a.nseg);
-        const int xl = map_index(x, nx, px);
-        const bool out_lane = lane >= 1 && lane <= a.strip && x < nx;
-        const int voff = out_lane ? x * 8 : 0x7fffffff;
-        const bool wall_xlo = a.bc[0] == BC_WALL && x == 0;
-        const bool wall_xhi = a.bc[1] == BC_WALL && x == nx - 1;
-
-        // prologue: rows y0-1 and y0 fill the two-row pipeline (no output)
-        double f[16], nxt[16], U[4];
-        Shifted sh;
-        load_row(f, fin, ps, (long long)map_index(y0 - 1, ny, py) * rs + xl);
-        load_row(nxt, fin, ps, (long long)map_index(y0, ny, py) * rs + xl);
-        collide_and_shift(f, gm1, c4lam, omega, U, sh);
-        double A3[4], A4[4], B3[4], B4[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            A3[k] = sh.n3[k];
-            A4[k] = sh.n4[k];
-        }
-#pragma unroll
-        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-        load_row(nxt, fin, ps, (long long)map_index(y0 + 1, ny, py) * rs + xl);
-        collide_and_shift(f, gm1, c4lam, omega, U, sh);
-        if (TAPE) {
-            double* trow = a.tape + (long long)y0 * nx;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) store_row(trow + k * plane, row_bytes, voff, U[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            B3[k] = A3[k];
-            B4[k] = A4[k];
-            A3[k] = sh.n3[k];
-            A4[k] = sh.n4[k];
-        }
-
-        // main loop: row r completes output row r-1
-        for (int r = y0 + 1; r <= y1; ++r) {
-            // lockstep with the workgroup's neighbouring strips (same trip
-            // count by construction); no fence: nothing is exchanged
-            if (WPB > 1) __builtin_amdgcn_s_barrier();
-#pragma unroll
-            for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-            load_row(nxt, fin, ps, (long long)map_index(r + 1, ny, py) * rs + xl);
-            collide_and_shift(f, gm1, c4lam, omega, U, sh);
-            if (TAPE) {
-                // U^n of row r; row y1 is the next segment's first row
-                double* trow = a.tape + (long long)map_index(r, ny, false) * nx;
-                const int tv = r < y1 ? voff : 0x7fffffff;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) store_row(trow + k * plane, row_bytes, tv, U[k]);
-            }
-            const int o = r - 1;
-            double g[16];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                g[0 * 4 + k] = sh.s1[k];
-                g[1 * 4 + k] = sh.s2[k];
-                g[2 * 4 + k] = B3[k];
-                g[3 * 4 + k] = B4[k];
-            }
-            // specular reflection at wall node rows/columns: the incoming
-            // populations mirror the outgoing ones, normal momentum negated
-            const bool wall_top = a.bc[3] == BC_WALL && o == ny - 1;
-            const bool wall_bot = a.bc[2] == BC_WALL && o == 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double sy = (k == 2) ? -1.0 : 1.0, sx = (k == 1) ? -1.0 : 1.0;
-                if (wall_top) {
-                    g[0 * 4 + k] = sy * g[3 * 4 + k];
-                    g[1 * 4 + k] = sy * g[2 * 4 + k];
-                }
-                if (wall_bot) {
-                    g[3 * 4 + k] = sy * g[0 * 4 + k];
-                    g[2 * 4 + k] = sy * g[1 * 4 + k];
-                }
-                if (wall_xlo) {
-                    g[1 * 4 + k] = sx * g[0 * 4 + k];
-                    g[2 * 4 + k] = sx * g[3 * 4 + k];
-                }
-                if (wall_xhi) {
-                    g[0 * 4 + k] = sx * g[1 * 4 + k];
-                    g[3 * 4 + k] = sx * g[2 * 4 + k];
-                }
-            }
-            double* orow = fout + (long long)o * rs;
-#pragma unroll
-            for (int p = 0; p < 16; ++p) store_row(orow + p * ps, row_bytes, voff, g[p]);
-            double Un[4], l;
-            moments_d2q4(g, Un);
-            const bool ok = bound_d2q4(Un, a.gamma, &l);
-            bad |= out_lane && !ok;
-            lmax = fmax(lmax, out_lane ? l : 0.0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                B3[k] = A3[k];
-                B4[k] = A4[k];
-                A3[k] = sh.n3[k];
-                A4[k] = sh.n4[k];
-            }
-        }
-    }
+         tile += total_waves)
+        step_tile<TAPE, WPB>(g, tile, lane, lmax, bad);
 
     if (a.lam_mode == LAM_PER_STEP) {
         double wm = wave_max(lmax);
         if (lane == 0) publish_max(&st->lam[ls.la], wm);
     }
     if (__any(bad) && lane == 0) publish_bad(st, ls, c.n + 1);
+}
+
+// The same step over a batch of independent domains at fixed lattice speeds:
+// tiles are numbered domain by domain (each domain's tile count a multiple of
+// the waves per workgroup, so a workgroup's waves share a domain and a row
+// segment); `cur` selects the buffer holding f^n for every domain.
+template <bool TAPE, int WPB>
+__global__ __launch_bounds__(64 * WPB) void step2d_batch(Batch2DArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int total_waves = gridDim.x * WPB;
+    for (long long tile = (long long)xcd_remap(blockIdx.x, gridDim.x) * WPB + wave;
+         tile < a.ntiles; tile += total_waves) {
+        // domain of the tile (binary search over the first tiles)
+        int lo = 0, hi = a.ndom - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (a.doms[mid].tile0 <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const Domain2D& d = a.doms[lo];
+        TileGeom g;
+        const long long fo = 16 * d.coff;
+        g.fin = (a.cur ? a.f1 : a.f0) + fo;
+        g.fout = (a.cur ? a.f0 : a.f1) + fo;
+        g.tape = a.tape ? a.tape + d.coff : nullptr;
+        g.tape_ps = a.total;
+        g.ps = d.nx;
+        g.rs = 16LL * d.nx;
+        g.nx = d.nx;
+        g.ny = d.ny;
+        g.strip = d.strip;
+        g.nstrips = d.nstrips;
+        g.nseg = d.nseg;
+        g.c4lam = 1.0 / (4.0 * d.lam);
+        g.omega = d.omega;
+        g.gamma = d.gamma;
+        for (int s = 0; s < 4; ++s) g.bc[s] = d.bc[s];
+        double lmax = 0.0;
+        bool bad = false;
+        step_tile<TAPE, WPB>(g, (int)(tile - d.tile0), lane, lmax, bad);
+        if (__any(bad) && lane == 0) atomicOr(&a.status[lo], 1u);
+    }
 }
 
 template <bool TAPE, int WPB>
@@ -246,6 +325,24 @@ static hipError_t launch_one(const Step2DArgs& a, int max_blocks, hipStream_t s)
 hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, int max_blocks, hipStream_t s) {
 #define LBRS_CASE(W)                                                                       \
     if (wpb == W) return tape ? launch_one<true, W>(a, max_blocks, s) : launch_one<false, W>(a, max_blocks, s);
+    LBRS_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return hipErrorInvalidValue;
+}
+
+template <bool TAPE, int WPB>
+static hipError_t launch_batch_one(const Batch2DArgs& a, int max_blocks, hipStream_t s) {
+    long long nblocks = (a.ntiles + WPB - 1) / WPB;
+    if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
+    hipLaunchKernelGGL((step2d_batch<TAPE, WPB>), dim3((unsigned)nblocks), dim3(64 * WPB), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
+                               hipStream_t s) {
+#define LBRS_CASE(W)                                                                      \
+    if (wpb == W) return tape ? launch_batch_one<true, W>(a, max_blocks, s)              \
+                              : launch_batch_one<false, W>(a, max_blocks, s);
     LBRS_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return hipErrorInvalidValue;

@@ -31,7 +31,11 @@ EXPORTS = (
     "lbrs_isentropic_to_cons", "lbrs_isentropic_to_cons_adjoint", "lbrs_forward_checkpointed",
     "lbrs_backward_checkpointed", "lbrs_set_stream", "lbrs_set_tile", "lbrs_batch_query",
     "lbrs_batch_init", "lbrs_batch_run", "lbrs_batch_get_state", "lbrs_batch_moments",
-    "lbrs_batch_destroy", "lbrs_strerror", "lbrs_destroy",
+    "lbrs_batch_destroy", "lbrs_batch2d_query", "lbrs_batch2d_init", "lbrs_batch2d_reset",
+    "lbrs_batch2d_step", "lbrs_batch2d_step_tape", "lbrs_batch2d_adjoint_step",
+    "lbrs_batch2d_adjoint_init", "lbrs_batch2d_set_window", "lbrs_batch2d_window_objective",
+    "lbrs_batch2d_moments", "lbrs_batch2d_get_f", "lbrs_batch2d_set_f", "lbrs_batch2d_gradient",
+    "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_strerror", "lbrs_destroy",
 )
 
 
@@ -97,6 +101,21 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
                                      ctypes.POINTER(ll)]),
         "lbrs_batch_moments": (i, [vp, vp]),
         "lbrs_batch_destroy": (None, [vp]),
+        "lbrs_batch2d_query": (i, [i, P, ctypes.POINTER(ll), szp]),
+        "lbrs_batch2d_init": (i, [ctypes.POINTER(vp), i, P, vp, vp, vp, vp, vp]),
+        "lbrs_batch2d_reset": (i, [vp, vp]),
+        "lbrs_batch2d_step": (i, [vp, i]),
+        "lbrs_batch2d_step_tape": (i, [vp, vp]),
+        "lbrs_batch2d_adjoint_step": (i, [vp, vp, vp, vp]),
+        "lbrs_batch2d_adjoint_init": (i, [vp, vp, vp, vp]),
+        "lbrs_batch2d_set_window": (i, [vp, d, d]),
+        "lbrs_batch2d_window_objective": (i, [vp, vp, vp]),
+        "lbrs_batch2d_moments": (i, [vp, vp]),
+        "lbrs_batch2d_get_f": (i, [vp, vp]),
+        "lbrs_batch2d_set_f": (i, [vp, vp, ll]),
+        "lbrs_batch2d_gradient": (i, [vp, vp, i, i, vp, vp, vp, vp, vp, vp, i]),
+        "lbrs_batch2d_get_state": (i, [vp, ctypes.POINTER(ll), dp, ctypes.POINTER(ctypes.c_uint)]),
+        "lbrs_batch2d_destroy": (None, [vp]),
         "lbrs_strerror": (ctypes.c_char_p, [i]),
         "lbrs_destroy": (None, [vp]),
     }
@@ -447,6 +466,106 @@ class Batch1D:
     def close(self):
         if self.b is not None:
             load_library().lbrs_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- 2D batch
+class Batch2D:
+    """Independent 2D domains stepped together (fixed lattice speeds); pools,
+    checkpoint store and tape owned here.  Thin: every call is one C call."""
+
+    def __init__(self, doms, device="cuda"):
+        lib = load_library()
+        self.doms = list(doms)
+        self.n = len(self.doms)
+        arr = (lbrs_params * self.n)(*self.doms)
+        offs = (ctypes.c_longlong * (self.n + 1))()
+        sb = ctypes.c_size_t()
+        _check(lib.lbrs_batch2d_query(self.n, arr, offs, ctypes.byref(sb)), "lbrs_batch2d_query")
+        self.offsets = list(offs)
+        self.total = self.offsets[-1]
+        self.device = torch.device(device)
+        self.f0 = torch.empty(16 * self.total, dtype=torch.float64, device=self.device)
+        self.f1 = torch.empty(16 * self.total, dtype=torch.float64, device=self.device)
+        self.scratch = torch.zeros(max(sb.value, 256), dtype=torch.uint8, device=self.device)
+        self._arr = arr
+        self.b = None
+
+    def init(self, U0: torch.Tensor, stream=None):
+        lib = load_library()
+        if self.b is not None:
+            lib.lbrs_batch2d_destroy(self.b)
+        self.U0 = U0.contiguous()
+        b = ctypes.c_void_p()
+        _check(lib.lbrs_batch2d_init(ctypes.byref(b), self.n, self._arr, _dptr(self.U0),
+                                     _dptr(self.f0), _dptr(self.f1),
+                                     ctypes.c_void_p(self.scratch.data_ptr()), _stream(stream)),
+               "lbrs_batch2d_init")
+        self.b = b
+        return self
+
+    def reset(self, U0):
+        _check(load_library().lbrs_batch2d_reset(self.b, _dptr(U0)), "lbrs_batch2d_reset")
+
+    def step(self, n: int):
+        _check(load_library().lbrs_batch2d_step(self.b, int(n)), "lbrs_batch2d_step")
+
+    def step_tape(self, tape):
+        _check(load_library().lbrs_batch2d_step_tape(self.b, _dptr(tape)), "lbrs_batch2d_step_tape")
+
+    def adjoint_step(self, tape, gn, g):
+        _check(load_library().lbrs_batch2d_adjoint_step(self.b, _dptr(tape), _dptr(gn), _dptr(g)),
+               "lbrs_batch2d_adjoint_step")
+
+    def adjoint_init(self, fb0, U0, Ub):
+        _check(load_library().lbrs_batch2d_adjoint_init(self.b, _dptr(fb0), _dptr(U0), _dptr(Ub)),
+               "lbrs_batch2d_adjoint_init")
+
+    def set_window(self, lo: float, hi: float):
+        _check(load_library().lbrs_batch2d_set_window(self.b, float(lo), float(hi)),
+               "lbrs_batch2d_set_window")
+
+    def window_objective(self, J, fbar):
+        _check(load_library().lbrs_batch2d_window_objective(self.b, _dptr(J), _dptr(fbar)),
+               "lbrs_batch2d_window_objective")
+
+    def moments(self) -> torch.Tensor:
+        U = torch.empty((4, self.total), dtype=torch.float64, device=self.device)
+        _check(load_library().lbrs_batch2d_moments(self.b, _dptr(U)), "lbrs_batch2d_moments")
+        return U
+
+    def get_f(self) -> torch.Tensor:
+        f = torch.empty(16 * self.total, dtype=torch.float64, device=self.device)
+        _check(load_library().lbrs_batch2d_get_f(self.b, _dptr(f)), "lbrs_batch2d_get_f")
+        return f
+
+    def gradient(self, U0, nsteps: int, segment: int, ckpt, tape, fbar, work, J, Ubar0,
+                 use_graph: bool = True):
+        _check(load_library().lbrs_batch2d_gradient(
+            self.b, _dptr(U0), int(nsteps), int(segment), _dptr(ckpt), _dptr(tape), _dptr(fbar),
+            _dptr(work), _dptr(J), _dptr(Ubar0), int(use_graph)), "lbrs_batch2d_gradient")
+
+    def state(self):
+        n = ctypes.c_longlong()
+        lam = (ctypes.c_double * self.n)()
+        st = (ctypes.c_uint * self.n)()
+        rc = load_library().lbrs_batch2d_get_state(self.b, ctypes.byref(n), lam, st)
+        if rc not in (LBRS_OK, LBRS_E_NONPHYSICAL):
+            raise LBRSError(rc, "lbrs_batch2d_get_state")
+        return {"rc": rc, "nsteps": n.value, "lambda": list(lam), "status": list(st)}
+
+    def unit_slice(self, d: int):
+        return slice(self.offsets[d], self.offsets[d + 1])
+
+    def close(self):
+        if self.b is not None:
+            load_library().lbrs_batch2d_destroy(self.b)
             self.b = None
 
     def __del__(self):

@@ -156,9 +156,10 @@ def fourier_modes(n: int, seed: int, nmodes: int = 8, gamma: float = 1.4,
     theta ~ U[0, 2 pi) and a random sign, normalised by nmodes."""
     rng = np.random.default_rng(seed)
     x = centres(n, 0.0, 1.0)
-    X, Y = np.meshgrid(x, x, indexing="xy")
 
     def field():
+        # cos(a + b) = cos a cos b - sin a sin b with a = 2 pi kx x + theta and
+        # b = 2 pi ky y: each mode is a sum of two outer products ([y][x])
         acc = np.zeros((n, n))
         for _ in range(nmodes):
             while True:
@@ -167,7 +168,9 @@ def fourier_modes(n: int, seed: int, nmodes: int = 8, gamma: float = 1.4,
                     break
             th = rng.uniform(0.0, 2.0 * math.pi)
             sg = rng.choice([-1.0, 1.0])
-            acc += sg * np.cos(2.0 * math.pi * (kx * X + ky * Y) + th)
+            a = 2.0 * math.pi * kx * x + th
+            b = 2.0 * math.pi * ky * x
+            acc += sg * (np.outer(np.cos(b), np.cos(a)) - np.outer(np.sin(b), np.sin(a)))
         return acc / nmodes
 
     W = np.empty((4, n, n))
