@@ -24,8 +24,8 @@ METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (calibrated against a plain copy), valid for the kernel source they were taken
 # on (profiles/step2d_d2q4_riemann4096.md); null once the source changes.
-TRAFFIC_BYTES = 4.433e9
-TRAFFIC_SOURCE_HASH = "e4135b5d4352c596"
+TRAFFIC_BYTES = 4.432e9
+TRAFFIC_SOURCE_HASH = "79bd4658efd82c8a"
 TRAFFIC_SHAPE = {"rows": 0, "wpb": 16, "layout": 1}
 
 
@@ -129,6 +129,98 @@ def batched_1d(chunks=(510, 1022, 2046), subset=32):
                        "sequential_ms": round(ms_s, 2), "speedup": round(ms_s / ms_b, 2)}}
 
 
+def _time_ms(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def adjoint_2d(n=2048, steps=2000, k=50):
+    """Adjoint configuration (2048^2 periodic acoustic pulse, frozen lattice
+    speed, 2000 steps, J over [0.7,0.8]^2): time of a plain step, of a step
+    writing the U^n tape, of an adjoint step, and of the whole sqrt(T)
+    checkpointed gradient (forward with checkpoints + recompute + reverse)."""
+    import torch
+
+    from paper_1504_07034_amd import adjoint, lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    w = wl.acoustic_pulse(n, steps=steps)
+    rho0 = torch.from_numpy(w.W[0].copy()).cuda()
+    run = adjoint.GradientRunner(adjoint.GradientSpec(n=n, steps=steps), rho0)
+    sim = run.sim
+    run.forward(rho0, keep=False)
+    fwd = _time_ms(lambda: sim.step(k)) / k
+    tape = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
+    tap = _time_ms(lambda: [lbrs.lbrs_step_tape(sim.ctx, tape) for _ in range(k)]) / k
+    g = torch.empty_like(run.fbar)
+    adj = _time_ms(lambda: [lbrs.lbrs_adjoint_step(sim.ctx, tape, run.fbar, g) for _ in range(k)]) / k
+    r = rho0.clone().requires_grad_(True)
+
+    def grad():
+        J = adjoint.LBRSFunction.apply(r, run)
+        J.backward()
+
+    grad()
+    t_grad = _time_ms(grad)
+    t_fwd = _time_ms(lambda: run.forward(rho0, keep=False))
+    run.close()
+    cells = n * n
+    return {"n": n, "steps": steps, "segment": run.spec.seg,
+            "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap, 4),
+            "adjoint_step_ms": round(adj, 4),
+            "adjoint_over_forward": round((tap + adj) / fwd, 3),
+            "adjoint_step_GBs": round(288 * cells / (adj * 1e-3) / 1e9, 1),
+            "gradient_ms": round(t_grad, 1), "forward_run_ms": round(t_fwd, 1),
+            "gradient_over_forward_run": round(t_grad / t_fwd, 3)}
+
+
+def batched_2d(k=10):
+    """128 seeded periodic domains (sides 256..2048): one launch per step for all
+    domains, against the same domains stepped one at a time."""
+    import torch
+
+    from paper_1504_07034_amd import lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    ws = wl.domain_batch(128, seed=0)
+    doms = [lbrs.make_params(lbrs.LBRS_D2Q4, w.nx, w.ny, w.domain, w.gamma, w.omega, w.cfl,
+                             w.sides, lbrs.LBRS_LAMBDA_FROZEN_INIT, 0.0, lbrs.LBRS_LAYOUT_ROWS)
+            for w in ws]
+    Us = []
+    for w, p in zip(ws, doms):
+        Wt = torch.from_numpy(w.W).cuda()
+        U = torch.empty_like(Wt)
+        lbrs.lbrs_prim_to_cons(p, Wt, U)
+        Us.append(U)
+    B = lbrs.Batch2D(doms)
+    B.init(torch.cat([U.reshape(4, -1) for U in Us], dim=1))
+    B.step(2)
+    ms_b = _time_ms(lambda: B.step(k)) / k
+    total = B.total
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+    ms_s = 0.0
+    for w, U in zip(ws, Us):
+        sim = lbrs.Sim(lbrs.LBRS_D2Q4, w.nx, w.ny, domain=w.domain, gamma=w.gamma, cfl=w.cfl,
+                       bc=w.sides, lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT,
+                       layout=lbrs.LBRS_LAYOUT_ROWS)
+        sim.init(U)
+        sim.step(2)
+        ms_s += _time_ms(lambda: sim.step(k)) / k
+        sim.close()
+    return {"domains": len(ws), "cells": int(total), "batched_ms_per_step": round(ms_b, 3),
+            "MLUPS": round(total / ms_b / 1e3, 1),
+            "sequential_ms_per_step": round(ms_s, 3), "speedup": round(ms_s / ms_b, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +233,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
+    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d"], default=None,
+                    help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain copy of the populations (lbrs_get_f: "
                          "16 planes read and written) as a known-size reference for counters")
@@ -156,6 +250,10 @@ def main():
     from paper_1504_07034_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.only:
+        fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
     n = 4096
     t_end = 0.3
     w = wl.riemann2d(n, t_end=t_end)
@@ -245,7 +343,12 @@ def main():
     del U0
     torch.cuda.empty_cache()
     if not args.no_extras:
+        rec["adjoint_2d"] = adjoint_2d()
+        torch.cuda.empty_cache()
         rec["batched_1d"] = batched_1d()
+        torch.cuda.empty_cache()
+        rec["batched_2d"] = batched_2d()
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()
     print(json.dumps(rec), flush=True)
