@@ -22,11 +22,18 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
 
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# (calibrated against a plain copy), valid for the kernel source they were taken
-# on (profiles/step2d_d2q4_riemann4096.md); null once the source changes.
-TRAFFIC_BYTES = 4.432e9
-TRAFFIC_SOURCE_HASH = "79bd4658efd82c8a"
-TRAFFIC_SHAPE = {"rows": 0, "wpb": 16, "layout": 1}
+# (calibrated against a plain copy), by launch shape "waves_per_block,alternate"
+# (automatic row segments, row-interleaved layout), valid for the kernel source
+# they were taken on (profiles/step2d_d2q4_riemann4096.md); null once the
+# source changes or for a shape not profiled.
+TRAFFIC_BYTES = {}
+TRAFFIC_SOURCE_HASH = ""
+
+
+def traffic_bytes(shape, layout):
+    if kernel_source_hash() != TRAFFIC_SOURCE_HASH or shape["rows"] != 0 or layout != 1:
+        return None
+    return TRAFFIC_BYTES.get(f"{shape['wpb']},{shape['alt']}")
 
 
 def kernel_source_hash() -> str:
@@ -60,7 +67,22 @@ def cpu_baseline(nsteps: int = 2):
     lups = 4096 * 4096 * r.nsteps
     return {"value": lups / secs / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"4096x4096 four-quadrant problem, {r.nsteps} steps from t=0 "
-                      f"({secs:.1f} s of stepping; init excluded)"}
+                      f"({secs:.1f} s of stepping; init excluded)",
+            "host": _host_cpu()}
+
+
+def _host_cpu() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
 
 
 def batched_1d(chunks=(510, 1022, 2046), subset=32):
@@ -124,6 +146,7 @@ def batched_1d(chunks=(510, 1022, 2046), subset=32):
     ms_s = (time.perf_counter() - t0) * 1e3
     return {"units": len(tubes), "cells": int(sum(t.nx for t in tubes)), "chunk": best,
             "ms": round(ms, 2), "MLUPS": round(lups / ms / 1e3, 1),
+            "effective_GBs": round(144 * lups / ms / 1e6, 1),
             "chunk_ms": {str(c): round(v[0], 2) for c, v in tuned.items()},
             "subset": {"units": subset, "batched_ms": round(ms_b, 2),
                        "sequential_ms": round(ms_s, 2), "speedup": round(ms_s / ms_b, 2)}}
@@ -154,6 +177,7 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     w = wl.acoustic_pulse(n, steps=steps)
     rho0 = torch.from_numpy(w.W[0].copy()).cuda()
     run = adjoint.GradientRunner(adjoint.GradientSpec(n=n, steps=steps), rho0)
+    best = run.tune(rho0)
     sim = run.sim
     run.forward(rho0, keep=False)
     fwd = _time_ms(lambda: sim.step(k)) / k
@@ -173,6 +197,7 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     run.close()
     cells = n * n
     return {"n": n, "steps": steps, "segment": run.spec.seg,
+            "tile_rows": best["rows"], "waves_per_block": best["wpb"], "alternate": best["alt"],
             "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap, 4),
             "adjoint_step_ms": round(adj, 4),
             "adjoint_over_forward": round((tap + adj) / fwd, 3),
@@ -181,7 +206,7 @@ def adjoint_2d(n=2048, steps=2000, k=50):
             "gradient_over_forward_run": round(t_grad / t_fwd, 3)}
 
 
-def batched_2d(k=10):
+def batched_2d(k=10, ws=None):
     """128 seeded periodic domains (sides 256..2048): one launch per step for all
     domains, against the same domains stepped one at a time."""
     import torch
@@ -189,7 +214,7 @@ def batched_2d(k=10):
     from paper_1504_07034_amd import lbrs
     from paper_1504_07034_amd import workloads as wl
 
-    ws = wl.domain_batch(128, seed=0)
+    ws = ws or wl.domain_batch(128, seed=0)
     doms = [lbrs.make_params(lbrs.LBRS_D2Q4, w.nx, w.ny, w.domain, w.gamma, w.omega, w.cfl,
                              w.sides, lbrs.LBRS_LAMBDA_FROZEN_INIT, 0.0, lbrs.LBRS_LAYOUT_ROWS)
             for w in ws]
@@ -221,6 +246,177 @@ def batched_2d(k=10):
             "sequential_ms_per_step": round(ms_s, 3), "speedup": round(ms_s / ms_b, 3)}
 
 
+def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None):
+    """Batched forward+adjoint: dJ_d/dU0 of the 128 seeded periodic domains after
+    1000 steps (frozen lattice speeds, J over [0.7,0.8]^2), sqrt(T) checkpointed.
+    The pools run in memory waves, each wave one captured hipGraph (capture
+    included in the time: every wave runs once); against the single-domain
+    checkpointed path run domain by domain on a seeded subset."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1504_07034_amd import adjoint, lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    ws = ws or wl.domain_batch(128, seed=0, steps=steps)
+    seg = max(1, round(2 * math.sqrt(steps)))  # minimises 128*ceil(T/s) + 32*s bytes per cell
+    nck = math.ceil(steps / seg)
+    per_cell = 8 * (16 * (nck + 4) + 4 * (seg + 2))  # ckpt, f0 f1 fbar work, tape, U0 Ubar0
+
+    def doms_of(sel):
+        return [lbrs.make_params(lbrs.LBRS_D2Q4, w.nx, w.ny, w.domain, w.gamma, w.omega, w.cfl,
+                                 w.sides, lbrs.LBRS_LAMBDA_FROZEN_INIT, 0.0,
+                                 lbrs.LBRS_LAYOUT_ROWS) for w in sel]
+
+    def U0_of(sel, doms):
+        out = []
+        for w, p in zip(sel, doms):
+            Wt = torch.from_numpy(w.W).cuda()
+            U = torch.empty_like(Wt)
+            lbrs.lbrs_prim_to_cons(p, Wt, U)
+            out.append(U.reshape(4, -1))
+        return torch.cat(out, dim=1).contiguous()
+
+    def run_wave(sel, replays=0):
+        doms = doms_of(sel)
+        B = lbrs.Batch2D(doms)
+        U0 = U0_of(sel, doms)
+        B.init(U0)
+        B.set_window(0.7, 0.8)
+        T = B.total
+        ck = torch.empty(nck * 16 * T, dtype=torch.float64, device="cuda")
+        tp = torch.empty(seg * 4 * T, dtype=torch.float64, device="cuda")
+        fb = torch.empty(16 * T, dtype=torch.float64, device="cuda")
+        wk = torch.empty_like(fb)
+        J = torch.zeros(len(sel), dtype=torch.float64, device="cuda")
+        Ub = torch.empty((4, T), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        t0 = time.perf_counter()
+        B.gradient(U0, steps, seg, ck, tp, fb, wk, J, Ub, use_graph=True)  # capture + launch
+        host_ms = (time.perf_counter() - t0) * 1e3
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = B.state()
+        assert st["rc"] == 0 and bool(torch.isfinite(J).all()) and bool(torch.isfinite(Ub).all())
+        Jh = J.cpu().numpy()
+        replay_ms = None
+        if replays:
+            replay_ms = _time_ms(lambda: B.gradient(U0, steps, seg, ck, tp, fb, wk, J, Ub,
+                                                    use_graph=True), replays)
+        B.close()
+        del B, ck, tp, fb, wk, Ub, U0
+        torch.cuda.empty_cache()
+        return ms, T, Jh, host_ms, replay_ms
+
+    free = torch.cuda.mem_get_info()[0]
+    cap = int(mem_frac * free / per_cell)
+    order = sorted(range(len(ws)), key=lambda b: -ws[b].nx * ws[b].ny)
+    waves, cur, cells = [], [], 0
+    for b in order:  # first fit into the current wave, largest domains first
+        c = ws[b].nx * ws[b].ny
+        if cur and cells + c > cap:
+            waves.append(cur)
+            cur, cells = [], 0
+        cur.append(b)
+        cells += c
+    waves.append(cur)
+    total_ms, total_cells, wave_info = 0.0, 0, []
+    for wv in waves:
+        ms, T, _, host_ms, _ = run_wave([ws[b] for b in wv])
+        total_ms += ms
+        total_cells += T
+        wave_info.append({"domains": len(wv), "cells": int(T), "ms": round(ms, 1),
+                          "capture_ms": round(host_ms, 1)})
+
+    rng = np.random.default_rng(2)
+    sub = [ws[b] for b in sorted(rng.choice(len(ws), size=subset, replace=False))]
+    ms_first, T_b, J_b, _, ms_b = run_wave(sub, replays=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J_s = []
+    for w, p in zip(sub, doms_of(sub)):
+        sim = lbrs.Sim(lbrs.LBRS_D2Q4, w.nx, w.ny, domain=w.domain, gamma=w.gamma, omega=w.omega,
+                       cfl=w.cfl, bc=w.sides, lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT,
+                       layout=lbrs.LBRS_LAYOUT_ROWS)
+        Wt = torch.from_numpy(w.W).cuda()
+        U0 = torch.empty_like(Wt)
+        lbrs.lbrs_prim_to_cons(p, Wt, U0)
+        sim.init(U0)
+        cells = w.nx * w.ny
+        ck = torch.empty(nck * 16 * cells, dtype=torch.float64, device="cuda")
+        tp = torch.empty(seg * 4 * cells, dtype=torch.float64, device="cuda")
+        fb = torch.empty(16 * cells, dtype=torch.float64, device="cuda")
+        wk = torch.empty_like(fb)
+        J = torch.zeros(1, dtype=torch.float64, device="cuda")
+        Ub = torch.empty_like(U0)
+        lbrs.lbrs_forward_checkpointed(sim.ctx, steps, seg, ck)
+        i0, i1 = adjoint.window_range(w.nx, 0.7, 0.8)
+        lbrs.lbrs_window_objective(sim.ctx, i0, i1, i0, i1, J, fb)
+        lbrs.lbrs_backward_checkpointed(sim.ctx, steps, seg, ck, tp, fb, wk)
+        lbrs.lbrs_adjoint_init(sim.ctx, fb, U0, Ub)
+        J_s.append(J.item())
+        sim.close()
+        del ck, tp, fb, wk
+    torch.cuda.synchronize()
+    ms_s = (time.perf_counter() - t0) * 1e3
+    rel = float(np.max(np.abs(np.asarray(J_s) - J_b) / np.abs(np.asarray(J_s))))
+    lups = total_cells * steps
+    return {"domains": len(ws), "cells": int(total_cells), "steps": steps, "segment": seg,
+            "waves": wave_info, "ms": round(total_ms, 1),
+            "forward_equiv_MLUPS": round(lups / total_ms / 1e3, 1),
+            "subset": {"domains": subset, "cells": int(T_b),
+                       "batched_first_call_ms": round(ms_first, 1),
+                       "batched_replay_ms": round(ms_b, 1),
+                       "sequential_ms": round(ms_s, 1), "speedup": round(ms_s / ms_b, 3),
+                       "speedup_incl_capture": round(ms_s / ms_first, 3),
+                       "J_max_rel_diff": rel}}
+
+
+def copy_bandwidth(src, dst, reps=20):
+    """Measured copy reference on this GPU: torch's device-to-device copy of
+    one population buffer (read + write counted), HIP events."""
+    dst.copy_(src)
+    ms = _time_ms(lambda: dst.copy_(src), reps)
+    nbytes = 2 * src.numel() * src.element_size()
+    return {"kind": "torch copy_ of one population buffer", "bytes": nbytes,
+            "ms": round(ms, 4), "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def slab_step(shape, steps=200, warmup=20):
+    """One GPU's share of an eight-way slab decomposition of the 4096^2
+    four-quadrant problem: the step on a 4096 x 512 slab through the middle of
+    the domain (own transmissive sides; no halo exchange)."""
+    import torch
+
+    from paper_1504_07034_amd import lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    n, h, y0 = 4096, 512, 1792
+    w = wl.riemann2d(n)
+    W = torch.from_numpy(w.W[:, y0:y0 + h, :].copy()).cuda()
+    sim = lbrs.Sim(w.model, n, h, domain=(0.0, 1.0, y0 / n, (y0 + h) / n), gamma=w.gamma,
+                   omega=w.omega, cfl=w.cfl, bc=w.sides, layout=lbrs.LBRS_LAYOUT_ROWS)
+    U0 = sim.prim_to_cons(W)
+    del w, W
+    sim.init(U0)
+    sim.set_tile(shape["rows"], shape["wpb"], shape["alt"])
+    sim.step(warmup, 0.3)
+    ms = _time_ms(lambda: sim.step(steps, 0.3)) / steps
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+    sim.close()
+    cells = n * h
+    gbs = BYTES_PER_LUP * cells / (ms * 1e-3) / 1e9
+    return {"nx": n, "ny": h, "ms_per_step": round(ms, 4),
+            "MLUPS": round(cells / ms / 1e3, 1), "GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,11 +425,14 @@ def main():
     ap.add_argument("--rows", type=int, default=-1,
                     help="rows per tile (0 = automatic); default: autotune")
     ap.add_argument("--wpb", type=int, default=4)
+    ap.add_argument("--alt", type=int, default=1, choices=[0, 1],
+                    help="march odd row segments upwards (with --rows >= 0)")
     ap.add_argument("--layout", type=int, default=1, help="0 planar, 1 row-interleaved")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
-    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad"],
+                    default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain copy of the populations (lbrs_get_f: "
@@ -251,7 +450,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.only:
-        fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d}[args.only]
+        fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
+              "batchgrad": batched_grad_2d}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
@@ -263,19 +463,19 @@ def main():
     U0 = sim.prim_to_cons(W)
     del W, w
 
-    shape = {"rows": args.rows, "wpb": args.wpb}
+    shape = {"rows": args.rows, "wpb": args.wpb, "alt": args.alt}
 
     def fresh():
         sim.init(U0)
         if shape["rows"] >= 0:
-            sim.set_tile(shape["rows"], shape["wpb"])
+            sim.set_tile(shape["rows"], shape["wpb"], shape["alt"])
 
     if args.rows < 0:  # autotune the launch shape (untimed), then start over
         sim.init(U0)
         sim.step(20, t_end)
         best = autotune.tune(sim, t_end, use_cache=False)
-        shape = {"rows": best["rows"], "wpb": best["wpb"]}
-        print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']}) {c['ms']:.3f} ms"
+        shape = {"rows": best["rows"], "wpb": best["wpb"], "alt": best["alt"]}
+        print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']}) {c['ms']:.3f} ms"
                                        for c in best["candidates"]), file=sys.stderr, flush=True)
 
     # The run reaches t_end after ~7.8k steps; time in segments that stay
@@ -310,6 +510,7 @@ def main():
         f_copy = sim.get_f()
         torch.cuda.synchronize()
         del f_copy
+    copy_ref = None if args.no_extras else copy_bandwidth(sim.f0, sim.f1)
 
     ms_per_step = total_ms / args.steps
     cells = n * n
@@ -332,25 +533,33 @@ def main():
                    "nx": n, "ny": n, "domain": "[0,1]^2", "gamma": 1.4, "omega": 1.0,
                    "cfl": 0.5, "sides": "transmissive", "t_end": t_end,
                    "tile_rows": shape["rows"], "waves_per_block": shape["wpb"],
+                   "alternate_march": shape["alt"],
                    "layout": "row-interleaved" if args.layout == 1 else "planar"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (TRAFFIC_BYTES if kernel_source_hash() == TRAFFIC_SOURCE_HASH
-                                 and shape["wpb"] == TRAFFIC_SHAPE["wpb"]
-                                 and args.layout == TRAFFIC_SHAPE["layout"] else None)},
+                     "traffic": traffic_bytes(shape, args.layout)},
     }
+    if copy_ref is not None:
+        copy_ref["frac_of_copy"] = round(achieved / copy_ref["GBs"], 4)
+        rec["copy_reference"] = copy_ref
     sim.close()
     del U0
     torch.cuda.empty_cache()
+    def stage(name, fn):
+        rec[name] = fn()
+        torch.cuda.empty_cache()
+        print(f"bench: {name} done", file=sys.stderr, flush=True)
+
     if not args.no_extras:
-        rec["adjoint_2d"] = adjoint_2d()
-        torch.cuda.empty_cache()
-        rec["batched_1d"] = batched_1d()
-        torch.cuda.empty_cache()
-        rec["batched_2d"] = batched_2d()
-        torch.cuda.empty_cache()
+        stage("slab_4096x512", lambda: slab_step(shape))
+        stage("adjoint_2d", adjoint_2d)
+        stage("batched_1d", batched_1d)
+        ws = wl.domain_batch(128, seed=0, steps=1000)
+        stage("batched_2d", lambda: batched_2d(ws=ws))
+        stage("batched_grad_2d", lambda: batched_grad_2d(ws=ws))
+        del ws
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline()
+        stage("cpu_baseline", cpu_baseline)
     print(json.dumps(rec), flush=True)
 
 

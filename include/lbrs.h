@@ -227,9 +227,14 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);
  * persistent grid of the resident workgroups.  rows_per_tile = 0 (the
  * default) picks as many segments as make the tiles one balanced round of the
  * resident waves; otherwise segments of about rows_per_tile rows (1..65536).
- * waves_per_block is 1, 2, 4, 6, 8, 12 or 16: the waves of a workgroup march
- * adjacent strips in lockstep.  Takes effect for later calls. */
-int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block);
+ * waves_per_block is 1, 2, 4, 6, 8, 12 or 16 (default 4): the waves of a
+ * workgroup march adjacent strips in lockstep.  alternate = 1 (the default)
+ * marches odd row segments upwards, through a y-mirrored view of the
+ * populations under which the update is exactly invariant, so that
+ * neighbouring segments read their shared rows at the same time; 0 marches
+ * every segment downwards.  The results are the same bits either way.  Takes
+ * effect for later calls; LBRS_E_INVAL for values outside these sets. */
+int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alternate);
 
 /* ------------------------------------------------------------------------
  * Ragged batch of independent 1D units (shock tubes) in one persistent launch.
@@ -335,8 +340,9 @@ int lbrs_batch2d_set_f(lbrs_batch2d* b, const double* d_f, long long n);
  * `segment` sets of [4][total], then reverse adjoint steps; d_fbar, d_work:
  * pools), adjoint of the initialisation into d_Ubar0 [4][total].  With
  * use_graph != 0 the whole sequence is captured in a hipGraph on the first
- * call and replayed after (later calls must pass the same arguments).  No
- * host synchronisation. */
+ * call and replayed by later calls with the same arguments (a call with other
+ * pointers, nsteps or segment captures a new graph).  No host
+ * synchronisation. */
 int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int segment,
                           double* d_ckpt, double* d_tape, double* d_fbar, double* d_work,
                           double* d_J, double* d_Ubar0, int use_graph);

@@ -47,6 +47,7 @@ class GradientSpec:
     layout: int = lbrs.LBRS_LAYOUT_ROWS
     segment: int | None = None  # checkpoint spacing; default ceil(sqrt(T))
     lam: float | None = None    # frozen lattice speed; set by prepare()
+    tile: tuple | None = None   # (rows_per_tile, waves_per_block, alternate) of the step kernel
 
     def params(self, mode, lam_user=0.0):
         return lbrs.make_params(lbrs.LBRS_D2Q4, self.n, self.n, (0.0, 1.0, 0.0, 1.0), self.gamma,
@@ -77,6 +78,8 @@ class GradientRunner:
         self.sim = lbrs.Sim(lbrs.LBRS_D2Q4, n, n, gamma=spec.gamma, omega=spec.omega, cfl=spec.cfl,
                             bc=(1, 1, 1, 1), lambda_mode=lbrs.LBRS_LAMBDA_USER,
                             lambda_user=spec.lam, layout=spec.layout, device=dev)
+        if spec.tile is not None:
+            self.sim.set_tile(*spec.tile)
         nck = math.ceil(spec.steps / spec.seg)
         fcount = 16 * n * n
         self.ckpt = torch.empty(nck * fcount, dtype=torch.float64, device=dev)
@@ -108,6 +111,16 @@ class GradientRunner:
         rbar = torch.empty_like(rho0)
         lbrs.lbrs_isentropic_to_cons_adjoint(sim.p, rho0.contiguous(), Ubar0, rbar)
         return rbar
+
+    def tune(self, rho0: torch.Tensor, steps: int = 10) -> dict:
+        """Autotune the step kernel's launch shape on this runner's problem
+        (from the initial state of rho0; the caller's results are unaffected)."""
+        from . import autotune
+        lbrs.lbrs_isentropic_to_cons(self.sim.p, rho0.contiguous(), self.U0)
+        self.sim.init(self.U0)
+        best = autotune.tune(self.sim, steps=steps, use_cache=False)
+        self.spec.tile = (best["rows"], best["wpb"], best["alt"])
+        return best
 
     def close(self):
         self.sim.close()

@@ -1,7 +1,9 @@
 """Autotuner for the launch shape of the 2D step kernel.
 
-Candidates are (rows_per_tile, waves_per_block) pairs; rows_per_tile = 0 is
-the library's automatic choice (one balanced round of the resident waves).
+Candidates are (rows_per_tile, waves_per_block, alternate) triples;
+rows_per_tile = 0 is the library's automatic choice (one balanced round of the
+resident waves), alternate = 1 marches odd row segments upwards (same results,
+different memory order).
 Each candidate is timed with HIP events over a few steps that start from the
 same checkpoint of the populations (lbrs_get_f / lbrs_set_f), so tuning does
 not advance the caller's solution.  The best shape is applied to the context
@@ -21,12 +23,13 @@ CACHE = os.environ.get("LBRS_TUNE_CACHE",
 
 DEFAULT_ROWS = (0, 32, 64, 96, 128)
 DEFAULT_WPB = (4, 6, 8, 12, 16)
+DEFAULT_ALT = (0, 1)
 
 
 def _key(sim: "lbrs.Sim") -> str:
     p = sim.p
     name = torch.cuda.get_device_name(sim.device)
-    return f"{name}|m{p.model}|{p.nx}x{p.ny}|bc{tuple(p.bc)}"
+    return f"{name}|m{p.model}|{p.nx}x{p.ny}|bc{tuple(p.bc)}|v2"
 
 
 def _load_cache() -> dict:
@@ -47,9 +50,9 @@ def _save_cache(c: dict) -> None:
 
 
 def time_shape(sim: "lbrs.Sim", rows: int, wpb: int, steps: int, f0: torch.Tensor,
-               t0: float, n0: int, t_end: float) -> float:
+               t0: float, n0: int, t_end: float, alternate: int = 1) -> float:
     """Milliseconds per step of one launch shape, from the checkpoint (f0, t0, n0)."""
-    sim.set_tile(rows, wpb)
+    sim.set_tile(rows, wpb, alternate)
     sim.set_f(f0, t0, n0)
     sim.step(2, t_end)  # warm the shape
     sim.set_f(f0, t0, n0)
@@ -65,26 +68,28 @@ def time_shape(sim: "lbrs.Sim", rows: int, wpb: int, steps: int, f0: torch.Tenso
 
 
 def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=DEFAULT_ROWS,
-         wpbs=DEFAULT_WPB, use_cache: bool = True, verbose: bool = False) -> dict:
+         wpbs=DEFAULT_WPB, alts=DEFAULT_ALT, use_cache: bool = True,
+         verbose: bool = False) -> dict:
     """Pick and apply the fastest 2D launch shape for `sim` (already initialised)."""
     key = _key(sim)
     cache = _load_cache() if use_cache else {}
     if use_cache and key in cache:
         best = cache[key]
-        sim.set_tile(best["rows"], best["wpb"])
+        sim.set_tile(best["rows"], best["wpb"], best.get("alt", 1))
         return best
     st = sim.state()
     f0 = sim.get_f()
     results = []
-    for w in wpbs:
-        for r in rows:
-            ms = time_shape(sim, r, w, steps, f0, st["t"], st["nsteps"], t_end)
-            results.append({"rows": r, "wpb": w, "ms": ms})
-            if verbose:
-                print(f"autotune rows={r} wpb={w}: {ms:.4f} ms/step", flush=True)
+    for a in alts:
+        for w in wpbs:
+            for r in rows:
+                ms = time_shape(sim, r, w, steps, f0, st["t"], st["nsteps"], t_end, a)
+                results.append({"rows": r, "wpb": w, "alt": a, "ms": ms})
+                if verbose:
+                    print(f"autotune rows={r} wpb={w} alt={a}: {ms:.4f} ms/step", flush=True)
     best = min(results, key=lambda d: d["ms"])
     sim.set_f(f0, st["t"], st["nsteps"])
-    sim.set_tile(best["rows"], best["wpb"])
+    sim.set_tile(best["rows"], best["wpb"], best["alt"])
     best = dict(best, candidates=results)
     if use_cache:
         cache[key] = best

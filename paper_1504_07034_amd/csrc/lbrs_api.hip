@@ -24,9 +24,10 @@ struct lbrs_ctx {
     long long launches;  // step launches since the last (re)initialisation
     int rows_per_tile;   // 0: automatic (one balanced round of resident waves)
     int waves_per_block;
+    int alternate;       // 2D: odd row segments march upwards (mirrored view)
     int persistent_max;  // largest 1D domain run by the persistent kernel
     int cu_count;
-    int bpc[17];         // resident step-kernel workgroups per CU, by waves per block
+    int bpc[2][17];      // resident step-kernel workgroups per CU, by (alternate, waves per block)
 };
 
 static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
@@ -176,6 +177,7 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     c->launches = 0;
     c->rows_per_tile = 0;
     c->waves_per_block = 4;
+    c->alternate = 1;
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -196,12 +198,14 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     return LBRS_OK;
 }
 
-int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block) {
+int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alternate) {
     if (!c) return LBRS_E_INVAL;
     if (rows_per_tile != 0 && (rows_per_tile < 1 || rows_per_tile > 65536)) return LBRS_E_INVAL;
     if (!step2d_wpb_supported(waves_per_block)) return LBRS_E_INVAL;
+    if (alternate != 0 && alternate != 1) return LBRS_E_INVAL;
     c->rows_per_tile = rows_per_tile;
     c->waves_per_block = waves_per_block;
+    c->alternate = alternate;
     return LBRS_OK;
 }
 
@@ -216,8 +220,9 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream) {
 static int blocks_per_cu(const lbrs_ctx* c) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
     int w = c->waves_per_block;
-    if (m->bpc[w] == 0) m->bpc[w] = step2d_blocks_per_cu(w);
-    return m->bpc[w];
+    int& n = m->bpc[c->alternate][w];
+    if (n == 0) n = step2d_blocks_per_cu(w, c->alternate != 0);
+    return n;
 }
 
 static int step2d_segments(const lbrs_ctx* c, int nstrips) {
@@ -294,7 +299,8 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
     if (c->dim == 2) {
         for (int s = 0; s < max_steps; ++s) {
             Step2DArgs a = step2d_args(c, t_end, nullptr);
-            hipError_t e = launch_step2d(a, c->waves_per_block, false, step2d_max_blocks(c), c->stream);
+            hipError_t e = launch_step2d(a, c->waves_per_block, false, c->alternate != 0,
+                                         step2d_max_blocks(c), c->stream);
             if (e != hipSuccess) return LBRS_E_HIP;
             ++c->launches;
         }
@@ -321,7 +327,8 @@ int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n) {
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP) return LBRS_E_STATE;
     if (c->dim != 2) return LBRS_E_STATE;
     Step2DArgs a = step2d_args(c, INFINITY, d_Utape_n);
-    hipError_t e = launch_step2d(a, c->waves_per_block, true, step2d_max_blocks(c), c->stream);
+    hipError_t e = launch_step2d(a, c->waves_per_block, true, c->alternate != 0, step2d_max_blocks(c),
+                                 c->stream);
     if (e != hipSuccess) return LBRS_E_HIP;
     ++c->launches;
     return LBRS_OK;

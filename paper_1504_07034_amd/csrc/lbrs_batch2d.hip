@@ -211,6 +211,8 @@ struct lbrs_batch2d {
     int wpb, max_blocks;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    const void* graph_args[7];  // arguments the captured gradient graph was built with
+    long long graph_steps[2];
 };
 
 namespace {
@@ -280,7 +282,7 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
     }
     b->ndom = ndom;
     b->wpb = 8;
-    b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb);
+    b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb, true);
     b->doms.resize(ndom);
     long long off = 0, rows = 0, tiles = 0;
     b->max_nx = 0;
@@ -328,6 +330,8 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
     b->stream = (hipStream_t)hip_stream;
     b->graph = nullptr;
     b->exec = nullptr;
+    for (auto& a : b->graph_args) a = nullptr;
+    b->graph_steps[0] = b->graph_steps[1] = 0;
     bool good = ok(hipMemcpyAsync(b->d_doms, b->doms.data(), sizeof(Domain2D) * ndom,
                                   hipMemcpyHostToDevice, b->stream)) &&
                 ok(hipStreamSynchronize(b->stream));
@@ -518,6 +522,15 @@ int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int s
         return LBRS_E_INVAL;
     if (!use_graph)
         return b2_gradient_enqueue(b, d_U0, nsteps, segment, d_ckpt, d_tape, d_fbar, d_work, d_J, d_Ubar0);
+    const void* args[7] = {d_U0, d_ckpt, d_tape, d_fbar, d_work, d_J, d_Ubar0};
+    bool same = b->exec && b->graph_steps[0] == nsteps && b->graph_steps[1] == segment;
+    for (int i = 0; same && i < 7; ++i) same = b->graph_args[i] == args[i];
+    if (b->exec && !same) {  // other arguments: capture a new graph
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
     if (!b->exec) {
         hipStream_t cap;
         if (!ok(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking))) return LBRS_E_HIP;
@@ -536,6 +549,9 @@ int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int s
             return rc ? rc : LBRS_E_HIP;
         }
         b->graph = g;
+        for (int i = 0; i < 7; ++i) b->graph_args[i] = args[i];
+        b->graph_steps[0] = nsteps;
+        b->graph_steps[1] = segment;
     }
     if (!ok(hipGraphLaunch(b->exec, b->stream))) return LBRS_E_HIP;
     return LBRS_OK;

@@ -141,8 +141,9 @@ struct Batch2DArgs {
 
 hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
                                hipStream_t s);
-hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, int max_blocks, hipStream_t s);
-int step2d_blocks_per_cu(int wpb);
+hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, int max_blocks,
+                         hipStream_t s);
+int step2d_blocks_per_cu(int wpb, bool alt);
 bool step2d_wpb_supported(int wpb);
 hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
 hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);

@@ -13,15 +13,16 @@
 // contiguous 128*nx-byte block (a wave's row touches 2 pages, not 32).
 //
 // Work decomposition.  A wavefront owns a strip of S <= 62 output columns and
-// marches down a segment of rows.  Lane l holds column x0 - 1 + l, so lanes 0
-// and S + 1 are the strip's halo columns, recomputed by both neighbouring
-// strips.
+// marches through a segment of rows (down in even segments, up in odd ones).
+// Lane l holds column x0 - 1 + l, so lanes 0 and S + 1 are the strip's halo
+// columns, recomputed by both neighbouring strips.
 // Each row is read once from HBM: the lane computes U, the flux and the 16
 // post-collision values of its column, and the diagonal hops become DPP
 // wavefront shifts by one lane (x) plus a two-row register pipeline (y):
 //   f1^{n+1}(x, r-1) = f1*(x+1, r)   f2^{n+1}(x, r-1) = f2*(x-1, r)
 //   f3^{n+1}(x, r+1) = f3*(x-1, r)   f4^{n+1}(x, r+1) = f4*(x+1, r)
-// The output row r-1 is complete after row r is processed, so the new moments
+// Marching down, output row r-1 is complete after row r is processed
+// (marching up, row r+1), so the new moments
 // U^{n+1} and the local bound are formed in registers and reduced (wave max,
 // one atomic per wave at most) into the next step's lambda*.
 //
@@ -104,26 +105,51 @@ struct TileGeom {
     int bc[4];
 };
 
-// One tile: a strip of g.strip output columns (lanes 1..strip; lanes 0 and
-// strip+1 are its halo columns) over row segment `seg` of the domain,
-// marched row by row.  Accumulates the lane's bound of the new state and its
-// admissibility.
+// How a tile's march sees memory.  Odd row segments are marched through the
+// domain mirrored in y: march row j is memory row ny-1-j, population i is
+// memory population 3-i (the one with the opposite s_y), and the y-momentum
+// changes sign.  The LBRS update commutes with this mirror exactly (every
+// operation maps to the same operation on negated operands), so both
+// directions produce the same bits, while two neighbouring segments now reach
+// the rows they both read at the same time (both at the start or both at the
+// end of the launch) and the second read is served by the cache.
+struct MarchView {
+    long long rbase, rstep;  // element offset of march row j: rbase + j * rstep
+    long long ibase, istep;  // offset of plane (i, k): ibase + i * istep + k * ps
+    long long tbase, tstep;  // offset of march row j in a moment plane: tbase + j * tstep
+    double s2;               // sign of the y-momentum component
+    int bc_lo, bc_hi;        // side conditions at march rows 0 and ny-1
+};
+
+// The 16 populations of march row j at column xl (a wave-uniform row base
+// plus the lane's column, so that the loads take a scalar base address).
+__device__ inline void load_view(double v[16], const double* __restrict__ fin, const MarchView& m,
+                                 long long ps, int j, unsigned xl) {
+    const double* __restrict__ row = fin + (m.rbase + (long long)j * m.rstep);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double x = (row + (m.ibase + i * m.istep + k * ps))[xl];
+            v[i * 4 + k] = k == 2 ? m.s2 * x : x;
+        }
+}
+
+// Rows y0..y1-1 (march coordinates) of one strip: lanes 1..g.strip are output
+// columns, lanes 0 and g.strip+1 its halo columns.  Accumulates the lane's
+// bound of the new state and its admissibility.
 template <bool TAPE, int WPB>
-__device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane, double& lmax,
-                                          bool& bad) {
+__device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m, int strip, int y0,
+                                           int y1, int lane, double& lmax, bool& bad) {
     const int nx = g.nx, ny = g.ny;
     const bool px = g.bc[0] == BC_PERIODIC, py = g.bc[2] == BC_PERIODIC;
     const double* __restrict__ fin = g.fin;
     double* __restrict__ fout = g.fout;
-    const long long ps = g.ps, rs = g.rs;
+    const long long ps = g.ps;
     const double gm1 = g.gamma - 1.0;
     const double c4lam = g.c4lam, omega = g.omega;
     const int row_bytes = nx * 8;
-    const int strip = tile % g.nstrips;
-    const int seg = tile / g.nstrips;
     const int x = strip * g.strip - 1 + lane;
-    const int y0 = (int)(((long long)seg * ny) / g.nseg);
-    const int y1 = (int)(((long long)(seg + 1) * ny) / g.nseg);
     const int xl = map_index(x, nx, px);
     const bool out_lane = lane >= 1 && lane <= g.strip && x < nx;
     const int voff = out_lane ? x * 8 : 0x7fffffff;
@@ -133,8 +159,8 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
     // prologue: rows y0-1 and y0 fill the two-row pipeline (no output)
     double f[16], nxt[16], U[4];
     Shifted sh;
-    load_row(f, fin, ps, (long long)map_index(y0 - 1, ny, py) * rs + xl);
-    load_row(nxt, fin, ps, (long long)map_index(y0, ny, py) * rs + xl);
+    load_view(f, fin, m, ps, map_index(y0 - 1, ny, py), xl);
+    load_view(nxt, fin, m, ps, map_index(y0, ny, py), xl);
     collide_and_shift(f, gm1, c4lam, omega, U, sh);
     double A3[4], A4[4], B3[4], B4[4];
 #pragma unroll
@@ -144,12 +170,13 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
     }
 #pragma unroll
     for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-    load_row(nxt, fin, ps, (long long)map_index(y0 + 1, ny, py) * rs + xl);
+    load_view(nxt, fin, m, ps, map_index(y0 + 1, ny, py), xl);
     collide_and_shift(f, gm1, c4lam, omega, U, sh);
     if (TAPE) {
-        double* trow = g.tape + (long long)y0 * nx;
+        double* trow = g.tape + m.tbase + y0 * m.tstep;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) store_row(trow + k * g.tape_ps, row_bytes, voff, U[k]);
+        for (int k = 0; k < 4; ++k)
+            store_row(trow + k * g.tape_ps, row_bytes, voff, k == 2 ? m.s2 * U[k] : U[k]);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -166,14 +193,15 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
         if (WPB > 1) __builtin_amdgcn_s_barrier();
 #pragma unroll
         for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-        load_row(nxt, fin, ps, (long long)map_index(r + 1, ny, py) * rs + xl);
+        load_view(nxt, fin, m, ps, map_index(r + 1, ny, py), xl);
         collide_and_shift(f, gm1, c4lam, omega, U, sh);
         if (TAPE) {
             // U^n of row r; row y1 is the next segment's first row
-            double* trow = g.tape + (long long)map_index(r, ny, false) * nx;
+            double* trow = g.tape + m.tbase + map_index(r, ny, false) * m.tstep;
             const int tv = r < y1 ? voff : 0x7fffffff;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) store_row(trow + k * g.tape_ps, row_bytes, tv, U[k]);
+            for (int k = 0; k < 4; ++k)
+                store_row(trow + k * g.tape_ps, row_bytes, tv, k == 2 ? m.s2 * U[k] : U[k]);
         }
         const int o = r - 1;
         double go[16];
@@ -186,8 +214,8 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
         }
         // specular reflection at wall node rows/columns: the incoming
         // populations mirror the outgoing ones, normal momentum negated
-        const bool wall_top = g.bc[3] == BC_WALL && o == ny - 1;
-        const bool wall_bot = g.bc[2] == BC_WALL && o == 0;
+        const bool wall_top = m.bc_hi == BC_WALL && o == ny - 1;
+        const bool wall_bot = m.bc_lo == BC_WALL && o == 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double sy = (k == 2) ? -1.0 : 1.0, sx = (k == 1) ? -1.0 : 1.0;
@@ -208,9 +236,13 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
                 go[3 * 4 + k] = sx * go[2 * 4 + k];
             }
         }
-        double* orow = fout + (long long)o * rs;
+        double* orow = fout + m.rbase + (long long)o * m.rstep;
 #pragma unroll
-        for (int p = 0; p < 16; ++p) store_row(orow + p * ps, row_bytes, voff, go[p]);
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                store_row(orow + m.ibase + i * m.istep + k * ps, row_bytes, voff,
+                          k == 2 ? m.s2 * go[i * 4 + k] : go[i * 4 + k]);
         double Un[4], l;
         moments_d2q4(go, Un);
         const bool ok = bound_d2q4(Un, g.gamma, &l);
@@ -226,7 +258,47 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
     }
 }
 
-template <bool TAPE, int WPB>
+// One tile: strip `tile % nstrips` over row segment `tile / nstrips`.  With
+// ALT, odd segments are marched through the mirrored view, so that they run
+// upwards in memory while even ones run downwards; without it every segment
+// runs downwards (the view is then a compile-time identity).
+template <bool TAPE, int WPB, bool ALT>
+__device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane, double& lmax,
+                                          bool& bad) {
+    const int strip = tile % g.nstrips;
+    const int seg = tile / g.nstrips;
+    const int ny = g.ny;
+    int y0 = (int)(((long long)seg * ny) / g.nseg);
+    int y1 = (int)(((long long)(seg + 1) * ny) / g.nseg);
+    MarchView m;
+    if (ALT && (seg & 1)) {
+        const int t = y0;
+        y0 = ny - y1;
+        y1 = ny - t;
+        m.rbase = (long long)(ny - 1) * g.rs;
+        m.rstep = -g.rs;
+        m.ibase = 12 * g.ps;
+        m.istep = -4 * g.ps;
+        m.tbase = (long long)(ny - 1) * g.nx;
+        m.tstep = -(long long)g.nx;
+        m.s2 = -1.0;
+        m.bc_lo = g.bc[3];
+        m.bc_hi = g.bc[2];
+    } else {
+        m.rbase = 0;
+        m.rstep = g.rs;
+        m.ibase = 0;
+        m.istep = 4 * g.ps;
+        m.tbase = 0;
+        m.tstep = g.nx;
+        m.s2 = 1.0;
+        m.bc_lo = g.bc[2];
+        m.bc_hi = g.bc[3];
+    }
+    march_tile<TAPE, WPB>(g, m, strip, y0, y1, lane, lmax, bad);
+}
+
+template <bool TAPE, int WPB, bool ALT>
 __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
     const LaunchSlots ls = slots_for(a.launch);
     DevState* st = a.st;
@@ -260,7 +332,7 @@ __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
     bool bad = false;
     for (int tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wave; tile < a.ntiles;
          tile += total_waves)
-        step_tile<TAPE, WPB>(g, tile, lane, lmax, bad);
+        step_tile<TAPE, WPB, ALT>(g, tile, lane, lmax, bad);
 
     if (a.lam_mode == LAM_PER_STEP) {
         double wm = wave_max(lmax);
@@ -307,24 +379,31 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch(Batch2DArgs a) {
         for (int s = 0; s < 4; ++s) g.bc[s] = d.bc[s];
         double lmax = 0.0;
         bool bad = false;
-        step_tile<TAPE, WPB>(g, (int)(tile - d.tile0), lane, lmax, bad);
+        step_tile<TAPE, WPB, true>(g, (int)(tile - d.tile0), lane, lmax, bad);
         if (__any(bad) && lane == 0) atomicOr(&a.status[lo], 1u);
     }
 }
 
-template <bool TAPE, int WPB>
+template <bool TAPE, int WPB, bool ALT>
 static hipError_t launch_one(const Step2DArgs& a, int max_blocks, hipStream_t s) {
     int nblocks = (a.ntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    hipLaunchKernelGGL((step2d_d2q4<TAPE, WPB>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    hipLaunchKernelGGL((step2d_d2q4<TAPE, WPB, ALT>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
     return hipGetLastError();
 }
 
 #define LBRS_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12) X(16)
 
-hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, int max_blocks, hipStream_t s) {
-#define LBRS_CASE(W)                                                                       \
-    if (wpb == W) return tape ? launch_one<true, W>(a, max_blocks, s) : launch_one<false, W>(a, max_blocks, s);
+hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, int max_blocks,
+                         hipStream_t s) {
+#define LBRS_CASE(W)                                                           \
+    if (wpb == W) {                                                            \
+        if (alt)                                                               \
+            return tape ? launch_one<true, W, true>(a, max_blocks, s)          \
+                        : launch_one<false, W, true>(a, max_blocks, s);        \
+        return tape ? launch_one<true, W, false>(a, max_blocks, s)             \
+                    : launch_one<false, W, false>(a, max_blocks, s);           \
+    }
     LBRS_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return hipErrorInvalidValue;
@@ -356,11 +435,15 @@ bool step2d_wpb_supported(int wpb) {
 }
 
 // Resident workgroups of the step kernel per CU for a workgroup size.
-int step2d_blocks_per_cu(int wpb) {
+int step2d_blocks_per_cu(int wpb, bool alt) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
-#define LBRS_CASE(W) \
-    if (wpb == W) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W>, 64 * W, 0);
+#define LBRS_CASE(W)                                                                         \
+    if (wpb == W)                                                                            \
+        e = alt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, true>, \
+                                                               64 * W, 0)                    \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, false>, \
+                                                               64 * W, 0);
     LBRS_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return e == hipSuccess && n > 0 ? n : 1;

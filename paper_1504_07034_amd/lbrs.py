@@ -93,7 +93,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_forward_checkpointed": (i, [vp, i, i, vp]),
         "lbrs_backward_checkpointed": (i, [vp, i, i, vp, vp, vp, vp]),
         "lbrs_set_stream": (i, [vp, vp]),
-        "lbrs_set_tile": (i, [vp, i, i]),
+        "lbrs_set_tile": (i, [vp, i, i, i]),
         "lbrs_batch_query": (i, [i, P, i, ctypes.POINTER(ll), szp]),
         "lbrs_batch_init": (i, [ctypes.POINTER(vp), i, P, dp, i, vp, vp, vp, vp]),
         "lbrs_batch_run": (i, [vp, i]),
@@ -265,9 +265,9 @@ def lbrs_set_stream(ctx, stream=None):
     _check(load_library().lbrs_set_stream(ctx, _stream(stream)), "lbrs_set_stream")
 
 
-def lbrs_set_tile(ctx, rows_per_tile: int, waves_per_block: int = 4):
-    _check(load_library().lbrs_set_tile(ctx, int(rows_per_tile), int(waves_per_block)),
-           "lbrs_set_tile")
+def lbrs_set_tile(ctx, rows_per_tile: int, waves_per_block: int = 4, alternate: int = 1):
+    _check(load_library().lbrs_set_tile(ctx, int(rows_per_tile), int(waves_per_block),
+                                        int(alternate)), "lbrs_set_tile")
 
 
 def lbrs_destroy(ctx):
@@ -336,8 +336,8 @@ class Sim:
             W = torch.from_numpy(W)
         return self.init(self.prim_to_cons(W))
 
-    def set_tile(self, rows_per_tile: int, waves_per_block: int = 4):
-        lbrs_set_tile(self.ctx, rows_per_tile, waves_per_block)
+    def set_tile(self, rows_per_tile: int, waves_per_block: int = 4, alternate: int = 1):
+        lbrs_set_tile(self.ctx, rows_per_tile, waves_per_block, alternate)
 
     def step(self, max_steps: int, t_end: float = math.inf):
         lbrs_step(self.ctx, max_steps, t_end)

@@ -164,6 +164,16 @@ def test_batch2d_gradient_graph_vs_oracle_and_replays():
         assert torch.equal(J, J_e) and torch.equal(Ub, Ub_e), rep
         B.step(3)  # eager work between replays
         torch.cuda.synchronize()
+    # other arguments recapture the graph instead of replaying the old one
+    steps2, seg2 = 17, 4
+    B.gradient(U0, steps2, seg2, ck, tp, fb, wk, J, Ub, use_graph=False)
+    J_e2, Ub_e2 = J.clone(), Ub.clone()
+    J.zero_()
+    Ub.zero_()
+    B.gradient(U0, steps2, seg2, ck, tp, fb, wk, J, Ub, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(J, J_e2) and torch.equal(Ub, Ub_e2)
+    assert not torch.equal(J_e2, J_e)
     rng = np.random.default_rng(8)
     for d, w in enumerate(ws):
         dU = rng.standard_normal((4, w.ny, w.nx)) * np.array([1.0, 0.1, 0.1, 1.0])[:, None, None]

@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import oracle
+from paper_1504_07034_amd import lbrs
 from paper_1504_07034_amd import workloads as wl
 
 from helpers import TOL, gpu_sim, max_abs, oracle_problem, report
@@ -120,7 +121,7 @@ def test_2d_explosion(omega):
 
 
 @pytest.mark.parametrize("tile", [(64, 4), (7, 1), (50, 2), (200, 4), (0, 6), (0, 8), (33, 12),
-                                  (0, 16)])
+                                  (0, 16), (64, 4, 0), (7, 2, 0), (0, 16, 0)])
 def test_2d_tile_shapes(tile):
     """Ragged row segments and every workgroup shape (lockstep groups of 1 to 16
     waves, strip widths below 62) give the same answer."""
@@ -180,6 +181,30 @@ def test_rows_layout_matches_planar_bitwise(sides):
     assert torch.equal(outs[0][0], outs[1][0])
     assert torch.equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("sides", [(0, 0, 0, 0), (1, 1, 2, 2), (2, 0, 1, 1), (0, 0, 2, 0),
+                                   (1, 1, 1, 1)])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_alternate_march_bitwise(sides, layout):
+    """Odd row segments marched upwards through the y-mirrored view give the
+    same bits as marching every segment downwards: populations, moments,
+    state, and the moment tape of a fixed-speed step."""
+    w = wl.explosion(150)
+    outs = []
+    for alt in (0, 1):
+        sim = gpu_sim(w, sides=sides, omega=1.3, layout=layout, lam_mode=1)
+        sim.init_primitive(w.W)
+        sim.set_tile(7, 4, alt)  # 22 segments, half of them mirrored
+        sim.step(60)
+        tape = torch.empty((4, w.ny, w.nx), dtype=torch.float64, device="cuda")
+        lbrs.lbrs_step_tape(sim.ctx, tape)
+        outs.append((sim.moments(), sim.to_planar(sim.get_f()), sim.state(), tape))
+        sim.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+    assert torch.equal(outs[0][3], outs[1][3])
 
 
 def test_rows_layout_parity():
