@@ -377,6 +377,39 @@ def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None):
                        "J_max_rel_diff": rel}}
 
 
+def dirichlet_2d(nx=12288, ny=4096, steps=200, warmup=20):
+    """The oblique-shock reflection (prescribed inflow and post-shock sides,
+    free-slip wall; omega = 1.8) at nx x ny: the step kernel with Dirichlet
+    ghosts, autotuned launch shape, HIP events."""
+    import torch
+
+    from paper_1504_07034_amd import autotune, lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    w = wl.oblique_shock(nx, ny, omega=1.8)
+    sim = lbrs.Sim(w.model, nx, ny, domain=w.domain, gamma=w.gamma, omega=w.omega, cfl=w.cfl,
+                   bc=w.sides, layout=lbrs.LBRS_LAYOUT_ROWS, dirichlet_W=w.dirichlet_W)
+    U0 = sim.prim_to_cons(torch.from_numpy(w.W))
+    del w
+    sim.init(U0)
+    sim.step(5)
+    best = autotune.tune(sim, use_cache=False)
+    sim.init(U0)
+    sim.set_tile(best["rows"], best["wpb"], best["alt"])
+    sim.step(warmup)
+    ms = _time_ms(lambda: sim.step(steps)) / steps
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+    sim.close()
+    cells = nx * ny
+    gbs = BYTES_PER_LUP * cells / (ms * 1e-3) / 1e9
+    return {"workload": "oblique shock reflection, Dirichlet inflow/top, wall below",
+            "nx": nx, "ny": ny, "omega": 1.8, "tile_rows": best["rows"],
+            "waves_per_block": best["wpb"], "alternate": best["alt"],
+            "ms_per_step": round(ms, 4), "MLUPS": round(cells / ms / 1e3, 1),
+            "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def copy_bandwidth(src, dst, reps=20):
     """Measured copy reference on this GPU: torch's device-to-device copy of
     one population buffer (read + write counted), HIP events."""
@@ -431,7 +464,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
-    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad"],
+    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad", "dirichlet"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -451,7 +484,7 @@ def main():
     torch.cuda.set_device(0)
     if args.only:
         fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
-              "batchgrad": batched_grad_2d}[args.only]
+              "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
@@ -552,6 +585,7 @@ def main():
 
     if not args.no_extras:
         stage("slab_4096x512", lambda: slab_step(shape))
+        stage("dirichlet_2d", dirichlet_2d)
         stage("adjoint_2d", adjoint_2d)
         stage("batched_1d", batched_1d)
         ws = wl.domain_batch(128, seed=0, steps=1000)

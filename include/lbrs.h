@@ -69,9 +69,17 @@ enum { LBRS_D1Q2 = 0, LBRS_D1Q3 = 1, LBRS_D2Q4 = 2 };
  * the wall on the first/last node row or column; walls on two perpendicular
  * sides (a corner) are rejected.  TRANSMISSIVE (zero gradient of the
  * post-collision populations) and PERIODIC are not in the paper.  PERIODIC
- * must be set on both sides of an axis.  1D models accept TRANSMISSIVE and
- * PERIODIC on x only. */
-enum { LBRS_BC_TRANSMISSIVE = 0, LBRS_BC_PERIODIC = 1, LBRS_BC_WALL = 2 };
+ * must be set on both sides of an axis.  DIRICHLET prescribes the state
+ * beyond a side (the inflow and post-shock top boundaries of the paper's
+ * oblique-shock reflection case, Sec. III, whose treatment the paper does not
+ * spell out): the ghost cells across it hold the given conserved states in
+ * equilibrium at the step's lattice speed, so every population pulled from
+ * across the side is f^eq_i(U_b); at a corner ghost cell the y-side's state
+ * applies; the prescribed states enter the global lambda* like interior
+ * cells.  DIRICHLET is available for D2Q4 single domains (lbrs_init) and
+ * needs lbrs_params.dirichlet for that side.  1D models accept TRANSMISSIVE
+ * and PERIODIC on x only. */
+enum { LBRS_BC_TRANSMISSIVE = 0, LBRS_BC_PERIODIC = 1, LBRS_BC_WALL = 2, LBRS_BC_DIRICHLET = 3 };
 
 /* Lattice speed.  PER_STEP: every step takes the global bound
  * lambda* = max over cells of the local bound (Sec. II.C Jin-Xin choice in 1D,
@@ -97,6 +105,13 @@ typedef struct {
     int lambda_mode;      /* LBRS_LAMBDA_* */
     double lambda_user;   /* lattice speed for LBRS_LAMBDA_USER, > 0 */
     int layout;           /* LBRS_LAYOUT_PLANAR (0) or LBRS_LAYOUT_ROWS (1) */
+    /* Per side, the prescribed conserved states of a DIRICHLET side: device
+     * pointer to [K][n] doubles along the side, n = ny for the x-sides (index
+     * = row y) and n = nx for the y-sides (index = column x); NULL for other
+     * sides.  Borrowed: the caller keeps the data alive and unchanged while
+     * the context exists.  A non-admissible prescribed state is reported
+     * like a non-admissible U0 (LBRS_E_NONPHYSICAL at step 0). */
+    const double* dirichlet[4];
 } lbrs_params;
 
 /* Sizes in bytes of one population buffer (f0 or f1), of one conserved-state
@@ -162,8 +177,8 @@ int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, doubl
 
 /* Forward step that also stores the step's input moments U^n into
  * d_Utape_n [K][ny][nx] (the tape the adjoint step reads).  FROZEN_INIT or
- * USER mode only (else LBRS_E_STATE); otherwise identical to lbrs_step(c, 1,
- * +inf). */
+ * USER mode and no DIRICHLET side only (else LBRS_E_STATE); otherwise
+ * identical to lbrs_step(c, 1, +inf). */
 int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n);
 
 /* Adjoint (vector-Jacobian product) of one fixed-speed step, D2Q4 with

@@ -29,7 +29,7 @@ LIB = os.path.join(HERE, "liblbrs_oracle.so")
 
 D1Q2, D1Q3, D2Q4 = 0, 1, 2
 FLUX_EULER, FLUX_LINEAR = 0, 1
-TRANSMISSIVE, PERIODIC, WALL = 0, 1, 2
+TRANSMISSIVE, PERIODIC, WALL, DIRICHLET = 0, 1, 2, 3
 LAM_PER_STEP, LAM_FROZEN, LAM_USER = 0, 1, 2
 OK, INVAL, NONPHYSICAL = 0, -1, -4
 
@@ -57,6 +57,7 @@ class _Problem(ctypes.Structure):
         ("side", ctypes.c_int * 4),
         ("lam_mode", ctypes.c_int), ("lam_user", ctypes.c_double),
         ("adv_x", ctypes.c_double), ("adv_y", ctypes.c_double),
+        ("dir", ctypes.POINTER(ctypes.c_double) * 4),
     ]
 
 
@@ -109,6 +110,9 @@ class Problem:
     lam_user: float = 0.0
     flux: int = FLUX_EULER
     adv: tuple = (0.0, 0.0)
+    # Dirichlet data per side (xlo, xhi, ylo, yhi): conserved states [K][n],
+    # n = ny for the x-sides, nx for the y-sides; None for other sides.
+    dirichlet: tuple = (None, None, None, None)
 
     @property
     def Q(self) -> int:
@@ -133,6 +137,16 @@ class Problem:
             p.side[i] = self.sides[i]
         p.lam_mode, p.lam_user = self.lam_mode, self.lam_user
         p.adv_x, p.adv_y = self.adv
+        keep = []
+        for i in range(4):
+            d = self.dirichlet[i]
+            if d is None:
+                p.dir[i] = ctypes.POINTER(ctypes.c_double)()
+            else:
+                a = np.ascontiguousarray(d, dtype=np.float64)
+                keep.append(a)
+                p.dir[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p._keep = keep  # the arrays live as long as the struct
         return p
 
 

@@ -33,6 +33,12 @@
 //     after streaming by specular reflection of the outgoing ones, with the
 //     normal momentum component negated (Sec. II.E, upper wall written out
 //     there; the other three sides by the same mirror rule);
+//   * Dirichlet side (the inflow and top boundaries of the oblique-shock case,
+//     Sec. III, are prescribed but not described): the ghost cells beyond it
+//     hold the prescribed conserved state U_b in equilibrium at the step's
+//     lattice speed, so a population pulled from across it is f^eq_i(U_b);
+//     at a corner ghost the y-side decides; the prescribed states take part
+//     in the global lambda* maximum like interior cells;
 //   * f^0 = f^eq(U0) with the lattice speed lambda*(U0)/cfl (frozen / user
 //     modes: the fixed speed).
 //
@@ -51,7 +57,7 @@ namespace orc {
 // ----------------------------------------------------------------- parameters
 enum { D1Q2 = 0, D1Q3 = 1, D2Q4 = 2 };
 enum { FLUX_EULER = 0, FLUX_LINEAR = 1 };
-enum { SIDE_TRANSMISSIVE = 0, SIDE_PERIODIC = 1, SIDE_WALL = 2 };
+enum { SIDE_TRANSMISSIVE = 0, SIDE_PERIODIC = 1, SIDE_WALL = 2, SIDE_DIRICHLET = 3 };
 enum { LAM_PER_STEP = 0, LAM_FROZEN = 1, LAM_USER = 2 };
 enum { ST_OK = 0, ST_INVAL = -1, ST_NONPHYSICAL = -4 };
 
@@ -66,6 +72,9 @@ struct Problem {
     int lam_mode;
     double lam_user;  // lattice speed for LAM_USER
     double adv_x, adv_y;  // advection speed for FLUX_LINEAR
+    // Dirichlet data per side (xlo, xhi, ylo, yhi): conserved states [K][n]
+    // along the side, n = ny for the x-sides and nx for the y-sides.
+    const double* dir[4];
 };
 
 // ------------------------------------------------------------ dual numbers
@@ -271,6 +280,9 @@ struct Sim {
             }
     }
 
+    // Number of prescribed states along side s.
+    int side_len(int s) const { return s < 2 ? P.ny : P.nx; }
+
     double max_local_lambda() {
         double m = 0.0;
         std::vector<double> Uc(K);
@@ -278,6 +290,12 @@ struct Sim {
             for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
             m = std::max(m, local_lambda(P, Uc.data()));
         }
+        for (int s = 0; s < 4; ++s)  // the ghost cells of Dirichlet sides
+            if (P.side[s] == SIDE_DIRICHLET)
+                for (int j = 0; j < side_len(s); ++j) {
+                    for (int k = 0; k < K; ++k) Uc[k] = P.dir[s][(size_t)k * side_len(s) + j];
+                    m = std::max(m, local_lambda(P, Uc.data()));
+                }
         return m;
     }
 
@@ -336,12 +354,52 @@ struct Sim {
         return -1;  // wall
     }
 
+    // Index along one axis into a Dirichlet side's array for a ghost position
+    // j: wrapped on a periodic axis, clamped otherwise.
+    static int along(int j, int n, int side_lo, int side_hi) {
+        if (j >= 0 && j < n) return j;
+        int side = j < 0 ? side_lo : side_hi;
+        if (side == SIDE_PERIODIC) return ((j % n) + n) % n;
+        return j < 0 ? 0 : n - 1;
+    }
+
+    // Prescribed state of the ghost cell (xs, ys) if it lies across a
+    // Dirichlet side (the y-side first at a corner).
+    bool ghost_state(int xs, int ys, double* Ub) {
+        if (D == 2 && (ys < 0 || ys >= P.ny)) {
+            int s = ys < 0 ? 2 : 3;
+            if (P.side[s] == SIDE_DIRICHLET) {
+                int j = along(xs, P.nx, P.side[0], P.side[1]);
+                for (int k = 0; k < K; ++k) Ub[k] = P.dir[s][(size_t)k * P.nx + j];
+                return true;
+            }
+        }
+        if (xs < 0 || xs >= P.nx) {
+            int s = xs < 0 ? 0 : 1;
+            if (P.side[s] == SIDE_DIRICHLET) {
+                int j = D == 2 ? along(ys, P.ny, P.side[2], P.side[3]) : 0;
+                for (int k = 0; k < K; ++k) Ub[k] = P.dir[s][(size_t)k * P.ny + j];
+                return true;
+            }
+        }
+        return false;
+    }
+
     // Streaming with exact hopping: f_i(x + s_i, t + dt) = f*_i(x, t)   (Sec. II.A)
-    // written as a pull f_i^{n+1}(x) = f*_i(x - s_i), then the walls.
-    void stream() {
+    // written as a pull f_i^{n+1}(x) = f*_i(x - s_i), then the walls.  A pull
+    // from a Dirichlet ghost cell takes its equilibrium at lattice speed lam.
+    void stream(double lam) {
+        std::vector<double> Ub(K), Gx(K), Gy(K, 0.0);
         for (int i = 0; i < Q; ++i)
             for (int y = 0; y < P.ny; ++y)
                 for (int x = 0; x < P.nx; ++x) {
+                    int xsrc = x - sx(P.model, i), ysrc = D == 2 ? y - sy(P.model, i) : 0;
+                    if (ghost_state(xsrc, ysrc, Ub.data())) {
+                        flux(P, Ub.data(), Gx.data(), Gy.data());
+                        for (int k = 0; k < K; ++k)
+                            F(f, i, k, x, y) = T(equilibrium(P.model, i, Ub[k], Gx[k], Gy[k], lam));
+                        continue;
+                    }
                     int xs = source(x, sx(P.model, i), P.nx, P.side[0], P.side[1]);
                     int ys = D == 2 ? source(y, sy(P.model, i), P.ny, P.side[2], P.side[3]) : 0;
                     for (int k = 0; k < K; ++k)
@@ -398,6 +456,22 @@ struct Sim {
     }
 };
 
+// Are the prescribed states of every Dirichlet side admissible?  (Checked with
+// the initial state: a bad one is reported as non-physical at step 0.)
+bool dirichlet_admissible(const Problem& P) {
+    int K = ncomp(P);
+    std::vector<double> Ub(K);
+    for (int s = 0; s < 4; ++s) {
+        if (P.side[s] != SIDE_DIRICHLET) continue;
+        int n = s < 2 ? P.ny : P.nx;
+        for (int j = 0; j < n; ++j) {
+            for (int k = 0; k < K; ++k) Ub[k] = P.dir[s][(size_t)k * n + j];
+            if (!physical(P, Ub.data())) return false;
+        }
+    }
+    return true;
+}
+
 int validate(const Problem& P) {
     if (P.model < D1Q2 || P.model > D2Q4) return ST_INVAL;
     if (P.flux != FLUX_EULER && P.flux != FLUX_LINEAR) return ST_INVAL;
@@ -412,7 +486,10 @@ int validate(const Problem& P) {
         if (!(std::fabs(dx - dy) <= 1e-12 * dx)) return ST_INVAL;
     }
     for (int s = 0; s < 4; ++s)
-        if (P.side[s] < 0 || P.side[s] > 2) return ST_INVAL;
+        if (P.side[s] < 0 || P.side[s] > 3) return ST_INVAL;
+    for (int s = 0; s < 4; ++s)
+        if (P.side[s] == SIDE_DIRICHLET && (!P.dir[s] || (ndim(P.model) == 1 && s >= 2)))
+            return ST_INVAL;
     if ((P.side[0] == SIDE_PERIODIC) != (P.side[1] == SIDE_PERIODIC)) return ST_INVAL;
     if (ndim(P.model) == 2 && (P.side[2] == SIDE_PERIODIC) != (P.side[3] == SIDE_PERIODIC))
         return ST_INVAL;
@@ -487,7 +564,7 @@ double orc_initial_lattice_speed(const Problem* P, const double* U0) {
     if (P->lam_mode == LAM_USER) return P->lam_user;
     Sim<double> S(*P);
     std::memcpy(S.U.data(), U0, sizeof(double) * S.K * S.ncell);
-    if (!S.all_physical(nullptr)) return -1.0;
+    if (!S.all_physical(nullptr) || !dirichlet_admissible(*P)) return -1.0;
     return S.max_local_lambda() / P->cfl;
 }
 
@@ -509,7 +586,7 @@ int orc_run(const Problem* Pp, const double* U0, double t_end, long max_steps, d
     if (st != ST_OK) return st;
     Sim<double> S(P);
     std::memcpy(S.U.data(), U0, sizeof(double) * S.K * S.ncell);
-    if (!S.all_physical(nullptr)) {
+    if (!S.all_physical(nullptr) || !dirichlet_admissible(P)) {
         if (fail_step) *fail_step = 0;
         return ST_NONPHYSICAL;
     }
@@ -543,7 +620,7 @@ int orc_run(const Problem* Pp, const double* U0, double t_end, long max_steps, d
         if (dt_seq) dt_seq[n] = dt;
         if (lam_seq) lam_seq[n] = lam;
         S.collide(lam);
-        S.stream();
+        S.stream(lam);
         ++n;
         S.moments();
         if (!S.all_physical(nullptr)) {
@@ -573,7 +650,7 @@ int orc_step_fixed(const Problem* Pp, const double* f, const double* df, double 
     for (size_t j = 0; j < nf; ++j) S.f[j] = Dual(f[j], df ? df[j] : 0.0);
     S.moments();
     S.collide(lam);
-    S.stream();
+    S.stream(lam);
     for (size_t j = 0; j < nf; ++j) {
         f_out[j] = S.f[j].v;
         if (df_out) df_out[j] = S.f[j].d;
@@ -636,7 +713,7 @@ int orc_run_tangent(const Problem* Pp, const double* W0, const double* dW0, int 
     for (long s = 0; s < nsteps; ++s) {
         S.moments();
         S.collide(lam);
-        S.stream();
+        S.stream(lam);
     }
     S.moments();
     for (size_t j = 0; j < (size_t)S.K * n; ++j) {

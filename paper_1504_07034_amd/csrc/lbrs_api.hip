@@ -27,7 +27,8 @@ struct lbrs_ctx {
     int alternate;       // 2D: odd row segments march upwards (mirrored view)
     int persistent_max;  // largest 1D domain run by the persistent kernel
     int cu_count;
-    int bpc[2][17];      // resident step-kernel workgroups per CU, by (alternate, waves per block)
+    int bpc[2][2][17];   // resident step-kernel workgroups per CU, by (alternate, dirichlet, waves)
+    bool dir;            // some side is DIRICHLET
 };
 
 static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
@@ -49,8 +50,11 @@ static int check_params(const lbrs_params* p) {
         double dx = (p->x1 - p->x0) / p->nx, dy = (p->y1 - p->y0) / p->ny;
         if (!(fabs(dx - dy) <= 1e-12 * dx)) return LBRS_E_INVAL;
     }
-    for (int s = 0; s < 4; ++s)
-        if (p->bc[s] < LBRS_BC_TRANSMISSIVE || p->bc[s] > LBRS_BC_WALL) return LBRS_E_INVAL;
+    for (int s = 0; s < 4; ++s) {
+        if (p->bc[s] < LBRS_BC_TRANSMISSIVE || p->bc[s] > LBRS_BC_DIRICHLET) return LBRS_E_INVAL;
+        if (p->bc[s] == LBRS_BC_DIRICHLET && (dim != 2 || !p->dirichlet[s])) return LBRS_E_INVAL;
+        if (p->dirichlet[s] && ((uintptr_t)p->dirichlet[s] & 7u) != 0) return LBRS_E_INVAL;
+    }
     if ((p->bc[0] == LBRS_BC_PERIODIC) != (p->bc[1] == LBRS_BC_PERIODIC)) return LBRS_E_INVAL;
     if (dim == 2 && (p->bc[2] == LBRS_BC_PERIODIC) != (p->bc[3] == LBRS_BC_PERIODIC))
         return LBRS_E_INVAL;
@@ -178,6 +182,8 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     c->rows_per_tile = 0;
     c->waves_per_block = 4;
     c->alternate = 1;
+    c->dir = false;
+    for (int s = 0; s < 4; ++s) c->dir = c->dir || p->bc[s] == LBRS_BC_DIRICHLET;
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -187,9 +193,12 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     c->persistent_max = persistent1d_max_cells(c->Q, prop.sharedMemPerBlock);
     c->cu_count = prop.multiProcessorCount;
     CellArgs a = cell_args(c);
+    const double* dir[4];
+    for (int s = 0; s < 4; ++s) dir[s] = p->bc[s] == LBRS_BC_DIRICHLET ? p->dirichlet[s] : nullptr;
     hipError_t e = launch_reset(c->st, c->stream);
     if (e == hipSuccess)
-        e = launch_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl, c->stream);
+        e = launch_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl, dir,
+                        c->stream);
     if (e != hipSuccess) {
         free(c);
         return LBRS_E_HIP;
@@ -220,8 +229,8 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream) {
 static int blocks_per_cu(const lbrs_ctx* c) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
     int w = c->waves_per_block;
-    int& n = m->bpc[c->alternate][w];
-    if (n == 0) n = step2d_blocks_per_cu(w, c->alternate != 0);
+    int& n = m->bpc[c->alternate][c->dir ? 1 : 0][w];
+    if (n == 0) n = step2d_blocks_per_cu(w, c->alternate != 0, c->dir);
     return n;
 }
 
@@ -270,7 +279,10 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
     a.gamma = c->P.gamma;
     a.t_end = t_end;
     a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
-    for (int s = 0; s < 4; ++s) a.bc[s] = c->P.bc[s];
+    for (int s = 0; s < 4; ++s) {
+        a.bc[s] = c->P.bc[s];
+        a.dir[s] = c->P.bc[s] == LBRS_BC_DIRICHLET ? c->P.dirichlet[s] : nullptr;
+    }
     return a;
 }
 
@@ -300,7 +312,7 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         for (int s = 0; s < max_steps; ++s) {
             Step2DArgs a = step2d_args(c, t_end, nullptr);
             hipError_t e = launch_step2d(a, c->waves_per_block, false, c->alternate != 0,
-                                         step2d_max_blocks(c), c->stream);
+                                         c->dir, step2d_max_blocks(c), c->stream);
             if (e != hipSuccess) return LBRS_E_HIP;
             ++c->launches;
         }
@@ -325,10 +337,10 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
 int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n) {
     if (!c || !d_Utape_n) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP) return LBRS_E_STATE;
-    if (c->dim != 2) return LBRS_E_STATE;
+    if (c->dim != 2 || c->dir) return LBRS_E_STATE;  // the tape serves the periodic adjoint
     Step2DArgs a = step2d_args(c, INFINITY, d_Utape_n);
-    hipError_t e = launch_step2d(a, c->waves_per_block, true, c->alternate != 0, step2d_max_blocks(c),
-                                 c->stream);
+    hipError_t e = launch_step2d(a, c->waves_per_block, true, c->alternate != 0, false,
+                                 step2d_max_blocks(c), c->stream);
     if (e != hipSuccess) return LBRS_E_HIP;
     ++c->launches;
     return LBRS_OK;

@@ -282,7 +282,7 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
     }
     b->ndom = ndom;
     b->wpb = 8;
-    b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb, true);
+    b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb, true, false);
     b->doms.resize(ndom);
     long long off = 0, rows = 0, tiles = 0;
     b->max_nx = 0;

@@ -15,7 +15,7 @@
 namespace lbrs {
 
 enum : int { D1Q2 = 0, D1Q3 = 1, D2Q4 = 2 };
-enum : int { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_WALL = 2 };
+enum : int { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1, BC_WALL = 2, BC_DIRICHLET = 3 };
 enum : int { LAM_PER_STEP = 0, LAM_FROZEN = 1, LAM_USER = 2 };
 
 // ---------------------------------------------------------------- time state
@@ -42,6 +42,7 @@ struct DevState {
     double lam_fixed;            // lattice speed of FROZEN / USER modes
     unsigned long long lam_init; // lambda*(U0) accumulator used by init
     double J;                    // objective accumulator
+    unsigned long long lam_bc;   // bound of the prescribed (Dirichlet) side states
 };
 
 struct LaunchSlots {
@@ -81,7 +82,10 @@ __device__ inline StepCtl step_control(const DevState* st, LaunchSlots ls, int l
     bool bad = st->bad[ls.lr] != 0u;
     c.active = !bad && (t < t_end);
     if (lam_mode == LAM_PER_STEP) {
-        double lam_star = __longlong_as_double((long long)st->lam[ls.lr]);
+        // the ghost cells of Dirichlet sides count like interior cells
+        double lam_star = __longlong_as_double((long long)(st->lam[ls.lr] > st->lam_bc
+                                                               ? st->lam[ls.lr]
+                                                               : st->lam_bc));
         double dt = cfl * dx / lam_star;
         double rem = t_end - t;
         bool last = false;
@@ -151,6 +155,24 @@ __device__ inline void collide_d2q4(const double f[16], const double U[4], const
         fs[1 * 4 + k] = om1 * f[1 * 4 + k] + omega * (q + b);
         fs[2 * 4 + k] = om1 * f[2 * 4 + k] + omega * (q + a);
         fs[3 * 4 + k] = om1 * f[3 * 4 + k] + omega * (q - b);
+    }
+}
+
+// Equilibria alone, f^eq_i = U/4 + (s_ix G1 + s_iy G2)/(4 lambda), in the same
+// folded form as the collision (the populations of a Dirichlet ghost cell).
+__device__ inline void equilibria_d2q4(const double U[4], const Euler2& e, double c4lam,
+                                       double feq[16]) {
+    const double G1[4] = {U[1], U[1] * e.u + e.p, U[1] * e.v, e.u * e.H};
+    const double G2[4] = {U[2], U[2] * e.u, U[2] * e.v + e.p, e.v * e.H};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double q = 0.25 * U[k];
+        double a = (G1[k] + G2[k]) * c4lam;
+        double b = (G1[k] - G2[k]) * c4lam;
+        feq[0 * 4 + k] = q - a;
+        feq[1 * 4 + k] = q + b;
+        feq[2 * 4 + k] = q + a;
+        feq[3 * 4 + k] = q - b;
     }
 }
 

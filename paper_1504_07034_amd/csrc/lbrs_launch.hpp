@@ -23,6 +23,7 @@ struct Step2DArgs {
     double dx, cfl, omega, gamma, t_end;
     int lam_mode;
     int bc[4];
+    const double* dir[4]; // Dirichlet states per side, [4][n] conserved (or null)
 };
 
 struct Step1DArgs {
@@ -141,9 +142,9 @@ struct Batch2DArgs {
 
 hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
                                hipStream_t s);
-hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, int max_blocks,
-                         hipStream_t s);
-int step2d_blocks_per_cu(int wpb, bool alt);
+hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, bool dir,
+                         int max_blocks, hipStream_t s);
+int step2d_blocks_per_cu(int wpb, bool alt, bool dir);
 bool step2d_wpb_supported(int wpb);
 hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
 hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);
@@ -156,7 +157,7 @@ hipError_t launch_isentropic_to_cons(const CellArgs& a, const double* rho, doubl
 hipError_t launch_isentropic_to_cons_adjoint(const CellArgs& a, const double* rho, const double* Ub,
                                              double* rb, hipStream_t s);
 hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState* st, int lam_mode,
-                       double lam_user, double cfl, hipStream_t s);
+                       double lam_user, double cfl, const double* const dir[4], hipStream_t s);
 hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st, const double* ext,
                         double t, long long n, bool per_step, hipStream_t s);
 hipError_t launch_get_f(const CellArgs& a, double* f0, double* f1, const DevState* st, int slot,

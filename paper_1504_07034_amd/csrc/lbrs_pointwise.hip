@@ -33,6 +33,7 @@ __global__ void reset_state_kernel(DevState* st) {
         st->lam_fixed = 0.0;
         st->lam_init = 0ull;
         st->J = 0.0;
+        st->lam_bc = 0ull;
     }
 }
 
@@ -121,6 +122,42 @@ __global__ void bound_of_U_kernel(CellArgs a, const double* __restrict__ U, DevS
     }
     double wm = wave_max(l);
     if ((threadIdx.x & 63) == 0) publish_max(&st->lam_init, wm);
+    if (__any(bad) && (threadIdx.x & 63) == 0) {
+        atomicOr(&st->bad[0], 1u);
+        atomicOr(&st->status, 1u);
+        atomicMin(&st->fail_step, 0ull);
+    }
+}
+
+// Bounds of the prescribed states of the Dirichlet sides (D2Q4): into the
+// initial bound (the ghost cells count like interior cells) and into lam_bc,
+// which every later per-step bound includes.  A non-admissible prescribed
+// state is reported like a non-admissible U0.  Thread j covers position j of
+// the concatenated sides x-low, x-high (ny each), y-low, y-high (nx each).
+struct DirSides {
+    const double* d[4];
+};
+__global__ void dirichlet_bound_kernel(CellArgs a, DirSides ds, DevState* st) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    bool bad = false;
+    const long long nxs = a.ny, nys = a.nx;
+    int side = -1;
+    long long pos = 0, n = 0;
+    if (j < nxs) { side = 0; pos = j; n = nxs; }
+    else if (j < 2 * nxs) { side = 1; pos = j - nxs; n = nxs; }
+    else if (j < 2 * nxs + nys) { side = 2; pos = j - 2 * nxs; n = nys; }
+    else if (j < 2 * nxs + 2 * nys) { side = 3; pos = j - 2 * nxs - nys; n = nys; }
+    if (side >= 0 && ds.d[side]) {
+        double U[4];
+        for (int k = 0; k < 4; ++k) U[k] = ds.d[side][k * n + pos];
+        bad = !bound_d2q4(U, a.gamma, &l);
+    }
+    double wm = wave_max(l);
+    if ((threadIdx.x & 63) == 0) {
+        publish_max(&st->lam_init, wm);
+        publish_max(&st->lam_bc, wm);
+    }
     if (__any(bad) && (threadIdx.x & 63) == 0) {
         atomicOr(&st->bad[0], 1u);
         atomicOr(&st->status, 1u);
@@ -380,8 +417,17 @@ hipError_t launch_isentropic_to_cons_adjoint(const CellArgs& a, const double* rh
     return hipGetLastError();
 }
 hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState* st, int lam_mode,
-                       double lam_user, double cfl, hipStream_t s) {
+                       double lam_user, double cfl, const double* const dir[4], hipStream_t s) {
     hipLaunchKernelGGL(bound_of_U_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, U0, st);
+    DirSides ds;
+    bool any = false;
+    for (int k = 0; k < 4; ++k) {
+        ds.d[k] = dir ? dir[k] : nullptr;
+        any = any || ds.d[k];
+    }
+    if (any)
+        hipLaunchKernelGGL(dirichlet_bound_kernel, grid1(2LL * (a.nx + a.ny), 256), dim3(256), 0, s, a,
+                           ds, st);
     hipLaunchKernelGGL(init_eq_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, U0, f0, st, lam_mode,
                        lam_user, cfl);
     return hipGetLastError();

@@ -76,13 +76,8 @@ struct Shifted {
     double s1[4], s2[4], n3[4], n4[4];
 };
 
-// Collision of the lane's cell and the four diagonal hops across lanes.
-__device__ inline void collide_and_shift(const double f[16], double gm1, double c4lam, double omega,
-                                         double U[4], Shifted& sh) {
-    moments_d2q4(f, U);
-    const Euler2 e = euler2(U, gm1);
-    double fs[16];
-    collide_d2q4(f, U, e, c4lam, omega, fs);
+// The four diagonal hops of post-collision values across lanes.
+__device__ inline void shift_row(const double fs[16], Shifted& sh) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         sh.s1[k] = lane_from_right(fs[0 * 4 + k]);
@@ -103,6 +98,8 @@ struct TileGeom {
     int strip, nstrips, nseg;
     double c4lam, omega, gamma;
     int bc[4];
+    const double* dir[4];  // Dirichlet states per side ([4][ny] x-sides, [4][nx] y-sides)
+    bool any_dir;
 };
 
 // How a tile's march sees memory.  Odd row segments are marched through the
@@ -119,7 +116,45 @@ struct MarchView {
     long long tbase, tstep;  // offset of march row j in a moment plane: tbase + j * tstep
     double s2;               // sign of the y-momentum component
     int bc_lo, bc_hi;        // side conditions at march rows 0 and ny-1
+    const double* dlo;       // Dirichlet states beyond march row 0 / ny-1 ([4][nx])
+    const double* dhi;
+    bool mirror;
 };
+
+// Dirichlet ghost cells of march row j: the post-collision values of a lane
+// whose cell lies beyond a DIRICHLET side are replaced by the equilibria of
+// the prescribed state at this step's lattice speed (the y-side decides at a
+// corner; the x index along a y-side and the row index along an x-side are
+// wrapped or clamped like the grid's own).  Rows and lanes that are not
+// ghosts keep their values; without any ghost in the wave nothing happens.
+__device__ __forceinline__ void dirichlet_ghosts(const TileGeom& g, const MarchView& m, int j,
+                                                 int x, int xl, double gm1, double c4lam,
+                                                 double fs[16]) {
+    const int nx = g.nx, ny = g.ny;
+    const bool grow = (j < 0 && m.bc_lo == BC_DIRICHLET) || (j >= ny && m.bc_hi == BC_DIRICHLET);
+    const bool glane = !grow && ((x < 0 && g.bc[0] == BC_DIRICHLET) ||
+                                 (x >= nx && g.bc[1] == BC_DIRICHLET));
+    if (!grow && !__any(glane)) return;
+    double Ug[4] = {1.0, 0.0, 0.0, 1.0};  // placeholder for lanes that keep their values
+    if (grow) {
+        const double* d = j < 0 ? m.dlo : m.dhi;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Ug[k] = d[k * nx + xl];
+    } else if (glane) {
+        const double* d = x < 0 ? g.dir[0] : g.dir[1];
+        const int jj = map_index(j, ny, g.bc[2] == BC_PERIODIC);
+        const int row = m.mirror ? ny - 1 - jj : jj;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Ug[k] = d[k * ny + row];
+    }
+    Ug[2] = m.s2 * Ug[2];
+    const Euler2 e = euler2(Ug, gm1);
+    double fq[16];
+    equilibria_d2q4(Ug, e, c4lam, fq);
+    const bool ghost = grow || glane;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) fs[p] = ghost ? fq[p] : fs[p];
+}
 
 // The 16 populations of march row j at column xl (a wave-uniform row base
 // plus the lane's column, so that the loads take a scalar base address).
@@ -138,7 +173,7 @@ __device__ inline void load_view(double v[16], const double* __restrict__ fin, c
 // Rows y0..y1-1 (march coordinates) of one strip: lanes 1..g.strip are output
 // columns, lanes 0 and g.strip+1 its halo columns.  Accumulates the lane's
 // bound of the new state and its admissibility.
-template <bool TAPE, int WPB>
+template <bool TAPE, int WPB, bool DIR>
 __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m, int strip, int y0,
                                            int y1, int lane, double& lmax, bool& bad) {
     const int nx = g.nx, ny = g.ny;
@@ -156,12 +191,23 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
     const bool wall_xlo = g.bc[0] == BC_WALL && x == 0;
     const bool wall_xhi = g.bc[1] == BC_WALL && x == nx - 1;
 
-    // prologue: rows y0-1 and y0 fill the two-row pipeline (no output)
-    double f[16], nxt[16], U[4];
+    // collision of march row j (populations fr), Dirichlet ghosts, hops
+    double U[4];
     Shifted sh;
+    auto collide_row = [&](const double (&fr)[16], int j) {
+        moments_d2q4(fr, U);
+        const Euler2 e = euler2(U, gm1);
+        double fs[16];
+        collide_d2q4(fr, U, e, c4lam, omega, fs);
+        if (DIR) dirichlet_ghosts(g, m, j, x, xl, gm1, c4lam, fs);
+        shift_row(fs, sh);
+    };
+
+    // prologue: rows y0-1 and y0 fill the two-row pipeline (no output)
+    double f[16], nxt[16];
     load_view(f, fin, m, ps, map_index(y0 - 1, ny, py), xl);
     load_view(nxt, fin, m, ps, map_index(y0, ny, py), xl);
-    collide_and_shift(f, gm1, c4lam, omega, U, sh);
+    collide_row(f, y0 - 1);
     double A3[4], A4[4], B3[4], B4[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -171,7 +217,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
 #pragma unroll
     for (int p = 0; p < 16; ++p) f[p] = nxt[p];
     load_view(nxt, fin, m, ps, map_index(y0 + 1, ny, py), xl);
-    collide_and_shift(f, gm1, c4lam, omega, U, sh);
+    collide_row(f, y0);
     if (TAPE) {
         double* trow = g.tape + m.tbase + y0 * m.tstep;
 #pragma unroll
@@ -194,7 +240,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
 #pragma unroll
         for (int p = 0; p < 16; ++p) f[p] = nxt[p];
         load_view(nxt, fin, m, ps, map_index(r + 1, ny, py), xl);
-        collide_and_shift(f, gm1, c4lam, omega, U, sh);
+        collide_row(f, r);
         if (TAPE) {
             // U^n of row r; row y1 is the next segment's first row
             double* trow = g.tape + m.tbase + map_index(r, ny, false) * m.tstep;
@@ -262,7 +308,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
 // ALT, odd segments are marched through the mirrored view, so that they run
 // upwards in memory while even ones run downwards; without it every segment
 // runs downwards (the view is then a compile-time identity).
-template <bool TAPE, int WPB, bool ALT>
+template <bool TAPE, int WPB, bool ALT, bool DIR>
 __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane, double& lmax,
                                           bool& bad) {
     const int strip = tile % g.nstrips;
@@ -284,6 +330,9 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
         m.s2 = -1.0;
         m.bc_lo = g.bc[3];
         m.bc_hi = g.bc[2];
+        m.dlo = g.dir[3];
+        m.dhi = g.dir[2];
+        m.mirror = true;
     } else {
         m.rbase = 0;
         m.rstep = g.rs;
@@ -294,11 +343,14 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
         m.s2 = 1.0;
         m.bc_lo = g.bc[2];
         m.bc_hi = g.bc[3];
+        m.dlo = g.dir[2];
+        m.dhi = g.dir[3];
+        m.mirror = false;
     }
-    march_tile<TAPE, WPB>(g, m, strip, y0, y1, lane, lmax, bad);
+    march_tile<TAPE, WPB, DIR>(g, m, strip, y0, y1, lane, lmax, bad);
 }
 
-template <bool TAPE, int WPB, bool ALT>
+template <bool TAPE, int WPB, bool ALT, bool DIR>
 __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
     const LaunchSlots ls = slots_for(a.launch);
     DevState* st = a.st;
@@ -325,14 +377,19 @@ __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
     g.c4lam = 1.0 / (4.0 * c.lam);
     g.omega = a.omega;
     g.gamma = a.gamma;
-    for (int s = 0; s < 4; ++s) g.bc[s] = a.bc[s];
+    g.any_dir = false;
+    for (int s = 0; s < 4; ++s) {
+        g.bc[s] = a.bc[s];
+        g.dir[s] = a.dir[s];
+        g.any_dir = g.any_dir || a.bc[s] == BC_DIRICHLET;
+    }
     const int total_waves = gridDim.x * WPB;
 
     double lmax = 0.0;
     bool bad = false;
     for (int tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wave; tile < a.ntiles;
          tile += total_waves)
-        step_tile<TAPE, WPB, ALT>(g, tile, lane, lmax, bad);
+        step_tile<TAPE, WPB, ALT, DIR>(g, tile, lane, lmax, bad);
 
     if (a.lam_mode == LAM_PER_STEP) {
         double wm = wave_max(lmax);
@@ -376,34 +433,66 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch(Batch2DArgs a) {
         g.c4lam = 1.0 / (4.0 * d.lam);
         g.omega = d.omega;
         g.gamma = d.gamma;
-        for (int s = 0; s < 4; ++s) g.bc[s] = d.bc[s];
+        for (int s = 0; s < 4; ++s) {
+            g.bc[s] = d.bc[s];
+            g.dir[s] = nullptr;
+        }
+        g.any_dir = false;
         double lmax = 0.0;
         bool bad = false;
-        step_tile<TAPE, WPB, true>(g, (int)(tile - d.tile0), lane, lmax, bad);
+        step_tile<TAPE, WPB, true, false>(g, (int)(tile - d.tile0), lane, lmax, bad);
         if (__any(bad) && lane == 0) atomicOr(&a.status[lo], 1u);
     }
 }
 
-template <bool TAPE, int WPB, bool ALT>
+template <bool TAPE, int WPB, bool ALT, bool DIR>
 static hipError_t launch_one(const Step2DArgs& a, int max_blocks, hipStream_t s) {
     int nblocks = (a.ntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    hipLaunchKernelGGL((step2d_d2q4<TAPE, WPB, ALT>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    hipLaunchKernelGGL((step2d_d2q4<TAPE, WPB, ALT, DIR>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
     return hipGetLastError();
+}
+
+// Kernel for (tape, alternate, dirichlet); the moment tape exists for the
+// adjoint, which needs periodic sides, so it has no Dirichlet variant.
+template <int W>
+static hipError_t launch_w(const Step2DArgs& a, bool tape, bool alt, bool dir, int max_blocks,
+                           hipStream_t s) {
+    if (tape) {
+        if (dir) return hipErrorInvalidValue;
+        return alt ? launch_one<true, W, true, false>(a, max_blocks, s)
+                   : launch_one<true, W, false, false>(a, max_blocks, s);
+    }
+    if (dir)
+        return alt ? launch_one<false, W, true, true>(a, max_blocks, s)
+                   : launch_one<false, W, false, true>(a, max_blocks, s);
+    return alt ? launch_one<false, W, true, false>(a, max_blocks, s)
+               : launch_one<false, W, false, false>(a, max_blocks, s);
+}
+
+template <int W>
+static int blocks_w(bool alt, bool dir) {
+    int n = 0;
+    hipError_t e;
+    if (dir)
+        e = alt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, true, true>,
+                                                               64 * W, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, false, true>,
+                                                               64 * W, 0);
+    else
+        e = alt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, true, false>,
+                                                               64 * W, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, false, false>,
+                                                               64 * W, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 #define LBRS_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12) X(16)
 
-hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, int max_blocks,
-                         hipStream_t s) {
-#define LBRS_CASE(W)                                                           \
-    if (wpb == W) {                                                            \
-        if (alt)                                                               \
-            return tape ? launch_one<true, W, true>(a, max_blocks, s)          \
-                        : launch_one<false, W, true>(a, max_blocks, s);        \
-        return tape ? launch_one<true, W, false>(a, max_blocks, s)             \
-                    : launch_one<false, W, false>(a, max_blocks, s);           \
-    }
+hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, bool dir,
+                         int max_blocks, hipStream_t s) {
+#define LBRS_CASE(W) \
+    if (wpb == W) return launch_w<W>(a, tape, alt, dir, max_blocks, s);
     LBRS_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return hipErrorInvalidValue;
@@ -435,18 +524,12 @@ bool step2d_wpb_supported(int wpb) {
 }
 
 // Resident workgroups of the step kernel per CU for a workgroup size.
-int step2d_blocks_per_cu(int wpb, bool alt) {
-    int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-#define LBRS_CASE(W)                                                                         \
-    if (wpb == W)                                                                            \
-        e = alt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, true>, \
-                                                               64 * W, 0)                    \
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, false>, \
-                                                               64 * W, 0);
+int step2d_blocks_per_cu(int wpb, bool alt, bool dir) {
+#define LBRS_CASE(W) \
+    if (wpb == W) return blocks_w<W>(alt, dir);
     LBRS_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
-    return e == hipSuccess && n > 0 ? n : 1;
+    return 1;
 }
 
 }  // namespace lbrs

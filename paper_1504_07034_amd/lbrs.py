@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbrs.so")
 
 LBRS_OK, LBRS_E_INVAL, LBRS_E_NOMEM, LBRS_E_HIP, LBRS_E_NONPHYSICAL, LBRS_E_STATE = 0, -1, -2, -3, -4, -5
 LBRS_D1Q2, LBRS_D1Q3, LBRS_D2Q4 = 0, 1, 2
-LBRS_BC_TRANSMISSIVE, LBRS_BC_PERIODIC, LBRS_BC_WALL = 0, 1, 2
+LBRS_BC_TRANSMISSIVE, LBRS_BC_PERIODIC, LBRS_BC_WALL, LBRS_BC_DIRICHLET = 0, 1, 2, 3
 LBRS_LAMBDA_PER_STEP, LBRS_LAMBDA_FROZEN_INIT, LBRS_LAMBDA_USER = 0, 1, 2
 LBRS_LAYOUT_PLANAR, LBRS_LAYOUT_ROWS = 0, 1
 
@@ -48,6 +48,7 @@ class lbrs_params(ctypes.Structure):
         ("bc", ctypes.c_int * 4),
         ("lambda_mode", ctypes.c_int), ("lambda_user", ctypes.c_double),
         ("layout", ctypes.c_int),
+        ("dirichlet", ctypes.c_void_p * 4),
     ]
 
 
@@ -154,7 +155,8 @@ def _stream(stream=None):
 
 def make_params(model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0, cfl=0.5,
                 bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
-                layout=LBRS_LAYOUT_PLANAR) -> lbrs_params:
+                layout=LBRS_LAYOUT_PLANAR, dirichlet=(None, None, None, None)) -> lbrs_params:
+    """dirichlet: per side, a device tensor of conserved states [K][n] (or None)."""
     p = lbrs_params()
     p.model, p.nx, p.ny = int(model), int(nx), int(ny)
     p.x0, p.x1, p.y0, p.y1 = map(float, domain)
@@ -163,6 +165,9 @@ def make_params(model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1
         p.bc[s] = int(bc[s])
     p.lambda_mode, p.lambda_user = int(lambda_mode), float(lambda_user)
     p.layout = int(layout)
+    for s in range(4):
+        d = dirichlet[s]
+        p.dirichlet[s] = None if d is None else d.data_ptr()
     return p
 
 
@@ -281,20 +286,35 @@ class Sim:
 
     def __init__(self, model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0,
                  cfl=0.5, bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
-                 layout=LBRS_LAYOUT_PLANAR, device="cuda"):
+                 layout=LBRS_LAYOUT_PLANAR, device="cuda", dirichlet_W=(None, None, None, None)):
+        """dirichlet_W: per side, the prescribed primitive states [K][n] of a
+        DIRICHLET side (n = ny for the x-sides, nx for the y-sides), converted
+        to conserved states on the device and kept for the context's life."""
         load_library()
         self.layout = layout
+        self.device = torch.device(device)
+        self.dirichlet = tuple(None if d is None else self._side_to_cons(d, gamma)
+                               for d in dirichlet_W)
         self.p = make_params(model, nx, ny, domain, gamma, omega, cfl, bc, lambda_mode, lambda_user,
-                             layout)
+                             layout, self.dirichlet)
         self.model, self.nx, self.ny = model, nx, ny
         self.Q = {0: 2, 1: 3, 2: 4}[model]
         self.K = 4 if model == LBRS_D2Q4 else 3
         fb, ub, sb = lbrs_query_sizes(self.p)
-        self.device = torch.device(device)
         self.f0 = torch.empty(fb // 8, dtype=torch.float64, device=self.device)
         self.f1 = torch.empty(fb // 8, dtype=torch.float64, device=self.device)
         self.scratch = torch.zeros(sb // 8, dtype=torch.float64, device=self.device)
         self.ctx = None
+
+    def _side_to_cons(self, Wside, gamma):
+        """Conserved states of a side's primitive states [4][n] (2D Euler), by
+        the library's conversion on a 3-row strip of unit cells."""
+        W = torch.as_tensor(Wside, dtype=torch.float64).to(self.device)
+        n = W.shape[1]
+        Wg = W[:, None, :].expand(W.shape[0], 3, n).contiguous()
+        U = torch.empty_like(Wg)
+        lbrs_prim_to_cons(make_params(LBRS_D2Q4, n, 3, (0.0, float(n), 0.0, 3.0), gamma), Wg, U)
+        return U[:, 0, :].contiguous()
 
     @property
     def f_shape(self):

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 D1Q2, D1Q3, D2Q4 = 0, 1, 2
-TRANSMISSIVE, PERIODIC, WALL = 0, 1, 2
+TRANSMISSIVE, PERIODIC, WALL, DIRICHLET = 0, 1, 2, 3
 
 
 @dataclass
@@ -39,6 +39,9 @@ class Workload:
     t_end: float = math.inf
     steps: int | None = None  # fixed step count (frozen lattice speed runs)
     meta: dict = field(default_factory=dict)
+    # prescribed primitive states of Dirichlet sides (xlo, xhi, ylo, yhi):
+    # [K][n] along the side (n = ny for the x-sides, nx for the y-sides)
+    dirichlet_W: tuple = (None, None, None, None)
 
 
 def centres(n: int, a: float, b: float) -> np.ndarray:
@@ -109,6 +112,29 @@ def riemann2d_paper(n: int = 400, t_end: float = 0.25) -> Workload:
     w = riemann2d(n, states=states, t_end=t_end)
     w.name = "riemann2d_paper"
     return w
+
+
+# Oblique shock reflection (Sec. III): the inflow state and the post-shock state
+# the paper prints for the top boundary.
+OBLIQUE_INFLOW = (1.0, 2.9, 0.0, 1.0 / 1.4)
+OBLIQUE_POST_SHOCK = (1.69997, 2.61934, -0.50633, 1.52819)
+
+
+def oblique_shock(nx: int = 240, ny: int = 80, t_end: float = 4.0, omega: float = 1.0) -> Workload:
+    """Oblique shock reflection (Sec. III) on an nx x ny grid: the inflow state
+    prescribed on the left side, the post-shock state on the top side, a
+    free-slip wall at the bottom, a transmissive (supersonic outflow) right
+    side; the interior starts at the inflow state.  The domain extent is not
+    given: [0, nx/ny] x [0, 1], i.e. [0, 3] x [0, 1] with square cells at
+    240 x 80, so that the shock enters at the top-left corner."""
+    W = np.empty((4, ny, nx))
+    for k in range(4):
+        W[k] = OBLIQUE_INFLOW[k]
+    inflow = np.repeat(np.asarray(OBLIQUE_INFLOW, dtype=np.float64)[:, None], ny, axis=1)
+    top = np.repeat(np.asarray(OBLIQUE_POST_SHOCK, dtype=np.float64)[:, None], nx, axis=1)
+    return Workload("oblique_shock", D2Q4, nx, ny, (0.0, nx / ny, 0.0, 1.0), W, omega=omega,
+                    t_end=t_end, sides=(DIRICHLET, TRANSMISSIVE, WALL, DIRICHLET),
+                    dirichlet_W=(inflow, None, None, top))
 
 
 def explosion(n: int = 400, t_end: float = 0.25, omega: float = 1.0) -> Workload:

@@ -52,12 +52,27 @@ def test_query_sizes_and_validation(lib):
         dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, bc=(2, 0, 2, 0)),       # wall corner
         dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, lambda_mode=2, lambda_user=0.0),
         dict(model=7, nx=64),
+        dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, bc=(3, 0, 2, 0)),       # Dirichlet without data
+        dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, bc=(4, 0, 0, 0)),
+        dict(model=lbrs.LBRS_D1Q3, nx=400, bc=(3, 0, 0, 0)),             # 1D Dirichlet
     ]
     for kw in bad:
         p = lbrs.make_params(**kw)
         with pytest.raises(lbrs.LBRSError) as e:
             lbrs.lbrs_query_sizes(p)
         assert e.value.code == lbrs.LBRS_E_INVAL, kw
+
+
+def test_dirichlet_data_accepted_by_validation(lib):
+    """A Dirichlet side with a (device) pointer passes the host checks; the
+    pointer is not dereferenced on the host."""
+    class FakePtr:  # any 8-byte aligned address: validation only
+        def data_ptr(self):
+            return 4096
+    p = lbrs.make_params(lbrs.LBRS_D2Q4, 64, 64, bc=(3, 0, 2, 3),
+                         dirichlet=(FakePtr(), None, None, FakePtr()))
+    f, u, s = lbrs.lbrs_query_sizes(p)
+    assert f == 16 * 8 * 64 * 64
 
 
 def test_init_rejects_null_pointers(lib):
