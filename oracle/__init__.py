@@ -28,7 +28,7 @@ SRC = os.path.join(HERE, "lbrs_oracle.cpp")
 LIB = os.path.join(HERE, "liblbrs_oracle.so")
 
 D1Q2, D1Q3, D2Q4 = 0, 1, 2
-FLUX_EULER, FLUX_LINEAR = 0, 1
+FLUX_EULER, FLUX_LINEAR, FLUX_QUADRATIC = 0, 1, 2
 TRANSMISSIVE, PERIODIC, WALL, DIRICHLET = 0, 1, 2, 3
 LAM_PER_STEP, LAM_FROZEN, LAM_USER = 0, 1, 2
 OK, INVAL, NONPHYSICAL = 0, -1, -4
@@ -58,6 +58,7 @@ class _Problem(ctypes.Structure):
         ("lam_mode", ctypes.c_int), ("lam_user", ctypes.c_double),
         ("adv_x", ctypes.c_double), ("adv_y", ctypes.c_double),
         ("dir", ctypes.POINTER(ctypes.c_double) * 4),
+        ("q", ctypes.c_double * 4),
     ]
 
 
@@ -113,6 +114,8 @@ class Problem:
     # Dirichlet data per side (xlo, xhi, ylo, yhi): conserved states [K][n],
     # n = ny for the x-sides, nx for the y-sides; None for other sides.
     dirichlet: tuple = (None, None, None, None)
+    # FLUX_QUADRATIC: g1(u) = q0 u + q1 u^2/2, g2(u) = q2 u + q3 u^2/2
+    quad: tuple = (0.0, 0.0, 0.0, 0.0)
 
     @property
     def Q(self) -> int:
@@ -120,7 +123,7 @@ class Problem:
 
     @property
     def K(self) -> int:
-        if self.flux == FLUX_LINEAR:
+        if self.flux != FLUX_EULER:
             return 1
         return 4 if self.model == D2Q4 else 3
 
@@ -147,6 +150,8 @@ class Problem:
                 keep.append(a)
                 p.dir[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         p._keep = keep  # the arrays live as long as the struct
+        for i in range(4):
+            p.q[i] = float(self.quad[i])
         return p
 
 

@@ -56,7 +56,7 @@ namespace orc {
 
 // ----------------------------------------------------------------- parameters
 enum { D1Q2 = 0, D1Q3 = 1, D2Q4 = 2 };
-enum { FLUX_EULER = 0, FLUX_LINEAR = 1 };
+enum { FLUX_EULER = 0, FLUX_LINEAR = 1, FLUX_QUADRATIC = 2 };
 enum { SIDE_TRANSMISSIVE = 0, SIDE_PERIODIC = 1, SIDE_WALL = 2, SIDE_DIRICHLET = 3 };
 enum { LAM_PER_STEP = 0, LAM_FROZEN = 1, LAM_USER = 2 };
 enum { ST_OK = 0, ST_INVAL = -1, ST_NONPHYSICAL = -4 };
@@ -64,7 +64,7 @@ enum { ST_OK = 0, ST_INVAL = -1, ST_NONPHYSICAL = -4 };
 // Mirrored field by field in oracle/__init__.py (ctypes).
 struct Problem {
     int model;        // D1Q2, D1Q3, D2Q4
-    int flux;         // FLUX_EULER or FLUX_LINEAR (scalar test mode)
+    int flux;         // FLUX_EULER, or a scalar law: FLUX_LINEAR, FLUX_QUADRATIC
     int nx, ny;       // ny = 1 in 1D
     double x0, x1, y0, y1;
     double gamma, omega, cfl;
@@ -75,6 +75,10 @@ struct Problem {
     // Dirichlet data per side (xlo, xhi, ylo, yhi): conserved states [K][n]
     // along the side, n = ny for the x-sides and nx for the y-sides.
     const double* dir[4];
+    // FLUX_QUADRATIC: g1(u) = q[0] u + q[1] u^2/2, g2(u) = q[2] u + q[3] u^2/2
+    // (Burgers, Sec. II.A: q = (0, 1, ., .); the 2D Burgers law of Sec. III:
+    // q = (0, 1, 1, 0)).
+    double q[4];
 };
 
 // ------------------------------------------------------------ dual numbers
@@ -130,8 +134,9 @@ inline int sy(int model, int i) {
     static const int s24[4] = {-1, -1, +1, +1};
     return model == D2Q4 ? s24[i] : 0;
 }
+inline bool scalar_law(const Problem& P) { return P.flux != FLUX_EULER; }
 inline int ncomp(const Problem& P) {
-    if (P.flux == FLUX_LINEAR) return 1;
+    if (scalar_law(P)) return 1;
     return ndim(P.model) == 1 ? 3 : 4;
 }
 
@@ -179,6 +184,12 @@ void flux(const Problem& P, const T* U, T* Gx, T* Gy) {
         if (ndim(P.model) == 2) Gy[0] = P.adv_y * U[0];
         return;
     }
+    if (P.flux == FLUX_QUADRATIC) {  // g(u) = a u + b u^2/2 per direction
+        const T& u = U[0];
+        Gx[0] = P.q[0] * u + P.q[1] * (0.5 * (u * u));
+        if (ndim(P.model) == 2) Gy[0] = P.q[2] * u + P.q[3] * (0.5 * (u * u));
+        return;
+    }
     if (ndim(P.model) == 1)
         euler_flux_1d(U, P.gamma, Gx);
     else
@@ -203,10 +214,23 @@ T pressure(const Problem& P, const T* U) {
 //      (Sec. II.D, Bouchut's condition; "sqrt(2a)" read as sqrt(2)*a)
 //  linear advection: |c| in 1D, |cx| + |cy| in 2D (the sub-characteristic
 //  bound for the scalar D1Q2 model, Sec. II.A, and its D2Q4 analogue).
+//  quadratic scalar law: |g'(u)| in 1D (Sec. II.A sub-characteristic
+//  condition); in 2D the largest |s_x g1'(u) + s_y g2'(u)| over the four
+//  diagonal directions, i.e. |g1'| + |g2'| (the D2Q4 equilibria are then
+//  non-decreasing in u, the scalar form of the Sec. II.D condition).
 inline double local_lambda(const Problem& P, const double* U) {
     if (P.flux == FLUX_LINEAR)
         return ndim(P.model) == 1 ? std::fabs(P.adv_x)
                                   : std::fabs(P.adv_x) + std::fabs(P.adv_y);
+    if (P.flux == FLUX_QUADRATIC) {
+        double d1 = P.q[0] + P.q[1] * U[0];
+        if (ndim(P.model) == 1) return std::fabs(d1);
+        double d2 = P.q[2] + P.q[3] * U[0];
+        double m = 0.0;
+        for (int sxv = -1; sxv <= 1; sxv += 2)
+            for (int syv = -1; syv <= 1; syv += 2) m = std::max(m, std::fabs(sxv * d1 + syv * d2));
+        return m;
+    }
     double rho = U[0];
     double p = pressure(P, U);
     double a = std::sqrt(P.gamma * p / rho);
@@ -240,7 +264,7 @@ inline bool physical(const Problem& P, const double* U) {
     int K = ncomp(P);
     for (int k = 0; k < K; ++k)
         if (!std::isfinite(U[k])) return false;
-    if (P.flux == FLUX_LINEAR) return true;
+    if (scalar_law(P)) return true;
     if (!(U[0] > 0.0)) return false;
     double p = pressure(P, U);
     return p > 0.0 && std::isfinite(p);
@@ -474,7 +498,10 @@ bool dirichlet_admissible(const Problem& P) {
 
 int validate(const Problem& P) {
     if (P.model < D1Q2 || P.model > D2Q4) return ST_INVAL;
-    if (P.flux != FLUX_EULER && P.flux != FLUX_LINEAR) return ST_INVAL;
+    if (P.flux < FLUX_EULER || P.flux > FLUX_QUADRATIC) return ST_INVAL;
+    if (scalar_law(P) && (P.side[0] == SIDE_WALL || P.side[1] == SIDE_WALL ||
+                          P.side[2] == SIDE_WALL || P.side[3] == SIDE_WALL))
+        return ST_INVAL;  // specular walls are defined for the Euler equations
     if (P.nx < 3 || P.ny < 1) return ST_INVAL;
     if (ndim(P.model) == 1 && P.ny != 1) return ST_INVAL;
     if (ndim(P.model) == 2 && P.ny < 3) return ST_INVAL;
@@ -534,7 +561,7 @@ void orc_equilibria(const Problem* P, const double* U, double lam, double* feq) 
 void orc_prim_to_cons(const Problem* P, const double* W, double* U) {
     long n = (long)P->nx * P->ny;
     int K = ncomp(*P);
-    if (P->flux == FLUX_LINEAR) {
+    if (scalar_law(*P)) {
         std::memcpy(U, W, sizeof(double) * n);
         return;
     }

@@ -24,6 +24,9 @@ D1Q2, D1Q3, D2Q4 = 0, 1, 2
 TRANSMISSIVE, PERIODIC, WALL, DIRICHLET = 0, 1, 2, 3
 
 
+FLUX_EULER, FLUX_LINEAR, FLUX_QUADRATIC = 0, 1, 2
+
+
 @dataclass
 class Workload:
     name: str
@@ -42,6 +45,10 @@ class Workload:
     # prescribed primitive states of Dirichlet sides (xlo, xhi, ylo, yhi):
     # [K][n] along the side (n = ny for the x-sides, nx for the y-sides)
     dirichlet_W: tuple = (None, None, None, None)
+    # conservation law: the Euler equations, or a scalar law with
+    # g1(u) = quad[0] u + quad[1] u^2/2, g2(u) = quad[2] u + quad[3] u^2/2
+    flux: int = FLUX_EULER
+    quad: tuple = (0.0, 0.0, 0.0, 0.0)
 
 
 def centres(n: int, a: float, b: float) -> np.ndarray:
@@ -135,6 +142,34 @@ def oblique_shock(nx: int = 240, ny: int = 80, t_end: float = 4.0, omega: float 
     return Workload("oblique_shock", D2Q4, nx, ny, (0.0, nx / ny, 0.0, 1.0), W, omega=omega,
                     t_end=t_end, sides=(DIRICHLET, TRANSMISSIVE, WALL, DIRICHLET),
                     dirichlet_W=(inflow, None, None, top))
+
+
+def burgers_riemann(n: int = 400, uL: float = 1.0, uR: float = 0.0, t_end: float = 0.5,
+                    model: int = D1Q2, omega: float = 1.0) -> Workload:
+    """Inviscid Burgers equation u_t + (u^2/2)_x = 0 (Sec. II.A) on [-1, 1]
+    with a jump at x = 0, transmissive sides."""
+    x = centres(n, -1.0, 1.0)
+    W = np.where(x < 0.0, uL, uR)[None, None, :].astype(np.float64)
+    return Workload("burgers_riemann", model, n, 1, (-1.0, 1.0, 0.0, 1.0), W, omega=omega,
+                    t_end=t_end, flux=FLUX_QUADRATIC, quad=(0.0, 1.0, 0.0, 0.0),
+                    meta={"uL": uL, "uR": uR})
+
+
+def spekreijse(case: int = 1, n: int = 64, t_end: float = 3.0, omega: float = 1.0) -> Workload:
+    """2D inviscid Burgers u_t + (u^2/2)_x + u_y = 0 on [0,1]^2 (Sec. III,
+    after Spekreijse), n x n, D2Q4, prescribed u on the left, right and bottom
+    sides (case 1: 1, -1, 1 - 2x; case 2: 1.5, -0.5, 1.5 - 2x), outflow
+    (transmissive) on top.  The initial state is not given: u = 0 inside,
+    run to a steady state."""
+    left, right, c0 = (1.0, -1.0, 1.0) if case == 1 else (1.5, -0.5, 1.5)
+    x = centres(n, 0.0, 1.0)
+    W = np.zeros((1, n, n))
+    dirichlet = (np.full((1, n), left), np.full((1, n), right), (c0 - 2.0 * x)[None, :].copy(),
+                 None)
+    return Workload(f"spekreijse{case}", D2Q4, n, n, (0.0, 1.0, 0.0, 1.0), W, omega=omega,
+                    t_end=t_end, sides=(DIRICHLET, DIRICHLET, DIRICHLET, TRANSMISSIVE),
+                    dirichlet_W=dirichlet, flux=FLUX_QUADRATIC, quad=(0.0, 1.0, 1.0, 0.0),
+                    meta={"case": case})
 
 
 def explosion(n: int = 400, t_end: float = 0.25, omega: float = 1.0) -> Workload:
