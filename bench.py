@@ -40,7 +40,7 @@ def kernel_source_hash() -> str:
     import hashlib
     csrc = os.path.join(ROOT, "paper_1504_07034_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read()
-                   for f in ("lbrs_step2d.hip", "lbrs_device.hpp"))
+                   for f in ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp"))
     return hashlib.sha256(src).hexdigest()[:16]
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = 256  # 16 FP64 populations in + 16 out per lattice update
@@ -410,6 +410,55 @@ def dirichlet_2d(nx=12288, ny=4096, steps=200, warmup=20):
             "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def scalar_laws(n2=8192, n1=1 << 24, steps=200, warmup=20):
+    """Scalar LBRS: the 2D Burgers case 1 (prescribed sides) at n2 x n2 on
+    D2Q4 (64 B per lattice update: 4 populations in and out) with an autotuned
+    launch shape, and the 1D Burgers shock tube on n1 cells, D1Q2 (32 B per
+    update).  HIP events."""
+    import torch
+
+    from paper_1504_07034_amd import autotune, lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    out = {}
+    w = wl.spekreijse(1, n2)
+    sim = lbrs.Sim(w.model, n2, n2, domain=w.domain, omega=w.omega, cfl=w.cfl, bc=w.sides,
+                   layout=lbrs.LBRS_LAYOUT_ROWS, dirichlet_W=w.dirichlet_W,
+                   law=lbrs.LBRS_LAW_SCALAR, scalar_flux=w.quad)
+    U0 = sim.prim_to_cons(torch.from_numpy(w.W))
+    sim.init(U0)
+    sim.step(5)
+    best = autotune.tune(sim, use_cache=False, alts=(1,))
+    sim.init(U0)
+    sim.set_tile(best["rows"], best["wpb"])
+    sim.step(warmup)
+    ms = _time_ms(lambda: sim.step(steps)) / steps
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+    sim.close()
+    del U0
+    gbs = 64 * n2 * n2 / (ms * 1e-3) / 1e9
+    out["burgers_2d"] = {"workload": "2D Burgers case 1 (Dirichlet sides), D2Q4", "n": n2,
+                         "tile_rows": best["rows"], "waves_per_block": best["wpb"],
+                         "ms_per_step": round(ms, 4), "MLUPS": round(n2 * n2 / ms / 1e3, 1),
+                         "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    torch.cuda.empty_cache()
+    w = wl.burgers_riemann(n1, 1.0, 0.0, t_end=10.0)
+    sim = lbrs.Sim(w.model, n1, 1, domain=w.domain, omega=w.omega, cfl=w.cfl, bc=w.sides,
+                   law=lbrs.LBRS_LAW_SCALAR, scalar_flux=w.quad)
+    sim.init_primitive(w.W)
+    sim.step(warmup, w.t_end)
+    ms = _time_ms(lambda: sim.step(steps, w.t_end)) / steps
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+    sim.close()
+    gbs = 32 * n1 / (ms * 1e-3) / 1e9
+    out["burgers_1d"] = {"workload": "1D Burgers shock tube, D1Q2", "n": n1,
+                         "ms_per_step": round(ms, 4), "MLUPS": round(n1 / ms / 1e3, 1),
+                         "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def copy_bandwidth(src, dst, reps=20):
     """Measured copy reference on this GPU: torch's device-to-device copy of
     one population buffer (read + write counted), HIP events."""
@@ -464,7 +513,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
-    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad", "dirichlet"],
+    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad", "dirichlet",
+                                       "scalar"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -484,7 +534,8 @@ def main():
     torch.cuda.set_device(0)
     if args.only:
         fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
-              "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d}[args.only]
+              "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
+              "scalar": scalar_laws}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
@@ -586,6 +637,7 @@ def main():
     if not args.no_extras:
         stage("slab_4096x512", lambda: slab_step(shape))
         stage("dirichlet_2d", dirichlet_2d)
+        stage("scalar_laws", scalar_laws)
         stage("adjoint_2d", adjoint_2d)
         stage("batched_1d", batched_1d)
         ws = wl.domain_batch(128, seed=0, steps=1000)

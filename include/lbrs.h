@@ -81,6 +81,21 @@ enum { LBRS_D1Q2 = 0, LBRS_D1Q3 = 1, LBRS_D2Q4 = 2 };
  * and PERIODIC on x only. */
 enum { LBRS_BC_TRANSMISSIVE = 0, LBRS_BC_PERIODIC = 1, LBRS_BC_WALL = 2, LBRS_BC_DIRICHLET = 3 };
 
+/* Conservation law.  EULER: the gamma-law Euler equations (K = 3 conserved
+ * components in 1D, 4 in 2D).  SCALAR: one conserved scalar u (K = 1) with the
+ * quadratic fluxes g1(u) = c0 u + c1 u^2/2 and g2(u) = c2 u + c3 u^2/2,
+ * c = lbrs_params.scalar_flux: the scalar LBRS the paper starts from
+ * (Sec. II.A, Burgers: c = (0, 1, ., .)), its D2Q4 form (Sec. II.D; the 2D
+ * Burgers law of the Sec. III test cases: c = (0, 1, 1, 0)), linear advection
+ * (c1 = c3 = 0).  Equilibria match u = sum f_i and g = sum lambda_i f_i; the
+ * local bound is |g'(u)| in 1D and |g1'(u)| + |g2'(u)| in 2D.  SCALAR takes
+ * TRANSMISSIVE, PERIODIC and DIRICHLET sides (no WALL; in 1D DIRICHLET on the
+ * x-sides), and the calls lbrs_init, lbrs_step, lbrs_get_state, lbrs_moments,
+ * lbrs_get_f, lbrs_set_f, lbrs_prim_to_cons (a copy: u is its own conserved
+ * variable) and lbrs_set_tile; the gradient calls are Euler-only
+ * (LBRS_E_STATE / LBRS_E_INVAL), and so are the batches. */
+enum { LBRS_LAW_EULER = 0, LBRS_LAW_SCALAR = 1 };
+
 /* Lattice speed.  PER_STEP: every step takes the global bound
  * lambda* = max over cells of the local bound (Sec. II.C Jin-Xin choice in 1D,
  * Sec. II.D Bouchut condition in 2D), dt = min(cfl*dx/lambda*, t_end - t) and
@@ -98,7 +113,7 @@ typedef struct {
     int model;            /* LBRS_D1Q2, LBRS_D1Q3 or LBRS_D2Q4 */
     int nx, ny;           /* cells; ny = 1 for 1D; nx >= 3 (and ny >= 3 in 2D) */
     double x0, x1, y0, y1;/* domain; y0, y1 ignored in 1D */
-    double gamma;         /* ratio of specific heats, > 1 */
+    double gamma;         /* ratio of specific heats, > 1 (Euler) */
     double omega;         /* relaxation parameter omega = dt/epsilon, in (0, 2) (Sec. II.B) */
     double cfl;           /* in (0, 1]: lattice speed = (lambda star) / cfl */
     int bc[4];            /* side conditions, x-low, x-high, y-low, y-high */
@@ -112,6 +127,8 @@ typedef struct {
      * the context exists.  A non-admissible prescribed state is reported
      * like a non-admissible U0 (LBRS_E_NONPHYSICAL at step 0). */
     const double* dirichlet[4];
+    int law;              /* LBRS_LAW_EULER (0) or LBRS_LAW_SCALAR (1) */
+    double scalar_flux[4];/* SCALAR: c0..c3 of g1(u) = c0 u + c1 u^2/2, g2(u) = c2 u + c3 u^2/2 */
 } lbrs_params;
 
 /* Sizes in bytes of one population buffer (f0 or f1), of one conserved-state

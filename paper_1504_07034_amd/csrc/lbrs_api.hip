@@ -29,10 +29,13 @@ struct lbrs_ctx {
     int cu_count;
     int bpc[2][2][17];   // resident step-kernel workgroups per CU, by (alternate, dirichlet, waves)
     bool dir;            // some side is DIRICHLET
+    int sbpc[17];        // resident scalar-step workgroups per CU, by waves per block
 };
 
 static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
-static int nk(int model) { return model == LBRS_D2Q4 ? 4 : 3; }
+static int nk(const lbrs_params* p) {
+    return p->law == LBRS_LAW_SCALAR ? 1 : (p->model == LBRS_D2Q4 ? 4 : 3);
+}
 
 static int check_params(const lbrs_params* p) {
     if (!p) return LBRS_E_INVAL;
@@ -43,7 +46,11 @@ static int check_params(const lbrs_params* p) {
     if (dim == 2 && p->ny < 3) return LBRS_E_INVAL;
     if ((long long)p->nx * p->ny > (1ll << 40)) return LBRS_E_INVAL;
     if (!(p->x1 > p->x0) || !isfinite(p->x0) || !isfinite(p->x1)) return LBRS_E_INVAL;
-    if (!(p->gamma > 1.0) || !isfinite(p->gamma)) return LBRS_E_INVAL;
+    if (p->law != LBRS_LAW_EULER && p->law != LBRS_LAW_SCALAR) return LBRS_E_INVAL;
+    if (p->law == LBRS_LAW_EULER && (!(p->gamma > 1.0) || !isfinite(p->gamma))) return LBRS_E_INVAL;
+    if (p->law == LBRS_LAW_SCALAR)
+        for (int k = 0; k < 4; ++k)
+            if (!isfinite(p->scalar_flux[k])) return LBRS_E_INVAL;
     if (!(p->omega > 0.0 && p->omega < 2.0)) return LBRS_E_INVAL;
     if (dim == 2) {
         if (!(p->y1 > p->y0)) return LBRS_E_INVAL;
@@ -52,7 +59,10 @@ static int check_params(const lbrs_params* p) {
     }
     for (int s = 0; s < 4; ++s) {
         if (p->bc[s] < LBRS_BC_TRANSMISSIVE || p->bc[s] > LBRS_BC_DIRICHLET) return LBRS_E_INVAL;
-        if (p->bc[s] == LBRS_BC_DIRICHLET && (dim != 2 || !p->dirichlet[s])) return LBRS_E_INVAL;
+        if (p->bc[s] == LBRS_BC_DIRICHLET && !p->dirichlet[s]) return LBRS_E_INVAL;
+        if (p->bc[s] == LBRS_BC_DIRICHLET && dim != 2 && (p->law == LBRS_LAW_EULER || s >= 2))
+            return LBRS_E_INVAL;
+        if (p->bc[s] == LBRS_BC_WALL && p->law == LBRS_LAW_SCALAR) return LBRS_E_INVAL;
         if (p->dirichlet[s] && ((uintptr_t)p->dirichlet[s] & 7u) != 0) return LBRS_E_INVAL;
     }
     if ((p->bc[0] == LBRS_BC_PERIODIC) != (p->bc[1] == LBRS_BC_PERIODIC)) return LBRS_E_INVAL;
@@ -82,6 +92,8 @@ static CellArgs cell_args(const lbrs_ctx* c) {
     a.ny = c->P.ny;
     a.model = c->P.model;
     a.gamma = c->P.gamma;
+    a.law = c->P.law;
+    for (int k = 0; k < 4; ++k) a.sc[k] = c->P.scalar_flux[k];
     return a;
 }
 
@@ -93,8 +105,8 @@ int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes, siz
     int rc = check_params(p);
     if (rc) return rc;
     size_t cells = (size_t)p->nx * (size_t)p->ny;
-    if (f_bytes) *f_bytes = sizeof(double) * (size_t)nq(p->model) * nk(p->model) * cells;
-    if (u_bytes) *u_bytes = sizeof(double) * (size_t)nk(p->model) * cells;
+    if (f_bytes) *f_bytes = sizeof(double) * (size_t)nq(p->model) * nk(p) * cells;
+    if (u_bytes) *u_bytes = sizeof(double) * (size_t)nk(p) * cells;
     if (scratch_bytes) *scratch_bytes = (sizeof(DevState) + 255) / 256 * 256;
     return LBRS_OK;
 }
@@ -103,6 +115,9 @@ int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void
     int rc = check_params(p);
     if (rc) return rc;
     if (!d_W || !d_U || d_W == d_U) return LBRS_E_INVAL;
+    if (p->law == LBRS_LAW_SCALAR)  // the conserved scalar is the primitive one
+        return hip_status(hipMemcpyAsync(d_U, d_W, sizeof(double) * (size_t)p->nx * p->ny,
+                                         hipMemcpyDeviceToDevice, (hipStream_t)hip_stream));
     CellArgs a;
     a.plane = (long long)p->nx * p->ny;
     a.ps = a.plane;
@@ -131,6 +146,7 @@ int lbrs_prim_to_cons_adjoint(const lbrs_params* p, const double* d_W, const dou
     int rc = check_params(p);
     if (rc) return rc;
     if (!d_W || !d_Ubar || !d_Wbar || d_Wbar == d_W || d_Wbar == d_Ubar) return LBRS_E_INVAL;
+    if (p->law != LBRS_LAW_EULER) return LBRS_E_INVAL;
     return hip_status(launch_prim_to_cons_adjoint(cell_args_of(p), d_W, d_Ubar, d_Wbar,
                                                   (hipStream_t)hip_stream));
 }
@@ -139,6 +155,7 @@ int lbrs_isentropic_to_cons(const lbrs_params* p, const double* d_rho, double* d
     int rc = check_params(p);
     if (rc) return rc;
     if (!d_rho || !d_U || d_rho == d_U) return LBRS_E_INVAL;
+    if (p->law != LBRS_LAW_EULER) return LBRS_E_INVAL;
     return hip_status(launch_isentropic_to_cons(cell_args_of(p), d_rho, d_U, (hipStream_t)hip_stream));
 }
 
@@ -147,6 +164,7 @@ int lbrs_isentropic_to_cons_adjoint(const lbrs_params* p, const double* d_rho, c
     int rc = check_params(p);
     if (rc) return rc;
     if (!d_rho || !d_Ubar || !d_rhobar || d_rhobar == d_rho || d_rhobar == d_Ubar) return LBRS_E_INVAL;
+    if (p->law != LBRS_LAW_EULER) return LBRS_E_INVAL;
     return hip_status(launch_isentropic_to_cons_adjoint(cell_args_of(p), d_rho, d_Ubar, d_rhobar,
                                                         (hipStream_t)hip_stream));
 }
@@ -163,7 +181,7 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     if (!c) return LBRS_E_NOMEM;
     c->P = *p;
     c->Q = nq(p->model);
-    c->K = nk(p->model);
+    c->K = nk(p);
     c->dim = p->model == LBRS_D2Q4 ? 2 : 1;
     c->plane = (long long)p->nx * p->ny;
     if (p->layout == LBRS_LAYOUT_ROWS) {
@@ -197,8 +215,11 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     for (int s = 0; s < 4; ++s) dir[s] = p->bc[s] == LBRS_BC_DIRICHLET ? p->dirichlet[s] : nullptr;
     hipError_t e = launch_reset(c->st, c->stream);
     if (e == hipSuccess)
-        e = launch_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl, dir,
-                        c->stream);
+        e = p->law == LBRS_LAW_SCALAR
+                ? launch_scalar_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl,
+                                     dir, c->stream)
+                : launch_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl, dir,
+                              c->stream);
     if (e != hipSuccess) {
         free(c);
         return LBRS_E_HIP;
@@ -286,6 +307,58 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
     return a;
 }
 
+// Scalar laws: the 2D row-marching tiles use the same strip and segment
+// decomposition as the Euler step (no lockstep groups, one march direction).
+static int scalar_blocks_per_cu(const lbrs_ctx* c) {
+    lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
+    int& n = m->sbpc[c->waves_per_block];
+    if (n == 0) n = scalar2d_blocks_per_cu(c->waves_per_block);
+    return n;
+}
+
+static int scalar_max_blocks(const lbrs_ctx* c) { return c->cu_count * scalar_blocks_per_cu(c); }
+
+static ScalarArgs scalar_args(const lbrs_ctx* c, double t_end) {
+    ScalarArgs a;
+    a.f0 = c->f0;
+    a.f1 = c->f1;
+    a.st = c->st;
+    a.ps = c->ps;
+    a.rs = c->rs;
+    a.nx = c->P.nx;
+    a.ny = c->P.ny;
+    a.strip = a.nstrips = a.nseg = a.ntiles = 0;
+    if (c->dim == 2) {
+        const int wpb = c->waves_per_block;
+        a.nstrips = ((c->P.nx + 61) / 62 + wpb - 1) / wpb * wpb;
+        a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
+        long long nseg;
+        if (c->rows_per_tile > 0) {
+            nseg = (c->P.ny + c->rows_per_tile - 1) / c->rows_per_tile;
+        } else {
+            nseg = (long long)c->cu_count * scalar_blocks_per_cu(c) * wpb / a.nstrips;
+            const long long cap = (c->P.ny + 7) / 8;
+            if (nseg > cap) nseg = cap;
+        }
+        if (nseg < 1) nseg = 1;
+        if (nseg > c->P.ny) nseg = c->P.ny;
+        a.nseg = (int)nseg;
+        a.ntiles = a.nstrips * a.nseg;
+    }
+    a.launch = c->launches;
+    a.dx = c->dx;
+    a.cfl = c->P.cfl;
+    a.omega = c->P.omega;
+    a.t_end = t_end;
+    a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
+    for (int s = 0; s < 4; ++s) {
+        a.bc[s] = c->P.bc[s];
+        a.dir[s] = c->P.bc[s] == LBRS_BC_DIRICHLET ? c->P.dirichlet[s] : nullptr;
+        a.sc[s] = c->P.scalar_flux[s];
+    }
+    return a;
+}
+
 static Step1DArgs step1d_args(const lbrs_ctx* c, double t_end, int max_steps) {
     Step1DArgs a;
     a.f0 = c->f0;
@@ -308,6 +381,18 @@ static Step1DArgs step1d_args(const lbrs_ctx* c, double t_end, int max_steps) {
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
     if (!c || max_steps < 0 || isnan(t_end)) return LBRS_E_INVAL;
     if (max_steps == 0) return LBRS_OK;
+    if (c->P.law == LBRS_LAW_SCALAR) {
+        for (int s = 0; s < max_steps; ++s) {
+            ScalarArgs a = scalar_args(c, t_end);
+            hipError_t e = c->dim == 2
+                               ? launch_scalar_step2d(a, c->waves_per_block, scalar_max_blocks(c),
+                                                      c->stream)
+                               : launch_scalar_step1d(a, c->Q, c->stream);
+            if (e != hipSuccess) return LBRS_E_HIP;
+            ++c->launches;
+        }
+        return LBRS_OK;
+    }
     if (c->dim == 2) {
         for (int s = 0; s < max_steps; ++s) {
             Step2DArgs a = step2d_args(c, t_end, nullptr);
@@ -336,6 +421,7 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
 
 int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n) {
     if (!c || !d_Utape_n) return LBRS_E_INVAL;
+    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP) return LBRS_E_STATE;
     if (c->dim != 2 || c->dir) return LBRS_E_STATE;  // the tape serves the periodic adjoint
     Step2DArgs a = step2d_args(c, INFINITY, d_Utape_n);
@@ -364,6 +450,9 @@ int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda, un
 int lbrs_moments(lbrs_ctx* c, double* d_U) {
     if (!c || !d_U) return LBRS_E_INVAL;
     CellArgs a = cell_args(c);
+    if (c->P.law == LBRS_LAW_SCALAR)
+        return hip_status(launch_scalar_moments(a, c->f0, c->f1, c->st, (int)(c->launches & 1), d_U,
+                                                c->stream));
     return hip_status(launch_moments(a, c->f0, c->f1, c->st, (int)(c->launches & 1), d_U, c->stream));
 }
 
@@ -385,7 +474,7 @@ int lbrs_set_f(lbrs_ctx* c, const double* d_f, double t, long long n) {
 int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, double* d_J,
                           double* d_fbar) {
     if (!c || !d_J || !d_fbar) return LBRS_E_INVAL;
-    if (c->dim != 2) return LBRS_E_STATE;
+    if (c->dim != 2 || c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
     if (ix0 < 0 || iy0 < 0 || ix1 > c->P.nx || iy1 > c->P.ny || ix0 > ix1 || iy0 > iy1)
         return LBRS_E_INVAL;
     CellArgs a = cell_args(c);
@@ -396,6 +485,7 @@ int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, doubl
 int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar_next, double* d_fbar) {
     if (!c || !d_Utape_n || !d_fbar_next || !d_fbar || d_fbar == d_fbar_next) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
     for (int s = 0; s < 4; ++s)
         if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
     AdjArgs a;
@@ -413,6 +503,7 @@ int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar
 int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, double* d_Ubar0) {
     if (!c || !d_fbar0 || !d_U0 || !d_Ubar0) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
     AdjArgs a;
     a.plane = c->plane;
     a.ps = c->ps;
@@ -428,6 +519,7 @@ int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, do
 int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ckpt) {
     if (!c || !d_ckpt || nsteps < 1 || segment < 1) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
     const long long fcount = (long long)c->Q * c->K * c->plane;
     const int nckpt = (nsteps + segment - 1) / segment;
     for (int j = 0; j < nckpt; ++j) {
@@ -446,6 +538,7 @@ int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const doubl
         segment < 1)
         return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
     for (int s = 0; s < 4; ++s)
         if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
     // time and step count of the first checkpoint (the state the forward

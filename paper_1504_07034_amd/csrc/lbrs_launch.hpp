@@ -39,12 +39,33 @@ struct Step1DArgs {
     int max_steps;     // persistent kernel only
 };
 
+enum : int { LAW_EULER = 0, LAW_SCALAR = 1 };
+
 struct CellArgs {
     long long plane;   // nx * ny
     long long ps, rs;  // population offset = p*ps + y*rs + x
     int nx, ny;
     int model;         // D1Q2, D1Q3, D2Q4
     double gamma;
+    int law = LAW_EULER;                     // LAW_SCALAR: one conserved scalar u
+    double sc[4] = {0.0, 0.0, 0.0, 0.0};     // g1 = sc0 u + sc1 u^2/2, g2 = sc2 u + sc3 u^2/2
+};
+
+// One step of a scalar law on the D2Q4 lattice (row-marching tiles) or on the
+// D1Q2 / D1Q3 lattice (LDS tiles); the time-state protocol is the Euler step's.
+struct ScalarArgs {
+    double* f0;
+    double* f1;
+    DevState* st;
+    long long ps, rs;       // population offset = p*ps + y*rs + x
+    int nx, ny;
+    int strip, nstrips, nseg, ntiles;  // 2D tiles, as in Step2DArgs
+    long long launch;
+    double dx, cfl, omega, t_end;
+    int lam_mode;
+    int bc[4];
+    const double* dir[4];   // prescribed u along Dirichlet sides ([ny] x-sides, [nx] y-sides)
+    double sc[4];
 };
 
 struct AdjArgs {
@@ -142,6 +163,15 @@ struct Batch2DArgs {
 
 hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
                                hipStream_t s);
+hipError_t launch_scalar_step2d(const ScalarArgs& a, int wpb, int max_blocks, hipStream_t s);
+hipError_t launch_scalar_step1d(const ScalarArgs& a, int q, hipStream_t s);
+int scalar2d_blocks_per_cu(int wpb);
+hipError_t launch_scalar_init(const CellArgs& a, const double* U0, double* f0, DevState* st,
+                              int lam_mode, double lam_user, double cfl,
+                              const double* const dir[4], hipStream_t s);
+hipError_t launch_scalar_bound_f(const CellArgs& a, const double* f, DevState* st, hipStream_t s);
+hipError_t launch_scalar_moments(const CellArgs& a, const double* f0, const double* f1,
+                                 const DevState* st, int slot, double* U, hipStream_t s);
 hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, bool dir,
                          int max_blocks, hipStream_t s);
 int step2d_blocks_per_cu(int wpb, bool alt, bool dir);

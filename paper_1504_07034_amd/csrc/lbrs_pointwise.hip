@@ -434,17 +434,20 @@ hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState
 }
 hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st, const double* ext,
                         double t, long long n, bool per_step, hipStream_t s) {
-    const int Q = nq_of(a.model), K = nk_of(a.model);
+    const int Q = nq_of(a.model), K = a.law == LAW_SCALAR ? 1 : nk_of(a.model);
     long long cnt = (long long)Q * K * a.plane;
     hipLaunchKernelGGL(set_slot0_kernel, dim3(1), dim3(64), 0, s, st, t, n);
     hipLaunchKernelGGL(copy_f_kernel, grid1(cnt, 256), dim3(256), 0, s, cnt, f0, f1, st, 0,
                        const_cast<double*>(ext), 1);
-    if (per_step) hipLaunchKernelGGL(bound_of_f_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, st);
+    if (per_step) {
+        if (a.law == LAW_SCALAR) return launch_scalar_bound_f(a, f0, st, s);
+        hipLaunchKernelGGL(bound_of_f_kernel, grid1(a.plane, 256), dim3(256), 0, s, a, f0, st);
+    }
     return hipGetLastError();
 }
 hipError_t launch_get_f(const CellArgs& a, double* f0, double* f1, const DevState* st, int slot,
                         double* ext, hipStream_t s) {
-    const int Q = nq_of(a.model), K = nk_of(a.model);
+    const int Q = nq_of(a.model), K = a.law == LAW_SCALAR ? 1 : nk_of(a.model);
     long long cnt = (long long)Q * K * a.plane;
     hipLaunchKernelGGL(copy_f_kernel, grid1(cnt, 256), dim3(256), 0, s, cnt, f0, f1, st, slot, ext, 0);
     return hipGetLastError();

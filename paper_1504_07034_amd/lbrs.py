@@ -22,6 +22,7 @@ LBRS_D1Q2, LBRS_D1Q3, LBRS_D2Q4 = 0, 1, 2
 LBRS_BC_TRANSMISSIVE, LBRS_BC_PERIODIC, LBRS_BC_WALL, LBRS_BC_DIRICHLET = 0, 1, 2, 3
 LBRS_LAMBDA_PER_STEP, LBRS_LAMBDA_FROZEN_INIT, LBRS_LAMBDA_USER = 0, 1, 2
 LBRS_LAYOUT_PLANAR, LBRS_LAYOUT_ROWS = 0, 1
+LBRS_LAW_EULER, LBRS_LAW_SCALAR = 0, 1
 
 # Every symbol include/lbrs.h declares (checked by the CPU test-suite).
 EXPORTS = (
@@ -49,6 +50,7 @@ class lbrs_params(ctypes.Structure):
         ("lambda_mode", ctypes.c_int), ("lambda_user", ctypes.c_double),
         ("layout", ctypes.c_int),
         ("dirichlet", ctypes.c_void_p * 4),
+        ("law", ctypes.c_int), ("scalar_flux", ctypes.c_double * 4),
     ]
 
 
@@ -155,8 +157,11 @@ def _stream(stream=None):
 
 def make_params(model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0, cfl=0.5,
                 bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
-                layout=LBRS_LAYOUT_PLANAR, dirichlet=(None, None, None, None)) -> lbrs_params:
-    """dirichlet: per side, a device tensor of conserved states [K][n] (or None)."""
+                layout=LBRS_LAYOUT_PLANAR, dirichlet=(None, None, None, None),
+                law=LBRS_LAW_EULER, scalar_flux=(0.0, 0.0, 0.0, 0.0)) -> lbrs_params:
+    """dirichlet: per side, a device tensor of conserved states [K][n] (or None);
+    law / scalar_flux: the conservation law (scalar: g1 = c0 u + c1 u^2/2,
+    g2 = c2 u + c3 u^2/2)."""
     p = lbrs_params()
     p.model, p.nx, p.ny = int(model), int(nx), int(ny)
     p.x0, p.x1, p.y0, p.y1 = map(float, domain)
@@ -168,6 +173,9 @@ def make_params(model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1
     for s in range(4):
         d = dirichlet[s]
         p.dirichlet[s] = None if d is None else d.data_ptr()
+    p.law = int(law)
+    for k in range(4):
+        p.scalar_flux[k] = float(scalar_flux[k])
     return p
 
 
@@ -286,20 +294,22 @@ class Sim:
 
     def __init__(self, model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0,
                  cfl=0.5, bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
-                 layout=LBRS_LAYOUT_PLANAR, device="cuda", dirichlet_W=(None, None, None, None)):
+                 layout=LBRS_LAYOUT_PLANAR, device="cuda", dirichlet_W=(None, None, None, None),
+                 law=LBRS_LAW_EULER, scalar_flux=(0.0, 0.0, 0.0, 0.0)):
         """dirichlet_W: per side, the prescribed primitive states [K][n] of a
         DIRICHLET side (n = ny for the x-sides, nx for the y-sides), converted
         to conserved states on the device and kept for the context's life."""
         load_library()
         self.layout = layout
         self.device = torch.device(device)
+        self.law = law
         self.dirichlet = tuple(None if d is None else self._side_to_cons(d, gamma)
                                for d in dirichlet_W)
         self.p = make_params(model, nx, ny, domain, gamma, omega, cfl, bc, lambda_mode, lambda_user,
-                             layout, self.dirichlet)
+                             layout, self.dirichlet, law, scalar_flux)
         self.model, self.nx, self.ny = model, nx, ny
         self.Q = {0: 2, 1: 3, 2: 4}[model]
-        self.K = 4 if model == LBRS_D2Q4 else 3
+        self.K = 1 if law == LBRS_LAW_SCALAR else (4 if model == LBRS_D2Q4 else 3)
         fb, ub, sb = lbrs_query_sizes(self.p)
         self.f0 = torch.empty(fb // 8, dtype=torch.float64, device=self.device)
         self.f1 = torch.empty(fb // 8, dtype=torch.float64, device=self.device)
@@ -310,6 +320,8 @@ class Sim:
         """Conserved states of a side's primitive states [4][n] (2D Euler), by
         the library's conversion on a 3-row strip of unit cells."""
         W = torch.as_tensor(Wside, dtype=torch.float64).to(self.device)
+        if self.law == LBRS_LAW_SCALAR:  # u is its own conserved variable
+            return W.reshape(-1).contiguous()
         n = W.shape[1]
         Wg = W[:, None, :].expand(W.shape[0], 3, n).contiguous()
         U = torch.empty_like(Wg)

@@ -39,6 +39,10 @@ def test_query_sizes_and_validation(lib):
     p = lbrs.make_params(lbrs.LBRS_D1Q3, 400)
     f, u, s = lbrs.lbrs_query_sizes(p)
     assert f == 9 * 8 * 400 and u == 3 * 8 * 400
+    p = lbrs.make_params(lbrs.LBRS_D2Q4, 64, 64, law=lbrs.LBRS_LAW_SCALAR, gamma=0.0,
+                         scalar_flux=(0.0, 1.0, 1.0, 0.0))
+    f, u, s = lbrs.lbrs_query_sizes(p)
+    assert f == 4 * 8 * 64 * 64 and u == 8 * 64 * 64
     bad = [
         dict(model=lbrs.LBRS_D1Q3, nx=400, omega=2.0),
         dict(model=lbrs.LBRS_D1Q3, nx=400, omega=0.0),
@@ -54,7 +58,12 @@ def test_query_sizes_and_validation(lib):
         dict(model=7, nx=64),
         dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, bc=(3, 0, 2, 0)),       # Dirichlet without data
         dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, bc=(4, 0, 0, 0)),
-        dict(model=lbrs.LBRS_D1Q3, nx=400, bc=(3, 0, 0, 0)),             # 1D Dirichlet
+        dict(model=lbrs.LBRS_D1Q3, nx=400, bc=(3, 0, 0, 0)),             # 1D Euler Dirichlet
+        dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, bc=(2, 2, 0, 0),         # scalar wall
+             law=lbrs.LBRS_LAW_SCALAR),
+        dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, law=2),
+        dict(model=lbrs.LBRS_D2Q4, nx=64, ny=64, law=lbrs.LBRS_LAW_SCALAR,
+             scalar_flux=(0.0, float("nan"), 0.0, 0.0)),
     ]
     for kw in bad:
         p = lbrs.make_params(**kw)
