@@ -460,6 +460,29 @@ def scalar_laws(n2=8192, n1=1 << 24, steps=200, warmup=20):
     return out
 
 
+def euler_1d_long(n=1 << 24, steps=200, warmup=20):
+    """The Euler shock tube (Sod) on n cells with D1Q3: the one-launch-per-step
+    1D kernel (512-cell LDS tiles), 144 B per lattice update."""
+    import torch
+
+    from paper_1504_07034_amd import lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    w = wl.sod(n, t_end=0.2)
+    sim = lbrs.Sim(w.model, n, 1, domain=w.domain, gamma=w.gamma, omega=w.omega, cfl=w.cfl)
+    sim.init_primitive(w.W)
+    del w
+    sim.step(warmup, 0.2)
+    ms = _time_ms(lambda: sim.step(steps, 0.2)) / steps
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+    sim.close()
+    gbs = 144 * n / (ms * 1e-3) / 1e9
+    return {"workload": "Sod shock tube, D1Q3", "n": n, "ms_per_step": round(ms, 4),
+            "MLUPS": round(n / ms / 1e3, 1), "GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def copy_bandwidth(src, dst, reps=20):
     """Measured copy reference on this GPU: torch's device-to-device copy of
     one population buffer (read + write counted), HIP events."""
@@ -515,7 +538,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
     ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad", "dirichlet",
-                                       "scalar"],
+                                       "scalar", "euler1d"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -536,7 +559,7 @@ def main():
     if args.only:
         fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
               "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
-              "scalar": scalar_laws}[args.only]
+              "scalar": scalar_laws, "euler1d": euler_1d_long}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
@@ -639,6 +662,7 @@ def main():
         stage("slab_4096x512", lambda: slab_step(shape))
         stage("dirichlet_2d", dirichlet_2d)
         stage("scalar_laws", scalar_laws)
+        stage("euler_1d_long", euler_1d_long)
         stage("adjoint_2d", adjoint_2d)
         stage("batched_1d", batched_1d)
         ws = wl.domain_batch(128, seed=0, steps=1000)

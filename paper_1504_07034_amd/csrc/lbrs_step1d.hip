@@ -4,10 +4,10 @@
 // Sec. II.C equilibria and the Jin-Xin wave-speed bound):
 //
 //  * step1d_tile: one launch per step for long domains.  A 256-lane workgroup
-//    owns 254 output cells plus one halo cell on each side; every lane forms
-//    the post-collision populations of its cell, stages them in LDS, and pulls
-//    f_i^{n+1}(x) = f*_i(x - s_i) from its neighbours.  The next step's bound
-//    is reduced from the new moments in the same pass.
+//    owns 512 output cells (two per lane) plus one halo cell on each side; the
+//    lanes form the post-collision populations of those cells, stage them in
+//    LDS, and pull f_i^{n+1}(x) = f*_i(x - s_i) from the neighbours' entries.
+//    The next step's bound is reduced from the new moments in the same pass.
 //
 //  * run1d_persistent: the whole time loop of a domain that fits in one
 //    workgroup's LDS, in one launch.  Populations live in registers; each step
@@ -18,12 +18,13 @@
 
 namespace lbrs {
 
-static constexpr int TILE1D = 254;
+static constexpr int TILE1D = 512;  // output cells per workgroup (2 per lane)
 
 template <int Q>
 __global__ __launch_bounds__(256) void step1d_tile(Step1DArgs a) {
     constexpr int QK = Q * 3;
-    __shared__ double fsl[QK][256];
+    constexpr int E = TILE1D + 2;  // LDS entry e holds cell x0 - 1 + e
+    __shared__ double fsl[QK][E];
     const LaunchSlots ls = slots_for(a.launch);
     DevState* st = a.st;
     const StepCtl c = step_control(st, ls, a.lam_mode, a.dx, a.cfl, a.t_end);
@@ -31,39 +32,54 @@ __global__ __launch_bounds__(256) void step1d_tile(Step1DArgs a) {
     if (!c.active) return;
 
     const int t = threadIdx.x;
-    const int x = blockIdx.x * TILE1D - 1 + t;
-    const int xl = map_index(x, a.nx, a.periodic != 0);
+    const int x0 = blockIdx.x * TILE1D;
     const double* __restrict__ fin = c.cur ? a.f1 : a.f0;
     double* __restrict__ fout = c.cur ? a.f0 : a.f1;
+    const double gm1 = a.gamma - 1.0, c2lam = 1.0 / (2.0 * c.lam);
 
-    double f[QK], U[3], fs[QK];
+    // post-collision values of the tile's cells and its two halo cells
+    constexpr int PASSES = TILE1D / 256 + 1;  // the last pass covers the halo entries
 #pragma unroll
-    for (int p = 0; p < QK; ++p) f[p] = fin[p * a.plane + xl];
-    moments_1d<Q>(f, U);
-    collide_1d<Q>(f, U, a.gamma - 1.0, 1.0 / (2.0 * c.lam), a.omega, fs);
+    for (int k = 0; k < PASSES; ++k) {
+        const int e = t + 256 * k;
+        if (k == PASSES - 1 && e >= E) break;
+        const int xl = map_index(x0 - 1 + e, a.nx, a.periodic != 0);
+        double f[QK], U[3], fs[QK];
 #pragma unroll
-    for (int p = 0; p < QK; ++p) fsl[p][t] = fs[p];
+        for (int p = 0; p < QK; ++p) f[p] = fin[p * a.plane + xl];
+        moments_1d<Q>(f, U);
+        collide_1d<Q>(f, U, gm1, c2lam, a.omega, fs);
+#pragma unroll
+        for (int p = 0; p < QK; ++p) fsl[p][e] = fs[p];
+    }
     __syncthreads();
 
     double lmax = 0.0;
     bool bad = false;
-    if (t >= 1 && t <= TILE1D && x < a.nx) {
-        double g[QK];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            g[0 * 3 + k] = fsl[0 * 3 + k][t + 1];          // s = -1: from x + 1
-            if (Q == 2) {
-                g[1 * 3 + k] = fsl[1 * 3 + k][t - 1];      // s = +1: from x - 1
-            } else {
-                g[1 * 3 + k] = fsl[1 * 3 + k][t];          // rest particle
-                g[2 * 3 + k] = fsl[2 * 3 + k][t - 1];      // s = +1: from x - 1
+    for (int k = 0; k < TILE1D / 256; ++k) {
+        const int j = t + 256 * k;  // output cell x0 + j reads entries j, j+1, j+2
+        const int x = x0 + j;
+        if (x < a.nx) {
+            double g[QK];
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                g[0 * 3 + kk] = fsl[0 * 3 + kk][j + 2];          // s = -1: from x + 1
+                if (Q == 2) {
+                    g[1 * 3 + kk] = fsl[1 * 3 + kk][j];          // s = +1: from x - 1
+                } else {
+                    g[1 * 3 + kk] = fsl[1 * 3 + kk][j + 1];      // rest particle
+                    g[2 * 3 + kk] = fsl[2 * 3 + kk][j];          // s = +1: from x - 1
+                }
             }
-        }
 #pragma unroll
-        for (int p = 0; p < QK; ++p) fout[p * a.plane + x] = g[p];
-        double Un[3];
-        moments_1d<Q>(g, Un);
-        bad = !bound_1d(Un, a.gamma, &lmax);
+            for (int p = 0; p < QK; ++p) fout[p * a.plane + x] = g[p];
+            double Un[3], l;
+            moments_1d<Q>(g, Un);
+            const bool ok = bound_1d(Un, a.gamma, &l);
+            bad |= !ok;
+            lmax = fmax(lmax, l);
+        }
     }
     if (a.lam_mode == LAM_PER_STEP) {
         double wm = wave_max(lmax);
