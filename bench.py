@@ -493,13 +493,14 @@ def copy_bandwidth(src, dst, reps=20):
             "ms": round(ms, 4), "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
-def slab_step(shape, steps=200, warmup=20):
+def slab_step(steps=200, warmup=20):
     """One GPU's share of an eight-way slab decomposition of the 4096^2
     four-quadrant problem: the step on a 4096 x 512 slab through the middle of
-    the domain (own transmissive sides; no halo exchange)."""
+    the domain (own transmissive sides; no halo exchange), launch shape
+    autotuned for the slab."""
     import torch
 
-    from paper_1504_07034_amd import lbrs
+    from paper_1504_07034_amd import autotune, lbrs
     from paper_1504_07034_amd import workloads as wl
 
     n, h, y0 = 4096, 512, 1792
@@ -510,7 +511,10 @@ def slab_step(shape, steps=200, warmup=20):
     U0 = sim.prim_to_cons(W)
     del w, W
     sim.init(U0)
-    sim.set_tile(shape["rows"], shape["wpb"], shape["alt"])
+    sim.step(5, 0.3)
+    best = autotune.tune(sim, 0.3, use_cache=False, rows=(0, 16, 32, 64, 128))
+    sim.init(U0)
+    sim.set_tile(best["rows"], best["wpb"], best["alt"])
     sim.step(warmup, 0.3)
     ms = _time_ms(lambda: sim.step(steps, 0.3)) / steps
     st = sim.state()
@@ -518,7 +522,8 @@ def slab_step(shape, steps=200, warmup=20):
     sim.close()
     cells = n * h
     gbs = BYTES_PER_LUP * cells / (ms * 1e-3) / 1e9
-    return {"nx": n, "ny": h, "ms_per_step": round(ms, 4),
+    return {"nx": n, "ny": h, "tile_rows": best["rows"], "waves_per_block": best["wpb"],
+            "alternate": best["alt"], "ms_per_step": round(ms, 4),
             "MLUPS": round(cells / ms / 1e3, 1), "GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
@@ -538,7 +543,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
     ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad", "dirichlet",
-                                       "scalar", "euler1d"],
+                                       "scalar", "euler1d", "slab"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -559,7 +564,7 @@ def main():
     if args.only:
         fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
               "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
-              "scalar": scalar_laws, "euler1d": euler_1d_long}[args.only]
+              "scalar": scalar_laws, "euler1d": euler_1d_long, "slab": slab_step}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
@@ -659,7 +664,7 @@ def main():
         print(f"bench: {name} done", file=sys.stderr, flush=True)
 
     if not args.no_extras:
-        stage("slab_4096x512", lambda: slab_step(shape))
+        stage("slab_4096x512", slab_step)
         stage("dirichlet_2d", dirichlet_2d)
         stage("scalar_laws", scalar_laws)
         stage("euler_1d_long", euler_1d_long)
