@@ -1,7 +1,8 @@
 /*
  * lbrs.h -- C ABI of the MI355X (gfx950) implementation of the Lattice
  * Boltzmann Relaxation Scheme (LBRS) for the inviscid gamma-law Euler
- * equations: S. V. Raghurama Rao, R. Deshmukh, S. Kotnala, "A Lattice
+ * equations and for scalar laws with quadratic fluxes (Burgers, advection):
+ * S. V. Raghurama Rao, R. Deshmukh, S. Kotnala, "A Lattice
  * Boltzmann Relaxation Scheme for Inviscid Compressible Flows",
  * arXiv 1504.07034.
  *
@@ -18,8 +19,9 @@
  *    lbrs_destroy().  The library allocates only its small host-side context.
  *  * Layouts (C order, x fastest):
  *      U  (conserved)  : K planes [K][ny][nx]; K = 3 in 1D (rho, rho u, rho E),
- *                        K = 4 in 2D (rho, rho u, rho v, rho E)
- *      W  (primitive)  : [K][ny][nx] = (rho, u, p) or (rho, u, v, p)
+ *                        K = 4 in 2D (rho, rho u, rho v, rho E), K = 1 for a
+ *                        scalar law (u)
+ *      W  (primitive)  : [K][ny][nx] = (rho, u, p) or (rho, u, v, p), or u
  *      f  (populations): Q*K planes p = i*K + k, velocity order as in the
  *                        paper: D1Q2 (-,+), D1Q3 (-,0,+),
  *                        D2Q4 (-,-), (+,-), (+,+), (-,+); element (p, y, x) at
@@ -37,9 +39,10 @@
  *    the stream.
  *  * Return codes: LBRS_OK (0) or a negative lbrs_status; lbrs_strerror()
  *    names them.  An invalid argument is rejected before anything is
- *    enqueued.  A non-physical state (rho <= 0, p <= 0 or a non-finite value)
- *    met on the device stops the time loop at that step and is reported by
- *    the next lbrs_get_state() as LBRS_E_NONPHYSICAL with the step index.
+ *    enqueued.  A non-physical state (rho <= 0, p <= 0 or a non-finite value;
+ *    for a scalar law a non-finite value) met on the device stops the time
+ *    loop at that step and is reported by the next lbrs_get_state() as
+ *    LBRS_E_NONPHYSICAL with the step index.
  */
 #ifndef LBRS_H
 #define LBRS_H
@@ -138,13 +141,15 @@ int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes,
                      size_t* scratch_bytes);
 
 /* Primitive -> conserved variables on the device: U = (rho, rho u, [rho v,]
- * rho E) with E = p/(rho(gamma-1)) + |u|^2/2 (Sec. II.C).  d_W and d_U are
- * [K][ny][nx]; they may not alias.  Enqueued on hip_stream (NULL = default). */
+ * rho E) with E = p/(rho(gamma-1)) + |u|^2/2 (Sec. II.C); for a scalar law a
+ * copy (u is conserved).  d_W and d_U are [K][ny][nx]; they may not alias.
+ * Enqueued on hip_stream (NULL = default). */
 int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void* hip_stream);
 
 /* Create a context and set the populations to equilibrium, f^0 = f^eq(U0)
  * (Sec. II.A: the initial data are given to the populations through their
- * equilibria), with the lattice speed lambda*(U0)/cfl (or lambda_user).
+ * equilibria), with the lattice speed lambda*(U0)/cfl (or lambda_user);
+ * lambda*(U0) includes the prescribed states of DIRICHLET sides.
  *   d_U0      [K][ny][nx] conserved initial state (read during this call's
  *             kernels only)
  *   d_f0,d_f1 two population buffers of f_bytes each (ping-pong; borrowed)
@@ -160,7 +165,7 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
  * update; Sec. II.D in 2D; walls Sec. II.E).  Each step reads the lattice
  * speed from the device, forms U, the flux, the equilibria, relaxes, streams
  * one node along every link, applies the side conditions and reduces the next
- * step's lambda*.  A step whose start time is >= t_end, or that follows a
+ * step's lambda* (with the prescribed states of DIRICHLET sides).  A step whose start time is >= t_end, or that follows a
  * non-physical step, does nothing, so the run stops exactly at t_end
  * (PER_STEP mode clips the last dt).  Asynchronous. */
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
