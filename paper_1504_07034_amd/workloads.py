@@ -82,6 +82,24 @@ def sod_dimensional(model: int = D1Q3, omega: float = 1.0, cfl: float = 0.5) -> 
                                                "right": (0.125, 0.0, 1.0e4), "x_interface": 0.0})
 
 
+def steady_shock(n: int = 400, model: int = D1Q3, omega: float = 1.0, t_end: float = 1.0,
+                 mach: float = 2.0, gamma: float = 1.4) -> Workload:
+    """Steady shock (Sec. III, after Zhang and Shu) on [-1, 1], shock at x = 0:
+    pre-shock rho = 1, p = 1, u = M a with M = 2 (the paper gives only the Mach
+    number); post-shock state by the normal-shock relations; transmissive
+    sides."""
+    rhoL, pL = 1.0, 1.0
+    uL = mach * math.sqrt(gamma * pL / rhoL)
+    m2 = mach * mach
+    rhoR = rhoL * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    pR = pL * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    uR = uL * rhoL / rhoR
+    W = _tube(n, (-1.0, 1.0), 0.0, (rhoL, uL, pL), (rhoR, uR, pR), model=model)
+    return Workload("steady_shock", model, n, 1, (-1.0, 1.0, 0.0, 1.0), W, gamma=gamma,
+                    omega=omega, t_end=t_end,
+                    meta={"left": (rhoL, uL, pL), "right": (rhoR, uR, pR)})
+
+
 def steady_contact(n: int = 100, model: int = D1Q3, omega: float = 1.0,
                    t_end: float = 2.0) -> Workload:
     """Stationary contact (Sec. III): rho 1.4 | 1.0, u = 0, p = 1 on [0,1], split at 0.5."""

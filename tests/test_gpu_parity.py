@@ -84,10 +84,23 @@ def test_1d_periodic(omega):
 @pytest.mark.parametrize("model", [wl.D1Q2, wl.D1Q3])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_1d_long_tiled(model, periodic):
-    """5003 cells (beyond the one-workgroup form, ragged against 254-cell tiles)."""
+    """5003 cells (beyond the one-workgroup form, ragged against 512-cell tiles)."""
     w = wl.sod(5003, model=model, omega=1.3, t_end=0.02)
     sides = (1, 1, 0, 0) if periodic else (0, 0, 0, 0)
     _compare(w, t_end=0.02, sides=sides, name=f"1d long m{model} p{periodic}")
+
+
+@pytest.mark.parametrize("model,omega", [(wl.D1Q3, 1.0), (wl.D1Q2, 1.6)])
+def test_steady_shock(model, omega):
+    """The paper's steady shock (M = 2, 400 points on [-1, 1]) to t = 2."""
+    w = wl.steady_shock(400, model=model, omega=omega, t_end=2.0)
+    _compare(w, t_end=w.t_end, name=f"steady shock m{model} w{omega}")
+
+
+def test_steady_shock_long_tiled():
+    """The steady shock on 20011 cells (512-cell tiles, ragged), 600 steps."""
+    w = wl.steady_shock(20011, omega=1.2)
+    _compare(w, max_steps=600, name="steady shock 20011")
 
 
 def _riemann_rect(nx=300, ny=200):

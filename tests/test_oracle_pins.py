@@ -503,3 +503,46 @@ def test_parameter_validation_and_nonphysical():
     Pbad = P1(oracle.D1Q2, n=40, omega=1.9, lam_mode=oracle.LAM_USER, lam_user=0.2)
     r = oracle.run(Pbad, oracle.prim_to_cons(Pbad, wl.sod(40, model=0).W), max_steps=500)
     assert r.status == oracle.NONPHYSICAL and 0 < r.fail_step <= 500
+
+
+# ---------------------------------------------------------------- steady shock
+def test_steady_shock_states_satisfy_rankine_hugoniot():
+    """The steady-shock workload (Sec. III, M = 2 upstream; the pre-shock rho
+    and p are a reading): mass, momentum and energy fluxes are equal across
+    the jump, and the upstream Mach number is 2."""
+    w = wl.steady_shock(400)
+    g = w.gamma
+    (rL, uL, pL), (rR, uR, pR) = w.meta["left"], w.meta["right"]
+    EL = pL / (g - 1) + 0.5 * rL * uL * uL
+    ER = pR / (g - 1) + 0.5 * rR * uR * uR
+    for a, b in [(rL * uL, rR * uR), (rL * uL * uL + pL, rR * uR * uR + pR),
+                 (uL * (EL + pL), uR * (ER + pR))]:
+        assert abs(a - b) <= 1e-14 * abs(a)
+    assert uL / math.sqrt(g * pL / rL) == pytest.approx(2.0, rel=1e-15)
+    assert uR < math.sqrt(g * pR / rR)  # subsonic downstream
+
+
+@pytest.mark.parametrize("model,omega", [(oracle.D1Q3, 1.0), (oracle.D1Q2, 1.6)])
+def test_steady_shock_stays_put(model, omega):
+    """Run to t = 2, 4 and 8: the supersonic upstream state is untouched, the
+    downstream state returns to the Rankine-Hugoniot state once the start-up
+    waves have left, and the shock (density midpoint) stays within three
+    cells of x = 0 -- a wrong jump condition would make it drift."""
+    w = wl.steady_shock(400, model=model, omega=omega)
+    P = oracle.Problem(model=model, nx=400, domain=w.domain, omega=omega, cfl=w.cfl)
+    U0 = oracle.prim_to_cons(P, w.W)
+    x = wl.centres(400, -1.0, 1.0)
+    rL, rR = w.meta["left"][0], w.meta["right"][0]
+    mid = 0.5 * (rL + rR)
+    for T in (2.0, 4.0, 8.0):
+        r = oracle.run(P, U0, t_end=T, record=False)
+        assert r.status == oracle.OK
+        rho = r.U[0, 0]
+        i = int(np.argmax(rho > mid))
+        xs = x[i - 1] + (mid - rho[i - 1]) / (rho[i] - rho[i - 1]) * (x[i] - x[i - 1])
+        assert abs(xs) <= 3 * 2.0 / 400, (T, xs)
+        up, down = x < -0.25, x > 0.25
+        assert np.abs(r.U[:, 0, up] - U0[:, 0, up]).max() <= 1e-8
+        if T >= 4.0:
+            scale = np.abs(U0[:, 0, down]).max(axis=1)[:, None]
+            assert (np.abs(r.U[:, 0, down] - U0[:, 0, down]) / scale).max() <= 1e-4
