@@ -97,6 +97,20 @@ def test_steady_shock(model, omega):
     _compare(w, t_end=w.t_end, name=f"steady shock m{model} w{omega}")
 
 
+@pytest.mark.parametrize("omega", [1.0, 1.7])
+def test_steady_contact(omega):
+    """The paper's steady contact (100 points, t = 2)."""
+    w = wl.steady_contact(100, omega=omega)
+    _compare(w, t_end=2.0, name=f"steady contact w{omega}")
+
+
+def test_paper_riemann2d_400():
+    """The paper's own four-quadrant case at its resolution (400^2), 300 steps
+    (its end time is not given)."""
+    w = wl.riemann2d_paper(400)
+    _compare(w, max_steps=300, name="paper riemann 400")
+
+
 def test_steady_shock_long_tiled():
     """The steady shock on 20011 cells (512-cell tiles, ragged), 600 steps."""
     w = wl.steady_shock(20011, omega=1.2)

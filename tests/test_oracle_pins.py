@@ -381,6 +381,18 @@ def test_riemann2d_diagonal_symmetry():
     assert np.max(np.abs(rE - rE.T)) <= 1e-13
 
 
+def test_paper_riemann2d_diagonal_symmetry():
+    """The paper's own quadrant set (Sec. III, Liska-Wendroff case 4) is
+    symmetric about the diagonal too: the solution keeps it."""
+    w = wl.riemann2d_paper(48)
+    P = P2(n=48)
+    r = oracle.run(P, oracle.prim_to_cons(P, w.W), max_steps=60)
+    rho, m, n, rE = r.U
+    assert np.max(np.abs(rho - rho.T)) <= 1e-13
+    assert np.max(np.abs(m - n.T)) <= 1e-13
+    assert np.max(np.abs(rE - rE.T)) <= 1e-13
+
+
 def test_explosion_d4_symmetry():
     """Explosion (Sec. III): the disc is invariant under x -> -x, y -> -y, x <-> y."""
     w = wl.explosion(40)
