@@ -59,6 +59,7 @@ class _Problem(ctypes.Structure):
         ("adv_x", ctypes.c_double), ("adv_y", ctypes.c_double),
         ("dir", ctypes.POINTER(ctypes.c_double) * 4),
         ("q", ctypes.c_double * 4),
+        ("solid", ctypes.POINTER(ctypes.c_ubyte)),
     ]
 
 
@@ -116,6 +117,9 @@ class Problem:
     dirichlet: tuple = (None, None, None, None)
     # FLUX_QUADRATIC: g1(u) = q0 u + q1 u^2/2, g2(u) = q2 u + q3 u^2/2
     quad: tuple = (0.0, 0.0, 0.0, 0.0)
+    # Solid cells [ny][nx] (nonzero = solid) of a body in a D2Q4 Euler
+    # domain, or None.
+    solid: object = None
 
     @property
     def Q(self) -> int:
@@ -152,6 +156,12 @@ class Problem:
         p._keep = keep  # the arrays live as long as the struct
         for i in range(4):
             p.q[i] = float(self.quad[i])
+        if self.solid is None:
+            p.solid = ctypes.POINTER(ctypes.c_ubyte)()
+        else:
+            m = np.ascontiguousarray(self.solid, dtype=np.uint8).reshape(self.ny, self.nx)
+            keep.append(m)
+            p.solid = m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
         return p
 
 

@@ -40,7 +40,21 @@
 //     at a corner ghost the y-side decides; the prescribed states take part
 //     in the global lambda* maximum like interior cells;
 //   * f^0 = f^eq(U0) with the lattice speed lambda*(U0)/cfl (frozen / user
-//     modes: the fixed speed).
+//     modes: the fixed speed);
+//   * solid bodies (the step, the backward step and the ramp of the Sec. III
+//     test cases, whose geometry the paper does not give) are a mask of solid
+//     cells; the wall runs through the fluid nodes next to the body, as on a
+//     wall side.  A solid cell holds no populations (zero), takes no part in
+//     lambda* and is never checked.  A population whose pull source is solid
+//     takes the same-node specular image that makes the wall's normal flux
+//     vanish (Sec. II.E): across a face (source's x- or y-neighbour solid) the
+//     mirror population with that momentum component negated; in a concave
+//     corner (both neighbours solid) the opposite population with both
+//     components negated (the two images combined); at a convex corner tip
+//     (only the diagonal source solid) the opposite population reflected about
+//     the corner's bisector, which swaps the two momentum components.  Beyond
+//     a wall side every position is solid; elsewhere a position outside the
+//     grid is wrapped (periodic) or clamped onto it and the mask decides.
 //
 // The core is templated on the scalar so that a forward-mode dual number gives
 // exact directional derivatives (the reference for the adjoint).
@@ -79,6 +93,8 @@ struct Problem {
     // (Burgers, Sec. II.A: q = (0, 1, ., .); the 2D Burgers law of Sec. III:
     // q = (0, 1, 1, 0)).
     double q[4];
+    // Solid cells [ny][nx] (nonzero = solid), or null: no body (D2Q4 Euler).
+    const unsigned char* solid;
 };
 
 // ------------------------------------------------------------ dual numbers
@@ -270,6 +286,71 @@ inline bool physical(const Problem& P, const double* U) {
     return p > 0.0 && std::isfinite(p);
 }
 
+// ------------------------------------------------------------ solid bodies
+// Position j along an axis of n cells, brought onto the grid: wrapped on a
+// periodic axis, clamped otherwise.
+inline int onto_grid(int j, int n, bool periodic) {
+    if (j >= 0 && j < n) return j;
+    if (periodic) return ((j % n) + n) % n;
+    return j < 0 ? 0 : n - 1;
+}
+
+inline bool is_solid_cell(const Problem& P, long c) { return P.solid && P.solid[c] != 0; }
+
+// Is the position (xs, ys), possibly outside the grid, solid?  Everything
+// beyond a wall side is; otherwise the mask at the position brought onto the
+// grid decides.
+inline bool solid_at(const Problem& P, int xs, int ys) {
+    if ((ys < 0 && P.side[2] == SIDE_WALL) || (ys >= P.ny && P.side[3] == SIDE_WALL)) return true;
+    if ((xs < 0 && P.side[0] == SIDE_WALL) || (xs >= P.nx && P.side[1] == SIDE_WALL)) return true;
+    if (!P.solid) return false;
+    int x = onto_grid(xs, P.nx, P.side[0] == SIDE_PERIODIC);
+    int y = onto_grid(ys, P.ny, P.side[2] == SIDE_PERIODIC);
+    return P.solid[(long)y * P.nx + x] != 0;
+}
+
+// D2Q4 population whose velocity is that of i with s_x (flipx) and/or s_y
+// (flipy) reversed.
+inline int flipped(int i, bool flipx, bool flipy) {
+    int tx = flipx ? -sx(D2Q4, i) : sx(D2Q4, i);
+    int ty = flipy ? -sy(D2Q4, i) : sy(D2Q4, i);
+    for (int j = 0; j < 4; ++j)
+        if (sx(D2Q4, j) == tx && sy(D2Q4, j) == ty) return j;
+    return -1;
+}
+
+// How population i of the fluid node (x, y) is found when its pull source
+// (x - s_ix, y - s_iy) is solid: the population j of the same node it is
+// imaged from, and the kind of image.
+enum { IMG_FACE_X, IMG_FACE_Y, IMG_CONCAVE, IMG_TIP };
+inline int image_of(const Problem& P, int x, int y, int i, int* kind) {
+    bool bx = solid_at(P, x - sx(D2Q4, i), y);
+    bool by = solid_at(P, x, y - sy(D2Q4, i));
+    if (bx && !by) { *kind = IMG_FACE_X; return flipped(i, true, false); }
+    if (by && !bx) { *kind = IMG_FACE_Y; return flipped(i, false, true); }
+    *kind = bx ? IMG_CONCAVE : IMG_TIP;
+    return flipped(i, true, true);
+}
+
+// A mask is admissible when some cell is fluid and every imaged population's
+// source population is itself pulled from a non-solid position (bodies and
+// gaps at least two cells across).
+inline bool mask_admissible(const Problem& P) {
+    bool any_fluid = false;
+    for (int y = 0; y < P.ny; ++y)
+        for (int x = 0; x < P.nx; ++x) {
+            if (is_solid_cell(P, (long)y * P.nx + x)) continue;
+            any_fluid = true;
+            for (int i = 0; i < 4; ++i) {
+                if (!solid_at(P, x - sx(D2Q4, i), y - sy(D2Q4, i))) continue;
+                int kind;
+                int j = image_of(P, x, y, i, &kind);
+                if (solid_at(P, x - sx(D2Q4, j), y - sy(D2Q4, j))) return false;
+            }
+        }
+    return any_fluid;
+}
+
 // ---------------------------------------------------------- the simulation
 template <class T>
 struct Sim {
@@ -311,6 +392,7 @@ struct Sim {
         double m = 0.0;
         std::vector<double> Uc(K);
         for (long c = 0; c < ncell; ++c) {
+            if (is_solid_cell(P, c)) continue;
             for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
             m = std::max(m, local_lambda(P, Uc.data()));
         }
@@ -326,6 +408,7 @@ struct Sim {
     bool all_physical(long* bad) {
         std::vector<double> Uc(K);
         for (long c = 0; c < ncell; ++c) {
+            if (is_solid_cell(P, c)) continue;
             for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
             if (!physical(P, Uc.data())) {
                 if (bad) *bad = c;
@@ -336,12 +419,13 @@ struct Sim {
     }
 
     // f^0 = f^eq(U0) in every cell (Sec. II.A: the initial data are given to
-    // the populations through their equilibria).
+    // the populations through their equilibria); solid cells hold zeros.
     void init_equilibrium(const T* U0, double lam) {
         std::vector<T> Uc(K), Gx(K), Gy(K);
         for (int y = 0; y < P.ny; ++y)
             for (int x = 0; x < P.nx; ++x) {
                 long c = (long)y * P.nx + x;
+                if (is_solid_cell(P, c)) continue;  // f stays zero
                 for (int k = 0; k < K; ++k) Uc[k] = U0[(size_t)k * ncell + c];
                 flux(P, Uc.data(), Gx.data(), Gy.data());
                 for (int i = 0; i < Q; ++i)
@@ -357,6 +441,7 @@ struct Sim {
         for (int y = 0; y < P.ny; ++y)
             for (int x = 0; x < P.nx; ++x) {
                 long c = (long)y * P.nx + x;
+                if (is_solid_cell(P, c)) continue;  // never pulled from
                 for (int k = 0; k < K; ++k) Uc[k] = U[(size_t)k * ncell + c];
                 flux(P, Uc.data(), Gx.data(), Gy.data());
                 for (int i = 0; i < Q; ++i)
@@ -413,6 +498,10 @@ struct Sim {
     // written as a pull f_i^{n+1}(x) = f*_i(x - s_i), then the walls.  A pull
     // from a Dirichlet ghost cell takes its equilibrium at lattice speed lam.
     void stream(double lam) {
+        if (P.solid) {
+            stream_with_bodies(lam);
+            return;
+        }
         std::vector<double> Ub(K), Gx(K), Gy(K, 0.0);
         for (int i = 0; i < Q; ++i)
             for (int y = 0; y < P.ny; ++y)
@@ -430,6 +519,57 @@ struct Sim {
                         F(f, i, k, x, y) = (xs < 0 || ys < 0) ? T(0.0) : F(fs, i, k, xs, ys);
                 }
         apply_walls();
+    }
+
+    // Streaming with solid bodies (and the wall sides folded into them):
+    // first every population whose source position is not solid is pulled as
+    // in stream(); then each population whose source is solid is set from
+    // the node's own pulled populations by the specular image of its kind.
+    void stream_with_bodies(double lam) {
+        std::vector<double> Ub(K), Gx(K), Gy(K, 0.0);
+        const int kx = 1, ky = 2;  // momentum components
+        for (int y = 0; y < P.ny; ++y)
+            for (int x = 0; x < P.nx; ++x) {
+                bool solid = is_solid_cell(P, (long)y * P.nx + x);
+                for (int i = 0; i < 4; ++i) {
+                    int xsrc = x - sx(P.model, i), ysrc = y - sy(P.model, i);
+                    if (solid || solid_at(P, xsrc, ysrc)) {
+                        for (int k = 0; k < K; ++k) F(f, i, k, x, y) = T(0.0);
+                        continue;
+                    }
+                    if (ghost_state(xsrc, ysrc, Ub.data())) {
+                        flux(P, Ub.data(), Gx.data(), Gy.data());
+                        for (int k = 0; k < K; ++k)
+                            F(f, i, k, x, y) = T(equilibrium(P.model, i, Ub[k], Gx[k], Gy[k], lam));
+                        continue;
+                    }
+                    int xs = source(x, sx(P.model, i), P.nx, P.side[0], P.side[1]);
+                    int ys = source(y, sy(P.model, i), P.ny, P.side[2], P.side[3]);
+                    for (int k = 0; k < K; ++k) F(f, i, k, x, y) = F(fs, i, k, xs, ys);
+                }
+            }
+        for (int y = 0; y < P.ny; ++y)
+            for (int x = 0; x < P.nx; ++x) {
+                if (is_solid_cell(P, (long)y * P.nx + x)) continue;
+                for (int i = 0; i < 4; ++i) {
+                    if (!solid_at(P, x - sx(P.model, i), y - sy(P.model, i))) continue;
+                    int kind;
+                    int j = image_of(P, x, y, i, &kind);
+                    for (int k = 0; k < K; ++k) {
+                        T v = F(f, j, k, x, y);
+                        if (kind == IMG_FACE_X && k == kx) v = -v;
+                        if (kind == IMG_FACE_Y && k == ky) v = -v;
+                        if (kind == IMG_CONCAVE && (k == kx || k == ky)) v = -v;
+                        if (kind == IMG_TIP && (k == kx || k == ky)) {
+                            // reflection about the bisector normal n ~ s_i:
+                            // (m_x, m_y) -> -s_ix s_iy (m_y, m_x)
+                            double c = -double(sx(P.model, i) * sy(P.model, i));
+                            v = c * F(f, j, k == kx ? ky : kx, x, y);
+                        }
+                        F(f, i, k, x, y) = v;
+                    }
+                }
+            }
     }
 
     // Specular reflection at a wall node row/column (Sec. II.E).  The paper
@@ -521,11 +661,12 @@ int validate(const Problem& P) {
     if (ndim(P.model) == 2 && (P.side[2] == SIDE_PERIODIC) != (P.side[3] == SIDE_PERIODIC))
         return ST_INVAL;
     if (ndim(P.model) == 1 && (P.side[0] == SIDE_WALL || P.side[1] == SIDE_WALL)) return ST_INVAL;
-    if (ndim(P.model) == 2) {  // walls meeting at a corner are not defined
+    if (ndim(P.model) == 2 && !P.solid) {  // walls meeting at a corner need the body rules
         bool xw = P.side[0] == SIDE_WALL || P.side[1] == SIDE_WALL;
         bool yw = P.side[2] == SIDE_WALL || P.side[3] == SIDE_WALL;
         if (xw && yw) return ST_INVAL;
     }
+    if (P.solid && (P.model != D2Q4 || scalar_law(P) || !mask_admissible(P))) return ST_INVAL;
     if (P.lam_mode < LAM_PER_STEP || P.lam_mode > LAM_USER) return ST_INVAL;
     if (P.lam_mode == LAM_USER && !(P.lam_user > 0.0)) return ST_INVAL;
     if (P.lam_mode != LAM_USER && !(P.cfl > 0.0 && P.cfl <= 1.0)) return ST_INVAL;
