@@ -70,7 +70,8 @@ enum { LBRS_D1Q2 = 0, LBRS_D1Q3 = 1, LBRS_D2Q4 = 2 };
 /* Side conditions, given per side in the order x-low, x-high, y-low, y-high.
  * WALL is the paper's free-slip wall by specular reflection (Sec. II.E), with
  * the wall on the first/last node row or column; walls on two perpendicular
- * sides (a corner) are rejected.  TRANSMISSIVE (zero gradient of the
+ * sides (a corner) are rejected unless a body mask is given (lbrs_params.solid,
+ * whose corner rules then apply).  TRANSMISSIVE (zero gradient of the
  * post-collision populations) and PERIODIC are not in the paper.  PERIODIC
  * must be set on both sides of an axis.  DIRICHLET prescribes the state
  * beyond a side (the inflow and post-shock top boundaries of the paper's
@@ -132,13 +133,48 @@ typedef struct {
     const double* dirichlet[4];
     int law;              /* LBRS_LAW_EULER (0) or LBRS_LAW_SCALAR (1) */
     double scalar_flux[4];/* SCALAR: c0..c3 of g1(u) = c0 u + c1 u^2/2, g2(u) = c2 u + c3 u^2/2 */
+    /* Solid body (D2Q4 Euler single domains): HOST pointer to nx*ny bytes,
+     * row-major [y][x], nonzero = solid cell; NULL = no body.  Read by
+     * lbrs_init and lbrs_body_codes only.  The Sec. III cases with a body
+     * (forward-facing step, backward-facing step of the shock diffraction,
+     * ramp) do not give the geometry: it is the caller's mask.  The wall runs
+     * through the fluid nodes next to the body, as on a WALL side: a
+     * population whose pull source is solid takes the same-node specular
+     * image that cancels the normal flux (the Sec. II.E rule) -- across a face
+     * (the source's x- or y-neighbour solid) the mirror population with that
+     * momentum component negated, in a concave corner (both neighbours solid)
+     * the opposite population with both negated, at a convex corner tip (only
+     * the diagonal source solid) the opposite population reflected about the
+     * corner's bisector (momentum components swapped, times -s_x s_y).
+     * Beyond a WALL side every position is solid; elsewhere positions outside
+     * the grid are wrapped or clamped onto it and the mask decides.  With a
+     * body, WALL sides may meet at corners.  Solid cells hold zero
+     * populations, read U = 0 and take no part in lambda* or the
+     * admissibility check (their U0 is ignored).  A mask whose image
+     * populations would themselves come from solid positions (a fluid gap one
+     * cell wide) or with no fluid cell is rejected (LBRS_E_INVAL at
+     * lbrs_init).  Body contexts march one way (lbrs_set_tile's alternate must
+     * be 0) and have no gradient calls (LBRS_E_STATE). */
+    const unsigned char* solid;
 } lbrs_params;
 
 /* Sizes in bytes of one population buffer (f0 or f1), of one conserved-state
- * buffer (U, K planes) and of the device scratch area lbrs_init needs.
+ * buffer (U, K planes) and of the device scratch area lbrs_init needs (with a
+ * body it also holds the 2-byte node codes, nx*ny of them).
  * Any output pointer may be NULL.  Returns LBRS_E_INVAL for invalid params. */
 int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes,
                      size_t* scratch_bytes);
+
+/* Node codes of p->solid, computed on the host (no GPU needed), as lbrs_init
+ * stores them for the step kernel: h_codes receives nx*ny uint16 values,
+ * [y][x]; bits 3i..3i+2 give the rule of population i (D2Q4 order
+ * (-,-), (+,-), (+,+), (-,+)) -- 0 pulled, 1 face image across x (population
+ * with s_x reversed, x-momentum negated), 2 face image across y, 3 concave
+ * corner (opposite population, both momenta negated), 4 convex corner tip
+ * (opposite population, momenta swapped times -s_x s_y) -- and bit 15 marks a
+ * solid cell.  Returns LBRS_E_INVAL for invalid params, a NULL p->solid or an
+ * inadmissible body. */
+int lbrs_body_codes(const lbrs_params* p, unsigned short* h_codes);
 
 /* Primitive -> conserved variables on the device: U = (rho, rho u, [rho v,]
  * rho E) with E = p/(rho(gamma-1)) + |u|^2/2 (Sec. II.C); for a scalar law a

@@ -3,12 +3,13 @@
 Candidates are (rows_per_tile, waves_per_block, alternate) triples;
 rows_per_tile = 0 is the library's automatic choice (one balanced round of the
 resident waves), alternate = 1 marches odd row segments upwards (same results,
-different memory order).
+different memory order; a domain with a solid body marches one way only).
 Each candidate is timed with HIP events over a few steps that start from the
 same checkpoint of the populations (lbrs_get_f / lbrs_set_f), so tuning does
 not advance the caller's solution; the fastest few are timed again over four
 times as many steps before one is chosen.  The best shape is applied to the context
-and cached per (device, model, nx, ny, side conditions) in a JSON file.
+and cached per (device, model, nx, ny, side conditions, body or not) in a
+JSON file.
 """
 from __future__ import annotations
 
@@ -30,7 +31,8 @@ DEFAULT_ALT = (0, 1)
 def _key(sim: "lbrs.Sim") -> str:
     p = sim.p
     name = torch.cuda.get_device_name(sim.device)
-    return f"{name}|m{p.model}|{p.nx}x{p.ny}|bc{tuple(p.bc)}|v2"
+    body = "|body" if getattr(sim, "body", False) else ""
+    return f"{name}|m{p.model}|{p.nx}x{p.ny}|bc{tuple(p.bc)}{body}|v2"
 
 
 def _load_cache() -> dict:
@@ -73,10 +75,12 @@ def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=DEF
          verbose: bool = False, confirm: int = 4) -> dict:
     """Pick and apply the fastest 2D launch shape for `sim` (already initialised)."""
     key = _key(sim)
+    if getattr(sim, "body", False):
+        alts = (0,)
     cache = _load_cache() if use_cache else {}
     if use_cache and key in cache:
         best = cache[key]
-        sim.set_tile(best["rows"], best["wpb"], best.get("alt", 1))
+        sim.set_tile(best["rows"], best["wpb"], best.get("alt"))
         return best
     st = sim.state()
     f0 = sim.get_f()

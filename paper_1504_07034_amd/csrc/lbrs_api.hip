@@ -30,6 +30,7 @@ struct lbrs_ctx {
     int bpc[2][2][17];   // resident step-kernel workgroups per CU, by (alternate, dirichlet, waves)
     bool dir;            // some side is DIRICHLET
     int sbpc[17];        // resident scalar-step workgroups per CU, by waves per block
+    unsigned short* codes;  // body node codes in the scratch area (null: no body)
 };
 
 static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
@@ -69,11 +70,12 @@ static int check_params(const lbrs_params* p) {
     if (dim == 2 && (p->bc[2] == LBRS_BC_PERIODIC) != (p->bc[3] == LBRS_BC_PERIODIC))
         return LBRS_E_INVAL;
     if (dim == 1 && (p->bc[0] == LBRS_BC_WALL || p->bc[1] == LBRS_BC_WALL)) return LBRS_E_INVAL;
-    if (dim == 2) {
+    if (dim == 2 && !p->solid) {  // wall corners take the body rules
         bool xw = p->bc[0] == LBRS_BC_WALL || p->bc[1] == LBRS_BC_WALL;
         bool yw = p->bc[2] == LBRS_BC_WALL || p->bc[3] == LBRS_BC_WALL;
         if (xw && yw) return LBRS_E_INVAL;
     }
+    if (p->solid && (dim != 2 || p->law != LBRS_LAW_EULER)) return LBRS_E_INVAL;
     if (p->lambda_mode < LBRS_LAMBDA_PER_STEP || p->lambda_mode > LBRS_LAMBDA_USER)
         return LBRS_E_INVAL;
     if (p->lambda_mode == LBRS_LAMBDA_USER && !(p->lambda_user > 0.0 && isfinite(p->lambda_user)))
@@ -94,10 +96,68 @@ static CellArgs cell_args(const lbrs_ctx* c) {
     a.gamma = c->P.gamma;
     a.law = c->P.law;
     for (int k = 0; k < 4; ++k) a.sc[k] = c->P.scalar_flux[k];
+    a.code = c->codes;
     return a;
 }
 
 static int hip_status(hipError_t e) { return e == hipSuccess ? LBRS_OK : LBRS_E_HIP; }
+
+// ------------------------------------------------------------ body codes
+// The D2Q4 sign patterns in the library's population order.
+static const int kSx[4] = {-1, +1, +1, -1};
+static const int kSy[4] = {-1, -1, +1, +1};
+
+// Solid test of a position that may lie outside the grid: beyond a WALL side
+// always; else the mask at the position wrapped (periodic axis) or clamped.
+static bool solid_pos(const lbrs_params* p, int x, int y) {
+    const int nx = p->nx, ny = p->ny;
+    if (x < 0 && p->bc[0] == LBRS_BC_WALL) return true;
+    if (x >= nx && p->bc[1] == LBRS_BC_WALL) return true;
+    if (y < 0 && p->bc[2] == LBRS_BC_WALL) return true;
+    if (y >= ny && p->bc[3] == LBRS_BC_WALL) return true;
+    if (x < 0 || x >= nx)
+        x = p->bc[0] == LBRS_BC_PERIODIC ? ((x % nx) + nx) % nx : (x < 0 ? 0 : nx - 1);
+    if (y < 0 || y >= ny)
+        y = p->bc[2] == LBRS_BC_PERIODIC ? ((y % ny) + ny) % ny : (y < 0 ? 0 : ny - 1);
+    return p->solid[(size_t)y * nx + x] != 0;
+}
+
+// Node codes (see IMG_* in the launch header).  For population i of a fluid
+// node whose pull source (x - s_ix, y - s_iy) is solid, the rule follows from
+// the source's two axis neighbours (x - s_ix, y) and (x, y - s_iy); the image
+// source population must itself be pulled from a non-solid position.
+static int build_body_codes(const lbrs_params* p, unsigned short* codes) {
+    const int nx = p->nx, ny = p->ny;
+    bool any_fluid = false;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t c = (size_t)y * nx + x;
+            if (p->solid[c]) {
+                codes[c] = (unsigned short)CODE_SOLID;
+                continue;
+            }
+            any_fluid = true;
+            unsigned code = 0;
+            for (int i = 0; i < 4; ++i) {
+                if (!solid_pos(p, x - kSx[i], y - kSy[i])) continue;
+                const bool bx = solid_pos(p, x - kSx[i], y);
+                const bool by = solid_pos(p, x, y - kSy[i]);
+                unsigned rule;
+                int j;
+                if (bx && by) { rule = IMG_CONCAVE; j = i ^ 2; }
+                else if (bx) { rule = IMG_FACE_X; j = i ^ 1; }
+                else if (by) { rule = IMG_FACE_Y; j = 3 - i; }
+                else { rule = IMG_TIP; j = i ^ 2; }
+                if (solid_pos(p, x - kSx[j], y - kSy[j])) return LBRS_E_INVAL;
+                code |= rule << (3 * i);
+            }
+            codes[c] = (unsigned short)code;
+        }
+    return any_fluid ? LBRS_OK : LBRS_E_INVAL;
+}
+
+// Byte offset of the body codes in the scratch area.
+static size_t codes_offset() { return (sizeof(DevState) + 255) / 256 * 256; }
 
 extern "C" {
 
@@ -107,8 +167,16 @@ int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes, siz
     size_t cells = (size_t)p->nx * (size_t)p->ny;
     if (f_bytes) *f_bytes = sizeof(double) * (size_t)nq(p->model) * nk(p) * cells;
     if (u_bytes) *u_bytes = sizeof(double) * (size_t)nk(p) * cells;
-    if (scratch_bytes) *scratch_bytes = (sizeof(DevState) + 255) / 256 * 256;
+    if (scratch_bytes)
+        *scratch_bytes = codes_offset() + (p->solid ? (2 * cells + 255) / 256 * 256 : 0);
     return LBRS_OK;
+}
+
+int lbrs_body_codes(const lbrs_params* p, unsigned short* h_codes) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!p->solid || !h_codes) return LBRS_E_INVAL;
+    return build_body_codes(p, h_codes);
 }
 
 int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void* hip_stream) {
@@ -199,9 +267,35 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     c->launches = 0;
     c->rows_per_tile = 0;
     c->waves_per_block = 4;
-    c->alternate = 1;
+    c->alternate = p->solid ? 0 : 1;
     c->dir = false;
     for (int s = 0; s < 4; ++s) c->dir = c->dir || p->bc[s] == LBRS_BC_DIRICHLET;
+    c->codes = nullptr;
+    c->P.solid = nullptr;  // the host mask is not kept
+    if (p->solid) {
+        // node codes, built here and copied into the scratch area behind the
+        // time state (the copy completes before this call returns)
+        const size_t n = (size_t)p->nx * p->ny;
+        unsigned short* h = (unsigned short*)malloc(2 * n);
+        if (!h) {
+            free(c);
+            return LBRS_E_NOMEM;
+        }
+        rc = build_body_codes(p, h);
+        if (rc) {
+            free(h);
+            free(c);
+            return rc;
+        }
+        c->codes = (unsigned short*)((char*)d_scratch + codes_offset());
+        hipError_t e = hipMemcpyAsync(c->codes, h, 2 * n, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        free(h);
+        if (e != hipSuccess) {
+            free(c);
+            return LBRS_E_HIP;
+        }
+    }
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -233,6 +327,7 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
     if (rows_per_tile != 0 && (rows_per_tile < 1 || rows_per_tile > 65536)) return LBRS_E_INVAL;
     if (!step2d_wpb_supported(waves_per_block)) return LBRS_E_INVAL;
     if (alternate != 0 && alternate != 1) return LBRS_E_INVAL;
+    if (alternate && c->codes) return LBRS_E_STATE;  // body kernels march one way
     c->rows_per_tile = rows_per_tile;
     c->waves_per_block = waves_per_block;
     c->alternate = alternate;
@@ -251,7 +346,7 @@ static int blocks_per_cu(const lbrs_ctx* c) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
     int w = c->waves_per_block;
     int& n = m->bpc[c->alternate][c->dir ? 1 : 0][w];
-    if (n == 0) n = step2d_blocks_per_cu(w, c->alternate != 0, c->dir);
+    if (n == 0) n = step2d_blocks_per_cu(w, c->alternate != 0, c->dir, c->codes != nullptr);
     return n;
 }
 
@@ -304,6 +399,7 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
         a.bc[s] = c->P.bc[s];
         a.dir[s] = c->P.bc[s] == LBRS_BC_DIRICHLET ? c->P.dirichlet[s] : nullptr;
     }
+    a.code = c->codes;
     return a;
 }
 
@@ -423,7 +519,7 @@ int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n) {
     if (!c || !d_Utape_n) return LBRS_E_INVAL;
     if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP) return LBRS_E_STATE;
-    if (c->dim != 2 || c->dir) return LBRS_E_STATE;  // the tape serves the periodic adjoint
+    if (c->dim != 2 || c->dir || c->codes) return LBRS_E_STATE;  // the tape serves the periodic adjoint
     Step2DArgs a = step2d_args(c, INFINITY, d_Utape_n);
     hipError_t e = launch_step2d(a, c->waves_per_block, true, c->alternate != 0, false,
                                  step2d_max_blocks(c), c->stream);
@@ -485,7 +581,7 @@ int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, doubl
 int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar_next, double* d_fbar) {
     if (!c || !d_Utape_n || !d_fbar_next || !d_fbar || d_fbar == d_fbar_next) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
-    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER || c->codes) return LBRS_E_STATE;
     for (int s = 0; s < 4; ++s)
         if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
     AdjArgs a;
@@ -503,7 +599,7 @@ int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar
 int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, double* d_Ubar0) {
     if (!c || !d_fbar0 || !d_U0 || !d_Ubar0) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
-    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER || c->codes) return LBRS_E_STATE;
     AdjArgs a;
     a.plane = c->plane;
     a.ps = c->ps;
@@ -519,7 +615,7 @@ int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, do
 int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ckpt) {
     if (!c || !d_ckpt || nsteps < 1 || segment < 1) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
-    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER || c->codes) return LBRS_E_STATE;
     const long long fcount = (long long)c->Q * c->K * c->plane;
     const int nckpt = (nsteps + segment - 1) / segment;
     for (int j = 0; j < nckpt; ++j) {
@@ -538,7 +634,7 @@ int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const doubl
         segment < 1)
         return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
-    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER || c->codes) return LBRS_E_STATE;
     for (int s = 0; s < 4; ++s)
         if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
     // time and step count of the first checkpoint (the state the forward

@@ -222,7 +222,7 @@ size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 static inline unsigned grid_cells(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 int b2_check(const lbrs_params* p) {
-    if (p->model != LBRS_D2Q4 || p->law != LBRS_LAW_EULER || p->nx < 3 || p->ny < 3)
+    if (p->model != LBRS_D2Q4 || p->law != LBRS_LAW_EULER || p->solid || p->nx < 3 || p->ny < 3)
         return LBRS_E_INVAL;
     if (!(p->x1 > p->x0) || !(p->y1 > p->y0) || !(p->gamma > 1.0)) return LBRS_E_INVAL;
     if (!(p->omega > 0.0 && p->omega < 2.0)) return LBRS_E_INVAL;

@@ -48,7 +48,7 @@ struct Plan {
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 int check_unit(const lbrs_params* p, int model) {
-    if (p->model != model || p->law != LBRS_LAW_EULER) return LBRS_E_INVAL;
+    if (p->model != model || p->law != LBRS_LAW_EULER || p->solid) return LBRS_E_INVAL;
     if (p->model == LBRS_D2Q4 || p->nx < 3 || p->ny != 1) return LBRS_E_INVAL;
     if (!(p->x1 > p->x0) || !(p->gamma > 1.0) || !(p->omega > 0.0 && p->omega < 2.0)) return LBRS_E_INVAL;
     if (p->bc[0] == LBRS_BC_WALL || p->bc[1] == LBRS_BC_WALL) return LBRS_E_INVAL;

@@ -24,6 +24,19 @@ struct Step2DArgs {
     int lam_mode;
     int bc[4];
     const double* dir[4]; // Dirichlet states per side, [4][n] conserved (or null)
+    const unsigned short* code;  // node codes of a solid body [ny][nx] (or null)
+};
+
+// Node codes of a solid body: per population i (0..3, the D2Q4 order) a
+// 3-bit rule in bits 3i..3i+2 for a population whose pull source is solid,
+// and the solid-cell bit.
+enum : unsigned {
+    IMG_PULL = 0u,     // pulled as usual
+    IMG_FACE_X = 1u,   // population i^1 (s_x reversed), x-momentum negated
+    IMG_FACE_Y = 2u,   // population 3-i (s_y reversed), y-momentum negated
+    IMG_CONCAVE = 3u,  // population i^2 (opposite), both momenta negated
+    IMG_TIP = 4u,      // population i^2, momenta swapped times -s_ix s_iy
+    CODE_SOLID = 0x8000u
 };
 
 struct Step1DArgs {
@@ -49,6 +62,7 @@ struct CellArgs {
     double gamma;
     int law = LAW_EULER;                     // LAW_SCALAR: one conserved scalar u
     double sc[4] = {0.0, 0.0, 0.0, 0.0};     // g1 = sc0 u + sc1 u^2/2, g2 = sc2 u + sc3 u^2/2
+    const unsigned short* code = nullptr;    // body node codes (solid cells are skipped)
 };
 
 // One step of a scalar law on the D2Q4 lattice (row-marching tiles) or on the
@@ -172,9 +186,10 @@ hipError_t launch_scalar_init(const CellArgs& a, const double* U0, double* f0, D
 hipError_t launch_scalar_bound_f(const CellArgs& a, const double* f, DevState* st, hipStream_t s);
 hipError_t launch_scalar_moments(const CellArgs& a, const double* f0, const double* f1,
                                  const DevState* st, int slot, double* U, hipStream_t s);
+// The body kernels (a.code set) march one direction and have no tape.
 hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, bool dir,
                          int max_blocks, hipStream_t s);
-int step2d_blocks_per_cu(int wpb, bool alt, bool dir);
+int step2d_blocks_per_cu(int wpb, bool alt, bool dir, bool body = false);
 bool step2d_wpb_supported(int wpb);
 hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
 hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);

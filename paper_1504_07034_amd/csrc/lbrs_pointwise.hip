@@ -109,12 +109,18 @@ __device__ inline bool cell_bound(int model, const double* U, double gamma, doub
     return model == D2Q4 ? bound_d2q4(U, gamma, l) : bound_1d(U, gamma, l);
 }
 
+// Is cell c solid (a body's codes are given and mark it)?
+__device__ inline bool solid_cell(const CellArgs& a, long long c) {
+    return a.code && (a.code[c] & CODE_SOLID);
+}
+
 // lambda*(U0) -> st->lam_init; a non-physical U0 sets the status (step 0).
+// Solid cells take no part.
 __global__ void bound_of_U_kernel(CellArgs a, const double* __restrict__ U, DevState* st) {
     long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double l = 0.0;
     bool bad = false;
-    if (c < a.plane) {
+    if (c < a.plane && !solid_cell(a, c)) {
         const int K = nk_of(a.model);
         double Uc[4];
         for (int k = 0; k < K; ++k) Uc[k] = U[k * a.plane + c];
@@ -166,7 +172,8 @@ __global__ void dirichlet_bound_kernel(CellArgs a, DirSides ds, DevState* st) {
 }
 
 // f^0 = f^eq(U0) at the lattice speed lambda*(U0)/cfl (or the user's), then
-// lambda*_0 from U^0 = sum_i f^0_i into reduction slot 0.
+// lambda*_0 from U^0 = sum_i f^0_i into reduction slot 0.  Solid cells of a
+// body hold zeros and take no part in the bound.
 __global__ void init_eq_kernel(CellArgs a, const double* __restrict__ U0, double* __restrict__ f,
                                DevState* st, int lam_mode, double lam_user, double cfl) {
     long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -189,10 +196,12 @@ __global__ void init_eq_kernel(CellArgs a, const double* __restrict__ U0, double
             for (int p = 0; p < 16; ++p) z[p] = 0.0;
             Euler2 e = euler2(U, a.gamma - 1.0);
             collide_d2q4(z, U, e, 1.0 / (4.0 * lam0), 1.0, fs);
-            for (int p = 0; p < 16; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = fs[p];
+            const bool solid = solid_cell(a, c);
+            for (int p = 0; p < 16; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = solid ? 0.0 : fs[p];
             double Un[4];
             moments_d2q4(fs, Un);
             bound_d2q4(Un, a.gamma, &l);
+            if (solid) l = 0.0;
         } else {
             double U[3], z[9], fs[9];
             for (int k = 0; k < 3; ++k) U[k] = U0[k * P + c];
@@ -214,12 +223,13 @@ __global__ void init_eq_kernel(CellArgs a, const double* __restrict__ U0, double
     if ((threadIdx.x & 63) == 0) publish_max(&st->lam[0], wm);
 }
 
-// lambda* of given populations into reduction slot 0 (after lbrs_set_f).
+// lambda* of given populations into reduction slot 0 (after lbrs_set_f);
+// solid cells take no part.
 __global__ void bound_of_f_kernel(CellArgs a, const double* __restrict__ f, DevState* st) {
     long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double l = 0.0;
     bool bad = false;
-    if (c < a.plane) {
+    if (c < a.plane && !solid_cell(a, c)) {
         const int Q = nq_of(a.model), K = nk_of(a.model);
         double Uc[4] = {0.0, 0.0, 0.0, 0.0};
         double fc[16];

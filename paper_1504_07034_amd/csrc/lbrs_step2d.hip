@@ -38,6 +38,17 @@
 // so the cache lines two strips share are fetched once, while both waves need
 // them.  The host makes the strip count a multiple of the waves per workgroup,
 // so every wave of a workgroup runs the same number of rows and tiles.
+//
+// Solid bodies (BODY kernels).  A 16-bit code per node, built on the host,
+// says for each population of the node whether its pull source is solid and
+// which same-node specular image replaces it (Sec. II.E free-slip principle;
+// faces, concave corners and convex corner tips), and marks solid cells.  The
+// images only need the node's own freshly streamed populations, so they are
+// a register select after the hops; the code of a row is loaded one row ahead
+// of its use, ahead of the next row's populations.  Solid cells are written
+// as zeros and left out of lambda* and the admissibility check; their
+// collision (a division by zero) only feeds values that the images discard.
+// Wall sides are folded into the codes, and BODY kernels march one way.
 #include "lbrs_launch.hpp"
 #include "lbrs_rowops.hpp"
 
@@ -71,6 +82,7 @@ struct TileGeom {
     int bc[4];
     const double* dir[4];  // Dirichlet states per side ([4][ny] x-sides, [4][nx] y-sides)
     bool any_dir;
+    const unsigned short* code;  // body node codes [ny][nx] (BODY kernels)
 };
 
 // How a tile's march sees memory.  Odd row segments are marched through the
@@ -127,6 +139,36 @@ __device__ __forceinline__ void dirichlet_ghosts(const TileGeom& g, const MarchV
     for (int p = 0; p < 16; ++p) fs[p] = ghost ? fq[p] : fs[p];
 }
 
+// Populations of a node whose pull sources are solid, from the node's own
+// streamed populations go[i*4+k] by the rules of code cd (a solid cell: all
+// zero).  The image sources are never imaged themselves (the host rejects
+// bodies where they would be), so the selects may read go as it is updated.
+__device__ __forceinline__ void body_images(unsigned cd, double go[16]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const unsigned r = (cd >> (3 * i)) & 7u;
+        const int ix = i ^ 1, iy = 3 - i, io = i ^ 2;
+        const double c = (i & 1) ? 1.0 : -1.0;  // -s_ix s_iy
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double fx = (k == 1 ? -1.0 : 1.0) * go[ix * 4 + k];
+            const double fy = (k == 2 ? -1.0 : 1.0) * go[iy * 4 + k];
+            const double fc = (k == 1 || k == 2 ? -1.0 : 1.0) * go[io * 4 + k];
+            const double ft = k == 1 ? c * go[io * 4 + 2] : (k == 2 ? c * go[io * 4 + 1] : go[io * 4 + k]);
+            double v = go[i * 4 + k];
+            v = r == IMG_FACE_X ? fx : v;
+            v = r == IMG_FACE_Y ? fy : v;
+            v = r == IMG_CONCAVE ? fc : v;
+            v = r == IMG_TIP ? ft : v;
+            go[i * 4 + k] = v;
+        }
+    }
+    if (cd & CODE_SOLID) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) go[p] = 0.0;
+    }
+}
+
 // The 16 populations of march row j at column xl (a wave-uniform row base
 // plus the lane's column, so that the loads take a scalar base address).
 __device__ inline void load_view(double v[16], const double* __restrict__ fin, const MarchView& m,
@@ -144,7 +186,7 @@ __device__ inline void load_view(double v[16], const double* __restrict__ fin, c
 // Rows y0..y1-1 (march coordinates) of one strip: lanes 1..g.strip are output
 // columns, lanes 0 and g.strip+1 its halo columns.  Accumulates the lane's
 // bound of the new state and its admissibility.
-template <bool TAPE, int WPB, bool DIR>
+template <bool TAPE, int WPB, bool DIR, bool BODY>
 __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m, int strip, int y0,
                                            int y1, int lane, double& lmax, bool& bad) {
     const int nx = g.nx, ny = g.ny;
@@ -176,8 +218,10 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
 
     // prologue: rows y0-1 and y0 fill the two-row pipeline (no output)
     double f[16], nxt[16];
+    unsigned ccur = 0, cnext = 0;  // body codes of this and the next output row
     load_view(f, fin, m, ps, map_index(y0 - 1, ny, py), xl);
     load_view(nxt, fin, m, ps, map_index(y0, ny, py), xl);
+    if (BODY) ccur = g.code[(long long)y0 * nx + xl];
     collide_row(f, y0 - 1);
     double A3[4], A4[4], B3[4], B4[4];
 #pragma unroll
@@ -210,6 +254,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
         if (WPB > 1) __builtin_amdgcn_s_barrier();
 #pragma unroll
         for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+        if (BODY) cnext = g.code[(long long)map_index(r, ny, py) * nx + xl];
         load_view(nxt, fin, m, ps, map_index(r + 1, ny, py), xl);
         collide_row(f, r);
         if (TAPE) {
@@ -231,8 +276,15 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
         }
         // specular reflection at wall node rows/columns: the incoming
         // populations mirror the outgoing ones, normal momentum negated
-        const bool wall_top = m.bc_hi == BC_WALL && o == ny - 1;
-        const bool wall_bot = m.bc_lo == BC_WALL && o == 0;
+        // (with a body the codes hold the walls)
+        const bool wall_top = !BODY && m.bc_hi == BC_WALL && o == ny - 1;
+        const bool wall_bot = !BODY && m.bc_lo == BC_WALL && o == 0;
+        bool fluid = true;
+        if (BODY) {
+            if (__any(ccur != 0)) body_images(ccur, go);
+            fluid = (ccur & CODE_SOLID) == 0;
+            ccur = cnext;
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double sy = (k == 2) ? -1.0 : 1.0, sx = (k == 1) ? -1.0 : 1.0;
@@ -244,11 +296,11 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
                 go[3 * 4 + k] = sy * go[0 * 4 + k];
                 go[2 * 4 + k] = sy * go[1 * 4 + k];
             }
-            if (wall_xlo) {
+            if (!BODY && wall_xlo) {
                 go[1 * 4 + k] = sx * go[0 * 4 + k];
                 go[2 * 4 + k] = sx * go[3 * 4 + k];
             }
-            if (wall_xhi) {
+            if (!BODY && wall_xhi) {
                 go[0 * 4 + k] = sx * go[1 * 4 + k];
                 go[3 * 4 + k] = sx * go[2 * 4 + k];
             }
@@ -263,8 +315,8 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
         double Un[4], l;
         moments_d2q4(go, Un);
         const bool ok = bound_d2q4(Un, g.gamma, &l);
-        bad |= out_lane && !ok;
-        lmax = fmax(lmax, out_lane ? l : 0.0);
+        bad |= out_lane && fluid && !ok;
+        lmax = fmax(lmax, out_lane && fluid ? l : 0.0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             B3[k] = A3[k];
@@ -279,7 +331,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, const MarchView& m
 // ALT, odd segments are marched through the mirrored view, so that they run
 // upwards in memory while even ones run downwards; without it every segment
 // runs downwards (the view is then a compile-time identity).
-template <bool TAPE, int WPB, bool ALT, bool DIR>
+template <bool TAPE, int WPB, bool ALT, bool DIR, bool BODY>
 __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane, double& lmax,
                                           bool& bad) {
     const int strip = tile % g.nstrips;
@@ -318,11 +370,12 @@ __device__ __forceinline__ void step_tile(const TileGeom& g, int tile, int lane,
         m.dhi = g.dir[3];
         m.mirror = false;
     }
-    march_tile<TAPE, WPB, DIR>(g, m, strip, y0, y1, lane, lmax, bad);
+    march_tile<TAPE, WPB, DIR, BODY>(g, m, strip, y0, y1, lane, lmax, bad);
 }
 
-template <bool TAPE, int WPB, bool ALT, bool DIR>
+template <bool TAPE, int WPB, bool ALT, bool DIR, bool BODY>
 __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
+    static_assert(!BODY || (!ALT && !TAPE), "body kernels march one way, without a tape");
     const LaunchSlots ls = slots_for(a.launch);
     DevState* st = a.st;
     const StepCtl c = step_control(st, ls, a.lam_mode, a.dx, a.cfl, a.t_end);
@@ -354,13 +407,14 @@ __global__ __launch_bounds__(64 * WPB) void step2d_d2q4(Step2DArgs a) {
         g.dir[s] = a.dir[s];
         g.any_dir = g.any_dir || a.bc[s] == BC_DIRICHLET;
     }
+    g.code = a.code;
     const int total_waves = gridDim.x * WPB;
 
     double lmax = 0.0;
     bool bad = false;
     for (int tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wave; tile < a.ntiles;
          tile += total_waves)
-        step_tile<TAPE, WPB, ALT, DIR>(g, tile, lane, lmax, bad);
+        step_tile<TAPE, WPB, ALT, DIR, BODY>(g, tile, lane, lmax, bad);
 
     if (a.lam_mode == LAM_PER_STEP) {
         double wm = wave_max(lmax);
@@ -409,53 +463,63 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch(Batch2DArgs a) {
             g.dir[s] = nullptr;
         }
         g.any_dir = false;
+        g.code = nullptr;
         double lmax = 0.0;
         bool bad = false;
-        step_tile<TAPE, WPB, true, false>(g, (int)(tile - d.tile0), lane, lmax, bad);
+        step_tile<TAPE, WPB, true, false, false>(g, (int)(tile - d.tile0), lane, lmax, bad);
         if (__any(bad) && lane == 0) atomicOr(&a.status[lo], 1u);
     }
 }
 
-template <bool TAPE, int WPB, bool ALT, bool DIR>
+template <bool TAPE, int WPB, bool ALT, bool DIR, bool BODY>
 static hipError_t launch_one(const Step2DArgs& a, int max_blocks, hipStream_t s) {
     int nblocks = (a.ntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    hipLaunchKernelGGL((step2d_d2q4<TAPE, WPB, ALT, DIR>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    hipLaunchKernelGGL((step2d_d2q4<TAPE, WPB, ALT, DIR, BODY>), dim3(nblocks), dim3(64 * WPB), 0,
+                       s, a);
     return hipGetLastError();
 }
 
-// Kernel for (tape, alternate, dirichlet); the moment tape exists for the
-// adjoint, which needs periodic sides, so it has no Dirichlet variant.
+// Kernel for (tape, alternate, dirichlet, body); the moment tape exists for
+// the adjoint, which needs periodic sides, so it has no Dirichlet or body
+// variant, and body kernels march one way.
 template <int W>
 static hipError_t launch_w(const Step2DArgs& a, bool tape, bool alt, bool dir, int max_blocks,
                            hipStream_t s) {
+    if (a.code) {
+        if (tape || alt) return hipErrorInvalidValue;
+        return dir ? launch_one<false, W, false, true, true>(a, max_blocks, s)
+                   : launch_one<false, W, false, false, true>(a, max_blocks, s);
+    }
     if (tape) {
         if (dir) return hipErrorInvalidValue;
-        return alt ? launch_one<true, W, true, false>(a, max_blocks, s)
-                   : launch_one<true, W, false, false>(a, max_blocks, s);
+        return alt ? launch_one<true, W, true, false, false>(a, max_blocks, s)
+                   : launch_one<true, W, false, false, false>(a, max_blocks, s);
     }
     if (dir)
-        return alt ? launch_one<false, W, true, true>(a, max_blocks, s)
-                   : launch_one<false, W, false, true>(a, max_blocks, s);
-    return alt ? launch_one<false, W, true, false>(a, max_blocks, s)
-               : launch_one<false, W, false, false>(a, max_blocks, s);
+        return alt ? launch_one<false, W, true, true, false>(a, max_blocks, s)
+                   : launch_one<false, W, false, true, false>(a, max_blocks, s);
+    return alt ? launch_one<false, W, true, false, false>(a, max_blocks, s)
+               : launch_one<false, W, false, false, false>(a, max_blocks, s);
+}
+
+template <class K>
+static int occupancy(K kernel, int threads) {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 template <int W>
-static int blocks_w(bool alt, bool dir) {
-    int n = 0;
-    hipError_t e;
+static int blocks_w(bool alt, bool dir, bool body) {
+    if (body)
+        return dir ? occupancy(step2d_d2q4<false, W, false, true, true>, 64 * W)
+                   : occupancy(step2d_d2q4<false, W, false, false, true>, 64 * W);
     if (dir)
-        e = alt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, true, true>,
-                                                               64 * W, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, false, true>,
-                                                               64 * W, 0);
-    else
-        e = alt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, true, false>,
-                                                               64 * W, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_d2q4<false, W, false, false>,
-                                                               64 * W, 0);
-    return e == hipSuccess && n > 0 ? n : 1;
+        return alt ? occupancy(step2d_d2q4<false, W, true, true, false>, 64 * W)
+                   : occupancy(step2d_d2q4<false, W, false, true, false>, 64 * W);
+    return alt ? occupancy(step2d_d2q4<false, W, true, false, false>, 64 * W)
+               : occupancy(step2d_d2q4<false, W, false, false, false>, 64 * W);
 }
 
 #define LBRS_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12) X(16)
@@ -495,9 +559,9 @@ bool step2d_wpb_supported(int wpb) {
 }
 
 // Resident workgroups of the step kernel per CU for a workgroup size.
-int step2d_blocks_per_cu(int wpb, bool alt, bool dir) {
+int step2d_blocks_per_cu(int wpb, bool alt, bool dir, bool body) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return blocks_w<W>(alt, dir);
+    if (wpb == W) return blocks_w<W>(alt, dir, body);
     LBRS_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return 1;

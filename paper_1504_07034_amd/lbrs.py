@@ -12,6 +12,7 @@ import ctypes
 import math
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,7 +37,8 @@ EXPORTS = (
     "lbrs_batch2d_step", "lbrs_batch2d_step_tape", "lbrs_batch2d_adjoint_step",
     "lbrs_batch2d_adjoint_init", "lbrs_batch2d_set_window", "lbrs_batch2d_window_objective",
     "lbrs_batch2d_moments", "lbrs_batch2d_get_f", "lbrs_batch2d_set_f", "lbrs_batch2d_gradient",
-    "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_strerror", "lbrs_destroy",
+    "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
+    "lbrs_destroy",
 )
 
 
@@ -51,6 +53,7 @@ class lbrs_params(ctypes.Structure):
         ("layout", ctypes.c_int),
         ("dirichlet", ctypes.c_void_p * 4),
         ("law", ctypes.c_int), ("scalar_flux", ctypes.c_double * 4),
+        ("solid", ctypes.c_void_p),
     ]
 
 
@@ -119,6 +122,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_batch2d_gradient": (i, [vp, vp, i, i, vp, vp, vp, vp, vp, vp, i]),
         "lbrs_batch2d_get_state": (i, [vp, ctypes.POINTER(ll), dp, ctypes.POINTER(ctypes.c_uint)]),
         "lbrs_batch2d_destroy": (None, [vp]),
+        "lbrs_body_codes": (i, [P, ctypes.POINTER(ctypes.c_ushort)]),
         "lbrs_strerror": (ctypes.c_char_p, [i]),
         "lbrs_destroy": (None, [vp]),
     }
@@ -158,10 +162,12 @@ def _stream(stream=None):
 def make_params(model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0, cfl=0.5,
                 bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
                 layout=LBRS_LAYOUT_PLANAR, dirichlet=(None, None, None, None),
-                law=LBRS_LAW_EULER, scalar_flux=(0.0, 0.0, 0.0, 0.0)) -> lbrs_params:
+                law=LBRS_LAW_EULER, scalar_flux=(0.0, 0.0, 0.0, 0.0),
+                solid=None) -> lbrs_params:
     """dirichlet: per side, a device tensor of conserved states [K][n] (or None);
     law / scalar_flux: the conservation law (scalar: g1 = c0 u + c1 u^2/2,
-    g2 = c2 u + c3 u^2/2)."""
+    g2 = c2 u + c3 u^2/2); solid: a host uint8 array [ny][nx] (nonzero = solid
+    cell of a body) or None -- the params keep a reference to it."""
     p = lbrs_params()
     p.model, p.nx, p.ny = int(model), int(nx), int(ny)
     p.x0, p.x1, p.y0, p.y1 = map(float, domain)
@@ -176,7 +182,25 @@ def make_params(model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1
     p.law = int(law)
     for k in range(4):
         p.scalar_flux[k] = float(scalar_flux[k])
+    if solid is None:
+        p.solid = None
+    else:
+        m = np.ascontiguousarray(np.asarray(solid), dtype=np.uint8)
+        if m.shape != (int(ny), int(nx)):
+            raise ValueError(f"solid mask must be [ny][nx] = {(ny, nx)}, got {m.shape}")
+        p._solid = m  # kept alive with the struct
+        p.solid = m.ctypes.data
     return p
+
+
+def lbrs_body_codes(p: lbrs_params):
+    """Node codes of the body of p (host computation, no GPU needed):
+    uint16 [ny][nx], the rule of population i in bits 3i..3i+2 and bit 15
+    for a solid cell."""
+    out = np.zeros((p.ny, p.nx), dtype=np.uint16)
+    _check(load_library(require_gpu=False).lbrs_body_codes(
+        ctypes.byref(p), out.ctypes.data_as(ctypes.POINTER(ctypes.c_ushort))), "lbrs_body_codes")
+    return out
 
 
 # ------------------------------------------------------------- C-named calls
@@ -295,10 +319,11 @@ class Sim:
     def __init__(self, model, nx, ny=1, domain=(0.0, 1.0, 0.0, 1.0), gamma=1.4, omega=1.0,
                  cfl=0.5, bc=(0, 0, 0, 0), lambda_mode=LBRS_LAMBDA_PER_STEP, lambda_user=0.0,
                  layout=LBRS_LAYOUT_PLANAR, device="cuda", dirichlet_W=(None, None, None, None),
-                 law=LBRS_LAW_EULER, scalar_flux=(0.0, 0.0, 0.0, 0.0)):
+                 law=LBRS_LAW_EULER, scalar_flux=(0.0, 0.0, 0.0, 0.0), solid=None):
         """dirichlet_W: per side, the prescribed primitive states [K][n] of a
         DIRICHLET side (n = ny for the x-sides, nx for the y-sides), converted
-        to conserved states on the device and kept for the context's life."""
+        to conserved states on the device and kept for the context's life;
+        solid: host uint8 mask [ny][nx] of a body (2D Euler), or None."""
         load_library()
         self.layout = layout
         self.device = torch.device(device)
@@ -306,7 +331,8 @@ class Sim:
         self.dirichlet = tuple(None if d is None else self._side_to_cons(d, gamma)
                                for d in dirichlet_W)
         self.p = make_params(model, nx, ny, domain, gamma, omega, cfl, bc, lambda_mode, lambda_user,
-                             layout, self.dirichlet, law, scalar_flux)
+                             layout, self.dirichlet, law, scalar_flux, solid)
+        self.body = solid is not None
         self.model, self.nx, self.ny = model, nx, ny
         self.Q = {0: 2, 1: 3, 2: 4}[model]
         self.K = 1 if law == LBRS_LAW_SCALAR else (4 if model == LBRS_D2Q4 else 3)
@@ -368,7 +394,10 @@ class Sim:
             W = torch.from_numpy(W)
         return self.init(self.prim_to_cons(W))
 
-    def set_tile(self, rows_per_tile: int, waves_per_block: int = 4, alternate: int = 1):
+    def set_tile(self, rows_per_tile: int, waves_per_block: int = 4, alternate=None):
+        """alternate: None = the default march (alternating, one way with a body)."""
+        if alternate is None:
+            alternate = 0 if self.body else 1
         lbrs_set_tile(self.ctx, rows_per_tile, waves_per_block, alternate)
 
     def step(self, max_steps: int, t_end: float = math.inf):

@@ -11,7 +11,9 @@ an even cell count no centre lies on a mid-domain interface, so no tie-break
 is needed at the discontinuities below.
 
 Model ids: 0 = D1Q2, 1 = D1Q3, 2 = D2Q4.  Side ids: 0 transmissive,
-1 periodic, 2 wall; side order (x-low, x-high, y-low, y-high).
+1 periodic, 2 wall, 3 Dirichlet; side order (x-low, x-high, y-low, y-high).
+Bodies (the Sec. III step, backward step and ramp cases) are masks of solid
+cells, a cell being solid when its centre lies inside the body.
 """
 from __future__ import annotations
 
@@ -49,6 +51,8 @@ class Workload:
     # g1(u) = quad[0] u + quad[1] u^2/2, g2(u) = quad[2] u + quad[3] u^2/2
     flux: int = FLUX_EULER
     quad: tuple = (0.0, 0.0, 0.0, 0.0)
+    # solid cells of a body [ny][nx] (uint8, nonzero = solid), or None
+    solid: np.ndarray | None = None
 
 
 def centres(n: int, a: float, b: float) -> np.ndarray:
@@ -160,6 +164,102 @@ def oblique_shock(nx: int = 240, ny: int = 80, t_end: float = 4.0, omega: float 
     return Workload("oblique_shock", D2Q4, nx, ny, (0.0, nx / ny, 0.0, 1.0), W, omega=omega,
                     t_end=t_end, sides=(DIRICHLET, TRANSMISSIVE, WALL, DIRICHLET),
                     dirichlet_W=(inflow, None, None, top))
+
+
+def _uniform(nx: int, ny: int, state) -> np.ndarray:
+    W = np.empty((4, ny, nx))
+    for k in range(4):
+        W[k] = state[k]
+    return W
+
+
+def _along(state, n: int) -> np.ndarray:
+    return np.repeat(np.asarray(state, dtype=np.float64)[:, None], n, axis=1)
+
+
+def _cell_mask(nx: int, ny: int, domain, inside) -> np.ndarray:
+    """uint8 [ny][nx]: 1 where inside(x, y) holds at the cell centre."""
+    X, Y = np.meshgrid(centres(nx, domain[0], domain[1]), centres(ny, domain[2], domain[3]))
+    return inside(X, Y).astype(np.uint8)
+
+
+def forward_step(nx: int = 240, ny: int = 80, t_end: float = 4.0, omega: float = 1.0,
+                 mach: float = 3.0, step_x: float = 0.6, step_h: float = 0.2) -> Workload:
+    """Mach 3 flow over a forward-facing step in the channel [0, 3] x [0, 1]
+    (Sec. III; 240 x 80 cells, t = 4, the interior starts at the inflow
+    state, free-slip walls).  The step itself is not given: a step of height
+    0.2 from x = 0.6 to the outflow.  Inflow (rho, u, v, p) = (1.4, M, 0, 1),
+    so that the sound speed is 1; prescribed on the left side, transmissive
+    (supersonic outflow) right side, walls at the bottom and the top."""
+    domain = (0.0, 3.0, 0.0, 1.0)
+    inflow = (1.4, mach, 0.0, 1.0)
+    solid = _cell_mask(nx, ny, domain, lambda x, y: (x > step_x) & (y < step_h))
+    return Workload("forward_step", D2Q4, nx, ny, domain, _uniform(nx, ny, inflow), omega=omega,
+                    t_end=t_end, sides=(DIRICHLET, TRANSMISSIVE, WALL, WALL),
+                    dirichlet_W=(_along(inflow, ny), None, None, None), solid=solid,
+                    meta={"mach": mach, "step_x": step_x, "step_h": step_h})
+
+
+def moving_shock_state(mach: float, rho1: float = 1.4, p1: float = 1.0,
+                       gamma: float = 1.4) -> tuple:
+    """(rho, u, v, p) behind a normal shock of Mach number `mach` running
+    into gas at rest (rho1, p1): the normal-shock relations in the shock's
+    frame, shifted by the shock speed mach * a1."""
+    a1 = math.sqrt(gamma * p1 / rho1)
+    m2 = mach * mach
+    rho2 = rho1 * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = p1 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    u2 = mach * a1 * (1.0 - rho1 / rho2)
+    return (rho2, u2, 0.0, p2)
+
+
+def shock_diffraction(n: int = 400, t_end: float = 0.1561, omega: float = 1.0,
+                      mach: float = 5.09, corner=(0.2, 0.5)) -> Workload:
+    """A Mach 5.09 shock diffracting over a backward-facing step in [0, 1]^2
+    (Sec. III; 400 x 400 cells, t = 0.1561), the shock starting at the
+    step's tip.  The step is not given: the body is [0, 0.2] x [0, 0.5] (a
+    shock starting at x = 0.2 runs 0.795 in that time, reaching the right
+    side).  Gas at rest (1.4, 0, 0, 1) ahead of the shock, the post-shock
+    state behind it and prescribed on the left side; the other sides are
+    transmissive."""
+    domain = (0.0, 1.0, 0.0, 1.0)
+    xc, yc = corner
+    post = moving_shock_state(mach)
+    rest = (1.4, 0.0, 0.0, 1.0)
+    X, _ = np.meshgrid(centres(n, 0.0, 1.0), centres(n, 0.0, 1.0))
+    W = np.empty((4, n, n))
+    for k in range(4):
+        W[k] = np.where(X < xc, post[k], rest[k])
+    solid = _cell_mask(n, n, domain, lambda x, y: (x < xc) & (y < yc))
+    return Workload("shock_diffraction", D2Q4, n, n, domain, W, omega=omega, t_end=t_end,
+                    sides=(DIRICHLET, TRANSMISSIVE, TRANSMISSIVE, TRANSMISSIVE),
+                    dirichlet_W=(_along(post, n), None, None, None), solid=solid,
+                    meta={"mach": mach, "corner": corner, "post": post})
+
+
+def ramp(nx: int = 240, ny: int = 80, t_end: float = 4.0, omega: float = 1.0, mach: float = 2.0,
+         angle_deg: float = 15.0, x_start: float = 0.5, x_end: float = 1.5) -> Workload:
+    """Mach 2 flow over a compression ramp in a channel (Sec. III; 240 x 80
+    cells).  Channel, ramp and end time are not given: the channel
+    [0, 3] x [0, 1] of the step case, a 15-degree ramp from x = 0.5 to 1.5
+    followed by a flat top (a compression corner and an expansion corner),
+    t = 4, the interior starting at the inflow state (1.4, M, 0, 1); inflow
+    prescribed on the left, transmissive right side, walls at the bottom and
+    the top.  Cells whose centres lie below the ramp's surface are solid."""
+    domain = (0.0, 3.0, 0.0, 1.0)
+    inflow = (1.4, mach, 0.0, 1.0)
+    slope = math.tan(math.radians(angle_deg))
+
+    def below(x, y):
+        h = slope * (np.clip(x, x_start, x_end) - x_start)
+        return y < h
+
+    solid = _cell_mask(nx, ny, domain, below)
+    return Workload("ramp", D2Q4, nx, ny, domain, _uniform(nx, ny, inflow), omega=omega,
+                    t_end=t_end, sides=(DIRICHLET, TRANSMISSIVE, WALL, WALL),
+                    dirichlet_W=(_along(inflow, ny), None, None, None), solid=solid,
+                    meta={"mach": mach, "angle_deg": angle_deg, "x_start": x_start,
+                          "x_end": x_end})
 
 
 def burgers_riemann(n: int = 400, uL: float = 1.0, uR: float = 0.0, t_end: float = 0.5,

@@ -13,12 +13,17 @@ fixes these rules independently of the oracle's own code:
   at the wall nodes);
 * D4 symmetry around a square body and mirror symmetry around an off-centre
   rectangle;
-* a body that only reproduces wall sides gives the wall-side result.
+* a body that only reproduces wall sides gives the wall-side result;
+* the shock-diffraction case: far from the body the planar shock runs at the
+  Rankine-Hugoniot speed.
 """
 import numpy as np
 import pytest
 
 import oracle
+from paper_1504_07034_amd import workloads as wl
+
+from test_oracle_dirichlet import side_cons
 
 pytestmark = pytest.mark.filterwarnings("ignore")
 
@@ -322,3 +327,20 @@ def test_solid_cells_ignore_their_initial_state():
     assert ra.status == 0 and rb.status == 0
     assert np.array_equal(ra.U, rb.U)
     assert np.array_equal(ra.dt, rb.dt)
+
+
+def test_diffraction_planar_shock_speed():
+    """The Sec. III shock diffraction at 200 x 200 to t = 0.1: in the top rows,
+    which no signal from the corner has reached, the shock found from the
+    mass along the row (conservative scheme, post-shock inflow) is where the
+    Mach 5.09 shock speed puts it, x = 0.2 + 5.09 t, within half a cell."""
+    w = wl.shock_diffraction(200)
+    Pr = oracle.Problem(model=oracle.D2Q4, nx=w.nx, ny=w.ny, domain=w.domain, sides=w.sides,
+                        solid=w.solid)
+    Pr.dirichlet = tuple(None if d is None else side_cons(Pr, d) for d in w.dirichlet_W)
+    r = oracle.run(Pr, oracle.prim_to_cons(Pr, w.W), t_end=0.1, record=False)
+    assert r.status == 0
+    rho2 = w.meta["post"][0]
+    for j in (-1, -2, -5):
+        front = (r.U[0, j].mean() - 1.4) / (rho2 - 1.4)
+        assert abs(front - (0.2 + 5.09 * 0.1)) <= 0.5 / w.nx
