@@ -43,7 +43,8 @@ def compare(w, t_end=math.inf, max_steps=10**9, omega=None, tile=None, layout=1,
     sim.init_primitive(w.W)
     if tile:
         sim.set_tile(*tile)
-    sim.step(ref.nsteps if math.isinf(t_end) else ref.nsteps + 5, t_end)
+    # the oracle stopped at t_end (extra steps must do nothing) or at max_steps
+    sim.step(ref.nsteps + 5 if ref.t >= t_end else ref.nsteps, t_end)
     st = sim.state()
     U = sim.moments().cpu().numpy()
     err = max_abs(U, ref.U)
@@ -76,12 +77,22 @@ def test_forward_step_to_t4():
     check(*compare(w, t_end=w.t_end, name="ffs t4"), w)
 
 
-@pytest.mark.parametrize("omega,layout", [(1.0, 1), (1.7, 0)])
+@pytest.mark.parametrize("omega,layout", [(1.0, 1), (1.5, 0)])
 def test_ramp_parity(omega, layout):
     """Mach 2 over the 15-degree staircase ramp (faces, concave feet and
     convex tips on every stair), 240 x 80, to t = 4."""
     w = wl.ramp(omega=omega)
     check(*compare(w, t_end=w.t_end, omega=omega, layout=layout, name=f"ramp w{omega} l{layout}"), w)
+
+
+def test_ramp_breakdown_at_high_omega_agrees():
+    """At omega = 1.7 the ramp's start-up is not admissible: both sides report
+    the same failing step, with the same state up to the parity bar."""
+    w = wl.ramp(omega=1.7)
+    st, ref, U, err = compare(w, t_end=w.t_end, omega=1.7, name="ramp w1.7 breakdown")
+    assert ref.status == oracle.NONPHYSICAL and st["rc"] == lbrs.LBRS_E_NONPHYSICAL
+    assert st["fail_step"] == ref.fail_step == st["nsteps"] == ref.nsteps
+    assert err <= TOL
 
 
 def test_shock_diffraction_parity():
