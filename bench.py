@@ -411,6 +411,68 @@ def dirichlet_2d(nx=12288, ny=4096, steps=200, warmup=20):
             "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def bodies_2d(nx=7680, ny=2560, steps=200, warmup=20):
+    """Solid bodies: the forward-facing step case (Mach 3 channel, inflow
+    side, walls, the step as a mask of solid cells) at nx x ny with the body
+    kernel (2-byte node code per cell on top of the 256 B of populations;
+    solid cells are streamed like the others), autotuned launch shape, HIP
+    events.  Beside it, the wall-clock time of whole runs of the three Sec. III
+    body cases at the paper's grids (launch-bound: a few ten thousand cells)."""
+    import torch
+
+    from paper_1504_07034_amd import autotune, lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    def make(w):
+        return lbrs.Sim(w.model, w.nx, w.ny, domain=w.domain, gamma=w.gamma, omega=w.omega,
+                        cfl=w.cfl, bc=w.sides, layout=lbrs.LBRS_LAYOUT_ROWS,
+                        dirichlet_W=w.dirichlet_W, solid=w.solid)
+
+    w = wl.forward_step(nx, ny, omega=1.6)
+    solid_frac = float(w.solid.mean())
+    sim = make(w)
+    U0 = sim.prim_to_cons(torch.from_numpy(w.W))
+    del w
+    sim.init(U0)
+    sim.step(5)
+    best = autotune.tune(sim, use_cache=False)
+    sim.init(U0)
+    sim.set_tile(best["rows"], best["wpb"], 0)
+    sim.step(warmup)
+    ms = _time_ms(lambda: sim.step(steps)) / steps
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+    sim.close()
+    del U0
+    cells = nx * ny
+    bytes_per_lup = BYTES_PER_LUP + 2
+    gbs = bytes_per_lup * cells / (ms * 1e-3) / 1e9
+    out = {"workload": "forward-facing step, Mach 3, step as solid cells",
+           "nx": nx, "ny": ny, "omega": 1.6, "solid_fraction": round(solid_frac, 4),
+           "tile_rows": best["rows"], "waves_per_block": best["wpb"],
+           "ms_per_step": round(ms, 4), "MLUPS": round(cells / ms / 1e3, 1),
+           "fluid_MLUPS": round(cells * (1.0 - solid_frac) / ms / 1e3, 1),
+           "bytes_per_lup": bytes_per_lup, "GBs": round(gbs, 1),
+           "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    runs = {}
+    for w in (wl.forward_step(), wl.ramp(), wl.shock_diffraction()):
+        sim = make(w)
+        sim.init_primitive(w.W)
+        sim.step(10)  # first launches
+        sim.init_primitive(w.W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sim.run(w.t_end, chunk=4000)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        assert st["rc"] == 0 and st["t"] == w.t_end
+        runs[w.name] = {"grid": f"{w.nx}x{w.ny}", "t_end": w.t_end, "steps": st["nsteps"],
+                        "run_ms": round(sec * 1e3, 1)}
+        sim.close()
+    out["paper_grids"] = runs
+    return out
+
+
 def scalar_laws(n2=8192, n1=1 << 24, steps=200, warmup=20):
     """Scalar LBRS: the 2D Burgers case 1 (prescribed sides) at n2 x n2 on
     D2Q4 (64 B per lattice update: 4 populations in and out) with an autotuned
@@ -543,7 +605,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
     ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad", "dirichlet",
-                                       "scalar", "euler1d", "slab"],
+                                       "scalar", "euler1d", "slab", "bodies"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -564,7 +626,8 @@ def main():
     if args.only:
         fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
               "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
-              "scalar": scalar_laws, "euler1d": euler_1d_long, "slab": slab_step}[args.only]
+              "scalar": scalar_laws, "euler1d": euler_1d_long, "slab": slab_step,
+              "bodies": bodies_2d}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
@@ -666,6 +729,7 @@ def main():
     if not args.no_extras:
         stage("slab_4096x512", slab_step)
         stage("dirichlet_2d", dirichlet_2d)
+        stage("bodies_2d", bodies_2d)
         stage("scalar_laws", scalar_laws)
         stage("euler_1d_long", euler_1d_long)
         stage("adjoint_2d", adjoint_2d)
