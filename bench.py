@@ -457,17 +457,27 @@ def bodies_2d(nx=7680, ny=2560, steps=200, warmup=20):
     runs = {}
     for w in (wl.forward_step(), wl.ramp(), wl.shock_diffraction()):
         sim = make(w)
-        sim.init_primitive(w.W)
-        sim.step(10)  # first launches
-        sim.init_primitive(w.W)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = sim.run(w.t_end, chunk=4000)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        assert st["rc"] == 0 and st["t"] == w.t_end
-        runs[w.name] = {"grid": f"{w.nx}x{w.ny}", "t_end": w.t_end, "steps": st["nsteps"],
-                        "run_ms": round(sec * 1e3, 1)}
+        rec = {"grid": f"{w.nx}x{w.ny}", "t_end": w.t_end}
+        for label in ("default", "tuned"):
+            sim.init_primitive(w.W)
+            if label == "tuned":
+                sim.step(20)
+                best = autotune.tune(sim, w.t_end, use_cache=False)
+                rec["tile_rows"], rec["waves_per_block"] = best["rows"], best["wpb"]
+            else:
+                sim.step(10)  # first launches
+            sim.init_primitive(w.W)
+            if label == "tuned":
+                sim.set_tile(best["rows"], best["wpb"], 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.run(w.t_end, chunk=4000)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            assert st["rc"] == 0 and st["t"] == w.t_end
+            rec["steps"] = st["nsteps"]
+            rec[f"run_ms_{label}"] = round(sec * 1e3, 1)
+        runs[w.name] = rec
         sim.close()
     out["paper_grids"] = runs
     return out

@@ -26,13 +26,18 @@ CACHE = os.environ.get("LBRS_TUNE_CACHE",
 DEFAULT_ROWS = (0, 32, 64, 96, 128)
 DEFAULT_WPB = (4, 6, 8, 12, 16)
 DEFAULT_ALT = (0, 1)
+# Grids up to SMALL_CELLS cells are latency-bound (a step is a chain of a few
+# row latencies): short row segments and small workgroups are candidates.
+SMALL_CELLS = 1 << 20
+SMALL_ROWS = (0, 1, 2, 3, 4, 6, 8)
+SMALL_WPB = (1, 2, 4, 8)
 
 
 def _key(sim: "lbrs.Sim") -> str:
     p = sim.p
     name = torch.cuda.get_device_name(sim.device)
     body = "|body" if getattr(sim, "body", False) else ""
-    return f"{name}|m{p.model}|{p.nx}x{p.ny}|bc{tuple(p.bc)}{body}|v2"
+    return f"{name}|m{p.model}|{p.nx}x{p.ny}|bc{tuple(p.bc)}{body}|v3"
 
 
 def _load_cache() -> dict:
@@ -70,10 +75,16 @@ def time_shape(sim: "lbrs.Sim", rows: int, wpb: int, steps: int, f0: torch.Tenso
     return e0.elapsed_time(e1) / steps
 
 
-def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=DEFAULT_ROWS,
-         wpbs=DEFAULT_WPB, alts=DEFAULT_ALT, use_cache: bool = True,
+def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=None,
+         wpbs=None, alts=DEFAULT_ALT, use_cache: bool = True,
          verbose: bool = False, confirm: int = 4) -> dict:
-    """Pick and apply the fastest 2D launch shape for `sim` (already initialised)."""
+    """Pick and apply the fastest 2D launch shape for `sim` (already initialised).
+    rows / wpbs default to the candidate sets for the grid's size."""
+    small = sim.nx * sim.ny <= SMALL_CELLS
+    if rows is None:
+        rows = SMALL_ROWS if small else DEFAULT_ROWS
+    if wpbs is None:
+        wpbs = SMALL_WPB if small else DEFAULT_WPB
     key = _key(sim)
     if getattr(sim, "body", False):
         alts = (0,)

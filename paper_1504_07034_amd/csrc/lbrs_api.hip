@@ -341,7 +341,9 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream) {
 }
 
 // Row segments per strip.  Automatic: as many as make the tiles one balanced
-// round of the resident waves (at least 8 rows each); else ceil(ny / rows).
+// round of the resident waves (at least 3 rows each: on small grids a step
+// is a chain of row latencies, so short segments pay for their two extra
+// halo rows); else ceil(ny / rows).
 static int blocks_per_cu(const lbrs_ctx* c) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
     int w = c->waves_per_block;
@@ -358,7 +360,7 @@ static int step2d_segments(const lbrs_ctx* c, int nstrips) {
     } else {
         long long waves = (long long)c->cu_count * blocks_per_cu(c) * c->waves_per_block;
         nseg = waves / nstrips;
-        long long cap = (ny + 7) / 8;  // at least 8 rows per segment
+        long long cap = (ny + 2) / 3;  // at least 3 rows per segment
         if (nseg > cap) nseg = cap;
     }
     if (nseg < 1) nseg = 1;

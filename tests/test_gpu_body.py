@@ -63,7 +63,8 @@ def check(st, ref, U, err, w):
 
 
 @pytest.mark.parametrize("omega", [1.0, 1.6])
-@pytest.mark.parametrize("tile", [None, (0, 16, 0), (9, 4, 0), (0, 2, 0), (21, 8, 0)])
+@pytest.mark.parametrize("tile", [None, (0, 16, 0), (9, 4, 0), (0, 2, 0), (21, 8, 0), (1, 1, 0),
+                                  (3, 4, 0), (2, 8, 0)])
 def test_forward_step_parity(omega, tile):
     """Mach 3 over the forward-facing step, 240 x 80 (inflow side, walls,
     step faces, the step's tip and foot), to t = 1, in several launch shapes."""

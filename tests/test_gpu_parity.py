@@ -148,7 +148,8 @@ def test_2d_explosion(omega):
 
 
 @pytest.mark.parametrize("tile", [(64, 4), (7, 1), (50, 2), (200, 4), (0, 6), (0, 8), (33, 12),
-                                  (0, 16), (64, 4, 0), (7, 2, 0), (0, 16, 0)])
+                                  (0, 16), (64, 4, 0), (7, 2, 0), (0, 16, 0), (1, 1), (1, 4, 0),
+                                  (2, 8), (3, 2, 0), (3, 16)])
 def test_2d_tile_shapes(tile):
     """Ragged row segments and every workgroup shape (lockstep groups of 1 to 16
     waves, strip widths below 62) give the same answer."""
