@@ -26,9 +26,9 @@ METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
 # (automatic row segments, row-interleaved layout), valid for the kernel source
 # they were taken on (profiles/step2d_d2q4_riemann4096.md); null once the
 # source changes or for a shape not profiled.
-TRAFFIC_BYTES = {"16,0": 4.433e9, "16,1": 4.395e9, "12,1": 4.392e9, "8,0": 4.487e9,
-                 "8,1": 4.382e9, "6,1": 4.406e9}
-TRAFFIC_SOURCE_HASH = "6733a4959e78c83c"
+TRAFFIC_BYTES = {"16,0": 4.433e9, "16,1": 4.396e9, "12,1": 4.392e9, "8,0": 4.485e9, "8,1": 4.383e9,
+                 "6,1": 4.405e9}
+TRAFFIC_SOURCE_HASH = "d34d3ce179d013e0"
 
 
 def traffic_bytes(shape, layout):
