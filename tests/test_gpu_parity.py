@@ -84,7 +84,7 @@ def test_1d_periodic(omega):
 @pytest.mark.parametrize("model", [wl.D1Q2, wl.D1Q3])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_1d_long_tiled(model, periodic):
-    """5003 cells (beyond the one-workgroup form, ragged against 62-cell chunks)."""
+    """5003 cells (beyond the one-workgroup form, ragged against 512-cell tiles)."""
     w = wl.sod(5003, model=model, omega=1.3, t_end=0.02)
     sides = (1, 1, 0, 0) if periodic else (0, 0, 0, 0)
     _compare(w, t_end=0.02, sides=sides, name=f"1d long m{model} p{periodic}")
@@ -92,13 +92,12 @@ def test_1d_long_tiled(model, periodic):
 
 @pytest.mark.parametrize("n,model,periodic", [(62000, wl.D1Q3, False), (62001, wl.D1Q2, True),
                                                (400063, wl.D1Q3, True), (1 << 20, wl.D1Q2, False)])
-def test_1d_long_march(n, model, periodic):
-    """Long tubes in 62-cell chunks marched by persistent waves: an exact
-    multiple of the chunk, one cell more, and grids where every wave takes
-    several chunks (ragged last chunk, periodic wrap across it)."""
+def test_1d_long_tubes(n, model, periodic):
+    """Long tubes in many 512-cell tiles: a ragged last tile, one cell past a
+    multiple of the tile, a power of two, periodic wrap across the ends."""
     w = wl.sod(n, model=model, omega=1.2, t_end=0.02)
     sides = (1, 1, 0, 0) if periodic else (0, 0, 0, 0)
-    _compare(w, max_steps=25, sides=sides, name=f"1d march n{n} m{model} p{periodic}")
+    _compare(w, max_steps=25, sides=sides, name=f"1d long n{n} m{model} p{periodic}")
 
 
 @pytest.mark.parametrize("model,omega", [(wl.D1Q3, 1.0), (wl.D1Q2, 1.6)])
