@@ -193,7 +193,10 @@ int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void
  *             count, the lambda* reduction slots and the status word)
  *   hip_stream the stream every later call enqueues on (NULL = default)
  * On success *out receives the context.  A non-physical U0 is reported by the
- * next lbrs_get_state() with step index 0. */
+ * next lbrs_get_state() with step index 0.  With a body (p->solid) the node
+ * codes are built on the host, copied into d_scratch and the stream is
+ * synchronised before the call returns (an inadmissible mask: LBRS_E_INVAL,
+ * nothing enqueued). */
 int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* d_f0,
               double* d_f1, void* d_scratch, void* hip_stream);
 
