@@ -195,13 +195,57 @@ def test_2d_user_lambda_and_frozen():
     _compare(w, max_steps=50, lam_mode=1, name="frozen lambda")
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-def test_full_size_4096_first_steps(layout):
+@pytest.mark.parametrize("layout,tile", [(0, (0, 4)), (1, (0, 4)), (1, (0, 16, 0)),
+                                         (1, (0, 8, 1))])
+def test_full_size_4096_first_steps(layout, tile):
     """Full size (4096^2, transmissive, omega = 1) in the benchmark's launch shapes
-    (automatic tiles, both population layouts): three steps against the oracle on
-    every cell."""
+    (automatic row segments, 4-, 16- and 8-wave groups, both march orders, both
+    population layouts): three steps against the oracle on every cell."""
     w = wl.riemann2d(4096)
-    _compare(w, max_steps=3, tile=(0, 4), layout=layout, name=f"riemann 4096 x3 layout{layout}")
+    _compare(w, max_steps=3, tile=tile, layout=layout, name=f"riemann 4096 x3 l{layout} {tile}")
+
+
+@pytest.mark.parametrize("tile", [(0, 16, 0), (0, 8, 1)])
+def test_full_size_4096_cone_samples(tile):
+    """Full size, 100 steps, in the benchmark's launch shapes, checked on
+    sampled cells.  With a fixed lattice speed a cell after k steps depends
+    only on the (2k+1)^2 patch around it, so the oracle computes each sample on
+    a patch of radius k+1 (the real sides where the patch reaches them, any
+    side elsewhere: errors from an artificial patch edge travel one cell per
+    step and do not reach the centre).  The fixed speed is the oracle's own
+    lambda*(U0)/cfl of the whole grid."""
+    n, k = 4096, 100
+    w = wl.riemann2d(n)
+    Pfull = oracle_problem(w)
+    lam = oracle.initial_lattice_speed(Pfull, oracle.prim_to_cons(Pfull, w.W))
+    assert lam > 0
+    sim = gpu_sim(w, lam_mode=lbrs.LBRS_LAMBDA_USER, lam_user=lam, layout=1)
+    sim.init_primitive(w.W)
+    sim.set_tile(*tile)
+    sim.step(k)
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == k
+    U = sim.moments().cpu().numpy()
+    sim.close()
+    rng = np.random.default_rng(12)
+    samples = [(0, 0), (n - 1, n - 1), (0, n - 1), (n // 2, n // 2), (n // 2 - 1, n // 2),
+               (3, n // 2 + 7)] + [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(4)]
+    R = k + 1
+    worst = 0.0
+    for (j, i) in samples:  # (row, column)
+        y0, y1 = max(0, j - R), min(n, j + R + 1)
+        x0, x1 = max(0, i - R), min(n, i + R + 1)
+        P = oracle.Problem(model=oracle.D2Q4, nx=x1 - x0, ny=y1 - y0,
+                           domain=(0.0, (x1 - x0) / n, 0.0, (y1 - y0) / n), gamma=w.gamma,
+                           omega=w.omega, cfl=w.cfl, sides=(0, 0, 0, 0),
+                           lam_mode=oracle.LAM_USER, lam_user=lam)
+        ref = oracle.run(P, oracle.prim_to_cons(P, w.W[:, y0:y1, x0:x1]), max_steps=k,
+                         record=False)
+        assert ref.status == 0 and ref.nsteps == k
+        err = float(np.max(np.abs(U[:, j, i] - ref.U[:, j - y0, i - x0])))
+        worst = max(worst, err)
+        assert err <= TOL, ((j, i), err)
+    report(f"riemann 4096 cone {tile}", steps=k, samples=len(samples), err=worst)
 
 
 @pytest.mark.parametrize("sides", [(0, 0, 0, 0), (1, 1, 2, 2), (2, 0, 1, 1)])
