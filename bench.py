@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = 256  # 16 FP64 populations in + 16 out per lattice update
 
 
-def cpu_baseline(nsteps: int = 2):
+def cpu_baseline(nsteps: int = 7):
     """The oracle on the same 4096^2 workload for a bounded number of steps
     (single thread), init time excluded by differencing two runs."""
     import oracle
