@@ -90,7 +90,8 @@ def batched_1d(chunks=(510, 1022, 2046), subset=32):
     """Ragged 1D batch: 1024 seeded shock tubes (200..20000 cells, own t_end) in
     one persistent launch (chunk autotuned), against sequential single-domain
     runs of a seeded subset of the same tubes (the plain library path: one
-    persistent launch per tube of <= 2048 cells, one launch per step above)."""
+    persistent launch per tube of <= 2048 cells, one launch per step above).
+    subset = 0 runs the batch alone (for HBM counters of the batched launch)."""
     import numpy as np
     import torch
 
@@ -133,6 +134,12 @@ def batched_1d(chunks=(510, 1022, 2046), subset=32):
             pass
     best = min(tuned, key=lambda c: tuned[c][0])
     ms, lups = tuned[best]
+    out = {"units": len(tubes), "cells": int(sum(t.nx for t in tubes)), "chunk": best,
+           "ms": round(ms, 2), "MLUPS": round(lups / ms / 1e3, 1),
+           "effective_GBs": round(144 * lups / ms / 1e6, 1),
+           "chunk_ms": {str(c): round(v[0], 2) for c, v in tuned.items()}}
+    if subset <= 0:
+        return out
     rng = np.random.default_rng(1)
     sub = [tubes[i] for i in sorted(rng.choice(len(tubes), size=subset, replace=False))]
     ms_b, lups_b = timed_batch(sub, best)
@@ -145,12 +152,9 @@ def batched_1d(chunks=(510, 1022, 2046), subset=32):
         sim.close()
     torch.cuda.synchronize()
     ms_s = (time.perf_counter() - t0) * 1e3
-    return {"units": len(tubes), "cells": int(sum(t.nx for t in tubes)), "chunk": best,
-            "ms": round(ms, 2), "MLUPS": round(lups / ms / 1e3, 1),
-            "effective_GBs": round(144 * lups / ms / 1e6, 1),
-            "chunk_ms": {str(c): round(v[0], 2) for c, v in tuned.items()},
-            "subset": {"units": subset, "batched_ms": round(ms_b, 2),
-                       "sequential_ms": round(ms_s, 2), "speedup": round(ms_s / ms_b, 2)}}
+    out["subset"] = {"units": subset, "batched_ms": round(ms_b, 2),
+                     "sequential_ms": round(ms_s, 2), "speedup": round(ms_s / ms_b, 2)}
+    return out
 
 
 def _time_ms(fn, reps=1):
@@ -614,8 +618,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
-    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch2d", "batchgrad", "dirichlet",
-                                       "scalar", "euler1d", "slab", "bodies"],
+    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch1d_run", "batch2d", "batchgrad",
+                                       "dirichlet", "scalar", "euler1d", "slab", "bodies"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -637,7 +641,8 @@ def main():
         fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
               "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
               "scalar": scalar_laws, "euler1d": euler_1d_long, "slab": slab_step,
-              "bodies": bodies_2d}[args.only]
+              "bodies": bodies_2d,
+              "batch1d_run": lambda: batched_1d(chunks=(2046,), subset=0)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
