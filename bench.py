@@ -491,7 +491,8 @@ def scalar_laws(n2=8192, n1=1 << 24, steps=200, warmup=20):
     """Scalar LBRS: the 2D Burgers case 1 (prescribed sides) at n2 x n2 on
     D2Q4 (64 B per lattice update: 4 populations in and out) with an autotuned
     launch shape, and the 1D Burgers shock tube on n1 cells, D1Q2 (32 B per
-    update).  HIP events."""
+    update), planar 1D layout (and the blocked one for comparison).  HIP
+    events."""
     import torch
 
     from paper_1504_07034_amd import autotune, lbrs
@@ -521,42 +522,59 @@ def scalar_laws(n2=8192, n1=1 << 24, steps=200, warmup=20):
                          "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     torch.cuda.empty_cache()
     w = wl.burgers_riemann(n1, 1.0, 0.0, t_end=10.0)
-    sim = lbrs.Sim(w.model, n1, 1, domain=w.domain, omega=w.omega, cfl=w.cfl, bc=w.sides,
-                   law=lbrs.LBRS_LAW_SCALAR, scalar_flux=w.quad)
-    sim.init_primitive(w.W)
-    sim.step(warmup, w.t_end)
-    ms = _time_ms(lambda: sim.step(steps, w.t_end)) / steps
-    st = sim.state()
-    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+    blocked_ms = None
+    for layout in (lbrs.LBRS_LAYOUT_ROWS, lbrs.LBRS_LAYOUT_PLANAR):
+        sim = lbrs.Sim(w.model, n1, 1, domain=w.domain, omega=w.omega, cfl=w.cfl, bc=w.sides,
+                       law=lbrs.LBRS_LAW_SCALAR, scalar_flux=w.quad, layout=layout)
+        sim.init_primitive(w.W)
+        sim.step(warmup, w.t_end)
+        ms = _time_ms(lambda: sim.step(steps, w.t_end)) / steps
+        st = sim.state()
+        assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+        if layout == lbrs.LBRS_LAYOUT_ROWS:
+            blocked_ms = ms
+            sim.close()
     sim.close()
     gbs = 32 * n1 / (ms * 1e-3) / 1e9
-    out["burgers_1d"] = {"workload": "1D Burgers shock tube, D1Q2", "n": n1,
+    gbs_b = 32 * n1 / (blocked_ms * 1e-3) / 1e9
+    out["burgers_1d"] = {"workload": "1D Burgers shock tube, D1Q2", "n": n1, "layout": "planar",
                          "ms_per_step": round(ms, 4), "MLUPS": round(n1 / ms / 1e3, 1),
-                         "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                         "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "blocked": {"ms_per_step": round(blocked_ms, 4),
+                                     "frac": round(gbs_b / HBM_PEAK_GBS, 4)}}
     return out
 
 
 def euler_1d_long(n=1 << 24, steps=200, warmup=20):
     """The Euler shock tube (Sod) on n cells with D1Q3: the one-launch-per-step
-    1D kernel (512-cell LDS tiles), 144 B per lattice update."""
+    1D kernel (512-cell LDS tiles), 144 B per lattice update, in the blocked
+    population layout (the planes of each 64-cell block contiguous) and, for
+    comparison, the planar one."""
     import torch
 
     from paper_1504_07034_amd import lbrs
     from paper_1504_07034_amd import workloads as wl
 
     w = wl.sod(n, t_end=0.2)
-    sim = lbrs.Sim(w.model, n, 1, domain=w.domain, gamma=w.gamma, omega=w.omega, cfl=w.cfl)
-    sim.init_primitive(w.W)
-    del w
-    sim.step(warmup, 0.2)
-    ms = _time_ms(lambda: sim.step(steps, 0.2)) / steps
-    st = sim.state()
-    assert st["rc"] == 0 and st["nsteps"] == warmup + steps
-    sim.close()
-    gbs = 144 * n / (ms * 1e-3) / 1e9
-    return {"workload": "Sod shock tube, D1Q3", "n": n, "ms_per_step": round(ms, 4),
-            "MLUPS": round(n / ms / 1e3, 1), "GBs": round(gbs, 1),
-            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"workload": "Sod shock tube, D1Q3", "n": n}
+    for layout in (lbrs.LBRS_LAYOUT_PLANAR, lbrs.LBRS_LAYOUT_ROWS):
+        sim = lbrs.Sim(w.model, n, 1, domain=w.domain, gamma=w.gamma, omega=w.omega, cfl=w.cfl,
+                       layout=layout)
+        sim.init_primitive(w.W)
+        sim.step(warmup, 0.2)
+        ms = _time_ms(lambda: sim.step(steps, 0.2)) / steps
+        st = sim.state()
+        assert st["rc"] == 0 and st["nsteps"] == warmup + steps
+        sim.close()
+        torch.cuda.empty_cache()
+        gbs = 144 * n / (ms * 1e-3) / 1e9
+        if layout == lbrs.LBRS_LAYOUT_PLANAR:
+            out["planar"] = {"ms_per_step": round(ms, 4), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        else:
+            out.update({"layout": "blocked", "ms_per_step": round(ms, 4),
+                        "MLUPS": round(n / ms / 1e3, 1), "GBs": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return out
 
 
 def copy_bandwidth(src, dst, reps=20):

@@ -34,6 +34,16 @@ struct lbrs_ctx {
 };
 
 static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
+
+// Is this the blocked 1D population layout (LAYOUT_ROWS for a 1D model)?
+static bool blocked1d(const lbrs_params* p) {
+    return p->model != LBRS_D2Q4 && p->layout == LBRS_LAYOUT_ROWS;
+}
+// Cell slots of one population buffer (the blocked 1D layout pads the last block).
+static long long fcells(const lbrs_params* p) {
+    if (blocked1d(p)) return ((long long)p->nx + BLOCK1D - 1) / BLOCK1D * BLOCK1D;
+    return (long long)p->nx * p->ny;
+}
 static int nk(const lbrs_params* p) {
     return p->law == LBRS_LAW_SCALAR ? 1 : (p->model == LBRS_D2Q4 ? 4 : 3);
 }
@@ -97,6 +107,10 @@ static CellArgs cell_args(const lbrs_ctx* c) {
     a.law = c->P.law;
     for (int k = 0; k < 4; ++k) a.sc[k] = c->P.scalar_flux[k];
     a.code = c->codes;
+    if (blocked1d(&c->P)) {
+        a.row = BLOCK1D;
+        a.fcells = fcells(&c->P);
+    }
     return a;
 }
 
@@ -165,7 +179,7 @@ int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes, siz
     int rc = check_params(p);
     if (rc) return rc;
     size_t cells = (size_t)p->nx * (size_t)p->ny;
-    if (f_bytes) *f_bytes = sizeof(double) * (size_t)nq(p->model) * nk(p) * cells;
+    if (f_bytes) *f_bytes = sizeof(double) * (size_t)nq(p->model) * nk(p) * (size_t)fcells(p);
     if (u_bytes) *u_bytes = sizeof(double) * (size_t)nk(p) * cells;
     if (scratch_bytes)
         *scratch_bytes = codes_offset() + (p->solid ? (2 * cells + 255) / 256 * 256 : 0);
@@ -252,7 +266,10 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     c->K = nk(p);
     c->dim = p->model == LBRS_D2Q4 ? 2 : 1;
     c->plane = (long long)p->nx * p->ny;
-    if (p->layout == LBRS_LAYOUT_ROWS) {
+    if (blocked1d(p)) {
+        c->ps = BLOCK1D;
+        c->rs = (long long)c->Q * c->K * BLOCK1D;
+    } else if (p->layout == LBRS_LAYOUT_ROWS) {
         c->ps = p->nx;
         c->rs = (long long)c->Q * c->K * p->nx;
     } else {
@@ -454,6 +471,7 @@ static ScalarArgs scalar_args(const lbrs_ctx* c, double t_end) {
         a.dir[s] = c->P.bc[s] == LBRS_BC_DIRICHLET ? c->P.dirichlet[s] : nullptr;
         a.sc[s] = c->P.scalar_flux[s];
     }
+    a.blocked = blocked1d(&c->P) ? 1 : 0;
     return a;
 }
 
@@ -473,6 +491,7 @@ static Step1DArgs step1d_args(const lbrs_ctx* c, double t_end, int max_steps) {
     a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
     a.periodic = c->P.bc[0] == LBRS_BC_PERIODIC;
     a.max_steps = max_steps;
+    a.blocked = blocked1d(&c->P) ? 1 : 0;
     return a;
 }
 

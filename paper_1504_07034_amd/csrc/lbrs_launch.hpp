@@ -39,12 +39,22 @@ enum : unsigned {
     CODE_SOLID = 0x8000u
 };
 
+// 1D population layouts: planar, element (p, x) at p*nx + x, or blocked,
+// the planes of each 64-cell block contiguous: (x/64)*QK*64 + p*64 + x%64
+// (the last block padded).
+static constexpr int BLOCK1D = 64;
+__host__ __device__ inline long long ofs1d(bool blocked, long long plane, long long bstride, int p,
+                                          long long x) {
+    return blocked ? (x >> 6) * bstride + p * BLOCK1D + (x & (BLOCK1D - 1)) : p * plane + x;
+}
+
 struct Step1DArgs {
     double* f0;
     double* f1;
     DevState* st;
     long long plane;   // nx
     int nx;
+    int blocked;       // blocked 1D layout (block stride Q*3*64)
     long long launch;
     double dx, cfl, omega, gamma, t_end;
     int lam_mode;
@@ -63,7 +73,15 @@ struct CellArgs {
     int law = LAW_EULER;                     // LAW_SCALAR: one conserved scalar u
     double sc[4] = {0.0, 0.0, 0.0, 0.0};     // g1 = sc0 u + sc1 u^2/2, g2 = sc2 u + sc3 u^2/2
     const unsigned short* code = nullptr;    // body node codes (solid cells are skipped)
+    int row = 0;             // cells per layout row (0: nx; the blocked 1D layout: 64)
+    long long fcells = 0;    // cell slots of a population buffer (0: plane; padded when blocked)
 };
+
+// Offset of population plane p of cell c (row-major cell index).
+__host__ __device__ inline long long cell_ofs(const CellArgs& a, int p, long long c) {
+    const int row = a.row > 0 ? a.row : a.nx;
+    return p * a.ps + (c / row) * a.rs + c % row;
+}
 
 // One step of a scalar law on the D2Q4 lattice (row-marching tiles) or on the
 // D1Q2 / D1Q3 lattice (LDS tiles); the time-state protocol is the Euler step's.
@@ -80,6 +98,7 @@ struct ScalarArgs {
     int bc[4];
     const double* dir[4];   // prescribed u along Dirichlet sides ([ny] x-sides, [nx] y-sides)
     double sc[4];
+    int blocked;            // 1D: blocked layout (rs = Q*64 is the block stride)
 };
 
 struct AdjArgs {

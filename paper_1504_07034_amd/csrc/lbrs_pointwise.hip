@@ -7,10 +7,6 @@
 
 namespace lbrs {
 
-// offset of population plane p at cell c = y*nx + x
-__device__ inline long long fofs(long long ps, long long rs, int nx, int p, long long c) {
-    return p * ps + (c / nx) * rs + (c % nx);
-}
 
 __host__ __device__ inline int nq_of(int model) { return model == D1Q2 ? 2 : (model == D1Q3 ? 3 : 4); }
 __host__ __device__ inline int nk_of(int model) { return model == D2Q4 ? 4 : 3; }
@@ -197,7 +193,7 @@ __global__ void init_eq_kernel(CellArgs a, const double* __restrict__ U0, double
             Euler2 e = euler2(U, a.gamma - 1.0);
             collide_d2q4(z, U, e, 1.0 / (4.0 * lam0), 1.0, fs);
             const bool solid = solid_cell(a, c);
-            for (int p = 0; p < 16; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = solid ? 0.0 : fs[p];
+            for (int p = 0; p < 16; ++p) f[cell_ofs(a, p, c)] = solid ? 0.0 : fs[p];
             double Un[4];
             moments_d2q4(fs, Un);
             bound_d2q4(Un, a.gamma, &l);
@@ -209,11 +205,11 @@ __global__ void init_eq_kernel(CellArgs a, const double* __restrict__ U0, double
             double Un[3];
             if (a.model == D1Q2) {
                 collide_1d<2>(z, U, a.gamma - 1.0, 1.0 / (2.0 * lam0), 1.0, fs);
-                for (int p = 0; p < 6; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = fs[p];
+                for (int p = 0; p < 6; ++p) f[cell_ofs(a, p, c)] = fs[p];
                 moments_1d<2>(fs, Un);
             } else {
                 collide_1d<3>(z, U, a.gamma - 1.0, 1.0 / (2.0 * lam0), 1.0, fs);
-                for (int p = 0; p < 9; ++p) f[fofs(a.ps, a.rs, a.nx, p, c)] = fs[p];
+                for (int p = 0; p < 9; ++p) f[cell_ofs(a, p, c)] = fs[p];
                 moments_1d<3>(fs, Un);
             }
             bound_1d(Un, a.gamma, &l);
@@ -233,7 +229,7 @@ __global__ void bound_of_f_kernel(CellArgs a, const double* __restrict__ f, DevS
         const int Q = nq_of(a.model), K = nk_of(a.model);
         double Uc[4] = {0.0, 0.0, 0.0, 0.0};
         double fc[16];
-        for (int p = 0; p < Q * K; ++p) fc[p] = f[fofs(a.ps, a.rs, a.nx, p, c)];
+        for (int p = 0; p < Q * K; ++p) fc[p] = f[cell_ofs(a, p, c)];
         if (a.model == D2Q4) moments_d2q4(fc, Uc);
         else if (a.model == D1Q2) moments_1d<2>(fc, Uc);
         else moments_1d<3>(fc, Uc);
@@ -270,7 +266,7 @@ __global__ void moments_kernel(CellArgs a, const double* __restrict__ f0, const 
     const double* f = st->s[slot].cur ? f1 : f0;
     const int Q = nq_of(a.model), K = nk_of(a.model);
     double fc[16], Uc[4];
-    for (int p = 0; p < Q * K; ++p) fc[p] = f[fofs(a.ps, a.rs, a.nx, p, c)];
+    for (int p = 0; p < Q * K; ++p) fc[p] = f[cell_ofs(a, p, c)];
     if (a.model == D2Q4) moments_d2q4(fc, Uc);
     else if (a.model == D1Q2) moments_1d<2>(fc, Uc);
     else moments_1d<3>(fc, Uc);
@@ -283,7 +279,7 @@ __global__ void pool_moments_kernel(CellArgs a, const double* __restrict__ f, do
     if (c >= a.plane) return;
     const int Q = nq_of(a.model), K = nk_of(a.model);
     double fc[16], Uc[4];
-    for (int p = 0; p < Q * K; ++p) fc[p] = f[fofs(a.ps, a.rs, a.nx, p, c)];
+    for (int p = 0; p < Q * K; ++p) fc[p] = f[cell_ofs(a, p, c)];
     if (a.model == D2Q4) moments_d2q4(fc, Uc);
     else if (a.model == D1Q2) moments_1d<2>(fc, Uc);
     else moments_1d<3>(fc, Uc);
@@ -307,10 +303,10 @@ __global__ void copy_f_kernel(long long count, double* __restrict__ f0, double* 
 __device__ inline double density_at(const CellArgs& a, const double* f, long long c) {
     const int Q = nq_of(a.model), K = nk_of(a.model);
     if (Q == 4)
-        return (f[fofs(a.ps, a.rs, a.nx, 0 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 2 * K, c)]) +
-               (f[fofs(a.ps, a.rs, a.nx, 1 * K, c)] + f[fofs(a.ps, a.rs, a.nx, 3 * K, c)]);
+        return (f[cell_ofs(a, 0 * K, c)] + f[cell_ofs(a, 2 * K, c)]) +
+               (f[cell_ofs(a, 1 * K, c)] + f[cell_ofs(a, 3 * K, c)]);
     double rho = 0.0;
-    for (int i = 0; i < Q; ++i) rho += f[fofs(a.ps, a.rs, a.nx, i * K, c)];
+    for (int i = 0; i < Q; ++i) rho += f[cell_ofs(a, i * K, c)];
     return rho;
 }
 
@@ -327,7 +323,7 @@ __global__ void window_seed_kernel(CellArgs a, const double* __restrict__ f0,
     const bool in = x >= ix0 && x < ix1 && y >= iy0 && y < iy1;
     const double g = in ? 2.0 * density_at(a, f, c) : 0.0;
     for (int i = 0; i < Q; ++i)
-        for (int k = 0; k < K; ++k) fbar[fofs(a.ps, a.rs, a.nx, i * K + k, c)] = k == 0 ? g : 0.0;
+        for (int k = 0; k < K; ++k) fbar[cell_ofs(a, i * K + k, c)] = k == 0 ? g : 0.0;
 }
 
 // J = sum over the window of rho^2, by one workgroup in a fixed order (the
@@ -394,7 +390,7 @@ __global__ void adjoint_init_d2q4(AdjArgs a, const double* __restrict__ fb0,
     if (c >= a.plane) return;
     const long long P = a.plane;
     double fb[16], U[4], out[4];
-    for (int p = 0; p < 16; ++p) fb[p] = fb0[fofs(a.ps, a.rs, a.nx, p, c)];
+    for (int p = 0; p < 16; ++p) fb[p] = fb0[p * a.ps + (c / a.nx) * a.rs + c % a.nx];
     for (int k = 0; k < 4; ++k) U[k] = U0[k * P + c];
     adjoint_init_cell_d2q4(fb, U, a.gamma, a.st->lam_fixed, out);
     for (int k = 0; k < 4; ++k) Ub[k * P + c] = out[k];
@@ -445,7 +441,7 @@ hipError_t launch_init(const CellArgs& a, const double* U0, double* f0, DevState
 hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st, const double* ext,
                         double t, long long n, bool per_step, hipStream_t s) {
     const int Q = nq_of(a.model), K = a.law == LAW_SCALAR ? 1 : nk_of(a.model);
-    long long cnt = (long long)Q * K * a.plane;
+    long long cnt = (long long)Q * K * (a.fcells > 0 ? a.fcells : a.plane);
     hipLaunchKernelGGL(set_slot0_kernel, dim3(1), dim3(64), 0, s, st, t, n);
     hipLaunchKernelGGL(copy_f_kernel, grid1(cnt, 256), dim3(256), 0, s, cnt, f0, f1, st, 0,
                        const_cast<double*>(ext), 1);
@@ -458,7 +454,7 @@ hipError_t launch_set_f(const CellArgs& a, double* f0, double* f1, DevState* st,
 hipError_t launch_get_f(const CellArgs& a, double* f0, double* f1, const DevState* st, int slot,
                         double* ext, hipStream_t s) {
     const int Q = nq_of(a.model), K = a.law == LAW_SCALAR ? 1 : nk_of(a.model);
-    long long cnt = (long long)Q * K * a.plane;
+    long long cnt = (long long)Q * K * (a.fcells > 0 ? a.fcells : a.plane);
     hipLaunchKernelGGL(copy_f_kernel, grid1(cnt, 256), dim3(256), 0, s, cnt, f0, f1, st, slot, ext, 0);
     return hipGetLastError();
 }

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(64 * WPB) void scalar2d_step(ScalarArgs a) {
 // values of those cells and of one halo cell on each side go to LDS (lane t
 // forms entries t, t + 256, ...), then every output cell pulls its streamed
 // values from its neighbours' entries.
-template <int Q>
+template <int Q, bool BLOCKED>
 __global__ __launch_bounds__(256) void scalar1d_step(ScalarArgs a) {
     constexpr int E = STILE1D + 2;  // LDS entry e holds cell x0 - 1 + e
     __shared__ double fsl[Q][E];
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void scalar1d_step(ScalarArgs a) {
         const int xl = map_index(x, nx, periodic);
         double f[Q], fe[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p) f[p] = fin[p * a.ps + xl];
+        for (int p = 0; p < Q; ++p) f[p] = fin[ofs1d(BLOCKED, a.ps, a.rs, p, xl)];
         const bool ghost = (x < 0 && a.bc[0] == BC_DIRICHLET) || (x >= nx && a.bc[1] == BC_DIRICHLET);
         if (ghost) {
             scalar_eq_1d<Q>((x < 0 ? a.dir[0] : a.dir[1])[0], a.sc, c2lam, fe);
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void scalar1d_step(ScalarArgs a) {
             if (Q == 3) g[1] = fsl[1][j + 1];  // rest
             g[Q - 1] = fsl[Q - 1][j];       // s = +1: from x - 1
 #pragma unroll
-            for (int p = 0; p < Q; ++p) fout[p * a.ps + x] = g[p];
+            for (int p = 0; p < Q; ++p) fout[ofs1d(BLOCKED, a.ps, a.rs, p, x)] = g[p];
             const double un = scalar_sum<Q>(g);
             const bool b = !isfinite(un);
             bad |= b;
@@ -325,9 +325,7 @@ __global__ void scalar_dirichlet_bound_kernel(CellArgs a, ScalarSides ds, DevSta
     }
 }
 
-__device__ inline long long sofs(const CellArgs& a, int p, long long c) {
-    return p * a.ps + (c / a.nx) * a.rs + c % a.nx;
-}
+__device__ inline long long sofs(const CellArgs& a, int p, long long c) { return cell_ofs(a, p, c); }
 
 // f^0 = f^eq(u0) at lambda*(u0)/cfl (or the user's speed); the bound of
 // sum f^0 into reduction slot 0; time slot 0.
@@ -461,10 +459,13 @@ int scalar2d_blocks_per_cu(int wpb) {
 
 hipError_t launch_scalar_step1d(const ScalarArgs& a, int q, hipStream_t s) {
     const dim3 grid((unsigned)((a.nx + STILE1D - 1) / STILE1D));
-    if (q == 2)
-        hipLaunchKernelGGL(scalar1d_step<2>, grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(scalar1d_step<3>, grid, dim3(256), 0, s, a);
+    if (a.blocked) {
+        if (q == 2) hipLaunchKernelGGL((scalar1d_step<2, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((scalar1d_step<3, true>), grid, dim3(256), 0, s, a);
+    } else {
+        if (q == 2) hipLaunchKernelGGL((scalar1d_step<2, false>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((scalar1d_step<3, false>), grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -3,7 +3,8 @@
 // Two forms of the same step (Sec. II.A discrete update with exact hopping,
 // Sec. II.C equilibria and the Jin-Xin wave-speed bound):
 //
-//  * step1d_tile: one launch per step for long domains.  A 256-lane workgroup
+//  * step1d_tile: one launch per step for long domains (planar or blocked
+//    1D population layout).  A 256-lane workgroup
 //    owns 512 output cells (two per lane) plus one halo cell on each side; the
 //    lanes form the post-collision populations of those cells, stage them in
 //    LDS, and pull f_i^{n+1}(x) = f*_i(x - s_i) from the neighbours' entries.
@@ -20,7 +21,7 @@ namespace lbrs {
 
 static constexpr int TILE1D = 512;  // output cells per workgroup (2 per lane)
 
-template <int Q>
+template <int Q, bool BLOCKED>
 __global__ __launch_bounds__(256) void step1d_tile(Step1DArgs a) {
     constexpr int QK = Q * 3;
     constexpr int E = TILE1D + 2;  // LDS entry e holds cell x0 - 1 + e
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void step1d_tile(Step1DArgs a) {
         const int xl = map_index(x0 - 1 + e, a.nx, a.periodic != 0);
         double f[QK], U[3], fs[QK];
 #pragma unroll
-        for (int p = 0; p < QK; ++p) f[p] = fin[p * a.plane + xl];
+        for (int p = 0; p < QK; ++p) f[p] = fin[ofs1d(BLOCKED, a.plane, QK * BLOCK1D, p, xl)];
         moments_1d<Q>(f, U);
         collide_1d<Q>(f, U, gm1, c2lam, a.omega, fs);
 #pragma unroll
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(256) void step1d_tile(Step1DArgs a) {
                 }
             }
 #pragma unroll
-            for (int p = 0; p < QK; ++p) fout[p * a.plane + x] = g[p];
+            for (int p = 0; p < QK; ++p) fout[ofs1d(BLOCKED, a.plane, QK * BLOCK1D, p, x)] = g[p];
             double Un[3], l;
             moments_1d<Q>(g, Un);
             const bool ok = bound_1d(Un, a.gamma, &l);
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(1024) void run1d_persistent(Step1DArgs a) {
         int j = tid + c * nt;
         int jl = j < N ? j : N - 1;
 #pragma unroll
-        for (int p = 0; p < QK; ++p) f[c][p] = fin[p * a.plane + jl];
+        for (int p = 0; p < QK; ++p)
+            f[c][p] = fin[ofs1d(a.blocked != 0, a.plane, QK * BLOCK1D, p, jl)];
     }
 
     int steps = 0;
@@ -193,7 +195,8 @@ __global__ __launch_bounds__(1024) void run1d_persistent(Step1DArgs a) {
             int j = tid + c * nt;
             if (j < N) {
 #pragma unroll
-                for (int p = 0; p < QK; ++p) fout[p * a.plane + j] = f[c][p];
+                for (int p = 0; p < QK; ++p)
+                    fout[ofs1d(a.blocked != 0, a.plane, QK * BLOCK1D, p, j)] = f[c][p];
             }
         }
     }
@@ -217,8 +220,13 @@ __global__ __launch_bounds__(1024) void run1d_persistent(Step1DArgs a) {
 
 hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s) {
     int nblocks = (a.nx + TILE1D - 1) / TILE1D;
-    if (Q == 2) hipLaunchKernelGGL(step1d_tile<2>, dim3(nblocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(step1d_tile<3>, dim3(nblocks), dim3(256), 0, s, a);
+    if (a.blocked) {
+        if (Q == 2) hipLaunchKernelGGL((step1d_tile<2, true>), dim3(nblocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((step1d_tile<3, true>), dim3(nblocks), dim3(256), 0, s, a);
+    } else {
+        if (Q == 2) hipLaunchKernelGGL((step1d_tile<2, false>), dim3(nblocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((step1d_tile<3, false>), dim3(nblocks), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

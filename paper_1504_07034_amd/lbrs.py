@@ -355,19 +355,35 @@ class Sim:
         return U[:, 0, :].contiguous()
 
     @property
+    def blocked(self) -> bool:
+        """The blocked 1D layout: the populations of each 64-cell block contiguous."""
+        return self.layout == LBRS_LAYOUT_ROWS and self.model != LBRS_D2Q4
+
+    @property
     def f_shape(self):
         """Shape of population-shaped tensors in this context's layout."""
+        if self.blocked:
+            return ((self.nx + 63) // 64, self.Q, self.K, 64)
         if self.layout == LBRS_LAYOUT_ROWS:
             return (self.ny, self.Q, self.K, self.nx)
         return (self.Q, self.K, self.ny, self.nx)
 
     def to_planar(self, f: torch.Tensor) -> torch.Tensor:
         """[Q][K][ny][nx] view/copy of a population tensor of this context."""
+        if self.blocked:
+            nb = (self.nx + 63) // 64
+            g = f.reshape(nb, self.Q, self.K, 64).permute(1, 2, 0, 3).reshape(self.Q, self.K, -1)
+            return g[:, :, :self.nx].reshape(self.Q, self.K, 1, self.nx).contiguous()
         if self.layout == LBRS_LAYOUT_ROWS:
             return f.reshape(self.ny, self.Q, self.K, self.nx).permute(1, 2, 0, 3).contiguous()
         return f.reshape(self.Q, self.K, self.ny, self.nx)
 
     def from_planar(self, f: torch.Tensor) -> torch.Tensor:
+        if self.blocked:
+            nb = (self.nx + 63) // 64
+            g = torch.zeros((self.Q, self.K, nb * 64), dtype=f.dtype, device=f.device)
+            g[:, :, :self.nx] = f.reshape(self.Q, self.K, self.nx)
+            return g.reshape(self.Q, self.K, nb, 64).permute(2, 0, 1, 3).contiguous()
         if self.layout == LBRS_LAYOUT_ROWS:
             return f.reshape(self.Q, self.K, self.ny, self.nx).permute(2, 0, 1, 3).contiguous()
         return f.reshape(self.Q, self.K, self.ny, self.nx).contiguous()

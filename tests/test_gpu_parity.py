@@ -100,6 +100,48 @@ def test_1d_long_tubes(n, model, periodic):
     _compare(w, max_steps=25, sides=sides, name=f"1d long n{n} m{model} p{periodic}")
 
 
+@pytest.mark.parametrize("n,model,periodic", [(400, wl.D1Q3, False), (400, wl.D1Q2, True),
+                                               (5003, wl.D1Q3, False), (62001, wl.D1Q2, True),
+                                               (400063, wl.D1Q3, True)])
+def test_1d_blocked_layout(n, model, periodic):
+    """The blocked 1D layout (LAYOUT_ROWS: the planes of each 64-cell block
+    contiguous, last block padded) in the one-workgroup form and the tiled
+    form, ragged against the block, periodic wrap across the ends."""
+    w = wl.sod(n, model=model, omega=1.3, t_end=0.02)
+    sides = (1, 1, 0, 0) if periodic else (0, 0, 0, 0)
+    _compare(w, max_steps=40, sides=sides, layout=1, name=f"1d blocked n{n} m{model} p{periodic}")
+
+
+@pytest.mark.parametrize("n", [300, 5003])
+def test_1d_layouts_bitwise_and_f_round_trip(n):
+    """Planar and blocked 1D layouts give the same bits (moments, populations,
+    state); populations read with get_f and written back with set_f in the
+    blocked layout continue the run exactly."""
+    w = wl.sod(n, omega=1.4, t_end=0.05)
+    outs = []
+    for layout in (0, 1):
+        sim = gpu_sim(w, layout=layout)
+        sim.init_primitive(w.W)
+        sim.step(30, w.t_end)
+        outs.append((sim.moments(), sim.to_planar(sim.get_f()), sim.state()))
+        sim.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+    sim = gpu_sim(w, layout=1)
+    sim.init_primitive(w.W)
+    sim.step(10, w.t_end)
+    st = sim.state()
+    f = sim.from_planar(sim.to_planar(sim.get_f()))
+    sim.step(20, w.t_end)
+    ref = sim.moments().clone()
+    sim.set_f(f, st["t"], st["nsteps"])
+    sim.step(20, w.t_end)
+    assert torch.equal(sim.moments(), ref)
+    assert sim.state()["nsteps"] == 30
+    sim.close()
+
+
 @pytest.mark.parametrize("model,omega", [(wl.D1Q3, 1.0), (wl.D1Q2, 1.6)])
 def test_steady_shock(model, omega):
     """The paper's steady shock (M = 2, 400 points on [-1, 1]) to t = 2."""

@@ -57,6 +57,16 @@ def test_burgers_1d(model, uL, uR, n):
     compare(w, t_end=w.t_end, name=f"burgers m{model} ({uL},{uR}) n{n}")
 
 
+@pytest.mark.parametrize("model", [wl.D1Q2, wl.D1Q3])
+def test_burgers_1d_layouts(model):
+    """Planar and blocked (64-cell blocks) 1D layouts, a tube ragged against
+    both the block and the tile: same result as the oracle, same bits."""
+    w = wl.burgers_riemann(5003, 1.0, -0.5, t_end=0.3, model=model)
+    U0, _ = compare(w, t_end=w.t_end, layout=0, name=f"burgers planar m{model}")
+    U1, _ = compare(w, t_end=w.t_end, layout=1, name=f"burgers blocked m{model}")
+    assert np.array_equal(U0, U1)
+
+
 @pytest.mark.parametrize("omega", [0.7, 1.6])
 def test_burgers_1d_omega_and_dirichlet(omega):
     """Prescribed u on both sides (Dirichlet), over-/under-relaxed."""
