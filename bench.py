@@ -487,12 +487,12 @@ def bodies_2d(nx=7680, ny=2560, steps=200, warmup=20):
     return out
 
 
-def scalar_laws(n2=8192, n1=1 << 24, steps=200, warmup=20):
+def scalar_laws(n2=8192, n1=1 << 26, steps=200, warmup=20):
     """Scalar LBRS: the 2D Burgers case 1 (prescribed sides) at n2 x n2 on
     D2Q4 (64 B per lattice update: 4 populations in and out) with an autotuned
-    launch shape, and the 1D Burgers shock tube on n1 cells, D1Q2 (32 B per
-    update), planar 1D layout (and the blocked one for comparison).  HIP
-    events."""
+    launch shape, and the 1D Burgers shock tube on n1 cells (the 2D case's
+    cell count), D1Q2 (32 B per update), planar 1D layout (and the blocked one
+    for comparison).  HIP events."""
     import torch
 
     from paper_1504_07034_amd import autotune, lbrs
