@@ -26,8 +26,8 @@ METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
 # (automatic row segments, row-interleaved layout), valid for the kernel source
 # they were taken on (profiles/step2d_d2q4_riemann4096.md); null once the
 # source changes or for a shape not profiled.
-TRAFFIC_BYTES = {"16,0": 4.433e9, "16,1": 4.396e9, "12,1": 4.392e9, "8,0": 4.485e9, "8,1": 4.383e9,
-                 "6,1": 4.405e9}
+TRAFFIC_BYTES = {"16,0": 4.433e9, "16,1": 4.396e9, "12,0": 4.418e9, "12,1": 4.392e9, "8,0": 4.486e9,
+                 "8,1": 4.382e9, "6,0": 4.517e9, "6,1": 4.407e9, "4,0": 4.538e9, "4,1": 4.481e9}
 TRAFFIC_SOURCE_HASH = "d34d3ce179d013e0"
 
 
@@ -680,9 +680,12 @@ def main():
             sim.set_tile(shape["rows"], shape["wpb"], shape["alt"])
 
     if args.rows < 0:  # autotune the launch shape (untimed), then start over
+        # automatic row segments (one balanced round of the resident waves);
+        # every (waves per workgroup, march order) candidate has its HBM
+        # traffic measured, so the record carries it for whichever wins
         sim.init(U0)
         sim.step(20, t_end)
-        best = autotune.tune(sim, t_end, use_cache=False)
+        best = autotune.tune(sim, t_end, use_cache=False, rows=(0,))
         shape = {"rows": best["rows"], "wpb": best["wpb"], "alt": best["alt"]}
         print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']}) {c['ms']:.3f} ms"
                                        for c in best["candidates"]), file=sys.stderr, flush=True)
