@@ -685,7 +685,7 @@ def main():
         # traffic measured, so the record carries it for whichever wins
         sim.init(U0)
         sim.step(20, t_end)
-        best = autotune.tune(sim, t_end, use_cache=False, rows=(0,))
+        best = autotune.tune(sim, t_end, steps=20, use_cache=False, rows=(0,))
         shape = {"rows": best["rows"], "wpb": best["wpb"], "alt": best["alt"]}
         print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']}) {c['ms']:.3f} ms"
                                        for c in best["candidates"]), file=sys.stderr, flush=True)
