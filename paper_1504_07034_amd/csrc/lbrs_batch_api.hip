@@ -60,6 +60,8 @@ int check_unit(const lbrs_params* p, int model) {
     return LBRS_OK;
 }
 
+void schedule_jobs(const std::vector<double>& work, int grid, Plan& P);
+
 int make_plan(int nunits, const lbrs_params* units, const double* t_end, int chunk, int grid, Plan& P) {
     if (nunits < 1 || !units || chunk < 3 || grid < 1) return LBRS_E_INVAL;
     const int model = units[0].model;
@@ -90,14 +92,31 @@ int make_plan(int nunits, const lbrs_params* units, const double* t_end, int chu
         P.slot_off[b] = P.nslots;
         P.nslots += 2LL * u.g;
         gmax = std::max(gmax, u.g);
-        // relative work of a member: steps ~ t_end * n / (cfl * L), times its cells
+        // relative work of a member before the lattice speeds are known:
+        // steps ~ t_end * n / (cfl * L), times its cells
         double steps = isfinite(te) ? te * u.n / ((units[b].cfl > 0 ? units[b].cfl : 1.0) *
                                                   (units[b].x1 - units[b].x0))
                                     : 1.0;
         work[b] = steps * (double)((u.n + u.g - 1) / u.g) + 1.0;
     }
     if (gmax > grid || gmax > MAXTEAM) return LBRS_E_INVAL;  // a team must be co-resident
-    // list schedule: largest work first, each team on the earliest-free workgroups
+    schedule_jobs(work, grid, P);
+    P.bytes[0] = align256(sizeof(Unit1D) * nunits);
+    P.bytes[1] = align256(sizeof(UnitState1D) * nunits);
+    P.bytes[2] = align256(sizeof(unsigned) * COUNTER_STRIDE * (size_t)nunits);
+    P.bytes[3] = align256(sizeof(long long) * nunits);
+    P.bytes[4] = align256(sizeof(EdgeSlot) * (size_t)P.nslots);
+    P.bytes[5] = align256(sizeof(Job1D) * P.jobs.size());
+    P.bytes[6] = align256(sizeof(int) * (grid + 1));
+    P.total_bytes = 0;
+    for (int i = 0; i < 7; ++i) P.total_bytes += P.bytes[i];
+    return LBRS_OK;
+}
+
+// List schedule of the member jobs over the persistent workgroups: largest
+// work first, each team on the earliest-free workgroups (starting together).
+void schedule_jobs(const std::vector<double>& work, int grid, Plan& P) {
+    const int nunits = (int)P.units.size();
     std::vector<int> order(nunits);
     for (int b = 0; b < nunits; ++b) order[b] = b;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
@@ -123,20 +142,11 @@ int make_plan(int nunits, const lbrs_params* units, const double* t_end, int chu
         }
     }
     P.job_begin.assign(grid + 1, 0);
+    P.jobs.clear();
     for (int w = 0; w < grid; ++w) {
         P.job_begin[w + 1] = P.job_begin[w] + (int)per[w].size();
         P.jobs.insert(P.jobs.end(), per[w].begin(), per[w].end());
     }
-    P.bytes[0] = align256(sizeof(Unit1D) * nunits);
-    P.bytes[1] = align256(sizeof(UnitState1D) * nunits);
-    P.bytes[2] = align256(sizeof(unsigned) * COUNTER_STRIDE * (size_t)nunits);
-    P.bytes[3] = align256(sizeof(long long) * nunits);
-    P.bytes[4] = align256(sizeof(EdgeSlot) * (size_t)P.nslots);
-    P.bytes[5] = align256(sizeof(Job1D) * P.jobs.size());
-    P.bytes[6] = align256(sizeof(int) * (grid + 1));
-    P.total_bytes = 0;
-    for (int i = 0; i < 7; ++i) P.total_bytes += P.bytes[i];
-    return LBRS_OK;
 }
 
 int default_threads(int chunk) {
@@ -220,10 +230,27 @@ int lbrs_batch_init(lbrs_batch** out, int nunits, const lbrs_params* units, cons
     b->graph_steps = -1;
     hipStream_t st = b->stream;
     bool ok = hipMemcpyAsync(b->d_units, P.units.data(), sizeof(Unit1D) * nunits, hipMemcpyHostToDevice, st) == hipSuccess &&
-              hipMemcpyAsync(b->d_slot_off, P.slot_off.data(), sizeof(long long) * nunits, hipMemcpyHostToDevice, st) == hipSuccess &&
-              hipMemcpyAsync(b->d_jobs, P.jobs.data(), sizeof(Job1D) * P.jobs.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-              hipMemcpyAsync(b->d_job_begin, P.job_begin.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+              hipMemcpyAsync(b->d_slot_off, P.slot_off.data(), sizeof(long long) * nunits, hipMemcpyHostToDevice, st) == hipSuccess;
     if (ok) ok = launch_batch1d_init(b->d_units, b->d_units, nunits, d_U0, d_f, b->total, b->d_states, Q, st) == hipSuccess;
+    // Reschedule with the initial lattice speeds: a unit takes about
+    // t_end * lambda_0 * n / L steps (lambda_0 = lambda*(U0)/cfl or the
+    // user's speed), each member's work is that times its cells.
+    std::vector<UnitState1D> s0(nunits);
+    if (ok) ok = hipMemcpyAsync(s0.data(), b->d_states, sizeof(UnitState1D) * nunits, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                 hipStreamSynchronize(st) == hipSuccess;
+    if (ok) {
+        std::vector<double> work(nunits);
+        for (int u = 0; u < nunits; ++u) {
+            const Unit1D& un = P.units[u];
+            const double L = un.dx * un.n;
+            const double lam = isfinite(s0[u].lam_used) && s0[u].lam_used > 0.0 ? s0[u].lam_used : 1.0;
+            const double steps = isfinite(un.t_end) ? un.t_end * lam * un.n / L : 1.0;
+            work[u] = steps * (double)((un.n + un.g - 1) / un.g) + 1.0;
+        }
+        schedule_jobs(work, grid, P);
+        ok = hipMemcpyAsync(b->d_jobs, P.jobs.data(), sizeof(Job1D) * P.jobs.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(b->d_job_begin, P.job_begin.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+    }
     // the host plan must outlive the asynchronous copies
     if (ok) ok = hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
