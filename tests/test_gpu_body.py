@@ -154,6 +154,29 @@ def test_box_with_wall_sides(layout):
     check(*compare(w, max_steps=150, layout=layout, name=f"box l{layout}"), w)
 
 
+@pytest.mark.parametrize("case", ["forward_step", "shock_diffraction"])
+def test_body_frozen_lattice_speed(case):
+    """Frozen lattice speed lambda*(U0)/cfl: the initial bound skips solid
+    cells and includes the prescribed states on both sides."""
+    w = wl.forward_step(omega=1.3) if case == "forward_step" else wl.shock_diffraction(200)
+    Pr = oracle_body_problem(w)
+    Pr.lam_mode = oracle.LAM_FROZEN
+    ref = oracle.run(Pr, oracle.prim_to_cons(Pr, w.W), max_steps=150, record=False)
+    sim = lbrs.Sim(w.model, w.nx, w.ny, domain=w.domain, gamma=w.gamma, omega=w.omega, cfl=w.cfl,
+                   bc=tuple(w.sides), lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT, layout=1,
+                   dirichlet_W=w.dirichlet_W, solid=w.solid)
+    sim.init_primitive(w.W)
+    sim.step(150)
+    st = sim.state()
+    U = sim.moments().cpu().numpy()
+    sim.close()
+    err = max_abs(U, ref.U)
+    report(f"{case} frozen", steps=st["nsteps"], err=err, status=(st["rc"], ref.status))
+    assert ref.status == oracle.OK and st["rc"] == 0 and st["nsteps"] == ref.nsteps == 150
+    assert st["t"] == pytest.approx(ref.t, rel=1e-12, abs=0)
+    assert err <= TOL
+
+
 def test_solid_initial_state_ignored():
     """NaN in the solid cells' U0 changes nothing (they are skipped)."""
     w = synthetic(96, 64, (T, T, W, W), seed=4)
