@@ -319,6 +319,28 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);
  * effect for later calls; LBRS_E_INVAL for values outside these sets. */
 int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alternate);
 
+/* Time steps per launch of the 2D Euler step: 1 (the default) or 2.  With 2
+ * each wavefront keeps the rows of f^{n+1} it has just streamed in registers
+ * and streams them once more (the same Sec. II.D update, twice), so f^n is
+ * read and f^{n+2} written once per two steps: half the HBM traffic per step.
+ * The second step's lattice speed is known with FROZEN_INIT or USER speeds.
+ * With PER_STEP speeds it is the global bound of f^{n+1}: a launch takes it
+ * equal to the current one and the next launch checks the bound of f^{n+1}
+ * bit for bit; on a mismatch (or a non-physical f^{n+1}) that launch goes
+ * back to f^n, which the first launch left intact, and redoes the steps with
+ * the bound now known.  Either way t, the step count, every lattice speed,
+ * the status, fail_step and the reported state after each lbrs_step call are
+ * those of single steps (the populations agree with them to rounding: the
+ * two paths are different kernels).  lbrs_step(c, max_steps, t_end) then
+ * enqueues a one-thread set-up kernel and up to max_steps launches (with a
+ * fixed speed max_steps/2 + 1), of which the ones beyond the work done exit
+ * at once.  The shape set by lbrs_set_tile applies (strips of at most 60
+ * columns; automatic segments of at least 4 rows; alternate is ignored).
+ * lbrs_step_tape and the gradient calls' recompute steps stay single steps.
+ * LBRS_E_INVAL for other values; LBRS_E_STATE with 2 for a 1D, scalar-law,
+ * body or DIRICHLET context.  Takes effect for later calls. */
+int lbrs_set_fusion(lbrs_ctx* c, int steps_per_launch);
+
 /* ------------------------------------------------------------------------
  * Ragged batch of independent 1D units (shock tubes) in one persistent launch.
  * Every unit is a full problem of the paper's 1D scheme (Sec. II.A update,

@@ -48,6 +48,7 @@ class GradientSpec:
     segment: int | None = None  # checkpoint spacing; default ceil(sqrt(T))
     lam: float | None = None    # frozen lattice speed; set by prepare()
     tile: tuple | None = None   # (rows_per_tile, waves_per_block, alternate) of the step kernel
+    fuse: int = 1               # steps per launch of the plain forward steps (1, or 2 fused)
 
     def params(self, mode, lam_user=0.0):
         return lbrs.make_params(lbrs.LBRS_D2Q4, self.n, self.n, (0.0, 1.0, 0.0, 1.0), self.gamma,
@@ -80,6 +81,7 @@ class GradientRunner:
                             lambda_user=spec.lam, layout=spec.layout, device=dev)
         if spec.tile is not None:
             self.sim.set_tile(*spec.tile)
+        self.sim.set_fusion(spec.fuse)
         nck = math.ceil(spec.steps / spec.seg)
         fcount = 16 * n * n
         self.ckpt = torch.empty(nck * fcount, dtype=torch.float64, device=dev)
@@ -120,6 +122,7 @@ class GradientRunner:
         self.sim.init(self.U0)
         best = autotune.tune(self.sim, steps=steps, use_cache=False)
         self.spec.tile = (best["rows"], best["wpb"], best["alt"])
+        self.spec.fuse = best["fuse"]
         return best
 
     def close(self):

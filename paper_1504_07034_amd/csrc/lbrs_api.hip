@@ -31,6 +31,9 @@ struct lbrs_ctx {
     bool dir;            // some side is DIRICHLET
     int sbpc[17];        // resident scalar-step workgroups per CU, by waves per block
     unsigned short* codes;  // body node codes in the scratch area (null: no body)
+    int fuse;            // 2D Euler: time steps per launch (1, or 2 fused)
+    PairState* pst;      // record of the fused launches (scratch area, behind the time state)
+    int pbpc[17];        // resident fused-kernel workgroups per CU, by waves per block
 };
 
 static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
@@ -170,8 +173,11 @@ static int build_body_codes(const lbrs_params* p, unsigned short* codes) {
     return any_fluid ? LBRS_OK : LBRS_E_INVAL;
 }
 
-// Byte offset of the body codes in the scratch area.
-static size_t codes_offset() { return (sizeof(DevState) + 255) / 256 * 256; }
+// Scratch area: the time state, the record of the fused launches, then the
+// body codes (each at a 256-byte boundary).
+static size_t round256(size_t n) { return (n + 255) / 256 * 256; }
+static size_t pair_offset() { return round256(sizeof(DevState)); }
+static size_t codes_offset() { return pair_offset() + round256(sizeof(PairState)); }
 
 extern "C" {
 
@@ -280,6 +286,8 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
     c->f0 = d_f0;
     c->f1 = d_f1;
     c->st = (DevState*)d_scratch;
+    c->pst = (PairState*)((char*)d_scratch + pair_offset());
+    c->fuse = 1;
     c->stream = (hipStream_t)hip_stream;
     c->launches = 0;
     c->rows_per_tile = 0;
@@ -351,6 +359,15 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
     return LBRS_OK;
 }
 
+int lbrs_set_fusion(lbrs_ctx* c, int steps_per_launch) {
+    if (!c || (steps_per_launch != 1 && steps_per_launch != 2)) return LBRS_E_INVAL;
+    if (steps_per_launch == 2 &&
+        (c->dim != 2 || c->P.law != LBRS_LAW_EULER || c->dir || c->codes))
+        return LBRS_E_STATE;
+    c->fuse = steps_per_launch;
+    return LBRS_OK;
+}
+
 int lbrs_set_stream(lbrs_ctx* c, void* hip_stream) {
     if (!c) return LBRS_E_INVAL;
     c->stream = (hipStream_t)hip_stream;
@@ -419,6 +436,52 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
         a.dir[s] = c->P.bc[s] == LBRS_BC_DIRICHLET ? c->P.dirichlet[s] : nullptr;
     }
     a.code = c->codes;
+    return a;
+}
+
+// Fused two-step launches: strips of at most 60 columns (two halo lanes on
+// each side), segments of at least 4 rows (two halo rows on each side).
+static int pair_max_blocks(const lbrs_ctx* c) {
+    lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
+    int& n = m->pbpc[c->waves_per_block];
+    if (n == 0) n = step2d_pair_blocks_per_cu(c->waves_per_block);
+    return c->cu_count * n;
+}
+
+static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end) {
+    Pair2DArgs a;
+    a.f0 = c->f0;
+    a.f1 = c->f1;
+    a.st = c->st;
+    a.pst = c->pst;
+    a.ps = c->ps;
+    a.rs = c->rs;
+    a.nx = c->P.nx;
+    a.ny = c->P.ny;
+    const int wpb = c->waves_per_block;
+    a.nstrips = ((c->P.nx + 59) / 60 + wpb - 1) / wpb * wpb;
+    a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
+    long long nseg;
+    if (c->rows_per_tile > 0) {
+        nseg = (c->P.ny + c->rows_per_tile - 1) / c->rows_per_tile;
+    } else {
+        nseg = (long long)pair_max_blocks(c) * wpb / a.nstrips;
+        const long long cap = (c->P.ny + 3) / 4;
+        if (nseg > cap) nseg = cap;
+    }
+    if (nseg < 1) nseg = 1;
+    if (nseg > c->P.ny) nseg = c->P.ny;
+    a.nseg = (int)nseg;
+    a.ntiles = a.nstrips * a.nseg;
+    a.launch = c->launches;
+    a.dx = c->dx;
+    a.cfl = c->P.cfl;
+    a.omega = c->P.omega;
+    a.gamma = c->P.gamma;
+    a.t_end = t_end;
+    a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
+    for (int s = 0; s < 4; ++s) a.bc[s] = c->P.bc[s];
+    a.last = 0;
     return a;
 }
 
@@ -505,6 +568,26 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
                                ? launch_scalar_step2d(a, c->waves_per_block, scalar_max_blocks(c),
                                                       c->stream)
                                : launch_scalar_step1d(a, c->Q, c->stream);
+            if (e != hipSuccess) return LBRS_E_HIP;
+            ++c->launches;
+        }
+        return LBRS_OK;
+    }
+    if (c->dim == 2 && c->fuse == 2) {
+        // every launch advances one or two steps, except one that guessed
+        // the next lattice speed wrongly (the launch after it then advances
+        // two), so max_steps launches always suffice; with a fixed speed
+        // nothing is guessed and max_steps/2 + 1 suffice
+        Pair2DArgs a = pair_args(c, t_end);
+        const int nl = a.lam_mode == LAM_PER_STEP ? max_steps : max_steps / 2 + 1;
+        hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), max_steps,
+                                           c->stream);
+        if (e != hipSuccess) return LBRS_E_HIP;
+        const int mb = pair_max_blocks(c);
+        for (int s = 0; s < nl; ++s) {
+            a.launch = c->launches;
+            a.last = s == nl - 1;
+            e = launch_step2d_pair(a, c->waves_per_block, mb, c->stream);
             if (e != hipSuccess) return LBRS_E_HIP;
             ++c->launches;
         }

@@ -27,6 +27,47 @@ struct Step2DArgs {
     const unsigned short* code;  // node codes of a solid body [ny][nx] (or null)
 };
 
+// Fused two-step launches (2D Euler): the second step's lattice speed
+// depends on the global bound of the first step's states, which is known only
+// when the launch has ended.  A launch that guesses it (lambda*_{n+1} taken
+// equal to lambda*_n) or that cannot yet know whether its first step was
+// admissible is tentative: the next launch accepts its result when the
+// recorded bound equals the guess bit for bit and the first step was
+// admissible, else falls back to the state before it.  The record lives in
+// slot (p+1) & 1 beside the time state; the first step's bound and flag are
+// slotted like DevState::lam and DevState::bad.
+struct PairSlot {
+    double t_base;              // state before the launch's steps
+    long long n_base;
+    int cur_base;
+    int tentative;              // 1: the next launch must check this launch's guess
+    unsigned long long guess;   // bits of lambda*_n (the guessed lambda*_{n+1})
+};
+
+struct PairState {
+    PairSlot q[2];
+    unsigned long long lam1[3];  // bound of the first step's states (bits of doubles >= 0)
+    unsigned int bad1[3];        // the first step met a non-physical state
+    unsigned int pad;
+    long long n_limit;           // step count at which the current call stops
+};
+
+struct Pair2DArgs {
+    double* f0;
+    double* f1;
+    DevState* st;
+    PairState* pst;
+    long long ps, rs;     // population offset = p*ps + y*rs + x
+    int nx, ny;
+    int strip;            // output columns per strip (<= 60)
+    int nstrips, nseg, ntiles;
+    long long launch;     // host launch counter p
+    double dx, cfl, omega, gamma, t_end;
+    int lam_mode;
+    int bc[4];
+    int last;             // last launch of a call: its result must not be tentative
+};
+
 // Node codes of a solid body: per population i (0..3, the D2Q4 order) a
 // 3-bit rule in bits 3i..3i+2 for a population whose pull source is solid,
 // and the solid-cell bit.
@@ -210,6 +251,13 @@ hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, bool
                          int max_blocks, hipStream_t s);
 int step2d_blocks_per_cu(int wpb, bool alt, bool dir, bool body = false);
 bool step2d_wpb_supported(int wpb);
+// Fused two-step launches (same waves-per-workgroup choices as the step).
+hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, int max_blocks, hipStream_t s);
+int step2d_pair_blocks_per_cu(int wpb);
+// Start of a call of max_steps fused launches: clears the first-step
+// accumulators and records the step count to stop at.
+hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long long max_steps,
+                               hipStream_t s);
 hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
 hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);
 int persistent1d_max_cells(int Q, size_t lds_limit);

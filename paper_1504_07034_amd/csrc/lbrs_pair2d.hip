@@ -1,0 +1,499 @@
+// Two fused LBRS steps per launch for the 2D Euler equations (D2Q4, gfx950).
+//
+// The single-step kernel reads f^n and writes f^{n+1} once per step: 256 B of
+// HBM traffic per cell and step, which bounds it.  Here a wavefront feeds
+// every row of f^{n+1} it has just streamed straight into a second collision
+// and streaming, so f^n is read once and f^{n+2} written once: 128 B per cell
+// and step.  Both steps are the scheme of Sec. II.D unchanged (moments, the
+// folded equilibria, relaxation, exact diagonal hops, Sec. II.E walls,
+// transmissive and periodic sides); nothing but the order of the work differs.
+//
+// Lanes and rows.  Lane l holds column x0 - 2 + l.  The first step is valid
+// on lanes 1..62, the second on lanes 2..61, so a strip has <= 60 output
+// columns.  A tile's first step computes rows y0-1 .. y1 of f^{n+1} (one halo
+// row on each side, from f^n rows y0-2 .. y1+1), the second rows y0 .. y1-1 of
+// f^{n+2}.  Register pipelines: the upward hops of the last two rows of each
+// step, and the next row of f^n in flight.  At a clamped (transmissive or
+// wall) side the second step must pull from the edge cell of f^{n+1} itself,
+// not from a ghost row or column that the first step would make up: there
+// the edge column's values are copied into the halo lane, and at a clamped
+// bottom or top the edge row's hops are reused (selects, no extra rows).
+//
+// Lattice speed of the second step.  With a fixed speed it is known.  With
+// the per-step speed it is the global bound over f^{n+1}, which no workgroup
+// has before the launch ends.  The launch then takes lambda*_{n+1} equal to
+// lambda*_n, reduces the true bound of its f^{n+1} on the side, and leaves
+// its result tentative.  The next launch checks the guess: equal bit for bit
+// (and the first step admissible) means the two steps are exactly those of
+// two single steps, and it continues from f^{n+2}; otherwise f^n, still
+// intact in the other buffer, is current again, and that launch repeats the
+// pair with the now known lambda*_{n+1} (or one step when the first step was
+// non-physical).  A launch that resolves nothing takes the same decisions in
+// every workgroup from the same slots, so no grid barrier is needed.  The
+// last launch of a call never leaves a tentative result, so every other call
+// sees an ordinary time state.
+#include "lbrs_launch.hpp"
+#include "lbrs_rowops.hpp"
+
+namespace lbrs {
+
+namespace {
+
+// Post-collision values of one row moved one lane along their diagonal:
+// populations 0 (-,-) and 1 (+,-) travel to the row below, 2 (+,+) and
+// 3 (-,+) to the row above.
+struct Hops {
+    double d0[4], d1[4];  // f0*(x+1, r), f1*(x-1, r): pulled by row r-1
+    double u2[4], u3[4];  // f2*(x-1, r), f3*(x+1, r): pulled by row r+1
+};
+
+// Collision of one row (moments U given) and its hops.
+__device__ inline void collide_hops(const double f[16], const double U[4], double gm1, double c4lam,
+                                    double omega, Hops& h) {
+    const Euler2 e = euler2(U, gm1);
+    double fs[16];
+    collide_d2q4(f, U, e, c4lam, omega, fs);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        h.d0[k] = lane_from_right(fs[0 * 4 + k]);
+        h.d1[k] = lane_from_left(fs[1 * 4 + k]);
+        h.u2[k] = lane_from_left(fs[2 * 4 + k]);
+        h.u3[k] = lane_from_right(fs[3 * 4 + k]);
+    }
+}
+
+// Free-slip wall on a node row or column (Sec. II.E): the populations that
+// would come from beyond the wall are the mirror images of the outgoing ones,
+// normal momentum negated.
+__device__ inline void wall_images(double g[16], bool top, bool bot, bool xlo, bool xhi) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double ry = k == 2 ? -1.0 : 1.0, rx = k == 1 ? -1.0 : 1.0;
+        if (top) {
+            g[0 * 4 + k] = ry * g[3 * 4 + k];
+            g[1 * 4 + k] = ry * g[2 * 4 + k];
+        }
+        if (bot) {
+            g[3 * 4 + k] = ry * g[0 * 4 + k];
+            g[2 * 4 + k] = ry * g[1 * 4 + k];
+        }
+        if (xlo) {
+            g[1 * 4 + k] = rx * g[0 * 4 + k];
+            g[2 * 4 + k] = rx * g[3 * 4 + k];
+        }
+        if (xhi) {
+            g[0 * 4 + k] = rx * g[1 * 4 + k];
+            g[3 * 4 + k] = rx * g[2 * 4 + k];
+        }
+    }
+}
+
+struct PairGeom {
+    const double* fin;
+    double* fout;
+    long long ps, rs;
+    int nx, ny, strip;
+    double c4lam1, c4lam2, omega, gamma;
+    int bc[4];
+};
+
+__device__ inline void load_row(double v[16], const double* __restrict__ fin, long long ps,
+                                long long rs, int j, int xl) {
+    const double* __restrict__ row = fin + (long long)j * rs;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) v[p] = row[p * ps + xl];
+}
+
+__device__ inline void store_full_row(double* row, long long ps, int row_bytes, int voff,
+                                      const double g[16]) {
+#pragma unroll
+    for (int p = 0; p < 16; ++p) store_row(row + p * ps, row_bytes, voff, g[p]);
+}
+
+// Rows y0..y1-1 of one strip, one step (TWO = false: f^{n+1} is the output)
+// or two.  lm1/bad1 gather the bound and admissibility of this tile's cells
+// of f^{n+1}, lm2/bad2 those of f^{n+2}.
+template <int WPB, bool TWO>
+__device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0, int y1, int lane,
+                                           double& lm1, bool& bad1, double& lm2, bool& bad2) {
+    const int nx = g.nx, ny = g.ny;
+    const bool px = g.bc[0] == BC_PERIODIC, py = g.bc[2] == BC_PERIODIC;
+    const double gm1 = g.gamma - 1.0;
+    const int row_bytes = nx * 8;
+    const int x0 = strip * g.strip;
+    const int x = x0 - 2 + lane;
+    const int xl = map_index(x, nx, px);
+    const bool out_lane = lane >= 2 && lane <= g.strip + 1 && x < nx;
+    const int voff = out_lane ? x * 8 : 0x7fffffff;
+    const bool wxlo = g.bc[0] == BC_WALL && x == 0;
+    const bool wxhi = g.bc[1] == BC_WALL && x == nx - 1;
+    const bool wlo = g.bc[2] == BC_WALL, whi = g.bc[3] == BC_WALL;
+    // rows [a0, b0) of f^{n+1}; f^n rows a0-1 .. b0 are read
+    const int a0 = TWO ? y0 - 1 : y0, b0 = TWO ? y1 + 1 : y1;
+    // strips that may hold the ghost lanes x = -1 or x = nx of a clamped x side
+    const bool xfix = TWO && !px && (x0 == 0 || x0 + 61 >= nx);
+    const bool clamp_lo = TWO && !py && y0 == 0;
+    const bool clamp_hi = TWO && !py && y1 == ny;
+
+    double f[16], nxt[16], U[4];
+    double A3[4], A4[4], B3[4], B4[4];  // first step: upward hops of rows r-1, r-2
+    double P3[4], P4[4], Q3[4], Q4[4];  // second step: upward hops of rows q-1, q-2
+    Hops h;
+    load_row(f, g.fin, g.ps, g.rs, map_index(a0 - 1, ny, py), xl);
+    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0, ny, py), xl);
+    moments_d2q4(f, U);
+    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        A3[k] = h.u2[k];
+        A4[k] = h.u3[k];
+    }
+#pragma unroll
+    for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0 + 1, ny, py), xl);
+    moments_d2q4(f, U);
+    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        B3[k] = A3[k];
+        B4[k] = A4[k];
+        A3[k] = h.u2[k];
+        A4[k] = h.u3[k];
+        P3[k] = P4[k] = Q3[k] = Q4[k] = 0.0;
+    }
+
+    for (int r = a0 + 1; r <= b0; ++r) {
+        // lockstep with the workgroup's neighbouring strips (equal trip counts)
+        if (WPB > 1) __builtin_amdgcn_s_barrier();
+#pragma unroll
+        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+        load_row(nxt, g.fin, g.ps, g.rs, map_index(r + 1, ny, py), xl);
+        moments_d2q4(f, U);
+        collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
+        // row o1 = r - 1 of f^{n+1}
+        const int o1 = r - 1;
+        double g1[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            g1[0 * 4 + k] = h.d0[k];
+            g1[1 * 4 + k] = h.d1[k];
+            g1[2 * 4 + k] = B3[k];
+            g1[3 * 4 + k] = B4[k];
+            B3[k] = A3[k];
+            B4[k] = A4[k];
+            A3[k] = h.u2[k];
+            A4[k] = h.u3[k];
+        }
+        wall_images(g1, whi && o1 == ny - 1, wlo && o1 == 0, wxlo, wxhi);
+        if (xfix) {
+            // a clamped side: beyond it, f^{n+1} is the edge column's
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const double fr = lane_from_right(g1[p]);
+                const double fl = lane_from_left(g1[p]);
+                g1[p] = x == -1 ? fr : (x == nx ? fl : g1[p]);
+            }
+        }
+        double U1[4], l1;
+        moments_d2q4(g1, U1);
+        const bool own1 = out_lane && o1 >= y0 && o1 < y1;
+        const bool ok1 = bound_d2q4(U1, g.gamma, &l1);
+        bad1 |= own1 && !ok1;
+        lm1 = fmax(lm1, own1 ? l1 : 0.0);
+        if (!TWO) {
+            store_full_row(g.fout + (long long)o1 * g.rs, g.ps, row_bytes, voff, g1);
+            continue;
+        }
+        // second step: row q = o1 of f^{n+1} completes row q - 1 of f^{n+2}
+        const int q = o1;
+        Hops h2;
+        collide_hops(g1, U1, gm1, g.c4lam2, g.omega, h2);
+        if (q > y0) {
+            const int o2 = q - 1;
+            // at a clamped top, row ny of f^{n+1} is row ny-1 again: its
+            // downward hops were kept in P at q = ny-1
+            const bool top_virtual = clamp_hi && q == ny;
+            double g2[16];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                g2[0 * 4 + k] = top_virtual ? P3[k] : h2.d0[k];
+                g2[1 * 4 + k] = top_virtual ? P4[k] : h2.d1[k];
+                g2[2 * 4 + k] = Q3[k];
+                g2[3 * 4 + k] = Q4[k];
+            }
+            wall_images(g2, whi && o2 == ny - 1, wlo && o2 == 0, wxlo, wxhi);
+            store_full_row(g.fout + (long long)o2 * g.rs, g.ps, row_bytes, voff, g2);
+            double U2[4], l2;
+            moments_d2q4(g2, U2);
+            const bool ok2 = bound_d2q4(U2, g.gamma, &l2);
+            bad2 |= out_lane && !ok2;
+            lm2 = fmax(lm2, out_lane ? l2 : 0.0);
+        }
+        // at a clamped bottom, row -1 of f^{n+1} is row 0 again; at a clamped
+        // top, keep row ny-1's downward hops for the virtual row ny
+        const bool lo_edge = clamp_lo && q == 0;
+        const bool hi_edge = clamp_hi && q == ny - 1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            Q3[k] = lo_edge ? h2.u2[k] : P3[k];
+            Q4[k] = lo_edge ? h2.u3[k] : P4[k];
+            P3[k] = hi_edge ? h2.d0[k] : h2.u2[k];
+            P4[k] = hi_edge ? h2.d1[k] : h2.u3[k];
+        }
+    }
+}
+
+__device__ inline double from_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// dt and the lattice speed of one step, in the order of operations of the
+// single-step control (so that both produce the same bits).
+__device__ inline void step_size(int lam_mode, double lam_star, double lam_fixed, double dx,
+                                 double cfl, double t, double t_end, double& lam, double& t_new) {
+    if (lam_mode == LAM_PER_STEP) {
+        double dt = cfl * dx / lam_star;
+        const double rem = t_end - t;
+        bool last = false;
+        if (dt >= rem) {
+            dt = rem;
+            last = true;
+        }
+        lam = dx / dt;
+        t_new = last ? t_end : t + dt;
+    } else {
+        lam = lam_fixed;
+        t_new = t + dx / lam;
+    }
+}
+
+// Time control of one fused launch (identical in every thread).
+struct PairCtl {
+    bool active;        // at least one step
+    bool two;           // two steps
+    bool tentative;     // the result waits for the next launch's check
+    bool accepted_bad;  // the previous launch's pair stands, with a non-physical f^{n+2}
+    int cur;
+    long long n;
+    double t, lam_used;
+    unsigned long long lstar;  // bits of lambda*_n (the bound of the current state)
+    unsigned bad;
+    double lam1, t1, lam2, t2;
+};
+
+__device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
+    const DevState* st = a.st;
+    const PairState* ps = a.pst;
+    PairCtl c;
+    Slot s = st->s[ls.sr];
+    const PairSlot q = ps->q[ls.sr];
+    unsigned long long lstar = st->lam[ls.lr];
+    unsigned bad = st->bad[ls.lr];
+    bool know_next = false, force_single = false;
+    unsigned long long next = 0ull;
+    c.accepted_bad = false;
+    if (q.tentative) {
+        const unsigned long long m1 = ps->lam1[ls.lr];
+        const bool b1 = ps->bad1[ls.lr] != 0u;
+        const bool ok = !b1 && (a.lam_mode != LAM_PER_STEP || m1 == q.guess);
+        if (ok) {
+            c.accepted_bad = bad != 0u;
+        } else {
+            // back to f^n; the bound of f^{n+1} is known now
+            s.t = q.t_base;
+            s.n = q.n_base;
+            s.cur = q.cur_base;
+            lstar = q.guess;
+            bad = 0u;
+            force_single = b1;
+            know_next = !b1;
+            next = m1;
+        }
+    }
+    c.cur = s.cur;
+    c.n = s.n;
+    c.t = s.t;
+    c.lam_used = s.lam_used;
+    c.lstar = lstar;
+    c.bad = bad;
+    const long long n_limit = ps->n_limit;
+    c.active = bad == 0u && s.t < a.t_end && s.n < n_limit;
+    const unsigned long long lbc = st->lam_bc;
+    step_size(a.lam_mode, from_bits(lstar > lbc ? lstar : lbc), st->lam_fixed, a.dx, a.cfl, s.t,
+              a.t_end, c.lam1, c.t1);
+    c.two = c.active && !force_single && c.t1 < a.t_end && s.n + 2 <= n_limit;
+    c.tentative = c.two && !know_next;
+    if (a.last && c.tentative) c.two = c.tentative = false;
+    c.lam2 = c.lam1;
+    c.t2 = c.t1;
+    if (c.two) {
+        const unsigned long long l2 = know_next ? next : lstar;
+        step_size(a.lam_mode, from_bits(l2 > lbc ? l2 : lbc), st->lam_fixed, a.dx, a.cfl, c.t1,
+                  a.t_end, c.lam2, c.t2);
+    }
+    return c;
+}
+
+// Block 0, thread 0: the time state after this launch and its pair record;
+// clears the accumulators of launch p+2.
+__device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const PairCtl& c) {
+    DevState* st = a.st;
+    PairState* ps = a.pst;
+    Slot s;
+    s.pad = 0;
+    PairSlot q;
+    q.t_base = c.t;
+    q.n_base = c.n;
+    q.cur_base = c.cur;
+    q.guess = c.lstar;
+    q.tentative = 0;
+    if (!c.active) {
+        s.t = c.t;
+        s.n = c.n;
+        s.lam_used = c.lam_used;
+        s.cur = c.cur;
+        st->lam[ls.la] = c.lstar;
+        st->bad[ls.la] = c.bad;
+    } else if (!c.two) {
+        s.t = c.t1;
+        s.n = c.n + 1;
+        s.lam_used = c.lam1;
+        s.cur = c.cur ^ 1;
+    } else {
+        s.t = c.t2;
+        s.n = c.n + 2;
+        s.lam_used = c.lam2;
+        s.cur = c.cur ^ 1;
+        q.tentative = c.tentative ? 1 : 0;
+    }
+    st->s[ls.sw] = s;
+    ps->q[ls.sw] = q;
+    st->lam[ls.lz] = 0ull;
+    st->bad[ls.lz] = 0u;
+    ps->lam1[ls.lz] = 0ull;
+    ps->bad1[ls.lz] = 0u;
+    if (c.accepted_bad) {
+        atomicOr(&st->status, 1u);
+        atomicMin(&st->fail_step, (unsigned long long)c.n);
+    }
+}
+
+}  // namespace
+
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
+    const LaunchSlots ls = slots_for(a.launch);
+    const PairCtl c = pair_control(a, ls);
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_pair(a, ls, c);
+    if (!c.active) return;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    PairGeom g;
+    // f^{n+2} (or f^{n+1}) goes to the other buffer; f^n stays intact
+    g.fin = c.cur ? a.f1 : a.f0;
+    g.fout = c.cur ? a.f0 : a.f1;
+    g.ps = a.ps;
+    g.rs = a.rs;
+    g.nx = a.nx;
+    g.ny = a.ny;
+    g.strip = a.strip;
+    g.c4lam1 = 1.0 / (4.0 * c.lam1);
+    g.c4lam2 = 1.0 / (4.0 * c.lam2);
+    g.omega = a.omega;
+    g.gamma = a.gamma;
+    for (int s = 0; s < 4; ++s) g.bc[s] = a.bc[s];
+    const int total_waves = gridDim.x * WPB;
+    const int ny = a.ny;
+
+    double lm1 = 0.0, lm2 = 0.0;
+    bool bad1 = false, bad2 = false;
+    for (int tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wave; tile < a.ntiles;
+         tile += total_waves) {
+        const int strip = tile % a.nstrips;
+        const int seg = tile / a.nstrips;
+        const int y0 = (int)(((long long)seg * ny) / a.nseg);
+        const int y1 = (int)(((long long)(seg + 1) * ny) / a.nseg);
+        if (c.two) march_pair<WPB, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+        else march_pair<WPB, false>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+    }
+
+    const bool per_step = a.lam_mode == LAM_PER_STEP;
+    if (c.two) {
+        if (per_step) {
+            const double w1 = wave_max(lm1), w2 = wave_max(lm2);
+            if (lane == 0) {
+                publish_max(&a.pst->lam1[ls.la], w1);
+                publish_max(&a.st->lam[ls.la], w2);
+            }
+        }
+        if (__any(bad1) && lane == 0) atomicOr(&a.pst->bad1[ls.la], 1u);
+        if (__any(bad2) && lane == 0) {
+            // a tentative f^{n+2} is reported by the launch that accepts it
+            if (c.tentative) atomicOr(&a.st->bad[ls.la], 1u);
+            else publish_bad(a.st, ls, c.n + 2);
+        }
+    } else {
+        if (per_step) {
+            const double w1 = wave_max(lm1);
+            if (lane == 0) publish_max(&a.st->lam[ls.la], w1);
+        }
+        if (__any(bad1) && lane == 0) publish_bad(a.st, ls, c.n + 1);
+    }
+}
+
+__global__ void pair_prepare_kernel(PairState* ps, const DevState* st, int slot,
+                                    long long max_steps) {
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < 2; ++i) {
+        ps->q[i].t_base = 0.0;
+        ps->q[i].n_base = 0;
+        ps->q[i].cur_base = 0;
+        ps->q[i].tentative = 0;
+        ps->q[i].guess = 0ull;
+    }
+    for (int i = 0; i < 3; ++i) {
+        ps->lam1[i] = 0ull;
+        ps->bad1[i] = 0u;
+    }
+    ps->n_limit = st->s[slot].n + max_steps;
+}
+
+hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long long max_steps,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(pair_prepare_kernel, dim3(1), dim3(64), 0, s, ps, st, slot, max_steps);
+    return hipGetLastError();
+}
+
+template <int WPB>
+static hipError_t launch_pair_w(const Pair2DArgs& a, int max_blocks, hipStream_t s) {
+    int nblocks = (a.ntiles + WPB - 1) / WPB;
+    if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
+    hipLaunchKernelGGL((step2d_pair<WPB>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int WPB>
+static int pair_blocks_w() {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB>, 64 * WPB, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+#define LBRS_PAIR_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12) X(16)
+
+hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, int max_blocks, hipStream_t s) {
+#define LBRS_CASE(W) \
+    if (wpb == W) return launch_pair_w<W>(a, max_blocks, s);
+    LBRS_PAIR_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return hipErrorInvalidValue;
+}
+
+int step2d_pair_blocks_per_cu(int wpb) {
+#define LBRS_CASE(W) \
+    if (wpb == W) return pair_blocks_w<W>();
+    LBRS_PAIR_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return 1;
+}
+
+}  // namespace lbrs

@@ -38,7 +38,7 @@ EXPORTS = (
     "lbrs_batch2d_adjoint_init", "lbrs_batch2d_set_window", "lbrs_batch2d_window_objective",
     "lbrs_batch2d_moments", "lbrs_batch2d_get_f", "lbrs_batch2d_set_f", "lbrs_batch2d_gradient",
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
-    "lbrs_destroy",
+    "lbrs_destroy", "lbrs_set_fusion",
 )
 
 
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_backward_checkpointed": (i, [vp, i, i, vp, vp, vp, vp]),
         "lbrs_set_stream": (i, [vp, vp]),
         "lbrs_set_tile": (i, [vp, i, i, i]),
+        "lbrs_set_fusion": (i, [vp, i]),
         "lbrs_batch_query": (i, [i, P, i, ctypes.POINTER(ll), szp]),
         "lbrs_batch_init": (i, [ctypes.POINTER(vp), i, P, dp, i, vp, vp, vp, vp]),
         "lbrs_batch_run": (i, [vp, i]),
@@ -302,6 +303,10 @@ def lbrs_set_stream(ctx, stream=None):
     _check(load_library().lbrs_set_stream(ctx, _stream(stream)), "lbrs_set_stream")
 
 
+def lbrs_set_fusion(ctx, steps_per_launch: int):
+    _check(load_library().lbrs_set_fusion(ctx, int(steps_per_launch)), "lbrs_set_fusion")
+
+
 def lbrs_set_tile(ctx, rows_per_tile: int, waves_per_block: int = 4, alternate: int = 1):
     _check(load_library().lbrs_set_tile(ctx, int(rows_per_tile), int(waves_per_block),
                                         int(alternate)), "lbrs_set_tile")
@@ -341,6 +346,8 @@ class Sim:
         self.f1 = torch.empty(fb // 8, dtype=torch.float64, device=self.device)
         self.scratch = torch.zeros(sb // 8, dtype=torch.float64, device=self.device)
         self.ctx = None
+        self._tile = None   # launch shape and fusion, re-applied to every new context
+        self._fuse = 1
 
     def _side_to_cons(self, Wside, gamma):
         """Conserved states of a side's primitive states [4][n] (2D Euler), by
@@ -403,6 +410,10 @@ class Sim:
         if self.ctx is not None:
             lbrs_destroy(self.ctx)
         self.ctx = lbrs_init(self.p, U0, self.f0, self.f1, self.scratch)
+        if self._tile is not None:
+            lbrs_set_tile(self.ctx, *self._tile)
+        if self._fuse != 1:
+            lbrs_set_fusion(self.ctx, self._fuse)
         return self
 
     def init_primitive(self, W):
@@ -411,10 +422,31 @@ class Sim:
         return self.init(self.prim_to_cons(W))
 
     def set_tile(self, rows_per_tile: int, waves_per_block: int = 4, alternate=None):
-        """alternate: None = the default march (alternating, one way with a body)."""
+        """alternate: None = the default march (alternating, one way with a body).
+        Kept for later contexts of this Sim (init creates a new one)."""
         if alternate is None:
             alternate = 0 if self.body else 1
-        lbrs_set_tile(self.ctx, rows_per_tile, waves_per_block, alternate)
+        if self.ctx is not None:
+            lbrs_set_tile(self.ctx, rows_per_tile, waves_per_block, alternate)
+        self._tile = (rows_per_tile, waves_per_block, alternate)
+
+    @property
+    def fusable(self) -> bool:
+        """Two fused steps per launch are available (2D Euler, no body, no
+        Dirichlet side)."""
+        return (self.model == LBRS_D2Q4 and self.law == LBRS_LAW_EULER and not self.body
+                and all(d is None for d in self.dirichlet))
+
+    @property
+    def fusion(self) -> int:
+        return self._fuse
+
+    def set_fusion(self, steps_per_launch: int):
+        """2: two fused steps per launch (2D Euler without body or Dirichlet sides).
+        Kept for later contexts of this Sim."""
+        if self.ctx is not None:
+            lbrs_set_fusion(self.ctx, steps_per_launch)
+        self._fuse = int(steps_per_launch)
 
     def step(self, max_steps: int, t_end: float = math.inf):
         lbrs_step(self.ctx, max_steps, t_end)
