@@ -335,7 +335,8 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * enqueues a one-thread set-up kernel and up to max_steps launches (with a
  * fixed speed max_steps/2 + 1), of which the ones beyond the work done exit
  * at once.  The shape set by lbrs_set_tile applies (strips of at most 60
- * columns; automatic segments of at least 4 rows; alternate is ignored).
+ * columns; automatic segments of at least 4 rows; 16 waves per workgroup run
+ * as 12; alternate is ignored).
  * lbrs_step_tape and the gradient calls' recompute steps stay single steps.
  * LBRS_E_INVAL for other values; LBRS_E_STATE with 2 for a 1D, scalar-law,
  * body or DIRICHLET context.  Takes effect for later calls. */

@@ -105,7 +105,7 @@ def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=Non
     results = []
     for fu in fuses:
         for a in (alts if fu == 1 else (0,)):
-            for w in wpbs:
+            for w in (wpbs if fu == 1 else [v for v in wpbs if v <= 12]):
                 for r in rows:
                     ms = time_shape(sim, r, w, steps, f0, st["t"], st["nsteps"], t_end, a, fu)
                     results.append({"rows": r, "wpb": w, "alt": a, "fuse": fu, "ms": ms})

@@ -441,10 +441,15 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
 
 // Fused two-step launches: strips of at most 60 columns (two halo lanes on
 // each side), segments of at least 4 rows (two halo rows on each side).
+// Waves per workgroup of the fused kernel: 16-wave groups do not fit its
+// registers at the occupancy it needs and run as 12.
+static int pair_wpb(const lbrs_ctx* c) { return c->waves_per_block > 12 ? 12 : c->waves_per_block; }
+
 static int pair_max_blocks(const lbrs_ctx* c) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
-    int& n = m->pbpc[c->waves_per_block];
-    if (n == 0) n = step2d_pair_blocks_per_cu(c->waves_per_block);
+    const int w = pair_wpb(c);
+    int& n = m->pbpc[w];
+    if (n == 0) n = step2d_pair_blocks_per_cu(w);
     return c->cu_count * n;
 }
 
@@ -458,7 +463,7 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end) {
     a.rs = c->rs;
     a.nx = c->P.nx;
     a.ny = c->P.ny;
-    const int wpb = c->waves_per_block;
+    const int wpb = pair_wpb(c);
     a.nstrips = ((c->P.nx + 59) / 60 + wpb - 1) / wpb * wpb;
     a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
     long long nseg;
@@ -587,7 +592,7 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         for (int s = 0; s < nl; ++s) {
             a.launch = c->launches;
             a.last = s == nl - 1;
-            e = launch_step2d_pair(a, c->waves_per_block, mb, c->stream);
+            e = launch_step2d_pair(a, pair_wpb(c), mb, c->stream);
             if (e != hipSuccess) return LBRS_E_HIP;
             ++c->launches;
         }

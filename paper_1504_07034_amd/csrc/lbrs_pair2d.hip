@@ -135,42 +135,22 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
     const bool clamp_lo = TWO && !py && y0 == 0;
     const bool clamp_hi = TWO && !py && y1 == ny;
 
-    double f[16], nxt[16], U[4];
     double A3[4], A4[4], B3[4], B4[4];  // first step: upward hops of rows r-1, r-2
     double P3[4], P4[4], Q3[4], Q4[4];  // second step: upward hops of rows q-1, q-2
+    double U[4];
     Hops h;
-    load_row(f, g.fin, g.ps, g.rs, map_index(a0 - 1, ny, py), xl);
-    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0, ny, py), xl);
-    moments_d2q4(f, U);
-    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        A3[k] = h.u2[k];
-        A4[k] = h.u3[k];
-    }
-#pragma unroll
-    for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0 + 1, ny, py), xl);
-    moments_d2q4(f, U);
-    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        B3[k] = A3[k];
-        B4[k] = A4[k];
-        A3[k] = h.u2[k];
-        A4[k] = h.u3[k];
-        P3[k] = P4[k] = Q3[k] = Q4[k] = 0.0;
-    }
 
-    for (int r = a0 + 1; r <= b0; ++r) {
+    // Row r of f^n (in cur) completes row r-1 of f^{n+1} and, with TWO, row
+    // r-2 of f^{n+2}; row r+1 is loaded into nxt first, so that it is in
+    // flight while row r is computed.  One copy of this code serves every
+    // row: two inlined copies may be contracted into different multiply-adds
+    // by the compiler, and rows would then round differently.
+    auto row = [&](double (&cur)[16], double (&nxt)[16], int r) {
         // lockstep with the workgroup's neighbouring strips (equal trip counts)
         if (WPB > 1) __builtin_amdgcn_s_barrier();
-#pragma unroll
-        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
         load_row(nxt, g.fin, g.ps, g.rs, map_index(r + 1, ny, py), xl);
-        moments_d2q4(f, U);
-        collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
-        // row o1 = r - 1 of f^{n+1}
+        moments_d2q4(cur, U);
+        collide_hops(cur, U, gm1, g.c4lam1, g.omega, h);
         const int o1 = r - 1;
         double g1[16];
 #pragma unroll
@@ -202,14 +182,19 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
         lm1 = fmax(lm1, own1 ? l1 : 0.0);
         if (!TWO) {
             store_full_row(g.fout + (long long)o1 * g.rs, g.ps, row_bytes, voff, g1);
-            continue;
+            return;
         }
         // second step: row q = o1 of f^{n+1} completes row q - 1 of f^{n+2}
         const int q = o1;
         Hops h2;
         collide_hops(g1, U1, gm1, g.c4lam2, g.omega, h2);
-        if (q > y0) {
-            const int o2 = q - 1;
+        {
+            // row q - 1 of f^{n+2}, an output row once q > y0.  The store is
+            // unconditional (an out-of-range offset is dropped by the buffer
+            // range check), so the wait for the next row's loads never has
+            // to cover this row's stores.
+            const bool row_out = q > y0;
+            const int o2 = row_out ? q - 1 : y0;
             // at a clamped top, row ny of f^{n+1} is row ny-1 again: its
             // downward hops were kept in P at q = ny-1
             const bool top_virtual = clamp_hi && q == ny;
@@ -222,12 +207,14 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
                 g2[3 * 4 + k] = Q4[k];
             }
             wall_images(g2, whi && o2 == ny - 1, wlo && o2 == 0, wxlo, wxhi);
-            store_full_row(g.fout + (long long)o2 * g.rs, g.ps, row_bytes, voff, g2);
+            store_full_row(g.fout + (long long)o2 * g.rs, g.ps, row_bytes,
+                           row_out ? voff : 0x7fffffff, g2);
             double U2[4], l2;
             moments_d2q4(g2, U2);
             const bool ok2 = bound_d2q4(U2, g.gamma, &l2);
-            bad2 |= out_lane && !ok2;
-            lm2 = fmax(lm2, out_lane ? l2 : 0.0);
+            const bool own2 = out_lane && row_out;
+            bad2 |= own2 && !ok2;
+            lm2 = fmax(lm2, own2 ? l2 : 0.0);
         }
         // at a clamped bottom, row -1 of f^{n+1} is row 0 again; at a clamped
         // top, keep row ny-1's downward hops for the virtual row ny
@@ -240,6 +227,36 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
             P3[k] = hi_edge ? h2.d0[k] : h2.u2[k];
             P4[k] = hi_edge ? h2.d1[k] : h2.u3[k];
         }
+    };
+
+    // prologue: rows a0-1 and a0 of f^n fill the first step's pipeline
+    double f[16], nxt[16];
+    load_row(f, g.fin, g.ps, g.rs, map_index(a0 - 1, ny, py), xl);
+    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0, ny, py), xl);
+    moments_d2q4(f, U);
+    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        A3[k] = h.u2[k];
+        A4[k] = h.u3[k];
+    }
+#pragma unroll
+    for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0 + 1, ny, py), xl);
+    moments_d2q4(f, U);
+    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        B3[k] = A3[k];
+        B4[k] = A4[k];
+        A3[k] = h.u2[k];
+        A4[k] = h.u3[k];
+        P3[k] = P4[k] = Q3[k] = Q4[k] = 0.0;
+    }
+    for (int r = a0 + 1; r <= b0; ++r) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+        row(f, nxt, r);
     }
 }
 
@@ -478,7 +495,7 @@ static int pair_blocks_w() {
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-#define LBRS_PAIR_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12) X(16)
+#define LBRS_PAIR_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12)
 
 hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, int max_blocks, hipStream_t s) {
 #define LBRS_CASE(W) \
