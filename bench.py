@@ -23,26 +23,49 @@ METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
 
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (calibrated against a plain copy), by launch shape "waves_per_block,alternate"
-# (automatic row segments, row-interleaved layout), valid for the kernel source
-# they were taken on (profiles/step2d_d2q4_riemann4096.md); null once the
-# source changes or for a shape not profiled.
+# (automatic row segments, row-interleaved layout), valid for the kernel code
+# they were taken on (profiles/step2d_d2q4_riemann4096.md); null once the code
+# changes or for a shape not profiled.
 TRAFFIC_BYTES = {"16,0": 4.433e9, "16,1": 4.396e9, "12,0": 4.418e9, "12,1": 4.392e9, "8,0": 4.486e9,
                  "8,1": 4.382e9, "6,0": 4.517e9, "6,1": 4.407e9, "4,0": 4.538e9, "4,1": 4.481e9}
-TRAFFIC_SOURCE_HASH = "d34d3ce179d013e0"
+TRAFFIC_SOURCE_HASH = "aeb4140bef7481ec"
+SINGLE_SOURCES = ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
+# The same for the fused two-step kernel, by waves per workgroup: the mean HBM
+# bytes per launch over the timed launches of the benchmark window (per-step
+# lattice speeds: one launch per step, of which those past the steps done exit
+# at once), profiles/step2d_pair_riemann4096.md.
+PAIR_TRAFFIC_BYTES = {}
+PAIR_TRAFFIC_SOURCE_HASH = None
+PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 
 
 def traffic_bytes(shape, layout):
-    if kernel_source_hash() != TRAFFIC_SOURCE_HASH or shape["rows"] != 0 or layout != 1:
+    if shape["rows"] != 0 or layout != 1:
+        return None
+    if shape.get("fuse", 1) == 2:
+        if kernel_source_hash(PAIR_SOURCES) != PAIR_TRAFFIC_SOURCE_HASH:
+            return None
+        return PAIR_TRAFFIC_BYTES.get(str(shape["wpb"]))
+    if kernel_source_hash(SINGLE_SOURCES) != TRAFFIC_SOURCE_HASH:
         return None
     return TRAFFIC_BYTES.get(f"{shape['wpb']},{shape['alt']}")
 
 
-def kernel_source_hash() -> str:
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines (what the compiler sees)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.split("\n") if line.strip())
+
+
+def kernel_source_hash(files=SINGLE_SOURCES) -> str:
     import hashlib
     csrc = os.path.join(ROOT, "paper_1504_07034_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read()
-                   for f in ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp"))
-    return hashlib.sha256(src).hexdigest()[:16]
+    src = "".join(_code_only(open(os.path.join(csrc, f)).read()) for f in files)
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
+
+
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = 256  # 16 FP64 populations in + 16 out per lattice update
 
@@ -186,6 +209,9 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     sim = run.sim
     run.forward(rho0, keep=False)
     fwd = _time_ms(lambda: sim.step(k)) / k
+    sim.set_fusion(1)
+    fwd1 = _time_ms(lambda: sim.step(k)) / k
+    sim.set_fusion(best["fuse"])
     tape = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
     tap = _time_ms(lambda: [lbrs.lbrs_step_tape(sim.ctx, tape) for _ in range(k)]) / k
     g = torch.empty_like(run.fbar)
@@ -203,9 +229,11 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     cells = n * n
     return {"n": n, "steps": steps, "segment": run.spec.seg,
             "tile_rows": best["rows"], "waves_per_block": best["wpb"], "alternate": best["alt"],
-            "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap, 4),
-            "adjoint_step_ms": round(adj, 4),
+            "steps_per_launch": best["fuse"],
+            "forward_step_ms": round(fwd, 4), "forward_single_step_ms": round(fwd1, 4),
+            "tape_step_ms": round(tap, 4), "adjoint_step_ms": round(adj, 4),
             "adjoint_over_forward": round((tap + adj) / fwd, 3),
+            "adjoint_over_single_forward": round((tap + adj) / fwd1, 3),
             "adjoint_step_GBs": round(288 * cells / (adj * 1e-3) / 1e9, 1),
             "gradient_ms": round(t_grad, 1), "forward_run_ms": round(t_fwd, 1),
             "gradient_over_forward_run": round(t_grad / t_fwd, 3)}
@@ -237,18 +265,23 @@ def batched_2d(k=10, ws=None):
     B.close()
     del B
     torch.cuda.empty_cache()
-    ms_s = 0.0
+    # the same domains one at a time, in single and in fused launches
+    ms_s = {1: 0.0, 2: 0.0}
     for w, U in zip(ws, Us):
         sim = lbrs.Sim(lbrs.LBRS_D2Q4, w.nx, w.ny, domain=w.domain, gamma=w.gamma, cfl=w.cfl,
                        bc=w.sides, lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT,
                        layout=lbrs.LBRS_LAYOUT_ROWS)
         sim.init(U)
-        sim.step(2)
-        ms_s += _time_ms(lambda: sim.step(k)) / k
+        for fuse in (1, 2):
+            sim.set_fusion(fuse)
+            sim.step(2)
+            ms_s[fuse] += _time_ms(lambda: sim.step(k)) / k
         sim.close()
     return {"domains": len(ws), "cells": int(total), "batched_ms_per_step": round(ms_b, 3),
             "MLUPS": round(total / ms_b / 1e3, 1),
-            "sequential_ms_per_step": round(ms_s, 3), "speedup": round(ms_s / ms_b, 3)}
+            "sequential_ms_per_step": round(ms_s[1], 3), "speedup": round(ms_s[1] / ms_b, 3),
+            "sequential_fused_ms_per_step": round(ms_s[2], 3),
+            "speedup_vs_fused": round(ms_s[2] / ms_b, 3)}
 
 
 def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None):
@@ -609,6 +642,7 @@ def slab_step(steps=200, warmup=20):
     best = autotune.tune(sim, 0.3, use_cache=False, rows=(0, 16, 32, 64, 128))
     sim.init(U0)
     sim.set_tile(best["rows"], best["wpb"], best["alt"])
+    sim.set_fusion(best["fuse"])
     sim.step(warmup, 0.3)
     ms = _time_ms(lambda: sim.step(steps, 0.3)) / steps
     st = sim.state()
@@ -617,7 +651,7 @@ def slab_step(steps=200, warmup=20):
     cells = n * h
     gbs = BYTES_PER_LUP * cells / (ms * 1e-3) / 1e9
     return {"nx": n, "ny": h, "tile_rows": best["rows"], "waves_per_block": best["wpb"],
-            "alternate": best["alt"], "ms_per_step": round(ms, 4),
+            "alternate": best["alt"], "steps_per_launch": best["fuse"], "ms_per_step": round(ms, 4),
             "MLUPS": round(cells / ms / 1e3, 1), "GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
@@ -633,6 +667,8 @@ def main():
     ap.add_argument("--alt", type=int, default=1, choices=[0, 1],
                     help="march odd row segments upwards (with --rows >= 0)")
     ap.add_argument("--layout", type=int, default=1, help="0 planar, 1 row-interleaved")
+    ap.add_argument("--fuse", type=int, default=1, choices=[1, 2],
+                    help="time steps per launch (with --rows >= 0; autotuned otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
@@ -672,51 +708,85 @@ def main():
     U0 = sim.prim_to_cons(W)
     del W, w
 
-    shape = {"rows": args.rows, "wpb": args.wpb, "alt": args.alt}
+    shape = {"rows": args.rows, "wpb": args.wpb, "alt": args.alt, "fuse": args.fuse}
+    single = None  # the best single-step shape, when the fused one wins
 
-    def fresh():
-        sim.init(U0)
-        if shape["rows"] >= 0:
-            sim.set_tile(shape["rows"], shape["wpb"], shape["alt"])
+    def use(sh):
+        sim.set_tile(sh["rows"], sh["wpb"], sh["alt"])
+        sim.set_fusion(sh["fuse"])
 
     if args.rows < 0:  # autotune the launch shape (untimed), then start over
         # automatic row segments (one balanced round of the resident waves);
-        # every (waves per workgroup, march order) candidate has its HBM
-        # traffic measured, so the record carries it for whichever wins
+        # single and fused launches, every (waves per workgroup, march order)
+        # candidate with its HBM traffic measured
         sim.init(U0)
         sim.step(20, t_end)
         best = autotune.tune(sim, t_end, steps=20, use_cache=False, rows=(0,))
-        shape = {"rows": best["rows"], "wpb": best["wpb"], "alt": best["alt"]}
-        print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']}) {c['ms']:.3f} ms"
-                                       for c in best["candidates"]), file=sys.stderr, flush=True)
+        shape = {k: best[k] for k in ("rows", "wpb", "alt", "fuse")}
+        print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']},{c['fuse']}) "
+                                       f"{c['ms']:.3f} ms" for c in best["candidates"]),
+              file=sys.stderr, flush=True)
+        if shape["fuse"] == 2:
+            s1 = min((c for c in best["candidates"] if c["fuse"] == 1), key=lambda c: c["ms"])
+            single = {k: s1[k] for k in ("rows", "wpb", "alt", "fuse")}
 
-    # The run reaches t_end after ~7.8k steps; time in segments that stay
-    # inside [0, t_end) so that every timed step does real work.
-    seg_cap = 6000
-    fresh()
-    sim.step(args.warmup, t_end)
-    done_in_seg = args.warmup
     stream = torch.cuda.current_stream()
-    total_ms = 0.0
-    left = args.steps
-    while left > 0:
-        if done_in_seg >= seg_cap:
-            fresh()
-            done_in_seg = 0
-        k = min(left, seg_cap - done_in_seg)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        sim.step(k, t_end)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        total_ms += e0.elapsed_time(e1)
-        st = sim.state()
-        if st["rc"] != 0 or st["nsteps"] != done_in_seg + k:
-            raise RuntimeError(f"timed steps did not all run: {st}")
-        done_in_seg += k
-        left -= k
+
+    def timed_window(sh, steps, warmup):
+        """ms per step over `steps` steps after `warmup` steps from t = 0.  The
+        run reaches t_end after ~8k steps; segments restart from t = 0 so that
+        every timed step does real work."""
+        seg_cap = 6000
+        sim.init(U0)
+        use(sh)
+        sim.step(warmup, t_end)
+        done_in_seg = warmup
+        total_ms = 0.0
+        left = steps
+        while left > 0:
+            if done_in_seg >= seg_cap:
+                sim.init(U0)
+                done_in_seg = 0
+            k = min(left, seg_cap - done_in_seg)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sim.step(k, t_end)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            total_ms += e0.elapsed_time(e1)
+            st = sim.state()
+            if st["rc"] != 0 or st["nsteps"] != done_in_seg + k:
+                raise RuntimeError(f"timed steps did not all run: {st}")
+            done_in_seg += k
+            left -= k
+        return total_ms / steps
+
+    def whole_run(sh):
+        """The whole run from t = 0 to t_end, timed in calls of 1000 steps."""
+        sim.init(U0)
+        use(sh)
+        total_ms, steps = 0.0, 0
+        while True:
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            sim.step(1000, t_end)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            total_ms += e0.elapsed_time(e1)
+            st = sim.state()
+            if st["rc"] != 0:
+                raise RuntimeError(f"whole run failed: {st}")
+            if st["t"] >= t_end:
+                steps = st["nsteps"]
+                break
+        return {"steps": steps, "ms": round(total_ms, 1),
+                "MLUPS": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1)}
+
+    ms_per_step = timed_window(shape, args.steps, args.warmup)
 
     if args.calibrate_copy:
         f_copy = sim.get_f()
@@ -724,7 +794,6 @@ def main():
         del f_copy
     copy_ref = None if args.no_extras else copy_bandwidth(sim.f0, sim.f1)
 
-    ms_per_step = total_ms / args.steps
     cells = n * n
     mlups = cells / (ms_per_step * 1e-3) / 1e6
     achieved = BYTES_PER_LUP * cells / (ms_per_step * 1e-3) / 1e9
@@ -745,12 +814,27 @@ def main():
                    "nx": n, "ny": n, "domain": "[0,1]^2", "gamma": 1.4, "omega": 1.0,
                    "cfl": 0.5, "sides": "transmissive", "t_end": t_end,
                    "tile_rows": shape["rows"], "waves_per_block": shape["wpb"],
-                   "alternate_march": shape["alt"],
+                   "alternate_march": shape["alt"], "steps_per_launch": shape["fuse"],
                    "layout": "row-interleaved" if args.layout == 1 else "planar"},
+        # achieved = 256 B per lattice update (the single step's algorithmic
+        # bytes) x updates per launch / launch time; a fused launch keeps
+        # f^{n+1} in registers, so its measured traffic is about half of that
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes(shape, args.layout)},
+                     "traffic": traffic_bytes(shape, args.layout),
+                     "kernel": "step2d_pair" if shape["fuse"] == 2 else "step2d_d2q4"},
     }
+    if single is not None and not args.no_extras:
+        ms1 = timed_window(single, args.steps, args.warmup)
+        a1 = BYTES_PER_LUP * cells / (ms1 * 1e-3) / 1e9
+        rec["single_step"] = {
+            "tile_rows": single["rows"], "waves_per_block": single["wpb"],
+            "alternate_march": single["alt"], "ms_per_step": round(ms1, 4),
+            "MLUPS": round(cells / (ms1 * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(a1, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(a1 / HBM_PEAK_GBS, 4),
+                         "traffic": traffic_bytes(single, args.layout), "kernel": "step2d_d2q4"}}
+        rec["full_run"] = {"fused": whole_run(shape), "single": whole_run(single)}
     if copy_ref is not None:
         copy_ref["frac_of_copy"] = round(achieved / copy_ref["GBs"], 4)
         rec["copy_reference"] = copy_ref

@@ -131,7 +131,8 @@ __device__ inline Euler2 euler2(const double U[4], double gm1) {
     double ir = 1.0 / U[0];
     e.u = U[1] * ir;
     e.v = U[2] * ir;
-    // m u + n v without contraction, so that swapping x and y is exact
+    // m u + n v; the compiler may still fuse one product into the sum (the
+    // kernels are built with contraction), so x <-> y symmetry holds to rounding
     double ke = 0.5 * __dadd_rn(__dmul_rn(U[1], e.u), __dmul_rn(U[2], e.v));
     e.p = gm1 * (U[3] - ke);
     e.H = U[3] + e.p;
