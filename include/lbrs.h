@@ -410,8 +410,20 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
  * f^0 = f^eq(U0) per domain (Sec. II.A), step count 0. */
 int lbrs_batch2d_reset(lbrs_batch2d* b, const double* d_U0);
 
-/* nsteps fused steps of every domain (one launch each). */
+/* nsteps collide-and-stream steps of every domain: one launch per step, or
+ * with lbrs_batch2d_set_fusion(b, 2) one launch per two steps (and one more
+ * for an odd count). */
 int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps);
+
+/* Time steps per forward launch of lbrs_batch2d_step and of the forward
+ * sweep of lbrs_batch2d_gradient: 1 (the default) or 2.  With 2 each
+ * wavefront streams the rows of f^{n+1} it has just produced straight into
+ * the next step (as lbrs_set_fusion; the speeds are fixed, so nothing is
+ * guessed): half the HBM traffic per step, the same results to rounding.  A
+ * domain whose f^{n+1} or f^{n+2} is non-physical gets its status set.  The
+ * taped recompute and the adjoint steps stay single steps.  LBRS_E_INVAL for
+ * other values. */
+int lbrs_batch2d_set_fusion(lbrs_batch2d* b, int steps_per_launch);
 
 /* One step that also stores every domain's input moments U^n in d_Utape [4][total]. */
 int lbrs_batch2d_step_tape(lbrs_batch2d* b, double* d_Utape);

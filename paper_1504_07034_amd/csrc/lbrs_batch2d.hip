@@ -209,10 +209,14 @@ struct lbrs_batch2d {
     long long nsteps;
     hipStream_t stream;
     int wpb, max_blocks;
+    int fuse;                 // time steps per forward launch (1, or 2 fused)
+    long long pntiles;        // tiles of the fused launches
+    int pmax_blocks;
     hipGraph_t graph;
     hipGraphExec_t exec;
     const void* graph_args[7];  // arguments the captured gradient graph was built with
     long long graph_steps[2];
+    int graph_fuse;
 };
 
 namespace {
@@ -284,8 +288,10 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
     b->ndom = ndom;
     b->wpb = 8;
     b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb, true, false);
+    b->pmax_blocks = prop.multiProcessorCount * step2d_batch_pair_blocks_per_cu(b->wpb);
+    b->fuse = 1;
     b->doms.resize(ndom);
-    long long off = 0, rows = 0, tiles = 0;
+    long long off = 0, rows = 0, tiles = 0, ptiles = 0;
     b->max_nx = 0;
     for (int i = 0; i < ndom; ++i) {
         const lbrs_params* p = &doms[i];
@@ -297,6 +303,9 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
         d.ny = p->ny;
         d.nstrips = ((p->nx + 61) / 62 + b->wpb - 1) / b->wpb * b->wpb;
         d.strip = (p->nx + d.nstrips - 1) / d.nstrips;
+        d.ptile0 = ptiles;
+        d.pnstrips = ((p->nx + 59) / 60 + b->wpb - 1) / b->wpb * b->wpb;
+        d.pstrip = (p->nx + d.pnstrips - 1) / d.pnstrips;
         // row segments of about 64 rows (the batch has many tiles per round)
         long long nseg = (p->ny + 63) / 64;
         d.nseg = (int)std::max(1LL, std::min<long long>(nseg, p->ny));
@@ -311,11 +320,13 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
         off += (long long)p->nx * p->ny;
         rows += p->ny;
         tiles += (long long)d.nstrips * d.nseg;
+        ptiles += (long long)d.pnstrips * d.nseg;
         b->max_nx = std::max(b->max_nx, p->nx);
     }
     b->total = off;
     b->rows = rows;
     b->ntiles = tiles;
+    b->pntiles = ptiles;
     char* s = (char*)d_scratch;
     b->d_doms = (Domain2D*)s;
     s += al256(sizeof(Domain2D) * ndom);
@@ -365,6 +376,7 @@ static Batch2DArgs b2_args(const lbrs_batch2d* b, double* tape) {
     a.doms = b->d_doms;
     a.ndom = b->ndom;
     a.ntiles = b->ntiles;
+    a.pntiles = b->pntiles;
     a.total = b->total;
     a.f0 = b->f0;
     a.f1 = b->f1;
@@ -374,8 +386,23 @@ static Batch2DArgs b2_args(const lbrs_batch2d* b, double* tape) {
     return a;
 }
 
+int lbrs_batch2d_set_fusion(lbrs_batch2d* b, int steps_per_launch) {
+    if (!b || (steps_per_launch != 1 && steps_per_launch != 2)) return LBRS_E_INVAL;
+    b->fuse = steps_per_launch;
+    return LBRS_OK;
+}
+
 int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps) {
     if (!b || nsteps < 0) return LBRS_E_INVAL;
+    if (b->fuse == 2) {
+        for (; nsteps >= 2; nsteps -= 2) {
+            if (!ok(launch_step2d_batch_pair(b2_args(b, nullptr), b->wpb, b->pmax_blocks,
+                                             b->stream)))
+                return LBRS_E_HIP;
+            b->cur ^= 1;
+            b->nsteps += 2;
+        }
+    }
     for (int i = 0; i < nsteps; ++i) {
         if (!ok(launch_step2d_batch(b2_args(b, nullptr), b->wpb, false, b->max_blocks, b->stream)))
             return LBRS_E_HIP;
@@ -524,7 +551,8 @@ int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int s
     if (!use_graph)
         return b2_gradient_enqueue(b, d_U0, nsteps, segment, d_ckpt, d_tape, d_fbar, d_work, d_J, d_Ubar0);
     const void* args[7] = {d_U0, d_ckpt, d_tape, d_fbar, d_work, d_J, d_Ubar0};
-    bool same = b->exec && b->graph_steps[0] == nsteps && b->graph_steps[1] == segment;
+    bool same = b->exec && b->graph_steps[0] == nsteps && b->graph_steps[1] == segment &&
+                b->graph_fuse == b->fuse;
     for (int i = 0; same && i < 7; ++i) same = b->graph_args[i] == args[i];
     if (b->exec && !same) {  // other arguments: capture a new graph
         (void)hipGraphExecDestroy(b->exec);
@@ -553,6 +581,7 @@ int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int s
         for (int i = 0; i < 7; ++i) b->graph_args[i] = args[i];
         b->graph_steps[0] = nsteps;
         b->graph_steps[1] = segment;
+        b->graph_fuse = b->fuse;
     }
     if (!ok(hipGraphLaunch(b->exec, b->stream))) return LBRS_E_HIP;
     return LBRS_OK;

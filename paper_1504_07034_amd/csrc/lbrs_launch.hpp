@@ -215,8 +215,10 @@ struct Domain2D {
     long long coff;
     long long tile0;       // first tile of the domain in the batch's tile list
     long long row0;        // first row of the domain among all domains' rows
+    long long ptile0;      // the same in the tile list of the fused two-step launches
     int nx, ny;
     int strip, nstrips, nseg;
+    int pstrip, pnstrips;  // strips of the fused launches (<= 60 columns)
     int bc[4];
     double dx, gamma, omega, cfl, lam;
     int lam_mode;
@@ -227,6 +229,7 @@ struct Batch2DArgs {
     const Domain2D* doms;
     int ndom;
     long long ntiles;
+    long long pntiles;     // tiles of the fused launches
     long long total;       // cells of all domains
     double* f0;
     double* f1;
@@ -237,6 +240,9 @@ struct Batch2DArgs {
 
 hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
                                hipStream_t s);
+// Two fused steps of every domain (fixed lattice speeds), f^n in buffer a.cur.
+hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, int max_blocks, hipStream_t s);
+int step2d_batch_pair_blocks_per_cu(int wpb);
 hipError_t launch_scalar_step2d(const ScalarArgs& a, int wpb, int max_blocks, hipStream_t s);
 hipError_t launch_scalar_step1d(const ScalarArgs& a, int q, hipStream_t s);
 int scalar2d_blocks_per_cu(int wpb);

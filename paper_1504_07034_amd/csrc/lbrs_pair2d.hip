@@ -457,6 +457,50 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     }
 }
 
+// Two fused steps of every domain of a 2D batch (fixed lattice speeds, so
+// nothing is guessed): the single-domain march over the fused launches' tile
+// list, numbered domain by domain (each domain's strip count a multiple of
+// the waves per workgroup, so a workgroup's waves share a domain and a row
+// segment); a non-physical f^{n+1} or f^{n+2} sets the domain's status.
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long total_waves = (long long)gridDim.x * WPB;
+    for (long long tile = (long long)xcd_remap(blockIdx.x, gridDim.x) * WPB + wave;
+         tile < a.pntiles; tile += total_waves) {
+        int lo = 0, hi = a.ndom - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.doms[mid].ptile0 <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const Domain2D& d = a.doms[lo];
+        PairGeom g;
+        const long long fo = 16 * d.coff;
+        g.fin = (a.cur ? a.f1 : a.f0) + fo;
+        g.fout = (a.cur ? a.f0 : a.f1) + fo;
+        g.ps = d.nx;
+        g.rs = 16LL * d.nx;
+        g.nx = d.nx;
+        g.ny = d.ny;
+        g.strip = d.pstrip;
+        g.c4lam1 = g.c4lam2 = 1.0 / (4.0 * d.lam);
+        g.omega = d.omega;
+        g.gamma = d.gamma;
+        for (int s = 0; s < 4; ++s) g.bc[s] = d.bc[s];
+        const int local = (int)(tile - d.ptile0);
+        const int strip = local % d.pnstrips;
+        const int seg = local / d.pnstrips;
+        const int y0 = (int)(((long long)seg * d.ny) / d.nseg);
+        const int y1 = (int)(((long long)(seg + 1) * d.ny) / d.nseg);
+        double lm1 = 0.0, lm2 = 0.0;
+        bool bad1 = false, bad2 = false;
+        march_pair<WPB, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+        if (__any(bad1 || bad2) && lane == 0) atomicOr(&a.status[lo], 1u);
+    }
+}
+
 __global__ void pair_prepare_kernel(PairState* ps, const DevState* st, int slot,
                                     long long max_steps) {
     if (threadIdx.x != 0) return;
@@ -508,6 +552,38 @@ hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, int max_blocks, hipS
 int step2d_pair_blocks_per_cu(int wpb) {
 #define LBRS_CASE(W) \
     if (wpb == W) return pair_blocks_w<W>();
+    LBRS_PAIR_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return 1;
+}
+
+template <int WPB>
+static hipError_t launch_batch_pair_w(const Batch2DArgs& a, int max_blocks, hipStream_t s) {
+    long long nblocks = (a.pntiles + WPB - 1) / WPB;
+    if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
+    hipLaunchKernelGGL((step2d_batch_pair<WPB>), dim3((unsigned)nblocks), dim3(64 * WPB), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int WPB>
+static int batch_pair_blocks_w() {
+    int n = 0;
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_batch_pair<WPB>, 64 * WPB, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, int max_blocks, hipStream_t s) {
+#define LBRS_CASE(W) \
+    if (wpb == W) return launch_batch_pair_w<W>(a, max_blocks, s);
+    LBRS_PAIR_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return hipErrorInvalidValue;
+}
+
+int step2d_batch_pair_blocks_per_cu(int wpb) {
+#define LBRS_CASE(W) \
+    if (wpb == W) return batch_pair_blocks_w<W>();
     LBRS_PAIR_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return 1;

@@ -38,7 +38,7 @@ EXPORTS = (
     "lbrs_batch2d_adjoint_init", "lbrs_batch2d_set_window", "lbrs_batch2d_window_objective",
     "lbrs_batch2d_moments", "lbrs_batch2d_get_f", "lbrs_batch2d_set_f", "lbrs_batch2d_gradient",
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
-    "lbrs_destroy", "lbrs_set_fusion",
+    "lbrs_destroy", "lbrs_set_fusion", "lbrs_batch2d_set_fusion",
 )
 
 
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_set_stream": (i, [vp, vp]),
         "lbrs_set_tile": (i, [vp, i, i, i]),
         "lbrs_set_fusion": (i, [vp, i]),
+        "lbrs_batch2d_set_fusion": (i, [vp, i]),
         "lbrs_batch_query": (i, [i, P, i, ctypes.POINTER(ll), szp]),
         "lbrs_batch_init": (i, [ctypes.POINTER(vp), i, P, dp, i, vp, vp, vp, vp]),
         "lbrs_batch_run": (i, [vp, i]),
@@ -605,6 +606,7 @@ class Batch2D:
         self.scratch = torch.zeros(max(sb.value, 256), dtype=torch.uint8, device=self.device)
         self._arr = arr
         self.b = None
+        self._fuse = 1  # kept for later handles (init creates a new one)
 
     def init(self, U0: torch.Tensor, stream=None):
         lib = load_library()
@@ -617,7 +619,16 @@ class Batch2D:
                                      ctypes.c_void_p(self.scratch.data_ptr()), _stream(stream)),
                "lbrs_batch2d_init")
         self.b = b
+        if self._fuse != 1:
+            self.set_fusion(self._fuse)
         return self
+
+    def set_fusion(self, steps_per_launch: int):
+        """2: two fused steps per forward launch (lbrs_batch2d_set_fusion)."""
+        self._fuse = int(steps_per_launch)
+        if self.b is not None:
+            _check(load_library().lbrs_batch2d_set_fusion(self.b, self._fuse),
+                   "lbrs_batch2d_set_fusion")
 
     def reset(self, U0):
         _check(load_library().lbrs_batch2d_reset(self.b, _dptr(U0)), "lbrs_batch2d_reset")
