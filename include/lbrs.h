@@ -337,7 +337,8 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * at once.  The shape set by lbrs_set_tile applies (strips of at most 60
  * columns; automatic segments of at least 4 rows; 16 waves per workgroup run
  * as 12; alternate is ignored).
- * lbrs_step_tape and the gradient calls' recompute steps stay single steps.
+ * lbrs_step_tape stays a single step; lbrs_backward_checkpointed recomputes
+ * its segments two steps per launch as well (both steps' input moments taped).
  * LBRS_E_INVAL for other values; LBRS_E_STATE with 2 for a 1D, scalar-law,
  * body or DIRICHLET context.  Takes effect for later calls. */
 int lbrs_set_fusion(lbrs_ctx* c, int steps_per_launch);
@@ -421,8 +422,9 @@ int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps);
  * the next step (as lbrs_set_fusion; the speeds are fixed, so nothing is
  * guessed): half the HBM traffic per step, the same results to rounding.  A
  * domain whose f^{n+1} or f^{n+2} is non-physical gets its status set.  The
- * taped recompute and the adjoint steps stay single steps.  LBRS_E_INVAL for
- * other values. */
+ * gradient's taped recompute is fused too (both steps' input moments taped);
+ * lbrs_batch2d_step_tape and the adjoint steps stay single steps.
+ * LBRS_E_INVAL for other values. */
 int lbrs_batch2d_set_fusion(lbrs_batch2d* b, int steps_per_launch);
 
 /* One step that also stores every domain's input moments U^n in d_Utape [4][total]. */

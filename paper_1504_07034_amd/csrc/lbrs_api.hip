@@ -487,6 +487,8 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end) {
     a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
     for (int s = 0; s < 4; ++s) a.bc[s] = c->P.bc[s];
     a.last = 0;
+    a.tape0 = a.tape1 = nullptr;
+    a.plane = c->plane;
     return a;
 }
 
@@ -592,7 +594,7 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         for (int s = 0; s < nl; ++s) {
             a.launch = c->launches;
             a.last = s == nl - 1;
-            e = launch_step2d_pair(a, pair_wpb(c), mb, c->stream);
+            e = launch_step2d_pair(a, pair_wpb(c), false, mb, c->stream);
             if (e != hipSuccess) return LBRS_E_HIP;
             ++c->launches;
         }
@@ -737,6 +739,31 @@ int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ck
     return LBRS_OK;
 }
 
+// The recompute of a segment in fused launches (fixed lattice speed, so
+// nothing is guessed): launch k takes steps 2k+1 and 2k+2 of the segment and
+// writes their input moments to tape slots 2k and 2k+1 (an odd last step: a
+// one-step launch, slot len-1).
+static int step_tape_fused(lbrs_ctx* c, int len, double* d_tape) {
+    Pair2DArgs a = pair_args(c, INFINITY);
+    const long long ucount = (long long)c->K * c->plane;
+    const int nl = len / 2 + 1;
+    hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), len, c->stream);
+    if (e != hipSuccess) return LBRS_E_HIP;
+    const int mb = pair_max_blocks(c);
+    for (int k = 0; k < nl; ++k) {
+        const long long s0 = 2LL * k < len ? 2LL * k : len - 1;
+        const long long s1 = 2LL * k + 1 < len ? 2LL * k + 1 : len - 1;
+        a.launch = c->launches;
+        a.last = k == nl - 1;
+        a.tape0 = d_tape + s0 * ucount;
+        a.tape1 = d_tape + s1 * ucount;
+        e = launch_step2d_pair(a, pair_wpb(c), true, mb, c->stream);
+        if (e != hipSuccess) return LBRS_E_HIP;
+        ++c->launches;
+    }
+    return LBRS_OK;
+}
+
 int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const double* d_ckpt,
                                double* d_tape, double* d_fbar, double* d_work) {
     if (!c || !d_ckpt || !d_tape || !d_fbar || !d_work || d_fbar == d_work || nsteps < 1 ||
@@ -764,9 +791,14 @@ int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const doubl
         int rc = lbrs_set_f(c, d_ckpt + j * fcount, t0 + (double)j * segment * dt, n0 + (long long)j * segment);
         if (rc) return rc;
         int len = nsteps - j * segment < segment ? nsteps - j * segment : segment;
-        for (int i = 0; i < len; ++i) {
-            rc = lbrs_step_tape(c, d_tape + i * ucount);
+        if (c->fuse == 2) {
+            rc = step_tape_fused(c, len, d_tape);
             if (rc) return rc;
+        } else {
+            for (int i = 0; i < len; ++i) {
+                rc = lbrs_step_tape(c, d_tape + i * ucount);
+                if (rc) return rc;
+            }
         }
         for (int i = len - 1; i >= 0; --i) {
             rc = lbrs_adjoint_step(c, d_tape + i * ucount, cur, nxt);

@@ -382,6 +382,7 @@ static Batch2DArgs b2_args(const lbrs_batch2d* b, double* tape) {
     a.f1 = b->f1;
     a.cur = b->cur;
     a.tape = tape;
+    a.tape2 = nullptr;
     a.status = b->d_status;
     return a;
 }
@@ -396,7 +397,7 @@ int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps) {
     if (!b || nsteps < 0) return LBRS_E_INVAL;
     if (b->fuse == 2) {
         for (; nsteps >= 2; nsteps -= 2) {
-            if (!ok(launch_step2d_batch_pair(b2_args(b, nullptr), b->wpb, b->pmax_blocks,
+            if (!ok(launch_step2d_batch_pair(b2_args(b, nullptr), b->wpb, false, b->pmax_blocks,
                                              b->stream)))
                 return LBRS_E_HIP;
             b->cur ^= 1;
@@ -532,7 +533,18 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
     for (int j = nck - 1; j >= 0; --j) {
         if ((rc = lbrs_batch2d_set_f(b, d_ckpt + j * fcount, (long long)j * segment))) return rc;
         int len = std::min(segment, nsteps - j * segment);
-        for (int i = 0; i < len; ++i)
+        int i = 0;
+        if (b->fuse == 2) {  // recompute two steps per launch, both inputs taped
+            for (; i + 1 < len; i += 2) {
+                Batch2DArgs a = b2_args(b, d_tape + i * ucount);
+                a.tape2 = d_tape + (i + 1) * ucount;
+                if (!ok(launch_step2d_batch_pair(a, b->wpb, true, b->pmax_blocks, b->stream)))
+                    return LBRS_E_HIP;
+                b->cur ^= 1;
+                b->nsteps += 2;
+            }
+        }
+        for (; i < len; ++i)
             if ((rc = lbrs_batch2d_step_tape(b, d_tape + i * ucount))) return rc;
         for (int i = len - 1; i >= 0; --i) {
             if ((rc = lbrs_batch2d_adjoint_step(b, d_tape + i * ucount, cur, nxt))) return rc;

@@ -66,6 +66,9 @@ struct Pair2DArgs {
     int lam_mode;
     int bc[4];
     int last;             // last launch of a call: its result must not be tentative
+    double* tape0;        // taped form: U^n of the launch's first step and U^{n+1} of its
+    double* tape1;        // second ([4][ny][nx] each; a one-step launch writes tape0 only)
+    long long plane;      // nx * ny
 };
 
 // Node codes of a solid body: per population i (0..3, the D2Q4 order) a
@@ -235,13 +238,15 @@ struct Batch2DArgs {
     double* f1;
     int cur;               // buffer holding f^n (host parity)
     double* tape;          // [4][total] or null
+    double* tape2;         // fused taped launches: U^{n+1} ([4][total])
     unsigned* status;      // per domain
 };
 
 hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
                                hipStream_t s);
 // Two fused steps of every domain (fixed lattice speeds), f^n in buffer a.cur.
-hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, int max_blocks, hipStream_t s);
+hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
+                                    hipStream_t s);
 int step2d_batch_pair_blocks_per_cu(int wpb);
 hipError_t launch_scalar_step2d(const ScalarArgs& a, int wpb, int max_blocks, hipStream_t s);
 hipError_t launch_scalar_step1d(const ScalarArgs& a, int q, hipStream_t s);
@@ -258,7 +263,8 @@ hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, bool
 int step2d_blocks_per_cu(int wpb, bool alt, bool dir, bool body = false);
 bool step2d_wpb_supported(int wpb);
 // Fused two-step launches (same waves-per-workgroup choices as the step).
-hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, int max_blocks, hipStream_t s);
+hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, bool tape, int max_blocks,
+                              hipStream_t s);
 int step2d_pair_blocks_per_cu(int wpb);
 // Start of a call of max_steps fused launches: clears the first-step
 // accumulators and records the step count to stop at.

@@ -95,6 +95,9 @@ struct PairGeom {
     int nx, ny, strip;
     double c4lam1, c4lam2, omega, gamma;
     int bc[4];
+    double* tape0;   // TAPE: U^n and U^{n+1}, element (k, y, x) at k*tape_ps + y*nx + x
+    double* tape1;
+    long long tape_ps;
 };
 
 __device__ inline void load_row(double v[16], const double* __restrict__ fin, long long ps,
@@ -113,7 +116,17 @@ __device__ inline void store_full_row(double* row, long long ps, int row_bytes, 
 // Rows y0..y1-1 of one strip, one step (TWO = false: f^{n+1} is the output)
 // or two.  lm1/bad1 gather the bound and admissibility of this tile's cells
 // of f^{n+1}, lm2/bad2 those of f^{n+2}.
-template <int WPB, bool TWO>
+// Moments of row j of a tape (rows [y0, y1) of the tile only: other rows
+// and lanes carry an out-of-range offset, so the store is unconditional).
+__device__ inline void tape_row(double* tape, long long tape_ps, int nx, int j, int y0, int y1,
+                                int voff, const double U[4]) {
+    const bool own = j >= y0 && j < y1;
+    double* row = tape + (long long)(own ? j : y0) * nx;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) store_row(row + k * tape_ps, nx * 8, own ? voff : 0x7fffffff, U[k]);
+}
+
+template <int WPB, bool TWO, bool TAPE>
 __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0, int y1, int lane,
                                            double& lm1, bool& bad1, double& lm2, bool& bad2) {
     const int nx = g.nx, ny = g.ny;
@@ -150,6 +163,7 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
         if (WPB > 1) __builtin_amdgcn_s_barrier();
         load_row(nxt, g.fin, g.ps, g.rs, map_index(r + 1, ny, py), xl);
         moments_d2q4(cur, U);
+        if (TAPE) tape_row(g.tape0, g.tape_ps, nx, r, y0, y1, voff, U);  // U^n of row r
         collide_hops(cur, U, gm1, g.c4lam1, g.omega, h);
         const int o1 = r - 1;
         double g1[16];
@@ -177,6 +191,7 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
         double U1[4], l1;
         moments_d2q4(g1, U1);
         const bool own1 = out_lane && o1 >= y0 && o1 < y1;
+        if (TAPE && TWO) tape_row(g.tape1, g.tape_ps, nx, o1, y0, y1, voff, U1);  // U^{n+1}
         const bool ok1 = bound_d2q4(U1, g.gamma, &l1);
         bad1 |= own1 && !ok1;
         lm1 = fmax(lm1, own1 ? l1 : 0.0);
@@ -244,6 +259,7 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
     for (int p = 0; p < 16; ++p) f[p] = nxt[p];
     load_row(nxt, g.fin, g.ps, g.rs, map_index(a0 + 1, ny, py), xl);
     moments_d2q4(f, U);
+    if (TAPE && !TWO) tape_row(g.tape0, g.tape_ps, nx, a0, y0, y1, voff, U);  // U^n of row y0
     collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -395,7 +411,7 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
 
 }  // namespace
 
-template <int WPB>
+template <int WPB, bool TAPE>
 __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     const LaunchSlots ls = slots_for(a.launch);
     const PairCtl c = pair_control(a, ls);
@@ -418,6 +434,9 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     g.omega = a.omega;
     g.gamma = a.gamma;
     for (int s = 0; s < 4; ++s) g.bc[s] = a.bc[s];
+    g.tape0 = a.tape0;
+    g.tape1 = a.tape1;
+    g.tape_ps = a.plane;
     const int total_waves = gridDim.x * WPB;
     const int ny = a.ny;
 
@@ -429,8 +448,8 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
         const int seg = tile / a.nstrips;
         const int y0 = (int)(((long long)seg * ny) / a.nseg);
         const int y1 = (int)(((long long)(seg + 1) * ny) / a.nseg);
-        if (c.two) march_pair<WPB, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
-        else march_pair<WPB, false>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+        if (c.two) march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+        else march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
     }
 
     const bool per_step = a.lam_mode == LAM_PER_STEP;
@@ -462,7 +481,7 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
 // list, numbered domain by domain (each domain's strip count a multiple of
 // the waves per workgroup, so a workgroup's waves share a domain and a row
 // segment); a non-physical f^{n+1} or f^{n+2} sets the domain's status.
-template <int WPB>
+template <int WPB, bool TAPE>
 __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -489,6 +508,9 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
         g.omega = d.omega;
         g.gamma = d.gamma;
         for (int s = 0; s < 4; ++s) g.bc[s] = d.bc[s];
+        g.tape0 = TAPE ? a.tape + d.coff : nullptr;
+        g.tape1 = TAPE ? a.tape2 + d.coff : nullptr;
+        g.tape_ps = a.total;
         const int local = (int)(tile - d.ptile0);
         const int strip = local % d.pnstrips;
         const int seg = local / d.pnstrips;
@@ -496,7 +518,7 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
         const int y1 = (int)(((long long)(seg + 1) * d.ny) / d.nseg);
         double lm1 = 0.0, lm2 = 0.0;
         bool bad1 = false, bad2 = false;
-        march_pair<WPB, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+        march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
         if (__any(bad1 || bad2) && lane == 0) atomicOr(&a.status[lo], 1u);
     }
 }
@@ -525,25 +547,32 @@ hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long
 }
 
 template <int WPB>
-static hipError_t launch_pair_w(const Pair2DArgs& a, int max_blocks, hipStream_t s) {
+static hipError_t launch_pair_w(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
     int nblocks = (a.ntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    hipLaunchKernelGGL((step2d_pair<WPB>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    if (tape) hipLaunchKernelGGL((step2d_pair<WPB, true>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    else hipLaunchKernelGGL((step2d_pair<WPB, false>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
     return hipGetLastError();
 }
 
 template <int WPB>
 static int pair_blocks_w() {
-    int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB>, 64 * WPB, 0);
-    return e == hipSuccess && n > 0 ? n : 1;
+    int n = 0, m = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false>,
+                                                                64 * WPB, 0);
+    hipError_t f = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, step2d_pair<WPB, true>,
+                                                                64 * WPB, 0);
+    if (e != hipSuccess || f != hipSuccess) return 1;
+    n = n < m ? n : m;  // one persistent grid size serves both forms
+    return n > 0 ? n : 1;
 }
 
 #define LBRS_PAIR_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12)
 
-hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, int max_blocks, hipStream_t s) {
+hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, bool tape, int max_blocks,
+                              hipStream_t s) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return launch_pair_w<W>(a, max_blocks, s);
+    if (wpb == W) return launch_pair_w<W>(a, tape, max_blocks, s);
     LBRS_PAIR_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return hipErrorInvalidValue;
@@ -558,24 +587,35 @@ int step2d_pair_blocks_per_cu(int wpb) {
 }
 
 template <int WPB>
-static hipError_t launch_batch_pair_w(const Batch2DArgs& a, int max_blocks, hipStream_t s) {
+static hipError_t launch_batch_pair_w(const Batch2DArgs& a, bool tape, int max_blocks,
+                                      hipStream_t s) {
     long long nblocks = (a.pntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    hipLaunchKernelGGL((step2d_batch_pair<WPB>), dim3((unsigned)nblocks), dim3(64 * WPB), 0, s, a);
+    if (tape)
+        hipLaunchKernelGGL((step2d_batch_pair<WPB, true>), dim3((unsigned)nblocks), dim3(64 * WPB),
+                           0, s, a);
+    else
+        hipLaunchKernelGGL((step2d_batch_pair<WPB, false>), dim3((unsigned)nblocks),
+                           dim3(64 * WPB), 0, s, a);
     return hipGetLastError();
 }
 
 template <int WPB>
 static int batch_pair_blocks_w() {
-    int n = 0;
-    hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_batch_pair<WPB>, 64 * WPB, 0);
-    return e == hipSuccess && n > 0 ? n : 1;
+    int n = 0, m = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_batch_pair<WPB, false>,
+                                                                64 * WPB, 0);
+    hipError_t f = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, step2d_batch_pair<WPB, true>,
+                                                                64 * WPB, 0);
+    if (e != hipSuccess || f != hipSuccess) return 1;
+    n = n < m ? n : m;
+    return n > 0 ? n : 1;
 }
 
-hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, int max_blocks, hipStream_t s) {
+hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
+                                    hipStream_t s) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return launch_batch_pair_w<W>(a, max_blocks, s);
+    if (wpb == W) return launch_batch_pair_w<W>(a, tape, max_blocks, s);
     LBRS_PAIR_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return hipErrorInvalidValue;
