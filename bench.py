@@ -216,6 +216,9 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     tap = _time_ms(lambda: [lbrs.lbrs_step_tape(sim.ctx, tape) for _ in range(k)]) / k
     g = torch.empty_like(run.fbar)
     adj = _time_ms(lambda: [lbrs.lbrs_adjoint_step(sim.ctx, tape, run.fbar, g) for _ in range(k)]) / k
+    k2 = max(1, k // 2)
+    adj2 = _time_ms(lambda: [lbrs.lbrs_adjoint_step2(sim.ctx, tape, tape, run.fbar, g)
+                             for _ in range(k2)]) / (2 * k2)
     r = rho0.clone().requires_grad_(True)
 
     def grad():
@@ -235,6 +238,8 @@ def adjoint_2d(n=2048, steps=2000, k=50):
             "adjoint_over_forward": round((tap + adj) / fwd, 3),
             "adjoint_over_single_forward": round((tap + adj) / fwd1, 3),
             "adjoint_step_GBs": round(288 * cells / (adj * 1e-3) / 1e9, 1),
+            "adjoint_step2_ms_per_step": round(adj2, 4),
+            "adjoint_step2_effective_GBs": round(288 * cells / (adj2 * 1e-3) / 1e9, 1),
             "gradient_ms": round(t_grad, 1), "forward_run_ms": round(t_fwd, 1),
             "gradient_over_forward_run": round(t_grad / t_fwd, 3)}
 

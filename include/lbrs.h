@@ -262,6 +262,16 @@ int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n);
 int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar_next,
                       double* d_fbar);
 
+/* Two adjoint steps in one launch: fbar^n from fbar^{n+2}, equal to
+ * lbrs_adjoint_step with d_Utape_n1 (U^{n+1}) followed by lbrs_adjoint_step
+ * with d_Utape_n (U^n), to rounding.  Each wavefront forms the rows of
+ * fbar^{n+1} and feeds them straight into the second step, so fbar^{n+2} is
+ * read and fbar^n written once (half the HBM traffic per step).  Layouts,
+ * modes and errors as lbrs_adjoint_step; d_fbar may not alias d_fbar_next2.
+ * lbrs_backward_checkpointed uses it when lbrs_set_fusion(c, 2) is on. */
+int lbrs_adjoint_step2(lbrs_ctx* c, const double* d_Utape_n1, const double* d_Utape_n,
+                       const double* d_fbar_next2, double* d_fbar);
+
 /* Adjoint of the initialisation f^0 = f^eq(U0): Ubar0 = sum_i (df_i^eq/dU)^T
  * fbar0_i at U0.  d_fbar0 [Q][K][ny][nx], d_U0 and d_Ubar0 [K][ny][nx].
  * FROZEN_INIT or USER mode only.  Asynchronous. */
@@ -338,7 +348,8 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * columns; automatic segments of at least 4 rows; 16 waves per workgroup run
  * as 12; alternate is ignored).
  * lbrs_step_tape stays a single step; lbrs_backward_checkpointed recomputes
- * its segments two steps per launch as well (both steps' input moments taped).
+ * its segments two steps per launch as well (both steps' input moments taped)
+ * and runs its adjoint steps two per launch (lbrs_adjoint_step2).
  * LBRS_E_INVAL for other values; LBRS_E_STATE with 2 for a 1D, scalar-law,
  * body or DIRICHLET context.  Takes effect for later calls. */
 int lbrs_set_fusion(lbrs_ctx* c, int steps_per_launch);
@@ -422,8 +433,9 @@ int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps);
  * the next step (as lbrs_set_fusion; the speeds are fixed, so nothing is
  * guessed): half the HBM traffic per step, the same results to rounding.  A
  * domain whose f^{n+1} or f^{n+2} is non-physical gets its status set.  The
- * gradient's taped recompute is fused too (both steps' input moments taped);
- * lbrs_batch2d_step_tape and the adjoint steps stay single steps.
+ * gradient's taped recompute and its adjoint steps are fused too (two per
+ * launch); lbrs_batch2d_step_tape and lbrs_batch2d_adjoint_step stay single
+ * steps.
  * LBRS_E_INVAL for other values. */
 int lbrs_batch2d_set_fusion(lbrs_batch2d* b, int steps_per_launch);
 

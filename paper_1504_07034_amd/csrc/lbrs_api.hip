@@ -34,6 +34,7 @@ struct lbrs_ctx {
     int fuse;            // 2D Euler: time steps per launch (1, or 2 fused)
     PairState* pst;      // record of the fused launches (scratch area, behind the time state)
     int pbpc[17];        // resident fused-kernel workgroups per CU, by waves per block
+    int abpc[17];        // the same for the fused adjoint kernel
 };
 
 static int nq(int model) { return model == LBRS_D1Q2 ? 2 : (model == LBRS_D1Q3 ? 3 : 4); }
@@ -439,6 +440,9 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
     return a;
 }
 
+static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const double* gn,
+                        double* g);
+
 // Fused two-step launches: strips of at most 60 columns (two halo lanes on
 // each side), segments of at least 4 rows (two halo rows on each side).
 // Waves per workgroup of the fused kernel: 16-wave groups do not fit its
@@ -707,6 +711,17 @@ int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar
     return hip_status(launch_adjoint_step(a, d_Utape_n, d_fbar_next, d_fbar, c->stream));
 }
 
+int lbrs_adjoint_step2(lbrs_ctx* c, const double* d_Utape_n1, const double* d_Utape_n,
+                       const double* d_fbar_next2, double* d_fbar) {
+    if (!c || !d_Utape_n1 || !d_Utape_n || !d_fbar_next2 || !d_fbar || d_fbar == d_fbar_next2)
+        return LBRS_E_INVAL;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER || c->codes) return LBRS_E_STATE;
+    for (int s = 0; s < 4; ++s)
+        if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
+    return adjoint_pair(c, d_Utape_n1, d_Utape_n, d_fbar_next2, d_fbar);
+}
+
 int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, double* d_Ubar0) {
     if (!c || !d_fbar0 || !d_U0 || !d_Ubar0) return LBRS_E_INVAL;
     if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
@@ -737,6 +752,40 @@ int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ck
         if (rc) return rc;
     }
     return LBRS_OK;
+}
+
+// Two adjoint steps in one launch: fbar^{n+2} -> fbar^n with U^{n+1} (Ua) and
+// U^n (Ub), in the fused launches' strips and automatic row segments.
+static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const double* gn,
+                        double* g) {
+    AdjPairArgs a;
+    a.plane = c->plane;
+    a.ps = c->ps;
+    a.rs = c->rs;
+    a.nx = c->P.nx;
+    a.ny = c->P.ny;
+    const int wpb = pair_wpb(c);
+    a.nstrips = ((c->P.nx + 59) / 60 + wpb - 1) / wpb * wpb;
+    a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
+    int& bpc = c->abpc[wpb];
+    if (bpc == 0) bpc = adjoint_pair_blocks_per_cu(wpb);
+    const int mb = c->cu_count * bpc;
+    long long nseg = (long long)mb * wpb / a.nstrips;
+    const long long cap = (c->P.ny + 3) / 4;
+    if (c->rows_per_tile > 0) nseg = (c->P.ny + c->rows_per_tile - 1) / c->rows_per_tile;
+    else if (nseg > cap) nseg = cap;
+    if (nseg < 1) nseg = 1;
+    if (nseg > c->P.ny) nseg = c->P.ny;
+    a.nseg = (int)nseg;
+    a.ntiles = a.nstrips * a.nseg;
+    a.gamma = c->P.gamma;
+    a.omega = c->P.omega;
+    a.st = c->st;
+    a.Ua = Ua;
+    a.Ub = Ub;
+    a.gn = gn;
+    a.g = g;
+    return hip_status(launch_adjoint_pair(a, wpb, mb, c->stream));
 }
 
 // The recompute of a segment in fused launches (fixed lattice speed, so
@@ -800,7 +849,17 @@ int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const doubl
                 if (rc) return rc;
             }
         }
-        for (int i = len - 1; i >= 0; --i) {
+        int i = len - 1;
+        if (c->fuse == 2) {  // two adjoint steps per launch: tapes i (U^{n+1}) and i-1 (U^n)
+            for (; i >= 1; i -= 2) {
+                rc = adjoint_pair(c, d_tape + i * ucount, d_tape + (i - 1) * ucount, cur, nxt);
+                if (rc) return rc;
+                double* t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+        }
+        for (; i >= 0; --i) {
             rc = lbrs_adjoint_step(c, d_tape + i * ucount, cur, nxt);
             if (rc) return rc;
             double* t = cur;

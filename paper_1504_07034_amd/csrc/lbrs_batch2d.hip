@@ -212,6 +212,7 @@ struct lbrs_batch2d {
     int fuse;                 // time steps per forward launch (1, or 2 fused)
     long long pntiles;        // tiles of the fused launches
     int pmax_blocks;
+    int amax_blocks;          // resident workgroups of the fused adjoint kernel
     hipGraph_t graph;
     hipGraphExec_t exec;
     const void* graph_args[7];  // arguments the captured gradient graph was built with
@@ -289,6 +290,7 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
     b->wpb = 8;
     b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb, true, false);
     b->pmax_blocks = prop.multiProcessorCount * step2d_batch_pair_blocks_per_cu(b->wpb);
+    b->amax_blocks = prop.multiProcessorCount * b2_adjoint_pair_blocks_per_cu(b->wpb);
     b->fuse = 1;
     b->doms.resize(ndom);
     long long off = 0, rows = 0, tiles = 0, ptiles = 0;
@@ -513,11 +515,30 @@ int lbrs_batch2d_window_objective(lbrs_batch2d* b, double* d_J, double* d_fbar) 
 
 // Whole gradient of J_d (each domain's window objective) with respect to U0:
 // reset from U0, forward with checkpoints every `segment` steps, objective,
+// Two adjoint steps of every domain (fused launch): fbar^{n+2} -> fbar^n with
+// U^{n+1} (Ua) and U^n (Ub).
+static int b2_adjoint_pair_step(lbrs_batch2d* b, const double* Ua, const double* Ub,
+                                const double* gn, double* g) {
+    Batch2DAdjPairArgs a;
+    a.doms = b->d_doms;
+    a.ndom = b->ndom;
+    a.pntiles = b->pntiles;
+    a.total = b->total;
+    a.Ua = Ua;
+    a.Ub = Ub;
+    a.gn = gn;
+    a.g = g;
+    return ok(launch_b2_adjoint_pair(a, b->wpb, b->amax_blocks, b->stream)) ? LBRS_OK : LBRS_E_HIP;
+}
+
 // backward sweep (recompute each segment with a tape, reverse adjoint steps),
 // adjoint of the initialisation.  Enqueue only (no host synchronisation).
 static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, int segment,
                                double* d_ckpt, double* d_tape, double* d_fbar, double* d_work,
                                double* d_J, double* d_Ubar0) {
+    for (const Domain2D& d : b->doms)  // the adjoint steps are written for periodic sides
+        for (int s = 0; s < 4; ++s)
+            if (d.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
     int rc = lbrs_batch2d_reset(b, d_U0);
     if (rc) return rc;
     const long long fcount = 16 * b->total, ucount = 4 * b->total;
@@ -546,7 +567,16 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
         }
         for (; i < len; ++i)
             if ((rc = lbrs_batch2d_step_tape(b, d_tape + i * ucount))) return rc;
-        for (int i = len - 1; i >= 0; --i) {
+        i = len - 1;
+        if (b->fuse == 2) {  // two adjoint steps per launch: tapes i (U^{n+1}) and i-1 (U^n)
+            for (; i >= 1; i -= 2) {
+                if ((rc = b2_adjoint_pair_step(b, d_tape + i * ucount, d_tape + (i - 1) * ucount,
+                                               cur, nxt)))
+                    return rc;
+                std::swap(cur, nxt);
+            }
+        }
+        for (; i >= 0; --i) {
             if ((rc = lbrs_batch2d_adjoint_step(b, d_tape + i * ucount, cur, nxt))) return rc;
             std::swap(cur, nxt);
         }

@@ -153,6 +153,21 @@ struct AdjArgs {
     const DevState* st;  // the fixed lattice speed is read from st->lam_fixed
 };
 
+// Two adjoint steps per launch (periodic D2Q4): fbar^n from fbar^{n+2}, with
+// U^{n+1} and U^n from the tape; tiles as in Pair2DArgs.
+struct AdjPairArgs {
+    long long plane;
+    long long ps, rs;       // population layout
+    int nx, ny;
+    int strip, nstrips, nseg, ntiles;
+    double gamma, omega;
+    const DevState* st;     // the fixed lattice speed is read from st->lam_fixed
+    const double* Ua;       // U^{n+1} [4][ny][nx]
+    const double* Ub;       // U^n
+    const double* gn;       // fbar^{n+2}
+    double* g;              // fbar^n
+};
+
 // team arrival counters sit on separate 128-byte lines
 static constexpr int COUNTER_STRIDE = 32;
 // largest team (workgroups sharing one unit)
@@ -296,5 +311,21 @@ hipError_t launch_adjoint_step(const AdjArgs& a, const double* Un, const double*
                                hipStream_t s);
 hipError_t launch_adjoint_init(const AdjArgs& a, const double* fb0, const double* U0, double* Ub,
                                hipStream_t s);
+hipError_t launch_adjoint_pair(const AdjPairArgs& a, int wpb, int max_blocks, hipStream_t s);
+int adjoint_pair_blocks_per_cu(int wpb);
+// Two adjoint steps of every domain of a 2D batch (tiles of the fused launches).
+struct Batch2DAdjPairArgs {
+    const Domain2D* doms;
+    int ndom;
+    long long pntiles;
+    long long total;        // cells of all domains (plane of the tapes)
+    const double* Ua;       // U^{n+1} [4][total]
+    const double* Ub;       // U^n
+    const double* gn;       // fbar^{n+2}
+    double* g;              // fbar^n
+};
+hipError_t launch_b2_adjoint_pair(const Batch2DAdjPairArgs& a, int wpb, int max_blocks,
+                                  hipStream_t s);
+int b2_adjoint_pair_blocks_per_cu(int wpb);
 
 }  // namespace lbrs

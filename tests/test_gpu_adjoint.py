@@ -123,14 +123,17 @@ def _oracle_dJ(n, steps, rho0, d, window):
     return float(np.sum(U[0][m] ** 2)), float(np.sum(2.0 * U[0][m] * dU[0][m]))
 
 
+@pytest.mark.parametrize("fuse,segment", [(1, 8), (2, 8), (2, 7)])
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_gradient_matches_oracle_dual_numbers(layout):
-    """Checkpointed gradient (48^2, 60 steps, segment 8) against the oracle's exact
-    directional derivatives along three smooth directions."""
+def test_gradient_matches_oracle_dual_numbers(layout, fuse, segment):
+    """Checkpointed gradient (48^2, 60 steps) against the oracle's exact
+    directional derivatives along three smooth directions; single launches, or
+    fused forward, recompute and adjoint steps (two per launch; an odd segment
+    leaves one single step of each)."""
     n, steps = 48, 60
     w = wl.acoustic_pulse(n, steps=steps)
     rho0 = torch.from_numpy(w.W[0].copy()).cuda()
-    spec = adjoint.GradientSpec(n=n, steps=steps, layout=layout, segment=8)
+    spec = adjoint.GradientSpec(n=n, steps=steps, layout=layout, segment=segment, fuse=fuse)
     run = adjoint.GradientRunner(spec, rho0)
     r = rho0.clone().requires_grad_(True)
     J = adjoint.LBRSFunction.apply(r, run)
@@ -140,20 +143,23 @@ def test_gradient_matches_oracle_dual_numbers(layout):
         d = wl.bump_direction(n, seed=200 + k)
         J_o, dJ_o = _oracle_dJ(n, steps, w.W[0], d, (0.7, 0.8))
         dJ_g = float(np.sum(grad * d))
-        report("grad vs dual", k=k, layout=layout, J=J.item(), J_oracle=J_o, gpu=dJ_g, oracle=dJ_o)
+        report("grad vs dual", k=k, layout=layout, fuse=fuse, J=J.item(), J_oracle=J_o, gpu=dJ_g,
+               oracle=dJ_o)
         assert abs(J.item() - J_o) <= 1e-12 * abs(J_o)
         assert abs(dJ_g - dJ_o) <= 1e-9 * abs(dJ_o)
     run.close()
 
 
-def test_gradient_finite_differences_full_size():
-    """Full size: 2048^2 periodic acoustic pulse, 2000 steps, sqrt(T) checkpoints;
-    the gradient dJ/drho0 against central differences (h = 1e-4) along 16 seeded
-    smooth directions, relative error <= 1e-5."""
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_gradient_finite_differences_full_size(fuse):
+    """Full size: 2048^2 periodic acoustic pulse, 2000 steps, sqrt(T) checkpoints
+    (segments of 45), single or fused launches; the gradient dJ/drho0 against
+    central differences (h = 1e-4) along 16 seeded smooth directions, relative
+    error <= 1e-5."""
     n, steps = 2048, 2000
     w = wl.acoustic_pulse(n, steps=steps)
     rho0 = torch.from_numpy(w.W[0].copy()).cuda()
-    spec = adjoint.GradientSpec(n=n, steps=steps)
+    spec = adjoint.GradientSpec(n=n, steps=steps, fuse=fuse)
     run = adjoint.GradientRunner(spec, rho0)
     report("fd setup", lam=spec.lam, segment=spec.seg, window=run.win)
     r = rho0.clone().requires_grad_(True)
@@ -174,3 +180,37 @@ def test_gradient_finite_differences_full_size():
         assert rel <= 1e-5
     report("fd worst", rel=worst)
     run.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("n", [48, 130])
+def test_adjoint_step2_equals_two_steps(layout, n):
+    """lbrs_adjoint_step2 (two reverse steps per launch) against two calls of
+    lbrs_adjoint_step on the same tapes and random fbar, ragged strips and
+    segments included."""
+    w = wl.fourier_modes(n, seed=5)
+    sim = lbrs.Sim(lbrs.LBRS_D2Q4, n, n, gamma=w.gamma, omega=1.3, cfl=w.cfl, bc=(1, 1, 1, 1),
+                   lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT, layout=layout)
+    sim.init_primitive(w.W)
+    t0 = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
+    t1 = torch.empty_like(t0)
+    lbrs.lbrs_step_tape(sim.ctx, t0)
+    lbrs.lbrs_step_tape(sim.ctx, t1)
+    rng = np.random.default_rng(4)
+    g2 = torch.from_numpy(rng.standard_normal(16 * n * n)).cuda()
+    g1 = torch.empty_like(g2)
+    g0 = torch.empty_like(g2)
+    lbrs.lbrs_adjoint_step(sim.ctx, t1, g2, g1)
+    lbrs.lbrs_adjoint_step(sim.ctx, t0, g1, g0)
+    h0 = torch.empty_like(g2)
+    for tile in [(0, 4), (0, 8), (3, 2), (0, 1)]:
+        sim.set_tile(*tile)
+        h0.fill_(float("nan"))
+        lbrs.lbrs_adjoint_step2(sim.ctx, t1, t0, g2, h0)
+        diff = float((h0 - g0).abs().max())
+        report("adjoint step2", n=n, layout=layout, tile=tile, max_abs=diff,
+               bitwise=bool(torch.equal(h0, g0)))
+        assert diff <= 1e-12 * float(g0.abs().max())
+    with pytest.raises(lbrs.LBRSError):
+        lbrs.lbrs_adjoint_step2(sim.ctx, t1, t0, g2, g2)
+    sim.close()
