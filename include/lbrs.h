@@ -213,7 +213,9 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
  * one node along every link, applies the side conditions and reduces the next
  * step's lambda* (with the prescribed states of DIRICHLET sides).  A step whose start time is >= t_end, or that follows a
  * non-physical step, does nothing, so the run stops exactly at t_end
- * (PER_STEP mode clips the last dt).  Asynchronous. */
+ * (PER_STEP mode clips the last dt).  With lbrs_set_fusion(c, 2) (2D Euler)
+ * the steps run two per launch with the same results (see there).
+ * Asynchronous. */
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
 
 /* Wait for the stream and report the current time, completed step count,
