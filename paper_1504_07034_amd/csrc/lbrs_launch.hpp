@@ -35,13 +35,18 @@ struct Step2DArgs {
 // recorded bound equals the guess bit for bit and the first step was
 // admissible, else falls back to the state before it.  The record lives in
 // slot (p+1) & 1 beside the time state; the first step's bound and flag are
-// slotted like DevState::lam and DevState::bad.
+// slotted like DevState::lam and DevState::bad.  When the bound has stopped
+// repeating (trust 0), a launch instead reduces the bound of f^{n+1} alone
+// (nothing stored) and the next launch takes two steps with it.
 struct PairSlot {
     double t_base;              // state before the launch's steps
     long long n_base;
     int cur_base;
     int tentative;              // 1: the next launch must check this launch's guess
     unsigned long long guess;   // bits of lambda*_n (the guessed lambda*_{n+1})
+    int known;                  // 1: this launch only reduced the bound of f^{n+1} (no step)
+    int trust;                  // 0..3: +1 when a check finds the bound repeated, -1 when
+                                // not; new pairs guess while > 0
 };
 
 struct PairState {

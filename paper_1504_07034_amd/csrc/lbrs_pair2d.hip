@@ -28,8 +28,13 @@
 // two single steps, and it continues from f^{n+2}; otherwise f^n, still
 // intact in the other buffer, is current again, and that launch repeats the
 // pair with the now known lambda*_{n+1} (or one step when the first step was
-// non-physical).  A launch that resolves nothing takes the same decisions in
-// every workgroup from the same slots, so no grid barrier is needed.  The
+// non-physical).  Where the bound keeps changing, guessing wastes a pass per
+// two steps; a saturating count of how often the checked bound repeated
+// (0..3, one up for a repeat, one down for a change) decides: at 0 a launch
+// first reduces the bound of f^{n+1} alone (reading f^n, storing nothing) and
+// the next launch takes the two steps with it; above 0 it guesses.  Every launch takes the
+// same decisions in every workgroup from the same slots, so no grid barrier
+// is needed.  The
 // last launch of a call never leaves a tentative result, so every other call
 // sees an ordinary time state.
 #include "lbrs_launch.hpp"
@@ -128,7 +133,8 @@ __device__ inline void tape_row(double* tape, long long tape_ps, int nx, int j, 
 
 template <int WPB, bool TWO, bool TAPE>
 __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0, int y1, int lane,
-                                           double& lm1, bool& bad1, double& lm2, bool& bad2) {
+                                           double& lm1, bool& bad1, double& lm2, bool& bad2,
+                                           bool store = true) {
     const int nx = g.nx, ny = g.ny;
     const bool px = g.bc[0] == BC_PERIODIC, py = g.bc[2] == BC_PERIODIC;
     const double gm1 = g.gamma - 1.0;
@@ -196,7 +202,9 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
         bad1 |= own1 && !ok1;
         lm1 = fmax(lm1, own1 ? l1 : 0.0);
         if (!TWO) {
-            store_full_row(g.fout + (long long)o1 * g.rs, g.ps, row_bytes, voff, g1);
+            // (a bound-only launch drops the row: out-of-range offset)
+            store_full_row(g.fout + (long long)o1 * g.rs, g.ps, row_bytes,
+                           store ? voff : 0x7fffffff, g1);
             return;
         }
         // second step: row q = o1 of f^{n+1} completes row q - 1 of f^{n+2}
@@ -303,7 +311,9 @@ struct PairCtl {
     bool active;        // at least one step
     bool two;           // two steps
     bool tentative;     // the result waits for the next launch's check
+    bool bound;         // this launch only reduces the bound of f^{n+1}
     bool accepted_bad;  // the previous launch's pair stands, with a non-physical f^{n+2}
+    int trust;          // saturating count of repeated bounds at the last checks (0..3)
     int cur;
     long long n;
     double t, lam_used;
@@ -322,11 +332,13 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
     unsigned bad = st->bad[ls.lr];
     bool know_next = false, force_single = false;
     unsigned long long next = 0ull;
+    int trust = q.trust;
     c.accepted_bad = false;
     if (q.tentative) {
         const unsigned long long m1 = ps->lam1[ls.lr];
         const bool b1 = ps->bad1[ls.lr] != 0u;
         const bool ok = !b1 && (a.lam_mode != LAM_PER_STEP || m1 == q.guess);
+        if (!b1) trust = m1 == q.guess ? min(trust + 1, 3) : max(trust - 1, 0);
         if (ok) {
             c.accepted_bad = bad != 0u;
         } else {
@@ -340,6 +352,14 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
             know_next = !b1;
             next = m1;
         }
+    } else if (q.known) {
+        // the previous launch reduced the bound of f^{n+1} of this state
+        const unsigned long long m1 = ps->lam1[ls.lr];
+        const bool b1 = ps->bad1[ls.lr] != 0u;
+        force_single = b1;
+        know_next = !b1;
+        next = m1;
+        if (!b1) trust = m1 == lstar ? min(trust + 1, 3) : max(trust - 1, 0);
     }
     c.cur = s.cur;
     c.n = s.n;
@@ -353,8 +373,13 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
     step_size(a.lam_mode, from_bits(lstar > lbc ? lstar : lbc), st->lam_fixed, a.dx, a.cfl, s.t,
               a.t_end, c.lam1, c.t1);
     c.two = c.active && !force_single && c.t1 < a.t_end && s.n + 2 <= n_limit;
+    // a new pair with per-step speeds: guess the bound while it has been
+    // repeating, else reduce it first
+    c.bound = c.two && !know_next && a.lam_mode == LAM_PER_STEP && trust == 0;
+    if (c.bound) c.two = false;
     c.tentative = c.two && !know_next;
-    if (a.last && c.tentative) c.two = c.tentative = false;
+    if (a.last && (c.tentative || c.bound)) c.two = c.tentative = c.bound = false;
+    c.trust = trust;
     c.lam2 = c.lam1;
     c.t2 = c.t1;
     if (c.two) {
@@ -378,6 +403,8 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
     q.cur_base = c.cur;
     q.guess = c.lstar;
     q.tentative = 0;
+    q.known = 0;
+    q.trust = c.trust;
     if (!c.active) {
         s.t = c.t;
         s.n = c.n;
@@ -385,6 +412,16 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
         s.cur = c.cur;
         st->lam[ls.la] = c.lstar;
         st->bad[ls.la] = c.bad;
+    } else if (c.bound) {
+        // no step: the state and its bound carry over; the first-step
+        // accumulators receive the bound of f^{n+1}
+        s.t = c.t;
+        s.n = c.n;
+        s.lam_used = c.lam_used;
+        s.cur = c.cur;
+        st->lam[ls.la] = c.lstar;
+        st->bad[ls.la] = 0u;
+        q.known = 1;
     } else if (!c.two) {
         s.t = c.t1;
         s.n = c.n + 1;
@@ -449,7 +486,7 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
         const int y0 = (int)(((long long)seg * ny) / a.nseg);
         const int y1 = (int)(((long long)(seg + 1) * ny) / a.nseg);
         if (c.two) march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
-        else march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+        else march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2, !c.bound);
     }
 
     const bool per_step = a.lam_mode == LAM_PER_STEP;
@@ -467,6 +504,10 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
             if (c.tentative) atomicOr(&a.st->bad[ls.la], 1u);
             else publish_bad(a.st, ls, c.n + 2);
         }
+    } else if (c.bound) {
+        const double w1 = wave_max(lm1);
+        if (lane == 0) publish_max(&a.pst->lam1[ls.la], w1);
+        if (__any(bad1) && lane == 0) atomicOr(&a.pst->bad1[ls.la], 1u);
     } else {
         if (per_step) {
             const double w1 = wave_max(lm1);
@@ -532,6 +573,8 @@ __global__ void pair_prepare_kernel(PairState* ps, const DevState* st, int slot,
         ps->q[i].cur_base = 0;
         ps->q[i].tentative = 0;
         ps->q[i].guess = 0ull;
+        ps->q[i].known = 0;
+        ps->q[i].trust = 3;  // start a call by guessing
     }
     for (int i = 0; i < 3; ++i) {
         ps->lam1[i] = 0ull;
