@@ -34,8 +34,8 @@ SINGLE_SOURCES = ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 # bytes per launch over the timed launches of the benchmark window (per-step
 # lattice speeds: one launch per step, of which those past the steps done exit
 # at once), profiles/step2d_pair_riemann4096.md.
-PAIR_TRAFFIC_BYTES = {"8": 2.8724e9, "6": 2.8738e9, "4": 2.9097e9}
-PAIR_TRAFFIC_SOURCE_HASH = "b3f4c23b075cb350"
+PAIR_TRAFFIC_BYTES = {"8": 2.9920e9, "6": 2.9919e9, "4": 3.0305e9}
+PAIR_TRAFFIC_SOURCE_HASH = "2f5c1556053b413f"
 PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 
 
