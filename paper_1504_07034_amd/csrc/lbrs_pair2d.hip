@@ -32,11 +32,13 @@
 // two steps; a saturating count of how often the checked bound repeated
 // (0..3, one up for a repeat, one down for a change) decides: at 0 a launch
 // first reduces the bound of f^{n+1} alone (reading f^n, storing nothing) and
-// the next launch takes the two steps with it; above 0 it guesses.  Every launch takes the
-// same decisions in every workgroup from the same slots, so no grid barrier
-// is needed.  The
-// last launch of a call never leaves a tentative result, so every other call
-// sees an ordinary time state.
+// the next launch takes the two steps with it; above 0 it guesses.  Every
+// workgroup of a launch takes the same decisions from the same slots, so no
+// grid barrier is needed.  The last launch of a call never leaves a
+// tentative result, so every other call sees an ordinary time state.
+//
+// Also here: the taped form (U^n and U^{n+1} stored for the gradients'
+// recompute) and the 2D batch's form over all domains (fixed speeds).
 #include "lbrs_launch.hpp"
 #include "lbrs_rowops.hpp"
 
