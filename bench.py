@@ -213,12 +213,17 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     fwd1 = _time_ms(lambda: sim.step(k)) / k
     sim.set_fusion(best["fuse"])
     tape = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
+    tape1 = torch.empty_like(tape)
     tap = _time_ms(lambda: [lbrs.lbrs_step_tape(sim.ctx, tape) for _ in range(k)]) / k
+    k2 = max(1, k // 2)
+    tap2 = _time_ms(lambda: [lbrs.lbrs_step_tape2(sim.ctx, tape, tape1)
+                             for _ in range(k2)]) / (2 * k2)
     g = torch.empty_like(run.fbar)
     adj = _time_ms(lambda: [lbrs.lbrs_adjoint_step(sim.ctx, tape, run.fbar, g) for _ in range(k)]) / k
-    k2 = max(1, k // 2)
     adj2 = _time_ms(lambda: [lbrs.lbrs_adjoint_step2(sim.ctx, tape, tape, run.fbar, g)
                              for _ in range(k2)]) / (2 * k2)
+    if best["fuse"] == 1:
+        tap2, adj2 = tap, adj
     r = rho0.clone().requires_grad_(True)
 
     def grad():
@@ -233,13 +238,16 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     return {"n": n, "steps": steps, "segment": run.spec.seg,
             "tile_rows": best["rows"], "waves_per_block": best["wpb"], "alternate": best["alt"],
             "steps_per_launch": best["fuse"],
-            "forward_step_ms": round(fwd, 4), "forward_single_step_ms": round(fwd1, 4),
-            "tape_step_ms": round(tap, 4), "adjoint_step_ms": round(adj, 4),
-            "adjoint_over_forward": round((tap + adj) / fwd, 3),
-            "adjoint_over_single_forward": round((tap + adj) / fwd1, 3),
-            "adjoint_step_GBs": round(288 * cells / (adj * 1e-3) / 1e9, 1),
-            "adjoint_step2_ms_per_step": round(adj2, 4),
-            "adjoint_step2_effective_GBs": round(288 * cells / (adj2 * 1e-3) / 1e9, 1),
+            # per step: forward, taped recompute and adjoint, in the tuned
+            # (fused) form and as single steps
+            "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap2, 4),
+            "adjoint_step_ms": round(adj2, 4),
+            "adjoint_over_forward": round((tap2 + adj2) / fwd, 3),
+            "adjoint_step_effective_GBs": round(288 * cells / (adj2 * 1e-3) / 1e9, 1),
+            "single": {"forward_step_ms": round(fwd1, 4), "tape_step_ms": round(tap, 4),
+                       "adjoint_step_ms": round(adj, 4),
+                       "adjoint_over_forward": round((tap + adj) / fwd1, 3),
+                       "adjoint_step_GBs": round(288 * cells / (adj * 1e-3) / 1e9, 1)},
             "gradient_ms": round(t_grad, 1), "forward_run_ms": round(t_fwd, 1),
             "gradient_over_forward_run": round(t_grad / t_fwd, 3)}
 

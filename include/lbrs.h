@@ -251,6 +251,12 @@ int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, doubl
  * identical to lbrs_step(c, 1, +inf). */
 int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n);
 
+/* Two taped forward steps in fused launches (two steps per launch, as
+ * lbrs_set_fusion(c, 2)): U^n goes to d_Utape_n and U^{n+1} to d_Utape_n1;
+ * equal to two lbrs_step_tape calls to rounding.  Same modes and errors as
+ * lbrs_step_tape; the tapes may not alias.  Asynchronous. */
+int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1);
+
 /* Adjoint (vector-Jacobian product) of one fixed-speed step, D2Q4 with
  * periodic sides: given fbar^{n+1} = dJ/df^{n+1} and the step's input moments
  * U^n, write fbar^n = dJ/df^n:

@@ -813,6 +813,29 @@ static int step_tape_fused(lbrs_ctx* c, int len, double* d_tape) {
     return LBRS_OK;
 }
 
+int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
+    if (!c || !d_Utape_n || !d_Utape_n1 || d_Utape_n == d_Utape_n1) return LBRS_E_INVAL;
+    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP) return LBRS_E_STATE;
+    if (c->dim != 2 || c->dir || c->codes) return LBRS_E_STATE;
+    // the set-up kernel and two launches: the pair, then the one that checks
+    // it (a one-step fallback writes slot d_Utape_n, as the first step would)
+    Pair2DArgs a = pair_args(c, INFINITY);
+    hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), 2, c->stream);
+    if (e != hipSuccess) return LBRS_E_HIP;
+    const int mb = pair_max_blocks(c);
+    a.tape0 = d_Utape_n;
+    a.tape1 = d_Utape_n1;
+    for (int k = 0; k < 2; ++k) {
+        a.launch = c->launches;
+        a.last = k == 1;
+        e = launch_step2d_pair(a, pair_wpb(c), true, mb, c->stream);
+        if (e != hipSuccess) return LBRS_E_HIP;
+        ++c->launches;
+    }
+    return LBRS_OK;
+}
+
 int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const double* d_ckpt,
                                double* d_tape, double* d_fbar, double* d_work) {
     if (!c || !d_ckpt || !d_tape || !d_fbar || !d_work || d_fbar == d_work || nsteps < 1 ||

@@ -39,6 +39,7 @@ EXPORTS = (
     "lbrs_batch2d_moments", "lbrs_batch2d_get_f", "lbrs_batch2d_set_f", "lbrs_batch2d_gradient",
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
     "lbrs_destroy", "lbrs_set_fusion", "lbrs_batch2d_set_fusion", "lbrs_adjoint_step2",
+    "lbrs_step_tape2",
 )
 
 
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_set_fusion": (i, [vp, i]),
         "lbrs_batch2d_set_fusion": (i, [vp, i]),
         "lbrs_adjoint_step2": (i, [vp, vp, vp, vp, vp]),
+        "lbrs_step_tape2": (i, [vp, vp, vp]),
         "lbrs_batch_query": (i, [i, P, i, ctypes.POINTER(ll), szp]),
         "lbrs_batch_init": (i, [ctypes.POINTER(vp), i, P, dp, i, vp, vp, vp, vp]),
         "lbrs_batch_run": (i, [vp, i]),
@@ -294,6 +296,10 @@ def lbrs_step_tape(ctx, Utape):
 def lbrs_adjoint_step(ctx, Utape, fbar_next, fbar):
     _check(load_library().lbrs_adjoint_step(ctx, _dptr(Utape), _dptr(fbar_next), _dptr(fbar)),
            "lbrs_adjoint_step")
+
+
+def lbrs_step_tape2(ctx, Utape_n, Utape_n1):
+    _check(load_library().lbrs_step_tape2(ctx, _dptr(Utape_n), _dptr(Utape_n1)), "lbrs_step_tape2")
 
 
 def lbrs_adjoint_step2(ctx, Utape_n1, Utape_n, fbar_next2, fbar):

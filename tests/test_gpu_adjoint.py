@@ -214,3 +214,35 @@ def test_adjoint_step2_equals_two_steps(layout, n):
     with pytest.raises(lbrs.LBRSError):
         lbrs.lbrs_adjoint_step2(sim.ctx, t1, t0, g2, g2)
     sim.close()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("n", [70, 130])
+def test_step_tape2_equals_two_taped_steps(layout, n):
+    """lbrs_step_tape2 (two taped steps in fused launches) against two calls of
+    lbrs_step_tape from the same state: tapes, populations, time and count."""
+    w = wl.fourier_modes(n, seed=6)
+    outs = []
+    for fused in (False, True):
+        sim = lbrs.Sim(lbrs.LBRS_D2Q4, n, n, gamma=w.gamma, omega=1.3, cfl=w.cfl,
+                       bc=(1, 1, 1, 1), lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT, layout=layout)
+        sim.init_primitive(w.W)
+        sim.step(3)
+        t0 = torch.full((4, n, n), float("nan"), dtype=torch.float64, device="cuda")
+        t1 = torch.full_like(t0, float("nan"))
+        if fused:
+            lbrs.lbrs_step_tape2(sim.ctx, t0, t1)
+            with pytest.raises(lbrs.LBRSError):
+                lbrs.lbrs_step_tape2(sim.ctx, t0, t0)
+        else:
+            lbrs.lbrs_step_tape(sim.ctx, t0)
+            lbrs.lbrs_step_tape(sim.ctx, t1)
+        outs.append((t0, t1, sim.get_f(), sim.state()))
+        sim.close()
+    (a0, a1, fa, sa), (b0, b1, fb, sb) = outs
+    assert sa["nsteps"] == sb["nsteps"] == 5 and sa["t"] == sb["t"]
+    d = max(float((a0 - b0).abs().max()), float((a1 - b1).abs().max()),
+            float((fa - fb).abs().max()))
+    report("step_tape2", n=n, layout=layout, max_abs=d,
+           bitwise=bool(torch.equal(a0, b0) and torch.equal(a1, b1) and torch.equal(fa, fb)))
+    assert d <= 1e-12
