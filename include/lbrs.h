@@ -246,9 +246,9 @@ int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, doubl
                           double* d_fbar);
 
 /* Forward step that also stores the step's input moments U^n into
- * d_Utape_n [K][ny][nx] (the tape the adjoint step reads).  FROZEN_INIT or
- * USER mode and no DIRICHLET side only (else LBRS_E_STATE); otherwise
- * identical to lbrs_step(c, 1, +inf). */
+ * d_Utape_n [K][ny][nx] (the tape the adjoint step reads).  2D Euler with
+ * no body and no DIRICHLET side, FROZEN_INIT or USER mode only (else
+ * LBRS_E_STATE); otherwise identical to lbrs_step(c, 1, +inf). */
 int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n);
 
 /* Two taped forward steps in fused launches (two steps per launch, as
