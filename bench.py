@@ -109,7 +109,7 @@ def _host_cpu() -> dict:
             "affinity": len(os.sched_getaffinity(0))}
 
 
-def batched_1d(chunks=(510, 1022, 2046), subset=32):
+def batched_1d(chunks=(1022, 2046, 3070), subset=32):
     """Ragged 1D batch: 1024 seeded shock tubes (200..20000 cells, own t_end) in
     one persistent launch (chunk autotuned), against sequential single-domain
     runs of a seeded subset of the same tubes (the plain library path: one
@@ -716,7 +716,7 @@ def main():
               "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
               "scalar": scalar_laws, "euler1d": euler_1d_long, "slab": slab_step,
               "bodies": bodies_2d,
-              "batch1d_run": lambda: batched_1d(chunks=(2046,), subset=0)}[args.only]
+              "batch1d_run": lambda: batched_1d(chunks=(3070,), subset=0)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096

@@ -376,7 +376,8 @@ typedef struct lbrs_batch lbrs_batch;
 
 /* Offsets of the units in the pools (offsets[nunits] = total cells; may be
  * NULL) and the device scratch size for a chunk size (cells per workgroup,
- * >= 3; at most what the LDS holds: 3*Q*(chunk+2) doubles).  A unit may span
+ * >= 3; at most what the LDS holds: 6*(chunk+2) doubles, the post-collision
+ * values of the two moving populations).  A unit may span
  * at most 64 workgroups (nx <= 64*chunk).  Needs the GPU (occupancy). */
 int lbrs_batch_query(int nunits, const lbrs_params* units, int chunk, long long* offsets,
                      size_t* scratch_bytes);

@@ -235,7 +235,9 @@ __device__ void run_job(const Batch1DArgs& a, const Job1D job, double* lds, doub
             tn = t + u.dx / lam;
         }
         const double c2lam = 1.0 / (2.0 * lam);
-        // collide the local cells (own and halo) into LDS
+        // collide the local cells (own and halo); the two moving populations
+        // go to LDS (slots 0..2: s = -1, 3..5: s = +1), D1Q3's rest
+        // population stays in its cell's registers
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             int q = tid + k * nt - 1;
@@ -244,7 +246,11 @@ __device__ void run_job(const Batch1DArgs& a, const Job1D job, double* lds, doub
                 moments_1d<Q>(f[k], U);
                 collide_1d<Q>(f[k], U, gm1, c2lam, u.omega, fs);
 #pragma unroll
-                for (int p = 0; p < QK; ++p) lds[p * W + q + 1] = fs[p];
+                for (int c = 0; c < 3; ++c) {
+                    lds[c * W + q + 1] = fs[c];
+                    lds[(3 + c) * W + q + 1] = fs[(Q - 1) * 3 + c];
+                    if (Q == 3) f[k][3 + c] = fs[3 + c];
+                }
             }
         }
         __syncthreads();
@@ -257,13 +263,8 @@ __device__ void run_job(const Batch1DArgs& a, const Job1D job, double* lds, doub
             if (q >= 0 && q < C) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    f[k][0 * 3 + c] = lds[(0 * 3 + c) * W + q + 2];        // s = -1: from q + 1
-                    if (Q == 2) {
-                        f[k][1 * 3 + c] = lds[(1 * 3 + c) * W + q];        // s = +1: from q - 1
-                    } else {
-                        f[k][1 * 3 + c] = lds[(1 * 3 + c) * W + q + 1];    // rest
-                        f[k][2 * 3 + c] = lds[(2 * 3 + c) * W + q];        // s = +1: from q - 1
-                    }
+                    f[k][c] = lds[c * W + q + 2];                          // s = -1: from q + 1
+                    f[k][(Q - 1) * 3 + c] = lds[(3 + c) * W + q];          // s = +1: from q - 1
                 }
                 double U[3], l;
                 moments_1d<Q>(f[k], U);
@@ -301,8 +302,12 @@ __device__ void run_job(const Batch1DArgs& a, const Job1D job, double* lds, doub
     }
 }
 
-template <int Q, int CPT>
-__global__ __launch_bounds__(1024) void batch1d_persistent(Batch1DArgs a) {
+// MAXT: the largest workgroup the instance is launched with.  Four cells per
+// thread need more than the 128 registers a 1024-thread bound leaves (they
+// spilled to scratch memory), so workgroups of up to 512 and of up to 768
+// threads get instances of their own.
+template <int Q, int CPT, int MAXT>
+__global__ __launch_bounds__(MAXT) void batch1d_persistent(Batch1DArgs a) {
     extern __shared__ double lds[];
     // [0,32) wave partials, 62 barrier flag, [64,82) edge cells, then the
     // members' bounds and flags for the two step parities
@@ -378,10 +383,34 @@ hipError_t launch_batch1d_init(const Unit1D* units, Unit1D* units_rw, int nunits
 
 // (the dynamic LDS limit of the instance is raised by batch1d_blocks_per_cu,
 // which the plan calls first, so nothing here is illegal under graph capture)
-template <int Q, int CPT>
+template <int Q, int CPT, int MAXT>
 static hipError_t launch_b1(const Batch1DArgs& a, int grid, int threads, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((batch1d_persistent<Q, CPT>), dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((batch1d_persistent<Q, CPT, MAXT>), dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
+}
+
+// The instance for (Q, cells per thread, workgroup size).
+template <int Q>
+static const void* b1_kernel(int cpt, int threads) {
+    if (cpt <= 1) return (const void*)batch1d_persistent<Q, 1, 1024>;
+    if (cpt <= 2) return (const void*)batch1d_persistent<Q, 2, 1024>;
+    if (cpt <= 4)
+        return threads <= 512 ? (const void*)batch1d_persistent<Q, 4, 512>
+             : threads <= 768 ? (const void*)batch1d_persistent<Q, 4, 768>
+                              : (const void*)batch1d_persistent<Q, 4, 1024>;
+    return nullptr;
+}
+
+template <int Q>
+static hipError_t launch_b1q(const Batch1DArgs& a, int grid, int threads, int cpt, size_t lds,
+                             hipStream_t s) {
+    if (cpt <= 1) return launch_b1<Q, 1, 1024>(a, grid, threads, lds, s);
+    if (cpt <= 2) return launch_b1<Q, 2, 1024>(a, grid, threads, lds, s);
+    if (cpt <= 4)
+        return threads <= 512 ? launch_b1<Q, 4, 512>(a, grid, threads, lds, s)
+             : threads <= 768 ? launch_b1<Q, 4, 768>(a, grid, threads, lds, s)
+                              : launch_b1<Q, 4, 1024>(a, grid, threads, lds, s);
+    return hipErrorInvalidValue;
 }
 
 // chunk = cells per member; threads per workgroup; the local cells (chunk + 2
@@ -389,30 +418,24 @@ static hipError_t launch_b1(const Batch1DArgs& a, int grid, int threads, size_t 
 hipError_t launch_batch1d(const Batch1DArgs& a, int grid, int threads, int chunk, hipStream_t s) {
     const int W = chunk + 2;
     const int cpt = (W + threads - 1) / threads;
-    size_t lds = sizeof(double) * 3 * a.Q * (size_t)W;
-    if (a.Q == 2) {
-        if (cpt <= 1) return launch_b1<2, 1>(a, grid, threads, lds, s);
-        if (cpt <= 2) return launch_b1<2, 2>(a, grid, threads, lds, s);
-        if (cpt <= 4) return launch_b1<2, 4>(a, grid, threads, lds, s);
-    } else {
-        if (cpt <= 1) return launch_b1<3, 1>(a, grid, threads, lds, s);
-        if (cpt <= 2) return launch_b1<3, 2>(a, grid, threads, lds, s);
-        if (cpt <= 4) return launch_b1<3, 4>(a, grid, threads, lds, s);
-    }
-    return hipErrorInvalidValue;
+    size_t lds = batch1d_lds_bytes(chunk);
+    if (threads < 1 || threads > 1024) return hipErrorInvalidValue;
+    return a.Q == 2 ? launch_b1q<2>(a, grid, threads, cpt, lds, s)
+                    : launch_b1q<3>(a, grid, threads, cpt, lds, s);
 }
+
+// Dynamic LDS of one workgroup: the two moving populations' post-collision
+// values (3 components each) of the chunk's cells and its two halo cells.
+size_t batch1d_lds_bytes(int chunk) { return sizeof(double) * 6 * (size_t)(chunk + 2); }
 
 int batch1d_blocks_per_cu(int Q, int threads, int chunk) {
     const int W = chunk + 2;
     const int cpt = (W + threads - 1) / threads;
-    size_t lds = sizeof(double) * 3 * Q * (size_t)W;
+    size_t lds = batch1d_lds_bytes(chunk);
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
-    const void* k = nullptr;
-    if (Q == 2) k = cpt <= 1 ? (const void*)batch1d_persistent<2, 1>
-                             : (cpt <= 2 ? (const void*)batch1d_persistent<2, 2> : (const void*)batch1d_persistent<2, 4>);
-    else k = cpt <= 1 ? (const void*)batch1d_persistent<3, 1>
-                      : (cpt <= 2 ? (const void*)batch1d_persistent<3, 2> : (const void*)batch1d_persistent<3, 4>);
+    const void* k = Q == 2 ? b1_kernel<2>(cpt, threads) : b1_kernel<3>(cpt, threads);
+    if (!k) return 0;
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds);
     return e == hipSuccess ? n : 0;

@@ -152,7 +152,7 @@ void schedule_jobs(const std::vector<double>& work, int grid, Plan& P) {
 int default_threads(int chunk) {
     // chunk + 2 local cells over at most 4 cells per thread
     int w = chunk + 2;
-    for (int t : {256, 512, 1024})
+    for (int t : {256, 512, 768, 1024})
         if (w <= t * 4 && (w + t - 1) / t <= 4 && t >= (w + 3) / 4) return t;
     return 1024;
 }
@@ -161,8 +161,7 @@ int grid_for(int Q, int chunk, int threads) {
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-    size_t lds = sizeof(double) * 3 * Q * (size_t)(chunk + 2);
-    if (lds > prop.sharedMemPerBlock) return 0;
+    if (batch1d_lds_bytes(chunk) > prop.sharedMemPerBlock) return 0;
     int bpc = batch1d_blocks_per_cu(Q, threads, chunk);
     return bpc * prop.multiProcessorCount;
 }

@@ -229,6 +229,7 @@ hipError_t launch_batch1d_init(const Unit1D* units, Unit1D* units_rw, int nunits
 hipError_t launch_zero_counters(unsigned* c, int n, hipStream_t s);
 hipError_t launch_batch1d(const Batch1DArgs& a, int grid, int threads, int chunk, hipStream_t s);
 int batch1d_blocks_per_cu(int Q, int threads, int chunk);
+size_t batch1d_lds_bytes(int chunk);
 
 // One domain of a 2D batch (periodic or other sides, fixed lattice speed).
 // Its cells are [coff, coff + nx*ny) of the moment pools ([K][total]); its

@@ -47,10 +47,11 @@ def _oracle_tube(t, model=wl.D1Q3, omega=None, periodic=False, lam_user=None):
     return oracle.run(P, oracle.prim_to_cons(P, t.W), t_end=t.t_end, record=False)
 
 
-@pytest.mark.parametrize("chunk", [254, 1022])
+@pytest.mark.parametrize("chunk", [254, 1022, 2046, 3070])
 def test_batch_matches_oracle_per_unit(chunk):
     """20 seeded tubes of 100..3000 cells; chunk 254 splits most into teams of up to
-    12 workgroups (one team barrier per step), chunk 1022 into teams of up to 3."""
+    12 workgroups (one team barrier per step), chunk 1022 into teams of up to 3;
+    2046 (512 threads) and 3070 (768 threads) hold four cells per thread."""
     tubes = wl.tube_batch(20, seed=1, nmin=100, nmax=3000)
     B, _ = _batch(tubes, chunk)
     B.run(10**6)
@@ -87,11 +88,12 @@ def test_batch_mixed_models_sides_omega():
     B.close()
 
 
-def test_batch_bitwise_equals_single_domain_runs():
+@pytest.mark.parametrize("chunk", [1022, 3070])
+def test_batch_bitwise_equals_single_domain_runs(chunk):
     """Each unit of the batch equals the same problem run alone through lbrs_init /
     lbrs_step, bit for bit (same arithmetic, exact max reductions)."""
     tubes = wl.tube_batch(6, seed=5, nmin=300, nmax=6000)
-    B, units = _batch(tubes, 1022)
+    B, units = _batch(tubes, chunk)
     B.run(10**6)
     U = B.moments()
     for b, t in enumerate(tubes):
@@ -100,7 +102,7 @@ def test_batch_bitwise_equals_single_domain_runs():
         s = sim.run(t.t_end, chunk=20000)
         Us = sim.moments()[:, 0, :]
         same = torch.equal(Us, U[:, B.unit_slice(b)])
-        report("batch vs single", unit=b, n=t.nx, steps=s["nsteps"], bitwise=same)
+        report("batch vs single", chunk=chunk, unit=b, n=t.nx, steps=s["nsteps"], bitwise=same)
         assert same
         sim.close()
     B.close()
@@ -124,12 +126,14 @@ def test_batch_nonphysical_unit_is_isolated():
     B.close()
 
 
-def test_batch_full_configuration():
+@pytest.mark.parametrize("chunk", [1022, 2046, 3070])
+def test_batch_full_configuration(chunk):
     """1024 tubes, cells log-uniform in [200, 20000] (seed 0), each to its own
-    t_end in [0.1, 0.25]: every unit finishes; the smallest units match the oracle
-    and a sample of large ones matches single-domain runs bit for bit."""
+    t_end in [0.1, 0.25], in the chunk sizes the benchmark tunes over: every unit
+    finishes; the smallest units match the oracle and a sample of large ones
+    matches single-domain runs bit for bit."""
     tubes = wl.tube_batch(1024, seed=0)
-    B, _ = _batch(tubes, 1022)
+    B, _ = _batch(tubes, chunk)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -138,7 +142,7 @@ def test_batch_full_configuration():
     st = B.state()
     ms = e0.elapsed_time(e1)
     lups = sum(st["nsteps"][b] * t.nx for b, t in enumerate(tubes))
-    report("batch full", ms=ms, lups=lups, glups=lups / ms / 1e6, total_cells=B.total,
+    report("batch full", chunk=chunk, ms=ms, lups=lups, glups=lups / ms / 1e6, total_cells=B.total,
            max_steps=max(st["nsteps"]))
     assert st["rc"] == 0
     assert all(st["t"][b] == t.t_end for b, t in enumerate(tubes))
