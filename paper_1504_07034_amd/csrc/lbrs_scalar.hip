@@ -19,7 +19,7 @@
 // register pipeline for the y hops, the next bound reduced from the new u;
 // the waves of a workgroup march adjacent strips of one segment in lockstep;
 // a ring of three row buffers keeps two rows of loads in flight);
-// the 1D kernel stages a 2048-cell tile of post-collision values in LDS.  Side
+// the 1D kernel stages a 1024-cell tile of post-collision values in LDS.  Side
 // conditions: transmissive, periodic and DIRICHLET (ghost cells hold the
 // prescribed u in equilibrium at the step's lattice speed; the y-side decides
 // at a corner).  The time-state and reduction-slot protocol is the Euler
@@ -29,7 +29,7 @@
 
 namespace lbrs {
 
-static constexpr int STILE1D = 2048;
+static constexpr int STILE1D = 1024;
 
 __device__ inline double sflux(const double c[4], int axis, double u) {
     return c[2 * axis] * u + c[2 * axis + 1] * (0.5 * (u * u));
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(64 * WPB) void scalar2d_step(ScalarArgs a) {
 }
 
 // ------------------------------------------------------------------ 1D step
-// A 256-lane workgroup owns STILE1D = 2048 output cells: the post-collision
+// A 256-lane workgroup owns STILE1D = 1024 output cells: the post-collision
 // values of those cells and of one halo cell on each side go to LDS (lane t
 // forms entries t, t + 256, ...), then every output cell pulls its streamed
 // values from its neighbours' entries.

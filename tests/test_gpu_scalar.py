@@ -49,10 +49,11 @@ def compare(w, t_end=math.inf, max_steps=10**9, omega=None, tile=None, lam_mode=
 
 @pytest.mark.parametrize("model", [wl.D1Q2, wl.D1Q3])
 @pytest.mark.parametrize("uL,uR", [(1.0, 0.0), (-0.5, 1.0), (1.2, -0.8)])
-@pytest.mark.parametrize("n", [400, 1000])
+@pytest.mark.parametrize("n", [400, 1000, 2500])
 def test_burgers_1d(model, uL, uR, n):
-    """Shock, rarefaction and a stationary-ish shock, to t = 0.5, on 2 and 4
-    tiles of 254 cells (ragged last tile)."""
+    """Shock, rarefaction and a stationary-ish shock, to t = 0.5, on one
+    1024-cell tile (400, 1000 cells) and on three with a ragged last one
+    (2500 cells)."""
     w = wl.burgers_riemann(n, uL, uR, t_end=0.5, model=model)
     compare(w, t_end=w.t_end, name=f"burgers m{model} ({uL},{uR}) n{n}")
 
