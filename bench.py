@@ -195,8 +195,9 @@ def _time_ms(fn, reps=1):
 def adjoint_2d(n=2048, steps=2000, k=50):
     """Adjoint configuration (2048^2 periodic acoustic pulse, frozen lattice
     speed, 2000 steps, J over [0.7,0.8]^2): time of a plain step, of a step
-    writing the U^n tape, of an adjoint step, and of the whole sqrt(T)
-    checkpointed gradient (forward with checkpoints + recompute + reverse)."""
+    writing the U^n tape, of an adjoint step, of the whole sqrt(T)
+    checkpointed gradient (forward with checkpoints + recompute + reverse),
+    and of the gradient with every step's moments kept when they fit."""
     import torch
 
     from paper_1504_07034_amd import adjoint, lbrs
@@ -233,9 +234,32 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     grad()
     t_grad = _time_ms(grad)
     t_fwd = _time_ms(lambda: run.forward(rho0, keep=False))
+    tile, fuse, seg = run.spec.tile, run.spec.fuse, run.spec.seg
     run.close()
+    del run, r
+    # the same gradient with every step's moments kept (no checkpoints, no
+    # recompute) when the tape fits in device memory
+    run2 = adjoint.GradientRunner(adjoint.GradientSpec(n=n, steps=steps, tile=tile, fuse=fuse,
+                                                       store_all=None), rho0)
+    store_all = {"used": run2.store_all, "tape_GiB": round(steps * 32 * n * n / 2**30, 1)}
+    if run2.store_all:
+        r2 = rho0.clone().requires_grad_(True)
+
+        def grad2():
+            J = adjoint.LBRSFunction.apply(r2, run2)
+            J.backward()
+
+        grad2()
+        t_sa = _time_ms(grad2)
+        store_all.update(gradient_ms=round(t_sa, 1),
+                         gradient_over_forward_run=round(t_sa / t_fwd, 3),
+                         speedup_over_checkpointed=round(t_grad / t_sa, 3))
+        del r2
+    run2.close()
+    del run2
+    torch.cuda.empty_cache()
     cells = n * n
-    return {"n": n, "steps": steps, "segment": run.spec.seg,
+    return {"n": n, "steps": steps, "segment": seg,
             "tile_rows": best["rows"], "waves_per_block": best["wpb"], "alternate": best["alt"],
             "steps_per_launch": best["fuse"],
             # per step: forward, taped recompute and adjoint, in the tuned
@@ -249,7 +273,8 @@ def adjoint_2d(n=2048, steps=2000, k=50):
                        "adjoint_over_forward": round((tap + adj) / fwd1, 3),
                        "adjoint_step_GBs": round(288 * cells / (adj * 1e-3) / 1e9, 1)},
             "gradient_ms": round(t_grad, 1), "forward_run_ms": round(t_fwd, 1),
-            "gradient_over_forward_run": round(t_grad / t_fwd, 3)}
+            "gradient_over_forward_run": round(t_grad / t_fwd, 3),
+            "gradient_store_all": store_all}
 
 
 def batched_2d(k=10, ws=None):

@@ -320,6 +320,23 @@ int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ck
 int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const double* d_ckpt,
                                double* d_tape, double* d_fbar, double* d_work);
 
+/* The same gradient with every step's moments kept instead of checkpoints
+ * (no recompute), for problems whose tape fits in device memory: nsteps
+ * taped steps (as lbrs_step_tape; fused launches when lbrs_set_fusion(c, 2)
+ * is on) from the current state, U^{n0+i} stored at d_tape + i*K*nx*ny
+ * (nsteps*K*nx*ny doubles, caller-allocated).  Periodic D2Q4 Euler without
+ * body or DIRICHLET side, FROZEN_INIT or USER mode (else LBRS_E_STATE).
+ * Asynchronous. */
+int lbrs_forward_taped(lbrs_ctx* c, int nsteps, double* d_tape);
+
+/* Backward sweep over a tape of lbrs_forward_taped (same nsteps and d_tape):
+ * on entry d_fbar holds dJ/df^{n0+nsteps}, on return dJ/df^{n0}; d_work is
+ * one population-sized buffer (not d_fbar).  The context's state is not
+ * used or changed.  Same modes and errors as lbrs_forward_taped.
+ * Asynchronous. */
+int lbrs_backward_taped(lbrs_ctx* c, int nsteps, const double* d_tape, double* d_fbar,
+                        double* d_work);
+
 /* Change the stream later calls enqueue on. */
 int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);
 

@@ -14,6 +14,11 @@ backward -- lbrs_backward_checkpointed (per segment: recompute with a U^n
             tape, then reverse adjoint steps), lbrs_adjoint_init and
             lbrs_isentropic_to_cons_adjoint.
 Memory: ceil(T/segment) population sets plus `segment` moment sets.
+
+With `store_all` the forward sweep keeps every step's moments instead
+(lbrs_forward_taped: T moment sets, 32 B per cell and step -- 250 GiB for
+2048^2 cells and 2000 steps, which the device's HBM holds) and the backward
+sweep runs straight through that tape (lbrs_backward_taped): no recompute.
 """
 from __future__ import annotations
 
@@ -49,6 +54,7 @@ class GradientSpec:
     lam: float | None = None    # frozen lattice speed; set by prepare()
     tile: tuple | None = None   # (rows_per_tile, waves_per_block, alternate) of the step kernel
     fuse: int = 1               # steps per launch of the plain forward steps (1, or 2 fused)
+    store_all: bool | None = False  # keep every step's moments (None: if they fit)
 
     def params(self, mode, lam_user=0.0):
         return lbrs.make_params(lbrs.LBRS_D2Q4, self.n, self.n, (0.0, 1.0, 0.0, 1.0), self.gamma,
@@ -82,10 +88,30 @@ class GradientRunner:
         if spec.tile is not None:
             self.sim.set_tile(*spec.tile)
         self.sim.set_fusion(spec.fuse)
-        nck = math.ceil(spec.steps / spec.seg)
         fcount = 16 * n * n
-        self.ckpt = torch.empty(nck * fcount, dtype=torch.float64, device=dev)
-        self.tape = torch.empty(spec.seg * 4 * n * n, dtype=torch.float64, device=dev)
+        tape_all = spec.steps * 4 * n * n
+        if spec.store_all is None:
+            # every step's moments if they fit in 90% of the free memory,
+            # leaving room for the buffers below
+            torch.cuda.empty_cache()
+            free, _ = torch.cuda.mem_get_info(dev)
+            self.store_all = 8 * (tape_all + 4 * fcount) <= 0.9 * free
+        else:
+            self.store_all = bool(spec.store_all)
+        self.tape = None
+        if self.store_all:
+            self.ckpt = None
+            try:
+                self.tape = torch.empty(tape_all, dtype=torch.float64, device=dev)
+            except torch.cuda.OutOfMemoryError:
+                if spec.store_all:
+                    raise
+                self.store_all = False  # automatic choice: fall back to checkpoints
+                torch.cuda.empty_cache()
+        if not self.store_all:
+            nck = math.ceil(spec.steps / spec.seg)
+            self.ckpt = torch.empty(nck * fcount, dtype=torch.float64, device=dev)
+            self.tape = torch.empty(spec.seg * 4 * n * n, dtype=torch.float64, device=dev)
         self.fbar = torch.empty(fcount, dtype=torch.float64, device=dev)
         self.work = torch.empty(fcount, dtype=torch.float64, device=dev)
         self.U0 = torch.empty((4, n, n), dtype=torch.float64, device=dev)
@@ -96,7 +122,9 @@ class GradientRunner:
         s, sim = self.spec, self.sim
         lbrs.lbrs_isentropic_to_cons(sim.p, rho0.contiguous(), self.U0)
         sim.init(self.U0)
-        if keep:
+        if keep and self.store_all:
+            lbrs.lbrs_forward_taped(sim.ctx, s.steps, self.tape)
+        elif keep:
             lbrs.lbrs_forward_checkpointed(sim.ctx, s.steps, s.seg, self.ckpt)
         else:
             sim.step(s.steps)
@@ -106,8 +134,11 @@ class GradientRunner:
 
     def backward(self, rho0: torch.Tensor) -> torch.Tensor:
         s, sim = self.spec, self.sim
-        lbrs.lbrs_backward_checkpointed(sim.ctx, s.steps, s.seg, self.ckpt, self.tape, self.fbar,
-                                        self.work)
+        if self.store_all:
+            lbrs.lbrs_backward_taped(sim.ctx, s.steps, self.tape, self.fbar, self.work)
+        else:
+            lbrs.lbrs_backward_checkpointed(sim.ctx, s.steps, s.seg, self.ckpt, self.tape,
+                                            self.fbar, self.work)
         Ubar0 = torch.empty_like(self.U0)
         lbrs.lbrs_adjoint_init(sim.ctx, self.fbar, self.U0, Ubar0)
         rbar = torch.empty_like(rho0)
@@ -127,6 +158,7 @@ class GradientRunner:
 
     def close(self):
         self.sim.close()
+        self.ckpt = self.tape = self.fbar = self.work = None
 
 
 class LBRSFunction(torch.autograd.Function):

@@ -836,6 +836,31 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
     return LBRS_OK;
 }
 
+// Reverse adjoint steps over tape slots len-1 .. 0 (slot i = U^{n0+i}), from
+// fbar in cur; cur and nxt swap after every launch, so cur ends holding
+// fbar^{n0}.  Fused contexts take two steps per launch (tapes i and i-1).
+static int reverse_sweep(lbrs_ctx* c, int len, const double* d_tape, double*& cur, double*& nxt) {
+    const long long ucount = (long long)c->K * c->plane;
+    int i = len - 1;
+    if (c->fuse == 2) {
+        for (; i >= 1; i -= 2) {
+            int rc = adjoint_pair(c, d_tape + i * ucount, d_tape + (i - 1) * ucount, cur, nxt);
+            if (rc) return rc;
+            double* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    }
+    for (; i >= 0; --i) {
+        int rc = lbrs_adjoint_step(c, d_tape + i * ucount, cur, nxt);
+        if (rc) return rc;
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    return LBRS_OK;
+}
+
 int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const double* d_ckpt,
                                double* d_tape, double* d_fbar, double* d_work) {
     if (!c || !d_ckpt || !d_tape || !d_fbar || !d_work || d_fbar == d_work || nsteps < 1 ||
@@ -872,25 +897,49 @@ int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const doubl
                 if (rc) return rc;
             }
         }
-        int i = len - 1;
-        if (c->fuse == 2) {  // two adjoint steps per launch: tapes i (U^{n+1}) and i-1 (U^n)
-            for (; i >= 1; i -= 2) {
-                rc = adjoint_pair(c, d_tape + i * ucount, d_tape + (i - 1) * ucount, cur, nxt);
-                if (rc) return rc;
-                double* t = cur;
-                cur = nxt;
-                nxt = t;
-            }
-        }
-        for (; i >= 0; --i) {
-            rc = lbrs_adjoint_step(c, d_tape + i * ucount, cur, nxt);
-            if (rc) return rc;
-            double* t = cur;
-            cur = nxt;
-            nxt = t;
-        }
+        rc = reverse_sweep(c, len, d_tape, cur, nxt);
+        if (rc) return rc;
     }
     if (cur != d_fbar) {
+        if (hipMemcpyAsync(d_fbar, cur, sizeof(double) * fcount, hipMemcpyDeviceToDevice, c->stream) !=
+            hipSuccess)
+            return LBRS_E_HIP;
+    }
+    return LBRS_OK;
+}
+
+// The adjoint (fixed-speed, periodic 2D Euler) preconditions of the gradient
+// sweeps.
+static int gradient_state_ok(const lbrs_ctx* c) {
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return 0;
+    if (c->P.law != LBRS_LAW_EULER || c->codes || c->dir) return 0;
+    for (int s = 0; s < 4; ++s)
+        if (c->P.bc[s] != LBRS_BC_PERIODIC) return 0;
+    return 1;
+}
+
+int lbrs_forward_taped(lbrs_ctx* c, int nsteps, double* d_tape) {
+    if (!c || !d_tape || nsteps < 1) return LBRS_E_INVAL;
+    if (!gradient_state_ok(c)) return LBRS_E_STATE;
+    if (c->fuse == 2) return step_tape_fused(c, nsteps, d_tape);
+    const long long ucount = (long long)c->K * c->plane;
+    for (int i = 0; i < nsteps; ++i) {
+        int rc = lbrs_step_tape(c, d_tape + i * ucount);
+        if (rc) return rc;
+    }
+    return LBRS_OK;
+}
+
+int lbrs_backward_taped(lbrs_ctx* c, int nsteps, const double* d_tape, double* d_fbar,
+                        double* d_work) {
+    if (!c || !d_tape || !d_fbar || !d_work || d_fbar == d_work || nsteps < 1) return LBRS_E_INVAL;
+    if (!gradient_state_ok(c)) return LBRS_E_STATE;
+    double* cur = d_fbar;
+    double* nxt = d_work;
+    int rc = reverse_sweep(c, nsteps, d_tape, cur, nxt);
+    if (rc) return rc;
+    if (cur != d_fbar) {
+        const long long fcount = (long long)c->Q * c->K * c->plane;
         if (hipMemcpyAsync(d_fbar, cur, sizeof(double) * fcount, hipMemcpyDeviceToDevice, c->stream) !=
             hipSuccess)
             return LBRS_E_HIP;

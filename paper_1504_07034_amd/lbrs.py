@@ -39,7 +39,7 @@ EXPORTS = (
     "lbrs_batch2d_moments", "lbrs_batch2d_get_f", "lbrs_batch2d_set_f", "lbrs_batch2d_gradient",
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
     "lbrs_destroy", "lbrs_set_fusion", "lbrs_batch2d_set_fusion", "lbrs_adjoint_step2",
-    "lbrs_step_tape2",
+    "lbrs_step_tape2", "lbrs_forward_taped", "lbrs_backward_taped",
 )
 
 
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_batch2d_set_fusion": (i, [vp, i]),
         "lbrs_adjoint_step2": (i, [vp, vp, vp, vp, vp]),
         "lbrs_step_tape2": (i, [vp, vp, vp]),
+        "lbrs_forward_taped": (i, [vp, i, vp]),
+        "lbrs_backward_taped": (i, [vp, i, vp, vp, vp]),
         "lbrs_batch_query": (i, [i, P, i, ctypes.POINTER(ll), szp]),
         "lbrs_batch_init": (i, [ctypes.POINTER(vp), i, P, dp, i, vp, vp, vp, vp]),
         "lbrs_batch_run": (i, [vp, i]),
@@ -247,6 +249,15 @@ def lbrs_backward_checkpointed(ctx, nsteps: int, segment: int, ckpt, tape, fbar,
     _check(load_library().lbrs_backward_checkpointed(ctx, int(nsteps), int(segment), _dptr(ckpt),
                                                      _dptr(tape), _dptr(fbar), _dptr(work)),
            "lbrs_backward_checkpointed")
+
+
+def lbrs_forward_taped(ctx, nsteps: int, tape):
+    _check(load_library().lbrs_forward_taped(ctx, int(nsteps), _dptr(tape)), "lbrs_forward_taped")
+
+
+def lbrs_backward_taped(ctx, nsteps: int, tape, fbar, work):
+    _check(load_library().lbrs_backward_taped(ctx, int(nsteps), _dptr(tape), _dptr(fbar),
+                                              _dptr(work)), "lbrs_backward_taped")
 
 
 def lbrs_init(p: lbrs_params, U0, f0, f1, scratch, stream=None):

@@ -123,17 +123,20 @@ def _oracle_dJ(n, steps, rho0, d, window):
     return float(np.sum(U[0][m] ** 2)), float(np.sum(2.0 * U[0][m] * dU[0][m]))
 
 
-@pytest.mark.parametrize("fuse,segment", [(1, 8), (2, 8), (2, 7)])
+@pytest.mark.parametrize("fuse,segment,store_all", [(1, 8, False), (2, 8, False), (2, 7, False),
+                                                    (1, None, True), (2, None, True)])
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_gradient_matches_oracle_dual_numbers(layout, fuse, segment):
-    """Checkpointed gradient (48^2, 60 steps) against the oracle's exact
-    directional derivatives along three smooth directions; single launches, or
-    fused forward, recompute and adjoint steps (two per launch; an odd segment
-    leaves one single step of each)."""
+def test_gradient_matches_oracle_dual_numbers(layout, fuse, segment, store_all):
+    """Gradient (48^2, 60 steps) against the oracle's exact directional
+    derivatives along three smooth directions: checkpointed, in single launches
+    or with fused forward, recompute and adjoint steps (two per launch; an odd
+    segment leaves one single step of each), and with every step's moments
+    kept (no checkpoints, no recompute)."""
     n, steps = 48, 60
     w = wl.acoustic_pulse(n, steps=steps)
     rho0 = torch.from_numpy(w.W[0].copy()).cuda()
-    spec = adjoint.GradientSpec(n=n, steps=steps, layout=layout, segment=segment, fuse=fuse)
+    spec = adjoint.GradientSpec(n=n, steps=steps, layout=layout, segment=segment, fuse=fuse,
+                                store_all=store_all)
     run = adjoint.GradientRunner(spec, rho0)
     r = rho0.clone().requires_grad_(True)
     J = adjoint.LBRSFunction.apply(r, run)
@@ -143,8 +146,8 @@ def test_gradient_matches_oracle_dual_numbers(layout, fuse, segment):
         d = wl.bump_direction(n, seed=200 + k)
         J_o, dJ_o = _oracle_dJ(n, steps, w.W[0], d, (0.7, 0.8))
         dJ_g = float(np.sum(grad * d))
-        report("grad vs dual", k=k, layout=layout, fuse=fuse, J=J.item(), J_oracle=J_o, gpu=dJ_g,
-               oracle=dJ_o)
+        report("grad vs dual", k=k, layout=layout, fuse=fuse, store_all=store_all, J=J.item(),
+               J_oracle=J_o, gpu=dJ_g, oracle=dJ_o)
         assert abs(J.item() - J_o) <= 1e-12 * abs(J_o)
         assert abs(dJ_g - dJ_o) <= 1e-9 * abs(dJ_o)
     run.close()
@@ -246,3 +249,41 @@ def test_step_tape2_equals_two_taped_steps(layout, n):
     report("step_tape2", n=n, layout=layout, max_abs=d,
            bitwise=bool(torch.equal(a0, b0) and torch.equal(a1, b1) and torch.equal(fa, fb)))
     assert d <= 1e-12
+
+
+def _gradient(spec, rho0):
+    run = adjoint.GradientRunner(spec, rho0)
+    r = rho0.clone().requires_grad_(True)
+    J = adjoint.LBRSFunction.apply(r, run)
+    J.backward()
+    used = run.store_all
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    return J.item(), r.grad.cpu(), used
+
+
+@pytest.mark.parametrize("n,steps", [(70, 37), (2048, 2000)])
+def test_store_all_equals_checkpointed(n, steps):
+    """Every step's moments kept (lbrs_forward_taped / lbrs_backward_taped)
+    against sqrt(T) checkpoints, fused launches, at a ragged size with an odd
+    step count and at full size (2048^2, 2000 steps: a 250 GiB tape): the
+    same J and the same gradient (fixed speed: the taped steps are the same
+    bits either way)."""
+    w = wl.acoustic_pulse(n, steps=steps)
+    rho0 = torch.from_numpy(w.W[0].copy()).cuda()
+    Jc, gc, used_c = _gradient(adjoint.GradientSpec(n=n, steps=steps, fuse=2), rho0)
+    # the full-size tape is taken only if the device holds it (automatic choice)
+    store_all = True if n < 1024 else None
+    Js, gs, used_s = _gradient(adjoint.GradientSpec(n=n, steps=steps, fuse=2, store_all=store_all),
+                               rho0)
+    assert not used_c
+    if not used_s:
+        free, total = torch.cuda.mem_get_info()
+        pytest.skip(f"a {steps * 32 * n * n / 2**30:.0f} GiB tape does not fit "
+                    f"({free / 2**30:.0f} of {total / 2**30:.0f} GiB free)")
+    diff = float((gs - gc).abs().max() / gc.abs().max())
+    report("store all vs checkpointed", n=n, steps=steps, J=Js, J_ckpt=Jc, rel=diff,
+           bitwise=bool(torch.equal(gs, gc)))
+    assert abs(Js - Jc) <= 1e-13 * abs(Jc)
+    assert diff <= 1e-12
