@@ -236,7 +236,8 @@ def adjoint_2d(n=2048, steps=2000, k=50):
     t_fwd = _time_ms(lambda: run.forward(rho0, keep=False))
     tile, fuse, seg = run.spec.tile, run.spec.fuse, run.spec.seg
     run.close()
-    del run, r
+    del run, r, sim, tape, tape1, g
+    torch.cuda.empty_cache()
     # the same gradient with every step's moments kept (no checkpoints, no
     # recompute) when the tape fits in device memory
     run2 = adjoint.GradientRunner(adjoint.GradientSpec(n=n, steps=steps, tile=tile, fuse=fuse,
@@ -884,8 +885,9 @@ def main():
         copy_ref["frac_of_copy"] = round(achieved / copy_ref["GBs"], 4)
         rec["copy_reference"] = copy_ref
     sim.close()
-    del U0
+    del U0, sim
     torch.cuda.empty_cache()
+
     def stage(name, fn):
         rec[name] = fn()
         torch.cuda.empty_cache()

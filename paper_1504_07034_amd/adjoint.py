@@ -91,11 +91,11 @@ class GradientRunner:
         fcount = 16 * n * n
         tape_all = spec.steps * 4 * n * n
         if spec.store_all is None:
-            # every step's moments if they fit in 90% of the free memory,
-            # leaving room for the buffers below
+            # every step's moments if they fit beside the buffers below with
+            # 2 GiB to spare
             torch.cuda.empty_cache()
             free, _ = torch.cuda.mem_get_info(dev)
-            self.store_all = 8 * (tape_all + 4 * fcount) <= 0.9 * free
+            self.store_all = 8 * (tape_all + 4 * fcount) + (2 << 30) <= free
         else:
             self.store_all = bool(spec.store_all)
         self.tape = None
