@@ -361,7 +361,9 @@ def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None, fuse=2):
             out.append(U.reshape(4, -1))
         return torch.cat(out, dim=1).contiguous()
 
-    def run_wave(sel, replays=0):
+    def run_wave(sel, replays=0, seg=seg, nck=nck, bufs=None):
+        # nck = 0: one segment, every step's moments taped (no checkpoints);
+        # bufs: flat buffers reused across waves (else allocated here)
         doms = doms_of(sel)
         B = lbrs.Batch2D(doms)
         U0 = U0_of(sel, doms)
@@ -369,12 +371,14 @@ def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None, fuse=2):
         B.set_fusion(fuse)
         B.set_window(0.7, 0.8)
         T = B.total
-        ck = torch.empty(nck * 16 * T, dtype=torch.float64, device="cuda")
-        tp = torch.empty(seg * 4 * T, dtype=torch.float64, device="cuda")
-        fb = torch.empty(16 * T, dtype=torch.float64, device="cuda")
-        wk = torch.empty_like(fb)
+        if bufs is None:
+            bufs = alloc(T, seg, nck)
+        ck = bufs["ck"][:max(1, nck * 16 * T)]
+        tp = bufs["tp"][:seg * 4 * T]
+        fb = bufs["fb"][:16 * T]
+        wk = bufs["wk"][:16 * T]
+        Ub = bufs["Ub"][:4 * T].view(4, T)
         J = torch.zeros(len(sel), dtype=torch.float64, device="cuda")
-        Ub = torch.empty((4, T), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -392,29 +396,49 @@ def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None, fuse=2):
             replay_ms = _time_ms(lambda: B.gradient(U0, steps, seg, ck, tp, fb, wk, J, Ub,
                                                     use_graph=True), replays)
         B.close()
-        del B, ck, tp, fb, wk, Ub, U0
-        torch.cuda.empty_cache()
+        del B, ck, tp, fb, wk, Ub, U0, bufs
         return ms, T, Jh, host_ms, replay_ms
 
-    free = torch.cuda.mem_get_info()[0]
-    cap = int(mem_frac * free / per_cell)
-    order = sorted(range(len(ws)), key=lambda b: -ws[b].nx * ws[b].ny)
-    waves, cur, cells = [], [], 0
-    for b in order:  # first fit into the current wave, largest domains first
-        c = ws[b].nx * ws[b].ny
-        if cur and cells + c > cap:
-            waves.append(cur)
-            cur, cells = [], 0
-        cur.append(b)
-        cells += c
-    waves.append(cur)
-    total_ms, total_cells, wave_info = 0.0, 0, []
-    for wv in waves:
-        ms, T, _, host_ms, _ = run_wave([ws[b] for b in wv])
-        total_ms += ms
-        total_cells += T
-        wave_info.append({"domains": len(wv), "cells": int(T), "ms": round(ms, 1),
-                          "capture_ms": round(host_ms, 1)})
+    def alloc(cells, seg, nck):
+        def z(k):
+            return torch.empty(max(1, k), dtype=torch.float64, device="cuda")
+        return {"ck": z(nck * 16 * cells), "tp": z(seg * 4 * cells), "fb": z(16 * cells),
+                "wk": z(16 * cells), "Ub": z(4 * cells)}
+
+    def run_all(per_cell, name, seg=seg, nck=nck):
+        torch.cuda.empty_cache()
+        free = torch.cuda.mem_get_info()[0]
+        cap = int(mem_frac * free / per_cell)
+        order = sorted(range(len(ws)), key=lambda b: -ws[b].nx * ws[b].ny)
+        waves, cur, cells = [], [], 0
+        for b in order:  # first fit into the current wave, largest domains first
+            c = ws[b].nx * ws[b].ny
+            if cur and cells + c > cap:
+                waves.append(cur)
+                cur, cells = [], 0
+            cur.append(b)
+            cells += c
+        waves.append(cur)
+        # one set of buffers for the largest wave, reused by every wave
+        bufs = alloc(max(sum(ws[b].nx * ws[b].ny for b in wv) for wv in waves), seg, nck)
+        total_ms, total_cells, wave_info = 0.0, 0, []
+        for i, wv in enumerate(waves):
+            ms, T, _, host_ms, _ = run_wave([ws[b] for b in wv], seg=seg, nck=nck, bufs=bufs)
+            total_ms += ms
+            total_cells += T
+            wave_info.append({"domains": len(wv), "cells": int(T), "ms": round(ms, 1),
+                              "capture_ms": round(host_ms, 1)})
+            print(f"bench: batched_grad_2d {name} wave {i + 1}/{len(waves)}: {ms:.0f} ms",
+                  file=sys.stderr, flush=True)
+        del bufs
+        torch.cuda.empty_cache()
+        return total_ms, total_cells, wave_info
+
+    total_ms, total_cells, wave_info = run_all(per_cell, "checkpointed")
+    # the same gradients with one segment: every step's moments taped in the
+    # forward sweep, no checkpoints, no recompute (more, smaller waves)
+    per_cell_w = 8 * (16 * 4 + 4 * (steps + 2))
+    ms_w, _, info_w = run_all(per_cell_w, "whole tape", seg=steps, nck=0)
 
     rng = np.random.default_rng(2)
     sub = [ws[b] for b in sorted(rng.choice(len(ws), size=subset, replace=False))]
@@ -453,6 +477,9 @@ def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None, fuse=2):
     return {"domains": len(ws), "cells": int(total_cells), "steps": steps, "segment": seg,
             "forward_steps_per_launch": fuse, "waves": wave_info, "ms": round(total_ms, 1),
             "forward_equiv_MLUPS": round(lups / total_ms / 1e3, 1),
+            "whole_tape": {"ms": round(ms_w, 1), "waves": len(info_w),
+                           "bytes_per_cell": per_cell_w,
+                           "speedup_over_checkpointed": round(total_ms / ms_w, 3)},
             "subset": {"domains": subset, "cells": int(T_b),
                        "batched_first_call_ms": round(ms_first, 1),
                        "batched_replay_ms": round(ms_b, 1),

@@ -499,8 +499,10 @@ int lbrs_batch2d_set_f(lbrs_batch2d* b, const double* d_f, long long n);
  * pools), adjoint of the initialisation into d_Ubar0 [4][total].  With
  * use_graph != 0 the whole sequence is captured in a hipGraph on the first
  * call and replayed by later calls with the same arguments (a call with other
- * pointers, nsteps or segment captures a new graph).  No host
- * synchronisation. */
+ * pointers, nsteps or segment captures a new graph).  With segment >= nsteps
+ * the forward sweep itself writes every step's moments to d_tape (nsteps sets)
+ * and the adjoint runs straight back through them: no checkpoint (d_ckpt is
+ * not used) and no recompute.  No host synchronisation. */
 int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int segment,
                           double* d_ckpt, double* d_tape, double* d_fbar, double* d_work,
                           double* d_J, double* d_Ubar0, int use_graph);

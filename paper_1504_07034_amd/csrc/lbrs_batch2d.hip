@@ -542,20 +542,12 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
     int rc = lbrs_batch2d_reset(b, d_U0);
     if (rc) return rc;
     const long long fcount = 16 * b->total, ucount = 4 * b->total;
-    const int nck = (nsteps + segment - 1) / segment;
-    for (int j = 0; j < nck; ++j) {
-        if ((rc = lbrs_batch2d_get_f(b, d_ckpt + j * fcount))) return rc;
-        int len = std::min(segment, nsteps - j * segment);
-        if ((rc = lbrs_batch2d_step(b, len))) return rc;
-    }
-    if ((rc = lbrs_batch2d_window_objective(b, d_J, d_fbar))) return rc;
     double* cur = d_fbar;
     double* nxt = d_work;
-    for (int j = nck - 1; j >= 0; --j) {
-        if ((rc = lbrs_batch2d_set_f(b, d_ckpt + j * fcount, (long long)j * segment))) return rc;
-        int len = std::min(segment, nsteps - j * segment);
+    // len steps from the current state, U^{n+i} to tape slot i
+    auto taped_steps = [&](int len) -> int {
         int i = 0;
-        if (b->fuse == 2) {  // recompute two steps per launch, both inputs taped
+        if (b->fuse == 2) {  // two steps per launch, both inputs taped
             for (; i + 1 < len; i += 2) {
                 Batch2DArgs a = b2_args(b, d_tape + i * ucount);
                 a.tape2 = d_tape + (i + 1) * ucount;
@@ -565,21 +557,51 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
                 b->nsteps += 2;
             }
         }
-        for (; i < len; ++i)
-            if ((rc = lbrs_batch2d_step_tape(b, d_tape + i * ucount))) return rc;
-        i = len - 1;
+        for (; i < len; ++i) {
+            int r = lbrs_batch2d_step_tape(b, d_tape + i * ucount);
+            if (r) return r;
+        }
+        return LBRS_OK;
+    };
+    // adjoint steps back through tape slots len-1 .. 0 (cur and nxt swap)
+    auto reverse_steps = [&](int len) -> int {
+        int i = len - 1;
         if (b->fuse == 2) {  // two adjoint steps per launch: tapes i (U^{n+1}) and i-1 (U^n)
             for (; i >= 1; i -= 2) {
-                if ((rc = b2_adjoint_pair_step(b, d_tape + i * ucount, d_tape + (i - 1) * ucount,
-                                               cur, nxt)))
-                    return rc;
+                int r = b2_adjoint_pair_step(b, d_tape + i * ucount, d_tape + (i - 1) * ucount,
+                                             cur, nxt);
+                if (r) return r;
                 std::swap(cur, nxt);
             }
         }
         for (; i >= 0; --i) {
-            if ((rc = lbrs_batch2d_adjoint_step(b, d_tape + i * ucount, cur, nxt))) return rc;
+            int r = lbrs_batch2d_adjoint_step(b, d_tape + i * ucount, cur, nxt);
+            if (r) return r;
             std::swap(cur, nxt);
         }
+        return LBRS_OK;
+    };
+    if (segment >= nsteps) {
+        // one segment: the forward sweep itself writes the tape of every
+        // step, then the adjoint runs straight back (no checkpoint, no
+        // recompute; d_ckpt is not used)
+        if ((rc = taped_steps(nsteps))) return rc;
+        if ((rc = lbrs_batch2d_window_objective(b, d_J, d_fbar))) return rc;
+        if ((rc = reverse_steps(nsteps))) return rc;
+        return lbrs_batch2d_adjoint_init(b, cur, d_U0, d_Ubar0);
+    }
+    const int nck = (nsteps + segment - 1) / segment;
+    for (int j = 0; j < nck; ++j) {
+        if ((rc = lbrs_batch2d_get_f(b, d_ckpt + j * fcount))) return rc;
+        int len = std::min(segment, nsteps - j * segment);
+        if ((rc = lbrs_batch2d_step(b, len))) return rc;
+    }
+    if ((rc = lbrs_batch2d_window_objective(b, d_J, d_fbar))) return rc;
+    for (int j = nck - 1; j >= 0; --j) {
+        if ((rc = lbrs_batch2d_set_f(b, d_ckpt + j * fcount, (long long)j * segment))) return rc;
+        int len = std::min(segment, nsteps - j * segment);
+        if ((rc = taped_steps(len))) return rc;
+        if ((rc = reverse_steps(len))) return rc;
     }
     return lbrs_batch2d_adjoint_init(b, cur, d_U0, d_Ubar0);
 }

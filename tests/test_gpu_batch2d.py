@@ -336,3 +336,42 @@ def test_batch2d_gradient_fused_forward():
     assert torch.allclose(J1, J2, rtol=1e-13, atol=0)
     assert float((U1 - U2).abs().max()) <= 1e-11 * scale
     B.close()
+
+
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_batch2d_gradient_whole_tape(fuse):
+    """segment >= nsteps: one forward sweep writes every step's moments and the
+    adjoint runs straight back (no checkpoint, no recompute).  J and dJ/dU0
+    equal the checkpointed gradient's (segments of 7, odd step count), eager
+    and graph-replayed."""
+    ws = [wl.fourier_modes(n, seed=50 + i) for i, n in enumerate([24, 40, 32])]
+    steps = 31
+    doms = _doms(ws)
+    B = lbrs.Batch2D(doms)
+    U0 = _pool_U0(ws, doms)
+    B.init(U0)
+    B.set_window(0.7, 0.8)
+    B.set_fusion(fuse)
+    T = B.total
+    ck = torch.empty(math.ceil(steps / 7) * 16 * T, dtype=torch.float64, device="cuda")
+    tp = torch.empty(steps * 4 * T, dtype=torch.float64, device="cuda")
+    fb = torch.empty(16 * T, dtype=torch.float64, device="cuda")
+    wk = torch.empty_like(fb)
+    J = torch.zeros(len(ws), dtype=torch.float64, device="cuda")
+    Ub = torch.empty((4, T), dtype=torch.float64, device="cuda")
+    B.gradient(U0, steps, 7, ck, tp, fb, wk, J, Ub, use_graph=False)
+    Jc, Uc = J.clone(), Ub.clone()
+    ck.fill_(float("nan"))  # not read by the whole-tape sweep
+    for use_graph in (False, True, True):
+        J.zero_()
+        Ub.zero_()
+        B.gradient(U0, steps, steps, ck, tp, fb, wk, J, Ub, use_graph=use_graph)
+        torch.cuda.synchronize()
+        scale = float(Uc.abs().max())
+        rel = float((Ub - Uc).abs().max()) / scale
+        report("batch2d gradient whole tape", fuse=fuse, graph=use_graph, rel=rel,
+               bitwise=bool(torch.equal(Ub, Uc)))
+        assert torch.allclose(J, Jc, rtol=1e-13, atol=0)
+        assert rel <= 1e-12
+    assert B.state()["rc"] == 0
+    B.close()
