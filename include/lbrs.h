@@ -126,7 +126,7 @@ typedef struct {
     double x0, x1, y0, y1;/* domain; y0, y1 ignored in 1D */
     double gamma;         /* ratio of specific heats, > 1 (Euler) */
     double omega;         /* relaxation parameter omega = dt/epsilon, in (0, 2) (Sec. II.B) */
-    double cfl;           /* in (0, 1]: lattice speed = (lambda star) / cfl */
+    double cfl;           /* in (0, lbrs_cfl_max(model)]: lattice speed = (lambda star) / cfl */
     int bc[4];            /* side conditions, x-low, x-high, y-low, y-high */
     int lambda_mode;      /* LBRS_LAMBDA_* */
     double lambda_user;   /* lattice speed for LBRS_LAMBDA_USER, > 0 */
@@ -171,6 +171,16 @@ typedef struct {
  * Any output pointer may be NULL.  Returns LBRS_E_INVAL for invalid params. */
 int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes,
                      size_t* scratch_bytes);
+
+/* Largest admissible cfl of a model: 1 for D1Q2 and D2Q4, 2/3 for D1Q3.  With
+ * the lattice speed (lambda star)/cfl the equilibria are monotone in U (Bouchut's
+ * condition, Sec. II.D) when every eigenvalue of df_i^eq/dU is >= 0: for the
+ * Sec. II.C D1Q3 equilibria U/3 -+ G/(2 lambda) that needs lambda >= 1.5
+ * max |u -+ a|, for D1Q2 lambda >= max |u -+ a|, for D2Q4 lambda >= the
+ * Sec. II.D bound.  lbrs_init, lbrs_query_sizes and the batch calls reject a
+ * larger cfl (LBRS_E_INVAL) in the PER_STEP and FROZEN_INIT modes.  Returns
+ * -1 for an unknown model.  Host only, no GPU needed. */
+double lbrs_cfl_max(int model);
 
 /* Node codes of p->solid, computed on the host (no GPU needed), as lbrs_init
  * stores them for the step kernel: h_codes receives nx*ny uint16 values,

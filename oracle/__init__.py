@@ -25,7 +25,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbrs_oracle.cpp")
-LIB = os.path.join(HERE, "liblbrs_oracle.so")
+LIB_SERIAL = os.path.join(HERE, "liblbrs_oracle.so")
+LIB_OMP = os.path.join(HERE, "liblbrs_oracle_omp.so")
+LIB = LIB_SERIAL
 
 D1Q2, D1Q3, D2Q4 = 0, 1, 2
 FLUX_EULER, FLUX_LINEAR, FLUX_QUADRATIC = 0, 1, 2
@@ -36,15 +38,38 @@ OK, INVAL, NONPHYSICAL = 0, -1, -4
 NQ = {D1Q2: 2, D1Q3: 3, D2Q4: 4}
 
 
+# The serial build the tests use, and the timing build (same source, OpenMP
+# over cells, -O3 -march=native); neither contracts multiply-adds.
+_FLAGS = {
+    LIB_SERIAL: ["-O2"],
+    LIB_OMP: ["-O3", "-march=native", "-fopenmp"],
+}
+
+
+def _compile(lib: str, force: bool) -> str:
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+        tmp = lib + ".tmp"
+        subprocess.check_call(["g++", *_FLAGS[lib], "-std=c++17", "-fPIC", "-shared",
+                               "-ffp-contract=off", SRC, "-o", tmp])
+        os.replace(tmp, lib)
+    return lib
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (plain -O2, no FMA contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(
-            ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-             SRC, "-o", tmp])
-        os.replace(tmp, LIB)
-    return LIB
+    """Compile both builds of the oracle with g++; returns the serial one."""
+    _compile(LIB_OMP, force)
+    return _compile(LIB_SERIAL, force)
+
+
+def use(variant: str = "serial", threads: int | None = None) -> int:
+    """Select the build later calls load: "serial" (the default) or "omp"
+    (OpenMP over cells; `threads` sets the thread count).  Returns the
+    number of threads the selected build runs its cell loops with."""
+    global LIB, _lib
+    lib = LIB_OMP if variant == "omp" else LIB_SERIAL
+    if lib != LIB:
+        LIB, _lib = lib, None
+    return _load().orc_threads(int(threads or 0))
 
 
 class _Problem(ctypes.Structure):
@@ -69,8 +94,8 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
+        if LIB in _FLAGS:
+            _compile(LIB, force=False)
         lib = ctypes.CDLL(LIB)
         P = ctypes.POINTER(_Problem)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -94,6 +119,8 @@ def _load():
         lib.orc_run_tangent.restype = ctypes.c_int
         lib.orc_init_tangent.argtypes = [P, dp, dp, ctypes.c_double, dp, dp]
         lib.orc_init_tangent.restype = ctypes.c_int
+        lib.orc_threads.argtypes = [ctypes.c_int]
+        lib.orc_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 

@@ -58,9 +58,19 @@
 //
 // The core is templated on the scalar so that a forward-mode dual number gives
 // exact directional derivatives (the reference for the adjoint).
+//
+// Built twice from this one source: serially (g++ -O2, the build the tests
+// use) and with -O3 -march=native -fopenmp for timing on all host cores.  The
+// OpenMP pragmas only split the loops over cells (every cell is computed by
+// the same code) and take the global maximum and the first non-physical cell
+// as reductions, which do not depend on the order; both builds give the same
+// bits (no contraction of multiply-adds in either).
 
 #include <cmath>
 #include <cstdint>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <cstring>
 #include <vector>
 #include <algorithm>
@@ -378,6 +388,7 @@ struct Sim {
     // U = sum_i f_i in every cell                      (eq. "moments_system")
     void moments() {
         for (int k = 0; k < K; ++k)
+#pragma omp parallel for schedule(static)
             for (long c = 0; c < ncell; ++c) {
                 T s = T(0.0);
                 for (int i = 0; i < Q; ++i) s = s + f[((size_t)(i * K + k)) * ncell + c];
@@ -390,12 +401,17 @@ struct Sim {
 
     double max_local_lambda() {
         double m = 0.0;
-        std::vector<double> Uc(K);
-        for (long c = 0; c < ncell; ++c) {
-            if (is_solid_cell(P, c)) continue;
-            for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
-            m = std::max(m, local_lambda(P, Uc.data()));
+#pragma omp parallel reduction(max : m)
+        {
+            std::vector<double> Uc(K);
+#pragma omp for schedule(static)
+            for (long c = 0; c < ncell; ++c) {
+                if (is_solid_cell(P, c)) continue;
+                for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
+                m = std::max(m, local_lambda(P, Uc.data()));
+            }
         }
+        std::vector<double> Uc(K);
         for (int s = 0; s < 4; ++s)  // the ghost cells of Dirichlet sides
             if (P.side[s] == SIDE_DIRICHLET)
                 for (int j = 0; j < side_len(s); ++j) {
@@ -406,23 +422,28 @@ struct Sim {
     }
 
     bool all_physical(long* bad) {
-        std::vector<double> Uc(K);
-        for (long c = 0; c < ncell; ++c) {
-            if (is_solid_cell(P, c)) continue;
-            for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
-            if (!physical(P, Uc.data())) {
-                if (bad) *bad = c;
-                return false;
+        long first = ncell;  // the first non-physical cell
+#pragma omp parallel reduction(min : first)
+        {
+            std::vector<double> Uc(K);
+#pragma omp for schedule(static)
+            for (long c = 0; c < ncell; ++c) {
+                if (is_solid_cell(P, c)) continue;
+                for (int k = 0; k < K; ++k) Uc[k] = val(U[(size_t)k * ncell + c]);
+                if (!physical(P, Uc.data())) first = std::min(first, c);
             }
         }
-        return true;
+        if (first == ncell) return true;
+        if (bad) *bad = first;
+        return false;
     }
 
     // f^0 = f^eq(U0) in every cell (Sec. II.A: the initial data are given to
     // the populations through their equilibria); solid cells hold zeros.
     void init_equilibrium(const T* U0, double lam) {
-        std::vector<T> Uc(K), Gx(K), Gy(K);
-        for (int y = 0; y < P.ny; ++y)
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < P.ny; ++y) {
+            std::vector<T> Uc(K), Gx(K), Gy(K);
             for (int x = 0; x < P.nx; ++x) {
                 long c = (long)y * P.nx + x;
                 if (is_solid_cell(P, c)) continue;  // f stays zero
@@ -432,13 +453,15 @@ struct Sim {
                     for (int k = 0; k < K; ++k)
                         F(f, i, k, x, y) = equilibrium(P.model, i, Uc[k], Gx[k], Gy[k], lam);
             }
+        }
     }
 
     // Collision: f* = (1 - omega) f + omega f^eq(U), with U from moments().
     // (Discrete LBRS update with omega = dt/epsilon, Sec. II.A and II.D.)
     void collide(double lam) {
-        std::vector<T> Uc(K), Gx(K), Gy(K);
-        for (int y = 0; y < P.ny; ++y)
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < P.ny; ++y) {
+            std::vector<T> Uc(K), Gx(K), Gy(K);
             for (int x = 0; x < P.nx; ++x) {
                 long c = (long)y * P.nx + x;
                 if (is_solid_cell(P, c)) continue;  // never pulled from
@@ -450,6 +473,7 @@ struct Sim {
                         F(fs, i, k, x, y) = (1.0 - P.omega) * F(f, i, k, x, y) + P.omega * feq;
                     }
             }
+        }
     }
 
     // Source index along one axis for a pull from position j - s.  Returns -1
@@ -502,9 +526,10 @@ struct Sim {
             stream_with_bodies(lam);
             return;
         }
-        std::vector<double> Ub(K), Gx(K), Gy(K, 0.0);
         for (int i = 0; i < Q; ++i)
-            for (int y = 0; y < P.ny; ++y)
+#pragma omp parallel for schedule(static)
+            for (int y = 0; y < P.ny; ++y) {
+                std::vector<double> Ub(K), Gx(K), Gy(K, 0.0);
                 for (int x = 0; x < P.nx; ++x) {
                     int xsrc = x - sx(P.model, i), ysrc = D == 2 ? y - sy(P.model, i) : 0;
                     if (ghost_state(xsrc, ysrc, Ub.data())) {
@@ -518,6 +543,7 @@ struct Sim {
                     for (int k = 0; k < K; ++k)
                         F(f, i, k, x, y) = (xs < 0 || ys < 0) ? T(0.0) : F(fs, i, k, xs, ys);
                 }
+            }
         apply_walls();
     }
 
@@ -526,9 +552,10 @@ struct Sim {
     // in stream(); then each population whose source is solid is set from
     // the node's own pulled populations by the specular image of its kind.
     void stream_with_bodies(double lam) {
-        std::vector<double> Ub(K), Gx(K), Gy(K, 0.0);
         const int kx = 1, ky = 2;  // momentum components
-        for (int y = 0; y < P.ny; ++y)
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < P.ny; ++y) {
+            std::vector<double> Ub(K), Gx(K), Gy(K, 0.0);
             for (int x = 0; x < P.nx; ++x) {
                 bool solid = is_solid_cell(P, (long)y * P.nx + x);
                 for (int i = 0; i < 4; ++i) {
@@ -548,6 +575,8 @@ struct Sim {
                     for (int k = 0; k < K; ++k) F(f, i, k, x, y) = F(fs, i, k, xs, ys);
                 }
             }
+        }
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < P.ny; ++y)
             for (int x = 0; x < P.nx; ++x) {
                 if (is_solid_cell(P, (long)y * P.nx + x)) continue;
@@ -636,6 +665,16 @@ bool dirichlet_admissible(const Problem& P) {
     return true;
 }
 
+// Largest admissible CFL number of each model.  The lattice speed is
+// lambda*/cfl; the equilibria are monotone in U (Bouchut's condition,
+// Sec. II.D) when every eigenvalue of df_i^eq/dU is >= 0.  D1Q2:
+// 1/2 - mu/(2 lambda) >= 0, i.e. lambda >= |mu| (cfl <= 1).  D1Q3 (the Sec. II.C
+// equilibria U/3 -+ G/(2 lambda)): 1/3 - mu/(2 lambda) >= 0, i.e.
+// lambda >= 1.5 |mu| (cfl <= 2/3).  D2Q4: 1/4 - (s . mu)/(4 lambda) >= 0 with
+// the bound of Sec. II.D (cfl <= 1).  mu runs over the eigenvalues of the flux
+// Jacobian (g'(u) for a scalar law).
+inline double cfl_max(int model) { return model == D1Q3 ? 2.0 / 3.0 : 1.0; }
+
 int validate(const Problem& P) {
     if (P.model < D1Q2 || P.model > D2Q4) return ST_INVAL;
     if (P.flux < FLUX_EULER || P.flux > FLUX_QUADRATIC) return ST_INVAL;
@@ -669,7 +708,7 @@ int validate(const Problem& P) {
     if (P.solid && (P.model != D2Q4 || scalar_law(P) || !mask_admissible(P))) return ST_INVAL;
     if (P.lam_mode < LAM_PER_STEP || P.lam_mode > LAM_USER) return ST_INVAL;
     if (P.lam_mode == LAM_USER && !(P.lam_user > 0.0)) return ST_INVAL;
-    if (P.lam_mode != LAM_USER && !(P.cfl > 0.0 && P.cfl <= 1.0)) return ST_INVAL;
+    if (P.lam_mode != LAM_USER && !(P.cfl > 0.0 && P.cfl <= cfl_max(P.model))) return ST_INVAL;
     return ST_OK;
 }
 
@@ -678,6 +717,19 @@ int validate(const Problem& P) {
 using namespace orc;
 
 extern "C" {
+
+// Threads of the cell loops: a build with OpenMP (the timing build of the CPU
+// baseline) runs every loop over cells in parallel, the default build is
+// serial.  n > 0 sets the count; returns the count in use (1 when serial).
+int orc_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 // Flux vectors of one state.  Gx, Gy: K values each (Gy unused in 1D).
 void orc_flux(const Problem* P, const double* U, double* Gx, double* Gy) {

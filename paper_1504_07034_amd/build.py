@@ -4,6 +4,7 @@ from __future__ import annotations
 import glob
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -26,17 +27,34 @@ FLAGS = [
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    """HIP sources, and the plain C++ host checks (lbrs_host.cpp)."""
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    """Compile every HIP source of the library into liblbrs.so (always rebuilds)."""
+OBJ = os.path.join(ROOT, "_build", "obj")
+
+
+def build(verbose: bool = False, extra=None, jobs: int | None = None) -> str:
+    """Compile every source of the library into liblbrs.so (always rebuilds):
+    one hipcc per source file, in parallel, then one link."""
+    os.makedirs(OBJ, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+
+    def one(src):
+        obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *compile_flags, *(extra or []), "-I", os.path.join(ROOT, "include"), "-c",
+               src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    srcs = sources()
+    n = jobs or min(len(srcs), max(1, (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        objs = list(ex.map(one, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), *sources(),
-           "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -218,6 +218,8 @@ struct lbrs_batch2d {
     const void* graph_args[7];  // arguments the captured gradient graph was built with
     long long graph_steps[2];
     int graph_fuse;
+    int graph_cur;            // host state (buffer of f^n, step count) at the end of the
+    long long graph_nsteps;   // captured sequence, restored after every replay
 };
 
 namespace {
@@ -646,8 +648,16 @@ int lbrs_batch2d_gradient(lbrs_batch2d* b, const double* d_U0, int nsteps, int s
         b->graph_steps[0] = nsteps;
         b->graph_steps[1] = segment;
         b->graph_fuse = b->fuse;
+        // enqueueing the sequence advanced the host's view of the state
+        // (which buffer holds f^n, the step count) to its end
+        b->graph_cur = b->cur;
+        b->graph_nsteps = b->nsteps;
     }
     if (!ok(hipGraphLaunch(b->exec, b->stream))) return LBRS_E_HIP;
+    // a replay leaves the state where the captured sequence ends, whatever
+    // eager calls ran in between
+    b->cur = b->graph_cur;
+    b->nsteps = b->graph_nsteps;
     return LBRS_OK;
 }
 

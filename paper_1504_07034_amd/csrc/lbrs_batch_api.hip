@@ -56,7 +56,8 @@ int check_unit(const lbrs_params* p, int model) {
     if (p->bc[0] < 0 || p->bc[0] > 2 || p->bc[1] < 0 || p->bc[1] > 2) return LBRS_E_INVAL;
     if (p->lambda_mode < LBRS_LAMBDA_PER_STEP || p->lambda_mode > LBRS_LAMBDA_USER) return LBRS_E_INVAL;
     if (p->lambda_mode == LBRS_LAMBDA_USER && !(p->lambda_user > 0.0)) return LBRS_E_INVAL;
-    if (p->lambda_mode != LBRS_LAMBDA_USER && !(p->cfl > 0.0 && p->cfl <= 1.0)) return LBRS_E_INVAL;
+    if (p->lambda_mode != LBRS_LAMBDA_USER && !(p->cfl > 0.0 && p->cfl <= cfl_limit(p->model)))
+        return LBRS_E_INVAL;
     return LBRS_OK;
 }
 
@@ -173,6 +174,8 @@ extern "C" {
 int lbrs_batch_query(int nunits, const lbrs_params* units, int chunk, long long* offsets,
                      size_t* scratch_bytes) {
     if (nunits < 1 || !units) return LBRS_E_INVAL;
+    for (int b = 0; b < nunits; ++b)  // before the occupancy query asks the GPU
+        if (check_unit(&units[b], units[0].model)) return LBRS_E_INVAL;
     const int Q = units[0].model == LBRS_D1Q2 ? 2 : 3;
     const int threads = default_threads(chunk);
     const int grid = grid_for(Q, chunk, threads);

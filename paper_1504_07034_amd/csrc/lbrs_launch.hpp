@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lbrs_device.hpp"
+#include "lbrs_host.hpp"
 
 namespace lbrs {
 
@@ -76,22 +77,9 @@ struct Pair2DArgs {
     long long plane;      // nx * ny
 };
 
-// Node codes of a solid body: per population i (0..3, the D2Q4 order) a
-// 3-bit rule in bits 3i..3i+2 for a population whose pull source is solid,
-// and the solid-cell bit.
-enum : unsigned {
-    IMG_PULL = 0u,     // pulled as usual
-    IMG_FACE_X = 1u,   // population i^1 (s_x reversed), x-momentum negated
-    IMG_FACE_Y = 2u,   // population 3-i (s_y reversed), y-momentum negated
-    IMG_CONCAVE = 3u,  // population i^2 (opposite), both momenta negated
-    IMG_TIP = 4u,      // population i^2, momenta swapped times -s_ix s_iy
-    CODE_SOLID = 0x8000u
-};
-
 // 1D population layouts: planar, element (p, x) at p*nx + x, or blocked,
 // the planes of each 64-cell block contiguous: (x/64)*QK*64 + p*64 + x%64
 // (the last block padded).
-static constexpr int BLOCK1D = 64;
 __host__ __device__ inline long long ofs1d(bool blocked, long long plane, long long bstride, int p,
                                           long long x) {
     return blocked ? (x >> 6) * bstride + p * BLOCK1D + (x & (BLOCK1D - 1)) : p * plane + x;

@@ -39,7 +39,7 @@ EXPORTS = (
     "lbrs_batch2d_moments", "lbrs_batch2d_get_f", "lbrs_batch2d_set_f", "lbrs_batch2d_gradient",
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
     "lbrs_destroy", "lbrs_set_fusion", "lbrs_batch2d_set_fusion", "lbrs_adjoint_step2",
-    "lbrs_step_tape2", "lbrs_forward_taped", "lbrs_backward_taped",
+    "lbrs_step_tape2", "lbrs_forward_taped", "lbrs_backward_taped", "lbrs_cfl_max",
 )
 
 
@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_batch2d_destroy": (None, [vp]),
         "lbrs_body_codes": (i, [P, ctypes.POINTER(ctypes.c_ushort)]),
         "lbrs_strerror": (ctypes.c_char_p, [i]),
+        "lbrs_cfl_max": (d, [i]),
         "lbrs_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -216,6 +217,11 @@ def lbrs_query_sizes(p: lbrs_params):
     _check(load_library().lbrs_query_sizes(ctypes.byref(p), ctypes.byref(f), ctypes.byref(u),
                                            ctypes.byref(s)), "lbrs_query_sizes")
     return f.value, u.value, s.value
+
+
+def lbrs_cfl_max(model: int) -> float:
+    """Largest admissible cfl of a model (host only)."""
+    return load_library(require_gpu=False).lbrs_cfl_max(int(model))
 
 
 def lbrs_prim_to_cons(p: lbrs_params, W: torch.Tensor, U: torch.Tensor, stream=None):

@@ -72,6 +72,32 @@ def test_query_sizes_and_validation(lib):
         assert e.value.code == lbrs.LBRS_E_INVAL, kw
 
 
+def test_cfl_max_per_model(lib):
+    """Bouchut's condition (Sec. II.D) on the Sec. II.C D1Q3 equilibria
+    U/3 -+ G/(2 lambda) needs lambda >= 1.5 max|u -+ a|: cfl <= 2/3; D1Q2 and
+    D2Q4 take cfl <= 1.  A larger cfl is rejected before anything runs; a
+    user lattice speed is not limited."""
+    assert lbrs.lbrs_cfl_max(lbrs.LBRS_D1Q2) == 1.0
+    assert lbrs.lbrs_cfl_max(lbrs.LBRS_D1Q3) == 2.0 / 3.0
+    assert lbrs.lbrs_cfl_max(lbrs.LBRS_D2Q4) == 1.0
+    assert lbrs.lbrs_cfl_max(9) == -1.0
+    for model, nx, ny, ok, bad in [(lbrs.LBRS_D1Q2, 400, 1, 1.0, 1.0 + 1e-12),
+                                   (lbrs.LBRS_D1Q3, 400, 1, 2.0 / 3.0, 0.6667),
+                                   (lbrs.LBRS_D2Q4, 64, 64, 1.0, 1.0 + 1e-12)]:
+        lbrs.lbrs_query_sizes(lbrs.make_params(model, nx, ny, cfl=ok))
+        for mode in (lbrs.LBRS_LAMBDA_PER_STEP, lbrs.LBRS_LAMBDA_FROZEN_INIT):
+            with pytest.raises(lbrs.LBRSError) as e:
+                lbrs.lbrs_query_sizes(lbrs.make_params(model, nx, ny, cfl=bad, lambda_mode=mode))
+            assert e.value.code == lbrs.LBRS_E_INVAL
+        lbrs.lbrs_query_sizes(lbrs.make_params(model, nx, ny, cfl=5.0,
+                                               lambda_mode=lbrs.LBRS_LAMBDA_USER, lambda_user=3.0))
+    # the scalar D1Q3 law has the same limit (1/3 - g'/(2 lambda) >= 0)
+    with pytest.raises(lbrs.LBRSError):
+        lbrs.lbrs_query_sizes(lbrs.make_params(lbrs.LBRS_D1Q3, 400, cfl=0.7,
+                                               law=lbrs.LBRS_LAW_SCALAR, gamma=0.0,
+                                               scalar_flux=(0.0, 1.0, 0.0, 0.0)))
+
+
 def test_dirichlet_data_accepted_by_validation(lib):
     """A Dirichlet side with a (device) pointer passes the host checks; the
     pointer is not dereferenced on the host."""

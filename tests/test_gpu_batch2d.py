@@ -156,14 +156,21 @@ def test_batch2d_gradient_graph_vs_oracle_and_replays():
     Ub = torch.empty((4, T), dtype=torch.float64, device="cuda")
     B.gradient(U0, steps, seg, ck, tp, fb, wk, J, Ub, use_graph=False)
     J_e, Ub_e = J.clone(), Ub.clone()
+    # the state the sequence leaves (the gradient's recompute ends at the first segment)
+    M_e, n_e = B.moments().clone(), B.state()["nsteps"]
     for rep in range(3):
         J.zero_()
         Ub.zero_()
         B.gradient(U0, steps, seg, ck, tp, fb, wk, J, Ub, use_graph=True)
         torch.cuda.synchronize()
         assert torch.equal(J, J_e) and torch.equal(Ub, Ub_e), rep
+        # after a replay the host reads the state the graph left, although
+        # eager steps moved it in between (the buffer of f^n and the count)
+        assert B.state()["nsteps"] == n_e, rep
+        assert torch.equal(B.moments(), M_e), rep
         B.step(3)  # eager work between replays
         torch.cuda.synchronize()
+        assert B.state()["nsteps"] == n_e + 3
     # other arguments recapture the graph instead of replaying the old one
     steps2, seg2 = 17, 4
     B.gradient(U0, steps2, seg2, ck, tp, fb, wk, J, Ub, use_graph=False)

@@ -344,3 +344,55 @@ def test_diffraction_planar_shock_speed():
     for j in (-1, -2, -5):
         front = (r.U[0, j].mean() - 1.4) / (rho2 - 1.4)
         assert abs(front - (0.2 + 5.09 * 0.1)) <= 0.5 / w.nx
+
+
+@pytest.mark.parametrize("omega", [0.7, 1.0, 1.6])
+def test_convex_tip_method_of_images_about_a_diagonal(omega):
+    """The convex-tip rule is the method of images about a 45-degree line.
+
+    D2Q4 hops change x and y by one cell each, so the nodes with x + y even and
+    those with x + y odd form two lattices that never exchange populations
+    (away from clamped sides, with a fixed lattice speed).  Take the body
+    {x + y <= N - 3} on an N x N grid (N odd): every fluid node of the even
+    lattice on the line x + y = N - 1 sees a solid cell only across its
+    (-1,-1) diagonal, never across an axis, i.e. a convex tip.  The mirror
+    sigma(x, y) = (N-1-y, N-1-x) about that line maps the even lattice onto
+    itself, the velocity (+,+) onto (-,-) and (m_x, m_y) onto (-m_y, -m_x).
+    On the line a sigma-symmetric solution therefore has
+    f_(+,+) = M f_(-,-) with M = that momentum map: the tip rule (opposite
+    population, momenta swapped times -s_x s_y = -1).  So the body run equals
+    the body-free run from sigma-symmetric data on the even lattice at and
+    above the line, inside the region no clamped side reaches.  A bounce-back
+    tip (both momenta negated without the swap) breaks the equality wherever
+    m_x != m_y on the line."""
+    N, steps = 41, 8
+    rng = np.random.default_rng(11)
+    A = random_state(rng, N, N)
+    sig = lambda F: F[::-1, ::-1].T      # F(sigma(p)) for a [y][x] plane
+    W = np.empty_like(A)
+    W[0] = 0.5 * (A[0] + sig(A[0]))
+    W[3] = 0.5 * (A[3] + sig(A[3]))
+    W[1] = 0.5 * (A[1] - sig(A[2]))      # u(sigma p) = -v(p)
+    W[2] = 0.5 * (A[2] - sig(A[1]))      # v(sigma p) = -u(p)
+    assert np.array_equal(sig(W[0]), W[0]) and np.allclose(sig(W[1]), -W[2], atol=0)
+    y, x = np.mgrid[0:N, 0:N]
+    solid = ((x + y) <= N - 3).astype(np.uint8)
+    free = P2(N, N, (T,) * 4, omega=omega)
+    U0 = oracle.prim_to_cons(free, W)
+    lam = 2.0 * oracle.initial_lattice_speed(free, U0)  # fixed speed: the lattices decouple
+    for pr in (free,):
+        pr.lam_mode, pr.lam_user = oracle.LAM_USER, lam
+    body = P2(N, N, (T,) * 4, solid=solid, omega=omega)
+    body.lam_mode, body.lam_user = oracle.LAM_USER, lam
+    ref = oracle.run(free, U0, max_steps=steps)
+    got = oracle.run(body, U0, max_steps=steps)
+    assert ref.status == 0 and got.status == 0
+    even_above = ((x + y) % 2 == (N - 1) % 2) & ((x + y) >= N - 1)
+    inner = (x >= steps) & (y >= steps) & (x <= N - 1 - steps) & (y <= N - 1 - steps)
+    sel = even_above & inner
+    assert sel.sum() > 100
+    on_line = sel & ((x + y) == N - 1)
+    # the tip nodes carry tangential momentum, so a bounce-back tip would show
+    assert np.max(np.abs(ref.U[1][on_line] - ref.U[2][on_line])) > 1e-2
+    for k in range(4):
+        np.testing.assert_allclose(got.U[k][sel], ref.U[k][sel], rtol=0, atol=1e-13)
