@@ -1,13 +1,18 @@
 """Benchmark of the LBRS hot path on one MI355X.
 
 Workload: the four-quadrant 2D Riemann problem, 4096 x 4096 cells on [0,1]^2,
-D2Q4, FP64, gamma = 1.4, omega = 1, CFL 0.5, transmissive sides, t_end = 0.3.
-One "step" is one fused collide-and-stream LBRS step over the whole grid
-(moments, flux, equilibria, relaxation, streaming, sides, next-step lambda*).
+D2Q4, FP64, gamma = 1.4, omega = 1, CFL 0.5, transmissive sides, t_end = 0.3,
+per-step lattice speed.  One "step" is one collide-and-stream LBRS step over
+the whole grid (moments, flux, equilibria, relaxation, streaming, sides,
+next-step lambda*).  The K timed steps (after W untimed ones) are taken from
+the middle of the run to t_end, in the autotuned launch form (single steps,
+or two fused steps per launch).
 
-Prints one JSON line: MLUPS (value), the HBM roofline of the step kernel
-(algorithmic 256 B per lattice update: 16 FP64 populations read + 16 written),
-and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: MLUPS (value), the HBM roofline of the timed kernel on
+its own algorithmic bytes (256 B per lattice update for a single step, 128 B
+for two fused steps: f^{n+1} stays in registers), whole runs to t_end, and the
+CPU oracle timed on a bounded sample of the same workload (one thread and all
+host cores).
 """
 import argparse
 import json
@@ -67,12 +72,19 @@ def kernel_source_hash(files=SINGLE_SOURCES) -> str:
 
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = 256  # 16 FP64 populations in + 16 out per lattice update
+BYTES_PER_LUP = 256  # single step: 16 FP64 populations in + 16 out per lattice update
+PAIR_BYTES_PER_LUP = 128  # two fused steps: f^n in, f^{n+2} out per two updates
 
 
-def cpu_baseline(nsteps: int = 7):
-    """The oracle on the same 4096^2 workload for a bounded number of steps
-    (single thread), init time excluded by differencing two runs."""
+def form_bytes(fuse: int) -> int:
+    return PAIR_BYTES_PER_LUP if fuse == 2 else BYTES_PER_LUP
+
+
+def cpu_baseline(nsteps: int = 4):
+    """The oracle on the same 4096^2 workload for a bounded number of steps from
+    t = 0, init time excluded by differencing two runs: its timing build (the
+    same source, -O3 -march=native, OpenMP over cells, no contraction of
+    multiply-adds) on one thread, then on every host core the process may use."""
     import oracle
     from paper_1504_07034_amd import workloads as wl
 
@@ -81,18 +93,31 @@ def cpu_baseline(nsteps: int = 7):
                        omega=w.omega, cfl=w.cfl, sides=w.sides)
     U0 = oracle.prim_to_cons(P, w.W)
     del w
-    t0 = time.perf_counter()
-    oracle.run(P, U0, t_end=0.3, max_steps=0, record=False)
-    t_init = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = oracle.run(P, U0, t_end=0.3, max_steps=nsteps, record=False)
-    t_run = time.perf_counter() - t0
-    secs = max(t_run - t_init, 1e-9)
-    lups = 4096 * 4096 * r.nsteps
-    return {"value": lups / secs / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"4096x4096 four-quadrant problem, {r.nsteps} steps from t=0 "
-                      f"({secs:.1f} s of stepping; init excluded)",
-            "host": _host_cpu()}
+    host = _host_cpu()
+
+    def timed(threads):
+        used = oracle.use("omp", threads)
+        t0 = time.perf_counter()
+        oracle.run(P, U0, t_end=0.3, max_steps=0, record=False)
+        t_init = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = oracle.run(P, U0, t_end=0.3, max_steps=nsteps, record=False)
+        t_run = time.perf_counter() - t0
+        secs = max(t_run - t_init, 1e-9)
+        return used, 4096 * 4096 * r.nsteps / secs / 1e6, secs, r.nsteps
+
+    try:
+        one = timed(1)
+        allc = timed(host["affinity"])
+    finally:
+        oracle.use("serial")
+    return {"value": round(allc[1], 2), "unit": "MLUPS", "cores": allc[0], "kind": "oracle",
+            "sample": f"4096x4096 four-quadrant problem, {allc[3]} steps from t=0 on {allc[0]} "
+                      f"threads ({allc[2]:.1f} s of stepping; init excluded)",
+            "build": "g++ -O3 -march=native -fopenmp -ffp-contract=off",
+            "single_thread": {"value": round(one[1], 2), "cores": 1,
+                              "sample": f"{one[3]} steps ({one[2]:.1f} s)"},
+            "host": host}
 
 
 def _host_cpu() -> dict:
@@ -109,12 +134,16 @@ def _host_cpu() -> dict:
             "affinity": len(os.sched_getaffinity(0))}
 
 
-def batched_1d(chunks=(1022, 2046, 3070), subset=32):
+def batched_1d(chunks=(1022, 2046, 3070), sequential=True):
     """Ragged 1D batch: 1024 seeded shock tubes (200..20000 cells, own t_end) in
-    one persistent launch (chunk autotuned), against sequential single-domain
-    runs of a seeded subset of the same tubes (the plain library path: one
-    persistent launch per tube of <= 2048 cells, one launch per step above).
-    subset = 0 runs the batch alone (for HBM counters of the batched launch)."""
+    one persistent launch (chunk autotuned).  Beside it: the critical path --
+    the largest unit alone in the same batched kernel (its team's serial chain
+    of steps bounds the batch's time from below) -- and the same 1024 tubes run
+    one after another through the plain single-domain path (one persistent
+    launch per tube of <= 2048 cells, one launch per step above), timed on
+    the GPU only: every tube is set up and initialised before the timed region,
+    whose launches are enqueued back to back.  sequential=False runs the batch
+    alone (for HBM counters of the batched launch)."""
     import numpy as np
     import torch
 
@@ -147,7 +176,7 @@ def batched_1d(chunks=(1022, 2046, 3070), subset=32):
         lups = sum(n * t.nx for n, t in zip(st["nsteps"], sel))
         assert st["rc"] == 0 and all(x == t.t_end for x, t in zip(st["t"], sel))
         B.close()
-        return ms, lups
+        return ms, lups, st["nsteps"]
 
     tuned = {}
     for c in chunks:
@@ -156,28 +185,75 @@ def batched_1d(chunks=(1022, 2046, 3070), subset=32):
         except lbrs.LBRSError:  # chunk too large for this device's LDS
             pass
     best = min(tuned, key=lambda c: tuned[c][0])
-    ms, lups = tuned[best]
+    ms, lups, nsteps = tuned[best]
     out = {"units": len(tubes), "cells": int(sum(t.nx for t in tubes)), "chunk": best,
            "ms": round(ms, 2), "MLUPS": round(lups / ms / 1e3, 1),
+           # algorithmic bytes (144 per update, D1Q3) over the time: the
+           # chunks stay in LDS for the whole run, so this is not HBM traffic
            "effective_GBs": round(144 * lups / ms / 1e6, 1),
            "chunk_ms": {str(c): round(v[0], 2) for c, v in tuned.items()}}
-    if subset <= 0:
+    # critical path: the unit with the longest serial chain (cells per member
+    # times steps) alone in the batched kernel
+    def chain(b):
+        t = tubes[b]
+        return nsteps[b] * min(t.nx, best)
+    crit = max(range(len(tubes)), key=chain)
+    ms_c, _, st_c = timed_batch([tubes[crit]], best)
+    out["critical_path"] = {
+        "unit": crit, "cells": tubes[crit].nx, "steps": int(st_c[0]),
+        "members": -(-tubes[crit].nx // best), "alone_ms": round(ms_c, 2),
+        "per_step_us": round(1e3 * ms_c / st_c[0], 3),
+        "batch_over_critical_path": round(ms / ms_c, 3)}
+    if not sequential:
         return out
-    rng = np.random.default_rng(1)
-    sub = [tubes[i] for i in sorted(rng.choice(len(tubes), size=subset, replace=False))]
-    ms_b, lups_b = timed_batch(sub, best)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in sub:
+    sims = []
+    for t in tubes:
         sim = lbrs.Sim(t.model, t.nx, 1, domain=t.domain, gamma=t.gamma, omega=t.omega, cfl=t.cfl)
         sim.init_primitive(t.W)
-        sim.run(t.t_end, chunk=100000)
-        sim.close()
+        sims.append(sim)
     torch.cuda.synchronize()
-    ms_s = (time.perf_counter() - t0) * 1e3
-    out["subset"] = {"units": subset, "batched_ms": round(ms_b, 2),
-                     "sequential_ms": round(ms_s, 2), "speedup": round(ms_s / ms_b, 2)}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for sim, t, k in zip(sims, tubes, nsteps):
+        sim.step(int(k), t.t_end)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    done = [sim.state() for sim in sims]
+    assert all(d["rc"] == 0 and d["t"] == t.t_end and d["nsteps"] == k
+               for d, t, k in zip(done, tubes, nsteps))
+    for sim in sims:
+        sim.close()
+    out["sequential"] = {"units": len(tubes), "kind": "single-domain launches, GPU time only",
+                         "ms": round(ms_s, 2), "speedup": round(ms_s / ms, 2)}
     return out
+
+
+def sod_400():
+    """The 400-cell Sod tube (D1Q3, omega = 1, cfl 0.5, transmissive) run to
+    t = 0.2: the whole run is one persistent launch (one workgroup, the tube in
+    LDS); latency-bound, so MLUPS here is not a roofline figure."""
+    import torch
+
+    from paper_1504_07034_amd import lbrs
+    from paper_1504_07034_amd import workloads as wl
+
+    w = wl.sod(400)
+    sim = lbrs.Sim(w.model, w.nx, 1, domain=w.domain, gamma=w.gamma, omega=w.omega, cfl=w.cfl)
+    U0 = sim.prim_to_cons(torch.from_numpy(w.W).cuda())
+    sim.init(U0)
+    sim.step(10**6, 0.2)  # warm up
+    times = []
+    for _ in range(5):
+        sim.init(U0)
+        times.append(_time_ms(lambda: sim.step(10**6, 0.2)))
+    st = sim.state()
+    assert st["rc"] == 0 and st["t"] == 0.2
+    sim.close()
+    ms = sorted(times)[len(times) // 2]
+    return {"workload": "Sod shock tube, D1Q3, 400 cells, t = 0.2", "steps": st["nsteps"],
+            "launches": 1, "ms": round(ms, 3), "us_per_step": round(1e3 * ms / st["nsteps"], 3),
+            "MLUPS": round(400 * st["nsteps"] / ms / 1e3, 2)}
 
 
 def _time_ms(fn, reps=1):
@@ -268,7 +344,13 @@ def adjoint_2d(n=2048, steps=2000, k=50):
             "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap2, 4),
             "adjoint_step_ms": round(adj2, 4),
             "adjoint_over_forward": round((tap2 + adj2) / fwd, 3),
-            "adjoint_step_effective_GBs": round(288 * cells / (adj2 * 1e-3) / 1e9, 1),
+            # the timed forms' own bytes per lattice update: fused adjoint
+            # 160 (fbar^{n+2} 128 + two tapes 64 + fbar^n 128 per two
+            # updates), single adjoint 288 (128 + 32 + 128)
+            "adjoint_step_bytes_per_lup": 160 if best["fuse"] == 2 else 288,
+            "adjoint_step_GBs": round((160 if best["fuse"] == 2 else 288) * cells /
+                                      (adj2 * 1e-3) / 1e9, 1),
+            "adjoint_step_single_equivalent_GBs": round(288 * cells / (adj2 * 1e-3) / 1e9, 1),
             "single": {"forward_step_ms": round(fwd1, 4), "tape_step_ms": round(tap, 4),
                        "adjoint_step_ms": round(adj, 4),
                        "adjoint_over_forward": round((tap + adj) / fwd1, 3),
@@ -722,11 +804,13 @@ def slab_step(steps=200, warmup=20):
     assert st["rc"] == 0 and st["nsteps"] == warmup + steps
     sim.close()
     cells = n * h
-    gbs = BYTES_PER_LUP * cells / (ms * 1e-3) / 1e9
+    bpl = form_bytes(best["fuse"])
+    gbs = bpl * cells / (ms * 1e-3) / 1e9
     return {"nx": n, "ny": h, "tile_rows": best["rows"], "waves_per_block": best["wpb"],
             "alternate": best["alt"], "steps_per_launch": best["fuse"], "ms_per_step": round(ms, 4),
-            "MLUPS": round(cells / ms / 1e3, 1), "GBs": round(gbs, 1),
-            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            "MLUPS": round(cells / ms / 1e3, 1), "bytes_per_lup": bpl, "GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "single_step_equivalent_GBs": round(BYTES_PER_LUP * cells / (ms * 1e-3) / 1e9, 1)}
 
 
 def main():
@@ -746,7 +830,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
     ap.add_argument("--only", choices=["adjoint", "batch1d", "batch1d_run", "batch2d", "batchgrad",
-                                       "dirichlet", "scalar", "euler1d", "slab", "bodies"],
+                                       "dirichlet", "scalar", "euler1d", "slab", "bodies", "sod"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -769,7 +853,8 @@ def main():
               "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
               "scalar": scalar_laws, "euler1d": euler_1d_long, "slab": slab_step,
               "bodies": bodies_2d,
-              "batch1d_run": lambda: batched_1d(chunks=(3070,), subset=0)}[args.only]
+              "batch1d_run": lambda: batched_1d(chunks=(3070,), sequential=False),
+              "sod": sod_400}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     n = 4096
@@ -783,58 +868,11 @@ def main():
 
     shape = {"rows": args.rows, "wpb": args.wpb, "alt": args.alt, "fuse": args.fuse}
     single = None  # the best single-step shape, when the fused one wins
+    stream = torch.cuda.current_stream()
 
     def use(sh):
         sim.set_tile(sh["rows"], sh["wpb"], sh["alt"])
         sim.set_fusion(sh["fuse"])
-
-    if args.rows < 0:  # autotune the launch shape (untimed), then start over
-        # automatic row segments (one balanced round of the resident waves);
-        # single and fused launches, every (waves per workgroup, march order)
-        # candidate with its HBM traffic measured
-        sim.init(U0)
-        sim.step(20, t_end)
-        best = autotune.tune(sim, t_end, steps=20, use_cache=False, rows=(0,))
-        shape = {k: best[k] for k in ("rows", "wpb", "alt", "fuse")}
-        print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']},{c['fuse']}) "
-                                       f"{c['ms']:.3f} ms" for c in best["candidates"]),
-              file=sys.stderr, flush=True)
-        if shape["fuse"] == 2:
-            s1 = min((c for c in best["candidates"] if c["fuse"] == 1), key=lambda c: c["ms"])
-            single = {k: s1[k] for k in ("rows", "wpb", "alt", "fuse")}
-
-    stream = torch.cuda.current_stream()
-
-    def timed_window(sh, steps, warmup):
-        """ms per step over `steps` steps after `warmup` steps from t = 0.  The
-        run reaches t_end after ~8k steps; segments restart from t = 0 so that
-        every timed step does real work."""
-        seg_cap = 6000
-        sim.init(U0)
-        use(sh)
-        sim.step(warmup, t_end)
-        done_in_seg = warmup
-        total_ms = 0.0
-        left = steps
-        while left > 0:
-            if done_in_seg >= seg_cap:
-                sim.init(U0)
-                done_in_seg = 0
-            k = min(left, seg_cap - done_in_seg)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            sim.step(k, t_end)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            total_ms += e0.elapsed_time(e1)
-            st = sim.state()
-            if st["rc"] != 0 or st["nsteps"] != done_in_seg + k:
-                raise RuntimeError(f"timed steps did not all run: {st}")
-            done_in_seg += k
-            left -= k
-        return total_ms / steps
 
     def whole_run(sh):
         """The whole run from t = 0 to t_end, timed in calls of 1000 steps."""
@@ -856,10 +894,85 @@ def main():
             if st["t"] >= t_end:
                 steps = st["nsteps"]
                 break
-        return {"steps": steps, "ms": round(total_ms, 1),
+        return {"steps": steps, "ms": round(total_ms, 1), "ms_per_step": round(total_ms / steps, 4),
                 "MLUPS": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1)}
 
-    ms_per_step = timed_window(shape, args.steps, args.warmup)
+    # The timed window sits in the middle of the run to t_end: the whole run
+    # in a default shape gives its step count, then the state at the window's
+    # start is kept, and the tuner and every timed form start from it.
+    default = dict(shape) if args.rows >= 0 else {"rows": 0, "wpb": 6, "alt": 0, "fuse": 2}
+    first = whole_run(default)
+    n_total = first["steps"]
+    mid = max(0, (n_total - args.warmup - args.steps) // 2)
+    sim.init(U0)
+    use(default)
+    if mid:
+        sim.step(mid, t_end)
+    st = sim.state()
+    assert st["rc"] == 0 and st["nsteps"] == mid, st
+    f_mid, t_mid = sim.get_f(), st["t"]
+    print(f"bench: whole run {n_total} steps; window from step {mid} (t = {t_mid:.5f})",
+          file=sys.stderr, flush=True)
+
+    if args.rows < 0:  # autotune the launch shape from the window's start (untimed)
+        # automatic row segments (one balanced round of the resident waves);
+        # single and fused launches, every (waves per workgroup, march order)
+        # candidate
+        best = autotune.tune(sim, t_end, steps=20, use_cache=False, rows=(0,))
+        shape = {k: best[k] for k in ("rows", "wpb", "alt", "fuse")}
+        print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']},{c['fuse']}) "
+                                       f"{c['ms']:.3f} ms" for c in best["candidates"]),
+              file=sys.stderr, flush=True)
+        if shape["fuse"] == 2:
+            s1 = min((c for c in best["candidates"] if c["fuse"] == 1), key=lambda c: c["ms"])
+            single = {k: s1[k] for k in ("rows", "wpb", "alt", "fuse")}
+
+    def timed_window(sh, steps, warmup):
+        """ms per step over `steps` steps after `warmup` untimed ones, from the
+        state at step `mid` of the run; the steps taken (fewer only where the
+        run reaches t_end first)."""
+        sim.set_f(f_mid, t_mid, mid)
+        use(sh)
+        if warmup:
+            sim.step(warmup, t_end)
+        st0 = sim.state()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps, t_end)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st1 = sim.state()
+        done = st1["nsteps"] - st0["nsteps"]
+        if st1["rc"] != 0 or (done != steps and st1["t"] < t_end) or done < 1:
+            raise RuntimeError(f"timed steps did not all run: {st0} -> {st1}")
+        return ms, done
+
+    def roofline(sh, ms, done):
+        """The kernel's own algorithmic bytes: 256 B per lattice update for a
+        single step (16 FP64 populations in, 16 out), 128 B for the fused pair
+        (f^n in and f^{n+2} out per two updates: f^{n+1} never leaves the
+        registers); per launch: the launches the window enqueued (a call of
+        K steps enqueues K launches of the step kernel either way)."""
+        bpl = 128 if sh["fuse"] == 2 else 256
+        cells = n * n
+        alg = bpl * cells * done
+        launches = args.steps
+        achieved = alg / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_bytes(sh, args.layout),
+                "kernel": "step2d_pair" if sh["fuse"] == 2 else "step2d_d2q4",
+                "bytes_per_lup": bpl, "launches": launches,
+                "avg_launch_ms": round(ms / launches, 5),
+                "alg_bytes_per_launch": round(alg / launches),
+                # the single step's 256 B per update over the same time
+                "single_step_equivalent_GBs": round(256 * cells * done / (ms * 1e-3) / 1e9, 1)}
+
+    ms_win, done = timed_window(shape, args.steps, args.warmup)
+    ms_per_step = ms_win / done
 
     if args.calibrate_copy:
         f_copy = sim.get_f()
@@ -869,13 +982,13 @@ def main():
 
     cells = n * n
     mlups = cells / (ms_per_step * 1e-3) / 1e6
-    achieved = BYTES_PER_LUP * cells / (ms_per_step * 1e-3) / 1e9
+    rf = roofline(shape, ms_win, done)
     rec = {
         "metric": METRIC,
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": done,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
@@ -886,31 +999,30 @@ def main():
         "config": {"workload": "2D four-quadrant Riemann problem, plain LBRS D2Q4",
                    "nx": n, "ny": n, "domain": "[0,1]^2", "gamma": 1.4, "omega": 1.0,
                    "cfl": 0.5, "sides": "transmissive", "t_end": t_end,
+                   "lambda": "per step", "window_first_step": mid, "run_steps": n_total,
                    "tile_rows": shape["rows"], "waves_per_block": shape["wpb"],
                    "alternate_march": shape["alt"], "steps_per_launch": shape["fuse"],
                    "layout": "row-interleaved" if args.layout == 1 else "planar"},
-        # achieved = 256 B per lattice update (the single step's algorithmic
-        # bytes) x updates per launch / launch time; a fused launch keeps
-        # f^{n+1} in registers, so its measured traffic is about half of that
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes(shape, args.layout),
-                     "kernel": "step2d_pair" if shape["fuse"] == 2 else "step2d_d2q4"},
+        "roofline": rf,
     }
-    if single is not None and not args.no_extras:
-        ms1 = timed_window(single, args.steps, args.warmup)
-        a1 = BYTES_PER_LUP * cells / (ms1 * 1e-3) / 1e9
-        rec["single_step"] = {
-            "tile_rows": single["rows"], "waves_per_block": single["wpb"],
-            "alternate_march": single["alt"], "ms_per_step": round(ms1, 4),
-            "MLUPS": round(cells / (ms1 * 1e-3) / 1e6, 1),
-            "roofline": {"bound": "hbm", "achieved": round(a1, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(a1 / HBM_PEAK_GBS, 4),
-                         "traffic": traffic_bytes(single, args.layout), "kernel": "step2d_d2q4"}}
-        rec["full_run"] = {"fused": whole_run(shape), "single": whole_run(single)}
+    if not args.no_extras:
+        full = {"default_shape": dict(default, **first)}
+        if single is not None:
+            ms1, done1 = timed_window(single, args.steps, args.warmup)
+            rec["single_step"] = {
+                "tile_rows": single["rows"], "waves_per_block": single["wpb"],
+                "alternate_march": single["alt"], "ms_per_step": round(ms1 / done1, 4),
+                "MLUPS": round(cells * done1 / (ms1 * 1e-3) / 1e6, 1),
+                "roofline": roofline(single, ms1, done1)}
+            full["fused"] = whole_run(shape)
+            full["single"] = whole_run(single)
+        else:
+            full["tuned"] = whole_run(shape)
+        rec["full_run"] = full
     if copy_ref is not None:
-        copy_ref["frac_of_copy"] = round(achieved / copy_ref["GBs"], 4)
+        copy_ref["frac_of_copy"] = round(rf["achieved"] / copy_ref["GBs"], 4)
         rec["copy_reference"] = copy_ref
+    del f_mid
     sim.close()
     del U0, sim
     torch.cuda.empty_cache()
@@ -921,6 +1033,7 @@ def main():
         print(f"bench: {name} done", file=sys.stderr, flush=True)
 
     if not args.no_extras:
+        stage("sod_400", sod_400)
         stage("slab_4096x512", slab_step)
         stage("dirichlet_2d", dirichlet_2d)
         stage("bodies_2d", bodies_2d)
