@@ -523,6 +523,29 @@ int lbrs_batch2d_get_state(lbrs_batch2d* b, long long* nsteps, double* lambda, u
 
 void lbrs_batch2d_destroy(lbrs_batch2d* b);
 
+/* ------------------------------------------------------------------------
+ * No-allocation entry point, for callers that cannot allocate: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * One whole run -- lbrs_init, lbrs_step(max_steps, t_end) (two steps per
+ * launch when steps_per_launch is 2, as lbrs_set_fusion) and lbrs_moments --
+ * with the same kernels and results, but the time state (t, step count, the
+ * lambda* reduction slots, the status and the fused launches' record) lives
+ * in a static device array of the library (4 KiB per GPU, kept until the
+ * process ends) instead of a caller scratch area, and the context on the
+ * stack: the call allocates nothing, host or device.  The caller passes
+ * d_U0, the two population buffers (lbrs_query_sizes' f_bytes each), the
+ * output d_U [K][ny][nx] and optionally d_state (5 device doubles: t,
+ * completed steps, lattice speed of the last step, status, first
+ * non-physical step or -1).  Asynchronous on hip_stream.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams, threads) race; calls in one stream are ordered.  Parameters as
+ * lbrs_init, except that solid bodies (whose node codes would need a staging
+ * buffer and more scratch than the array holds) are rejected: LBRS_E_INVAL.
+ * LBRS_E_HIP if the array's device address cannot be found. */
+int lbrs_run_noalloc(const lbrs_params* p, const double* d_U0, double* d_f0, double* d_f1,
+                     int max_steps, double t_end, int steps_per_launch, double* d_U,
+                     double* d_state, void* hip_stream);
+
 const char* lbrs_strerror(int code);
 void lbrs_destroy(lbrs_ctx* c);
 

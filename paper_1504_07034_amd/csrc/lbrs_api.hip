@@ -147,16 +147,17 @@ int lbrs_isentropic_to_cons_adjoint(const lbrs_params* p, const double* d_rho, c
                                                         (hipStream_t)hip_stream));
 }
 
-int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* d_f0, double* d_f1,
-              void* d_scratch, void* hip_stream) {
-    if (!out) return LBRS_E_INVAL;
-    *out = nullptr;
+// Fill a context and enqueue the initialisation (f^0 = f^eq(U0)); body codes
+// need a host staging copy (malloc) and a synchronisation: `allow_body` is
+// false for the no-allocation entry point, which rejects bodies.
+static int ctx_setup(lbrs_ctx* c, const lbrs_params* p, const double* d_U0, double* d_f0,
+                     double* d_f1, void* d_scratch, void* hip_stream, bool allow_body) {
     int rc = check_params(p);
     if (rc) return rc;
     if (!d_U0 || !d_f0 || !d_f1 || !d_scratch || d_f0 == d_f1) return LBRS_E_INVAL;
     if (((uintptr_t)d_scratch & 7u) != 0) return LBRS_E_INVAL;
-    lbrs_ctx* c = (lbrs_ctx*)calloc(1, sizeof(lbrs_ctx));
-    if (!c) return LBRS_E_NOMEM;
+    if (p->solid && !allow_body) return LBRS_E_INVAL;
+    memset(c, 0, sizeof(*c));
     c->P = *p;
     c->Q = nq(p->model);
     c->K = nk(p);
@@ -192,31 +193,22 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
         // time state (the copy completes before this call returns)
         const size_t n = (size_t)p->nx * p->ny;
         unsigned short* h = (unsigned short*)malloc(2 * n);
-        if (!h) {
-            free(c);
-            return LBRS_E_NOMEM;
-        }
+        if (!h) return LBRS_E_NOMEM;
         rc = build_body_codes(p, h);
         if (rc) {
             free(h);
-            free(c);
             return rc;
         }
         c->codes = (unsigned short*)((char*)d_scratch + codes_offset());
         hipError_t e = hipMemcpyAsync(c->codes, h, 2 * n, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         free(h);
-        if (e != hipSuccess) {
-            free(c);
-            return LBRS_E_HIP;
-        }
+        if (e != hipSuccess) return LBRS_E_HIP;
     }
     int dev = 0;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
-        free(c);
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
         return LBRS_E_HIP;
-    }
     c->persistent_max = persistent1d_max_cells(c->Q, prop.sharedMemPerBlock);
     c->cu_count = prop.multiProcessorCount;
     CellArgs a = cell_args(c);
@@ -229,9 +221,19 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
                                      dir, c->stream)
                 : launch_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl, dir,
                               c->stream);
-    if (e != hipSuccess) {
+    return e == hipSuccess ? LBRS_OK : LBRS_E_HIP;
+}
+
+int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* d_f0, double* d_f1,
+              void* d_scratch, void* hip_stream) {
+    if (!out) return LBRS_E_INVAL;
+    *out = nullptr;
+    lbrs_ctx* c = (lbrs_ctx*)calloc(1, sizeof(lbrs_ctx));
+    if (!c) return LBRS_E_NOMEM;
+    int rc = ctx_setup(c, p, d_U0, d_f0, d_f1, d_scratch, hip_stream, true);
+    if (rc) {
         free(c);
-        return LBRS_E_HIP;
+        return rc;
     }
     *out = c;
     return LBRS_OK;
@@ -833,6 +835,60 @@ int lbrs_backward_taped(lbrs_ctx* c, int nsteps, const double* d_tape, double* d
             hipSuccess)
             return LBRS_E_HIP;
     }
+    return LBRS_OK;
+}
+
+// ------------------------------------------------ no-allocation whole run
+// The time state of lbrs_run_noalloc lives in this file-scope device array
+// (each GPU holds its own copy until the process ends).  Host code never
+// passes its name to a kernel: it is a host-side stand-in there.  Its device
+// address is looked up once per device, with that device current, and kept.
+static constexpr size_t NOALLOC_SCRATCH_BYTES = 4096;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static void* noalloc_ptr[NOALLOC_MAX_DEVICES];
+static int noalloc_state[NOALLOC_MAX_DEVICES];  // 0 unknown, 1 ready, -1 lookup failed
+
+static void* noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+    int st = __atomic_load_n(&noalloc_state[dev], __ATOMIC_ACQUIRE);
+    if (st == 0) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && ptr) {
+            noalloc_ptr[dev] = ptr;  // the same address from every thread that races here
+            __atomic_store_n(&noalloc_state[dev], 1, __ATOMIC_RELEASE);
+            st = 1;
+        } else {
+            __atomic_store_n(&noalloc_state[dev], -1, __ATOMIC_RELEASE);
+            st = -1;
+        }
+    }
+    return st == 1 ? noalloc_ptr[dev] : nullptr;
+}
+
+int lbrs_run_noalloc(const lbrs_params* p, const double* d_U0, double* d_f0, double* d_f1,
+                     int max_steps, double t_end, int steps_per_launch, double* d_U,
+                     double* d_state, void* hip_stream) {
+    if (!p || !d_U || max_steps < 0 || isnan(t_end)) return LBRS_E_INVAL;
+    if (steps_per_launch != 1 && steps_per_launch != 2) return LBRS_E_INVAL;
+    if (p->solid) return LBRS_E_INVAL;  // body codes would need a host staging buffer
+    // the time state and the fused launches' record must fit the array
+    if (codes_offset() > NOALLOC_SCRATCH_BYTES) return LBRS_E_INVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LBRS_E_HIP;
+    void* sp = noalloc_scratch(dev);
+    if (!sp) return LBRS_E_HIP;
+    lbrs_ctx c;  // on the stack: nothing is allocated
+    int rc = ctx_setup(&c, p, d_U0, d_f0, d_f1, sp, hip_stream, false);
+    if (rc) return rc;
+    if (steps_per_launch == 2 && (rc = lbrs_set_fusion(&c, 2))) return rc;
+    if ((rc = lbrs_step(&c, max_steps, t_end))) return rc;
+    if ((rc = lbrs_moments(&c, d_U))) return rc;
+    if (d_state &&
+        launch_export_state(c.st, (int)(c.launches & 1), d_state, c.stream) != hipSuccess)
+        return LBRS_E_HIP;
     return LBRS_OK;
 }
 

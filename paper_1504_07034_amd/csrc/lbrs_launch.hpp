@@ -283,6 +283,7 @@ hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
 hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);
 int persistent1d_max_cells(int Q, size_t lds_limit);
 hipError_t launch_reset(DevState* st, hipStream_t s);
+hipError_t launch_export_state(const DevState* st, int slot, double* out, hipStream_t s);
 hipError_t launch_prim_to_cons(const CellArgs& a, const double* W, double* U, hipStream_t s);
 hipError_t launch_prim_to_cons_adjoint(const CellArgs& a, const double* W, const double* Ub,
                                        double* Wb, hipStream_t s);

@@ -399,6 +399,25 @@ __global__ void adjoint_init_d2q4(AdjArgs a, const double* __restrict__ fb0,
 // ------------------------------------------------------------ launchers
 static inline dim3 grid1(long long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
+// The time state a sequence of launches left (slot `slot`), as doubles:
+// t, completed steps, lattice speed of the last step, status, first
+// non-physical step (-1: none).
+__global__ void export_state_kernel(const DevState* st, int slot, double* out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const Slot sl = st->s[slot];
+        out[0] = sl.t;
+        out[1] = (double)sl.n;
+        out[2] = sl.lam_used;
+        out[3] = (double)st->status;
+        out[4] = st->fail_step == ~0ull ? -1.0 : (double)st->fail_step;
+    }
+}
+
+hipError_t launch_export_state(const DevState* st, int slot, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(export_state_kernel, dim3(1), dim3(64), 0, s, st, slot, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset(DevState* st, hipStream_t s) {
     hipLaunchKernelGGL(reset_state_kernel, dim3(1), dim3(64), 0, s, st);
     return hipGetLastError();

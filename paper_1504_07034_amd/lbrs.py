@@ -40,6 +40,7 @@ EXPORTS = (
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
     "lbrs_destroy", "lbrs_set_fusion", "lbrs_batch2d_set_fusion", "lbrs_adjoint_step2",
     "lbrs_step_tape2", "lbrs_forward_taped", "lbrs_backward_taped", "lbrs_cfl_max",
+    "lbrs_run_noalloc",
 )
 
 
@@ -132,6 +133,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_body_codes": (i, [P, ctypes.POINTER(ctypes.c_ushort)]),
         "lbrs_strerror": (ctypes.c_char_p, [i]),
         "lbrs_cfl_max": (d, [i]),
+        "lbrs_run_noalloc": (i, [P, vp, vp, vp, i, d, i, vp, vp, vp]),
         "lbrs_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -222,6 +224,14 @@ def lbrs_query_sizes(p: lbrs_params):
 def lbrs_cfl_max(model: int) -> float:
     """Largest admissible cfl of a model (host only)."""
     return load_library(require_gpu=False).lbrs_cfl_max(int(model))
+
+
+def lbrs_run_noalloc(p: lbrs_params, U0, f0, f1, max_steps: int, t_end: float,
+                     steps_per_launch: int, U, state=None, stream=None):
+    """Whole run with the library's static time state (no allocation)."""
+    _check(load_library().lbrs_run_noalloc(
+        ctypes.byref(p), _dptr(U0), _dptr(f0), _dptr(f1), int(max_steps), float(t_end),
+        int(steps_per_launch), _dptr(U), _dptr(state), _stream(stream)), "lbrs_run_noalloc")
 
 
 def lbrs_prim_to_cons(p: lbrs_params, W: torch.Tensor, U: torch.Tensor, stream=None):
