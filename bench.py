@@ -80,11 +80,12 @@ def form_bytes(fuse: int) -> int:
     return PAIR_BYTES_PER_LUP if fuse == 2 else BYTES_PER_LUP
 
 
-def cpu_baseline(nsteps: int = 4):
+def cpu_baseline(nsteps_one: int = 8, nsteps_all: int = 48):
     """The oracle on the same 4096^2 workload for a bounded number of steps from
     t = 0, init time excluded by differencing two runs: its timing build (the
     same source, -O3 -march=native, OpenMP over cells, no contraction of
-    multiply-adds) on one thread, then on every host core the process may use."""
+    multiply-adds) on one thread (8 steps, ~12 s), then on every host core the
+    process may use (48 steps, ~10 s on 16 cores)."""
     import oracle
     from paper_1504_07034_amd import workloads as wl
 
@@ -95,7 +96,7 @@ def cpu_baseline(nsteps: int = 4):
     del w
     host = _host_cpu()
 
-    def timed(threads):
+    def timed(threads, nsteps):
         used = oracle.use("omp", threads)
         t0 = time.perf_counter()
         oracle.run(P, U0, t_end=0.3, max_steps=0, record=False)
@@ -107,8 +108,8 @@ def cpu_baseline(nsteps: int = 4):
         return used, 4096 * 4096 * r.nsteps / secs / 1e6, secs, r.nsteps
 
     try:
-        one = timed(1)
-        allc = timed(host["affinity"])
+        one = timed(1, nsteps_one)
+        allc = timed(host["affinity"], nsteps_all)
     finally:
         oracle.use("serial")
     return {"value": round(allc[1], 2), "unit": "MLUPS", "cores": allc[0], "kind": "oracle",
@@ -188,9 +189,9 @@ def batched_1d(chunks=(1022, 2046, 3070), sequential=True):
     ms, lups, nsteps = tuned[best]
     out = {"units": len(tubes), "cells": int(sum(t.nx for t in tubes)), "chunk": best,
            "ms": round(ms, 2), "MLUPS": round(lups / ms / 1e3, 1),
-           # algorithmic bytes (144 per update, D1Q3) over the time: the
-           # chunks stay in LDS for the whole run, so this is not HBM traffic
-           "effective_GBs": round(144 * lups / ms / 1e6, 1),
+           # a single 1D D1Q3 step's 144 B per update at this rate (the batch
+           # keeps its populations on chip: not HBM traffic)
+           "single_step_equivalent_GBs": round(144 * lups / ms / 1e6, 1),
            "chunk_ms": {str(c): round(v[0], 2) for c, v in tuned.items()}}
     # critical path: the unit with the longest serial chain (cells per member
     # times steps) alone in the batched kernel
@@ -894,8 +895,11 @@ def main():
             if st["t"] >= t_end:
                 steps = st["nsteps"]
                 break
-        return {"steps": steps, "ms": round(total_ms, 1), "ms_per_step": round(total_ms / steps, 4),
-                "MLUPS": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1)}
+        out = {"steps": steps, "ms": round(total_ms, 1), "ms_per_step": round(total_ms / steps, 4),
+               "MLUPS": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1)}
+        if sh["fuse"] == 2:
+            out["launches"] = sim.pair_stats()
+        return out
 
     # The timed window sits in the middle of the run to t_end: the whole run
     # in a default shape gives its step count, then the state at the window's
@@ -936,6 +940,7 @@ def main():
         if warmup:
             sim.step(warmup, t_end)
         st0 = sim.state()
+        c0 = sim.pair_stats() if sh["fuse"] == 2 else None
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -948,7 +953,12 @@ def main():
         done = st1["nsteps"] - st0["nsteps"]
         if st1["rc"] != 0 or (done != steps and st1["t"] < t_end) or done < 1:
             raise RuntimeError(f"timed steps did not all run: {st0} -> {st1}")
+        if c0 is not None:
+            c1 = sim.pair_stats()
+            window_launches[sh["wpb"], sh["alt"]] = {k: c1[k] - c0[k] for k in c1}
         return ms, done
+
+    window_launches = {}
 
     def roofline(sh, ms, done):
         """The kernel's own algorithmic bytes: 256 B per lattice update for a
@@ -961,15 +971,21 @@ def main():
         alg = bpl * cells * done
         launches = args.steps
         achieved = alg / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_bytes(sh, args.layout),
-                "kernel": "step2d_pair" if sh["fuse"] == 2 else "step2d_d2q4",
-                "bytes_per_lup": bpl, "launches": launches,
-                "avg_launch_ms": round(ms / launches, 5),
-                "alg_bytes_per_launch": round(alg / launches),
-                # the single step's 256 B per update over the same time
-                "single_step_equivalent_GBs": round(256 * cells * done / (ms * 1e-3) / 1e9, 1)}
+        r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+             "traffic": traffic_bytes(sh, args.layout),
+             "kernel": "step2d_pair" if sh["fuse"] == 2 else "step2d_d2q4",
+             "bytes_per_lup": bpl, "launches": launches,
+             "avg_launch_ms": round(ms / launches, 5),
+             "alg_bytes_per_launch": round(alg / launches),
+             # the single step's 256 B per update over the same time
+             "single_step_equivalent_GBs": round(256 * cells * done / (ms * 1e-3) / 1e9, 1)}
+        if sh["fuse"] == 2:
+            # what the window's launches did: pairs that stood, pairs rolled
+            # back, bound-only passes, single steps, predictions of the next
+            # bound taken (exact / within tolerance) and missed
+            r["launch_counts"] = window_launches.get((sh["wpb"], sh["alt"]))
+        return r
 
     ms_win, done = timed_window(shape, args.steps, args.warmup)
     ms_per_step = ms_win / done

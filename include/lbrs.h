@@ -237,6 +237,21 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
 int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda,
                    unsigned* status, long long* fail_step);
 
+/* Counters of the fused launches since lbrs_init (lbrs_set_fusion(c, 2)),
+ * into counts[0 .. n-1] (n <= 9; missing ones 0): [0] two-step launches whose
+ * result stood, [1] two-step launches rolled back (a guessed lambda*_{n+1}
+ * that was wrong), [2] launches that only reduced the bound of f^{n+1},
+ * [3] one-step launches, [4] predictions of the next launch's bound made,
+ * [5] predicted bounds that stood, [6] predicted bounds rolled back,
+ * [7] cells whose bound the predictions evaluated, [8] launches that listed
+ * candidates but left no prediction (too many, none, or a non-physical
+ * state).  With per-step lattice speeds a fused launch guesses the bound of
+ * the state after its first step (the prediction when the launch before left
+ * one, else the current bound while it keeps repeating) and the next launch
+ * checks the guess bit for bit, so the counters describe cost only: results
+ * are those of single steps.  Waits for the stream. */
+int lbrs_pair_stats(lbrs_ctx* c, long long* counts, int n);
+
 /* Moments of the current populations, U = sum_i f_i (eq. "moments_system"),
  * into d_U [K][ny][nx].  Asynchronous. */
 int lbrs_moments(lbrs_ctx* c, double* d_U);
@@ -530,7 +545,7 @@ void lbrs_batch2d_destroy(lbrs_batch2d* b);
  * launch when steps_per_launch is 2, as lbrs_set_fusion) and lbrs_moments --
  * with the same kernels and results, but the time state (t, step count, the
  * lambda* reduction slots, the status and the fused launches' record) lives
- * in a static device array of the library (4 KiB per GPU, kept until the
+ * in a static device array of the library (512 KiB per GPU, kept until the
  * process ends) instead of a caller scratch area, and the context on the
  * stack: the call allocates nothing, host or device.  The caller passes
  * d_U0, the two population buffers (lbrs_query_sizes' f_bytes each), the

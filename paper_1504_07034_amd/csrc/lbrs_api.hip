@@ -33,7 +33,8 @@ struct lbrs_ctx {
     unsigned short* codes;  // body node codes in the scratch area (null: no body)
     int fuse;            // 2D Euler: time steps per launch (1, or 2 fused)
     PairState* pst;      // record of the fused launches (scratch area, behind the time state)
-    int pbpc[17];        // resident fused-kernel workgroups per CU, by waves per block
+    PredCand* cand;      // candidate list of the per-step prediction (scratch area), or null
+    int pbpc[2][17];     // resident fused-kernel workgroups per CU, by (filter, waves per block)
     int abpc[17];        // the same for the fused adjoint kernel
 };
 
@@ -58,11 +59,22 @@ static CellArgs cell_args(const lbrs_ctx* c) {
 
 static int hip_status(hipError_t e) { return e == hipSuccess ? LBRS_OK : LBRS_E_HIP; }
 
-// Scratch area: the time state, the record of the fused launches, then the
-// body codes (each at a 256-byte boundary).
+// Scratch area: the time state, the record of the fused launches, the
+// candidate list of the per-step prediction (contexts that can fuse: 2D
+// Euler without Dirichlet sides or a body), then the body codes (each at a
+// 256-byte boundary).
 static size_t round256(size_t n) { return (n + 255) / 256 * 256; }
 static size_t pair_offset() { return round256(sizeof(DevState)); }
-static size_t codes_offset() { return pair_offset() + round256(sizeof(PairState)); }
+static size_t cand_offset() { return pair_offset() + round256(sizeof(PairState)); }
+static bool fusable(const lbrs_params* p) {
+    if (p->model != LBRS_D2Q4 || p->law != LBRS_LAW_EULER || p->solid) return false;
+    for (int s = 0; s < 4; ++s)
+        if (p->bc[s] == LBRS_BC_DIRICHLET) return false;
+    return true;
+}
+static size_t codes_offset(const lbrs_params* p) {
+    return cand_offset() + (fusable(p) ? round256(sizeof(PredCand) * (size_t)PRED_CAP) : 0);
+}
 
 extern "C" {
 
@@ -73,7 +85,7 @@ int lbrs_query_sizes(const lbrs_params* p, size_t* f_bytes, size_t* u_bytes, siz
     if (f_bytes) *f_bytes = sizeof(double) * (size_t)nq(p->model) * nk(p) * (size_t)fcells(p);
     if (u_bytes) *u_bytes = sizeof(double) * (size_t)nk(p) * cells;
     if (scratch_bytes)
-        *scratch_bytes = codes_offset() + (p->solid ? (2 * cells + 255) / 256 * 256 : 0);
+        *scratch_bytes = codes_offset(p) + (p->solid ? (2 * cells + 255) / 256 * 256 : 0);
     return LBRS_OK;
 }
 
@@ -178,6 +190,7 @@ static int ctx_setup(lbrs_ctx* c, const lbrs_params* p, const double* d_U0, doub
     c->f1 = d_f1;
     c->st = (DevState*)d_scratch;
     c->pst = (PairState*)((char*)d_scratch + pair_offset());
+    c->cand = fusable(p) ? (PredCand*)((char*)d_scratch + cand_offset()) : nullptr;
     c->fuse = 1;
     c->stream = (hipStream_t)hip_stream;
     c->launches = 0;
@@ -199,7 +212,7 @@ static int ctx_setup(lbrs_ctx* c, const lbrs_params* p, const double* d_U0, doub
             free(h);
             return rc;
         }
-        c->codes = (unsigned short*)((char*)d_scratch + codes_offset());
+        c->codes = (unsigned short*)((char*)d_scratch + codes_offset(p));
         hipError_t e = hipMemcpyAsync(c->codes, h, 2 * n, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         free(h);
@@ -215,6 +228,7 @@ static int ctx_setup(lbrs_ctx* c, const lbrs_params* p, const double* d_U0, doub
     const double* dir[4];
     for (int s = 0; s < 4; ++s) dir[s] = p->bc[s] == LBRS_BC_DIRICHLET ? p->dirichlet[s] : nullptr;
     hipError_t e = launch_reset(c->st, c->stream);
+    if (e == hipSuccess) e = launch_pair_reset(c->pst, c->stream);
     if (e == hipSuccess)
         e = p->law == LBRS_LAW_SCALAR
                 ? launch_scalar_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl,
@@ -336,15 +350,26 @@ static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const d
 
 // Fused two-step launches: strips of at most 60 columns (two halo lanes on
 // each side), segments of at least 4 rows (two halo rows on each side).
-// Waves per workgroup of the fused kernel: 16-wave groups do not fit its
-// registers at the occupancy it needs and run as 12.
-static int pair_wpb(const lbrs_ctx* c) { return c->waves_per_block > 12 ? 12 : c->waves_per_block; }
+// Per-step speeds run the fused launches in the form that lists candidates
+// for the prediction of the next launch's bound.
+static bool pair_filter(const lbrs_ctx* c) {
+    return c->cand && c->P.lambda_mode == LBRS_LAMBDA_PER_STEP;
+}
 
-static int pair_max_blocks(const lbrs_ctx* c) {
+// Waves per workgroup of the fused kernel: 16-wave groups do not fit its
+// registers at the occupancy it needs and run as 12; in the form that lists
+// candidates (210 registers) 12-wave groups spill, and run as 8.
+static int pair_wpb(const lbrs_ctx* c) {
+    const int cap = pair_filter(c) ? 8 : 12;
+    return c->waves_per_block > cap ? cap : c->waves_per_block;
+}
+
+static int pair_max_blocks(const lbrs_ctx* c, bool tape = false) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
     const int w = pair_wpb(c);
-    int& n = m->pbpc[w];
-    if (n == 0) n = step2d_pair_blocks_per_cu(w);
+    const int f = pair_filter(c) && !tape ? 1 : 0;
+    int& n = m->pbpc[f][w];
+    if (n == 0) n = step2d_pair_blocks_per_cu(w, f != 0);
     return c->cu_count * n;
 }
 
@@ -384,6 +409,7 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end) {
     a.last = 0;
     a.tape0 = a.tape1 = nullptr;
     a.plane = c->plane;
+    a.cand = pair_filter(c) ? c->cand : nullptr;
     return a;
 }
 
@@ -490,6 +516,9 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
             a.launch = c->launches;
             a.last = s == nl - 1;
             e = launch_step2d_pair(a, pair_wpb(c), false, mb, c->stream);
+            // with per-step speeds, the prediction of the bound the next
+            // launch's second step needs
+            if (e == hipSuccess && a.cand) e = launch_pair_predict(a, c->stream);
             if (e != hipSuccess) return LBRS_E_HIP;
             ++c->launches;
         }
@@ -547,6 +576,16 @@ int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda, un
     if (status) *status = h.status;
     if (fail_step) *fail_step = h.fail_step == ~0ull ? -1 : (long long)h.fail_step;
     return h.status ? LBRS_E_NONPHYSICAL : LBRS_OK;
+}
+
+int lbrs_pair_stats(lbrs_ctx* c, long long* counts, int n) {
+    if (!c || !counts || n < 0) return LBRS_E_INVAL;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LBRS_E_HIP;
+    unsigned long long h[PST_COUNT];
+    if (hipMemcpy(h, c->pst->stat, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return LBRS_E_HIP;
+    for (int i = 0; i < n; ++i) counts[i] = i < PST_COUNT ? (long long)h[i] : 0;
+    return LBRS_OK;
 }
 
 int lbrs_moments(lbrs_ctx* c, double* d_U) {
@@ -685,11 +724,12 @@ static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const d
 // one-step launch, slot len-1).
 static int step_tape_fused(lbrs_ctx* c, int len, double* d_tape) {
     Pair2DArgs a = pair_args(c, INFINITY);
+    a.cand = nullptr;
     const long long ucount = (long long)c->K * c->plane;
     const int nl = len / 2 + 1;
     hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), len, c->stream);
     if (e != hipSuccess) return LBRS_E_HIP;
-    const int mb = pair_max_blocks(c);
+    const int mb = pair_max_blocks(c, true);
     for (int k = 0; k < nl; ++k) {
         const long long s0 = 2LL * k < len ? 2LL * k : len - 1;
         const long long s1 = 2LL * k + 1 < len ? 2LL * k + 1 : len - 1;
@@ -712,9 +752,10 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
     // the set-up kernel and two launches: the pair, then the one that checks
     // it (a one-step fallback writes slot d_Utape_n, as the first step would)
     Pair2DArgs a = pair_args(c, INFINITY);
+    a.cand = nullptr;
     hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), 2, c->stream);
     if (e != hipSuccess) return LBRS_E_HIP;
-    const int mb = pair_max_blocks(c);
+    const int mb = pair_max_blocks(c, true);
     a.tape0 = d_Utape_n;
     a.tape1 = d_Utape_n1;
     for (int k = 0; k < 2; ++k) {
@@ -843,7 +884,7 @@ int lbrs_backward_taped(lbrs_ctx* c, int nsteps, const double* d_tape, double* d
 // (each GPU holds its own copy until the process ends).  Host code never
 // passes its name to a kernel: it is a host-side stand-in there.  Its device
 // address is looked up once per device, with that device current, and kept.
-static constexpr size_t NOALLOC_SCRATCH_BYTES = 4096;
+static constexpr size_t NOALLOC_SCRATCH_BYTES = 512 * 1024;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 static constexpr int NOALLOC_MAX_DEVICES = 64;
@@ -875,7 +916,7 @@ int lbrs_run_noalloc(const lbrs_params* p, const double* d_U0, double* d_f0, dou
     if (steps_per_launch != 1 && steps_per_launch != 2) return LBRS_E_INVAL;
     if (p->solid) return LBRS_E_INVAL;  // body codes would need a host staging buffer
     // the time state and the fused launches' record must fit the array
-    if (codes_offset() > NOALLOC_SCRATCH_BYTES) return LBRS_E_INVAL;
+    if (codes_offset(p) > NOALLOC_SCRATCH_BYTES) return LBRS_E_INVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return LBRS_E_HIP;
     void* sp = noalloc_scratch(dev);

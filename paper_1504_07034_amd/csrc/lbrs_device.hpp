@@ -126,17 +126,44 @@ struct Euler2 {
     double u, v, p, H;  // velocity, pressure, E + p
 };
 
+// The per-cell arithmetic below is written with the multiply-adds the kernels
+// take spelled out (fma_rn) and contraction off inside: the compiler may not
+// fuse a product into a sum on its own, so every inlined copy of a step (a
+// tile's first rows and its loop, the fused and single kernels, the
+// prediction of the next bound) rounds every cell alike, bit for bit.
+__device__ inline double fma_rn(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ inline Euler2 euler2(const double U[4], double gm1) {
+#pragma clang fp contract(off)
     Euler2 e;
     double ir = 1.0 / U[0];
     e.u = U[1] * ir;
     e.v = U[2] * ir;
-    // m u + n v; the compiler may still fuse one product into the sum (the
-    // kernels are built with contraction), so x <-> y symmetry holds to rounding
-    double ke = 0.5 * __dadd_rn(__dmul_rn(U[1], e.u), __dmul_rn(U[2], e.v));
+    // (m u + n v) / 2, symmetric in x and y
+    double ke = 0.5 * (U[1] * e.u + U[2] * e.v);
     e.p = gm1 * (U[3] - ke);
     e.H = U[3] + e.p;
     return e;
+}
+
+// Fluxes G1 = F(U), G2 = G(U) of the 2D Euler equations.
+__device__ inline void fluxes_d2q4(const double U[4], const Euler2& e, double G1[4],
+                                   double G2[4]) {
+#pragma clang fp contract(off)
+    G1[0] = U[1];
+    G1[1] = fma_rn(U[1], e.u, e.p);
+    G1[2] = U[1] * e.v;
+    G1[3] = e.u * e.H;
+    G2[0] = U[2];
+    G2[1] = U[2] * e.u;
+    G2[2] = fma_rn(U[2], e.v, e.p);
+    G2[3] = e.v * e.H;
+}
+
+// (1-omega) f + omega x.
+__device__ inline double relax(double om1, double f, double omega, double x) {
+#pragma clang fp contract(off)
+    return fma_rn(om1, f, omega * x);
 }
 
 // Post-collision populations of one cell, fs = (1-omega) f + omega f^eq, with
@@ -144,18 +171,19 @@ __device__ inline Euler2 euler2(const double U[4], double gm1) {
 // folded into a = G1 + G2 and b = G1 - G2.  f and fs: [i][k], 16 values.
 __device__ inline void collide_d2q4(const double f[16], const double U[4], const Euler2& e,
                                     double c4lam, double omega, double fs[16]) {
-    const double G1[4] = {U[1], U[1] * e.u + e.p, U[1] * e.v, e.u * e.H};
-    const double G2[4] = {U[2], U[2] * e.u, U[2] * e.v + e.p, e.v * e.H};
+#pragma clang fp contract(off)
+    double G1[4], G2[4];
+    fluxes_d2q4(U, e, G1, G2);
     const double om1 = 1.0 - omega;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         double q = 0.25 * U[k];
         double a = (G1[k] + G2[k]) * c4lam;
         double b = (G1[k] - G2[k]) * c4lam;
-        fs[0 * 4 + k] = om1 * f[0 * 4 + k] + omega * (q - a);
-        fs[1 * 4 + k] = om1 * f[1 * 4 + k] + omega * (q + b);
-        fs[2 * 4 + k] = om1 * f[2 * 4 + k] + omega * (q + a);
-        fs[3 * 4 + k] = om1 * f[3 * 4 + k] + omega * (q - b);
+        fs[0 * 4 + k] = relax(om1, f[0 * 4 + k], omega, q - a);
+        fs[1 * 4 + k] = relax(om1, f[1 * 4 + k], omega, q + b);
+        fs[2 * 4 + k] = relax(om1, f[2 * 4 + k], omega, q + a);
+        fs[3 * 4 + k] = relax(om1, f[3 * 4 + k], omega, q - b);
     }
 }
 
@@ -163,8 +191,9 @@ __device__ inline void collide_d2q4(const double f[16], const double U[4], const
 // folded form as the collision (the populations of a Dirichlet ghost cell).
 __device__ inline void equilibria_d2q4(const double U[4], const Euler2& e, double c4lam,
                                        double feq[16]) {
-    const double G1[4] = {U[1], U[1] * e.u + e.p, U[1] * e.v, e.u * e.H};
-    const double G2[4] = {U[2], U[2] * e.u, U[2] * e.v + e.p, e.v * e.H};
+#pragma clang fp contract(off)
+    double G1[4], G2[4];
+    fluxes_d2q4(U, e, G1, G2);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         double q = 0.25 * U[k];
@@ -179,6 +208,7 @@ __device__ inline void equilibria_d2q4(const double U[4], const Euler2& e, doubl
 
 // U = sum_i f_i, summed as (f1 + f3) + (f2 + f4) for every component.
 __device__ inline void moments_d2q4(const double f[16], double U[4]) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < 4; ++k) U[k] = (f[k] + f[8 + k]) + (f[4 + k] + f[12 + k]);
 }
@@ -187,12 +217,13 @@ __device__ inline void moments_d2q4(const double f[16], double U[4]) {
 // a >= 0 is max(|u+v|, |u-v|) + sqrt2 a exactly.  Returns false (and 0) for a
 // non-physical state.
 __device__ inline bool bound_d2q4(const double U[4], double gamma, double* lam) {
+#pragma clang fp contract(off)
     double gm1 = gamma - 1.0;
     Euler2 e = euler2(U, gm1);
     bool ok = (U[0] > 0.0) && (e.p > 0.0) && isfinite(U[0]) && isfinite(U[1]) &&
               isfinite(U[2]) && isfinite(U[3]) && isfinite(e.p);
     double a = sqrt(gamma * e.p / U[0]);
-    double l = fmax(fabs(e.u + e.v), fabs(e.u - e.v)) + 1.4142135623730951 * a;
+    double l = fma_rn(1.4142135623730951, a, fmax(fabs(e.u + e.v), fabs(e.u - e.v)));
     *lam = ok ? l : 0.0;
     return ok;
 }
@@ -263,6 +294,7 @@ __device__ inline void adjoint_init_cell_d2q4(const double fb[16], const double 
 
 // ----------------------------------------------------------- 1D Euler
 __device__ inline void euler1(const double U[3], double gm1, double* u, double* p, double* H) {
+#pragma clang fp contract(off)
     double ir = 1.0 / U[0];
     *u = U[1] * ir;
     *p = gm1 * (U[2] - 0.5 * U[1] * (*u));
@@ -273,6 +305,7 @@ __device__ inline void euler1(const double U[3], double gm1, double* u, double* 
 template <int Q>
 __device__ inline void collide_1d(const double* f, const double U[3], double gm1, double c2lam,
                                   double omega, double* fs) {
+#pragma clang fp contract(off)
     double u, p, H;
     euler1(U, gm1, &u, &p, &H);
     const double G[3] = {U[1], U[1] * u + p, u * H};
@@ -282,24 +315,26 @@ __device__ inline void collide_1d(const double* f, const double U[3], double gm1
     for (int k = 0; k < 3; ++k) {
         double q = w * U[k];
         double g = G[k] * c2lam;
-        fs[0 * 3 + k] = om1 * f[0 * 3 + k] + omega * (q - g);
+        fs[0 * 3 + k] = relax(om1, f[0 * 3 + k], omega, q - g);
         if (Q == 2) {
-            fs[1 * 3 + k] = om1 * f[1 * 3 + k] + omega * (q + g);
+            fs[1 * 3 + k] = relax(om1, f[1 * 3 + k], omega, q + g);
         } else {
-            fs[1 * 3 + k] = om1 * f[1 * 3 + k] + omega * q;
-            fs[2 * 3 + k] = om1 * f[2 * 3 + k] + omega * (q + g);
+            fs[1 * 3 + k] = relax(om1, f[1 * 3 + k], omega, q);
+            fs[2 * 3 + k] = relax(om1, f[2 * 3 + k], omega, q + g);
         }
     }
 }
 
 template <int Q>
 __device__ inline void moments_1d(const double* f, double U[3]) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < 3; ++k) U[k] = (Q == 2) ? (f[k] + f[3 + k]) : ((f[k] + f[6 + k]) + f[3 + k]);
 }
 
 // Local bound max(|u-a|, |u|, |u+a|) = |u| + a for a >= 0 (Sec. II.C).
 __device__ inline bool bound_1d(const double U[3], double gamma, double* lam) {
+#pragma clang fp contract(off)
     double u, p, H;
     euler1(U, gamma - 1.0, &u, &p, &H);
     bool ok = (U[0] > 0.0) && (p > 0.0) && isfinite(U[0]) && isfinite(U[1]) && isfinite(U[2]) &&

@@ -30,24 +30,75 @@ struct Step2DArgs {
 
 // Fused two-step launches (2D Euler): the second step's lattice speed
 // depends on the global bound of the first step's states, which is known only
-// when the launch has ended.  A launch that guesses it (lambda*_{n+1} taken
-// equal to lambda*_n) or that cannot yet know whether its first step was
-// admissible is tentative: the next launch accepts its result when the
-// recorded bound equals the guess bit for bit and the first step was
-// admissible, else falls back to the state before it.  The record lives in
+// when the launch has ended.  A launch that guesses it, or that cannot yet
+// know whether its first step was admissible, is tentative: the next launch
+// accepts its result when the recorded bound equals the guess bit for bit
+// and the first step was admissible, else falls back to the state before it.
+// The guess is the predicted bound when the previous launch left one (see
+// PredHeader), else lambda*_n while the bound has been repeating (trust > 0);
+// at trust 0 a launch instead reduces the bound of f^{n+1} alone (nothing
+// stored) and the next launch takes two steps with it.  The record lives in
 // slot (p+1) & 1 beside the time state; the first step's bound and flag are
-// slotted like DevState::lam and DevState::bad.  When the bound has stopped
-// repeating (trust 0), a launch instead reduces the bound of f^{n+1} alone
-// (nothing stored) and the next launch takes two steps with it.
+// slotted like DevState::lam and DevState::bad.
 struct PairSlot {
     double t_base;              // state before the launch's steps
     long long n_base;
     int cur_base;
     int tentative;              // 1: the next launch must check this launch's guess
-    unsigned long long guess;   // bits of lambda*_n (the guessed lambda*_{n+1})
+    unsigned long long guess;   // bits of the guessed lambda*_{n+1}
+    unsigned long long guess_base;  // bits of lambda*_n of the state before the launch
     int known;                  // 1: this launch only reduced the bound of f^{n+1} (no step)
     int trust;                  // 0..3: +1 when a check finds the bound repeated, -1 when
                                 // not; new pairs guess while > 0
+    int pred_valid;             // 1: `pred` is the prediction of the bound of the state after
+    int predicted;              //    the next launch's first step; 1: this launch's guess was
+                                //    such a prediction
+    unsigned long long pred;    // bits of the predicted bound (max over the evaluated cells)
+};
+
+// The prediction of lambda*_{n+3} after a pair n -> n+2: the launch lists
+// the cells whose bound of U^{n+2} lies within CAND_REL of the largest its
+// wave has seen (and above a floor CAND_REL below lambda*_{n+1}), leaving out
+// the inside of flat regions (a cell whose left, right and upper neighbours
+// have the same bound); once lambda*_{n+2} is known, a small kernel evaluates
+// the exact bound of the next step's states on the 3 x 3 cells around each
+// candidate (a cell's next state pulls from its diagonal neighbours) and
+// takes the largest.  Nothing assures that the maximum lies there: the
+// prediction is only a guess, which the launch after the next one checks bit
+// for bit like any other.
+static constexpr double CAND_REL = 1e-4;
+// Candidates one launch may leave (more: no prediction).
+static constexpr int PRED_CAP = 16384;
+
+// A candidate cell and its bound of U^{n+2}.
+struct PredCand {
+    long long cell;  // y*nx + x
+    double l;
+};
+
+// What a fused launch with candidates leaves for the prediction kernel that
+// follows it; two of them, by launch parity (a launch fills its own and
+// clears the other for the launch after it).
+struct PredHeader {
+    int armed;                  // 1: the launch was a two-step pair that listed candidates
+    int cur_out;                // buffer holding its f^{n+2}
+    unsigned int ncand;         // candidates written (may exceed PRED_CAP: overflow)
+    unsigned int pad;
+    double t2;                  // time after the launch's two steps
+};
+
+// Counters of the fused launches since the context's initialisation.
+enum : int {
+    PST_PAIRS = 0,        // two-step launches whose result stood
+    PST_REJECTED,         // two-step launches rolled back
+    PST_BOUND_ONLY,       // launches that only reduced the bound of f^{n+1}
+    PST_SINGLE,           // one-step launches
+    PST_PREDICTED,        // predictions left for the next launch
+    PST_PRED_HIT,         // predicted guesses that stood
+    PST_PRED_MISS,        // predicted guesses rolled back
+    PST_EVALUATED,        // cells whose bound the prediction kernel evaluated
+    PST_PRED_NONE,        // pairs with candidates but no prediction (overflow, none)
+    PST_COUNT
 };
 
 struct PairState {
@@ -56,6 +107,8 @@ struct PairState {
     unsigned int bad1[3];        // the first step met a non-physical state
     unsigned int pad;
     long long n_limit;           // step count at which the current call stops
+    PredHeader pred[2];
+    unsigned long long stat[PST_COUNT];
 };
 
 struct Pair2DArgs {
@@ -75,6 +128,8 @@ struct Pair2DArgs {
     double* tape0;        // taped form: U^n of the launch's first step and U^{n+1} of its
     double* tape1;        // second ([4][ny][nx] each; a one-step launch writes tape0 only)
     long long plane;      // nx * ny
+    PredCand* cand;       // candidate list (PRED_CAP entries) of the per-step prediction,
+                          // or null: no prediction
 };
 
 // 1D population layouts: planar, element (p, x) at p*nx + x, or blocked,
@@ -274,11 +329,16 @@ bool step2d_wpb_supported(int wpb);
 // Fused two-step launches (same waves-per-workgroup choices as the step).
 hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, bool tape, int max_blocks,
                               hipStream_t s);
-int step2d_pair_blocks_per_cu(int wpb);
+int step2d_pair_blocks_per_cu(int wpb, bool cand = false);
 // Start of a call of max_steps fused launches: clears the first-step
 // accumulators and records the step count to stop at.
 hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long long max_steps,
                                hipStream_t s);
+// After fused launch a.launch: evaluate its candidates and leave the
+// prediction (or none) for the next launch.
+hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s);
+// Clear the fused launches' record and counters (context initialisation).
+hipError_t launch_pair_reset(PairState* ps, hipStream_t s);
 hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
 hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);
 int persistent1d_max_cells(int Q, size_t lds_limit);

@@ -105,6 +105,11 @@ struct PairGeom {
     double* tape0;   // TAPE: U^n and U^{n+1}, element (k, y, x) at k*tape_ps + y*nx + x
     double* tape1;
     long long tape_ps;
+    // CAND: the floor of the candidates' bounds, this launch's header and
+    // where candidates go
+    double t0;
+    PredHeader* ph;
+    PredCand* cand;
 };
 
 __device__ inline void load_row(double v[16], const double* __restrict__ fin, long long ps,
@@ -133,10 +138,11 @@ __device__ inline void tape_row(double* tape, long long tape_ps, int nx, int j, 
     for (int k = 0; k < 4; ++k) store_row(row + k * tape_ps, nx * 8, own ? voff : 0x7fffffff, U[k]);
 }
 
-template <int WPB, bool TWO, bool TAPE>
+template <int WPB, bool TWO, bool TAPE, bool CAND = false>
 __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0, int y1, int lane,
                                            double& lm1, bool& bad1, double& lm2, bool& bad2,
                                            bool store = true) {
+    static_assert(!CAND || (TWO && !TAPE), "candidates ride on plain two-step launches");
     const int nx = g.nx, ny = g.ny;
     const bool px = g.bc[0] == BC_PERIODIC, py = g.bc[2] == BC_PERIODIC;
     const double gm1 = g.gamma - 1.0;
@@ -160,6 +166,42 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
     double P3[4], P4[4], Q3[4], Q4[4];  // second step: upward hops of rows q-1, q-2
     double U[4];
     Hops h;
+
+    // CAND: candidates for the prediction of lambda*_{n+3} (see PredCand).
+    // l: the bound of U^{n+2} of this lane's cell of row o2 (-1 outside the
+    // tile); the wave's running threshold, largest bound seen, and the bound
+    // of the row above in this lane.
+    double thr = CAND ? g.t0 : 0.0, wmax = 0.0, lup = -1.0;
+    auto candidates = [&](double l, int o2) {
+        if (__any(l > thr)) {
+            const double rowmax = wave_max(l);
+            const bool record = rowmax > wmax;
+            wmax = fmax(wmax, rowmax);
+            thr = fmax(g.t0, wmax * (1.0 - CAND_REL));
+            // the first lane holding a new largest bound always goes in
+            const unsigned long long rec = __ballot(record && l == rowmax);
+            const int rec_lane = rec ? __ffsll((long long)rec) - 1 : -1;
+            // inside a flat region (a neighbour outside the tile counts as equal)
+            const double ll = lane_from_left(l), lr = lane_from_right(l);
+            const bool flat = (ll == l || ll < 0.0) && (lr == l || lr < 0.0) &&
+                              (lup == l || lup < 0.0);
+            const bool emit = l > thr && (!flat || lane == rec_lane);
+            const unsigned long long m = __ballot(emit);
+            if (m) {
+                unsigned base = 0;
+                if (lane == 0) base = atomicAdd(&g.ph->ncand, (unsigned)__popcll(m));
+                base = __shfl(base, 0, 64);
+                if (emit) {
+                    const unsigned idx = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+                    if (idx < (unsigned)PRED_CAP) {
+                        g.cand[idx].cell = (long long)o2 * nx + x;
+                        g.cand[idx].l = l;
+                    }
+                }
+            }
+        }
+        lup = l;
+    };
 
     // Row r of f^n (in cur) completes row r-1 of f^{n+1} and, with TWO, row
     // r-2 of f^{n+2}; row r+1 is loaded into nxt first, so that it is in
@@ -218,7 +260,7 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
             // unconditional (an out-of-range offset is dropped by the buffer
             // range check), so the wait for the next row's loads never has
             // to cover this row's stores.
-            const bool row_out = q > y0;
+            const bool row_out = q > y0 && q - 1 < y1;
             const int o2 = row_out ? q - 1 : y0;
             // at a clamped top, row ny of f^{n+1} is row ny-1 again: its
             // downward hops were kept in P at q = ny-1
@@ -231,7 +273,9 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
                 g2[2 * 4 + k] = Q3[k];
                 g2[3 * 4 + k] = Q4[k];
             }
-            wall_images(g2, whi && o2 == ny - 1, wlo && o2 == 0, wxlo, wxhi);
+            // (the wall rows by the row's own index: the filter also reads the
+            // halo rows y0-1 and y1, which are not stored)
+            wall_images(g2, whi && q - 1 == ny - 1, wlo && q - 1 == 0, wxlo, wxhi);
             store_full_row(g.fout + (long long)o2 * g.rs, g.ps, row_bytes,
                            row_out ? voff : 0x7fffffff, g2);
             double U2[4], l2;
@@ -240,17 +284,19 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
             const bool own2 = out_lane && row_out;
             bad2 |= own2 && !ok2;
             lm2 = fmax(lm2, own2 ? l2 : 0.0);
-        }
-        // at a clamped bottom, row -1 of f^{n+1} is row 0 again; at a clamped
-        // top, keep row ny-1's downward hops for the virtual row ny
-        const bool lo_edge = clamp_lo && q == 0;
-        const bool hi_edge = clamp_hi && q == ny - 1;
+            // at a clamped bottom, row -1 of f^{n+1} is row 0 again; at a
+            // clamped top, keep row ny-1's downward hops for the virtual row
+            // ny (the hops are dead after this, before the filter's work)
+            const bool lo_edge = clamp_lo && q == 0;
+            const bool hi_edge = clamp_hi && q == ny - 1;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            Q3[k] = lo_edge ? h2.u2[k] : P3[k];
-            Q4[k] = lo_edge ? h2.u3[k] : P4[k];
-            P3[k] = hi_edge ? h2.d0[k] : h2.u2[k];
-            P4[k] = hi_edge ? h2.d1[k] : h2.u3[k];
+            for (int k = 0; k < 4; ++k) {
+                Q3[k] = lo_edge ? h2.u2[k] : P3[k];
+                Q4[k] = lo_edge ? h2.u3[k] : P4[k];
+                P3[k] = hi_edge ? h2.d0[k] : h2.u2[k];
+                P4[k] = hi_edge ? h2.d1[k] : h2.u3[k];
+            }
+            if (CAND) candidates(own2 && ok2 ? l2 : -1.0, q - 1);
         }
     };
 
@@ -315,13 +361,20 @@ struct PairCtl {
     bool tentative;     // the result waits for the next launch's check
     bool bound;         // this launch only reduces the bound of f^{n+1}
     bool accepted_bad;  // the previous launch's pair stands, with a non-physical f^{n+2}
+    bool predicted;     // this launch's guess is the predicted bound
+    bool cand;          // this launch lists candidates for the prediction of lambda*_{n+3}
     int trust;          // saturating count of repeated bounds at the last checks (0..3)
+    int check;          // outcome of the check of the previous launch (for the counters):
+                        // 0 none, 1 accepted, 2 predicted and accepted, 3 rejected,
+                        // 4 predicted and rejected
     int cur;
     long long n;
     double t, lam_used;
     unsigned long long lstar;  // bits of lambda*_n (the bound of the current state)
+    unsigned long long guess;  // bits of the lambda*_{n+1} a tentative pair takes
     unsigned bad;
     double lam1, t1, lam2, t2;
+    double t0;          // floor of the candidates' bounds
 };
 
 __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
@@ -335,12 +388,17 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
     bool know_next = false, force_single = false;
     unsigned long long next = 0ull;
     int trust = q.trust;
+    // the previous launch left a prediction for the state it produced
+    bool pred_ok = q.pred_valid != 0 && q.pred != 0ull;
     c.accepted_bad = false;
+    c.check = 0;
     if (q.tentative) {
         const unsigned long long m1 = ps->lam1[ls.lr];
         const bool b1 = ps->bad1[ls.lr] != 0u;
-        const bool ok = !b1 && (a.lam_mode != LAM_PER_STEP || m1 == q.guess);
-        if (!b1) trust = m1 == q.guess ? min(trust + 1, 3) : max(trust - 1, 0);
+        const bool exact = m1 == q.guess;
+        const bool ok = !b1 && (a.lam_mode != LAM_PER_STEP || exact);
+        if (!b1 && !q.predicted) trust = exact ? min(trust + 1, 3) : max(trust - 1, 0);
+        c.check = ok ? (q.predicted ? 2 : 1) : (q.predicted ? 4 : 3);
         if (ok) {
             c.accepted_bad = bad != 0u;
         } else {
@@ -348,11 +406,12 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
             s.t = q.t_base;
             s.n = q.n_base;
             s.cur = q.cur_base;
-            lstar = q.guess;
+            lstar = q.guess_base;
             bad = 0u;
             force_single = b1;
             know_next = !b1;
             next = m1;
+            pred_ok = false;
         }
     } else if (q.known) {
         // the previous launch reduced the bound of f^{n+1} of this state
@@ -362,6 +421,7 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
         know_next = !b1;
         next = m1;
         if (!b1) trust = m1 == lstar ? min(trust + 1, 3) : max(trust - 1, 0);
+        pred_ok = false;
     }
     c.cur = s.cur;
     c.n = s.n;
@@ -375,25 +435,31 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
     step_size(a.lam_mode, from_bits(lstar > lbc ? lstar : lbc), st->lam_fixed, a.dx, a.cfl, s.t,
               a.t_end, c.lam1, c.t1);
     c.two = c.active && !force_single && c.t1 < a.t_end && s.n + 2 <= n_limit;
-    // a new pair with per-step speeds: guess the bound while it has been
-    // repeating, else reduce it first
-    c.bound = c.two && !know_next && a.lam_mode == LAM_PER_STEP && trust == 0;
+    // a new pair with per-step speeds: take the predicted bound, else guess
+    // the current one while it has been repeating, else reduce it first
+    const bool per_step = a.lam_mode == LAM_PER_STEP;
+    c.predicted = c.two && !know_next && per_step && pred_ok;
+    c.bound = c.two && !know_next && per_step && !c.predicted && trust == 0;
     if (c.bound) c.two = false;
     c.tentative = c.two && !know_next;
-    if (a.last && (c.tentative || c.bound)) c.two = c.tentative = c.bound = false;
+    if (a.last && (c.tentative || c.bound)) c.two = c.tentative = c.bound = c.predicted = false;
     c.trust = trust;
     c.lam2 = c.lam1;
     c.t2 = c.t1;
-    if (c.two) {
-        const unsigned long long l2 = know_next ? next : lstar;
+    c.guess = c.predicted ? q.pred : lstar;
+    const unsigned long long l2 = know_next ? next : c.guess;
+    if (c.two)
         step_size(a.lam_mode, from_bits(l2 > lbc ? l2 : lbc), st->lam_fixed, a.dx, a.cfl, c.t1,
                   a.t_end, c.lam2, c.t2);
-    }
+    // candidates for the prediction of lambda*_{n+3}: bounds of U^{n+2} from
+    // CAND_REL below lambda*_{n+1} up
+    c.cand = c.two && per_step && a.cand != nullptr && c.t2 < a.t_end;
+    c.t0 = c.cand ? from_bits(l2) * (1.0 - CAND_REL) : 0.0;
     return c;
 }
 
 // Block 0, thread 0: the time state after this launch and its pair record;
-// clears the accumulators of launch p+2.
+// clears the accumulators of launch p+2; arms the prediction kernel.
 __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const PairCtl& c) {
     DevState* st = a.st;
     PairState* ps = a.pst;
@@ -403,10 +469,14 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
     q.t_base = c.t;
     q.n_base = c.n;
     q.cur_base = c.cur;
-    q.guess = c.lstar;
+    q.guess = c.guess;
+    q.guess_base = c.lstar;
     q.tentative = 0;
     q.known = 0;
     q.trust = c.trust;
+    q.pred_valid = 0;
+    q.predicted = c.predicted ? 1 : 0;
+    q.pred = 0ull;
     if (!c.active) {
         s.t = c.t;
         s.n = c.n;
@@ -442,6 +512,26 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
     st->bad[ls.lz] = 0u;
     ps->lam1[ls.lz] = 0ull;
     ps->bad1[ls.lz] = 0u;
+    // this launch's candidate header (its candidate count was cleared by the
+    // launch before) and the next launch's, whose last user, the prediction
+    // after the launch before, has finished
+    PredHeader& h = ps->pred[a.launch & 1];
+    h.armed = c.cand ? 1 : 0;
+    h.cur_out = c.cur ^ 1;
+    h.t2 = c.t2;
+    PredHeader& hn = ps->pred[(a.launch + 1) & 1];
+    hn.armed = 0;
+    hn.ncand = 0u;
+    // counters
+    if (c.check >= 3) ps->stat[PST_REJECTED] += 1;
+    else if (c.check > 0) ps->stat[PST_PAIRS] += 1;
+    if (c.check == 2) ps->stat[PST_PRED_HIT] += 1;
+    if (c.check == 4) ps->stat[PST_PRED_MISS] += 1;
+    if (c.active) {
+        if (c.bound) ps->stat[PST_BOUND_ONLY] += 1;
+        else if (!c.two) ps->stat[PST_SINGLE] += 1;
+        else if (!c.tentative) ps->stat[PST_PAIRS] += 1;
+    }
     if (c.accepted_bad) {
         atomicOr(&st->status, 1u);
         atomicMin(&st->fail_step, (unsigned long long)c.n);
@@ -450,7 +540,7 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
 
 }  // namespace
 
-template <int WPB, bool TAPE>
+template <int WPB, bool TAPE, bool CAND>
 __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     const LaunchSlots ls = slots_for(a.launch);
     const PairCtl c = pair_control(a, ls);
@@ -476,6 +566,9 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     g.tape0 = a.tape0;
     g.tape1 = a.tape1;
     g.tape_ps = a.plane;
+    g.t0 = c.t0;
+    g.ph = &a.pst->pred[a.launch & 1];
+    g.cand = a.cand;
     const int total_waves = gridDim.x * WPB;
     const int ny = a.ny;
 
@@ -487,8 +580,14 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
         const int seg = tile / a.nstrips;
         const int y0 = (int)(((long long)seg * ny) / a.nseg);
         const int y1 = (int)(((long long)(seg + 1) * ny) / a.nseg);
-        if (c.two) march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
-        else march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2, !c.bound);
+        if (c.two) {
+            if (CAND && c.cand)
+                march_pair<WPB, true, false, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+            else
+                march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+        } else {
+            march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2, !c.bound);
+        }
     }
 
     const bool per_step = a.lam_mode == LAM_PER_STEP;
@@ -516,6 +615,85 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
             if (lane == 0) publish_max(&a.st->lam[ls.la], w1);
         }
         if (__any(bad1) && lane == 0) publish_bad(a.st, ls, c.n + 1);
+    }
+}
+
+// The prediction after fused launch a.launch: the exact bound of the state
+// after the next launch's first step on the 3 x 3 cells around every
+// candidate the launch listed whose bound of U^{n+2} is within CAND_REL of
+// lambda*_{n+2}, by the first step's own arithmetic (f^{n+2} of the cell's
+// four pull sources, their collision at the now known speed of step n+2,
+// the pulls, walls, moments, bound: the same device functions, so the same
+// bits), maxed into the pair record the next launch reads.  None when the
+// launch listed no candidates or more than the list holds, or met a
+// non-physical state.  PRED_BLOCKS workgroups stride over (candidate,
+// neighbour) pairs; workgroup 0 also sets the record's validity and counters.
+static constexpr int PRED_BLOCKS = 64;
+
+__global__ __launch_bounds__(256) void pair_predict_kernel(Pair2DArgs a) {
+    const LaunchSlots ls = slots_for(a.launch);
+    PairState* ps = a.pst;
+    const PredHeader* h = &ps->pred[a.launch & 1];
+    const int tid = threadIdx.x;
+    const unsigned ncand = h->ncand;
+    const bool ok = h->armed != 0 && ncand > 0u && ncand <= (unsigned)PRED_CAP &&
+                    a.st->bad[ls.la] == 0u;
+    if (blockIdx.x == 0 && tid == 0) {
+        ps->q[ls.sw].pred_valid = ok ? 1 : 0;
+        if (h->armed) ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
+    }
+    if (!ok) return;
+    const unsigned long long lb = a.st->lam[ls.la];
+    const unsigned long long lbc = a.st->lam_bc;
+    const double lstar = from_bits(lb > lbc ? lb : lbc);
+    const double floor_l = from_bits(lb) * (1.0 - CAND_REL);
+    double lam, tn;
+    step_size(LAM_PER_STEP, lstar, 0.0, a.dx, a.cfl, h->t2, a.t_end, lam, tn);
+    const double c4lam = 1.0 / (4.0 * lam);
+    const double gm1 = a.gamma - 1.0;
+    const double* fin = h->cur_out ? a.f1 : a.f0;
+    const int nx = a.nx, ny = a.ny;
+    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
+    const int sxs[4] = {-1, 1, 1, -1}, sys[4] = {-1, -1, 1, 1};
+    double best = 0.0;
+    unsigned evaluated = 0;
+    const unsigned work = ncand * 9u;
+    for (unsigned i = blockIdx.x * blockDim.x + tid; i < work; i += gridDim.x * blockDim.x) {
+        const PredCand e = a.cand[i / 9u];
+        if (!(e.l >= floor_l)) continue;
+        const int cy = (int)(e.cell / nx), cx = (int)(e.cell % nx);
+        int x = cx + (int)(i % 3u) - 1, y = cy + (int)((i / 3u) % 3u) - 1;
+        if (px) x = map_index(x, nx, true);
+        if (py) y = map_index(y, ny, true);
+        if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
+        ++evaluated;
+        double g1[16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int xs = map_index(x - sxs[j], nx, px), ys = map_index(y - sys[j], ny, py);
+            double f[16], U[4], fs[16];
+            const double* row = fin + (long long)ys * a.rs;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) f[p] = row[p * a.ps + xs];
+            moments_d2q4(f, U);
+            const Euler2 eu = euler2(U, gm1);
+            collide_d2q4(f, U, eu, c4lam, a.omega, fs);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) g1[j * 4 + k] = fs[j * 4 + k];
+        }
+        wall_images(g1, a.bc[3] == BC_WALL && y == ny - 1, a.bc[2] == BC_WALL && y == 0,
+                    a.bc[0] == BC_WALL && x == 0, a.bc[1] == BC_WALL && x == nx - 1);
+        double U1[4], l1;
+        moments_d2q4(g1, U1);
+        if (bound_d2q4(U1, a.gamma, &l1)) best = fmax(best, l1);
+    }
+    best = wave_max(best);
+    unsigned cnt = evaluated;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((tid & 63) == 0) {
+        if (best > 0.0) publish_max(&ps->q[ls.sw].pred, best);
+        if (cnt) atomicAdd(&ps->stat[PST_EVALUATED], (unsigned long long)cnt);
     }
 }
 
@@ -575,14 +753,35 @@ __global__ void pair_prepare_kernel(PairState* ps, const DevState* st, int slot,
         ps->q[i].cur_base = 0;
         ps->q[i].tentative = 0;
         ps->q[i].guess = 0ull;
+        ps->q[i].guess_base = 0ull;
         ps->q[i].known = 0;
         ps->q[i].trust = 3;  // start a call by guessing
+        ps->q[i].pred_valid = 0;
+        ps->q[i].predicted = 0;
+        ps->q[i].pred = 0ull;
     }
     for (int i = 0; i < 3; ++i) {
         ps->lam1[i] = 0ull;
         ps->bad1[i] = 0u;
     }
+    for (int i = 0; i < 2; ++i) {
+        ps->pred[i].armed = 0;
+        ps->pred[i].ncand = 0u;
+    }
     ps->n_limit = st->s[slot].n + max_steps;
+}
+
+__global__ void pair_reset_kernel(PairState* ps) {
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < PST_COUNT; ++i) ps->stat[i] = 0ull;
+    for (int i = 0; i < 2; ++i) {
+        ps->pred[i].armed = 0;
+        ps->pred[i].ncand = 0u;
+        ps->q[i].tentative = 0;
+        ps->q[i].known = 0;
+        ps->q[i].pred_valid = 0;
+        ps->q[i].predicted = 0;
+    }
 }
 
 hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long long max_steps,
@@ -591,24 +790,49 @@ hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long
     return hipGetLastError();
 }
 
-template <int WPB>
-static hipError_t launch_pair_w(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
-    int nblocks = (a.ntiles + WPB - 1) / WPB;
-    if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    if (tape) hipLaunchKernelGGL((step2d_pair<WPB, true>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
-    else hipLaunchKernelGGL((step2d_pair<WPB, false>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+hipError_t launch_pair_reset(PairState* ps, hipStream_t s) {
+    hipLaunchKernelGGL(pair_reset_kernel, dim3(1), dim3(64), 0, s, ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(pair_predict_kernel, dim3(PRED_BLOCKS), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <int WPB>
-static int pair_blocks_w() {
+static hipError_t launch_pair_w(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
+    int nblocks = (a.ntiles + WPB - 1) / WPB;
+    if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
+    // per-step speeds with a candidate list: the form that lists candidates
+    const bool cand = a.cand != nullptr && a.lam_mode == LAM_PER_STEP && !tape;
+    if (cand)
+        hipLaunchKernelGGL((step2d_pair<WPB, false, true>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    else if (tape)
+        hipLaunchKernelGGL((step2d_pair<WPB, true, false>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    else
+        hipLaunchKernelGGL((step2d_pair<WPB, false, false>), dim3(nblocks), dim3(64 * WPB), 0, s,
+                           a);
+    return hipGetLastError();
+}
+
+template <int WPB>
+static int pair_blocks_w(bool cand) {
     int n = 0, m = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false>,
-                                                                64 * WPB, 0);
-    hipError_t f = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, step2d_pair<WPB, true>,
-                                                                64 * WPB, 0);
+    hipError_t e, f;
+    if (cand) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false, true>,
+                                                         64 * WPB, 0);
+        f = e;
+        m = n;
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false, false>,
+                                                         64 * WPB, 0);
+        f = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, step2d_pair<WPB, true, false>,
+                                                         64 * WPB, 0);
+    }
     if (e != hipSuccess || f != hipSuccess) return 1;
-    n = n < m ? n : m;  // one persistent grid size serves both forms
+    n = n < m ? n : m;  // one persistent grid size serves both plain forms
     return n > 0 ? n : 1;
 }
 
@@ -623,9 +847,9 @@ hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, bool tape, int max_b
     return hipErrorInvalidValue;
 }
 
-int step2d_pair_blocks_per_cu(int wpb) {
+int step2d_pair_blocks_per_cu(int wpb, bool cand) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return pair_blocks_w<W>();
+    if (wpb == W) return pair_blocks_w<W>(cand);
     LBRS_PAIR_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return 1;

@@ -40,7 +40,7 @@ EXPORTS = (
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
     "lbrs_destroy", "lbrs_set_fusion", "lbrs_batch2d_set_fusion", "lbrs_adjoint_step2",
     "lbrs_step_tape2", "lbrs_forward_taped", "lbrs_backward_taped", "lbrs_cfl_max",
-    "lbrs_run_noalloc",
+    "lbrs_run_noalloc", "lbrs_pair_stats",
 )
 
 
@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_strerror": (ctypes.c_char_p, [i]),
         "lbrs_cfl_max": (d, [i]),
         "lbrs_run_noalloc": (i, [P, vp, vp, vp, i, d, i, vp, vp, vp]),
+        "lbrs_pair_stats": (i, [vp, ctypes.POINTER(ll), i]),
         "lbrs_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -505,6 +506,16 @@ class Sim:
 
     def state(self):
         return lbrs_get_state(self.ctx)
+
+    PAIR_STATS = ("pairs", "rejected", "bound_only", "single", "predicted", "pred_hit",
+                  "pred_miss", "evaluated", "pred_none")
+
+    def pair_stats(self) -> dict:
+        """Counters of the fused launches since init (lbrs_pair_stats)."""
+        n = len(self.PAIR_STATS)
+        out = (ctypes.c_longlong * n)()
+        _check(load_library().lbrs_pair_stats(self.ctx, out, n), "lbrs_pair_stats")
+        return dict(zip(self.PAIR_STATS, list(out)))
 
     def moments(self) -> torch.Tensor:
         U = torch.empty(self.u_shape, dtype=torch.float64, device=self.device)

@@ -35,7 +35,10 @@ def test_every_declared_symbol_is_exported(lib):
 def test_query_sizes_and_validation(lib):
     p = lbrs.make_params(lbrs.LBRS_D2Q4, 4096, 4096)
     f, u, s = lbrs.lbrs_query_sizes(p)
-    assert f == 16 * 8 * 4096 * 4096 and u == 4 * 8 * 4096 * 4096 and 0 < s <= 4096
+    # scratch: the time state, the fused launches' record and the prediction's
+    # candidate list (16384 entries of 16 B)
+    assert f == 16 * 8 * 4096 * 4096 and u == 4 * 8 * 4096 * 4096
+    assert 16384 * 16 < s <= 16384 * 16 + 4096
     p = lbrs.make_params(lbrs.LBRS_D1Q3, 400)
     f, u, s = lbrs.lbrs_query_sizes(p)
     assert f == 9 * 8 * 400 and u == 3 * 8 * 400

@@ -95,6 +95,55 @@ def test_riemann_256_to_end(omega):
     _compare(w, t_end=0.3, omega=omega, name=f"pair riemann 256 w{omega}")
 
 
+def _oracle_omp_run(P, U0, **kw):
+    """The oracle's OpenMP build (cells in parallel; bitwise the serial
+    build's results) for the large whole runs."""
+    oracle.use("omp")
+    try:
+        return oracle.run(P, U0, **kw)
+    finally:
+        oracle.use("serial")
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_riemann_to_end_large(n):
+    """The benchmark's problem to t = 0.3 at 512^2 and 1024^2, fused launches
+    with per-step speeds in the benchmark's row-interleaved layout.  The bound
+    changes at nearly every step after the first few hundred, so guesses are
+    rejected, bounds reduced alone and predictions taken along the way.  Two
+    GPU runs: one call for the whole run (every cell at the end), and calls of
+    37 steps (t and lambda after every call against the oracle's sequence, so
+    a wrong dt anywhere shows in t)."""
+    w = wl.riemann2d(n)
+    P = oracle_problem(w)
+    ref = _oracle_omp_run(P, oracle.prim_to_cons(P, w.W), t_end=0.3)
+    assert ref.status == 0 and ref.t == 0.3
+    cum = np.cumsum(ref.dt)
+    for chunk in (None, 37):
+        sim = _fused(w, layout=1)
+        done = 0
+        while done < ref.nsteps:
+            k = ref.nsteps + 5 if chunk is None else min(chunk, ref.nsteps - done)
+            sim.step(k, 0.3)
+            done = min(done + k, ref.nsteps)
+            st = sim.state()
+            assert st["rc"] == 0 and st["nsteps"] == done
+            assert st["t"] == pytest.approx(cum[done - 1], rel=1e-12, abs=0), done
+            assert st["lambda"] == pytest.approx(ref.lam[done - 1], rel=1e-12), done
+        stats = sim.pair_stats()
+        U = sim.moments().cpu().numpy()
+        sim.close()
+        err = max_abs(U, ref.U)
+        report(f"pair riemann {n} to end, calls of {chunk or 'all'}", steps=st["nsteps"],
+               oracle_steps=ref.nsteps, t=st["t"], err=err, **stats)
+        assert st["t"] == ref.t
+        assert err <= TOL, err
+        # the path of the whole run went through checked guesses
+        assert stats["rejected"] + stats["bound_only"] + stats["pred_hit"] > 0
+        # every step accounted for: pairs count two, the others one
+        assert 2 * stats["pairs"] + stats["single"] == ref.nsteps
+
+
 @pytest.mark.parametrize("sides", [(1, 1, 1, 1), (1, 1, 0, 0), (0, 0, 1, 1)])
 def test_periodic(sides):
     w = wl.fourier_modes(130, seed=3)
