@@ -269,7 +269,7 @@ def _time_ms(fn, reps=1):
     return e0.elapsed_time(e1) / reps
 
 
-def adjoint_2d(n=2048, steps=2000, k=50):
+def adjoint_2d(n=2048, steps=2000, k=50, steps_only=False):
     """Adjoint configuration (2048^2 periodic acoustic pulse, frozen lattice
     speed, 2000 steps, J over [0.7,0.8]^2): time of a plain step, of a step
     writing the U^n tape, of an adjoint step, of the whole sqrt(T)
@@ -302,6 +302,11 @@ def adjoint_2d(n=2048, steps=2000, k=50):
                              for _ in range(k2)]) / (2 * k2)
     if best["fuse"] == 1:
         tap2, adj2 = tap, adj
+    if steps_only:  # the per-step figures alone (profiling)
+        run.close()
+        return {"n": n, "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap2, 4),
+                "adjoint_step_ms": round(adj2, 4), "single_forward_step_ms": round(fwd1, 4),
+                "steps_per_launch": best["fuse"], "waves_per_block": best["wpb"]}
     r = rho0.clone().requires_grad_(True)
 
     def grad():
@@ -830,10 +835,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint figures reported beside the main value")
-    ap.add_argument("--only", choices=["adjoint", "batch1d", "batch1d_run", "batch2d", "batchgrad",
-                                       "dirichlet", "scalar", "euler1d", "slab", "bodies", "sod"],
+    ap.add_argument("--only", choices=["adjoint", "adjoint_steps", "batch1d", "batch1d_run",
+                                       "batch2d", "batchgrad", "dirichlet", "scalar", "euler1d",
+                                       "slab", "bodies", "sod"],
                     default=None,
                     help="run only one of the secondary measurements and print it (profiling)")
+    ap.add_argument("--mid", type=int, default=-1,
+                    help="first step of the timed window (default: the middle of a whole run, "
+                         "which is then run first); with --rows >= 0 nothing else runs before "
+                         "the window (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain copy of the populations (lbrs_get_f: "
                          "16 planes read and written) as a known-size reference for counters")
@@ -850,7 +860,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.only:
-        fn = {"adjoint": adjoint_2d, "batch1d": batched_1d, "batch2d": batched_2d,
+        fn = {"adjoint": adjoint_2d, "adjoint_steps": lambda: adjoint_2d(steps_only=True),
+              "batch1d": batched_1d, "batch2d": batched_2d,
               "batchgrad": batched_grad_2d, "dirichlet": dirichlet_2d,
               "scalar": scalar_laws, "euler1d": euler_1d_long, "slab": slab_step,
               "bodies": bodies_2d,
@@ -905,9 +916,12 @@ def main():
     # in a default shape gives its step count, then the state at the window's
     # start is kept, and the tuner and every timed form start from it.
     default = dict(shape) if args.rows >= 0 else {"rows": 0, "wpb": 6, "alt": 0, "fuse": 2}
-    first = whole_run(default)
-    n_total = first["steps"]
-    mid = max(0, (n_total - args.warmup - args.steps) // 2)
+    if args.mid >= 0:
+        first, n_total, mid = None, None, args.mid
+    else:
+        first = whole_run(default)
+        n_total = first["steps"]
+        mid = max(0, (n_total - args.warmup - args.steps) // 2)
     sim.init(U0)
     use(default)
     if mid:
@@ -983,8 +997,15 @@ def main():
         if sh["fuse"] == 2:
             # what the window's launches did: pairs that stood, pairs rolled
             # back, bound-only passes, single steps, predictions of the next
-            # bound taken (exact / within tolerance) and missed
-            r["launch_counts"] = window_launches.get((sh["wpb"], sh["alt"]))
+            # bound made / standing / rolled back, cells evaluated for them;
+            # the launches that did work (the others exit at once) and their
+            # mean time, prediction kernels and gaps included
+            lc = window_launches.get((sh["wpb"], sh["alt"]))
+            r["launch_counts"] = lc
+            if lc:
+                active = lc["pairs"] + lc["rejected"] + lc["bound_only"] + lc["single"]
+                r["active_launches"] = active
+                r["avg_active_launch_ms"] = round(ms / max(active, 1), 5)
         return r
 
     ms_win, done = timed_window(shape, args.steps, args.warmup)
@@ -1022,7 +1043,7 @@ def main():
         "roofline": rf,
     }
     if not args.no_extras:
-        full = {"default_shape": dict(default, **first)}
+        full = {"default_shape": dict(default, **first)} if first else {}
         if single is not None:
             ms1, done1 = timed_window(single, args.steps, args.warmup)
             rec["single_step"] = {

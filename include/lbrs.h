@@ -238,14 +238,15 @@ int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda,
                    unsigned* status, long long* fail_step);
 
 /* Counters of the fused launches since lbrs_init (lbrs_set_fusion(c, 2)),
- * into counts[0 .. n-1] (n <= 9; missing ones 0): [0] two-step launches whose
+ * into counts[0 .. n-1] (n <= 11; missing ones 0): [0] two-step launches whose
  * result stood, [1] two-step launches rolled back (a guessed lambda*_{n+1}
  * that was wrong), [2] launches that only reduced the bound of f^{n+1},
  * [3] one-step launches, [4] predictions of the next launch's bound made,
  * [5] predicted bounds that stood, [6] predicted bounds rolled back,
  * [7] cells whose bound the predictions evaluated, [8] launches that listed
  * candidates but left no prediction (too many, none, or a non-physical
- * state).  With per-step lattice speeds a fused launch guesses the bound of
+ * state), [9] candidates listed, [10] launches whose candidates overflowed
+ * the list.  With per-step lattice speeds a fused launch guesses the bound of
  * the state after its first step (the prediction when the launch before left
  * one, else the current bound while it keeps repeating) and the next launch
  * checks the guess bit for bit, so the counters describe cost only: results

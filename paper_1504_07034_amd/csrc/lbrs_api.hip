@@ -228,7 +228,7 @@ static int ctx_setup(lbrs_ctx* c, const lbrs_params* p, const double* d_U0, doub
     const double* dir[4];
     for (int s = 0; s < 4; ++s) dir[s] = p->bc[s] == LBRS_BC_DIRICHLET ? p->dirichlet[s] : nullptr;
     hipError_t e = launch_reset(c->st, c->stream);
-    if (e == hipSuccess) e = launch_pair_reset(c->pst, c->stream);
+    if (e == hipSuccess) e = launch_pair_reset(c->pst, true, c->stream);
     if (e == hipSuccess)
         e = p->law == LBRS_LAW_SCALAR
                 ? launch_scalar_init(a, d_U0, d_f0, c->st, p->lambda_mode, p->lambda_user, p->cfl,
@@ -608,8 +608,11 @@ int lbrs_set_f(lbrs_ctx* c, const double* d_f, double t, long long n) {
     // the new state becomes launch 0: slot 0, buffer f0, bound in slot 0
     c->launches = 0;
     CellArgs a = cell_args(c);
-    return hip_status(launch_set_f(a, c->f0, c->f1, c->st, d_f, t, n,
-                                   c->P.lambda_mode == LBRS_LAMBDA_PER_STEP, c->stream));
+    hipError_t e = launch_set_f(a, c->f0, c->f1, c->st, d_f, t, n,
+                                c->P.lambda_mode == LBRS_LAMBDA_PER_STEP, c->stream);
+    // a prediction of the fused launches belonged to the old state
+    if (e == hipSuccess) e = launch_pair_reset(c->pst, false, c->stream);
+    return hip_status(e);
 }
 
 int lbrs_window_objective(lbrs_ctx* c, int ix0, int ix1, int iy0, int iy1, double* d_J,

@@ -56,16 +56,17 @@ struct PairSlot {
     unsigned long long pred;    // bits of the predicted bound (max over the evaluated cells)
 };
 
-// The prediction of lambda*_{n+3} after a pair n -> n+2: the launch lists
-// the cells whose bound of U^{n+2} lies within CAND_REL of the largest its
-// wave has seen (and above a floor CAND_REL below lambda*_{n+1}), leaving out
-// the inside of flat regions (a cell whose left, right and upper neighbours
-// have the same bound); once lambda*_{n+2} is known, a small kernel evaluates
-// the exact bound of the next step's states on the 3 x 3 cells around each
-// candidate (a cell's next state pulls from its diagonal neighbours) and
-// takes the largest.  Nothing assures that the maximum lies there: the
-// prediction is only a guess, which the launch after the next one checks bit
-// for bit like any other.
+// The prediction of lambda*_{n+3} after a pair n -> n+2 (or of lambda*_{n+2}
+// after a one-step launch, from U^{n+1}): the launch lists the cells whose
+// bound of U^{n+2} is a local maximum (no left, right, lower
+// or upper neighbour's is larger) within CAND_REL of the largest its wave has
+// seen and above a floor CAND_REL below lambda*_{n+1}, leaving out the inside
+// of flat regions (one cell per wave stands for a region at one value); once
+// lambda*_{n+2} is known, a small kernel evaluates the exact bound of the
+// next step's states on the 3 x 3 cells around each candidate (a cell's next
+// state pulls from its diagonal neighbours) and takes the largest.  Nothing
+// assures that the maximum lies there: the prediction is only a guess, which
+// the launch after the next one checks bit for bit like any other.
 static constexpr double CAND_REL = 1e-4;
 // Candidates one launch may leave (more: no prediction).
 static constexpr int PRED_CAP = 16384;
@@ -84,7 +85,7 @@ struct PredHeader {
     int cur_out;                // buffer holding its f^{n+2}
     unsigned int ncand;         // candidates written (may exceed PRED_CAP: overflow)
     unsigned int pad;
-    double t2;                  // time after the launch's two steps
+    double t2;                  // time after the launch's steps
 };
 
 // Counters of the fused launches since the context's initialisation.
@@ -98,6 +99,8 @@ enum : int {
     PST_PRED_MISS,        // predicted guesses rolled back
     PST_EVALUATED,        // cells whose bound the prediction kernel evaluated
     PST_PRED_NONE,        // pairs with candidates but no prediction (overflow, none)
+    PST_LISTED,           // candidates the launches listed
+    PST_OVERFLOW,         // launches whose candidates overflowed the list
     PST_COUNT
 };
 
@@ -337,8 +340,9 @@ hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long
 // After fused launch a.launch: evaluate its candidates and leave the
 // prediction (or none) for the next launch.
 hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s);
-// Clear the fused launches' record and counters (context initialisation).
-hipError_t launch_pair_reset(PairState* ps, hipStream_t s);
+// Clear the fused launches' record (a prediction left for the state, open
+// checks) and, with counters, their counters (context initialisation).
+hipError_t launch_pair_reset(PairState* ps, bool counters, hipStream_t s);
 hipError_t launch_step1d(const Step1DArgs& a, int Q, hipStream_t s);
 hipError_t launch_run1d(const Step1DArgs& a, int Q, hipStream_t s);
 int persistent1d_max_cells(int Q, size_t lds_limit);

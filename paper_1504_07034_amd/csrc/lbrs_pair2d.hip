@@ -142,7 +142,7 @@ template <int WPB, bool TWO, bool TAPE, bool CAND = false>
 __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0, int y1, int lane,
                                            double& lm1, bool& bad1, double& lm2, bool& bad2,
                                            bool store = true) {
-    static_assert(!CAND || (TWO && !TAPE), "candidates ride on plain two-step launches");
+    static_assert(!CAND || !TAPE, "candidates ride on plain launches");
     const int nx = g.nx, ny = g.ny;
     const bool px = g.bc[0] == BC_PERIODIC, py = g.bc[2] == BC_PERIODIC;
     const double gm1 = g.gamma - 1.0;
@@ -168,24 +168,34 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
     Hops h;
 
     // CAND: candidates for the prediction of lambda*_{n+3} (see PredCand).
-    // l: the bound of U^{n+2} of this lane's cell of row o2 (-1 outside the
-    // tile); the wave's running threshold, largest bound seen, and the bound
-    // of the row above in this lane.
-    double thr = CAND ? g.t0 : 0.0, wmax = 0.0, lup = -1.0;
-    auto candidates = [&](double l, int o2) {
-        if (__any(l > thr)) {
-            const double rowmax = wave_max(l);
-            const bool record = rowmax > wmax;
-            wmax = fmax(wmax, rowmax);
-            thr = fmax(g.t0, wmax * (1.0 - CAND_REL));
-            // the first lane holding a new largest bound always goes in
-            const unsigned long long rec = __ballot(record && l == rowmax);
-            const int rec_lane = rec ? __ffsll((long long)rec) - 1 : -1;
-            // inside a flat region (a neighbour outside the tile counts as equal)
-            const double ll = lane_from_left(l), lr = lane_from_right(l);
-            const bool flat = (ll == l || ll < 0.0) && (lr == l || lr < 0.0) &&
-                              (lup == l || lup < 0.0);
-            const bool emit = l > thr && (!flat || lane == rec_lane);
+    // A row's cells are decided when the row after it is known: l of rows
+    // o2-1 (lp, pending) and o2-2 (lpp) in this lane, -1 outside the tile;
+    // the wave's largest bound so far, the threshold CAND_REL below it (at
+    // least the launch's floor), and the first lane of the pending row that
+    // raised the largest bound (-1: none).
+    double thr = CAND ? g.t0 : 0.0, wmax = 0.0, lp = -1.0, lpp = -1.0;
+    int rec_prev = -1;
+    auto candidates = [&](double lc, int o2) {
+        int rec_cur = -1;
+        if (__any(lc > thr)) {
+            const double rowmax = wave_max(lc);
+            if (rowmax > wmax) {
+                rec_cur = __ffsll((long long)__ballot(lc == rowmax)) - 1;
+                wmax = rowmax;
+                thr = fmax(g.t0, wmax * (1.0 - CAND_REL));
+            }
+        }
+        // row o2-1: a cell goes in when its bound is above the threshold and
+        // no neighbour's exceeds it (a neighbour outside the tile is
+        // ignored), except inside a flat region, which leaves only the cell
+        // that first reached its value
+        if (__any(lp > thr)) {
+            const double ll = lane_from_left(lp), lr = lane_from_right(lp);
+            const bool top = (ll < 0.0 || lp >= ll) && (lr < 0.0 || lp >= lr) &&
+                             (lpp < 0.0 || lp >= lpp) && (lc < 0.0 || lp >= lc);
+            const bool flat = (ll < 0.0 || lp == ll) && (lr < 0.0 || lp == lr) &&
+                              (lpp < 0.0 || lp == lpp) && (lc < 0.0 || lp == lc);
+            const bool emit = lp > thr && top && (!flat || lane == rec_prev);
             const unsigned long long m = __ballot(emit);
             if (m) {
                 unsigned base = 0;
@@ -194,13 +204,15 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
                 if (emit) {
                     const unsigned idx = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
                     if (idx < (unsigned)PRED_CAP) {
-                        g.cand[idx].cell = (long long)o2 * nx + x;
-                        g.cand[idx].l = l;
+                        g.cand[idx].cell = (long long)(o2 - 1) * nx + x;
+                        g.cand[idx].l = lp;
                     }
                 }
             }
         }
-        lup = l;
+        rec_prev = rec_cur;
+        lpp = lp;
+        lp = lc;
     };
 
     // Row r of f^n (in cur) completes row r-1 of f^{n+1} and, with TWO, row
@@ -249,6 +261,7 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
             // (a bound-only launch drops the row: out-of-range offset)
             store_full_row(g.fout + (long long)o1 * g.rs, g.ps, row_bytes,
                            store ? voff : 0x7fffffff, g1);
+            if (CAND) candidates(own1 && ok1 ? l1 : -1.0, o1);
             return;
         }
         // second step: row q = o1 of f^{n+1} completes row q - 1 of f^{n+2}
@@ -330,6 +343,8 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
         for (int p = 0; p < 16; ++p) f[p] = nxt[p];
         row(f, nxt, r);
     }
+    // the tile's last row is decided without the row after it
+    if (CAND) candidates(-1.0, y1);
 }
 
 __device__ inline double from_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
@@ -375,6 +390,8 @@ struct PairCtl {
     unsigned bad;
     double lam1, t1, lam2, t2;
     double t0;          // floor of the candidates' bounds
+    bool pred_ok;       // the record read holds a prediction for the current state
+    unsigned long long pred;  // its bits
 };
 
 __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
@@ -451,10 +468,14 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
     if (c.two)
         step_size(a.lam_mode, from_bits(l2 > lbc ? l2 : lbc), st->lam_fixed, a.dx, a.cfl, c.t1,
                   a.t_end, c.lam2, c.t2);
-    // candidates for the prediction of lambda*_{n+3}: bounds of U^{n+2} from
-    // CAND_REL below lambda*_{n+1} up
-    c.cand = c.two && per_step && a.cand != nullptr && c.t2 < a.t_end;
-    c.t0 = c.cand ? from_bits(l2) * (1.0 - CAND_REL) : 0.0;
+    // candidates for the prediction of the bound after the next launch's
+    // first step: bounds of the state this launch leaves (U^{n+2}, or U^{n+1}
+    // of a one-step launch) from CAND_REL below the last known one up
+    c.cand = c.active && !c.bound && per_step && a.cand != nullptr &&
+             (c.two ? c.t2 : c.t1) < a.t_end;
+    c.t0 = c.cand ? from_bits(c.two ? l2 : lstar) * (1.0 - CAND_REL) : 0.0;
+    c.pred_ok = pred_ok;
+    c.pred = q.pred;
     return c;
 }
 
@@ -484,6 +505,9 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
         s.cur = c.cur;
         st->lam[ls.la] = c.lstar;
         st->bad[ls.la] = c.bad;
+        // the state stays: so does a prediction for it (also into the next call)
+        q.pred_valid = c.pred_ok ? 1 : 0;
+        q.pred = c.pred;
     } else if (c.bound) {
         // no step: the state and its bound carry over; the first-step
         // accumulators receive the bound of f^{n+1}
@@ -518,7 +542,7 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
     PredHeader& h = ps->pred[a.launch & 1];
     h.armed = c.cand ? 1 : 0;
     h.cur_out = c.cur ^ 1;
-    h.t2 = c.t2;
+    h.t2 = c.two ? c.t2 : c.t1;
     PredHeader& hn = ps->pred[(a.launch + 1) & 1];
     hn.armed = 0;
     hn.ncand = 0u;
@@ -586,7 +610,11 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
             else
                 march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
         } else {
-            march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2, !c.bound);
+            if (CAND && c.cand)
+                march_pair<WPB, false, false, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
+            else
+                march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2,
+                                             !c.bound);
         }
     }
 
@@ -638,9 +666,12 @@ __global__ __launch_bounds__(256) void pair_predict_kernel(Pair2DArgs a) {
     const unsigned ncand = h->ncand;
     const bool ok = h->armed != 0 && ncand > 0u && ncand <= (unsigned)PRED_CAP &&
                     a.st->bad[ls.la] == 0u;
-    if (blockIdx.x == 0 && tid == 0) {
+    if (blockIdx.x == 0 && tid == 0 && h->armed) {
+        // (a launch that listed nothing keeps what its record carries)
         ps->q[ls.sw].pred_valid = ok ? 1 : 0;
-        if (h->armed) ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
+        ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
+        ps->stat[PST_LISTED] += ncand;
+        if (ncand > (unsigned)PRED_CAP) ps->stat[PST_OVERFLOW] += 1;
     }
     if (!ok) return;
     const unsigned long long lb = a.st->lam[ls.la];
@@ -756,9 +787,8 @@ __global__ void pair_prepare_kernel(PairState* ps, const DevState* st, int slot,
         ps->q[i].guess_base = 0ull;
         ps->q[i].known = 0;
         ps->q[i].trust = 3;  // start a call by guessing
-        ps->q[i].pred_valid = 0;
         ps->q[i].predicted = 0;
-        ps->q[i].pred = 0ull;
+        // a prediction the last call left stays (it is only a guess: checked)
     }
     for (int i = 0; i < 3; ++i) {
         ps->lam1[i] = 0ull;
@@ -771,9 +801,10 @@ __global__ void pair_prepare_kernel(PairState* ps, const DevState* st, int slot,
     ps->n_limit = st->s[slot].n + max_steps;
 }
 
-__global__ void pair_reset_kernel(PairState* ps) {
+__global__ void pair_reset_kernel(PairState* ps, bool counters) {
     if (threadIdx.x != 0) return;
-    for (int i = 0; i < PST_COUNT; ++i) ps->stat[i] = 0ull;
+    if (counters)
+        for (int i = 0; i < PST_COUNT; ++i) ps->stat[i] = 0ull;
     for (int i = 0; i < 2; ++i) {
         ps->pred[i].armed = 0;
         ps->pred[i].ncand = 0u;
@@ -790,8 +821,8 @@ hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long
     return hipGetLastError();
 }
 
-hipError_t launch_pair_reset(PairState* ps, hipStream_t s) {
-    hipLaunchKernelGGL(pair_reset_kernel, dim3(1), dim3(64), 0, s, ps);
+hipError_t launch_pair_reset(PairState* ps, bool counters, hipStream_t s) {
+    hipLaunchKernelGGL(pair_reset_kernel, dim3(1), dim3(64), 0, s, ps, counters);
     return hipGetLastError();
 }
 

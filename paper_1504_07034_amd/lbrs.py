@@ -508,7 +508,7 @@ class Sim:
         return lbrs_get_state(self.ctx)
 
     PAIR_STATS = ("pairs", "rejected", "bound_only", "single", "predicted", "pred_hit",
-                  "pred_miss", "evaluated", "pred_none")
+                  "pred_miss", "evaluated", "pred_none", "listed", "overflow")
 
     def pair_stats(self) -> dict:
         """Counters of the fused launches since init (lbrs_pair_stats)."""

@@ -194,7 +194,10 @@ def test_batch2d_gradient_graph_vs_oracle_and_replays():
 
 def test_batch2d_full_configuration_wave():
     """128 seeded periodic domains with sides from {256, 512, 1024, 2048}: one
-    launch steps them all; a memory wave of about 16M cells runs the
+    launch steps them all, 20 steps against the oracle -- the two smallest
+    domains on every cell, the largest on sampled cells (a cell after k steps
+    depends only on the (2k+1)^2 patch around it, which the oracle runs at the
+    domain's frozen lattice speed); a memory wave of about 16M cells runs the
     1000-step checkpointed gradient in a captured graph, every J finite and
     every domain admissible."""
     ws = wl.domain_batch(128, seed=0)
@@ -203,14 +206,51 @@ def test_batch2d_full_configuration_wave():
     B.init(_pool_U0(ws, doms))
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k = 20
     e0.record()
-    B.step(20)
+    B.step(k)
     e1.record()
     st = B.state()
-    ms = e0.elapsed_time(e1) / 20
+    ms = e0.elapsed_time(e1) / k
     report("batch2d 128 forward", cells=B.total, ms_per_step=ms, mlups=B.total / ms / 1e3)
     assert st["rc"] == 0
+    U = B.moments().cpu().numpy()
     B.close()
+
+    def problem(w, nx, ny, domain, **kw):
+        return oracle.Problem(model=oracle.D2Q4, nx=nx, ny=ny, domain=domain, gamma=w.gamma,
+                              omega=1.0, cfl=w.cfl, **kw)
+
+    order = sorted(range(len(ws)), key=lambda d: ws[d].nx * ws[d].ny)
+    for d in order[:2]:
+        w = ws[d]
+        P = problem(w, w.nx, w.ny, w.domain, sides=w.sides, lam_mode=oracle.LAM_FROZEN)
+        ref = oracle.run(P, oracle.prim_to_cons(P, w.W), max_steps=k, record=False)
+        err = float(np.max(np.abs(U[:, B.unit_slice(d)] - ref.U.reshape(4, -1))))
+        report("batch2d 128 vs oracle", dom=d, n=w.nx, err=err)
+        assert ref.status == 0 and err <= TOL
+    d = order[-1]
+    w = ws[d]
+    Pf = problem(w, w.nx, w.ny, w.domain, sides=w.sides, lam_mode=oracle.LAM_FROZEN)
+    lam = oracle.initial_lattice_speed(Pf, oracle.prim_to_cons(Pf, w.W))
+    Ud = U[:, B.unit_slice(d)].reshape(4, w.ny, w.nx)
+    dx = (w.domain[1] - w.domain[0]) / w.nx
+    dy = (w.domain[3] - w.domain[2]) / w.ny
+    R = k + 1
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for _ in range(4):
+        j = int(rng.integers(R, w.ny - R))
+        i = int(rng.integers(R, w.nx - R))
+        m = 2 * R + 1
+        P = problem(w, m, m, (0.0, m * dx, 0.0, m * dy), sides=(0, 0, 0, 0),
+                    lam_mode=oracle.LAM_USER, lam_user=lam)
+        ref = oracle.run(P, oracle.prim_to_cons(P, w.W[:, j - R:j + R + 1, i - R:i + R + 1]),
+                         max_steps=k, record=False)
+        err = float(np.max(np.abs(Ud[:, j, i] - ref.U[:, R, R])))
+        worst = max(worst, err)
+        assert ref.status == 0 and err <= TOL, ((j, i), err)
+    report("batch2d 128 cone samples", dom=d, n=w.nx, err=worst)
     del B
     torch.cuda.empty_cache()
     sub, cells = [], 0
