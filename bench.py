@@ -35,11 +35,11 @@ TRAFFIC_BYTES = {"16,0": 4.433e9, "16,1": 4.396e9, "12,0": 4.418e9, "12,1": 4.39
                  "8,1": 4.382e9, "6,0": 4.517e9, "6,1": 4.407e9, "4,0": 4.538e9, "4,1": 4.481e9}
 TRAFFIC_SOURCE_HASH = "aeb4140bef7481ec"
 SINGLE_SOURCES = ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
-# The same for the fused two-step kernel, by waves per workgroup: the mean HBM
-# bytes per launch over the timed launches of the benchmark window (per-step
-# lattice speeds: one launch per step, of which those past the steps done exit
-# at once), profiles/step2d_pair_riemann4096.md.
-PAIR_TRAFFIC_BYTES = {"8": 2.9920e9, "6": 2.9919e9, "4": 3.0305e9}
+# The same for the fused multi-step kernel, by "steps_per_launch,waves_per_block":
+# the mean HBM bytes per launch over the timed launches of the benchmark window
+# (per-step lattice speeds: one launch per step, of which those past the steps
+# done exit at once), profiles/step2d_pair_riemann4096.md.
+PAIR_TRAFFIC_BYTES = {"2,8": 2.9920e9, "2,6": 2.9919e9, "2,4": 3.0305e9}
 PAIR_TRAFFIC_SOURCE_HASH = "2f5c1556053b413f"
 PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 
@@ -47,10 +47,10 @@ PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 def traffic_bytes(shape, layout):
     if shape["rows"] != 0 or layout != 1:
         return None
-    if shape.get("fuse", 1) == 2:
+    if shape.get("fuse", 1) >= 2:
         if kernel_source_hash(PAIR_SOURCES) != PAIR_TRAFFIC_SOURCE_HASH:
             return None
-        return PAIR_TRAFFIC_BYTES.get(str(shape["wpb"]))
+        return PAIR_TRAFFIC_BYTES.get(f"{shape['fuse']},{shape['wpb']}")
     if kernel_source_hash(SINGLE_SOURCES) != TRAFFIC_SOURCE_HASH:
         return None
     return TRAFFIC_BYTES.get(f"{shape['wpb']},{shape['alt']}")
@@ -73,11 +73,11 @@ def kernel_source_hash(files=SINGLE_SOURCES) -> str:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = 256  # single step: 16 FP64 populations in + 16 out per lattice update
-PAIR_BYTES_PER_LUP = 128  # two fused steps: f^n in, f^{n+2} out per two updates
+# k fused steps: f^n in, f^{n+k} out per k updates, 256/k B per update
 
 
-def form_bytes(fuse: int) -> int:
-    return PAIR_BYTES_PER_LUP if fuse == 2 else BYTES_PER_LUP
+def form_bytes(fuse: int) -> float:
+    return BYTES_PER_LUP / fuse
 
 
 def cpu_baseline(nsteps_one: int = 8, nsteps_all: int = 48):
@@ -353,8 +353,8 @@ def adjoint_2d(n=2048, steps=2000, k=50, steps_only=False):
             # the timed forms' own bytes per lattice update: fused adjoint
             # 160 (fbar^{n+2} 128 + two tapes 64 + fbar^n 128 per two
             # updates), single adjoint 288 (128 + 32 + 128)
-            "adjoint_step_bytes_per_lup": 160 if best["fuse"] == 2 else 288,
-            "adjoint_step_GBs": round((160 if best["fuse"] == 2 else 288) * cells /
+            "adjoint_step_bytes_per_lup": 160 if best["fuse"] >= 2 else 288,
+            "adjoint_step_GBs": round((160 if best["fuse"] >= 2 else 288) * cells /
                                       (adj2 * 1e-3) / 1e9, 1),
             "adjoint_step_single_equivalent_GBs": round(288 * cells / (adj2 * 1e-3) / 1e9, 1),
             "single": {"forward_step_ms": round(fwd1, 4), "tape_step_ms": round(tap, 4),
@@ -814,7 +814,8 @@ def slab_step(steps=200, warmup=20):
     gbs = bpl * cells / (ms * 1e-3) / 1e9
     return {"nx": n, "ny": h, "tile_rows": best["rows"], "waves_per_block": best["wpb"],
             "alternate": best["alt"], "steps_per_launch": best["fuse"], "ms_per_step": round(ms, 4),
-            "MLUPS": round(cells / ms / 1e3, 1), "bytes_per_lup": bpl, "GBs": round(gbs, 1),
+            "MLUPS": round(cells / ms / 1e3, 1), "bytes_per_lup": round(bpl, 2),
+            "GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "single_step_equivalent_GBs": round(BYTES_PER_LUP * cells / (ms * 1e-3) / 1e9, 1)}
 
@@ -830,7 +831,7 @@ def main():
     ap.add_argument("--alt", type=int, default=1, choices=[0, 1],
                     help="march odd row segments upwards (with --rows >= 0)")
     ap.add_argument("--layout", type=int, default=1, help="0 planar, 1 row-interleaved")
-    ap.add_argument("--fuse", type=int, default=1, choices=[1, 2],
+    ap.add_argument("--fuse", type=int, default=1, choices=[1, 2, 3],
                     help="time steps per launch (with --rows >= 0; autotuned otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -908,7 +909,7 @@ def main():
                 break
         out = {"steps": steps, "ms": round(total_ms, 1), "ms_per_step": round(total_ms / steps, 4),
                "MLUPS": round(n * n * steps / (total_ms * 1e-3) / 1e6, 1)}
-        if sh["fuse"] == 2:
+        if sh["fuse"] >= 2:
             out["launches"] = sim.pair_stats()
         return out
 
@@ -941,7 +942,7 @@ def main():
         print("autotune: " + ", ".join(f"({c['rows']},{c['wpb']},{c['alt']},{c['fuse']}) "
                                        f"{c['ms']:.3f} ms" for c in best["candidates"]),
               file=sys.stderr, flush=True)
-        if shape["fuse"] == 2:
+        if shape["fuse"] >= 2:
             s1 = min((c for c in best["candidates"] if c["fuse"] == 1), key=lambda c: c["ms"])
             single = {k: s1[k] for k in ("rows", "wpb", "alt", "fuse")}
 
@@ -954,7 +955,7 @@ def main():
         if warmup:
             sim.step(warmup, t_end)
         st0 = sim.state()
-        c0 = sim.pair_stats() if sh["fuse"] == 2 else None
+        c0 = sim.pair_stats() if sh["fuse"] >= 2 else None
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -969,18 +970,18 @@ def main():
             raise RuntimeError(f"timed steps did not all run: {st0} -> {st1}")
         if c0 is not None:
             c1 = sim.pair_stats()
-            window_launches[sh["wpb"], sh["alt"]] = {k: c1[k] - c0[k] for k in c1}
+            window_launches[sh["fuse"], sh["wpb"], sh["alt"]] = {k: c1[k] - c0[k] for k in c1}
         return ms, done
 
     window_launches = {}
 
     def roofline(sh, ms, done):
         """The kernel's own algorithmic bytes: 256 B per lattice update for a
-        single step (16 FP64 populations in, 16 out), 128 B for the fused pair
-        (f^n in and f^{n+2} out per two updates: f^{n+1} never leaves the
-        registers); per launch: the launches the window enqueued (a call of
-        K steps enqueues K launches of the step kernel either way)."""
-        bpl = 128 if sh["fuse"] == 2 else 256
+        single step (16 FP64 populations in, 16 out), 256/k B for k fused
+        steps (f^n in and f^{n+k} out per k updates: the states between never
+        leave the registers); per launch: the launches the window enqueued (a
+        call of K steps enqueues K launches of the step kernel either way)."""
+        bpl = BYTES_PER_LUP / sh["fuse"]
         cells = n * n
         alg = bpl * cells * done
         launches = args.steps
@@ -988,19 +989,19 @@ def main():
         r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
              "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
              "traffic": traffic_bytes(sh, args.layout),
-             "kernel": "step2d_pair" if sh["fuse"] == 2 else "step2d_d2q4",
-             "bytes_per_lup": bpl, "launches": launches,
+             "kernel": "step2d_pair" if sh["fuse"] >= 2 else "step2d_d2q4",
+             "bytes_per_lup": round(bpl, 2), "launches": launches,
              "avg_launch_ms": round(ms / launches, 5),
              "alg_bytes_per_launch": round(alg / launches),
              # the single step's 256 B per update over the same time
              "single_step_equivalent_GBs": round(256 * cells * done / (ms * 1e-3) / 1e9, 1)}
-        if sh["fuse"] == 2:
+        if sh["fuse"] >= 2:
             # what the window's launches did: pairs that stood, pairs rolled
             # back, bound-only passes, single steps, predictions of the next
             # bound made / standing / rolled back, cells evaluated for them;
             # the launches that did work (the others exit at once) and their
             # mean time, prediction kernels and gaps included
-            lc = window_launches.get((sh["wpb"], sh["alt"]))
+            lc = window_launches.get((sh["fuse"], sh["wpb"], sh["alt"]))
             r["launch_counts"] = lc
             if lc:
                 active = lc["pairs"] + lc["rejected"] + lc["bound_only"] + lc["single"]

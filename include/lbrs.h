@@ -223,8 +223,9 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
  * one node along every link, applies the side conditions and reduces the next
  * step's lambda* (with the prescribed states of DIRICHLET sides).  A step whose start time is >= t_end, or that follows a
  * non-physical step, does nothing, so the run stops exactly at t_end
- * (PER_STEP mode clips the last dt).  With lbrs_set_fusion(c, 2) (2D Euler)
- * the steps run two per launch with the same results (see there).
+ * (PER_STEP mode clips the last dt).  With lbrs_set_fusion(c, 2 or 3) (2D
+ * Euler) the steps run two or three per launch with the same results (see
+ * there).
  * Asynchronous. */
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
 
@@ -237,16 +238,16 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
 int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda,
                    unsigned* status, long long* fail_step);
 
-/* Counters of the fused launches since lbrs_init (lbrs_set_fusion(c, 2)),
- * into counts[0 .. n-1] (n <= 11; missing ones 0): [0] two-step launches whose
- * result stood, [1] two-step launches rolled back (a guessed lambda*_{n+1}
- * that was wrong), [2] launches that only reduced the bound of f^{n+1},
- * [3] one-step launches, [4] predictions of the next launch's bound made,
+/* Counters of the fused launches since lbrs_init (lbrs_set_fusion(c, k > 1)),
+ * into counts[0 .. n-1] (n <= 12; missing ones 0): [0] launches of two or
+ * three steps whose result stood, [1] such launches rolled back (a guessed
+ * bound that was wrong), [2] launches that only reduced the bound of f^{n+1},
+ * [3] one-step launches, [4] predictions of the next launch's bounds made,
  * [5] predicted bounds that stood, [6] predicted bounds rolled back,
  * [7] cells whose bound the predictions evaluated, [8] launches that listed
  * candidates but left no prediction (too many, none, or a non-physical
  * state), [9] candidates listed, [10] launches whose candidates overflowed
- * the list.  With per-step lattice speeds a fused launch guesses the bound of
+ * the list, [11] of [0], the three-step ones.  With per-step lattice speeds a fused launch guesses the bound of
  * the state after its first step (the prediction when the launch before left
  * one, else the current bound while it keeps repeating) and the next launch
  * checks the guess bit for bit, so the counters describe cost only: results
@@ -380,29 +381,32 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);
  * effect for later calls; LBRS_E_INVAL for values outside these sets. */
 int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alternate);
 
-/* Time steps per launch of the 2D Euler step: 1 (the default) or 2.  With 2
- * each wavefront keeps the rows of f^{n+1} it has just streamed in registers
- * and streams them once more (the same Sec. II.D update, twice), so f^n is
- * read and f^{n+2} written once per two steps: half the HBM traffic per step.
- * The second step's lattice speed is known with FROZEN_INIT or USER speeds.
- * With PER_STEP speeds it is the global bound of f^{n+1}: a launch takes it
- * equal to the current one and the next launch checks the bound of f^{n+1}
- * bit for bit; on a mismatch (or a non-physical f^{n+1}) that launch goes
- * back to f^n, which the first launch left intact, and redoes the steps with
- * the bound now known.  Either way t, the step count, every lattice speed,
- * the status, fail_step and the reported state after each lbrs_step call are
- * those of single steps (the populations agree with them to rounding: the
- * two paths are different kernels).  lbrs_step(c, max_steps, t_end) then
- * enqueues a one-thread set-up kernel and up to max_steps launches (with a
- * fixed speed max_steps/2 + 1), of which the ones beyond the work done exit
- * at once.  The shape set by lbrs_set_tile applies (strips of at most 60
- * columns; automatic segments of at least 4 rows; 16 waves per workgroup run
- * as 12; alternate is ignored).
+/* Time steps per launch of the 2D Euler step: 1 (the default), 2 or 3.  With
+ * k > 1 each wavefront keeps the rows of f^{n+1} it has just streamed in
+ * registers and streams them once more, k times (the same Sec. II.D update,
+ * k times), so f^n is read and f^{n+k} written once per k steps: 1/k of the
+ * HBM traffic per step.  The later steps' lattice speeds are known with
+ * FROZEN_INIT or USER speeds.  With PER_STEP speeds each is the global bound
+ * of the state before it: a launch guesses them -- a prediction the launch
+ * before left (the exact next bounds evaluated around the cells where the
+ * bound peaks), else the current bound -- and the next launch checks every
+ * guessed bound bit for bit; on a mismatch (or a non-physical intermediate
+ * state) that launch goes back to f^n, which the first launch left intact,
+ * and redoes the steps with the bounds now known.  Either way t, the step
+ * count, every lattice speed, the status, fail_step, the reported state after
+ * each lbrs_step call and the populations are those of single steps, bit for
+ * bit.  lbrs_step(c, max_steps, t_end) then enqueues a one-thread set-up
+ * kernel and up to max_steps launches (with a fixed speed max_steps/k + 1),
+ * of which the ones beyond the work done exit at once; with PER_STEP speeds
+ * each launch is followed by the prediction kernels.  The shape set by
+ * lbrs_set_tile applies (strips of at most 64 - 2k columns; automatic
+ * segments of at least 4 rows; 16 waves per workgroup run as 12, as 8 with
+ * k = 3 or PER_STEP speeds; alternate is ignored).
  * lbrs_step_tape stays a single step; lbrs_backward_checkpointed recomputes
- * its segments two steps per launch as well (both steps' input moments taped)
- * and runs its adjoint steps two per launch (lbrs_adjoint_step2).
- * LBRS_E_INVAL for other values; LBRS_E_STATE with 2 for a 1D, scalar-law,
- * body or DIRICHLET context.  Takes effect for later calls. */
+ * its segments two steps per launch when k > 1 (both steps' input moments
+ * taped) and runs its adjoint steps two per launch (lbrs_adjoint_step2).
+ * LBRS_E_INVAL for other values; LBRS_E_STATE with k > 1 for a 1D,
+ * scalar-law, body or DIRICHLET context.  Takes effect for later calls. */
 int lbrs_set_fusion(lbrs_ctx* c, int steps_per_launch);
 
 /* ------------------------------------------------------------------------
@@ -542,8 +546,8 @@ void lbrs_batch2d_destroy(lbrs_batch2d* b);
 /* ------------------------------------------------------------------------
  * No-allocation entry point, for callers that cannot allocate: code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation.
- * One whole run -- lbrs_init, lbrs_step(max_steps, t_end) (two steps per
- * launch when steps_per_launch is 2, as lbrs_set_fusion) and lbrs_moments --
+ * One whole run -- lbrs_init, lbrs_step(max_steps, t_end) (steps_per_launch
+ * steps per launch, 1 to 3, as lbrs_set_fusion) and lbrs_moments --
  * with the same kernels and results, but the time state (t, step count, the
  * lambda* reduction slots, the status and the fused launches' record) lives
  * in a static device array of the library (512 KiB per GPU, kept until the

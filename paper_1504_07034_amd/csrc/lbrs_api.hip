@@ -31,10 +31,11 @@ struct lbrs_ctx {
     bool dir;            // some side is DIRICHLET
     int sbpc[17];        // resident scalar-step workgroups per CU, by waves per block
     unsigned short* codes;  // body node codes in the scratch area (null: no body)
-    int fuse;            // 2D Euler: time steps per launch (1, or 2 fused)
+    int fuse;            // 2D Euler: time steps per launch (1, or 2 or 3 fused)
     PairState* pst;      // record of the fused launches (scratch area, behind the time state)
     PredCand* cand;      // candidate list of the per-step prediction (scratch area), or null
-    int pbpc[2][17];     // resident fused-kernel workgroups per CU, by (filter, waves per block)
+    int pbpc[3][2][17];  // resident fused-kernel workgroups per CU, by (plain, candidates,
+                         // taped), (two or three steps) and waves per block
     int abpc[17];        // the same for the fused adjoint kernel
 };
 
@@ -266,8 +267,8 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
 }
 
 int lbrs_set_fusion(lbrs_ctx* c, int steps_per_launch) {
-    if (!c || (steps_per_launch != 1 && steps_per_launch != 2)) return LBRS_E_INVAL;
-    if (steps_per_launch == 2 &&
+    if (!c || steps_per_launch < 1 || steps_per_launch > KMAX_STEPS) return LBRS_E_INVAL;
+    if (steps_per_launch >= 2 &&
         (c->dim != 2 || c->P.law != LBRS_LAW_EULER || c->dir || c->codes))
         return LBRS_E_STATE;
     c->fuse = steps_per_launch;
@@ -348,32 +349,37 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
 static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const double* gn,
                         double* g);
 
-// Fused two-step launches: strips of at most 60 columns (two halo lanes on
-// each side), segments of at least 4 rows (two halo rows on each side).
-// Per-step speeds run the fused launches in the form that lists candidates
-// for the prediction of the next launch's bound.
+// Fused launches of up to k steps: strips of at most 64 - 2k columns (k halo
+// lanes on each side), segments of at least 4 rows.  Per-step speeds run
+// the fused launches in the form that lists candidates for the predictions
+// of the next launch's bounds.  The taped launches of the gradients take two
+// steps.
 static bool pair_filter(const lbrs_ctx* c) {
     return c->cand && c->P.lambda_mode == LBRS_LAMBDA_PER_STEP;
 }
 
+static int pair_kmax(const lbrs_ctx* c, bool tape) { return tape ? 2 : c->fuse; }
+
 // Waves per workgroup of the fused kernel: 16-wave groups do not fit its
-// registers at the occupancy it needs and run as 12; in the form that lists
-// candidates (210 registers) 12-wave groups spill, and run as 8.
-static int pair_wpb(const lbrs_ctx* c) {
-    const int cap = pair_filter(c) ? 8 : 12;
+// registers at the occupancy it needs and run as 12; three-step launches and
+// the form that lists candidates (more registers) spill in 12-wave groups,
+// and run as 8.
+static int pair_wpb(const lbrs_ctx* c, bool tape = false) {
+    const int cap = !tape && (pair_filter(c) || c->fuse >= 3) ? 8 : 12;
     return c->waves_per_block > cap ? cap : c->waves_per_block;
 }
 
 static int pair_max_blocks(const lbrs_ctx* c, bool tape = false) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
-    const int w = pair_wpb(c);
-    const int f = pair_filter(c) && !tape ? 1 : 0;
-    int& n = m->pbpc[f][w];
-    if (n == 0) n = step2d_pair_blocks_per_cu(w, f != 0);
+    const int w = pair_wpb(c, tape);
+    const int form = tape ? 2 : (pair_filter(c) ? 1 : 0);
+    const int kmax = pair_kmax(c, tape);
+    int& n = m->pbpc[form][kmax >= 3 ? 1 : 0][w];
+    if (n == 0) n = step2d_pair_blocks_per_cu(w, form == 1, kmax, tape);
     return c->cu_count * n;
 }
 
-static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end) {
+static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end, bool tape = false) {
     Pair2DArgs a;
     a.f0 = c->f0;
     a.f1 = c->f1;
@@ -383,14 +389,16 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end) {
     a.rs = c->rs;
     a.nx = c->P.nx;
     a.ny = c->P.ny;
-    const int wpb = pair_wpb(c);
-    a.nstrips = ((c->P.nx + 59) / 60 + wpb - 1) / wpb * wpb;
+    const int wpb = pair_wpb(c, tape);
+    a.kmax = pair_kmax(c, tape);
+    const int cols = 64 - 2 * a.kmax;
+    a.nstrips = ((c->P.nx + cols - 1) / cols + wpb - 1) / wpb * wpb;
     a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
     long long nseg;
     if (c->rows_per_tile > 0) {
         nseg = (c->P.ny + c->rows_per_tile - 1) / c->rows_per_tile;
     } else {
-        nseg = (long long)pair_max_blocks(c) * wpb / a.nstrips;
+        nseg = (long long)pair_max_blocks(c, tape) * wpb / a.nstrips;
         const long long cap = (c->P.ny + 3) / 4;
         if (nseg > cap) nseg = cap;
     }
@@ -409,7 +417,7 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end) {
     a.last = 0;
     a.tape0 = a.tape1 = nullptr;
     a.plane = c->plane;
-    a.cand = pair_filter(c) ? c->cand : nullptr;
+    a.cand = pair_filter(c) && !tape ? c->cand : nullptr;
     return a;
 }
 
@@ -501,13 +509,16 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         }
         return LBRS_OK;
     }
-    if (c->dim == 2 && c->fuse == 2) {
-        // every launch advances one or two steps, except one that guessed
-        // the next lattice speed wrongly (the launch after it then advances
-        // two), so max_steps launches always suffice; with a fixed speed
-        // nothing is guessed and max_steps/2 + 1 suffice
+    if (c->dim == 2 && c->fuse >= 2) {
+        // Launches needed.  Per-step speeds: a launch advances at least one
+        // step, except a bound-only pass or one whose guess is rejected, and
+        // the launch after either of those advances at least two, so
+        // max_steps launches suffice.  Fixed speeds: every launch but the
+        // last advances kmax steps (a check that rolls back ends the run with
+        // a non-physical state) and the last one at least one.
         Pair2DArgs a = pair_args(c, t_end);
-        const int nl = a.lam_mode == LAM_PER_STEP ? max_steps : max_steps / 2 + 1;
+        const int nl = a.lam_mode == LAM_PER_STEP ? max_steps
+                                                  : (max_steps + a.kmax - 2) / a.kmax + 1;
         hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), max_steps,
                                            c->stream);
         if (e != hipSuccess) return LBRS_E_HIP;
@@ -726,8 +737,7 @@ static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const d
 // writes their input moments to tape slots 2k and 2k+1 (an odd last step: a
 // one-step launch, slot len-1).
 static int step_tape_fused(lbrs_ctx* c, int len, double* d_tape) {
-    Pair2DArgs a = pair_args(c, INFINITY);
-    a.cand = nullptr;
+    Pair2DArgs a = pair_args(c, INFINITY, true);
     const long long ucount = (long long)c->K * c->plane;
     const int nl = len / 2 + 1;
     hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), len, c->stream);
@@ -740,7 +750,7 @@ static int step_tape_fused(lbrs_ctx* c, int len, double* d_tape) {
         a.last = k == nl - 1;
         a.tape0 = d_tape + s0 * ucount;
         a.tape1 = d_tape + s1 * ucount;
-        e = launch_step2d_pair(a, pair_wpb(c), true, mb, c->stream);
+        e = launch_step2d_pair(a, pair_wpb(c, true), true, mb, c->stream);
         if (e != hipSuccess) return LBRS_E_HIP;
         ++c->launches;
     }
@@ -754,8 +764,7 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
     if (c->dim != 2 || c->dir || c->codes) return LBRS_E_STATE;
     // the set-up kernel and two launches: the pair, then the one that checks
     // it (a one-step fallback writes slot d_Utape_n, as the first step would)
-    Pair2DArgs a = pair_args(c, INFINITY);
-    a.cand = nullptr;
+    Pair2DArgs a = pair_args(c, INFINITY, true);
     hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), 2, c->stream);
     if (e != hipSuccess) return LBRS_E_HIP;
     const int mb = pair_max_blocks(c, true);
@@ -764,7 +773,7 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
     for (int k = 0; k < 2; ++k) {
         a.launch = c->launches;
         a.last = k == 1;
-        e = launch_step2d_pair(a, pair_wpb(c), true, mb, c->stream);
+        e = launch_step2d_pair(a, pair_wpb(c, true), true, mb, c->stream);
         if (e != hipSuccess) return LBRS_E_HIP;
         ++c->launches;
     }
@@ -777,7 +786,7 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
 static int reverse_sweep(lbrs_ctx* c, int len, const double* d_tape, double*& cur, double*& nxt) {
     const long long ucount = (long long)c->K * c->plane;
     int i = len - 1;
-    if (c->fuse == 2) {
+    if (c->fuse >= 2) {
         for (; i >= 1; i -= 2) {
             int rc = adjoint_pair(c, d_tape + i * ucount, d_tape + (i - 1) * ucount, cur, nxt);
             if (rc) return rc;
@@ -823,7 +832,7 @@ int lbrs_backward_checkpointed(lbrs_ctx* c, int nsteps, int segment, const doubl
         int rc = lbrs_set_f(c, d_ckpt + j * fcount, t0 + (double)j * segment * dt, n0 + (long long)j * segment);
         if (rc) return rc;
         int len = nsteps - j * segment < segment ? nsteps - j * segment : segment;
-        if (c->fuse == 2) {
+        if (c->fuse >= 2) {
             rc = step_tape_fused(c, len, d_tape);
             if (rc) return rc;
         } else {
@@ -856,7 +865,7 @@ static int gradient_state_ok(const lbrs_ctx* c) {
 int lbrs_forward_taped(lbrs_ctx* c, int nsteps, double* d_tape) {
     if (!c || !d_tape || nsteps < 1) return LBRS_E_INVAL;
     if (!gradient_state_ok(c)) return LBRS_E_STATE;
-    if (c->fuse == 2) return step_tape_fused(c, nsteps, d_tape);
+    if (c->fuse >= 2) return step_tape_fused(c, nsteps, d_tape);
     const long long ucount = (long long)c->K * c->plane;
     for (int i = 0; i < nsteps; ++i) {
         int rc = lbrs_step_tape(c, d_tape + i * ucount);
@@ -916,7 +925,7 @@ int lbrs_run_noalloc(const lbrs_params* p, const double* d_U0, double* d_f0, dou
                      int max_steps, double t_end, int steps_per_launch, double* d_U,
                      double* d_state, void* hip_stream) {
     if (!p || !d_U || max_steps < 0 || isnan(t_end)) return LBRS_E_INVAL;
-    if (steps_per_launch != 1 && steps_per_launch != 2) return LBRS_E_INVAL;
+    if (steps_per_launch < 1 || steps_per_launch > KMAX_STEPS) return LBRS_E_INVAL;
     if (p->solid) return LBRS_E_INVAL;  // body codes would need a host staging buffer
     // the time state and the fused launches' record must fit the array
     if (codes_offset(p) > NOALLOC_SCRATCH_BYTES) return LBRS_E_INVAL;
@@ -927,7 +936,7 @@ int lbrs_run_noalloc(const lbrs_params* p, const double* d_U0, double* d_f0, dou
     lbrs_ctx c;  // on the stack: nothing is allocated
     int rc = ctx_setup(&c, p, d_U0, d_f0, d_f1, sp, hip_stream, false);
     if (rc) return rc;
-    if (steps_per_launch == 2 && (rc = lbrs_set_fusion(&c, 2))) return rc;
+    if (steps_per_launch >= 2 && (rc = lbrs_set_fusion(&c, steps_per_launch))) return rc;
     if ((rc = lbrs_step(&c, max_steps, t_end))) return rc;
     if ((rc = lbrs_moments(&c, d_U))) return rc;
     if (d_state &&

@@ -28,32 +28,39 @@ struct Step2DArgs {
     const unsigned short* code;  // node codes of a solid body [ny][nx] (or null)
 };
 
-// Fused two-step launches (2D Euler): the second step's lattice speed
-// depends on the global bound of the first step's states, which is known only
-// when the launch has ended.  A launch that guesses it, or that cannot yet
-// know whether its first step was admissible, is tentative: the next launch
-// accepts its result when the recorded bound equals the guess bit for bit
-// and the first step was admissible, else falls back to the state before it.
-// The guess is the predicted bound when the previous launch left one (see
-// PredHeader), else lambda*_n while the bound has been repeating (trust > 0);
-// at trust 0 a launch instead reduces the bound of f^{n+1} alone (nothing
-// stored) and the next launch takes two steps with it.  The record lives in
-// slot (p+1) & 1 beside the time state; the first step's bound and flag are
-// slotted like DevState::lam and DevState::bad.
+// Fused launches of up to KMAX_STEPS steps (2D Euler): every step after the
+// first takes its lattice speed from the global bound of the state before it,
+// which is known only when the launch has ended.  A launch that guesses those
+// bounds, or that cannot yet know whether its intermediate states were
+// admissible, is tentative: the next launch accepts its result when every
+// recorded bound equals its guess bit for bit and every intermediate state
+// was admissible; else it falls back to the state before it, now knowing the
+// exact bounds up to the first wrong guess, and takes (without guessing) as
+// many steps as they allow -- or, where an intermediate state was
+// non-physical, exactly the steps up to it, so that the report names the same
+// step as single steps would.  The guesses are the predicted bounds when the
+// previous launch left them (see PredHeader), else lambda*_n while the bound
+// has been repeating (trust > 0); at trust 0 a launch instead reduces the
+// bound of f^{n+1} alone (nothing stored) and the next launch steps with it.
+// The record lives in slot (p+1) & 1 beside the time state; the intermediate
+// states' bounds and flags are slotted like DevState::lam and DevState::bad.
+static constexpr int KMAX_STEPS = 3;
+
 struct PairSlot {
     double t_base;              // state before the launch's steps
     long long n_base;
     int cur_base;
-    int tentative;              // 1: the next launch must check this launch's guess
-    unsigned long long guess;   // bits of the guessed lambda*_{n+1}
+    int tentative;              // > 0: the next launch must check this launch's result of
+                                // `tentative` steps
+    unsigned long long guess[KMAX_STEPS];  // guess[i]: bits of the lambda*_{n+i} taken (i >= 1)
     unsigned long long guess_base;  // bits of lambda*_n of the state before the launch
     int known;                  // 1: this launch only reduced the bound of f^{n+1} (no step)
     int trust;                  // 0..3: +1 when a check finds the bound repeated, -1 when
-                                // not; new pairs guess while > 0
-    int pred_valid;             // 1: `pred` is the prediction of the bound of the state after
-    int predicted;              //    the next launch's first step; 1: this launch's guess was
-                                //    such a prediction
-    unsigned long long pred;    // bits of the predicted bound (max over the evaluated cells)
+                                // not; new launches guess while > 0
+    int pred_valid;             // predictions left for the state after this launch: pred[i],
+    int predicted;              //   i = 1 .. pred_valid, the bound after the next launch's
+                                //   i-th step; 1: this launch's guesses were predictions
+    unsigned long long pred[KMAX_STEPS];
 };
 
 // The prediction of lambda*_{n+3} after a pair n -> n+2 (or of lambda*_{n+2}
@@ -90,8 +97,8 @@ struct PredHeader {
 
 // Counters of the fused launches since the context's initialisation.
 enum : int {
-    PST_PAIRS = 0,        // two-step launches whose result stood
-    PST_REJECTED,         // two-step launches rolled back
+    PST_PAIRS = 0,        // launches of two or more steps whose result stood
+    PST_REJECTED,         // launches of two or more steps rolled back
     PST_BOUND_ONLY,       // launches that only reduced the bound of f^{n+1}
     PST_SINGLE,           // one-step launches
     PST_PREDICTED,        // predictions left for the next launch
@@ -101,13 +108,17 @@ enum : int {
     PST_PRED_NONE,        // pairs with candidates but no prediction (overflow, none)
     PST_LISTED,           // candidates the launches listed
     PST_OVERFLOW,         // launches whose candidates overflowed the list
+    PST_STEPS3,           // of PST_PAIRS: three-step launches
     PST_COUNT
 };
 
 struct PairState {
     PairSlot q[2];
-    unsigned long long lam1[3];  // bound of the first step's states (bits of doubles >= 0)
-    unsigned int bad1[3];        // the first step met a non-physical state
+    // bounds (bits of doubles >= 0) and non-physical flags of the states
+    // after steps 1 .. KMAX_STEPS-1 of a launch; lamk[0] also receives the
+    // bound of a bound-only launch
+    unsigned long long lamk[KMAX_STEPS - 1][3];
+    unsigned int badk[KMAX_STEPS - 1][3];
     unsigned int pad;
     long long n_limit;           // step count at which the current call stops
     PredHeader pred[2];
@@ -121,8 +132,9 @@ struct Pair2DArgs {
     PairState* pst;
     long long ps, rs;     // population offset = p*ps + y*rs + x
     int nx, ny;
-    int strip;            // output columns per strip (<= 60)
+    int strip;            // output columns per strip (<= 64 - 2 kmax)
     int nstrips, nseg, ntiles;
+    int kmax;             // steps a launch may take (1 .. KMAX_STEPS)
     long long launch;     // host launch counter p
     double dx, cfl, omega, gamma, t_end;
     int lam_mode;
@@ -329,16 +341,16 @@ hipError_t launch_step2d(const Step2DArgs& a, int wpb, bool tape, bool alt, bool
                          int max_blocks, hipStream_t s);
 int step2d_blocks_per_cu(int wpb, bool alt, bool dir, bool body = false);
 bool step2d_wpb_supported(int wpb);
-// Fused two-step launches (same waves-per-workgroup choices as the step).
+// Fused launches of up to a.kmax steps (same waves-per-workgroup choices as the step).
 hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, bool tape, int max_blocks,
                               hipStream_t s);
-int step2d_pair_blocks_per_cu(int wpb, bool cand = false);
+int step2d_pair_blocks_per_cu(int wpb, bool cand, int kmax, bool tape);
 // Start of a call of max_steps fused launches: clears the first-step
 // accumulators and records the step count to stop at.
 hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long long max_steps,
                                hipStream_t s);
 // After fused launch a.launch: evaluate its candidates and leave the
-// prediction (or none) for the next launch.
+// predictions (or none) for the next launch (two levels when a.kmax >= 3).
 hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s);
 // Clear the fused launches' record (a prediction left for the state, open
 // checks) and, with counters, their counters (context initialisation).

@@ -100,17 +100,24 @@ struct PairGeom {
     double* fout;
     long long ps, rs;
     int nx, ny, strip;
-    double c4lam1, c4lam2, omega, gamma;
+    double c4lam[KMAX_STEPS];  // 1/(4 lambda) of each step
+    double omega, gamma;
     int bc[4];
-    double* tape0;   // TAPE: U^n and U^{n+1}, element (k, y, x) at k*tape_ps + y*nx + x
-    double* tape1;
-    long long tape_ps;
+    double* tape[KMAX_STEPS];  // TAPE: U^{n+s} of step s's input, element (k, y, x) at
+    long long tape_ps;         // k*tape_ps + y*nx + x
     // CAND: the floor of the candidates' bounds, this launch's header and
     // where candidates go
     double t0;
     PredHeader* ph;
     PredCand* cand;
 };
+
+// A wave-uniform double, moved to scalar registers.
+__device__ inline double uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
 
 __device__ inline void load_row(double v[16], const double* __restrict__ fin, long long ps,
                                 long long rs, int j, int xl) {
@@ -125,9 +132,6 @@ __device__ inline void store_full_row(double* row, long long ps, int row_bytes, 
     for (int p = 0; p < 16; ++p) store_row(row + p * ps, row_bytes, voff, g[p]);
 }
 
-// Rows y0..y1-1 of one strip, one step (TWO = false: f^{n+1} is the output)
-// or two.  lm1/bad1 gather the bound and admissibility of this tile's cells
-// of f^{n+1}, lm2/bad2 those of f^{n+2}.
 // Moments of row j of a tape (rows [y0, y1) of the tile only: other rows
 // and lanes carry an out-of-range offset, so the store is unconditional).
 __device__ inline void tape_row(double* tape, long long tape_ps, int nx, int j, int y0, int y1,
@@ -138,54 +142,87 @@ __device__ inline void tape_row(double* tape, long long tape_ps, int nx, int j, 
     for (int k = 0; k < 4; ++k) store_row(row + k * tape_ps, nx * 8, own ? voff : 0x7fffffff, U[k]);
 }
 
-template <int WPB, bool TWO, bool TAPE, bool CAND = false>
-__device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0, int y1, int lane,
-                                           double& lm1, bool& bad1, double& lm2, bool& bad2,
-                                           bool store = true) {
+// K fused steps of rows y0..y1-1 of one strip (K = 1: a single step).  Lane
+// l holds column x0 - K + l; step s (0-based) is valid on lanes s+1 .. 62-s,
+// so a strip has <= 64 - 2K output columns.  Row r of f^n (read once)
+// enters step 0; step s takes row j = r - s of f^{n+s} and completes row
+// j - 1 of f^{n+s+1}, which goes straight into step s+1: the downward hops
+// (populations 0, 1) come from row j, the upward hops (2, 3) from row j - 2,
+// kept in the step's two-row register pipeline.  Rows y0-K .. y1+K-1 of f^n
+// are read, so step s produces rows y0-K+s .. y1+K-2-s; the first rows of
+// each pipeline start as zeros and only feed rows that are never used.
+// After step s < K-1, at a clamped (transmissive or wall) side, the next
+// step must pull from the edge cell of f^{n+s+1} itself, not from a ghost
+// that this step would make up: the halo lane beyond a clamped x side takes
+// the edge column's values; at a clamped bottom, row -1 is row 0 again (its
+// upward hops stand in), at a clamped top row ny is row ny-1 again (its
+// downward hops are kept for the virtual row).  Walls overwrite the pulls
+// across them.  lm[s]/bad[s] gather the bound and admissibility of this
+// tile's cells of f^{n+s+1}; TAPE stores U^{n+s} of every step's input;
+// CAND lists candidates from the last step's output (see PredCand).  One
+// copy of the step code serves every row and step of a kernel's path, so
+// all cells round alike.
+template <int WPB, int K, bool TAPE, bool CAND = false, bool LPB = false>
+__device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, int y1, int lane,
+                                        double (&lm)[KMAX_STEPS], bool (&bad)[KMAX_STEPS],
+                                        bool store = true, double* pbl = nullptr) {
+    static_assert(K >= 1 && K <= KMAX_STEPS, "steps per launch");
     static_assert(!CAND || !TAPE, "candidates ride on plain launches");
     const int nx = g.nx, ny = g.ny;
     const bool px = g.bc[0] == BC_PERIODIC, py = g.bc[2] == BC_PERIODIC;
     const double gm1 = g.gamma - 1.0;
     const int row_bytes = nx * 8;
     const int x0 = strip * g.strip;
-    const int x = x0 - 2 + lane;
+    const int x = x0 - K + lane;
     const int xl = map_index(x, nx, px);
-    const bool out_lane = lane >= 2 && lane <= g.strip + 1 && x < nx;
+    const bool out_lane = lane >= K && lane <= g.strip + K - 1 && x < nx;
     const int voff = out_lane ? x * 8 : 0x7fffffff;
     const bool wxlo = g.bc[0] == BC_WALL && x == 0;
     const bool wxhi = g.bc[1] == BC_WALL && x == nx - 1;
     const bool wlo = g.bc[2] == BC_WALL, whi = g.bc[3] == BC_WALL;
-    // rows [a0, b0) of f^{n+1}; f^n rows a0-1 .. b0 are read
-    const int a0 = TWO ? y0 - 1 : y0, b0 = TWO ? y1 + 1 : y1;
     // strips that may hold the ghost lanes x = -1 or x = nx of a clamped x side
-    const bool xfix = TWO && !px && (x0 == 0 || x0 + 61 >= nx);
-    const bool clamp_lo = TWO && !py && y0 == 0;
-    const bool clamp_hi = TWO && !py && y1 == ny;
+    const bool xfix = K > 1 && !px && (x0 == 0 || x0 + 63 - K >= nx);
+    const bool clamp_lo = K > 1 && !py && y0 == 0;
+    const bool clamp_hi = K > 1 && !py && y1 == ny;
 
-    double A3[4], A4[4], B3[4], B4[4];  // first step: upward hops of rows r-1, r-2
-    double P3[4], P4[4], Q3[4], Q4[4];  // second step: upward hops of rows q-1, q-2
-    double U[4];
-    Hops h;
+    // per step: upward hops (u2, u3) of the last input row (PA) and of the
+    // one before (PB); at a clamped top PA keeps row ny-1's downward hops.
+    // LPB: PB lives in the wave's LDS area pbl instead of registers, element
+    // k of step st at pbl[(st*8 + k)*64 + lane] (each lane reads and writes
+    // only its own elements, in program order: no barrier)
+    double PA[K][8], PB[LPB ? 1 : K][8];
+#pragma unroll
+    for (int st = 0; st < K; ++st)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            PA[st][k] = 0.0;
+            if (LPB) pbl[(st * 8 + k) * 64 + lane] = 0.0;
+            else PB[st][k] = 0.0;
+        }
 
-    // CAND: candidates for the prediction of lambda*_{n+3} (see PredCand).
-    // A row's cells are decided when the row after it is known: l of rows
-    // o2-1 (lp, pending) and o2-2 (lpp) in this lane, -1 outside the tile;
-    // the wave's largest bound so far, the threshold CAND_REL below it (at
-    // least the launch's floor), and the first lane of the pending row that
-    // raised the largest bound (-1: none).
-    double thr = CAND ? g.t0 : 0.0, wmax = 0.0, lp = -1.0, lpp = -1.0;
-    int rec_prev = -1;
-    auto candidates = [&](double lc, int o2) {
+    // CAND: candidates for the prediction of the next launch's bounds (see
+    // PredCand).  A row's cells are decided when the row after it is known:
+    // l of rows o-1 (lp, pending) and o-2 (lpp) in this lane, -1 outside the
+    // tile; the wave's largest bound so far, the threshold CAND_REL below it
+    // (at least the launch's floor), and the first lane of the pending row
+    // that raised the largest bound (-1: none) -- wave-uniform, in scalar
+    // registers.  Each lane keeps the largest cell of its column that
+    // qualified (cbest, row crow; -1: none) and lists it when the tile ends:
+    // nothing but selects in the row loop.
+    double thr = CAND ? g.t0 : 0.0, wmax = 0.0, lp = -1.0, lpp = -1.0, cbest = -1.0;
+    int rec_prev = -1, crow = 0;
+    auto candidates = [&](double lc, int o) {
         int rec_cur = -1;
         if (__any(lc > thr)) {
-            const double rowmax = wave_max(lc);
+            const double rowmax = uniform(wave_max(lc));
             if (rowmax > wmax) {
-                rec_cur = __ffsll((long long)__ballot(lc == rowmax)) - 1;
+                rec_cur = __builtin_amdgcn_readfirstlane(
+                    __ffsll((long long)__ballot(lc == rowmax)) - 1);
                 wmax = rowmax;
-                thr = fmax(g.t0, wmax * (1.0 - CAND_REL));
+                thr = uniform(fmax(g.t0, wmax * (1.0 - CAND_REL)));
             }
         }
-        // row o2-1: a cell goes in when its bound is above the threshold and
+        // row o-1: a cell qualifies when its bound is above the threshold and
         // no neighbour's exceeds it (a neighbour outside the tile is
         // ignored), except inside a flat region, which leaves only the cell
         // that first reached its value
@@ -195,163 +232,132 @@ __device__ __forceinline__ void march_pair(const PairGeom& g, int strip, int y0,
                              (lpp < 0.0 || lp >= lpp) && (lc < 0.0 || lp >= lc);
             const bool flat = (ll < 0.0 || lp == ll) && (lr < 0.0 || lp == lr) &&
                               (lpp < 0.0 || lp == lpp) && (lc < 0.0 || lp == lc);
-            const bool emit = lp > thr && top && (!flat || lane == rec_prev);
-            const unsigned long long m = __ballot(emit);
-            if (m) {
-                unsigned base = 0;
-                if (lane == 0) base = atomicAdd(&g.ph->ncand, (unsigned)__popcll(m));
-                base = __shfl(base, 0, 64);
-                if (emit) {
-                    const unsigned idx = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
-                    if (idx < (unsigned)PRED_CAP) {
-                        g.cand[idx].cell = (long long)(o2 - 1) * nx + x;
-                        g.cand[idx].l = lp;
-                    }
-                }
-            }
+            const bool take = lp > thr && top && (!flat || lane == rec_prev) && lp > cbest;
+            cbest = take ? lp : cbest;
+            crow = take ? o - 1 : crow;
         }
         rec_prev = rec_cur;
         lpp = lp;
         lp = lc;
     };
-
-    // Row r of f^n (in cur) completes row r-1 of f^{n+1} and, with TWO, row
-    // r-2 of f^{n+2}; row r+1 is loaded into nxt first, so that it is in
-    // flight while row r is computed.  One copy of this code serves every
-    // row: two inlined copies may be contracted into different multiply-adds
-    // by the compiler, and rows would then round differently.
-    auto row = [&](double (&cur)[16], double (&nxt)[16], int r) {
-        // lockstep with the workgroup's neighbouring strips (equal trip counts)
-        if (WPB > 1) __builtin_amdgcn_s_barrier();
-        load_row(nxt, g.fin, g.ps, g.rs, map_index(r + 1, ny, py), xl);
-        moments_d2q4(cur, U);
-        if (TAPE) tape_row(g.tape0, g.tape_ps, nx, r, y0, y1, voff, U);  // U^n of row r
-        collide_hops(cur, U, gm1, g.c4lam1, g.omega, h);
-        const int o1 = r - 1;
-        double g1[16];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            g1[0 * 4 + k] = h.d0[k];
-            g1[1 * 4 + k] = h.d1[k];
-            g1[2 * 4 + k] = B3[k];
-            g1[3 * 4 + k] = B4[k];
-            B3[k] = A3[k];
-            B4[k] = A4[k];
-            A3[k] = h.u2[k];
-            A4[k] = h.u3[k];
-        }
-        wall_images(g1, whi && o1 == ny - 1, wlo && o1 == 0, wxlo, wxhi);
-        if (xfix) {
-            // a clamped side: beyond it, f^{n+1} is the edge column's
-#pragma unroll
-            for (int p = 0; p < 16; ++p) {
-                const double fr = lane_from_right(g1[p]);
-                const double fl = lane_from_left(g1[p]);
-                g1[p] = x == -1 ? fr : (x == nx ? fl : g1[p]);
+    auto list_candidates = [&]() {
+        const bool emit = cbest > thr;
+        const unsigned long long m = __ballot(emit);
+        if (m) {
+            unsigned base = 0;
+            if (lane == 0) base = atomicAdd(&g.ph->ncand, (unsigned)__popcll(m));
+            base = __shfl(base, 0, 64);
+            if (emit) {
+                const unsigned idx = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+                if (idx < (unsigned)PRED_CAP) {
+                    g.cand[idx].cell = (long long)crow * nx + x;
+                    g.cand[idx].l = cbest;
+                }
             }
-        }
-        double U1[4], l1;
-        moments_d2q4(g1, U1);
-        const bool own1 = out_lane && o1 >= y0 && o1 < y1;
-        if (TAPE && TWO) tape_row(g.tape1, g.tape_ps, nx, o1, y0, y1, voff, U1);  // U^{n+1}
-        const bool ok1 = bound_d2q4(U1, g.gamma, &l1);
-        bad1 |= own1 && !ok1;
-        lm1 = fmax(lm1, own1 ? l1 : 0.0);
-        if (!TWO) {
-            // (a bound-only launch drops the row: out-of-range offset)
-            store_full_row(g.fout + (long long)o1 * g.rs, g.ps, row_bytes,
-                           store ? voff : 0x7fffffff, g1);
-            if (CAND) candidates(own1 && ok1 ? l1 : -1.0, o1);
-            return;
-        }
-        // second step: row q = o1 of f^{n+1} completes row q - 1 of f^{n+2}
-        const int q = o1;
-        Hops h2;
-        collide_hops(g1, U1, gm1, g.c4lam2, g.omega, h2);
-        {
-            // row q - 1 of f^{n+2}, an output row once q > y0.  The store is
-            // unconditional (an out-of-range offset is dropped by the buffer
-            // range check), so the wait for the next row's loads never has
-            // to cover this row's stores.
-            const bool row_out = q > y0 && q - 1 < y1;
-            const int o2 = row_out ? q - 1 : y0;
-            // at a clamped top, row ny of f^{n+1} is row ny-1 again: its
-            // downward hops were kept in P at q = ny-1
-            const bool top_virtual = clamp_hi && q == ny;
-            double g2[16];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                g2[0 * 4 + k] = top_virtual ? P3[k] : h2.d0[k];
-                g2[1 * 4 + k] = top_virtual ? P4[k] : h2.d1[k];
-                g2[2 * 4 + k] = Q3[k];
-                g2[3 * 4 + k] = Q4[k];
-            }
-            // (the wall rows by the row's own index: the filter also reads the
-            // halo rows y0-1 and y1, which are not stored)
-            wall_images(g2, whi && q - 1 == ny - 1, wlo && q - 1 == 0, wxlo, wxhi);
-            store_full_row(g.fout + (long long)o2 * g.rs, g.ps, row_bytes,
-                           row_out ? voff : 0x7fffffff, g2);
-            double U2[4], l2;
-            moments_d2q4(g2, U2);
-            const bool ok2 = bound_d2q4(U2, g.gamma, &l2);
-            const bool own2 = out_lane && row_out;
-            bad2 |= own2 && !ok2;
-            lm2 = fmax(lm2, own2 ? l2 : 0.0);
-            // at a clamped bottom, row -1 of f^{n+1} is row 0 again; at a
-            // clamped top, keep row ny-1's downward hops for the virtual row
-            // ny (the hops are dead after this, before the filter's work)
-            const bool lo_edge = clamp_lo && q == 0;
-            const bool hi_edge = clamp_hi && q == ny - 1;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                Q3[k] = lo_edge ? h2.u2[k] : P3[k];
-                Q4[k] = lo_edge ? h2.u3[k] : P4[k];
-                P3[k] = hi_edge ? h2.d0[k] : h2.u2[k];
-                P4[k] = hi_edge ? h2.d1[k] : h2.u3[k];
-            }
-            if (CAND) candidates(own2 && ok2 ? l2 : -1.0, q - 1);
         }
     };
 
-    // prologue: rows a0-1 and a0 of f^n fill the first step's pipeline
-    double f[16], nxt[16];
-    load_row(f, g.fin, g.ps, g.rs, map_index(a0 - 1, ny, py), xl);
-    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0, ny, py), xl);
-    moments_d2q4(f, U);
-    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
+    double cur[16], nxt[16], Uc[4];
+    load_row(nxt, g.fin, g.ps, g.rs, map_index(y0 - K, ny, py), xl);
+    for (int r = y0 - K; r <= y1 + K - 1; ++r) {
+        // lockstep with the workgroup's neighbouring strips (equal trip counts)
+        if (WPB > 1) __builtin_amdgcn_s_barrier();
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        A3[k] = h.u2[k];
-        A4[k] = h.u3[k];
+        for (int p = 0; p < 16; ++p) cur[p] = nxt[p];
+        // row r+1 in flight while row r is computed
+        load_row(nxt, g.fin, g.ps, g.rs, map_index(r + 1, ny, py), xl);
+        moments_d2q4(cur, Uc);
+        if (TAPE) tape_row(g.tape[0], g.tape_ps, nx, r, y0, y1, voff, Uc);  // U^n of row r
+#pragma unroll
+        for (int st = 0; st < K; ++st) {
+            const int j = r - st;  // input row of step st
+            const int o = j - 1;   // its output row
+            const Euler2 e = euler2(Uc, gm1);
+            double fs[16];
+            collide_d2q4(cur, Uc, e, g.c4lam[st], g.omega, fs);
+            double d0[4], d1[4], u2[4], u3[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                d0[k] = lane_from_right(fs[0 * 4 + k]);
+                d1[k] = lane_from_left(fs[1 * 4 + k]);
+                u2[k] = lane_from_left(fs[2 * 4 + k]);
+                u3[k] = lane_from_right(fs[3 * 4 + k]);
+            }
+            // output row o: the downward movers of row j (at a clamped top,
+            // for the virtual row ny, those kept from row ny-1), the upward
+            // movers of row j-2
+            const bool topv = st > 0 && clamp_hi && j == ny;
+            const bool lo_edge = st > 0 && clamp_lo && j == 0;
+            const bool hi_edge = st > 0 && clamp_hi && j == ny - 1;
+            double gq[16];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                gq[0 * 4 + k] = topv ? PA[st][k] : d0[k];
+                gq[1 * 4 + k] = topv ? PA[st][4 + k] : d1[k];
+                const double b2 = lo_edge ? u2[k] : PA[st][k];
+                const double b3 = lo_edge ? u3[k] : PA[st][4 + k];
+                if (LPB) {
+                    double* e2 = pbl + (st * 8 + k) * 64 + lane;
+                    double* e3 = pbl + (st * 8 + 4 + k) * 64 + lane;
+                    gq[2 * 4 + k] = *e2;
+                    gq[3 * 4 + k] = *e3;
+                    *e2 = b2;
+                    *e3 = b3;
+                } else {
+                    gq[2 * 4 + k] = PB[LPB ? 0 : st][k];
+                    gq[3 * 4 + k] = PB[LPB ? 0 : st][4 + k];
+                    PB[LPB ? 0 : st][k] = b2;
+                    PB[LPB ? 0 : st][4 + k] = b3;
+                }
+                PA[st][k] = hi_edge ? d0[k] : u2[k];
+                PA[st][4 + k] = hi_edge ? d1[k] : u3[k];
+            }
+            wall_images(gq, whi && o == ny - 1, wlo && o == 0, wxlo, wxhi);
+            if (st < K - 1 && xfix) {
+                // a clamped side: beyond it, the next step pulls the edge column's values
+#pragma unroll
+                for (int p = 0; p < 16; ++p) {
+                    const double fr = lane_from_right(gq[p]);
+                    const double fl = lane_from_left(gq[p]);
+                    gq[p] = x == -1 ? fr : (x == nx ? fl : gq[p]);
+                }
+            }
+            double U1[4], l1;
+            moments_d2q4(gq, U1);
+            const bool own = out_lane && o >= y0 && o < y1;
+            const bool ok = bound_d2q4(U1, g.gamma, &l1);
+            bad[st] |= own && !ok;
+            lm[st] = fmax(lm[st], own ? l1 : 0.0);
+            if (st == K - 1) {
+                // an output row of the tile; the store is unconditional (an
+                // out-of-range offset is dropped by the buffer range check),
+                // so the wait for the next row's loads never has to cover it
+                const bool row_out = store && o >= y0 && o < y1;
+                store_full_row(g.fout + (long long)(row_out ? o : y0) * g.rs, g.ps, row_bytes,
+                               row_out ? voff : 0x7fffffff, gq);
+                if (CAND) candidates(own && ok ? l1 : -1.0, o);
+            } else {
+                if (TAPE) tape_row(g.tape[st + 1], g.tape_ps, nx, o, y0, y1, voff, U1);
+#pragma unroll
+                for (int p = 0; p < 16; ++p) cur[p] = gq[p];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) Uc[k] = U1[k];
+            }
+        }
     }
-#pragma unroll
-    for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-    load_row(nxt, g.fin, g.ps, g.rs, map_index(a0 + 1, ny, py), xl);
-    moments_d2q4(f, U);
-    if (TAPE && !TWO) tape_row(g.tape0, g.tape_ps, nx, a0, y0, y1, voff, U);  // U^n of row y0
-    collide_hops(f, U, gm1, g.c4lam1, g.omega, h);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        B3[k] = A3[k];
-        B4[k] = A4[k];
-        A3[k] = h.u2[k];
-        A4[k] = h.u3[k];
-        P3[k] = P4[k] = Q3[k] = Q4[k] = 0.0;
+    if (CAND) {
+        // the tile's last row is decided without the row after it
+        candidates(-1.0, y1);
+        list_candidates();
     }
-    for (int r = a0 + 1; r <= b0; ++r) {
-#pragma unroll
-        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-        row(f, nxt, r);
-    }
-    // the tile's last row is decided without the row after it
-    if (CAND) candidates(-1.0, y1);
 }
 
 __device__ inline double from_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+
 // dt and the lattice speed of one step, in the order of operations of the
 // single-step control (so that both produce the same bits).
-__device__ inline void step_size(int lam_mode, double lam_star, double lam_fixed, double dx,
+__device__ __forceinline__ void step_size(int lam_mode, double lam_star, double lam_fixed, double dx,
                                  double cfl, double t, double t_end, double& lam, double& t_new) {
     if (lam_mode == LAM_PER_STEP) {
         double dt = cfl * dx / lam_star;
@@ -369,76 +375,118 @@ __device__ inline void step_size(int lam_mode, double lam_star, double lam_fixed
     }
 }
 
-// Time control of one fused launch (identical in every thread).
+// Time control of one fused launch (identical in every thread).  Written
+// out for up to three steps, in scalars: a local array indexed by a run-time
+// step count would live in scratch memory.
+static_assert(KMAX_STEPS == 3, "the launch control is written out for three steps");
+
 struct PairCtl {
-    bool active;        // at least one step
-    bool two;           // two steps
+    bool active;        // at least one step, or a bound-only pass
+    int k;              // steps of this launch (0: none; a bound-only launch has k = 0)
     bool tentative;     // the result waits for the next launch's check
     bool bound;         // this launch only reduces the bound of f^{n+1}
-    bool accepted_bad;  // the previous launch's pair stands, with a non-physical f^{n+2}
-    bool predicted;     // this launch's guess is the predicted bound
-    bool cand;          // this launch lists candidates for the prediction of lambda*_{n+3}
+    bool accepted_bad;  // the previous launch's result stands, with a non-physical last state
+    bool predicted;     // this launch's guesses are predictions
+    bool cand;          // this launch lists candidates for the next launch's predictions
     int trust;          // saturating count of repeated bounds at the last checks (0..3)
     int check;          // outcome of the check of the previous launch (for the counters):
                         // 0 none, 1 accepted, 2 predicted and accepted, 3 rejected,
                         // 4 predicted and rejected
+    int checked_k;      // steps of the checked result
     int cur;
     long long n;
     double t, lam_used;
-    unsigned long long lstar;  // bits of lambda*_n (the bound of the current state)
-    unsigned long long guess;  // bits of the lambda*_{n+1} a tentative pair takes
+    unsigned long long lstar;         // bits of lambda*_n (the current state's bound)
+    unsigned long long g1, g2;        // bits of lambda*_{n+1}, lambda*_{n+2} taken (guessed
+                                      // or known) for steps 2 and 3
     unsigned bad;
-    double lam1, t1, lam2, t2;
-    double t0;          // floor of the candidates' bounds
-    bool pred_ok;       // the record read holds a prediction for the current state
-    unsigned long long pred;  // its bits
+    double lam1, lam2, lam3;          // lattice speed of steps 1..3
+    double t1, t2, t3;                // time after them
+    double t_out, lam_out;            // time after the last step, its speed
+    double t0;                        // floor of the candidates' bounds
+    int pred_n;                       // predictions the record read holds for the state
+    unsigned long long p1, p2;
 };
 
-__device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
+__device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
     const DevState* st = a.st;
     const PairState* ps = a.pst;
+    const bool per_step = a.lam_mode == LAM_PER_STEP;
     PairCtl c;
     Slot s = st->s[ls.sr];
-    const PairSlot q = ps->q[ls.sr];
+    // the record read field by field (a copy of the struct would go through
+    // scratch memory)
+    const PairSlot& q = ps->q[ls.sr];
     unsigned long long lstar = st->lam[ls.lr];
     unsigned bad = st->bad[ls.lr];
-    bool know_next = false, force_single = false;
-    unsigned long long next = 0ull;
+    // exact bounds of the states after steps 1 .. known of this launch
+    int known = 0;
+    unsigned long long next1 = 0ull, next2 = 0ull;
+    int force_k = 0;  // > 0: take exactly these steps (a non-physical state at the last)
     int trust = q.trust;
-    // the previous launch left a prediction for the state it produced
-    bool pred_ok = q.pred_valid != 0 && q.pred != 0ull;
+    // the previous launch left predictions for the state it produced
+    int pred_n = q.pred_valid;
+    const unsigned long long qp1 = q.pred[1], qp2 = q.pred[2];
+    if (pred_n > 0 && qp1 == 0ull) pred_n = 0;
+    if (pred_n > 1 && qp2 == 0ull) pred_n = 1;
     c.accepted_bad = false;
     c.check = 0;
-    if (q.tentative) {
-        const unsigned long long m1 = ps->lam1[ls.lr];
-        const bool b1 = ps->bad1[ls.lr] != 0u;
-        const bool exact = m1 == q.guess;
-        const bool ok = !b1 && (a.lam_mode != LAM_PER_STEP || exact);
-        if (!b1 && !q.predicted) trust = exact ? min(trust + 1, 3) : max(trust - 1, 0);
+    c.checked_k = q.tentative;
+    if (q.tentative > 0) {
+        // the first intermediate state that was non-physical or whose bound
+        // differs from the guess (0: none)
+        const int kt = q.tentative;
+        const unsigned long long m1 = ps->lamk[0][ls.lr], m2 = ps->lamk[1][ls.lr];
+        const bool b1 = ps->badk[0][ls.lr] != 0u, b2 = kt >= 3 && ps->badk[1][ls.lr] != 0u;
+        int fail = 0;
+        bool fail_bad = false;
+        next1 = m1;
+        if (b1) {
+            fail = 1;
+            fail_bad = true;
+        } else if (per_step && m1 != q.guess[1]) {
+            fail = 1;
+        } else if (kt >= 3) {
+            next2 = m2;
+            if (b2) {
+                fail = 2;
+                fail_bad = true;
+            } else if (per_step && m2 != q.guess[2]) {
+                fail = 2;
+            }
+        }
+        const bool ok = fail == 0;
+        if (!q.predicted && !b1) trust = ok ? min(trust + 1, 3) : max(trust - 1, 0);
         c.check = ok ? (q.predicted ? 2 : 1) : (q.predicted ? 4 : 3);
         if (ok) {
             c.accepted_bad = bad != 0u;
         } else {
-            // back to f^n; the bound of f^{n+1} is known now
+            // back to f^n, knowing the bounds up to the failing state
             s.t = q.t_base;
             s.n = q.n_base;
             s.cur = q.cur_base;
             lstar = q.guess_base;
             bad = 0u;
-            force_single = b1;
-            know_next = !b1;
-            next = m1;
-            pred_ok = false;
+            if (fail_bad) {
+                force_k = fail;
+                known = fail - 1;
+            } else {
+                known = fail;
+            }
+            pred_n = 0;
         }
     } else if (q.known) {
         // the previous launch reduced the bound of f^{n+1} of this state
-        const unsigned long long m1 = ps->lam1[ls.lr];
-        const bool b1 = ps->bad1[ls.lr] != 0u;
-        force_single = b1;
-        know_next = !b1;
-        next = m1;
-        if (!b1) trust = m1 == lstar ? min(trust + 1, 3) : max(trust - 1, 0);
-        pred_ok = false;
+        const unsigned long long m1 = ps->lamk[0][ls.lr];
+        const bool b1 = ps->badk[0][ls.lr] != 0u;
+        if (b1) {
+            force_k = 1;
+        } else {
+            known = 1;
+            next1 = m1;
+            trust = m1 == lstar ? min(trust + 1, 3) : max(trust - 1, 0);
+        }
+        pred_n = 0;
     }
     c.cur = s.cur;
     c.n = s.n;
@@ -449,55 +497,85 @@ __device__ inline PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
     const long long n_limit = ps->n_limit;
     c.active = bad == 0u && s.t < a.t_end && s.n < n_limit;
     const unsigned long long lbc = st->lam_bc;
-    step_size(a.lam_mode, from_bits(lstar > lbc ? lstar : lbc), st->lam_fixed, a.dx, a.cfl, s.t,
-              a.t_end, c.lam1, c.t1);
-    c.two = c.active && !force_single && c.t1 < a.t_end && s.n + 2 <= n_limit;
-    // a new pair with per-step speeds: take the predicted bound, else guess
-    // the current one while it has been repeating, else reduce it first
-    const bool per_step = a.lam_mode == LAM_PER_STEP;
-    c.predicted = c.two && !know_next && per_step && pred_ok;
-    c.bound = c.two && !know_next && per_step && !c.predicted && trust == 0;
-    if (c.bound) c.two = false;
-    c.tentative = c.two && !know_next;
-    if (a.last && (c.tentative || c.bound)) c.two = c.tentative = c.bound = c.predicted = false;
+    // the most steps the time, the step limit and a forced count allow
+    int kcap = a.kmax;
+    if (force_k > 0 && force_k < kcap) kcap = force_k;
+    if (s.n + kcap > n_limit) kcap = (int)(n_limit - s.n);
+    // where the speeds of steps 2 and 3 come from: known bounds, else
+    // predictions, else the current bound while it has been repeating (a
+    // guess), else a bound-only pass first
+    const bool use_pred = per_step && known == 0 && pred_n > 0;
+    int kguess;  // steps reachable with known or guessed speeds
+    if (!per_step) kguess = 3;
+    else if (known > 0) kguess = known + 1;
+    else if (use_pred) kguess = pred_n + 1;
+    else kguess = trust > 0 ? 3 : 1;
+    if (kcap > kguess) kcap = kguess;
+    c.g1 = known >= 1 ? next1 : (use_pred ? qp1 : lstar);
+    c.g2 = known >= 2 ? next2 : (use_pred ? qp2 : lstar);
+    const double fix = st->lam_fixed;
+    step_size(a.lam_mode, from_bits(lstar > lbc ? lstar : lbc), fix, a.dx, a.cfl, s.t, a.t_end,
+              c.lam1, c.t1);
+    step_size(a.lam_mode, from_bits(c.g1 > lbc ? c.g1 : lbc), fix, a.dx, a.cfl, c.t1, a.t_end,
+              c.lam2, c.t2);
+    step_size(a.lam_mode, from_bits(c.g2 > lbc ? c.g2 : lbc), fix, a.dx, a.cfl, c.t2, a.t_end,
+              c.lam3, c.t3);
+    // each step runs when the one before did, it is within the caps and the
+    // time before it is short of t_end
+    c.k = 0;
+    if (c.active && kcap >= 1) c.k = 1;
+    if (c.k == 1 && kcap >= 2 && c.t1 < a.t_end) c.k = 2;
+    if (c.k == 2 && kcap >= 3 && c.t2 < a.t_end) c.k = 3;
+    // an intermediate state whose bound is not yet known: the speed after it
+    // is a guess (per-step speeds), or its positivity is unchecked
+    c.tentative = c.k >= 2 && c.k - 1 > known;
+    c.predicted = c.tentative && use_pred;
+    // per-step speeds with nothing to guess from: reduce the bound first
+    c.bound = per_step && c.active && known == 0 && !use_pred && trust == 0 && force_k == 0 &&
+              a.kmax >= 2 && s.n + 2 <= n_limit && c.t1 < a.t_end;
+    if (c.bound) c.k = 0;
+    // the last launch of a call leaves an ordinary time state
+    if (a.last && (c.tentative || c.bound)) {
+        c.k = c.bound ? 1 : (per_step ? min(c.k, known + 1) : 1);
+        c.tentative = c.bound = c.predicted = false;
+    }
     c.trust = trust;
-    c.lam2 = c.lam1;
-    c.t2 = c.t1;
-    c.guess = c.predicted ? q.pred : lstar;
-    const unsigned long long l2 = know_next ? next : c.guess;
-    if (c.two)
-        step_size(a.lam_mode, from_bits(l2 > lbc ? l2 : lbc), st->lam_fixed, a.dx, a.cfl, c.t1,
-                  a.t_end, c.lam2, c.t2);
-    // candidates for the prediction of the bound after the next launch's
-    // first step: bounds of the state this launch leaves (U^{n+2}, or U^{n+1}
-    // of a one-step launch) from CAND_REL below the last known one up
-    c.cand = c.active && !c.bound && per_step && a.cand != nullptr &&
-             (c.two ? c.t2 : c.t1) < a.t_end;
-    c.t0 = c.cand ? from_bits(c.two ? l2 : lstar) * (1.0 - CAND_REL) : 0.0;
-    c.pred_ok = pred_ok;
-    c.pred = q.pred;
+    c.t_out = c.k == 3 ? c.t3 : (c.k == 2 ? c.t2 : c.t1);
+    c.lam_out = c.k == 3 ? c.lam3 : (c.k == 2 ? c.lam2 : c.lam1);
+    // candidates for the predictions of the next launch's bounds: bounds of
+    // the state this launch leaves from CAND_REL below the last known or
+    // guessed one up
+    c.cand = c.active && c.k > 0 && per_step && a.cand != nullptr && c.t_out < a.t_end;
+    const unsigned long long lref = c.k == 3 ? c.g2 : (c.k == 2 ? c.g1 : lstar);
+    c.t0 = c.cand ? from_bits(lref) * (1.0 - CAND_REL) : 0.0;
+    c.pred_n = pred_n;
+    c.p1 = qp1;
+    c.p2 = qp2;
     return c;
 }
 
-// Block 0, thread 0: the time state after this launch and its pair record;
-// clears the accumulators of launch p+2; arms the prediction kernel.
-__device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const PairCtl& c) {
+// Block 0, thread 0: the time state after this launch and its record;
+// clears the accumulators of launch p+2; arms the prediction kernels.
+__device__ __forceinline__ void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const PairCtl& c) {
     DevState* st = a.st;
     PairState* ps = a.pst;
     Slot s;
     s.pad = 0;
-    PairSlot q;
+    // written field by field into the slot (see pair_control)
+    PairSlot& q = ps->q[ls.sw];
     q.t_base = c.t;
     q.n_base = c.n;
     q.cur_base = c.cur;
-    q.guess = c.guess;
+    q.guess[0] = 0ull;
+    q.guess[1] = c.k >= 2 ? c.g1 : 0ull;
+    q.guess[2] = c.k >= 3 ? c.g2 : 0ull;
+    q.pred[0] = q.pred[1] = q.pred[2] = 0ull;
     q.guess_base = c.lstar;
     q.tentative = 0;
     q.known = 0;
     q.trust = c.trust;
     q.pred_valid = 0;
     q.predicted = c.predicted ? 1 : 0;
-    q.pred = 0ull;
     if (!c.active) {
         s.t = c.t;
         s.n = c.n;
@@ -505,11 +583,12 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
         s.cur = c.cur;
         st->lam[ls.la] = c.lstar;
         st->bad[ls.la] = c.bad;
-        // the state stays: so does a prediction for it (also into the next call)
-        q.pred_valid = c.pred_ok ? 1 : 0;
-        q.pred = c.pred;
+        // the state stays: so do predictions for it (also into the next call)
+        q.pred_valid = c.pred_n;
+        q.pred[1] = c.p1;
+        q.pred[2] = c.p2;
     } else if (c.bound) {
-        // no step: the state and its bound carry over; the first-step
+        // no step: the state and its bound carry over; the first intermediate
         // accumulators receive the bound of f^{n+1}
         s.t = c.t;
         s.n = c.n;
@@ -518,43 +597,44 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
         st->lam[ls.la] = c.lstar;
         st->bad[ls.la] = 0u;
         q.known = 1;
-    } else if (!c.two) {
-        s.t = c.t1;
-        s.n = c.n + 1;
-        s.lam_used = c.lam1;
-        s.cur = c.cur ^ 1;
     } else {
-        s.t = c.t2;
-        s.n = c.n + 2;
-        s.lam_used = c.lam2;
+        s.t = c.t_out;
+        s.n = c.n + c.k;
+        s.lam_used = c.lam_out;
         s.cur = c.cur ^ 1;
-        q.tentative = c.tentative ? 1 : 0;
+        q.tentative = c.tentative ? c.k : 0;
     }
     st->s[ls.sw] = s;
-    ps->q[ls.sw] = q;
     st->lam[ls.lz] = 0ull;
     st->bad[ls.lz] = 0u;
-    ps->lam1[ls.lz] = 0ull;
-    ps->bad1[ls.lz] = 0u;
+#pragma unroll
+    for (int i = 0; i < KMAX_STEPS - 1; ++i) {
+        ps->lamk[i][ls.lz] = 0ull;
+        ps->badk[i][ls.lz] = 0u;
+    }
     // this launch's candidate header (its candidate count was cleared by the
     // launch before) and the next launch's, whose last user, the prediction
     // after the launch before, has finished
     PredHeader& h = ps->pred[a.launch & 1];
     h.armed = c.cand ? 1 : 0;
     h.cur_out = c.cur ^ 1;
-    h.t2 = c.two ? c.t2 : c.t1;
+    h.t2 = c.t_out;
     PredHeader& hn = ps->pred[(a.launch + 1) & 1];
     hn.armed = 0;
     hn.ncand = 0u;
     // counters
     if (c.check >= 3) ps->stat[PST_REJECTED] += 1;
     else if (c.check > 0) ps->stat[PST_PAIRS] += 1;
+    if (c.check > 0 && c.check < 3 && c.checked_k == 3) ps->stat[PST_STEPS3] += 1;
     if (c.check == 2) ps->stat[PST_PRED_HIT] += 1;
     if (c.check == 4) ps->stat[PST_PRED_MISS] += 1;
     if (c.active) {
         if (c.bound) ps->stat[PST_BOUND_ONLY] += 1;
-        else if (!c.two) ps->stat[PST_SINGLE] += 1;
-        else if (!c.tentative) ps->stat[PST_PAIRS] += 1;
+        else if (c.k == 1) ps->stat[PST_SINGLE] += 1;
+        else if (!c.tentative) {
+            ps->stat[PST_PAIRS] += 1;
+            if (c.k == 3) ps->stat[PST_STEPS3] += 1;
+        }
     }
     if (c.accepted_bad) {
         atomicOr(&st->status, 1u);
@@ -562,9 +642,34 @@ __device__ inline void publish_pair(const Pair2DArgs& a, LaunchSlots ls, const P
     }
 }
 
+// One strip and row segment of a launch in its number of steps.  (The form
+// that lists candidates runs its own march also where it lists none: its
+// floor is then infinite.)
+template <int WPB, int KM, bool TAPE, bool CAND, bool LPB>
+__device__ __forceinline__ void march_launch(const PairGeom& g, int k, bool store, int strip,
+                                             int y0, int y1, int lane, double (&lm)[KMAX_STEPS],
+                                             bool (&bad)[KMAX_STEPS], double* pbl) {
+    if (KM >= 3 && k == 3)
+        march_k<WPB, (KM >= 3 ? 3 : 1), TAPE, CAND, LPB>(g, strip, y0, y1, lane, lm, bad, true,
+                                                         pbl);
+    else if (k == 2)
+        march_k<WPB, 2, TAPE, CAND, LPB>(g, strip, y0, y1, lane, lm, bad, true, pbl);
+    else
+        march_k<WPB, 1, TAPE, CAND, LPB>(g, strip, y0, y1, lane, lm, bad, store, pbl);
+}
+
+// Three-step kernels keep the second row of their pipelines in LDS (the
+// registers of the first, the prefetched row and the step's own values fill
+// the budget of two waves per SIMD), and so do 12-wave workgroups (three
+// waves per SIMD).
+template <int WPB, int KM>
+struct PipelineInLds {
+    static constexpr bool value = KM >= 3 || WPB >= 12;
+};
+
 }  // namespace
 
-template <int WPB, bool TAPE, bool CAND>
+template <int WPB, bool TAPE, bool CAND, int KM>
 __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     const LaunchSlots ls = slots_for(a.launch);
     const PairCtl c = pair_control(a, ls);
@@ -574,7 +679,7 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     PairGeom g;
-    // f^{n+2} (or f^{n+1}) goes to the other buffer; f^n stays intact
+    // the result goes to the other buffer; f^n stays intact
     g.fin = c.cur ? a.f1 : a.f0;
     g.fout = c.cur ? a.f0 : a.f1;
     g.ps = a.ps;
@@ -582,110 +687,166 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     g.nx = a.nx;
     g.ny = a.ny;
     g.strip = a.strip;
-    g.c4lam1 = 1.0 / (4.0 * c.lam1);
-    g.c4lam2 = 1.0 / (4.0 * c.lam2);
+    g.c4lam[0] = 1.0 / (4.0 * c.lam1);
+    g.c4lam[1] = 1.0 / (4.0 * (c.k >= 2 ? c.lam2 : c.lam1));
+    g.c4lam[2] = 1.0 / (4.0 * (c.k >= 3 ? c.lam3 : c.lam1));
     g.omega = a.omega;
     g.gamma = a.gamma;
     for (int s = 0; s < 4; ++s) g.bc[s] = a.bc[s];
-    g.tape0 = a.tape0;
-    g.tape1 = a.tape1;
+    g.tape[0] = a.tape0;
+    g.tape[1] = a.tape1;
+#pragma unroll
+    for (int i = 2; i < KMAX_STEPS; ++i) g.tape[i] = nullptr;
     g.tape_ps = a.plane;
-    g.t0 = c.t0;
+    g.t0 = c.cand ? c.t0 : INFINITY;
     g.ph = &a.pst->pred[a.launch & 1];
     g.cand = a.cand;
     const int total_waves = gridDim.x * WPB;
     const int ny = a.ny;
+    // a bound-only pass marches one step and stores nothing
+    const int km = c.bound ? 1 : c.k;
 
-    double lm1 = 0.0, lm2 = 0.0;
-    bool bad1 = false, bad2 = false;
+    double lm[KMAX_STEPS];
+    bool bad[KMAX_STEPS];
+#pragma unroll
+    for (int i = 0; i < KMAX_STEPS; ++i) {
+        lm[i] = 0.0;
+        bad[i] = false;
+    }
+    constexpr bool LPB = PipelineInLds<WPB, KM>::value;
+    __shared__ double pb_lds[LPB ? WPB * KM * 8 * 64 : 1];
+    double* pbl = pb_lds + (LPB ? wave * KM * 8 * 64 : 0);
     for (int tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wave; tile < a.ntiles;
          tile += total_waves) {
         const int strip = tile % a.nstrips;
         const int seg = tile / a.nstrips;
         const int y0 = (int)(((long long)seg * ny) / a.nseg);
         const int y1 = (int)(((long long)(seg + 1) * ny) / a.nseg);
-        if (c.two) {
-            if (CAND && c.cand)
-                march_pair<WPB, true, false, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
-            else
-                march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
-        } else {
-            if (CAND && c.cand)
-                march_pair<WPB, false, false, true>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
-            else
-                march_pair<WPB, false, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2,
-                                             !c.bound);
-        }
+        march_launch<WPB, KM, TAPE, CAND, LPB>(g, km, !c.bound, strip, y0, y1, lane, lm, bad,
+                                               pbl);
     }
 
     const bool per_step = a.lam_mode == LAM_PER_STEP;
-    if (c.two) {
-        if (per_step) {
-            const double w1 = wave_max(lm1), w2 = wave_max(lm2);
-            if (lane == 0) {
-                publish_max(&a.pst->lam1[ls.la], w1);
-                publish_max(&a.st->lam[ls.la], w2);
+    // the intermediate states (checked by the next launch)
+#pragma unroll
+    for (int i = 0; i < KMAX_STEPS - 1; ++i) {
+        if (i < km - 1 || (c.bound && i == 0)) {
+            if (per_step) {
+                const double w = wave_max(lm[i]);
+                if (lane == 0) publish_max(&a.pst->lamk[i][ls.la], w);
+            }
+            if (__any(bad[i]) && lane == 0) atomicOr(&a.pst->badk[i][ls.la], 1u);
+        }
+    }
+    if (!c.bound) {
+        // the state this launch leaves
+        double wl = 0.0;
+        bool wb = false;
+#pragma unroll
+        for (int i = 0; i < KMAX_STEPS; ++i) {
+            if (i == km - 1) {
+                wl = lm[i];
+                wb = bad[i];
             }
         }
-        if (__any(bad1) && lane == 0) atomicOr(&a.pst->bad1[ls.la], 1u);
-        if (__any(bad2) && lane == 0) {
-            // a tentative f^{n+2} is reported by the launch that accepts it
-            if (c.tentative) atomicOr(&a.st->bad[ls.la], 1u);
-            else publish_bad(a.st, ls, c.n + 2);
-        }
-    } else if (c.bound) {
-        const double w1 = wave_max(lm1);
-        if (lane == 0) publish_max(&a.pst->lam1[ls.la], w1);
-        if (__any(bad1) && lane == 0) atomicOr(&a.pst->bad1[ls.la], 1u);
-    } else {
         if (per_step) {
-            const double w1 = wave_max(lm1);
-            if (lane == 0) publish_max(&a.st->lam[ls.la], w1);
+            const double w = wave_max(wl);
+            if (lane == 0) publish_max(&a.st->lam[ls.la], w);
         }
-        if (__any(bad1) && lane == 0) publish_bad(a.st, ls, c.n + 1);
+        if (__any(wb) && lane == 0) {
+            // a tentative result is reported by the launch that accepts it
+            if (c.tentative) atomicOr(&a.st->bad[ls.la], 1u);
+            else publish_bad(a.st, ls, c.n + km);
+        }
     }
 }
 
-// The prediction after fused launch a.launch: the exact bound of the state
-// after the next launch's first step on the 3 x 3 cells around every
-// candidate the launch listed whose bound of U^{n+2} is within CAND_REL of
-// lambda*_{n+2}, by the first step's own arithmetic (f^{n+2} of the cell's
-// four pull sources, their collision at the now known speed of step n+2,
-// the pulls, walls, moments, bound: the same device functions, so the same
-// bits), maxed into the pair record the next launch reads.  None when the
-// launch listed no candidates or more than the list holds, or met a
-// non-physical state.  PRED_BLOCKS workgroups stride over (candidate,
-// neighbour) pairs; workgroup 0 also sets the record's validity and counters.
+namespace {
+
+// The populations of cell (x, y) after one step from f (pulls of the
+// post-collision values of its four diagonal neighbours at 1/(4 lambda) =
+// c4, then the walls), by the step kernels' own device functions.  f may be
+// any state of the domain: beyond a clamped side its ghost is the edge cell
+// (map_index), as the fused launches treat the states between their steps.
+template <typename Src>
+__device__ inline void pulled_cell(const Pair2DArgs& a, int x, int y, double c4, const Src& src,
+                                   double g1[16]) {
+    const int nx = a.nx, ny = a.ny;
+    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
+    const int sxs[4] = {-1, 1, 1, -1}, sys[4] = {-1, -1, 1, 1};
+    const double gm1 = a.gamma - 1.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int xs = map_index(x - sxs[j], nx, px), ys = map_index(y - sys[j], ny, py);
+        double f[16], U[4], fs[16];
+        src(xs, ys, f);
+        moments_d2q4(f, U);
+        const Euler2 eu = euler2(U, gm1);
+        collide_d2q4(f, U, eu, c4, a.omega, fs);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g1[j * 4 + k] = fs[j * 4 + k];
+    }
+    wall_images(g1, a.bc[3] == BC_WALL && y == ny - 1, a.bc[2] == BC_WALL && y == 0,
+                a.bc[0] == BC_WALL && x == 0, a.bc[1] == BC_WALL && x == nx - 1);
+}
+
+}  // namespace
+
+// The predictions after fused launch a.launch, for the state S it leaves:
+// level L (1 or 2) evaluates the exact bound of the state after L steps from
+// S on the 3 x 3 cells around every listed candidate whose bound is within
+// CAND_REL of lambda*(S) -- by the step kernels' own device functions, so
+// the same bits -- and maxes it into pred[L] of the record the next launch
+// reads.  Step 1 runs at the speed from lambda*(S) (known now), step 2 at the
+// speed from the level-1 prediction (read from the record, so level 2 is a
+// second launch).  None when the launch listed no candidates or more than
+// the list holds, or met a non-physical state.  PRED_BLOCKS workgroups
+// stride over (candidate, neighbour) pairs; workgroup 0 also sets the
+// record's count of valid levels and the counters.
 static constexpr int PRED_BLOCKS = 64;
 
-__global__ __launch_bounds__(256) void pair_predict_kernel(Pair2DArgs a) {
+__global__ __launch_bounds__(256) void pair_predict_kernel(Pair2DArgs a, int level) {
     const LaunchSlots ls = slots_for(a.launch);
     PairState* ps = a.pst;
     const PredHeader* h = &ps->pred[a.launch & 1];
+    PairSlot* q = &ps->q[ls.sw];
     const int tid = threadIdx.x;
     const unsigned ncand = h->ncand;
-    const bool ok = h->armed != 0 && ncand > 0u && ncand <= (unsigned)PRED_CAP &&
-                    a.st->bad[ls.la] == 0u;
+    bool ok = h->armed != 0 && ncand > 0u && ncand <= (unsigned)PRED_CAP &&
+              a.st->bad[ls.la] == 0u;
+    if (level == 2) ok = ok && q->pred_valid >= 1 && q->pred[1] != 0ull;
     if (blockIdx.x == 0 && tid == 0 && h->armed) {
         // (a launch that listed nothing keeps what its record carries)
-        ps->q[ls.sw].pred_valid = ok ? 1 : 0;
-        ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
-        ps->stat[PST_LISTED] += ncand;
-        if (ncand > (unsigned)PRED_CAP) ps->stat[PST_OVERFLOW] += 1;
+        if (level == 1) {
+            q->pred_valid = ok ? 1 : 0;
+            ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
+            ps->stat[PST_LISTED] += ncand;
+            if (ncand > (unsigned)PRED_CAP) ps->stat[PST_OVERFLOW] += 1;
+        } else if (ok) {
+            q->pred_valid = 2;
+        }
     }
     if (!ok) return;
     const unsigned long long lb = a.st->lam[ls.la];
     const unsigned long long lbc = a.st->lam_bc;
-    const double lstar = from_bits(lb > lbc ? lb : lbc);
     const double floor_l = from_bits(lb) * (1.0 - CAND_REL);
-    double lam, tn;
-    step_size(LAM_PER_STEP, lstar, 0.0, a.dx, a.cfl, h->t2, a.t_end, lam, tn);
-    const double c4lam = 1.0 / (4.0 * lam);
-    const double gm1 = a.gamma - 1.0;
+    // the speeds of the next launch's first two steps
+    double lam1, t1, lam2, t2;
+    step_size(LAM_PER_STEP, from_bits(lb > lbc ? lb : lbc), 0.0, a.dx, a.cfl, h->t2, a.t_end, lam1,
+              t1);
+    const unsigned long long p1 = q->pred[1];
+    step_size(LAM_PER_STEP, from_bits(p1 > lbc ? p1 : lbc), 0.0, a.dx, a.cfl, t1, a.t_end, lam2, t2);
+    if (level == 2 && !(t1 < a.t_end)) return;  // no second step
+    const double c41 = 1.0 / (4.0 * lam1), c42 = 1.0 / (4.0 * lam2);
     const double* fin = h->cur_out ? a.f1 : a.f0;
     const int nx = a.nx, ny = a.ny;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
-    const int sxs[4] = {-1, 1, 1, -1}, sys[4] = {-1, -1, 1, 1};
+    auto from_f = [&](int xs, int ys, double (&f)[16]) {
+        const double* row = fin + (long long)ys * a.rs;
+#pragma unroll
+        for (int p = 0; p < 16; ++p) f[p] = row[p * a.ps + xs];
+    };
+    auto after_one = [&](int xs, int ys, double (&f)[16]) { pulled_cell(a, xs, ys, c41, from_f, f); };
     double best = 0.0;
     unsigned evaluated = 0;
     const unsigned work = ncand * 9u;
@@ -698,24 +859,11 @@ __global__ __launch_bounds__(256) void pair_predict_kernel(Pair2DArgs a) {
         if (py) y = map_index(y, ny, true);
         if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
         ++evaluated;
-        double g1[16];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int xs = map_index(x - sxs[j], nx, px), ys = map_index(y - sys[j], ny, py);
-            double f[16], U[4], fs[16];
-            const double* row = fin + (long long)ys * a.rs;
-#pragma unroll
-            for (int p = 0; p < 16; ++p) f[p] = row[p * a.ps + xs];
-            moments_d2q4(f, U);
-            const Euler2 eu = euler2(U, gm1);
-            collide_d2q4(f, U, eu, c4lam, a.omega, fs);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) g1[j * 4 + k] = fs[j * 4 + k];
-        }
-        wall_images(g1, a.bc[3] == BC_WALL && y == ny - 1, a.bc[2] == BC_WALL && y == 0,
-                    a.bc[0] == BC_WALL && x == 0, a.bc[1] == BC_WALL && x == nx - 1);
+        double g[16];
+        if (level == 1) pulled_cell(a, x, y, c41, from_f, g);
+        else pulled_cell(a, x, y, c42, after_one, g);
         double U1[4], l1;
-        moments_d2q4(g1, U1);
+        moments_d2q4(g, U1);
         if (bound_d2q4(U1, a.gamma, &l1)) best = fmax(best, l1);
     }
     best = wave_max(best);
@@ -723,7 +871,7 @@ __global__ __launch_bounds__(256) void pair_predict_kernel(Pair2DArgs a) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
     if ((tid & 63) == 0) {
-        if (best > 0.0) publish_max(&ps->q[ls.sw].pred, best);
+        if (best > 0.0) publish_max(&q->pred[level], best);
         if (cnt) atomicAdd(&ps->stat[PST_EVALUATED], (unsigned long long)cnt);
     }
 }
@@ -756,22 +904,30 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
         g.nx = d.nx;
         g.ny = d.ny;
         g.strip = d.pstrip;
-        g.c4lam1 = g.c4lam2 = 1.0 / (4.0 * d.lam);
+#pragma unroll
+        for (int i = 0; i < KMAX_STEPS; ++i) g.c4lam[i] = 1.0 / (4.0 * d.lam);
         g.omega = d.omega;
         g.gamma = d.gamma;
         for (int s = 0; s < 4; ++s) g.bc[s] = d.bc[s];
-        g.tape0 = TAPE ? a.tape + d.coff : nullptr;
-        g.tape1 = TAPE ? a.tape2 + d.coff : nullptr;
+        g.tape[0] = TAPE ? a.tape + d.coff : nullptr;
+        g.tape[1] = TAPE ? a.tape2 + d.coff : nullptr;
+#pragma unroll
+        for (int i = 2; i < KMAX_STEPS; ++i) g.tape[i] = nullptr;
         g.tape_ps = a.total;
         const int local = (int)(tile - d.ptile0);
         const int strip = local % d.pnstrips;
         const int seg = local / d.pnstrips;
         const int y0 = (int)(((long long)seg * d.ny) / d.nseg);
         const int y1 = (int)(((long long)(seg + 1) * d.ny) / d.nseg);
-        double lm1 = 0.0, lm2 = 0.0;
-        bool bad1 = false, bad2 = false;
-        march_pair<WPB, true, TAPE>(g, strip, y0, y1, lane, lm1, bad1, lm2, bad2);
-        if (__any(bad1 || bad2) && lane == 0) atomicOr(&a.status[lo], 1u);
+        double lm[KMAX_STEPS];
+        bool bad[KMAX_STEPS];
+#pragma unroll
+        for (int i = 0; i < KMAX_STEPS; ++i) {
+            lm[i] = 0.0;
+            bad[i] = false;
+        }
+        march_k<WPB, 2, TAPE>(g, strip, y0, y1, lane, lm, bad);
+        if (__any(bad[0] || bad[1]) && lane == 0) atomicOr(&a.status[lo], 1u);
     }
 }
 
@@ -783,17 +939,18 @@ __global__ void pair_prepare_kernel(PairState* ps, const DevState* st, int slot,
         ps->q[i].n_base = 0;
         ps->q[i].cur_base = 0;
         ps->q[i].tentative = 0;
-        ps->q[i].guess = 0ull;
+        for (int j = 0; j < KMAX_STEPS; ++j) ps->q[i].guess[j] = 0ull;
         ps->q[i].guess_base = 0ull;
         ps->q[i].known = 0;
         ps->q[i].trust = 3;  // start a call by guessing
         ps->q[i].predicted = 0;
         // a prediction the last call left stays (it is only a guess: checked)
     }
-    for (int i = 0; i < 3; ++i) {
-        ps->lam1[i] = 0ull;
-        ps->bad1[i] = 0u;
-    }
+    for (int i = 0; i < KMAX_STEPS - 1; ++i)
+        for (int j = 0; j < 3; ++j) {
+            ps->lamk[i][j] = 0ull;
+            ps->badk[i][j] = 0u;
+        }
     for (int i = 0; i < 2; ++i) {
         ps->pred[i].armed = 0;
         ps->pred[i].ncand = 0u;
@@ -827,44 +984,56 @@ hipError_t launch_pair_reset(PairState* ps, bool counters, hipStream_t s) {
 }
 
 hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(pair_predict_kernel, dim3(PRED_BLOCKS), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pair_predict_kernel, dim3(PRED_BLOCKS), dim3(256), 0, s, a, 1);
+    if (a.kmax >= 3)
+        hipLaunchKernelGGL(pair_predict_kernel, dim3(PRED_BLOCKS), dim3(256), 0, s, a, 2);
     return hipGetLastError();
 }
 
-template <int WPB>
-static hipError_t launch_pair_w(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
+template <int WPB, int KM>
+static hipError_t launch_pair_wk(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
     int nblocks = (a.ntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
     // per-step speeds with a candidate list: the form that lists candidates
     const bool cand = a.cand != nullptr && a.lam_mode == LAM_PER_STEP && !tape;
     if (cand)
-        hipLaunchKernelGGL((step2d_pair<WPB, false, true>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
-    else if (tape)
-        hipLaunchKernelGGL((step2d_pair<WPB, true, false>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
-    else
-        hipLaunchKernelGGL((step2d_pair<WPB, false, false>), dim3(nblocks), dim3(64 * WPB), 0, s,
+        hipLaunchKernelGGL((step2d_pair<WPB, false, true, KM>), dim3(nblocks), dim3(64 * WPB), 0, s,
                            a);
+    else if (tape)
+        hipLaunchKernelGGL((step2d_pair<WPB, true, false, 2>), dim3(nblocks), dim3(64 * WPB), 0, s,
+                           a);
+    else
+        hipLaunchKernelGGL((step2d_pair<WPB, false, false, KM>), dim3(nblocks), dim3(64 * WPB), 0,
+                           s, a);
     return hipGetLastError();
 }
 
 template <int WPB>
-static int pair_blocks_w(bool cand) {
-    int n = 0, m = 0;
-    hipError_t e, f;
-    if (cand) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false, true>,
+static hipError_t launch_pair_w(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
+    if (a.kmax >= 3 && !tape) return launch_pair_wk<WPB, 3>(a, tape, max_blocks, s);
+    return launch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
+}
+
+template <int WPB, int KM>
+static int occupancy(bool cand, bool tape) {
+    int n = 0;
+    hipError_t e;
+    if (tape)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, true, false, 2>,
                                                          64 * WPB, 0);
-        f = e;
-        m = n;
-    } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false, false>,
+    else if (cand)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false, true, KM>,
                                                          64 * WPB, 0);
-        f = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, step2d_pair<WPB, true, false>,
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false, false, KM>,
                                                          64 * WPB, 0);
-    }
-    if (e != hipSuccess || f != hipSuccess) return 1;
-    n = n < m ? n : m;  // one persistent grid size serves both plain forms
-    return n > 0 ? n : 1;
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+template <int WPB>
+static int pair_blocks_w(bool cand, int kmax, bool tape) {
+    if (tape) return occupancy<WPB, 2>(false, true);
+    return kmax >= 3 ? occupancy<WPB, 3>(cand, false) : occupancy<WPB, 2>(cand, false);
 }
 
 #define LBRS_PAIR_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12)
@@ -878,9 +1047,9 @@ hipError_t launch_step2d_pair(const Pair2DArgs& a, int wpb, bool tape, int max_b
     return hipErrorInvalidValue;
 }
 
-int step2d_pair_blocks_per_cu(int wpb, bool cand) {
+int step2d_pair_blocks_per_cu(int wpb, bool cand, int kmax, bool tape) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return pair_blocks_w<W>(cand);
+    if (wpb == W) return pair_blocks_w<W>(cand, kmax, tape);
     LBRS_PAIR_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return 1;

@@ -38,23 +38,27 @@ def _riemann_rect(nx=301, ny=201):
     return wl.Workload("riemann_rect", wl.D2Q4, nx, ny, (0.0, nx / ny, 0.0, 1.0), W, t_end=0.03)
 
 
-def _fused(w, tile=None, layout=0, **kw):
+def _fused(w, tile=None, layout=0, fuse=2, **kw):
     sim = gpu_sim(w, layout=layout, **kw)
     sim.init_primitive(w.W)
     if tile:
         sim.set_tile(*tile)
-    sim.set_fusion(2)
+    sim.set_fusion(fuse)
     return sim
 
 
+# steps per fused launch
+FUSE = pytest.mark.parametrize("fuse", [2, 3])
+
+
 def _compare(w, t_end=math.inf, max_steps=10**9, omega=None, sides=None, lam_mode=0,
-             lam_user=0.0, tile=None, layout=0, name="", chunks=None):
+             lam_user=0.0, tile=None, layout=0, name="", chunks=None, fuse=2):
     """Run the oracle and the fused GPU path; chunks: the GPU's lbrs_step calls
     (default one call, as many steps as the oracle took, +5 when t_end stops it)."""
     P = oracle_problem(w, omega=omega, sides=sides, lam_mode=lam_mode, lam_user=lam_user)
     ref = oracle.run(P, oracle.prim_to_cons(P, w.W), t_end=t_end, max_steps=max_steps)
     sim = _fused(w, tile=tile, layout=layout, omega=omega, sides=sides, lam_mode=lam_mode,
-                 lam_user=lam_user)
+                 lam_user=lam_user, fuse=fuse)
     total = ref.nsteps + (5 if ref.status == 0 and ref.t >= t_end else 0)
     for k in (chunks or [total]):
         sim.step(k, t_end)
@@ -79,20 +83,22 @@ def _compare(w, t_end=math.inf, max_steps=10**9, omega=None, sides=None, lam_mod
 
 @pytest.mark.parametrize("tile", [(0, 4), (0, 8), (0, 1), (0, 2), (0, 6), (0, 12), (0, 16),
                                   (1, 4), (2, 2), (3, 8), (4, 1), (7, 4), (50, 2), (200, 8)])
-def test_tile_shapes_full_run(tile):
+@FUSE
+def test_tile_shapes_full_run(tile, fuse):
     """Ragged strips (<= 60 columns) and row segments shorter than the two halo
     rows, every workgroup shape, the per-step speed to t_end (clipped last
     step) on a transmissive rectangle."""
     w = _riemann_rect()
-    _compare(w, t_end=0.03, omega=1.4, tile=tile, name=f"pair tile {tile}")
+    _compare(w, t_end=0.03, omega=1.4, tile=tile, name=f"fused{fuse} tile {tile}", fuse=fuse)
 
 
 @pytest.mark.parametrize("omega", [0.6, 1.0, 1.4])
-def test_riemann_256_to_end(omega):
+@FUSE
+def test_riemann_256_to_end(omega, fuse):
     """The benchmark's problem at 256^2 to t = 0.3: the bound changes at
     dozens of steps, so guesses are rejected and repeated along the way."""
     w = wl.riemann2d(256)
-    _compare(w, t_end=0.3, omega=omega, name=f"pair riemann 256 w{omega}")
+    _compare(w, t_end=0.3, omega=omega, name=f"fused{fuse} riemann 256 w{omega}", fuse=fuse)
 
 
 def _oracle_omp_run(P, U0, **kw):
@@ -106,7 +112,8 @@ def _oracle_omp_run(P, U0, **kw):
 
 
 @pytest.mark.parametrize("n", [512, 1024])
-def test_riemann_to_end_large(n):
+@FUSE
+def test_riemann_to_end_large(n, fuse):
     """The benchmark's problem to t = 0.3 at 512^2 and 1024^2, fused launches
     with per-step speeds in the benchmark's row-interleaved layout.  The bound
     changes at nearly every step after the first few hundred, so guesses are
@@ -120,7 +127,7 @@ def test_riemann_to_end_large(n):
     assert ref.status == 0 and ref.t == 0.3
     cum = np.cumsum(ref.dt)
     for chunk in (None, 37):
-        sim = _fused(w, layout=1)
+        sim = _fused(w, layout=1, fuse=fuse)
         done = 0
         while done < ref.nsteps:
             k = ref.nsteps + 5 if chunk is None else min(chunk, ref.nsteps - done)
@@ -134,56 +141,66 @@ def test_riemann_to_end_large(n):
         U = sim.moments().cpu().numpy()
         sim.close()
         err = max_abs(U, ref.U)
-        report(f"pair riemann {n} to end, calls of {chunk or 'all'}", steps=st["nsteps"],
+        report(f"fused{fuse} riemann {n} to end, calls of {chunk or 'all'}", steps=st["nsteps"],
                oracle_steps=ref.nsteps, t=st["t"], err=err, **stats)
         assert st["t"] == ref.t
         assert err <= TOL, err
         # the path of the whole run went through checked guesses
         assert stats["rejected"] + stats["bound_only"] + stats["pred_hit"] > 0
-        # every step accounted for: pairs count two, the others one
-        assert 2 * stats["pairs"] + stats["single"] == ref.nsteps
+        # every step accounted for: accepted multi-step launches count two,
+        # three-step ones one more, single steps one
+        assert 2 * stats["pairs"] + stats["steps3"] + stats["single"] == ref.nsteps
+        if fuse == 2:
+            assert stats["steps3"] == 0
 
 
 @pytest.mark.parametrize("sides", [(1, 1, 1, 1), (1, 1, 0, 0), (0, 0, 1, 1)])
-def test_periodic(sides):
+@FUSE
+def test_periodic(sides, fuse):
     w = wl.fourier_modes(130, seed=3)
     w.sides = sides
-    _compare(w, max_steps=61, omega=1.2, sides=sides, name=f"pair periodic {sides}")
+    _compare(w, max_steps=61, omega=1.2, sides=sides, name=f"fused{fuse} periodic {sides}",
+             fuse=fuse)
 
 
 @pytest.mark.parametrize("sides", [(1, 1, 2, 2), (0, 0, 0, 2), (2, 0, 1, 1), (0, 2, 0, 0),
                                    (0, 0, 2, 0), (2, 2, 0, 0)])
 @pytest.mark.parametrize("omega", [0.7, 1.6])
-def test_walls(sides, omega):
+@FUSE
+def test_walls(sides, omega, fuse):
     """Free-slip walls on every side, with per-step speeds."""
     w = wl.explosion(96)
-    _compare(w, max_steps=81, omega=omega, sides=sides, name=f"pair wall {sides} w{omega}")
+    _compare(w, max_steps=81, omega=omega, sides=sides, name=f"fused{fuse} wall {sides} w{omega}",
+             fuse=fuse)
 
 
 @pytest.mark.parametrize("tile", [(0, 4), (3, 2), (0, 16)])
 @pytest.mark.parametrize("layout", [0, 1])
-def test_walls_and_layouts_small_segments(tile, layout):
+@FUSE
+def test_walls_and_layouts_small_segments(tile, layout, fuse):
     w = wl.explosion(70)
     _compare(w, max_steps=45, omega=1.3, sides=(2, 2, 0, 0), tile=tile, layout=layout,
-             name=f"pair walls x l{layout} {tile}")
+             name=f"fused{fuse} walls x l{layout} {tile}", fuse=fuse)
     _compare(w, max_steps=45, omega=1.3, sides=(0, 0, 2, 2), tile=tile, layout=layout,
-             name=f"pair walls y l{layout} {tile}")
+             name=f"fused{fuse} walls y l{layout} {tile}", fuse=fuse)
 
 
-def test_fixed_speeds():
+@FUSE
+def test_fixed_speeds(fuse):
     w = wl.acoustic_pulse(128, steps=50)
-    _compare(w, max_steps=51, lam_mode=2, lam_user=3.0, name="pair user lambda")
-    _compare(w, max_steps=50, lam_mode=1, name="pair frozen lambda")
+    _compare(w, max_steps=51, lam_mode=2, lam_user=3.0, name="pair user lambda", fuse=fuse)
+    _compare(w, max_steps=50, lam_mode=1, name="pair frozen lambda", fuse=fuse)
 
 
 @pytest.mark.parametrize("chunks", [[1, 2, 3, 5, 8, 13], [7, 7, 7], [2] * 11, [1] * 9, [40]])
 @pytest.mark.parametrize("lam_mode", [0, 1])
-def test_step_counts_per_call(chunks, lam_mode):
+@FUSE
+def test_step_counts_per_call(chunks, lam_mode, fuse):
     """Every call takes exactly its max_steps (odd and even counts, one-step
     calls), whatever the guesses do."""
     w = _riemann_rect(130, 90)
     P = oracle_problem(w, omega=1.2, lam_mode=lam_mode)
-    sim = _fused(w, omega=1.2, lam_mode=lam_mode)
+    sim = _fused(w, omega=1.2, lam_mode=lam_mode, fuse=fuse)
     done = 0
     for k in chunks:
         sim.step(k)
@@ -198,13 +215,14 @@ def test_step_counts_per_call(chunks, lam_mode):
     assert max_abs(U, ref.U) <= TOL
 
 
-def test_lattice_speed_sequence():
+@FUSE
+def test_lattice_speed_sequence(fuse):
     """After every call (of 3 to 14 steps) the reported lattice speed and time
     are the oracle's after that many steps."""
     w = wl.riemann2d(128)
     P = oracle_problem(w)
     ref = oracle.run(P, oracle.prim_to_cons(P, w.W), t_end=0.3)
-    sim = _fused(w)
+    sim = _fused(w, fuse=fuse)
     done = 0
     for k in [3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14] * 4:
         if done + k > ref.nsteps:
@@ -219,30 +237,35 @@ def test_lattice_speed_sequence():
 
 
 @pytest.mark.parametrize("lam_user,fail", [(1.0, 3), (1.2, 4), (1.8, 9), (2.2, 24)])
-def test_nonphysical_fixed_speed(lam_user, fail):
+@FUSE
+def test_nonphysical_fixed_speed(lam_user, fail, fuse):
     """Lattice speeds below the bound lose positivity at odd and even steps: a
     non-physical f^{n+1} inside a fused launch sends the next launch back to
     f^n for one step, a non-physical f^{n+2} is reported when accepted."""
     w = wl.explosion(64)
     _, ref, st = _compare(w, max_steps=400, omega=1.6, lam_mode=2, lam_user=lam_user,
-                          name=f"pair nonphysical user {lam_user}")
+                          name=f"fused{fuse} nonphysical user {lam_user}", fuse=fuse)
     assert ref.fail_step == fail and st["fail_step"] == fail
 
 
-def test_nonphysical_per_step():
+@FUSE
+def test_nonphysical_per_step(fuse):
     w = _riemann_rect(300, 200)
-    _, ref, st = _compare(w, t_end=0.04, omega=1.8, name="pair nonphysical rect")
+    _, ref, st = _compare(w, t_end=0.04, omega=1.8, name=f"fused{fuse} nonphysical rect",
+                          fuse=fuse)
     assert ref.fail_step == 2
     w = wl.explosion(96)
     w.cfl = 1.0
-    _, ref, st = _compare(w, max_steps=300, omega=1.95, name="pair nonphysical explosion")
+    _, ref, st = _compare(w, max_steps=300, omega=1.95,
+                          name=f"fused{fuse} nonphysical explosion", fuse=fuse)
     assert ref.fail_step == 210
 
 
-def test_nonphysical_initial_state():
+@FUSE
+def test_nonphysical_initial_state(fuse):
     w = wl.riemann2d(64)
     w.W[3, 10, 10] = -1.0
-    sim = _fused(w)
+    sim = _fused(w, fuse=fuse)
     sim.step(5)
     st = sim.state()
     assert st["rc"] == lbrs.LBRS_E_NONPHYSICAL and st["fail_step"] == 0 and st["nsteps"] == 0
@@ -250,42 +273,45 @@ def test_nonphysical_initial_state():
 
 
 @pytest.mark.parametrize("sides", [(0, 0, 0, 0), (1, 1, 1, 1), (2, 2, 0, 0), (0, 0, 2, 2)])
-def test_matches_single_steps(sides):
+@FUSE
+def test_matches_single_steps(sides, fuse):
     """Fused and single-step runs: identical step counts, status, times,
     speeds and populations, bit for bit (the per-cell arithmetic is written
     with its multiply-adds spelled out and contraction off, so both kernels
     round alike, and every guess of the next bound is checked exactly)."""
     w = wl.explosion(150)
     outs = []
-    for fuse in (1, 2):
+    for k in (1, fuse):
         sim = gpu_sim(w, sides=sides, omega=1.3, layout=1)
         sim.init_primitive(w.W)
-        sim.set_fusion(fuse)
+        sim.set_fusion(k)
         sim.step(57, 0.25)
         outs.append((sim.state(), sim.get_f()))
         sim.close()
     (s1, f1), (s2, f2) = outs
     diff = float((f1 - f2).abs().max())
-    report(f"pair vs single {sides}", max_abs_f=diff, bitwise=bool(torch.equal(f1, f2)),
+    report(f"fused{fuse} vs single {sides}", max_abs_f=diff, bitwise=bool(torch.equal(f1, f2)),
            t=(s1["t"], s2["t"]), lam=(s1["lambda"], s2["lambda"]))
     assert (s1["nsteps"], s1["rc"]) == (s2["nsteps"], s2["rc"])
     assert s2["t"] == s1["t"] and s2["lambda"] == s1["lambda"]
     assert torch.equal(f1, f2), diff
 
 
-def test_uniform_flow_bitwise():
+@FUSE
+def test_uniform_flow_bitwise(fuse):
     n = 70
     W = np.zeros((4, n, n))
     W[0], W[1], W[2], W[3] = 0.8, 0.3, -0.2, 0.7
     w = wl.Workload("uniform", wl.D2Q4, n, n, (0, 1, 0, 1), W, omega=1.7)
-    sim = _fused(w)
+    sim = _fused(w, fuse=fuse)
     sim.step(31)
     f = sim.get_f().reshape(16, -1)
     assert torch.all(f == f[:, :1])
     sim.close()
 
 
-def test_mixed_with_single_steps_tape_and_checkpoints():
+@FUSE
+def test_mixed_with_single_steps_tape_and_checkpoints(fuse):
     """Fused calls interleaved with single-step calls, taped steps and
     get_f / set_f continue the same run."""
     w = wl.acoustic_pulse(96, steps=40)
@@ -293,13 +319,13 @@ def test_mixed_with_single_steps_tape_and_checkpoints():
     ref = oracle.run(P, oracle.prim_to_cons(P, w.W), max_steps=40)
     sim = gpu_sim(w, lam_mode=1)
     sim.init_primitive(w.W)
-    sim.set_fusion(2)
+    sim.set_fusion(fuse)
     sim.step(9)
     sim.set_fusion(1)
     sim.step(4)
     tape = torch.empty((4, 96, 96), dtype=torch.float64, device="cuda")
     lbrs.lbrs_step_tape(sim.ctx, tape)
-    sim.set_fusion(2)
+    sim.set_fusion(fuse)
     sim.step(6)
     s20 = sim.state()
     f20 = sim.get_f()
@@ -322,28 +348,30 @@ def test_checkpointed_gradient_with_fused_forward():
     w = wl.acoustic_pulse(64, steps=30)
     rho0 = torch.from_numpy(w.W[0].copy()).cuda()
     out = []
-    for fuse in (1, 2):
+    for fuse in (1, 2, 3):
         run = adjoint.GradientRunner(adjoint.GradientSpec(n=64, steps=30, segment=7, fuse=fuse),
                                      rho0)
         J = run.forward(rho0)
         g = run.backward(rho0)
         out.append((float(J), g.clone()))
         run.close()
-    (J1, g1), (J2, g2) = out
-    assert J2 == pytest.approx(J1, rel=1e-13)
+    J1, g1 = out[0]
     scale = float(g1.abs().max())
-    diff = float((g1 - g2).abs().max())
-    report("pair gradient", J=J1, rel_diff=diff / scale)
-    assert diff <= 1e-11 * scale
+    for fuse, (J2, g2) in zip((2, 3), out[1:]):
+        assert J2 == pytest.approx(J1, rel=1e-13)
+        diff = float((g1 - g2).abs().max())
+        report(f"fused{fuse} gradient", J=J1, rel_diff=diff / scale)
+        assert diff <= 1e-11 * scale
 
 
 def test_mode_restrictions():
     w = wl.explosion(32)
     sim = gpu_sim(w)
     sim.init_primitive(w.W)
-    with pytest.raises(lbrs.LBRSError) as e:
-        sim.set_fusion(3)
-    assert e.value.code == lbrs.LBRS_E_INVAL
+    for bad in (0, 4):
+        with pytest.raises(lbrs.LBRSError) as e:
+            sim.set_fusion(bad)
+        assert e.value.code == lbrs.LBRS_E_INVAL
     sim.close()
     w1 = wl.sod(100)
     sim = gpu_sim(w1)
@@ -364,15 +392,18 @@ def test_mode_restrictions():
 
 
 @pytest.mark.parametrize("tile", [(0, 8), (0, 4), (0, 12)])
-def test_full_size_4096_first_steps(tile):
+@FUSE
+def test_full_size_4096_first_steps(tile, fuse):
     """Full size (4096^2, transmissive, omega = 1, row-interleaved) in fused
     launch shapes: five steps (two fused launches and a single one) against
     the oracle on every cell."""
     w = wl.riemann2d(4096)
-    _compare(w, max_steps=5, tile=tile, layout=1, name=f"pair riemann 4096 x5 {tile}")
+    _compare(w, max_steps=5, tile=tile, layout=1, name=f"fused{fuse} riemann 4096 x5 {tile}",
+             fuse=fuse)
 
 
-def test_full_size_4096_cone_samples():
+@FUSE
+def test_full_size_4096_cone_samples(fuse):
     """Full size, 100 fused steps at the oracle's fixed lattice speed, checked
     on sampled cells against the oracle on the (2k+3)^2 patch around each
     (a cell after k steps depends only on the (2k+1)^2 patch around it)."""
@@ -380,7 +411,8 @@ def test_full_size_4096_cone_samples():
     w = wl.riemann2d(n)
     Pfull = oracle_problem(w)
     lam = oracle.initial_lattice_speed(Pfull, oracle.prim_to_cons(Pfull, w.W))
-    sim = _fused(w, tile=(0, 8), layout=1, lam_mode=lbrs.LBRS_LAMBDA_USER, lam_user=lam)
+    sim = _fused(w, tile=(0, 8), layout=1, lam_mode=lbrs.LBRS_LAMBDA_USER, lam_user=lam,
+                 fuse=fuse)
     sim.step(k)
     st = sim.state()
     assert st["rc"] == 0 and st["nsteps"] == k
