@@ -180,6 +180,9 @@ __device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, in
     const bool wxlo = g.bc[0] == BC_WALL && x == 0;
     const bool wxhi = g.bc[1] == BC_WALL && x == nx - 1;
     const bool wlo = g.bc[2] == BC_WALL, whi = g.bc[3] == BC_WALL;
+    // a strip holding a wall column (wave-uniform)
+    const bool xwall = (g.bc[0] == BC_WALL && x0 == 0) ||
+                       (g.bc[1] == BC_WALL && x0 + 63 - K >= nx - 1);
     // strips that may hold the ghost lanes x = -1 or x = nx of a clamped x side
     const bool xfix = K > 1 && !px && (x0 == 0 || x0 + 63 - K >= nx);
     const bool clamp_lo = K > 1 && !py && y0 == 0;
@@ -289,30 +292,49 @@ __device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, in
             const bool topv = st > 0 && clamp_hi && j == ny;
             const bool lo_edge = st > 0 && clamp_lo && j == 0;
             const bool hi_edge = st > 0 && clamp_hi && j == ny - 1;
+            const bool wtop = whi && o == ny - 1, wbot = wlo && o == 0;
+            // the rows at a clamped side or a wall and the strips with a wall
+            // column take the general form; the others (wave-uniform branch)
+            // plain hops with no selects
             double gq[16];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                gq[0 * 4 + k] = topv ? PA[st][k] : d0[k];
-                gq[1 * 4 + k] = topv ? PA[st][4 + k] : d1[k];
-                const double b2 = lo_edge ? u2[k] : PA[st][k];
-                const double b3 = lo_edge ? u3[k] : PA[st][4 + k];
+                gq[0 * 4 + k] = d0[k];
+                gq[1 * 4 + k] = d1[k];
+            }
+            double b23[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) b23[k] = PA[st][k];
+            if (topv || lo_edge || hi_edge) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    gq[0 * 4 + k] = topv ? PA[st][k] : gq[0 * 4 + k];
+                    gq[1 * 4 + k] = topv ? PA[st][4 + k] : gq[1 * 4 + k];
+                    b23[k] = lo_edge ? u2[k] : b23[k];
+                    b23[4 + k] = lo_edge ? u3[k] : b23[4 + k];
+                    u2[k] = hi_edge ? d0[k] : u2[k];
+                    u3[k] = hi_edge ? d1[k] : u3[k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
                 if (LPB) {
                     double* e2 = pbl + (st * 8 + k) * 64 + lane;
                     double* e3 = pbl + (st * 8 + 4 + k) * 64 + lane;
                     gq[2 * 4 + k] = *e2;
                     gq[3 * 4 + k] = *e3;
-                    *e2 = b2;
-                    *e3 = b3;
+                    *e2 = b23[k];
+                    *e3 = b23[4 + k];
                 } else {
                     gq[2 * 4 + k] = PB[LPB ? 0 : st][k];
                     gq[3 * 4 + k] = PB[LPB ? 0 : st][4 + k];
-                    PB[LPB ? 0 : st][k] = b2;
-                    PB[LPB ? 0 : st][4 + k] = b3;
+                    PB[LPB ? 0 : st][k] = b23[k];
+                    PB[LPB ? 0 : st][4 + k] = b23[4 + k];
                 }
-                PA[st][k] = hi_edge ? d0[k] : u2[k];
-                PA[st][4 + k] = hi_edge ? d1[k] : u3[k];
+                PA[st][k] = u2[k];
+                PA[st][4 + k] = u3[k];
             }
-            wall_images(gq, whi && o == ny - 1, wlo && o == 0, wxlo, wxhi);
+            if (wtop || wbot || xwall) wall_images(gq, wtop, wbot, wxlo, wxhi);
             if (st < K - 1 && xfix) {
                 // a clamped side: beyond it, the next step pulls the edge column's values
 #pragma unroll

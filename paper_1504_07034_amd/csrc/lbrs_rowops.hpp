@@ -8,17 +8,18 @@ namespace lbrs {
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Wavefront shifts by one lane (DPP): lane l receives lane l-1 (shr) or
-// lane l+1 (shl).  Lanes with no source receive 0 and are halo lanes.
+// lane l+1 (shl).  Lanes with no source receive 0 (bound_ctrl, so no
+// register needs clearing first) and are halo lanes.
 __device__ inline double lane_from_left(double v) {
     int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);  // wave_shr:1
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true);  // wave_shr:1
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ inline double lane_from_right(double v) {
     int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);  // wave_shl:1
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true);  // wave_shl:1
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
