@@ -831,7 +831,7 @@ def main():
     ap.add_argument("--alt", type=int, default=1, choices=[0, 1],
                     help="march odd row segments upwards (with --rows >= 0)")
     ap.add_argument("--layout", type=int, default=1, help="0 planar, 1 row-interleaved")
-    ap.add_argument("--fuse", type=int, default=1, choices=[1, 2, 3],
+    ap.add_argument("--fuse", type=int, default=1, choices=[1, 2, 3, 4],
                     help="time steps per launch (with --rows >= 0; autotuned otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",

@@ -223,8 +223,8 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
  * one node along every link, applies the side conditions and reduces the next
  * step's lambda* (with the prescribed states of DIRICHLET sides).  A step whose start time is >= t_end, or that follows a
  * non-physical step, does nothing, so the run stops exactly at t_end
- * (PER_STEP mode clips the last dt).  With lbrs_set_fusion(c, 2 or 3) (2D
- * Euler) the steps run two or three per launch with the same results (see
+ * (PER_STEP mode clips the last dt).  With lbrs_set_fusion(c, k), k = 2 to 4
+ * (2D Euler), the steps run up to k per launch with the same results (see
  * there).
  * Asynchronous. */
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
@@ -239,19 +239,21 @@ int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda,
                    unsigned* status, long long* fail_step);
 
 /* Counters of the fused launches since lbrs_init (lbrs_set_fusion(c, k > 1)),
- * into counts[0 .. n-1] (n <= 12; missing ones 0): [0] launches of two or
- * three steps whose result stood, [1] such launches rolled back (a guessed
+ * into counts[0 .. n-1] (n <= 13; missing ones 0): [0] launches of two or
+ * more steps whose result stood, [1] such launches rolled back (a guessed
  * bound that was wrong), [2] launches that only reduced the bound of f^{n+1},
  * [3] one-step launches, [4] predictions of the next launch's bounds made,
  * [5] predicted bounds that stood, [6] predicted bounds rolled back,
  * [7] cells whose bound the predictions evaluated, [8] launches that listed
  * candidates but left no prediction (too many, none, or a non-physical
  * state), [9] candidates listed, [10] launches whose candidates overflowed
- * the list, [11] of [0], the three-step ones.  With per-step lattice speeds a fused launch guesses the bound of
- * the state after its first step (the prediction when the launch before left
- * one, else the current bound while it keeps repeating) and the next launch
- * checks the guess bit for bit, so the counters describe cost only: results
- * are those of single steps.  Waits for the stream. */
+ * the list, [11] of [0], the three-step ones, [12] of [0], the four-step
+ * ones (so the steps taken are 2 [0] + [11] + 2 [12] + [3]).  With per-step
+ * lattice speeds a fused launch guesses the bounds of the states after its
+ * first steps (the predictions when the launch before left them, else the
+ * current bound while it keeps repeating) and the next launch checks every
+ * guess bit for bit, so the counters describe cost only: results are those
+ * of single steps.  Waits for the stream. */
 int lbrs_pair_stats(lbrs_ctx* c, long long* counts, int n);
 
 /* Moments of the current populations, U = sum_i f_i (eq. "moments_system"),
@@ -381,7 +383,7 @@ int lbrs_set_stream(lbrs_ctx* c, void* hip_stream);
  * effect for later calls; LBRS_E_INVAL for values outside these sets. */
 int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alternate);
 
-/* Time steps per launch of the 2D Euler step: 1 (the default), 2 or 3.  With
+/* Time steps per launch of the 2D Euler step: 1 (the default), 2, 3 or 4.  With
  * k > 1 each wavefront keeps the rows of f^{n+1} it has just streamed in
  * registers and streams them once more, k times (the same Sec. II.D update,
  * k times), so f^n is read and f^{n+k} written once per k steps: 1/k of the
@@ -398,10 +400,10 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * bit.  lbrs_step(c, max_steps, t_end) then enqueues a one-thread set-up
  * kernel and up to max_steps launches (with a fixed speed max_steps/k + 1),
  * of which the ones beyond the work done exit at once; with PER_STEP speeds
- * each launch is followed by the prediction kernels.  The shape set by
- * lbrs_set_tile applies (strips of at most 64 - 2k columns; automatic
- * segments of at least 4 rows; 16 waves per workgroup run as 12, as 8 with
- * k = 3 or PER_STEP speeds; alternate is ignored).
+ * each launch is followed by the prediction kernel (one cooperative launch).
+ * The shape set by lbrs_set_tile applies (strips of at most 64 - 2k columns;
+ * automatic segments of at least 4 rows; 16 waves per workgroup run as 12,
+ * as 8 with k >= 3 or PER_STEP speeds; alternate is ignored).
  * lbrs_step_tape stays a single step; lbrs_backward_checkpointed recomputes
  * its segments two steps per launch when k > 1 (both steps' input moments
  * taped) and runs its adjoint steps two per launch (lbrs_adjoint_step2).
@@ -547,7 +549,7 @@ void lbrs_batch2d_destroy(lbrs_batch2d* b);
  * No-allocation entry point, for callers that cannot allocate: code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation.
  * One whole run -- lbrs_init, lbrs_step(max_steps, t_end) (steps_per_launch
- * steps per launch, 1 to 3, as lbrs_set_fusion) and lbrs_moments --
+ * steps per launch, 1 to 4, as lbrs_set_fusion) and lbrs_moments --
  * with the same kernels and results, but the time state (t, step count, the
  * lambda* reduction slots, the status and the fused launches' record) lives
  * in a static device array of the library (512 KiB per GPU, kept until the

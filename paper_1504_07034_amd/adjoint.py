@@ -53,7 +53,7 @@ class GradientSpec:
     segment: int | None = None  # checkpoint spacing; default ceil(sqrt(T))
     lam: float | None = None    # frozen lattice speed; set by prepare()
     tile: tuple | None = None   # (rows_per_tile, waves_per_block, alternate) of the step kernel
-    fuse: int = 1               # steps per launch of the plain forward steps (1, 2 or 3)
+    fuse: int = 1               # steps per launch of the plain forward steps (1 to 4)
     store_all: bool | None = False  # keep every step's moments (None: if they fit)
 
     def params(self, mode, lam_user=0.0):

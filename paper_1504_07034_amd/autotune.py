@@ -4,7 +4,7 @@ Candidates are (rows_per_tile, waves_per_block, alternate, fuse) tuples;
 rows_per_tile = 0 is the library's automatic choice (one balanced round of the
 resident waves), alternate = 1 marches odd row segments upwards (same results,
 different memory order; a domain with a solid body marches one way only),
-fuse = 2 or 3 takes that many fused steps per launch (2D Euler without body or
+fuse = 2, 3 or 4 takes that many fused steps per launch (2D Euler without body or
 Dirichlet side; such launches march one way).  Candidates are compared in time per step.
 Each candidate is timed with HIP events over a few steps that start from the
 same checkpoint of the populations (lbrs_get_f / lbrs_set_f), so tuning does
@@ -83,7 +83,7 @@ def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=Non
          verbose: bool = False, confirm: int = 4, fuses=None) -> dict:
     """Pick and apply the fastest 2D launch shape for `sim` (already initialised).
     rows / wpbs default to the candidate sets for the grid's size; fuses to
-    (1, 2, 3) where fused launches are available."""
+    (1, 2, 3, 4) where fused launches are available."""
     small = sim.nx * sim.ny <= SMALL_CELLS
     if rows is None:
         rows = SMALL_ROWS if small else DEFAULT_ROWS
@@ -93,7 +93,7 @@ def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=Non
     if getattr(sim, "body", False):
         alts = (0,)
     if fuses is None:
-        fuses = (1, 2, 3) if getattr(sim, "fusable", False) else (1,)
+        fuses = (1, 2, 3, 4) if getattr(sim, "fusable", False) else (1,)
     cache = _load_cache() if use_cache else {}
     if use_cache and key in cache:
         best = cache[key]
@@ -105,7 +105,8 @@ def tune(sim: "lbrs.Sim", t_end: float = float("inf"), steps: int = 10, rows=Non
     results = []
     for fu in fuses:
         for a in (alts if fu == 1 else (0,)):
-            # fused launches run at most 12 waves per group, three-step ones 8
+            # fused launches run at most 12 waves per group, those of three or
+            # more steps 8
             for w in (wpbs if fu == 1 else [v for v in wpbs if v <= (12 if fu == 2 else 8)]):
                 for r in rows:
                     ms = time_shape(sim, r, w, steps, f0, st["t"], st["nsteps"], t_end, a, fu)

@@ -31,11 +31,12 @@ struct lbrs_ctx {
     bool dir;            // some side is DIRICHLET
     int sbpc[17];        // resident scalar-step workgroups per CU, by waves per block
     unsigned short* codes;  // body node codes in the scratch area (null: no body)
-    int fuse;            // 2D Euler: time steps per launch (1, or 2 or 3 fused)
+    int fuse;            // 2D Euler: time steps per launch (1, or 2 to 4 fused)
     PairState* pst;      // record of the fused launches (scratch area, behind the time state)
     PredCand* cand;      // candidate list of the per-step prediction (scratch area), or null
-    int pbpc[3][2][17];  // resident fused-kernel workgroups per CU, by (plain, candidates,
-                         // taped), (two or three steps) and waves per block
+    int pbpc[3][KMAX_STEPS + 1][17];  // resident fused-kernel workgroups per CU, by (plain,
+                                      // candidates, taped), steps per launch and waves per
+                                      // block
     int abpc[17];        // the same for the fused adjoint kernel
 };
 
@@ -361,9 +362,9 @@ static bool pair_filter(const lbrs_ctx* c) {
 static int pair_kmax(const lbrs_ctx* c, bool tape) { return tape ? 2 : c->fuse; }
 
 // Waves per workgroup of the fused kernel: 16-wave groups do not fit its
-// registers at the occupancy it needs and run as 12; three-step launches and
-// the form that lists candidates (more registers) spill in 12-wave groups,
-// and run as 8.
+// registers at the occupancy it needs and run as 12; launches of three or
+// more steps and the form that lists candidates (more registers) spill in
+// 12-wave groups, and run as 8.
 static int pair_wpb(const lbrs_ctx* c, bool tape = false) {
     const int cap = !tape && (pair_filter(c) || c->fuse >= 3) ? 8 : 12;
     return c->waves_per_block > cap ? cap : c->waves_per_block;
@@ -374,7 +375,7 @@ static int pair_max_blocks(const lbrs_ctx* c, bool tape = false) {
     const int w = pair_wpb(c, tape);
     const int form = tape ? 2 : (pair_filter(c) ? 1 : 0);
     const int kmax = pair_kmax(c, tape);
-    int& n = m->pbpc[form][kmax >= 3 ? 1 : 0][w];
+    int& n = m->pbpc[form][kmax][w];
     if (n == 0) n = step2d_pair_blocks_per_cu(w, form == 1, kmax, tape);
     return c->cu_count * n;
 }

@@ -44,7 +44,7 @@ struct Step2DArgs {
 // bound of f^{n+1} alone (nothing stored) and the next launch steps with it.
 // The record lives in slot (p+1) & 1 beside the time state; the intermediate
 // states' bounds and flags are slotted like DevState::lam and DevState::bad.
-static constexpr int KMAX_STEPS = 3;
+static constexpr int KMAX_STEPS = 4;
 
 struct PairSlot {
     double t_base;              // state before the launch's steps
@@ -63,17 +63,18 @@ struct PairSlot {
     unsigned long long pred[KMAX_STEPS];
 };
 
-// The prediction of lambda*_{n+3} after a pair n -> n+2 (or of lambda*_{n+2}
-// after a one-step launch, from U^{n+1}): the launch lists the cells whose
-// bound of U^{n+2} is a local maximum (no left, right, lower
-// or upper neighbour's is larger) within CAND_REL of the largest its wave has
-// seen and above a floor CAND_REL below lambda*_{n+1}, leaving out the inside
-// of flat regions (one cell per wave stands for a region at one value); once
-// lambda*_{n+2} is known, a small kernel evaluates the exact bound of the
-// next step's states on the 3 x 3 cells around each candidate (a cell's next
-// state pulls from its diagonal neighbours) and takes the largest.  Nothing
-// assures that the maximum lies there: the prediction is only a guess, which
-// the launch after the next one checks bit for bit like any other.
+// The prediction of the bounds the next launch needs: after a launch that
+// leaves a state S, the launch lists the cells whose bound of S is a local
+// maximum (no left, right, lower or upper neighbour's is larger) within
+// CAND_REL of the largest its wave has seen and above a floor CAND_REL below
+// the bound it guessed or knew for its last step, leaving out the inside of
+// flat regions (one cell per wave stands for a region at one value); once
+// lambda*(S) is known, a small kernel evaluates the exact bound of the states
+// after 1, 2, ... steps from S on the 3 x 3 cells around each candidate (a
+// cell's next state pulls from its diagonal neighbours) and takes the
+// largest.  Nothing assures that the maximum lies there: a prediction is only
+// a guess, which the launch after the next one checks bit for bit like any
+// other.
 static constexpr double CAND_REL = 1e-4;
 // Candidates one launch may leave (more: no prediction).
 static constexpr int PRED_CAP = 16384;
@@ -88,11 +89,11 @@ struct PredCand {
 // follows it; two of them, by launch parity (a launch fills its own and
 // clears the other for the launch after it).
 struct PredHeader {
-    int armed;                  // 1: the launch was a two-step pair that listed candidates
-    int cur_out;                // buffer holding its f^{n+2}
+    int armed;                  // 1: the launch listed candidates
+    int cur_out;                // buffer holding the state it leaves
     unsigned int ncand;         // candidates written (may exceed PRED_CAP: overflow)
     unsigned int pad;
-    double t2;                  // time after the launch's steps
+    double t_out;               // time after the launch's steps
 };
 
 // Counters of the fused launches since the context's initialisation.
@@ -109,6 +110,7 @@ enum : int {
     PST_LISTED,           // candidates the launches listed
     PST_OVERFLOW,         // launches whose candidates overflowed the list
     PST_STEPS3,           // of PST_PAIRS: three-step launches
+    PST_STEPS4,           // of PST_PAIRS: four-step launches
     PST_COUNT
 };
 
@@ -140,7 +142,7 @@ struct Pair2DArgs {
     int lam_mode;
     int bc[4];
     int last;             // last launch of a call: its result must not be tentative
-    double* tape0;        // taped form: U^n of the launch's first step and U^{n+1} of its
+    double* tape0;        // taped form (two steps at most): U^n of the launch's first step and U^{n+1} of its
     double* tape1;        // second ([4][ny][nx] each; a one-step launch writes tape0 only)
     long long plane;      // nx * ny
     PredCand* cand;       // candidate list (PRED_CAP entries) of the per-step prediction,

@@ -39,6 +39,8 @@
 //
 // Also here: the taped form (U^n and U^{n+1} stored for the gradients'
 // recompute) and the 2D batch's form over all domains (fixed speeds).
+#include <hip/hip_cooperative_groups.h>
+
 #include "lbrs_launch.hpp"
 #include "lbrs_rowops.hpp"
 
@@ -180,13 +182,16 @@ __device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, in
     const bool wxlo = g.bc[0] == BC_WALL && x == 0;
     const bool wxhi = g.bc[1] == BC_WALL && x == nx - 1;
     const bool wlo = g.bc[2] == BC_WALL, whi = g.bc[3] == BC_WALL;
-    // a strip holding a wall column (wave-uniform)
-    const bool xwall = (g.bc[0] == BC_WALL && x0 == 0) ||
+    // Wave-uniform: the strip's lanes (halo lanes included) hold a wall
+    // column; they hold the ghost column x = -1 or x = nx of a clamped x
+    // side.  Every column and row a tile computes is a true cell of its
+    // state (halo ones feed the next steps), so the side rules apply to each,
+    // also in a strip or segment that does not begin at the side.
+    const bool xwall = (g.bc[0] == BC_WALL && x0 - K <= 0) ||
                        (g.bc[1] == BC_WALL && x0 + 63 - K >= nx - 1);
-    // strips that may hold the ghost lanes x = -1 or x = nx of a clamped x side
-    const bool xfix = K > 1 && !px && (x0 == 0 || x0 + 63 - K >= nx);
-    const bool clamp_lo = K > 1 && !py && y0 == 0;
-    const bool clamp_hi = K > 1 && !py && y1 == ny;
+    const bool xfix = K > 1 && !px && (x0 - K < 0 || x0 + 63 - K >= nx);
+    const bool clamp_lo = K > 1 && !py;
+    const bool clamp_hi = K > 1 && !py;
 
     // per step: upward hops (u2, u3) of the last input row (PA) and of the
     // one before (PB); at a clamped top PA keeps row ny-1's downward hops.
@@ -398,9 +403,9 @@ __device__ __forceinline__ void step_size(int lam_mode, double lam_star, double 
 }
 
 // Time control of one fused launch (identical in every thread).  Written
-// out for up to three steps, in scalars: a local array indexed by a run-time
+// out for up to four steps, in scalars: a local array indexed by a run-time
 // step count would live in scratch memory.
-static_assert(KMAX_STEPS == 3, "the launch control is written out for three steps");
+static_assert(KMAX_STEPS == 4, "the launch control is written out for four steps");
 
 struct PairCtl {
     bool active;        // at least one step, or a bound-only pass
@@ -419,15 +424,15 @@ struct PairCtl {
     long long n;
     double t, lam_used;
     unsigned long long lstar;         // bits of lambda*_n (the current state's bound)
-    unsigned long long g1, g2;        // bits of lambda*_{n+1}, lambda*_{n+2} taken (guessed
-                                      // or known) for steps 2 and 3
+    unsigned long long g1, g2, g3;    // bits of lambda*_{n+1..n+3} taken (guessed or known)
+                                      // for steps 2..4
     unsigned bad;
-    double lam1, lam2, lam3;          // lattice speed of steps 1..3
-    double t1, t2, t3;                // time after them
+    double lam1, lam2, lam3, lam4;    // lattice speed of steps 1..4
+    double t1, t2, t3, t4;            // time after them
     double t_out, lam_out;            // time after the last step, its speed
     double t0;                        // floor of the candidates' bounds
     int pred_n;                       // predictions the record read holds for the state
-    unsigned long long p1, p2;
+    unsigned long long p1, p2, p3;
 };
 
 __device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots ls) {
@@ -443,14 +448,15 @@ __device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots
     unsigned bad = st->bad[ls.lr];
     // exact bounds of the states after steps 1 .. known of this launch
     int known = 0;
-    unsigned long long next1 = 0ull, next2 = 0ull;
+    unsigned long long next1 = 0ull, next2 = 0ull, next3 = 0ull;
     int force_k = 0;  // > 0: take exactly these steps (a non-physical state at the last)
     int trust = q.trust;
     // the previous launch left predictions for the state it produced
     int pred_n = q.pred_valid;
-    const unsigned long long qp1 = q.pred[1], qp2 = q.pred[2];
+    const unsigned long long qp1 = q.pred[1], qp2 = q.pred[2], qp3 = q.pred[3];
     if (pred_n > 0 && qp1 == 0ull) pred_n = 0;
     if (pred_n > 1 && qp2 == 0ull) pred_n = 1;
+    if (pred_n > 2 && qp3 == 0ull) pred_n = 2;
     c.accepted_bad = false;
     c.check = 0;
     c.checked_k = q.tentative;
@@ -458,8 +464,10 @@ __device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots
         // the first intermediate state that was non-physical or whose bound
         // differs from the guess (0: none)
         const int kt = q.tentative;
-        const unsigned long long m1 = ps->lamk[0][ls.lr], m2 = ps->lamk[1][ls.lr];
-        const bool b1 = ps->badk[0][ls.lr] != 0u, b2 = kt >= 3 && ps->badk[1][ls.lr] != 0u;
+        const unsigned long long m1 = ps->lamk[0][ls.lr], m2 = ps->lamk[1][ls.lr],
+                                 m3 = ps->lamk[2][ls.lr];
+        const bool b1 = ps->badk[0][ls.lr] != 0u, b2 = kt >= 3 && ps->badk[1][ls.lr] != 0u,
+                   b3 = kt >= 4 && ps->badk[2][ls.lr] != 0u;
         int fail = 0;
         bool fail_bad = false;
         next1 = m1;
@@ -475,6 +483,14 @@ __device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots
                 fail_bad = true;
             } else if (per_step && m2 != q.guess[2]) {
                 fail = 2;
+            } else if (kt >= 4) {
+                next3 = m3;
+                if (b3) {
+                    fail = 3;
+                    fail_bad = true;
+                } else if (per_step && m3 != q.guess[3]) {
+                    fail = 3;
+                }
             }
         }
         const bool ok = fail == 0;
@@ -523,18 +539,19 @@ __device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots
     int kcap = a.kmax;
     if (force_k > 0 && force_k < kcap) kcap = force_k;
     if (s.n + kcap > n_limit) kcap = (int)(n_limit - s.n);
-    // where the speeds of steps 2 and 3 come from: known bounds, else
+    // where the speeds of steps 2.. come from: known bounds, else
     // predictions, else the current bound while it has been repeating (a
     // guess), else a bound-only pass first
     const bool use_pred = per_step && known == 0 && pred_n > 0;
     int kguess;  // steps reachable with known or guessed speeds
-    if (!per_step) kguess = 3;
+    if (!per_step) kguess = KMAX_STEPS;
     else if (known > 0) kguess = known + 1;
     else if (use_pred) kguess = pred_n + 1;
-    else kguess = trust > 0 ? 3 : 1;
+    else kguess = trust > 0 ? KMAX_STEPS : 1;
     if (kcap > kguess) kcap = kguess;
     c.g1 = known >= 1 ? next1 : (use_pred ? qp1 : lstar);
     c.g2 = known >= 2 ? next2 : (use_pred ? qp2 : lstar);
+    c.g3 = known >= 3 ? next3 : (use_pred ? qp3 : lstar);
     const double fix = st->lam_fixed;
     step_size(a.lam_mode, from_bits(lstar > lbc ? lstar : lbc), fix, a.dx, a.cfl, s.t, a.t_end,
               c.lam1, c.t1);
@@ -542,12 +559,15 @@ __device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots
               c.lam2, c.t2);
     step_size(a.lam_mode, from_bits(c.g2 > lbc ? c.g2 : lbc), fix, a.dx, a.cfl, c.t2, a.t_end,
               c.lam3, c.t3);
+    step_size(a.lam_mode, from_bits(c.g3 > lbc ? c.g3 : lbc), fix, a.dx, a.cfl, c.t3, a.t_end,
+              c.lam4, c.t4);
     // each step runs when the one before did, it is within the caps and the
     // time before it is short of t_end
     c.k = 0;
     if (c.active && kcap >= 1) c.k = 1;
     if (c.k == 1 && kcap >= 2 && c.t1 < a.t_end) c.k = 2;
     if (c.k == 2 && kcap >= 3 && c.t2 < a.t_end) c.k = 3;
+    if (c.k == 3 && kcap >= 4 && c.t3 < a.t_end) c.k = 4;
     // an intermediate state whose bound is not yet known: the speed after it
     // is a guess (per-step speeds), or its positivity is unchecked
     c.tentative = c.k >= 2 && c.k - 1 > known;
@@ -562,17 +582,19 @@ __device__ __forceinline__ PairCtl pair_control(const Pair2DArgs& a, LaunchSlots
         c.tentative = c.bound = c.predicted = false;
     }
     c.trust = trust;
-    c.t_out = c.k == 3 ? c.t3 : (c.k == 2 ? c.t2 : c.t1);
-    c.lam_out = c.k == 3 ? c.lam3 : (c.k == 2 ? c.lam2 : c.lam1);
+    c.t_out = c.k == 4 ? c.t4 : (c.k == 3 ? c.t3 : (c.k == 2 ? c.t2 : c.t1));
+    c.lam_out = c.k == 4 ? c.lam4 : (c.k == 3 ? c.lam3 : (c.k == 2 ? c.lam2 : c.lam1));
     // candidates for the predictions of the next launch's bounds: bounds of
     // the state this launch leaves from CAND_REL below the last known or
     // guessed one up
     c.cand = c.active && c.k > 0 && per_step && a.cand != nullptr && c.t_out < a.t_end;
-    const unsigned long long lref = c.k == 3 ? c.g2 : (c.k == 2 ? c.g1 : lstar);
+    const unsigned long long lref =
+        c.k == 4 ? c.g3 : (c.k == 3 ? c.g2 : (c.k == 2 ? c.g1 : lstar));
     c.t0 = c.cand ? from_bits(lref) * (1.0 - CAND_REL) : 0.0;
     c.pred_n = pred_n;
     c.p1 = qp1;
     c.p2 = qp2;
+    c.p3 = qp3;
     return c;
 }
 
@@ -591,7 +613,8 @@ __device__ __forceinline__ void publish_pair(const Pair2DArgs& a, LaunchSlots ls
     q.guess[0] = 0ull;
     q.guess[1] = c.k >= 2 ? c.g1 : 0ull;
     q.guess[2] = c.k >= 3 ? c.g2 : 0ull;
-    q.pred[0] = q.pred[1] = q.pred[2] = 0ull;
+    q.guess[3] = c.k >= 4 ? c.g3 : 0ull;
+    q.pred[0] = q.pred[1] = q.pred[2] = q.pred[3] = 0ull;
     q.guess_base = c.lstar;
     q.tentative = 0;
     q.known = 0;
@@ -609,6 +632,7 @@ __device__ __forceinline__ void publish_pair(const Pair2DArgs& a, LaunchSlots ls
         q.pred_valid = c.pred_n;
         q.pred[1] = c.p1;
         q.pred[2] = c.p2;
+        q.pred[3] = c.p3;
     } else if (c.bound) {
         // no step: the state and its bound carry over; the first intermediate
         // accumulators receive the bound of f^{n+1}
@@ -640,7 +664,7 @@ __device__ __forceinline__ void publish_pair(const Pair2DArgs& a, LaunchSlots ls
     PredHeader& h = ps->pred[a.launch & 1];
     h.armed = c.cand ? 1 : 0;
     h.cur_out = c.cur ^ 1;
-    h.t2 = c.t_out;
+    h.t_out = c.t_out;
     PredHeader& hn = ps->pred[(a.launch + 1) & 1];
     hn.armed = 0;
     hn.ncand = 0u;
@@ -648,6 +672,7 @@ __device__ __forceinline__ void publish_pair(const Pair2DArgs& a, LaunchSlots ls
     if (c.check >= 3) ps->stat[PST_REJECTED] += 1;
     else if (c.check > 0) ps->stat[PST_PAIRS] += 1;
     if (c.check > 0 && c.check < 3 && c.checked_k == 3) ps->stat[PST_STEPS3] += 1;
+    if (c.check > 0 && c.check < 3 && c.checked_k == 4) ps->stat[PST_STEPS4] += 1;
     if (c.check == 2) ps->stat[PST_PRED_HIT] += 1;
     if (c.check == 4) ps->stat[PST_PRED_MISS] += 1;
     if (c.active) {
@@ -656,6 +681,7 @@ __device__ __forceinline__ void publish_pair(const Pair2DArgs& a, LaunchSlots ls
         else if (!c.tentative) {
             ps->stat[PST_PAIRS] += 1;
             if (c.k == 3) ps->stat[PST_STEPS3] += 1;
+            if (c.k == 4) ps->stat[PST_STEPS4] += 1;
         }
     }
     if (c.accepted_bad) {
@@ -671,7 +697,10 @@ template <int WPB, int KM, bool TAPE, bool CAND, bool LPB>
 __device__ __forceinline__ void march_launch(const PairGeom& g, int k, bool store, int strip,
                                              int y0, int y1, int lane, double (&lm)[KMAX_STEPS],
                                              bool (&bad)[KMAX_STEPS], double* pbl) {
-    if (KM >= 3 && k == 3)
+    if (KM >= 4 && k == 4)
+        march_k<WPB, (KM >= 4 ? 4 : 1), TAPE, CAND, LPB>(g, strip, y0, y1, lane, lm, bad, true,
+                                                         pbl);
+    else if (KM >= 3 && k == 3)
         march_k<WPB, (KM >= 3 ? 3 : 1), TAPE, CAND, LPB>(g, strip, y0, y1, lane, lm, bad, true,
                                                          pbl);
     else if (k == 2)
@@ -680,10 +709,10 @@ __device__ __forceinline__ void march_launch(const PairGeom& g, int k, bool stor
         march_k<WPB, 1, TAPE, CAND, LPB>(g, strip, y0, y1, lane, lm, bad, store, pbl);
 }
 
-// Three-step kernels keep the second row of their pipelines in LDS (the
-// registers of the first, the prefetched row and the step's own values fill
-// the budget of two waves per SIMD), and so do 12-wave workgroups (three
-// waves per SIMD).
+// Kernels of three or more steps keep the second row of their pipelines in
+// LDS (the registers of the first, the prefetched row and the step's own
+// values fill the budget of two waves per SIMD), and so do 12-wave
+// workgroups (three waves per SIMD).
 template <int WPB, int KM>
 struct PipelineInLds {
     static constexpr bool value = KM >= 3 || WPB >= 12;
@@ -712,6 +741,7 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     g.c4lam[0] = 1.0 / (4.0 * c.lam1);
     g.c4lam[1] = 1.0 / (4.0 * (c.k >= 2 ? c.lam2 : c.lam1));
     g.c4lam[2] = 1.0 / (4.0 * (c.k >= 3 ? c.lam3 : c.lam1));
+    g.c4lam[3] = 1.0 / (4.0 * (c.k >= 4 ? c.lam4 : c.lam1));
     g.omega = a.omega;
     g.gamma = a.gamma;
     for (int s = 0; s < 4; ++s) g.bc[s] = a.bc[s];
@@ -783,119 +813,185 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     }
 }
 
+// The predictions after fused launch a.launch, for the state S it leaves:
+// level L (1 .. kmax-1) evaluates the exact bound of the state after L steps
+// from S on the 3 x 3 cells around every listed candidate whose bound is
+// within CAND_REL of lambda*(S), and maxes it into pred[L] of the record the
+// next launch reads.  Step 1 runs at the speed from lambda*(S) (known now),
+// step L > 1 at the speed from the level L-1 prediction, so the levels are
+// separated by grid barriers (a cooperative launch; every decision to go on
+// is taken alike by every workgroup from values in memory).  None when the
+// launch listed no candidates or more than the list holds, or met a
+// non-physical state.
+//
+// A one-wave workgroup takes a candidate at a time and marches its patch: the
+// post-collision populations of S on the cells within L+1 of the centre,
+// then of the states after 1 .. L-1 steps on shrinking patches (LDS, two
+// buffers, population-major), and the bound after step L on the 3 x 3 cells.
+// Every cell stands for its domain cell under the side conditions (a cell
+// beyond a clamped side is the edge cell, a periodic side wraps), and its
+// next state pulls from the domain cells its populations come from, as the
+// step kernels do, with the step kernels' own device functions: the same
+// bits.  Workgroup 0 also sets the record's count of valid levels and the
+// counters.
+static constexpr int PRED_BLOCKS = 256;
+static constexpr int PRED_R = KMAX_STEPS;              // patch radius of the deepest level
+static constexpr int PRED_C0 = (2 * PRED_R + 1) * (2 * PRED_R + 1);  // cells, even stages
+static constexpr int PRED_C1 = (2 * PRED_R - 1) * (2 * PRED_R - 1);  // cells, odd stages
+
 namespace {
 
-// The populations of cell (x, y) after one step from f (pulls of the
-// post-collision values of its four diagonal neighbours at 1/(4 lambda) =
-// c4, then the walls), by the step kernels' own device functions.  f may be
-// any state of the domain: beyond a clamped side its ghost is the edge cell
-// (map_index), as the fused launches treat the states between their steps.
-template <typename Src>
-__device__ inline void pulled_cell(const Pair2DArgs& a, int x, int y, double c4, const Src& src,
-                                   double g1[16]) {
-    const int nx = a.nx, ny = a.ny;
+// Offset from the centre c (along one axis) of the domain cell that patch
+// offset o stands for, shifted by -d: where a population of that cell comes
+// from.  Periodic: offsets wrap with the domain, so they simply add.
+__device__ inline int source_offset(int c, int o, int d, int n, bool periodic) {
+    if (periodic) return o - d;
+    return map_index(map_index(c + o, n, false) - d, n, false) - c;
+}
+
+// The state after one step at patch offset (ox, oy) of centre (cx, cy): the
+// pulls from the post-collision patch `post` (radius rp, population-major
+// with `stride` cells per plane), then the walls.
+__device__ inline void gather_patch(const Pair2DArgs& a, int cx, int cy, int ox, int oy,
+                                    const double* post, int rp, int stride, double g[16]) {
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
     const int sxs[4] = {-1, 1, 1, -1}, sys[4] = {-1, -1, 1, 1};
-    const double gm1 = a.gamma - 1.0;
+    const int sp = 2 * rp + 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int xs = map_index(x - sxs[j], nx, px), ys = map_index(y - sys[j], ny, py);
-        double f[16], U[4], fs[16];
-        src(xs, ys, f);
-        moments_d2q4(f, U);
-        const Euler2 eu = euler2(U, gm1);
-        collide_d2q4(f, U, eu, c4, a.omega, fs);
+        const int fx = source_offset(cx, ox, sxs[j], a.nx, px);
+        const int fy = source_offset(cy, oy, sys[j], a.ny, py);
+        const int idx = (fy + rp) * sp + (fx + rp);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) g1[j * 4 + k] = fs[j * 4 + k];
+        for (int k = 0; k < 4; ++k) g[j * 4 + k] = post[(j * 4 + k) * stride + idx];
     }
-    wall_images(g1, a.bc[3] == BC_WALL && y == ny - 1, a.bc[2] == BC_WALL && y == 0,
-                a.bc[0] == BC_WALL && x == 0, a.bc[1] == BC_WALL && x == nx - 1);
+    const int x = map_index(cx + ox, a.nx, px), y = map_index(cy + oy, a.ny, py);
+    wall_images(g, a.bc[3] == BC_WALL && y == a.ny - 1, a.bc[2] == BC_WALL && y == 0,
+                a.bc[0] == BC_WALL && x == 0, a.bc[1] == BC_WALL && x == a.nx - 1);
+}
+
+__device__ inline void collide_into(const double f[16], double gm1, double c4, double omega,
+                                    double* post, int stride, int idx) {
+    double U[4], fs[16];
+    moments_d2q4(f, U);
+    const Euler2 eu = euler2(U, gm1);
+    collide_d2q4(f, U, eu, c4, omega, fs);
+#pragma unroll
+    for (int p = 0; p < 16; ++p) post[p * stride + idx] = fs[p];
 }
 
 }  // namespace
 
-// The predictions after fused launch a.launch, for the state S it leaves:
-// level L (1 or 2) evaluates the exact bound of the state after L steps from
-// S on the 3 x 3 cells around every listed candidate whose bound is within
-// CAND_REL of lambda*(S) -- by the step kernels' own device functions, so
-// the same bits -- and maxes it into pred[L] of the record the next launch
-// reads.  Step 1 runs at the speed from lambda*(S) (known now), step 2 at the
-// speed from the level-1 prediction (read from the record, so level 2 is a
-// second launch).  None when the launch listed no candidates or more than
-// the list holds, or met a non-physical state.  PRED_BLOCKS workgroups
-// stride over (candidate, neighbour) pairs; workgroup 0 also sets the
-// record's count of valid levels and the counters.
-static constexpr int PRED_BLOCKS = 64;
-
-__global__ __launch_bounds__(256) void pair_predict_kernel(Pair2DArgs a, int level) {
+__global__ __launch_bounds__(64) void pair_predict_kernel(Pair2DArgs a) {
+    __shared__ double post0[16 * PRED_C0];
+    __shared__ double post1[16 * PRED_C1];
     const LaunchSlots ls = slots_for(a.launch);
     PairState* ps = a.pst;
     const PredHeader* h = &ps->pred[a.launch & 1];
     PairSlot* q = &ps->q[ls.sw];
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     const unsigned ncand = h->ncand;
-    bool ok = h->armed != 0 && ncand > 0u && ncand <= (unsigned)PRED_CAP &&
-              a.st->bad[ls.la] == 0u;
-    if (level == 2) ok = ok && q->pred_valid >= 1 && q->pred[1] != 0ull;
-    if (blockIdx.x == 0 && tid == 0 && h->armed) {
+    const bool armed = h->armed != 0;
+    const bool ok = armed && ncand > 0u && ncand <= (unsigned)PRED_CAP && a.st->bad[ls.la] == 0u;
+    if (blockIdx.x == 0 && lane == 0 && armed) {
         // (a launch that listed nothing keeps what its record carries)
-        if (level == 1) {
-            q->pred_valid = ok ? 1 : 0;
-            ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
-            ps->stat[PST_LISTED] += ncand;
-            if (ncand > (unsigned)PRED_CAP) ps->stat[PST_OVERFLOW] += 1;
-        } else if (ok) {
-            q->pred_valid = 2;
-        }
+        q->pred_valid = 0;
+        ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
+        ps->stat[PST_LISTED] += ncand;
+        if (ncand > (unsigned)PRED_CAP) ps->stat[PST_OVERFLOW] += 1;
     }
-    if (!ok) return;
+    if (!ok) return;  // alike in every workgroup: before any barrier
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     const unsigned long long lb = a.st->lam[ls.la];
     const unsigned long long lbc = a.st->lam_bc;
     const double floor_l = from_bits(lb) * (1.0 - CAND_REL);
-    // the speeds of the next launch's first two steps
-    double lam1, t1, lam2, t2;
-    step_size(LAM_PER_STEP, from_bits(lb > lbc ? lb : lbc), 0.0, a.dx, a.cfl, h->t2, a.t_end, lam1,
-              t1);
-    const unsigned long long p1 = q->pred[1];
-    step_size(LAM_PER_STEP, from_bits(p1 > lbc ? p1 : lbc), 0.0, a.dx, a.cfl, t1, a.t_end, lam2, t2);
-    if (level == 2 && !(t1 < a.t_end)) return;  // no second step
-    const double c41 = 1.0 / (4.0 * lam1), c42 = 1.0 / (4.0 * lam2);
+    const double gm1 = a.gamma - 1.0;
+    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
     const double* fin = h->cur_out ? a.f1 : a.f0;
     const int nx = a.nx, ny = a.ny;
-    const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
-    auto from_f = [&](int xs, int ys, double (&f)[16]) {
-        const double* row = fin + (long long)ys * a.rs;
-#pragma unroll
-        for (int p = 0; p < 16; ++p) f[p] = row[p * a.ps + xs];
-    };
-    auto after_one = [&](int xs, int ys, double (&f)[16]) { pulled_cell(a, xs, ys, c41, from_f, f); };
-    double best = 0.0;
+    // 1/(4 lambda) of the next launch's steps 1 .. 3 (scalars: an array
+    // indexed by the run-time level would live in scratch memory)
+    double c4a = 0.0, c4b = 0.0, c4c = 0.0;
+    auto c4_of = [&](int i) { return i == 0 ? c4a : (i == 1 ? c4b : c4c); };
+    static_assert(KMAX_STEPS <= 4, "three predicted steps at most");
+    double t = h->t_out;              // time before the next step
+    unsigned long long lstep = lb;    // the bound its speed comes from
     unsigned evaluated = 0;
-    const unsigned work = ncand * 9u;
-    for (unsigned i = blockIdx.x * blockDim.x + tid; i < work; i += gridDim.x * blockDim.x) {
-        const PredCand e = a.cand[i / 9u];
-        if (!(e.l >= floor_l)) continue;
-        const int cy = (int)(e.cell / nx), cx = (int)(e.cell % nx);
-        int x = cx + (int)(i % 3u) - 1, y = cy + (int)((i / 3u) % 3u) - 1;
-        if (px) x = map_index(x, nx, true);
-        if (py) y = map_index(y, ny, true);
-        if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
-        ++evaluated;
-        double g[16];
-        if (level == 1) pulled_cell(a, x, y, c41, from_f, g);
-        else pulled_cell(a, x, y, c42, after_one, g);
-        double U1[4], l1;
-        moments_d2q4(g, U1);
-        if (bound_d2q4(U1, a.gamma, &l1)) best = fmax(best, l1);
+    for (int level = 1; level < a.kmax; ++level) {
+        // step `level` runs only while the time is short of t_end
+        if (!(t < a.t_end)) break;
+        double lam, t_next;
+        step_size(LAM_PER_STEP, from_bits(lstep > lbc ? lstep : lbc), 0.0, a.dx, a.cfl, t,
+                  a.t_end, lam, t_next);
+        const double c4l = 1.0 / (4.0 * lam);
+        if (level == 1) c4a = c4l;
+        else if (level == 2) c4b = c4l;
+        else c4c = c4l;
+        if (blockIdx.x == 0 && lane == 0) q->pred_valid = level;
+        double best = 0.0;
+        for (unsigned i = blockIdx.x; i < ncand; i += gridDim.x) {
+            const PredCand e = a.cand[i];
+            if (!(e.l >= floor_l)) continue;
+            const int cy = (int)(e.cell / nx), cx = (int)(e.cell % nx);
+            // post-collision populations of S within level+1 of the centre
+            {
+                const int r = level + 1, sd = 2 * r + 1;
+                for (int cell = lane; cell < sd * sd; cell += 64) {
+                    const int ox = cell % sd - r, oy = cell / sd - r;
+                    const int x = map_index(cx + ox, nx, px), y = map_index(cy + oy, ny, py);
+                    const double* row = fin + (long long)y * a.rs;
+                    double f[16];
+#pragma unroll
+                    for (int p = 0; p < 16; ++p) f[p] = row[p * a.ps + x];
+                    collide_into(f, gm1, c4a, a.omega, post0, PRED_C0, cell);
+                }
+                __syncthreads();
+            }
+            // the states after steps 1 .. level-1, collided for the next step
+            for (int st = 1; st < level; ++st) {
+                const int r = level + 1 - st, sd = 2 * r + 1;
+                const double* src = (st & 1) ? post0 : post1;
+                double* dst = (st & 1) ? post1 : post0;
+                const int sstride = (st & 1) ? PRED_C0 : PRED_C1;
+                const int dstride = (st & 1) ? PRED_C1 : PRED_C0;
+                for (int cell = lane; cell < sd * sd; cell += 64) {
+                    const int ox = cell % sd - r, oy = cell / sd - r;
+                    double g[16];
+                    gather_patch(a, cx, cy, ox, oy, src, r + 1, sstride, g);
+                    collide_into(g, gm1, c4_of(st), a.omega, dst, dstride, cell);
+                }
+                __syncthreads();
+            }
+            // the bound after step `level` on the 3 x 3 cells
+            if (lane < 9) {
+                const int ox = lane % 3 - 1, oy = lane / 3 - 1;
+                const int x = cx + ox, y = cy + oy;
+                const bool inside = (px || (x >= 0 && x < nx)) && (py || (y >= 0 && y < ny));
+                if (inside) {
+                    const bool odd = ((level - 1) & 1) != 0;
+                    double g[16], U1[4], l1;
+                    gather_patch(a, cx, cy, ox, oy, odd ? post1 : post0, 2,
+                                 odd ? PRED_C1 : PRED_C0, g);
+                    moments_d2q4(g, U1);
+                    if (bound_d2q4(U1, a.gamma, &l1)) best = fmax(best, l1);
+                    ++evaluated;
+                }
+            }
+            __syncthreads();  // the patches are free for the next candidate
+        }
+        best = wave_max(best);
+        if (lane == 0 && best > 0.0) publish_max(&q->pred[level], best);
+        if (level + 1 >= a.kmax) break;
+        grid.sync();
+        // the level's prediction, complete now: the next step's speed
+        lstep = __hip_atomic_load(&q->pred[level], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lstep == 0ull) break;
+        t = t_next;
     }
-    best = wave_max(best);
     unsigned cnt = evaluated;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-    if ((tid & 63) == 0) {
-        if (best > 0.0) publish_max(&q->pred[level], best);
-        if (cnt) atomicAdd(&ps->stat[PST_EVALUATED], (unsigned long long)cnt);
-    }
+    if (lane == 0 && cnt) atomicAdd(&ps->stat[PST_EVALUATED], (unsigned long long)cnt);
 }
 
 // Two fused steps of every domain of a 2D batch (fixed lattice speeds, so
@@ -1006,10 +1102,11 @@ hipError_t launch_pair_reset(PairState* ps, bool counters, hipStream_t s) {
 }
 
 hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(pair_predict_kernel, dim3(PRED_BLOCKS), dim3(256), 0, s, a, 1);
-    if (a.kmax >= 3)
-        hipLaunchKernelGGL(pair_predict_kernel, dim3(PRED_BLOCKS), dim3(256), 0, s, a, 2);
-    return hipGetLastError();
+    if (a.kmax < 2) return hipSuccess;
+    Pair2DArgs arg = a;
+    void* params[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pair_predict_kernel),
+                                      dim3(PRED_BLOCKS), dim3(64), params, 0, s);
 }
 
 template <int WPB, int KM>
@@ -1030,10 +1127,15 @@ static hipError_t launch_pair_wk(const Pair2DArgs& a, bool tape, int max_blocks,
     return hipGetLastError();
 }
 
+// Launches of three or more steps run in workgroups of 8 waves at most.
 template <int WPB>
 static hipError_t launch_pair_w(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
-    if (a.kmax >= 3 && !tape) return launch_pair_wk<WPB, 3>(a, tape, max_blocks, s);
-    return launch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
+    if (tape || a.kmax <= 2) return launch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
+    if constexpr (WPB <= 8) {
+        if (a.kmax == 3) return launch_pair_wk<WPB, 3>(a, tape, max_blocks, s);
+        if (a.kmax == 4) return launch_pair_wk<WPB, 4>(a, tape, max_blocks, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int WPB, int KM>
@@ -1054,8 +1156,12 @@ static int occupancy(bool cand, bool tape) {
 
 template <int WPB>
 static int pair_blocks_w(bool cand, int kmax, bool tape) {
-    if (tape) return occupancy<WPB, 2>(false, true);
-    return kmax >= 3 ? occupancy<WPB, 3>(cand, false) : occupancy<WPB, 2>(cand, false);
+    if (tape || kmax <= 2) return occupancy<WPB, 2>(cand && !tape, tape);
+    if constexpr (WPB <= 8) {
+        if (kmax == 3) return occupancy<WPB, 3>(cand, false);
+        return occupancy<WPB, 4>(cand, false);
+    }
+    return 1;
 }
 
 #define LBRS_PAIR_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12)

@@ -508,7 +508,8 @@ class Sim:
         return lbrs_get_state(self.ctx)
 
     PAIR_STATS = ("pairs", "rejected", "bound_only", "single", "predicted", "pred_hit",
-                  "pred_miss", "evaluated", "pred_none", "listed", "overflow", "steps3")
+                  "pred_miss", "evaluated", "pred_none", "listed", "overflow", "steps3",
+                  "steps4")
 
     def pair_stats(self) -> dict:
         """Counters of the fused launches since init (lbrs_pair_stats)."""

@@ -124,14 +124,15 @@ def _oracle_dJ(n, steps, rho0, d, window):
 
 
 @pytest.mark.parametrize("fuse,segment,store_all", [(1, 8, False), (2, 8, False), (2, 7, False),
-                                                    (3, 7, False), (1, None, True),
-                                                    (2, None, True), (3, None, True)])
+                                                    (3, 7, False), (4, 7, False),
+                                                    (1, None, True), (2, None, True),
+                                                    (3, None, True), (4, None, True)])
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_gradient_matches_oracle_dual_numbers(layout, fuse, segment, store_all):
     """Gradient (48^2, 60 steps) against the oracle's exact directional
     derivatives along three smooth directions: checkpointed, in single launches
     or with fused forward, recompute and adjoint steps (forward sweeps in two
-    or three steps per launch, recompute and adjoint in two; an odd segment
+    to four steps per launch, recompute and adjoint in two; an odd segment
     leaves one single step of each), and with every step's moments
     kept (no checkpoints, no recompute)."""
     n, steps = 48, 60

@@ -48,7 +48,7 @@ def _fused(w, tile=None, layout=0, fuse=2, **kw):
 
 
 # steps per fused launch
-FUSE = pytest.mark.parametrize("fuse", [2, 3])
+FUSE = pytest.mark.parametrize("fuse", [2, 3, 4])
 
 
 def _compare(w, t_end=math.inf, max_steps=10**9, omega=None, sides=None, lam_mode=0,
@@ -148,10 +148,11 @@ def test_riemann_to_end_large(n, fuse):
         # the path of the whole run went through checked guesses
         assert stats["rejected"] + stats["bound_only"] + stats["pred_hit"] > 0
         # every step accounted for: accepted multi-step launches count two,
-        # three-step ones one more, single steps one
-        assert 2 * stats["pairs"] + stats["steps3"] + stats["single"] == ref.nsteps
-        if fuse == 2:
-            assert stats["steps3"] == 0
+        # three-step ones one more, four-step ones two more, single steps one
+        steps = 2 * stats["pairs"] + stats["steps3"] + 2 * stats["steps4"] + stats["single"]
+        assert steps == ref.nsteps
+        assert stats["steps3"] == 0 or fuse >= 3
+        assert stats["steps4"] == 0 or fuse >= 4
 
 
 @pytest.mark.parametrize("sides", [(1, 1, 1, 1), (1, 1, 0, 0), (0, 0, 1, 1)])
@@ -174,15 +175,30 @@ def test_walls(sides, omega, fuse):
              fuse=fuse)
 
 
-@pytest.mark.parametrize("tile", [(0, 4), (3, 2), (0, 16)])
+@pytest.mark.parametrize("tile", [(0, 4), (3, 2), (0, 16), (1, 8), (2, 4)])
 @pytest.mark.parametrize("layout", [0, 1])
 @FUSE
 def test_walls_and_layouts_small_segments(tile, layout, fuse):
+    """Row segments of 1 to 4 rows: a segment that begins 1 or 2 rows above a
+    clamped or wall side still computes the rows below it for the later
+    steps, by the side rules (the blast reaches the sides, so a wrong ghost
+    row would show)."""
     w = wl.explosion(70)
     _compare(w, max_steps=45, omega=1.3, sides=(2, 2, 0, 0), tile=tile, layout=layout,
              name=f"fused{fuse} walls x l{layout} {tile}", fuse=fuse)
     _compare(w, max_steps=45, omega=1.3, sides=(0, 0, 2, 2), tile=tile, layout=layout,
              name=f"fused{fuse} walls y l{layout} {tile}", fuse=fuse)
+
+
+@pytest.mark.parametrize("sides", [(2, 2, 0, 0), (0, 0, 2, 2), (0, 0, 0, 0), (0, 2, 1, 1)])
+@pytest.mark.parametrize("tile", [(1, 8), (2, 8), (1, 2)])
+@FUSE
+def test_narrow_strips_and_segments(sides, tile, fuse):
+    """A 16 x 16 domain in 8-wave workgroups: strips of 2 columns begin 2 to 4
+    columns from a side, so their halo lanes hold the wall or ghost column."""
+    w = wl.explosion(16)
+    _compare(w, max_steps=30, omega=1.3, sides=sides, tile=tile,
+             name=f"fused{fuse} narrow {sides} {tile}", fuse=fuse)
 
 
 @FUSE
@@ -348,7 +364,7 @@ def test_checkpointed_gradient_with_fused_forward():
     w = wl.acoustic_pulse(64, steps=30)
     rho0 = torch.from_numpy(w.W[0].copy()).cuda()
     out = []
-    for fuse in (1, 2, 3):
+    for fuse in (1, 2, 3, 4):
         run = adjoint.GradientRunner(adjoint.GradientSpec(n=64, steps=30, segment=7, fuse=fuse),
                                      rho0)
         J = run.forward(rho0)
@@ -357,7 +373,7 @@ def test_checkpointed_gradient_with_fused_forward():
         run.close()
     J1, g1 = out[0]
     scale = float(g1.abs().max())
-    for fuse, (J2, g2) in zip((2, 3), out[1:]):
+    for fuse, (J2, g2) in zip((2, 3, 4), out[1:]):
         assert J2 == pytest.approx(J1, rel=1e-13)
         diff = float((g1 - g2).abs().max())
         report(f"fused{fuse} gradient", J=J1, rel_diff=diff / scale)
@@ -368,7 +384,7 @@ def test_mode_restrictions():
     w = wl.explosion(32)
     sim = gpu_sim(w)
     sim.init_primitive(w.W)
-    for bad in (0, 4):
+    for bad in (0, 5):
         with pytest.raises(lbrs.LBRSError) as e:
             sim.set_fusion(bad)
         assert e.value.code == lbrs.LBRS_E_INVAL

@@ -51,8 +51,8 @@ def _noalloc(w, t_end, fuse, max_steps):
 
 
 def test_noalloc_matches_the_existing_entry_point_twice():
-    cases = [(wl.riemann2d(160), 0.06, 2), (wl.riemann2d(128), 0.05, 3),
-             (wl.riemann2d(96), 0.04, 1)]
+    cases = [(wl.riemann2d(160), 0.06, 2), (wl.riemann2d(144), 0.05, 3),
+             (wl.riemann2d(128), 0.05, 4), (wl.riemann2d(96), 0.04, 1)]
     for i, (w, t_end, fuse) in enumerate(cases):
         print(f"noalloc case {i}: {w.name} {w.nx}x{w.ny} fuse {fuse}", flush=True)
         U_ref, st = _existing(w, t_end, fuse, 10**4)
@@ -78,7 +78,7 @@ def test_noalloc_rejects_bodies_and_bad_arguments():
     p = lbrs.make_params(w.model, 32, 32, w.domain, bc=w.sides, solid=solid)
     buf = torch.empty(16 * 32 * 32, dtype=torch.float64, device="cuda")
     U = torch.empty(4 * 32 * 32, dtype=torch.float64, device="cuda")
-    for kw in [dict(p=p, fuse=1), dict(p=lbrs.make_params(w.model, 32, 32, w.domain), fuse=4)]:
+    for kw in [dict(p=p, fuse=1), dict(p=lbrs.make_params(w.model, 32, 32, w.domain), fuse=5)]:
         with pytest.raises(lbrs.LBRSError) as e:
             lbrs.lbrs_run_noalloc(kw["p"], U, buf, torch.empty_like(buf), 5, 0.1, kw["fuse"], U)
         assert e.value.code == lbrs.LBRS_E_INVAL
