@@ -39,8 +39,6 @@
 //
 // Also here: the taped form (U^n and U^{n+1} stored for the gradients'
 // recompute) and the 2D batch's form over all domains (fixed speeds).
-#include <hip/hip_cooperative_groups.h>
-
 #include "lbrs_launch.hpp"
 #include "lbrs_rowops.hpp"
 
@@ -814,15 +812,14 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
 }
 
 // The predictions after fused launch a.launch, for the state S it leaves:
-// level L (1 .. kmax-1) evaluates the exact bound of the state after L steps
-// from S on the 3 x 3 cells around every listed candidate whose bound is
-// within CAND_REL of lambda*(S), and maxes it into pred[L] of the record the
-// next launch reads.  Step 1 runs at the speed from lambda*(S) (known now),
-// step L > 1 at the speed from the level L-1 prediction, so the levels are
-// separated by grid barriers (a cooperative launch; every decision to go on
-// is taken alike by every workgroup from values in memory).  None when the
-// launch listed no candidates or more than the list holds, or met a
-// non-physical state.
+// level L (1 .. kmax-1, one launch each) evaluates the exact bound of the
+// state after L steps from S on the 3 x 3 cells around every listed
+// candidate whose bound is within CAND_REL of lambda*(S), and maxes it into
+// pred[L] of the record the next launch reads.  Step 1 runs at the speed from
+// lambda*(S) (known now), step L > 1 at the speed from the level L-1
+// prediction (so each level is a launch of its own).  None when the launch
+// listed no candidates or more than the list holds, or met a non-physical
+// state.
 //
 // A one-wave workgroup takes a candidate at a time and marches its patch: the
 // post-collision populations of S on the cells within L+1 of the centre,
@@ -832,9 +829,10 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
 // beyond a clamped side is the edge cell, a periodic side wraps), and its
 // next state pulls from the domain cells its populations come from, as the
 // step kernels do, with the step kernels' own device functions: the same
-// bits.  Workgroup 0 also sets the record's count of valid levels and the
+// bits.  Enough workgroups that every candidate of a usual list has its own
+// wave; workgroup 0 also sets the record's count of valid levels and the
 // counters.
-static constexpr int PRED_BLOCKS = 256;
+static constexpr int PRED_BLOCKS = 2048;
 static constexpr int PRED_R = KMAX_STEPS;              // patch radius of the deepest level
 static constexpr int PRED_C0 = (2 * PRED_R + 1) * (2 * PRED_R + 1);  // cells, even stages
 static constexpr int PRED_C1 = (2 * PRED_R - 1) * (2 * PRED_R - 1);  // cells, odd stages
@@ -882,7 +880,7 @@ __device__ inline void collide_into(const double f[16], double gm1, double c4, d
 
 }  // namespace
 
-__global__ __launch_bounds__(64) void pair_predict_kernel(Pair2DArgs a) {
+__global__ __launch_bounds__(64) void pair_predict_kernel(Pair2DArgs a, int level) {
     __shared__ double post0[16 * PRED_C0];
     __shared__ double post1[16 * PRED_C1];
     const LaunchSlots ls = slots_for(a.launch);
@@ -892,42 +890,48 @@ __global__ __launch_bounds__(64) void pair_predict_kernel(Pair2DArgs a) {
     const int lane = threadIdx.x;
     const unsigned ncand = h->ncand;
     const bool armed = h->armed != 0;
-    const bool ok = armed && ncand > 0u && ncand <= (unsigned)PRED_CAP && a.st->bad[ls.la] == 0u;
-    if (blockIdx.x == 0 && lane == 0 && armed) {
+    bool ok = armed && ncand > 0u && ncand <= (unsigned)PRED_CAP && a.st->bad[ls.la] == 0u;
+    if (level == 1 && blockIdx.x == 0 && lane == 0 && armed) {
         // (a launch that listed nothing keeps what its record carries)
-        q->pred_valid = 0;
+        q->pred_valid = ok ? 1 : 0;
         ps->stat[ok ? PST_PREDICTED : PST_PRED_NONE] += 1;
         ps->stat[PST_LISTED] += ncand;
         if (ncand > (unsigned)PRED_CAP) ps->stat[PST_OVERFLOW] += 1;
     }
-    if (!ok) return;  // alike in every workgroup: before any barrier
-    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    if (level > 1) ok = ok && q->pred_valid >= level - 1;
+    if (!ok) return;
     const unsigned long long lb = a.st->lam[ls.la];
     const unsigned long long lbc = a.st->lam_bc;
+    // 1/(4 lambda) of the next launch's steps 1 .. level (scalars: an array
+    // indexed by the run-time level would live in scratch memory); step s
+    // runs only while the time before it is short of t_end
+    static_assert(KMAX_STEPS <= 4, "three predicted steps at most");
+    double c4a = 0.0, c4b = 0.0, c4c = 0.0;
+    {
+        double t = h->t_out;
+        unsigned long long lstep = lb;
+        for (int st = 1; st <= level; ++st) {
+            if (lstep == 0ull || !(t < a.t_end)) return;
+            double lam, t_next;
+            step_size(LAM_PER_STEP, from_bits(lstep > lbc ? lstep : lbc), 0.0, a.dx, a.cfl, t,
+                      a.t_end, lam, t_next);
+            const double c4 = 1.0 / (4.0 * lam);
+            if (st == 1) c4a = c4;
+            else if (st == 2) c4b = c4;
+            else c4c = c4;
+            if (st < level) lstep = q->pred[st];
+            t = t_next;
+        }
+    }
+    auto c4_of = [&](int i) { return i == 0 ? c4a : (i == 1 ? c4b : c4c); };
+    if (level > 1 && blockIdx.x == 0 && lane == 0) q->pred_valid = level;
     const double floor_l = from_bits(lb) * (1.0 - CAND_REL);
     const double gm1 = a.gamma - 1.0;
     const bool px = a.bc[0] == BC_PERIODIC, py = a.bc[2] == BC_PERIODIC;
     const double* fin = h->cur_out ? a.f1 : a.f0;
     const int nx = a.nx, ny = a.ny;
-    // 1/(4 lambda) of the next launch's steps 1 .. 3 (scalars: an array
-    // indexed by the run-time level would live in scratch memory)
-    double c4a = 0.0, c4b = 0.0, c4c = 0.0;
-    auto c4_of = [&](int i) { return i == 0 ? c4a : (i == 1 ? c4b : c4c); };
-    static_assert(KMAX_STEPS <= 4, "three predicted steps at most");
-    double t = h->t_out;              // time before the next step
-    unsigned long long lstep = lb;    // the bound its speed comes from
     unsigned evaluated = 0;
-    for (int level = 1; level < a.kmax; ++level) {
-        // step `level` runs only while the time is short of t_end
-        if (!(t < a.t_end)) break;
-        double lam, t_next;
-        step_size(LAM_PER_STEP, from_bits(lstep > lbc ? lstep : lbc), 0.0, a.dx, a.cfl, t,
-                  a.t_end, lam, t_next);
-        const double c4l = 1.0 / (4.0 * lam);
-        if (level == 1) c4a = c4l;
-        else if (level == 2) c4b = c4l;
-        else c4c = c4l;
-        if (blockIdx.x == 0 && lane == 0) q->pred_valid = level;
+    {
         double best = 0.0;
         for (unsigned i = blockIdx.x; i < ncand; i += gridDim.x) {
             const PredCand e = a.cand[i];
@@ -981,12 +985,6 @@ __global__ __launch_bounds__(64) void pair_predict_kernel(Pair2DArgs a) {
         }
         best = wave_max(best);
         if (lane == 0 && best > 0.0) publish_max(&q->pred[level], best);
-        if (level + 1 >= a.kmax) break;
-        grid.sync();
-        // the level's prediction, complete now: the next step's speed
-        lstep = __hip_atomic_load(&q->pred[level], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (lstep == 0ull) break;
-        t = t_next;
     }
     unsigned cnt = evaluated;
 #pragma unroll
@@ -1102,11 +1100,9 @@ hipError_t launch_pair_reset(PairState* ps, bool counters, hipStream_t s) {
 }
 
 hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s) {
-    if (a.kmax < 2) return hipSuccess;
-    Pair2DArgs arg = a;
-    void* params[] = {&arg};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pair_predict_kernel),
-                                      dim3(PRED_BLOCKS), dim3(64), params, 0, s);
+    for (int level = 1; level < a.kmax; ++level)
+        hipLaunchKernelGGL(pair_predict_kernel, dim3(PRED_BLOCKS), dim3(64), 0, s, a, level);
+    return hipGetLastError();
 }
 
 template <int WPB, int KM>
