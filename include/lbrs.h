@@ -481,20 +481,23 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
 int lbrs_batch2d_reset(lbrs_batch2d* b, const double* d_U0);
 
 /* nsteps collide-and-stream steps of every domain: one launch per step, or
- * with lbrs_batch2d_set_fusion(b, 2) one launch per two steps (and one more
- * for an odd count). */
+ * with lbrs_batch2d_set_fusion(b, k) one launch per k steps (and one more
+ * for the remainder: a fused launch for two or more steps, a single step
+ * for one). */
 int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps);
 
 /* Time steps per forward launch of lbrs_batch2d_step and of the forward
- * sweep of lbrs_batch2d_gradient: 1 (the default) or 2.  With 2 each
- * wavefront streams the rows of f^{n+1} it has just produced straight into
- * the next step (as lbrs_set_fusion; the speeds are fixed, so nothing is
- * guessed): half the HBM traffic per step, the same results to rounding.  A
- * domain whose f^{n+1} or f^{n+2} is non-physical gets its status set.  The
- * gradient's taped recompute and its adjoint steps are fused too (two per
- * launch); lbrs_batch2d_step_tape and lbrs_batch2d_adjoint_step stay single
- * steps.
- * LBRS_E_INVAL for other values. */
+ * sweep of lbrs_batch2d_gradient: 1 (the default), 2, 3 or 4.  With k > 1
+ * each wavefront streams the rows of f^{n+1} it has just produced straight
+ * into the next step, k times (as lbrs_set_fusion; the speeds are fixed, so
+ * nothing is guessed): 1/k of the HBM traffic per step, the same results to
+ * rounding.  A domain with a non-physical state after any of the k steps
+ * gets its status set.  The gradient's taped recompute and its adjoint steps
+ * are fused too (two per launch); lbrs_batch2d_step_tape and
+ * lbrs_batch2d_adjoint_step stay single steps.  A change of k re-plans the
+ * fused launches' strips (at most 64 - 2k columns) and uploads the domain
+ * table (waits for the stream).
+ * LBRS_E_INVAL for other values; LBRS_E_HIP if the upload fails. */
 int lbrs_batch2d_set_fusion(lbrs_batch2d* b, int steps_per_launch);
 
 /* One step that also stores every domain's input moments U^n in d_Utape [4][total]. */

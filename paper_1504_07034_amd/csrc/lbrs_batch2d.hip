@@ -209,9 +209,9 @@ struct lbrs_batch2d {
     long long nsteps;
     hipStream_t stream;
     int wpb, max_blocks;
-    int fuse;                 // time steps per forward launch (1, or 2 fused)
+    int fuse;                 // time steps per forward launch (1, or 2 to KMAX_STEPS fused)
     long long pntiles;        // tiles of the fused launches
-    int pmax_blocks;
+    int pmax_blocks[KMAX_STEPS + 1];  // resident workgroups of the k-step fused kernel
     int amax_blocks;          // resident workgroups of the fused adjoint kernel
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -225,6 +225,21 @@ struct lbrs_batch2d {
 namespace {
 
 size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+// The tile list of the fused launches of up to k steps (k >= 2): strips of at
+// most 64 - 2k columns, a multiple of the waves per workgroup per domain, the
+// domain's row segments (host copy; the caller uploads it).
+void b2_fused_tiles(lbrs_batch2d* b, int k) {
+    const int cols = 64 - 2 * (k < 2 ? 2 : k);
+    long long ptiles = 0;
+    for (Domain2D& d : b->doms) {
+        d.ptile0 = ptiles;
+        d.pnstrips = ((d.nx + cols - 1) / cols + b->wpb - 1) / b->wpb * b->wpb;
+        d.pstrip = (d.nx + d.pnstrips - 1) / d.pnstrips;
+        ptiles += (long long)d.pnstrips * d.nseg;
+    }
+    b->pntiles = ptiles;
+}
 
 static inline unsigned grid_cells(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -291,11 +306,12 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
     b->ndom = ndom;
     b->wpb = 8;
     b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb, true, false);
-    b->pmax_blocks = prop.multiProcessorCount * step2d_batch_pair_blocks_per_cu(b->wpb);
+    for (int k = 2; k <= KMAX_STEPS; ++k)
+        b->pmax_blocks[k] = prop.multiProcessorCount * step2d_batch_pair_blocks_per_cu(b->wpb, k);
     b->amax_blocks = prop.multiProcessorCount * b2_adjoint_pair_blocks_per_cu(b->wpb);
     b->fuse = 1;
     b->doms.resize(ndom);
-    long long off = 0, rows = 0, tiles = 0, ptiles = 0;
+    long long off = 0, rows = 0, tiles = 0;
     b->max_nx = 0;
     for (int i = 0; i < ndom; ++i) {
         const lbrs_params* p = &doms[i];
@@ -307,9 +323,6 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
         d.ny = p->ny;
         d.nstrips = ((p->nx + 61) / 62 + b->wpb - 1) / b->wpb * b->wpb;
         d.strip = (p->nx + d.nstrips - 1) / d.nstrips;
-        d.ptile0 = ptiles;
-        d.pnstrips = ((p->nx + 59) / 60 + b->wpb - 1) / b->wpb * b->wpb;
-        d.pstrip = (p->nx + d.pnstrips - 1) / d.pnstrips;
         // row segments of about 64 rows (the batch has many tiles per round)
         long long nseg = (p->ny + 63) / 64;
         d.nseg = (int)std::max(1LL, std::min<long long>(nseg, p->ny));
@@ -324,13 +337,12 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
         off += (long long)p->nx * p->ny;
         rows += p->ny;
         tiles += (long long)d.nstrips * d.nseg;
-        ptiles += (long long)d.pnstrips * d.nseg;
         b->max_nx = std::max(b->max_nx, p->nx);
     }
     b->total = off;
     b->rows = rows;
     b->ntiles = tiles;
-    b->pntiles = ptiles;
+    b2_fused_tiles(b, 2);
     char* s = (char*)d_scratch;
     b->d_doms = (Domain2D*)s;
     s += al256(sizeof(Domain2D) * ndom);
@@ -392,20 +404,37 @@ static Batch2DArgs b2_args(const lbrs_batch2d* b, double* tape) {
 }
 
 int lbrs_batch2d_set_fusion(lbrs_batch2d* b, int steps_per_launch) {
-    if (!b || (steps_per_launch != 1 && steps_per_launch != 2)) return LBRS_E_INVAL;
+    if (!b || steps_per_launch < 1 || steps_per_launch > KMAX_STEPS) return LBRS_E_INVAL;
+    if (steps_per_launch != b->fuse) {
+        // the fused launches' strips for this many steps (every fused
+        // kernel, the taped and adjoint pairs too, walks this tile list),
+        // into the device table (whose lattice speeds the device computed)
+        const size_t bytes = sizeof(Domain2D) * b->ndom;
+        if (!ok(hipStreamSynchronize(b->stream)) ||
+            !ok(hipMemcpy(b->doms.data(), b->d_doms, bytes, hipMemcpyDeviceToHost)))
+            return LBRS_E_HIP;
+        b2_fused_tiles(b, steps_per_launch);
+        if (!ok(hipMemcpyAsync(b->d_doms, b->doms.data(), bytes, hipMemcpyHostToDevice,
+                               b->stream)) ||
+            !ok(hipStreamSynchronize(b->stream)))
+            return LBRS_E_HIP;
+    }
     b->fuse = steps_per_launch;
     return LBRS_OK;
 }
 
 int lbrs_batch2d_step(lbrs_batch2d* b, int nsteps) {
     if (!b || nsteps < 0) return LBRS_E_INVAL;
-    if (b->fuse == 2) {
-        for (; nsteps >= 2; nsteps -= 2) {
-            if (!ok(launch_step2d_batch_pair(b2_args(b, nullptr), b->wpb, false, b->pmax_blocks,
-                                             b->stream)))
+    if (b->fuse >= 2) {
+        // launches of fuse steps, then one of the remaining steps (two or more)
+        while (nsteps >= 2) {
+            const int k = nsteps < b->fuse ? nsteps : b->fuse;
+            if (!ok(launch_step2d_batch_pair(b2_args(b, nullptr), b->wpb, false, k,
+                                             b->pmax_blocks[k], b->stream)))
                 return LBRS_E_HIP;
             b->cur ^= 1;
-            b->nsteps += 2;
+            b->nsteps += k;
+            nsteps -= k;
         }
     }
     for (int i = 0; i < nsteps; ++i) {
@@ -549,11 +578,12 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
     // len steps from the current state, U^{n+i} to tape slot i
     auto taped_steps = [&](int len) -> int {
         int i = 0;
-        if (b->fuse == 2) {  // two steps per launch, both inputs taped
+        if (b->fuse >= 2) {  // two steps per launch, both inputs taped
             for (; i + 1 < len; i += 2) {
                 Batch2DArgs a = b2_args(b, d_tape + i * ucount);
                 a.tape2 = d_tape + (i + 1) * ucount;
-                if (!ok(launch_step2d_batch_pair(a, b->wpb, true, b->pmax_blocks, b->stream)))
+                if (!ok(launch_step2d_batch_pair(a, b->wpb, true, 2, b->pmax_blocks[2],
+                                                 b->stream)))
                     return LBRS_E_HIP;
                 b->cur ^= 1;
                 b->nsteps += 2;
@@ -568,7 +598,7 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
     // adjoint steps back through tape slots len-1 .. 0 (cur and nxt swap)
     auto reverse_steps = [&](int len) -> int {
         int i = len - 1;
-        if (b->fuse == 2) {  // two adjoint steps per launch: tapes i (U^{n+1}) and i-1 (U^n)
+        if (b->fuse >= 2) {  // two adjoint steps per launch: tapes i (U^{n+1}) and i-1 (U^n)
             for (; i >= 1; i -= 2) {
                 int r = b2_adjoint_pair_step(b, d_tape + i * ucount, d_tape + (i - 1) * ucount,
                                              cur, nxt);

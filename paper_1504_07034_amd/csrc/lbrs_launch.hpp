@@ -299,10 +299,10 @@ struct Domain2D {
     long long coff;
     long long tile0;       // first tile of the domain in the batch's tile list
     long long row0;        // first row of the domain among all domains' rows
-    long long ptile0;      // the same in the tile list of the fused two-step launches
+    long long ptile0;      // the same in the tile list of the fused launches
     int nx, ny;
     int strip, nstrips, nseg;
-    int pstrip, pnstrips;  // strips of the fused launches (<= 60 columns)
+    int pstrip, pnstrips;  // strips of the fused launches (<= 64 - 2k columns for k steps)
     int bc[4];
     double dx, gamma, omega, cfl, lam;
     int lam_mode;
@@ -325,10 +325,11 @@ struct Batch2DArgs {
 
 hipError_t launch_step2d_batch(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
                                hipStream_t s);
-// Two fused steps of every domain (fixed lattice speeds), f^n in buffer a.cur.
-hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
-                                    hipStream_t s);
-int step2d_batch_pair_blocks_per_cu(int wpb);
+// k fused steps of every domain (fixed lattice speeds, k = 2 .. KMAX_STEPS;
+// the taped form: 2), f^n in buffer a.cur.
+hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, bool tape, int k,
+                                    int max_blocks, hipStream_t s);
+int step2d_batch_pair_blocks_per_cu(int wpb, int k);
 hipError_t launch_scalar_step2d(const ScalarArgs& a, int wpb, int max_blocks, hipStream_t s);
 hipError_t launch_scalar_step1d(const ScalarArgs& a, int q, hipStream_t s);
 int scalar2d_blocks_per_cu(int wpb);
@@ -352,7 +353,7 @@ int step2d_pair_blocks_per_cu(int wpb, bool cand, int kmax, bool tape);
 hipError_t launch_pair_prepare(PairState* ps, const DevState* st, int slot, long long max_steps,
                                hipStream_t s);
 // After fused launch a.launch: evaluate its candidates and leave the
-// predictions (or none) for the next launch (two levels when a.kmax >= 3).
+// predictions (or none) for the next launch (levels 1 .. a.kmax-1).
 hipError_t launch_pair_predict(const Pair2DArgs& a, hipStream_t s);
 // Clear the fused launches' record (a prediction left for the state, open
 // checks) and, with counters, their counters (context initialisation).

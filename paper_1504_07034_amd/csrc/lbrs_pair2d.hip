@@ -992,16 +992,22 @@ __global__ __launch_bounds__(64) void pair_predict_kernel(Pair2DArgs a, int leve
     if (lane == 0 && cnt) atomicAdd(&ps->stat[PST_EVALUATED], (unsigned long long)cnt);
 }
 
-// Two fused steps of every domain of a 2D batch (fixed lattice speeds, so
-// nothing is guessed): the single-domain march over the fused launches' tile
-// list, numbered domain by domain (each domain's strip count a multiple of
-// the waves per workgroup, so a workgroup's waves share a domain and a row
-// segment); a non-physical f^{n+1} or f^{n+2} sets the domain's status.
-template <int WPB, bool TAPE>
+// K fused steps of every domain of a 2D batch (fixed lattice speeds, so
+// nothing is guessed): the single-domain march over the fused launches'
+// tile list, numbered domain by domain (each domain's strip count a multiple
+// of the waves per workgroup, so a workgroup's waves share a domain and a
+// row segment; strips of at most 64 - 2K columns); a non-physical state
+// after any of the K steps sets the domain's status.  The taped form takes
+// two steps.
+template <int WPB, bool TAPE, int K>
 __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
+    static_assert(!TAPE || K == 2, "the taped form takes two steps");
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long total_waves = (long long)gridDim.x * WPB;
+    constexpr bool LPB = PipelineInLds<WPB, K>::value;
+    __shared__ double pb_lds[LPB ? WPB * K * 8 * 64 : 1];
+    double* pbl = pb_lds + (LPB ? wave * K * 8 * 64 : 0);
     for (long long tile = (long long)xcd_remap(blockIdx.x, gridDim.x) * WPB + wave;
          tile < a.pntiles; tile += total_waves) {
         int lo = 0, hi = a.ndom - 1;
@@ -1042,8 +1048,11 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
             lm[i] = 0.0;
             bad[i] = false;
         }
-        march_k<WPB, 2, TAPE>(g, strip, y0, y1, lane, lm, bad);
-        if (__any(bad[0] || bad[1]) && lane == 0) atomicOr(&a.status[lo], 1u);
+        march_k<WPB, K, TAPE, false, LPB>(g, strip, y0, y1, lane, lm, bad, true, pbl);
+        bool any_bad = false;
+#pragma unroll
+        for (int i = 0; i < K; ++i) any_bad = any_bad || bad[i];
+        if (__any(any_bad) && lane == 0) atomicOr(&a.status[lo], 1u);
     }
 }
 
@@ -1179,44 +1188,67 @@ int step2d_pair_blocks_per_cu(int wpb, bool cand, int kmax, bool tape) {
     return 1;
 }
 
-template <int WPB>
-static hipError_t launch_batch_pair_w(const Batch2DArgs& a, bool tape, int max_blocks,
-                                      hipStream_t s) {
+template <int WPB, int K>
+static hipError_t launch_batch_pair_wk(const Batch2DArgs& a, bool tape, int max_blocks,
+                                       hipStream_t s) {
     long long nblocks = (a.pntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
     if (tape)
-        hipLaunchKernelGGL((step2d_batch_pair<WPB, true>), dim3((unsigned)nblocks), dim3(64 * WPB),
-                           0, s, a);
+        hipLaunchKernelGGL((step2d_batch_pair<WPB, true, 2>), dim3((unsigned)nblocks),
+                           dim3(64 * WPB), 0, s, a);
     else
-        hipLaunchKernelGGL((step2d_batch_pair<WPB, false>), dim3((unsigned)nblocks),
+        hipLaunchKernelGGL((step2d_batch_pair<WPB, false, K>), dim3((unsigned)nblocks),
                            dim3(64 * WPB), 0, s, a);
     return hipGetLastError();
 }
 
+// Launches of three or more steps run in workgroups of 8 waves at most.
 template <int WPB>
-static int batch_pair_blocks_w() {
-    int n = 0, m = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_batch_pair<WPB, false>,
-                                                                64 * WPB, 0);
-    hipError_t f = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, step2d_batch_pair<WPB, true>,
-                                                                64 * WPB, 0);
-    if (e != hipSuccess || f != hipSuccess) return 1;
-    n = n < m ? n : m;
-    return n > 0 ? n : 1;
+static hipError_t launch_batch_pair_w(const Batch2DArgs& a, bool tape, int k, int max_blocks,
+                                      hipStream_t s) {
+    if (tape || k == 2) return launch_batch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
+    if constexpr (WPB <= 8) {
+        if (k == 3) return launch_batch_pair_wk<WPB, 3>(a, false, max_blocks, s);
+        if (k == 4) return launch_batch_pair_wk<WPB, 4>(a, false, max_blocks, s);
+    }
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, bool tape, int max_blocks,
-                                    hipStream_t s) {
+template <int WPB, bool TAPE, int K>
+static int batch_occupancy() {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, step2d_batch_pair<WPB, TAPE, K>, 64 * WPB, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+// Resident workgroups per CU of the k-step form (k = 2: the plain and the
+// taped form, whichever fits fewer).
+template <int WPB>
+static int batch_pair_blocks_w(int k) {
+    if (k == 2) {
+        const int n = batch_occupancy<WPB, false, 2>(), m = batch_occupancy<WPB, true, 2>();
+        return n < m ? n : m;
+    }
+    if constexpr (WPB <= 8) {
+        if (k == 3) return batch_occupancy<WPB, false, 3>();
+        if (k == 4) return batch_occupancy<WPB, false, 4>();
+    }
+    return 1;
+}
+
+hipError_t launch_step2d_batch_pair(const Batch2DArgs& a, int wpb, bool tape, int k,
+                                    int max_blocks, hipStream_t s) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return launch_batch_pair_w<W>(a, tape, max_blocks, s);
+    if (wpb == W) return launch_batch_pair_w<W>(a, tape, k, max_blocks, s);
     LBRS_PAIR_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return hipErrorInvalidValue;
 }
 
-int step2d_batch_pair_blocks_per_cu(int wpb) {
+int step2d_batch_pair_blocks_per_cu(int wpb, int k) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return batch_pair_blocks_w<W>();
+    if (wpb == W) return batch_pair_blocks_w<W>(k);
     LBRS_PAIR_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return 1;

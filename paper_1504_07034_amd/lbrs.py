@@ -675,7 +675,7 @@ class Batch2D:
         return self
 
     def set_fusion(self, steps_per_launch: int):
-        """2: two fused steps per forward launch (lbrs_batch2d_set_fusion)."""
+        """k = 2 to 4: k fused steps per forward launch (lbrs_batch2d_set_fusion)."""
         self._fuse = int(steps_per_launch)
         if self.b is not None:
             _check(load_library().lbrs_batch2d_set_fusion(self.b, self._fuse),

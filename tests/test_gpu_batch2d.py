@@ -287,14 +287,14 @@ def test_batch2d_full_configuration_wave():
 
 @pytest.mark.parametrize("nsteps", [1, 2, 7, 40])
 def test_batch2d_fused_vs_single_launches(nsteps):
-    """Fused batch launches (two steps each, one more for an odd count) give
-    the fused single-domain path's results bit for bit, and the single-step
-    batch's to rounding."""
+    """Fused batch launches (k = 2, 3, 4 steps each, one more launch for the
+    remainder) give the fused single-domain path's results bit for bit, and
+    the single-step batch's to rounding."""
     ws = _ragged_domains()
     doms = _doms(ws)
     U0 = _pool_U0(ws, doms)
     outs = {}
-    for fuse in (1, 2):
+    for fuse in (1, 2, 3, 4):
         B = lbrs.Batch2D(doms)
         B.init(U0)
         B.set_fusion(fuse)
@@ -303,19 +303,20 @@ def test_batch2d_fused_vs_single_launches(nsteps):
         assert st["rc"] == 0 and st["nsteps"] == nsteps
         outs[fuse] = B.moments()
         B.close()
-    diff = float((outs[1] - outs[2]).abs().max())
-    report("batch2d fused vs single", nsteps=nsteps, max_abs=diff,
-           bitwise=bool(torch.equal(outs[1], outs[2])))
-    assert diff <= 1e-12
-    for d, w in enumerate(ws):
-        sim = lbrs.Sim(lbrs.LBRS_D2Q4, w.nx, w.ny, domain=w.domain, gamma=w.gamma, omega=1.0,
-                       cfl=w.cfl, bc=w.sides, lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT,
-                       layout=lbrs.LBRS_LAYOUT_ROWS)
-        sim.init_primitive(w.W)
-        sim.set_fusion(2)
-        sim.step(nsteps)
-        assert torch.equal(sim.moments().reshape(4, -1), outs[2][:, lbrs_slice(d, ws)])
-        sim.close()
+    for fuse in (2, 3, 4):
+        diff = float((outs[1] - outs[fuse]).abs().max())
+        report("batch2d fused vs single", fuse=fuse, nsteps=nsteps, max_abs=diff,
+               bitwise=bool(torch.equal(outs[1], outs[fuse])))
+        assert diff <= 1e-12
+        for d, w in enumerate(ws):
+            sim = lbrs.Sim(lbrs.LBRS_D2Q4, w.nx, w.ny, domain=w.domain, gamma=w.gamma,
+                           omega=1.0, cfl=w.cfl, bc=w.sides,
+                           lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT, layout=lbrs.LBRS_LAYOUT_ROWS)
+            sim.init_primitive(w.W)
+            sim.set_fusion(fuse)
+            sim.step(nsteps)
+            assert torch.equal(sim.moments().reshape(4, -1), outs[fuse][:, lbrs_slice(d, ws)])
+            sim.close()
 
 
 def lbrs_slice(d, ws):
@@ -325,8 +326,9 @@ def lbrs_slice(d, ws):
     return slice(off[d], off[d + 1])
 
 
+@pytest.mark.parametrize("fuse", [2, 3, 4])
 @pytest.mark.parametrize("omega", [0.7, 1.5])
-def test_batch2d_fused_mixed_sides_vs_oracle(omega):
+def test_batch2d_fused_mixed_sides_vs_oracle(omega, fuse):
     """Transmissive, periodic and wall sides in one fused batch, 31 steps,
     against the oracle."""
     ws = [wl.explosion(60), wl.riemann2d(80), wl.explosion(50), wl.fourier_modes(40, seed=3)]
@@ -334,7 +336,7 @@ def test_batch2d_fused_mixed_sides_vs_oracle(omega):
     doms = _doms(ws, sides=sides, omega=omega)
     B = lbrs.Batch2D(doms)
     B.init(_pool_U0(ws, doms))
-    B.set_fusion(2)
+    B.set_fusion(fuse)
     B.step(31)
     U = B.moments().cpu().numpy()
     st = B.state()
@@ -343,7 +345,8 @@ def test_batch2d_fused_mixed_sides_vs_oracle(omega):
                            sides=sides[d], lam_mode=oracle.LAM_FROZEN)
         ref = oracle.run(P, oracle.prim_to_cons(P, w.W), max_steps=31)
         err = float(np.max(np.abs(U[:, B.unit_slice(d)] - ref.U.reshape(4, -1))))
-        report("batch2d fused vs oracle", dom=d, sides=sides[d], err=err, status=st["status"][d])
+        report("batch2d fused vs oracle", fuse=fuse, dom=d, sides=sides[d], err=err,
+               status=st["status"][d])
         assert ref.status == 0 and st["status"][d] == 0 and err <= TOL
     B.close()
 
@@ -368,7 +371,7 @@ def test_batch2d_gradient_fused_forward():
     J = torch.zeros(len(ws), dtype=torch.float64, device="cuda")
     Ub = torch.empty((4, T), dtype=torch.float64, device="cuda")
     res = {}
-    for fuse in (1, 2):
+    for fuse in (1, 2, 4):
         B.set_fusion(fuse)
         B.gradient(U0, steps, seg, ck, tp, fb, wk, J, Ub, use_graph=False)
         res[fuse] = (J.clone(), Ub.clone())
@@ -377,15 +380,18 @@ def test_batch2d_gradient_fused_forward():
         B.gradient(U0, steps, seg, ck, tp, fb, wk, J, Ub, use_graph=True)
         torch.cuda.synchronize()
         assert torch.equal(J, res[fuse][0]) and torch.equal(Ub, res[fuse][1]), fuse
-    (J1, U1), (J2, U2) = res[1], res[2]
+    J1, U1 = res[1]
     scale = float(U1.abs().max())
-    report("batch2d gradient fused", J=J1.tolist(), rel=float((U1 - U2).abs().max()) / scale)
-    assert torch.allclose(J1, J2, rtol=1e-13, atol=0)
-    assert float((U1 - U2).abs().max()) <= 1e-11 * scale
+    for fuse in (2, 4):
+        J2, U2 = res[fuse]
+        report("batch2d gradient fused", fuse=fuse, J=J1.tolist(),
+               rel=float((U1 - U2).abs().max()) / scale)
+        assert torch.allclose(J1, J2, rtol=1e-13, atol=0)
+        assert float((U1 - U2).abs().max()) <= 1e-11 * scale
     B.close()
 
 
-@pytest.mark.parametrize("fuse", [1, 2])
+@pytest.mark.parametrize("fuse", [1, 2, 4])
 def test_batch2d_gradient_whole_tape(fuse):
     """segment >= nsteps: one forward sweep writes every step's moments and the
     adjoint runs straight back (no checkpoint, no recompute).  J and dJ/dU0
