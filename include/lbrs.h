@@ -405,7 +405,7 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * automatic segments of at least 4 rows; 16 waves per workgroup run as 12,
  * as 8 with k >= 3 or PER_STEP speeds; alternate is ignored).
  * lbrs_step_tape stays a single step; lbrs_backward_checkpointed recomputes
- * its segments two steps per launch when k > 1 (both steps' input moments
+ * its segments k steps per launch when k > 1 (every step's input moments
  * taped) and runs its adjoint steps two per launch (lbrs_adjoint_step2).
  * LBRS_E_INVAL for other values; LBRS_E_STATE with k > 1 for a 1D,
  * scalar-law, body or DIRICHLET context.  Takes effect for later calls. */

@@ -359,28 +359,28 @@ static bool pair_filter(const lbrs_ctx* c) {
     return c->cand && c->P.lambda_mode == LBRS_LAMBDA_PER_STEP;
 }
 
-static int pair_kmax(const lbrs_ctx* c, bool tape) { return tape ? 2 : c->fuse; }
+
 
 // Waves per workgroup of the fused kernel: 16-wave groups do not fit its
 // registers at the occupancy it needs and run as 12; launches of three or
 // more steps and the form that lists candidates (more registers) spill in
 // 12-wave groups, and run as 8.
-static int pair_wpb(const lbrs_ctx* c, bool tape = false) {
-    const int cap = !tape && (pair_filter(c) || c->fuse >= 3) ? 8 : 12;
+static int pair_wpb(const lbrs_ctx* c, bool tape, int kmax) {
+    const int cap = (!tape && pair_filter(c)) || kmax >= 3 ? 8 : 12;
     return c->waves_per_block > cap ? cap : c->waves_per_block;
 }
 
-static int pair_max_blocks(const lbrs_ctx* c, bool tape = false) {
+static int pair_max_blocks(const lbrs_ctx* c, bool tape, int kmax) {
     lbrs_ctx* m = const_cast<lbrs_ctx*>(c);
-    const int w = pair_wpb(c, tape);
+    const int w = pair_wpb(c, tape, kmax);
     const int form = tape ? 2 : (pair_filter(c) ? 1 : 0);
-    const int kmax = pair_kmax(c, tape);
     int& n = m->pbpc[form][kmax][w];
     if (n == 0) n = step2d_pair_blocks_per_cu(w, form == 1, kmax, tape);
     return c->cu_count * n;
 }
 
-static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end, bool tape = false) {
+// Launches of up to kmax steps (default: the context's fusion).
+static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end, bool tape = false, int kmax = 0) {
     Pair2DArgs a;
     a.f0 = c->f0;
     a.f1 = c->f1;
@@ -390,8 +390,8 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end, bool tape = false) 
     a.rs = c->rs;
     a.nx = c->P.nx;
     a.ny = c->P.ny;
-    const int wpb = pair_wpb(c, tape);
-    a.kmax = pair_kmax(c, tape);
+    a.kmax = kmax > 0 ? kmax : c->fuse;
+    const int wpb = pair_wpb(c, tape, a.kmax);
     const int cols = 64 - 2 * a.kmax;
     a.nstrips = ((c->P.nx + cols - 1) / cols + wpb - 1) / wpb * wpb;
     a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
@@ -399,7 +399,7 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end, bool tape = false) 
     if (c->rows_per_tile > 0) {
         nseg = (c->P.ny + c->rows_per_tile - 1) / c->rows_per_tile;
     } else {
-        nseg = (long long)pair_max_blocks(c, tape) * wpb / a.nstrips;
+        nseg = (long long)pair_max_blocks(c, tape, a.kmax) * wpb / a.nstrips;
         const long long cap = (c->P.ny + 3) / 4;
         if (nseg > cap) nseg = cap;
     }
@@ -416,7 +416,7 @@ static Pair2DArgs pair_args(const lbrs_ctx* c, double t_end, bool tape = false) 
     a.lam_mode = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP ? LAM_PER_STEP : LAM_FROZEN;
     for (int s = 0; s < 4; ++s) a.bc[s] = c->P.bc[s];
     a.last = 0;
-    a.tape0 = a.tape1 = nullptr;
+    for (int i = 0; i < KMAX_STEPS; ++i) a.tape[i] = nullptr;
     a.plane = c->plane;
     a.cand = pair_filter(c) && !tape ? c->cand : nullptr;
     return a;
@@ -523,11 +523,11 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), max_steps,
                                            c->stream);
         if (e != hipSuccess) return LBRS_E_HIP;
-        const int mb = pair_max_blocks(c);
+        const int mb = pair_max_blocks(c, false, a.kmax);
         for (int s = 0; s < nl; ++s) {
             a.launch = c->launches;
             a.last = s == nl - 1;
-            e = launch_step2d_pair(a, pair_wpb(c), false, mb, c->stream);
+            e = launch_step2d_pair(a, pair_wpb(c, false, a.kmax), false, mb, c->stream);
             // with per-step speeds, the prediction of the bound the next
             // launch's second step needs
             if (e == hipSuccess && a.cand) e = launch_pair_predict(a, c->stream);
@@ -709,7 +709,7 @@ static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const d
     a.rs = c->rs;
     a.nx = c->P.nx;
     a.ny = c->P.ny;
-    const int wpb = pair_wpb(c);
+    const int wpb = pair_wpb(c, false, 2);
     a.nstrips = ((c->P.nx + 59) / 60 + wpb - 1) / wpb * wpb;
     a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
     int& bpc = c->abpc[wpb];
@@ -733,25 +733,28 @@ static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const d
     return hip_status(launch_adjoint_pair(a, wpb, mb, c->stream));
 }
 
-// The recompute of a segment in fused launches (fixed lattice speed, so
-// nothing is guessed): launch k takes steps 2k+1 and 2k+2 of the segment and
-// writes their input moments to tape slots 2k and 2k+1 (an odd last step: a
-// one-step launch, slot len-1).
+// The recompute of a segment in fused launches of up to k = fuse steps
+// (fixed lattice speed, so nothing is guessed): every launch but the last
+// takes k steps (fewer at the segment's end), launch j steps kj+1 .. kj+k
+// writing their input moments to tape slots kj .. kj+k-1, and the last
+// launch at most one (a non-physical state ends the run; its tape is not
+// used).
 static int step_tape_fused(lbrs_ctx* c, int len, double* d_tape) {
     Pair2DArgs a = pair_args(c, INFINITY, true);
+    const int k = a.kmax;
     const long long ucount = (long long)c->K * c->plane;
-    const int nl = len / 2 + 1;
+    const int nl = (len + k - 2) / k + 1;
     hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), len, c->stream);
     if (e != hipSuccess) return LBRS_E_HIP;
-    const int mb = pair_max_blocks(c, true);
-    for (int k = 0; k < nl; ++k) {
-        const long long s0 = 2LL * k < len ? 2LL * k : len - 1;
-        const long long s1 = 2LL * k + 1 < len ? 2LL * k + 1 : len - 1;
+    const int mb = pair_max_blocks(c, true, k);
+    for (int j = 0; j < nl; ++j) {
         a.launch = c->launches;
-        a.last = k == nl - 1;
-        a.tape0 = d_tape + s0 * ucount;
-        a.tape1 = d_tape + s1 * ucount;
-        e = launch_step2d_pair(a, pair_wpb(c, true), true, mb, c->stream);
+        a.last = j == nl - 1;
+        for (int i = 0; i < KMAX_STEPS; ++i) {
+            const long long slot = (long long)k * j + i;
+            a.tape[i] = d_tape + (slot < len ? slot : len - 1) * ucount;
+        }
+        e = launch_step2d_pair(a, pair_wpb(c, true, k), true, mb, c->stream);
         if (e != hipSuccess) return LBRS_E_HIP;
         ++c->launches;
     }
@@ -765,16 +768,16 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
     if (c->dim != 2 || c->dir || c->codes) return LBRS_E_STATE;
     // the set-up kernel and two launches: the pair, then the one that checks
     // it (a one-step fallback writes slot d_Utape_n, as the first step would)
-    Pair2DArgs a = pair_args(c, INFINITY, true);
+    Pair2DArgs a = pair_args(c, INFINITY, true, 2);
     hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), 2, c->stream);
     if (e != hipSuccess) return LBRS_E_HIP;
-    const int mb = pair_max_blocks(c, true);
-    a.tape0 = d_Utape_n;
-    a.tape1 = d_Utape_n1;
+    const int mb = pair_max_blocks(c, true, 2);
+    a.tape[0] = d_Utape_n;
+    a.tape[1] = d_Utape_n1;
     for (int k = 0; k < 2; ++k) {
         a.launch = c->launches;
         a.last = k == 1;
-        e = launch_step2d_pair(a, pair_wpb(c, true), true, mb, c->stream);
+        e = launch_step2d_pair(a, pair_wpb(c, true, 2), true, mb, c->stream);
         if (e != hipSuccess) return LBRS_E_HIP;
         ++c->launches;
     }

@@ -142,8 +142,8 @@ struct Pair2DArgs {
     int lam_mode;
     int bc[4];
     int last;             // last launch of a call: its result must not be tentative
-    double* tape0;        // taped form (two steps at most): U^n of the launch's first step and U^{n+1} of its
-    double* tape1;        // second ([4][ny][nx] each; a one-step launch writes tape0 only)
+    double* tape[KMAX_STEPS];  // taped form: U^{n+s} of the launch's step s+1 ([4][ny][nx]
+                               // each; a launch of k steps writes tape[0 .. k-1])
     long long plane;      // nx * ny
     PredCand* cand;       // candidate list (PRED_CAP entries) of the per-step prediction,
                           // or null: no prediction

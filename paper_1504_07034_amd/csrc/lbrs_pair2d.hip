@@ -743,10 +743,8 @@ __global__ __launch_bounds__(64 * WPB) void step2d_pair(Pair2DArgs a) {
     g.omega = a.omega;
     g.gamma = a.gamma;
     for (int s = 0; s < 4; ++s) g.bc[s] = a.bc[s];
-    g.tape[0] = a.tape0;
-    g.tape[1] = a.tape1;
 #pragma unroll
-    for (int i = 2; i < KMAX_STEPS; ++i) g.tape[i] = nullptr;
+    for (int i = 0; i < KMAX_STEPS; ++i) g.tape[i] = a.tape[i];
     g.tape_ps = a.plane;
     g.t0 = c.cand ? c.t0 : INFINITY;
     g.ph = &a.pst->pred[a.launch & 1];
@@ -1124,8 +1122,8 @@ static hipError_t launch_pair_wk(const Pair2DArgs& a, bool tape, int max_blocks,
         hipLaunchKernelGGL((step2d_pair<WPB, false, true, KM>), dim3(nblocks), dim3(64 * WPB), 0, s,
                            a);
     else if (tape)
-        hipLaunchKernelGGL((step2d_pair<WPB, true, false, 2>), dim3(nblocks), dim3(64 * WPB), 0, s,
-                           a);
+        hipLaunchKernelGGL((step2d_pair<WPB, true, false, KM>), dim3(nblocks), dim3(64 * WPB), 0,
+                           s, a);
     else
         hipLaunchKernelGGL((step2d_pair<WPB, false, false, KM>), dim3(nblocks), dim3(64 * WPB), 0,
                            s, a);
@@ -1135,7 +1133,7 @@ static hipError_t launch_pair_wk(const Pair2DArgs& a, bool tape, int max_blocks,
 // Launches of three or more steps run in workgroups of 8 waves at most.
 template <int WPB>
 static hipError_t launch_pair_w(const Pair2DArgs& a, bool tape, int max_blocks, hipStream_t s) {
-    if (tape || a.kmax <= 2) return launch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
+    if (a.kmax <= 2) return launch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
     if constexpr (WPB <= 8) {
         if (a.kmax == 3) return launch_pair_wk<WPB, 3>(a, tape, max_blocks, s);
         if (a.kmax == 4) return launch_pair_wk<WPB, 4>(a, tape, max_blocks, s);
@@ -1148,7 +1146,7 @@ static int occupancy(bool cand, bool tape) {
     int n = 0;
     hipError_t e;
     if (tape)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, true, false, 2>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, true, false, KM>,
                                                          64 * WPB, 0);
     else if (cand)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step2d_pair<WPB, false, true, KM>,
@@ -1161,10 +1159,10 @@ static int occupancy(bool cand, bool tape) {
 
 template <int WPB>
 static int pair_blocks_w(bool cand, int kmax, bool tape) {
-    if (tape || kmax <= 2) return occupancy<WPB, 2>(cand && !tape, tape);
+    if (kmax <= 2) return occupancy<WPB, 2>(cand && !tape, tape);
     if constexpr (WPB <= 8) {
-        if (kmax == 3) return occupancy<WPB, 3>(cand, false);
-        return occupancy<WPB, 4>(cand, false);
+        if (kmax == 3) return occupancy<WPB, 3>(cand && !tape, tape);
+        return occupancy<WPB, 4>(cand && !tape, tape);
     }
     return 1;
 }
