@@ -31,26 +31,29 @@ METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
 # (automatic row segments, row-interleaved layout), valid for the kernel code
 # they were taken on (profiles/step2d_d2q4_riemann4096.md); null once the code
 # changes or for a shape not profiled.
-TRAFFIC_BYTES = {"16,0": 4.433e9, "16,1": 4.396e9, "12,0": 4.418e9, "12,1": 4.392e9, "8,0": 4.486e9,
-                 "8,1": 4.382e9, "6,0": 4.517e9, "6,1": 4.407e9, "4,0": 4.538e9, "4,1": 4.481e9}
-TRAFFIC_SOURCE_HASH = "aeb4140bef7481ec"
+TRAFFIC_BYTES = {"16,0": 4.431e9}
+TRAFFIC_SOURCE_HASH = "905b216eb87675aa"
 SINGLE_SOURCES = ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 # The same for the fused multi-step kernel, by "steps_per_launch,waves_per_block":
-# the mean HBM bytes per launch over the timed launches of the benchmark window
-# (per-step lattice speeds: one launch per step, of which those past the steps
-# done exit at once), profiles/step2d_pair_riemann4096.md.
-PAIR_TRAFFIC_BYTES = {"2,8": 2.9920e9, "2,6": 2.9919e9, "2,4": 3.0305e9}
-PAIR_TRAFFIC_SOURCE_HASH = "2f5c1556053b413f"
+# HBM bytes per launch that does work (profiles/step2d_pair_riemann4096.md);
+# the window's figure is that times the share of the enqueued launches that
+# did work (per-step lattice speeds: one launch per step, of which those past
+# the steps done exit at once, moving nothing).
+PAIR_TRAFFIC_BYTES = {"4,8": 4.464e9, "2,8": 4.430e9}
+PAIR_TRAFFIC_SOURCE_HASH = "ee022fbdb436e8ee"
 PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 
 
-def traffic_bytes(shape, layout):
+def traffic_bytes(shape, layout, active_share=1.0):
+    """HBM bytes per enqueued launch of the timed form (fused: per launch that
+    did work, times the share of such launches), or None."""
     if shape["rows"] != 0 or layout != 1:
         return None
     if shape.get("fuse", 1) >= 2:
         if kernel_source_hash(PAIR_SOURCES) != PAIR_TRAFFIC_SOURCE_HASH:
             return None
-        return PAIR_TRAFFIC_BYTES.get(f"{shape['fuse']},{shape['wpb']}")
+        b = PAIR_TRAFFIC_BYTES.get(f"{shape['fuse']},{shape['wpb']}")
+        return None if b is None else round(b * active_share)
     if kernel_source_hash(SINGLE_SOURCES) != TRAFFIC_SOURCE_HASH:
         return None
     return TRAFFIC_BYTES.get(f"{shape['wpb']},{shape['alt']}")
@@ -1012,6 +1015,9 @@ def main():
                 active = lc["pairs"] + lc["rejected"] + lc["bound_only"] + lc["single"]
                 r["active_launches"] = active
                 r["avg_active_launch_ms"] = round(ms / max(active, 1), 5)
+                r["traffic"] = traffic_bytes(sh, args.layout, active / launches)
+            else:
+                r["traffic"] = None
         return r
 
     ms_win, done = timed_window(shape, args.steps, args.warmup)
