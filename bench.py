@@ -260,8 +260,12 @@ def sod_400():
             "MLUPS": round(400 * st["nsteps"] / ms / 1e3, 2)}
 
 
-def _time_ms(fn, reps=1):
+def _time_ms(fn, reps=1, warm=False):
+    """Milliseconds of fn (mean of reps), after one untimed call with warm
+    (first launches of a kernel load its code)."""
     import torch
+    if warm:
+        fn()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -289,27 +293,38 @@ def adjoint_2d(n=2048, steps=2000, k=50, steps_only=False):
     best = run.tune(rho0)
     sim = run.sim
     run.forward(rho0, keep=False)
-    fwd = _time_ms(lambda: sim.step(k)) / k
+    fwd = _time_ms(lambda: sim.step(k), warm=True) / k
     sim.set_fusion(1)
-    fwd1 = _time_ms(lambda: sim.step(k)) / k
+    fwd1 = _time_ms(lambda: sim.step(k), warm=True) / k
     sim.set_fusion(best["fuse"])
-    tape = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
-    tape1 = torch.empty_like(tape)
-    tap = _time_ms(lambda: [lbrs.lbrs_step_tape(sim.ctx, tape) for _ in range(k)]) / k
-    k2 = max(1, k // 2)
-    tap2 = _time_ms(lambda: [lbrs.lbrs_step_tape2(sim.ctx, tape, tape1)
-                             for _ in range(k2)]) / (2 * k2)
+    # the taped and adjoint steps in the tuned number per launch (what the
+    # gradient's recompute and reverse sweep use), in pairs and single
+    kf = best["fuse"]
+    tapes = torch.empty((kf, 4, n, n), dtype=torch.float64, device="cuda")
+    tape = tapes[0]
+    tap = _time_ms(lambda: [lbrs.lbrs_step_tape(sim.ctx, tape) for _ in range(k)], warm=True) / k
+    kk = max(1, k // kf)
+    tapk = _time_ms(lambda: [lbrs.lbrs_step_tapes(sim.ctx, kf, tapes)
+                             for _ in range(kk)], warm=True) / (kf * kk)
     g = torch.empty_like(run.fbar)
-    adj = _time_ms(lambda: [lbrs.lbrs_adjoint_step(sim.ctx, tape, run.fbar, g) for _ in range(k)]) / k
-    adj2 = _time_ms(lambda: [lbrs.lbrs_adjoint_step2(sim.ctx, tape, tape, run.fbar, g)
-                             for _ in range(k2)]) / (2 * k2)
-    if best["fuse"] == 1:
-        tap2, adj2 = tap, adj
+    adj = _time_ms(lambda: [lbrs.lbrs_adjoint_step(sim.ctx, tape, run.fbar, g) for _ in range(k)],
+                   warm=True) / k
+    adjk = _time_ms(lambda: [lbrs.lbrs_adjoint_steps(sim.ctx, kf, tapes, run.fbar, g)
+                             for _ in range(kk)], warm=True) / (kf * kk)
+    pair = None
+    if kf > 2:
+        k2 = max(1, k // 2)
+        pair = {"tape_step_ms": round(_time_ms(lambda: [lbrs.lbrs_step_tapes(sim.ctx, 2, tapes)
+                                                        for _ in range(k2)], warm=True)
+                                      / (2 * k2), 4),
+                "adjoint_step_ms": round(_time_ms(lambda: [
+                    lbrs.lbrs_adjoint_steps(sim.ctx, 2, tapes, run.fbar, g)
+                    for _ in range(k2)], warm=True) / (2 * k2), 4)}
     if steps_only:  # the per-step figures alone (profiling)
         run.close()
-        return {"n": n, "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap2, 4),
-                "adjoint_step_ms": round(adj2, 4), "single_forward_step_ms": round(fwd1, 4),
-                "steps_per_launch": best["fuse"], "waves_per_block": best["wpb"]}
+        return {"n": n, "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tapk, 4),
+                "adjoint_step_ms": round(adjk, 4), "single_forward_step_ms": round(fwd1, 4),
+                "steps_per_launch": kf, "waves_per_block": best["wpb"]}
     r = rho0.clone().requires_grad_(True)
 
     def grad():
@@ -321,7 +336,7 @@ def adjoint_2d(n=2048, steps=2000, k=50, steps_only=False):
     t_fwd = _time_ms(lambda: run.forward(rho0, keep=False))
     tile, fuse, seg = run.spec.tile, run.spec.fuse, run.spec.seg
     run.close()
-    del run, r, sim, tape, tape1, g
+    del run, r, sim, tape, tapes, g
     torch.cuda.empty_cache()
     # the same gradient with every step's moments kept (no checkpoints, no
     # recompute) when the tape fits in device memory
@@ -347,19 +362,19 @@ def adjoint_2d(n=2048, steps=2000, k=50, steps_only=False):
     cells = n * n
     return {"n": n, "steps": steps, "segment": seg,
             "tile_rows": best["rows"], "waves_per_block": best["wpb"], "alternate": best["alt"],
-            "steps_per_launch": best["fuse"],
+            "steps_per_launch": kf,
             # per step: forward, taped recompute and adjoint, in the tuned
             # (fused) form and as single steps
-            "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tap2, 4),
-            "adjoint_step_ms": round(adj2, 4),
-            "adjoint_over_forward": round((tap2 + adj2) / fwd, 3),
-            # the timed forms' own bytes per lattice update: fused adjoint
-            # 160 (fbar^{n+2} 128 + two tapes 64 + fbar^n 128 per two
-            # updates), single adjoint 288 (128 + 32 + 128)
-            "adjoint_step_bytes_per_lup": 160 if best["fuse"] >= 2 else 288,
-            "adjoint_step_GBs": round((160 if best["fuse"] >= 2 else 288) * cells /
-                                      (adj2 * 1e-3) / 1e9, 1),
-            "adjoint_step_single_equivalent_GBs": round(288 * cells / (adj2 * 1e-3) / 1e9, 1),
+            "forward_step_ms": round(fwd, 4), "tape_step_ms": round(tapk, 4),
+            "adjoint_step_ms": round(adjk, 4),
+            "adjoint_over_forward": round((tapk + adjk) / fwd, 3),
+            # the timed forms' own bytes per lattice update: k fused adjoint
+            # steps (256 + 32 k) / k (fbar^{n+k} 128 + k tapes 32 + fbar^n
+            # 128 per k updates), the single adjoint 288 (128 + 32 + 128)
+            "adjoint_step_bytes_per_lup": round((256 + 32 * kf) / kf, 2),
+            "adjoint_step_GBs": round((256 + 32 * kf) / kf * cells / (adjk * 1e-3) / 1e9, 1),
+            "adjoint_step_single_equivalent_GBs": round(288 * cells / (adjk * 1e-3) / 1e9, 1),
+            "two_per_launch": pair,
             "single": {"forward_step_ms": round(fwd1, 4), "tape_step_ms": round(tap, 4),
                        "adjoint_step_ms": round(adj, 4),
                        "adjoint_over_forward": round((tap + adj) / fwd1, 3),

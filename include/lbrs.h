@@ -286,6 +286,13 @@ int lbrs_step_tape(lbrs_ctx* c, double* d_Utape_n);
  * lbrs_step_tape; the tapes may not alias.  Asynchronous. */
 int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1);
 
+/* k taped forward steps (k = 1 .. 4) in one fused launch (as
+ * lbrs_set_fusion(c, k); k = 1 is lbrs_step_tape): slot s of d_Utape
+ * [k][K][ny][nx] receives U^{n+s}, the input moments of step s+1; equal to k
+ * lbrs_step_tape calls to rounding.  Same modes and errors as
+ * lbrs_step_tape, LBRS_E_INVAL for k outside 1 .. 4.  Asynchronous. */
+int lbrs_step_tapes(lbrs_ctx* c, int k, double* d_Utape);
+
 /* Adjoint (vector-Jacobian product) of one fixed-speed step, D2Q4 with
  * periodic sides: given fbar^{n+1} = dJ/df^{n+1} and the step's input moments
  * U^n, write fbar^n = dJ/df^n:
@@ -308,6 +315,18 @@ int lbrs_adjoint_step(lbrs_ctx* c, const double* d_Utape_n, const double* d_fbar
  * lbrs_backward_checkpointed uses it when lbrs_set_fusion(c, 2) is on. */
 int lbrs_adjoint_step2(lbrs_ctx* c, const double* d_Utape_n1, const double* d_Utape_n,
                        const double* d_fbar_next2, double* d_fbar);
+
+/* k adjoint steps (k = 1 .. 4) in one launch: fbar^n from fbar^{n+k}
+ * (d_fbar_next), with slot s of d_Utape [k][K][ny][nx] holding U^{n+s} (the
+ * layout lbrs_step_tapes writes); equal to lbrs_adjoint_step with slots k-1,
+ * k-2, .., 0 in turn, to rounding.  Each wavefront feeds every row it forms
+ * straight into the next step, so fbar^{n+k} is read and fbar^n written once
+ * per k steps.  Layouts, modes and errors as lbrs_adjoint_step, LBRS_E_INVAL
+ * for k outside 1 .. 4; d_fbar may not alias d_fbar_next.
+ * lbrs_backward_checkpointed and lbrs_backward_taped use it with k the
+ * context's fusion.  Asynchronous. */
+int lbrs_adjoint_steps(lbrs_ctx* c, int k, const double* d_Utape, const double* d_fbar_next,
+                       double* d_fbar);
 
 /* Adjoint of the initialisation f^0 = f^eq(U0): Ubar0 = sum_i (df_i^eq/dU)^T
  * fbar0_i at U0.  d_fbar0 [Q][K][ny][nx], d_U0 and d_Ubar0 [K][ny][nx].
@@ -406,7 +425,7 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * as 8 with k >= 3 or PER_STEP speeds; alternate is ignored).
  * lbrs_step_tape stays a single step; lbrs_backward_checkpointed recomputes
  * its segments k steps per launch when k > 1 (every step's input moments
- * taped) and runs its adjoint steps two per launch (lbrs_adjoint_step2).
+ * taped) and runs its adjoint steps k per launch (lbrs_adjoint_steps).
  * LBRS_E_INVAL for other values; LBRS_E_STATE with k > 1 for a 1D,
  * scalar-law, body or DIRICHLET context.  Takes effect for later calls. */
 int lbrs_set_fusion(lbrs_ctx* c, int steps_per_launch);

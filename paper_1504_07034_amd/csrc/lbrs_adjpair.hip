@@ -1,20 +1,21 @@
-// Two adjoint steps per launch (D2Q4, fixed lattice speed, periodic sides).
+// Two to four adjoint steps per launch (D2Q4, fixed lattice speed, periodic sides).
 //
 // One adjoint step (the vector-Jacobian product of one LBRS step, Sec. II.D
 // update with a fixed lattice speed) maps fbar^{n+1} to fbar^n:
 //   fbar*_i(x) = fbar^{n+1}_i(x + s_i)                       (reverse stream)
 //   Ubar(x)    = omega [ sum_i fbar*_i / 4 + (A1^T h_x + A2^T h_y)/(4 lambda) ] at U^n(x)
 //   fbar^n_i   = (1 - omega) fbar*_i + Ubar.
-// Here a wavefront marches rows of fbar^{n+2}, forms the rows of fbar^{n+1}
-// (with U^{n+1} from the tape) and feeds each one straight into the second
-// adjoint step (with U^n), so fbar^{n+2} is read and fbar^n written once per
-// two steps.  The reverse stream pulls populations 0 (-,-) and 1 (+,-) from
-// the row below and populations 2 (+,+) and 3 (-,+) from the row above, one
-// lane left or right: a row of the input completes the output row above it
-// (with the lower populations kept from two rows before), mirroring the
-// forward kernel's pipeline.  Lanes, strips (<= 60 columns, two halo lanes
-// on each side) and row segments (two halo rows) are those of the fused
-// forward kernel; sides are periodic, so every halo position wraps.
+// Here a wavefront marches rows of fbar^{n+K}, forms the rows of fbar^{n+K-1}
+// (with U^{n+K-1} from the tape) and feeds each one straight into the next
+// adjoint step, K times (the last with U^n), so fbar^{n+K} is read and fbar^n
+// written once per K steps.  The reverse stream pulls populations 0 (-,-)
+// and 1 (+,-) from the row below and populations 2 (+,+) and 3 (-,+) from the
+// row above, one lane left or right: a row of a step's input completes the
+// output row above it (with the lower populations kept from two rows
+// before), mirroring the forward kernel's pipeline.  Lanes, strips (<= 64-2K
+// columns, K halo lanes on each side) and row segments (K halo rows) are
+// those of the fused forward kernel; sides are periodic, so every halo
+// position wraps.
 #include "lbrs_launch.hpp"
 #include "lbrs_rowops.hpp"
 
@@ -56,113 +57,127 @@ __device__ inline void upper_pulls(const double v[16], double u[8]) {
     }
 }
 
-// One domain as the march sees it: fbar^{n+2} in, fbar^n out (population
-// offset p*ps + y*rs + x), the tapes U^{n+1} (Ua) and U^n (Ub), element
-// (k, y, x) at k*plane + y*nx + x.
+// One domain as the march sees it: fbar^{n+K} in, fbar^n out (population
+// offset p*ps + y*rs + x), the tapes tape[s] = U^{n+K-1-s} of step s
+// (element (k, y, x) at k*plane + y*nx + x).
 struct AdjGeom {
     const double* gn;
     double* g;
-    const double* Ua;
-    const double* Ub;
+    const double* tape[KMAX_STEPS];
     long long ps, rs, plane;
     int nx, ny, strip;
     double gamma, omega, lam;
 };
 
-template <int WPB>
-__device__ __forceinline__ void march_adjoint_pair(const AdjGeom& a, int strip, int y0, int y1,
-                                                   int lane) {
+// K adjoint steps of rows y0..y1-1 of one strip.  Lane l holds column
+// x0 - K + l; step s (0-based) takes row j = r - s of its input at row
+// iteration r and completes row j - 1 of its output, valid on lanes
+// s+1 .. 62-s; rows y0-K .. y1+K-1 of fbar^{n+K} are read and the pipelines
+// start as zeros, which only feed rows that are never used (as in the forward
+// march).  LPB: the second row of each step's pipeline lives in the wave's
+// LDS area pbl, element k of step s at pbl[(s*8 + k)*64 + lane] (each lane
+// its own elements, in program order: no barrier).
+template <int WPB, int K, bool LPB>
+__device__ __forceinline__ void march_adjoint_k(const AdjGeom& a, int strip, int y0, int y1,
+                                                int lane, double* pbl) {
+    static_assert(K >= 2 && K <= KMAX_STEPS, "adjoint steps per launch");
     const double lam = a.lam;
     const int nx = a.nx, ny = a.ny;
     const int row_bytes = nx * 8;
-    const int x = strip * a.strip - 2 + lane;
+    const int x = strip * a.strip - K + lane;
     const int xl = map_index(x, nx, true);
-    const bool out_lane = lane >= 2 && lane <= a.strip + 1 && x < nx;
+    const bool out_lane = lane >= K && lane <= a.strip + K - 1 && x < nx;
     const int voff = out_lane ? x * 8 : 0x7fffffff;
-    // rows [y0-1, y1] of fbar^{n+1}, from rows y0-2 .. y1+1 of fbar^{n+2}
-    const int a0 = y0 - 1, b0 = y1 + 1;
 
-    double f[16], nxt[16];
-    double PA0[8], PA1[8];  // first step: lower pulls of input rows r-1 and r-2
-    double PB0[8], PB1[8];  // second step: lower pulls of fbar^{n+1} rows q-1 and q-2
-    double tA[4], tB[4], nA[4], nB[4];
-    load16(f, a.gn, a.ps, a.rs, map_index(a0 - 1, ny, true), xl);
-    load16(nxt, a.gn, a.ps, a.rs, map_index(a0, ny, true), xl);
-    lower_pulls(f, PA0);
+    double P0[K][8];                // per step: lower pulls of its last input row
+    double P1[LPB ? 1 : K][8];      // and of the one before
+    double tc[K][4], tn[K][4];      // tape rows of this iteration and the next
 #pragma unroll
-    for (int p = 0; p < 16; ++p) f[p] = nxt[p];
-    // loads for the first iteration: its tape rows, then the next input row
-    load4(nA, a.Ua, a.plane, nx, map_index(a0, ny, true), xl);
-    load4(nB, a.Ub, a.plane, nx, map_index(a0 - 1, ny, true), xl);
-    load16(nxt, a.gn, a.ps, a.rs, map_index(a0 + 1, ny, true), xl);
+    for (int s = 0; s < K; ++s)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        PA1[k] = PA0[k];
-        PB0[k] = PB1[k] = 0.0;
-    }
-    lower_pulls(f, PA0);
+        for (int k = 0; k < 8; ++k) {
+            P0[s][k] = 0.0;
+            if (LPB) pbl[(s * 8 + k) * 64 + lane] = 0.0;
+            else P1[s][k] = 0.0;
+        }
+    double nxt[16];
+    const int r0 = y0 - K;
+    load16(nxt, a.gn, a.ps, a.rs, map_index(r0, ny, true), xl);
+#pragma unroll
+    for (int s = 0; s < K; ++s) load4(tn[s], a.tape[s], a.plane, nx, map_index(r0 - s - 1, ny, true), xl);
 
-    for (int r = a0 + 1; r <= b0; ++r) {
+    for (int r = r0; r <= y1 + K - 1; ++r) {
         // lockstep with the workgroup's neighbouring strips (equal trip counts)
         if (WPB > 1) __builtin_amdgcn_s_barrier();
+        double in[16];
 #pragma unroll
-        for (int p = 0; p < 16; ++p) f[p] = nxt[p];
+        for (int p = 0; p < 16; ++p) in[p] = nxt[p];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            tA[k] = nA[k];
-            tB[k] = nB[k];
-        }
-        // the next iteration's tape rows and input row, in flight meanwhile
-        load4(nA, a.Ua, a.plane, nx, map_index(r, ny, true), xl);
-        load4(nB, a.Ub, a.plane, nx, map_index(r - 1, ny, true), xl);
+        for (int s = 0; s < K; ++s)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tc[s][k] = tn[s][k];
+        // the next iteration's input row and tape rows, in flight meanwhile
         load16(nxt, a.gn, a.ps, a.rs, map_index(r + 1, ny, true), xl);
-
-        // first step: row o = r-1 of fbar^{n+1}
-        double fb[16], u[8];
-        upper_pulls(f, u);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            fb[k] = PA1[k];
-            fb[8 + k] = u[k];
-            PA1[k] = PA0[k];
+        for (int s = 0; s < K; ++s) load4(tn[s], a.tape[s], a.plane, nx, map_index(r - s, ny, true), xl);
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int o = r - s - 1;  // this step's output row
+            double fb[16], u[8], lo[8];
+            upper_pulls(in, u);
+            lower_pulls(in, lo);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (LPB) {
+                    double* e = pbl + (s * 8 + k) * 64 + lane;
+                    fb[k] = *e;
+                    *e = P0[s][k];
+                } else {
+                    fb[k] = P1[LPB ? 0 : s][k];
+                    P1[LPB ? 0 : s][k] = P0[s][k];
+                }
+                fb[8 + k] = u[k];
+                P0[s][k] = lo[k];
+            }
+            double g[16];
+            adjoint_cell_d2q4(fb, tc[s], a.gamma, a.omega, lam, g);
+            if (s == K - 1) {
+                // an output row of the tile; the store is unconditional (an
+                // out-of-range offset is dropped), so no wait covers it
+                const bool row_out = o >= y0 && o < y1;
+                double* orow = a.g + (long long)(row_out ? o : y0) * a.rs;
+                const int vo = row_out ? voff : 0x7fffffff;
+#pragma unroll
+                for (int p = 0; p < 16; ++p) store_row(orow + p * a.ps, row_bytes, vo, g[p]);
+            } else {
+#pragma unroll
+                for (int p = 0; p < 16; ++p) in[p] = g[p];
+            }
         }
-        lower_pulls(f, PA0);
-        double g1[16];
-        adjoint_cell_d2q4(fb, tA, a.gamma, a.omega, lam, g1);
-
-        // second step: row q = o of fbar^{n+1} completes row q-1 of fbar^n
-        const int q = r - 1;
-        upper_pulls(g1, u);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            fb[k] = PB1[k];
-            fb[8 + k] = u[k];
-            PB1[k] = PB0[k];
-        }
-        lower_pulls(g1, PB0);
-        double g2[16];
-        adjoint_cell_d2q4(fb, tB, a.gamma, a.omega, lam, g2);
-        // an output row once q > y0; the store is unconditional (an
-        // out-of-range offset is dropped), so no wait covers it
-        const bool row_out = q > y0;
-        double* orow = a.g + (long long)(row_out ? q - 1 : y0) * a.rs;
-        const int vo = row_out ? voff : 0x7fffffff;
-#pragma unroll
-        for (int p = 0; p < 16; ++p) store_row(orow + p * a.ps, row_bytes, vo, g2[p]);
     }
 }
 
+// Kernels of three or more steps keep the second row of their pipelines in
+// LDS (as the forward kernels).
+template <int K>
+struct AdjPipelineInLds {
+    static constexpr bool value = K >= 3;
+};
+
 }  // namespace
 
-template <int WPB>
-__global__ __launch_bounds__(64 * WPB) void adjoint_pair_d2q4(AdjPairArgs a) {
+template <int WPB, int K>
+__global__ __launch_bounds__(64 * WPB) void adjoint_k_d2q4(AdjPairArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr bool LPB = AdjPipelineInLds<K>::value;
+    __shared__ double pb_lds[LPB ? WPB * K * 8 * 64 : 1];
+    double* pbl = pb_lds + (LPB ? wave * K * 8 * 64 : 0);
     AdjGeom g;
     g.gn = a.gn;
     g.g = a.g;
-    g.Ua = a.Ua;
-    g.Ub = a.Ub;
+#pragma unroll
+    for (int i = 0; i < KMAX_STEPS; ++i) g.tape[i] = a.tape[i];
     g.ps = a.ps;
     g.rs = a.rs;
     g.plane = a.plane;
@@ -179,16 +194,20 @@ __global__ __launch_bounds__(64 * WPB) void adjoint_pair_d2q4(AdjPairArgs a) {
         const int seg = tile / a.nstrips;
         const int y0 = (int)(((long long)seg * a.ny) / a.nseg);
         const int y1 = (int)(((long long)(seg + 1) * a.ny) / a.nseg);
-        march_adjoint_pair<WPB>(g, strip, y0, y1, lane);
+        march_adjoint_k<WPB, K, LPB>(g, strip, y0, y1, lane, pbl);
     }
 }
 
 // The same for every domain of a 2D batch (periodic sides, fixed speeds),
-// over the fused launches' tile list (as the fused forward batch kernel).
-template <int WPB>
-__global__ __launch_bounds__(64 * WPB) void b2_adjoint_pair(Batch2DAdjPairArgs a) {
+// over the fused launches' tile list (as the fused forward batch kernel,
+// whose strips fit K steps).
+template <int WPB, int K>
+__global__ __launch_bounds__(64 * WPB) void b2_adjoint_k(Batch2DAdjPairArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr bool LPB = AdjPipelineInLds<K>::value;
+    __shared__ double pb_lds[LPB ? WPB * K * 8 * 64 : 1];
+    double* pbl = pb_lds + (LPB ? wave * K * 8 * 64 : 0);
     const long long total_waves = (long long)gridDim.x * WPB;
     for (long long tile = (long long)xcd_remap(blockIdx.x, gridDim.x) * WPB + wave;
          tile < a.pntiles; tile += total_waves) {
@@ -202,8 +221,8 @@ __global__ __launch_bounds__(64 * WPB) void b2_adjoint_pair(Batch2DAdjPairArgs a
         AdjGeom g;
         g.gn = a.gn + 16 * d.coff;
         g.g = a.g + 16 * d.coff;
-        g.Ua = a.Ua + d.coff;
-        g.Ub = a.Ub + d.coff;
+#pragma unroll
+        for (int i = 0; i < KMAX_STEPS; ++i) g.tape[i] = a.tape[i] ? a.tape[i] + d.coff : nullptr;
         g.ps = d.nx;
         g.rs = 16LL * d.nx;
         g.plane = a.total;
@@ -218,73 +237,114 @@ __global__ __launch_bounds__(64 * WPB) void b2_adjoint_pair(Batch2DAdjPairArgs a
         const int seg = local / d.pnstrips;
         const int y0 = (int)(((long long)seg * d.ny) / d.nseg);
         const int y1 = (int)(((long long)(seg + 1) * d.ny) / d.nseg);
-        march_adjoint_pair<WPB>(g, strip, y0, y1, lane);
+        march_adjoint_k<WPB, K, LPB>(g, strip, y0, y1, lane, pbl);
     }
 }
 
-template <int WPB>
-static hipError_t launch_adjpair_w(const AdjPairArgs& a, int max_blocks, hipStream_t s) {
+// Launches of three or more steps run in workgroups of 8 waves at most.
+template <int WPB, int K>
+static hipError_t launch_adj_wk(const AdjPairArgs& a, int max_blocks, hipStream_t s) {
     int nblocks = (a.ntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    hipLaunchKernelGGL((adjoint_pair_d2q4<WPB>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
+    hipLaunchKernelGGL((adjoint_k_d2q4<WPB, K>), dim3(nblocks), dim3(64 * WPB), 0, s, a);
     return hipGetLastError();
 }
 
 template <int WPB>
-static int adjpair_blocks_w() {
-    int n = 0;
-    hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_pair_d2q4<WPB>, 64 * WPB, 0);
-    return e == hipSuccess && n > 0 ? n : 1;
-}
-
-#define LBRS_ADJPAIR_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12)
-
-hipError_t launch_adjoint_pair(const AdjPairArgs& a, int wpb, int max_blocks, hipStream_t s) {
-#define LBRS_CASE(W) \
-    if (wpb == W) return launch_adjpair_w<W>(a, max_blocks, s);
-    LBRS_ADJPAIR_WPB_CASES(LBRS_CASE)
-#undef LBRS_CASE
+static hipError_t launch_adj_w(const AdjPairArgs& a, int max_blocks, hipStream_t s) {
+    if (a.k == 2) return launch_adj_wk<WPB, 2>(a, max_blocks, s);
+    if constexpr (WPB <= 8) {
+        if (a.k == 3) return launch_adj_wk<WPB, 3>(a, max_blocks, s);
+        if (a.k == 4) return launch_adj_wk<WPB, 4>(a, max_blocks, s);
+    }
     return hipErrorInvalidValue;
 }
 
+template <int WPB, int K>
+static int adj_occupancy() {
+    int n = 0;
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_k_d2q4<WPB, K>, 64 * WPB, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
 template <int WPB>
-static hipError_t launch_b2adjpair_w(const Batch2DAdjPairArgs& a, int max_blocks, hipStream_t s) {
+static int adj_blocks_w(int k) {
+    if (k == 2) return adj_occupancy<WPB, 2>();
+    if constexpr (WPB <= 8) {
+        if (k == 3) return adj_occupancy<WPB, 3>();
+        if (k == 4) return adj_occupancy<WPB, 4>();
+    }
+    return 1;
+}
+
+template <int WPB, int K>
+static hipError_t launch_b2adj_wk(const Batch2DAdjPairArgs& a, int max_blocks, hipStream_t s) {
     long long nblocks = (a.pntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
-    hipLaunchKernelGGL((b2_adjoint_pair<WPB>), dim3((unsigned)nblocks), dim3(64 * WPB), 0, s, a);
+    hipLaunchKernelGGL((b2_adjoint_k<WPB, K>), dim3((unsigned)nblocks), dim3(64 * WPB), 0, s, a);
     return hipGetLastError();
 }
 
 template <int WPB>
-static int b2adjpair_blocks_w() {
+static hipError_t launch_b2adj_w(const Batch2DAdjPairArgs& a, int max_blocks, hipStream_t s) {
+    if (a.k == 2) return launch_b2adj_wk<WPB, 2>(a, max_blocks, s);
+    if constexpr (WPB <= 8) {
+        if (a.k == 3) return launch_b2adj_wk<WPB, 3>(a, max_blocks, s);
+        if (a.k == 4) return launch_b2adj_wk<WPB, 4>(a, max_blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int WPB, int K>
+static int b2adj_occupancy() {
     int n = 0;
     hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, b2_adjoint_pair<WPB>, 64 * WPB, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, b2_adjoint_k<WPB, K>, 64 * WPB, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-hipError_t launch_b2_adjoint_pair(const Batch2DAdjPairArgs& a, int wpb, int max_blocks,
-                                  hipStream_t s) {
+template <int WPB>
+static int b2adj_blocks_w(int k) {
+    if (k == 2) return b2adj_occupancy<WPB, 2>();
+    if constexpr (WPB <= 8) {
+        if (k == 3) return b2adj_occupancy<WPB, 3>();
+        if (k == 4) return b2adj_occupancy<WPB, 4>();
+    }
+    return 1;
+}
+
+#define LBRS_ADJ_WPB_CASES(X) X(1) X(2) X(4) X(6) X(8) X(12)
+
+hipError_t launch_adjoint_k(const AdjPairArgs& a, int wpb, int max_blocks, hipStream_t s) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return launch_b2adjpair_w<W>(a, max_blocks, s);
-    LBRS_ADJPAIR_WPB_CASES(LBRS_CASE)
+    if (wpb == W) return launch_adj_w<W>(a, max_blocks, s);
+    LBRS_ADJ_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return hipErrorInvalidValue;
 }
 
-int b2_adjoint_pair_blocks_per_cu(int wpb) {
+int adjoint_k_blocks_per_cu(int wpb, int k) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return b2adjpair_blocks_w<W>();
-    LBRS_ADJPAIR_WPB_CASES(LBRS_CASE)
+    if (wpb == W) return adj_blocks_w<W>(k);
+    LBRS_ADJ_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return 1;
 }
 
-int adjoint_pair_blocks_per_cu(int wpb) {
+hipError_t launch_b2_adjoint_k(const Batch2DAdjPairArgs& a, int wpb, int max_blocks,
+                               hipStream_t s) {
 #define LBRS_CASE(W) \
-    if (wpb == W) return adjpair_blocks_w<W>();
-    LBRS_ADJPAIR_WPB_CASES(LBRS_CASE)
+    if (wpb == W) return launch_b2adj_w<W>(a, max_blocks, s);
+    LBRS_ADJ_WPB_CASES(LBRS_CASE)
+#undef LBRS_CASE
+    return hipErrorInvalidValue;
+}
+
+int b2_adjoint_k_blocks_per_cu(int wpb, int k) {
+#define LBRS_CASE(W) \
+    if (wpb == W) return b2adj_blocks_w<W>(k);
+    LBRS_ADJ_WPB_CASES(LBRS_CASE)
 #undef LBRS_CASE
     return 1;
 }

@@ -37,7 +37,7 @@ struct lbrs_ctx {
     int pbpc[3][KMAX_STEPS + 1][17];  // resident fused-kernel workgroups per CU, by (plain,
                                       // candidates, taped), steps per launch and waves per
                                       // block
-    int abpc[17];        // the same for the fused adjoint kernel
+    int abpc[KMAX_STEPS + 1][17];  // the same for the fused adjoint kernel, by steps
 };
 
 static CellArgs cell_args(const lbrs_ctx* c) {
@@ -347,8 +347,8 @@ static Step2DArgs step2d_args(const lbrs_ctx* c, double t_end, double* tape) {
     return a;
 }
 
-static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const double* gn,
-                        double* g);
+static int adjoint_k(lbrs_ctx* c, int k, const double* const* tapes, const double* gn,
+                     double* g);
 
 // Fused launches of up to k steps: strips of at most 64 - 2k columns (k halo
 // lanes on each side), segments of at least 4 rows.  Per-step speeds run
@@ -664,7 +664,24 @@ int lbrs_adjoint_step2(lbrs_ctx* c, const double* d_Utape_n1, const double* d_Ut
     if (c->P.law != LBRS_LAW_EULER || c->codes) return LBRS_E_STATE;
     for (int s = 0; s < 4; ++s)
         if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
-    return adjoint_pair(c, d_Utape_n1, d_Utape_n, d_fbar_next2, d_fbar);
+    const double* tapes[2] = {d_Utape_n1, d_Utape_n};
+    return adjoint_k(c, 2, tapes, d_fbar_next2, d_fbar);
+}
+
+int lbrs_adjoint_steps(lbrs_ctx* c, int k, const double* d_Utape, const double* d_fbar_next,
+                       double* d_fbar) {
+    if (!c || !d_Utape || !d_fbar_next || !d_fbar || d_fbar == d_fbar_next || k < 1 ||
+        k > KMAX_STEPS)
+        return LBRS_E_INVAL;
+    if (k == 1) return lbrs_adjoint_step(c, d_Utape, d_fbar_next, d_fbar);
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP || c->dim != 2) return LBRS_E_STATE;
+    if (c->P.law != LBRS_LAW_EULER || c->codes) return LBRS_E_STATE;
+    for (int s = 0; s < 4; ++s)
+        if (c->P.bc[s] != LBRS_BC_PERIODIC) return LBRS_E_STATE;
+    const long long ucount = (long long)c->K * c->plane;
+    const double* tapes[KMAX_STEPS];
+    for (int s = 0; s < k; ++s) tapes[s] = d_Utape + (long long)(k - 1 - s) * ucount;
+    return adjoint_k(c, k, tapes, d_fbar_next, d_fbar);
 }
 
 int lbrs_adjoint_init(lbrs_ctx* c, const double* d_fbar0, const double* d_U0, double* d_Ubar0) {
@@ -699,21 +716,24 @@ int lbrs_forward_checkpointed(lbrs_ctx* c, int nsteps, int segment, double* d_ck
     return LBRS_OK;
 }
 
-// Two adjoint steps in one launch: fbar^{n+2} -> fbar^n with U^{n+1} (Ua) and
-// U^n (Ub), in the fused launches' strips and automatic row segments.
-static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const double* gn,
-                        double* g) {
+// k adjoint steps in one launch (k = 2 .. KMAX_STEPS): fbar^{n+k} -> fbar^n
+// with tapes[s] = U^{n+k-1-s}, in strips of at most 64 - 2k columns and
+// automatic row segments.
+static int adjoint_k(lbrs_ctx* c, int k, const double* const* tapes, const double* gn,
+                     double* g) {
     AdjPairArgs a;
     a.plane = c->plane;
     a.ps = c->ps;
     a.rs = c->rs;
     a.nx = c->P.nx;
     a.ny = c->P.ny;
-    const int wpb = pair_wpb(c, false, 2);
-    a.nstrips = ((c->P.nx + 59) / 60 + wpb - 1) / wpb * wpb;
+    // workgroups of 8 waves at most (12-wave groups spill)
+    const int wpb = c->waves_per_block > 8 ? 8 : c->waves_per_block;
+    const int cols = 64 - 2 * k;
+    a.nstrips = ((c->P.nx + cols - 1) / cols + wpb - 1) / wpb * wpb;
     a.strip = (c->P.nx + a.nstrips - 1) / a.nstrips;
-    int& bpc = c->abpc[wpb];
-    if (bpc == 0) bpc = adjoint_pair_blocks_per_cu(wpb);
+    int& bpc = c->abpc[k][wpb];
+    if (bpc == 0) bpc = adjoint_k_blocks_per_cu(wpb, k);
     const int mb = c->cu_count * bpc;
     long long nseg = (long long)mb * wpb / a.nstrips;
     const long long cap = (c->P.ny + 3) / 4;
@@ -726,11 +746,11 @@ static int adjoint_pair(lbrs_ctx* c, const double* Ua, const double* Ub, const d
     a.gamma = c->P.gamma;
     a.omega = c->P.omega;
     a.st = c->st;
-    a.Ua = Ua;
-    a.Ub = Ub;
+    a.k = k;
+    for (int s = 0; s < KMAX_STEPS; ++s) a.tape[s] = s < k ? tapes[s] : nullptr;
     a.gn = gn;
     a.g = g;
-    return hip_status(launch_adjoint_pair(a, wpb, mb, c->stream));
+    return hip_status(launch_adjoint_k(a, wpb, mb, c->stream));
 }
 
 // The recompute of a segment in fused launches of up to k = fuse steps
@@ -784,6 +804,31 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
     return LBRS_OK;
 }
 
+int lbrs_step_tapes(lbrs_ctx* c, int k, double* d_Utape) {
+    if (!c || !d_Utape || k < 1 || k > KMAX_STEPS) return LBRS_E_INVAL;
+    if (k == 1) return lbrs_step_tape(c, d_Utape);
+    if (c->P.law != LBRS_LAW_EULER) return LBRS_E_STATE;
+    if (c->P.lambda_mode == LBRS_LAMBDA_PER_STEP) return LBRS_E_STATE;
+    if (c->dim != 2 || c->dir || c->codes) return LBRS_E_STATE;
+    // the set-up kernel and two launches: the k steps, then the one that
+    // checks them (a fallback after a non-physical intermediate state takes
+    // the steps up to it, into the same slots)
+    Pair2DArgs a = pair_args(c, INFINITY, true, k);
+    hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), k, c->stream);
+    if (e != hipSuccess) return LBRS_E_HIP;
+    const int mb = pair_max_blocks(c, true, k);
+    const long long ucount = (long long)c->K * c->plane;
+    for (int i = 0; i < KMAX_STEPS; ++i) a.tape[i] = d_Utape + (long long)(i < k ? i : k - 1) * ucount;
+    for (int j = 0; j < 2; ++j) {
+        a.launch = c->launches;
+        a.last = j == 1;
+        e = launch_step2d_pair(a, pair_wpb(c, true, k), true, mb, c->stream);
+        if (e != hipSuccess) return LBRS_E_HIP;
+        ++c->launches;
+    }
+    return LBRS_OK;
+}
+
 // Reverse adjoint steps over tape slots len-1 .. 0 (slot i = U^{n0+i}), from
 // fbar in cur; cur and nxt swap after every launch, so cur ends holding
 // fbar^{n0}.  Fused contexts take two steps per launch (tapes i and i-1).
@@ -791,12 +836,18 @@ static int reverse_sweep(lbrs_ctx* c, int len, const double* d_tape, double*& cu
     const long long ucount = (long long)c->K * c->plane;
     int i = len - 1;
     if (c->fuse >= 2) {
-        for (; i >= 1; i -= 2) {
-            int rc = adjoint_pair(c, d_tape + i * ucount, d_tape + (i - 1) * ucount, cur, nxt);
+        // launches of fuse steps (tapes i, i-1, ...), then one of the
+        // remaining steps (two or more)
+        while (i >= 1) {
+            const int k = i + 1 < c->fuse ? i + 1 : c->fuse;
+            const double* tapes[KMAX_STEPS];
+            for (int s = 0; s < k; ++s) tapes[s] = d_tape + (long long)(i - s) * ucount;
+            int rc = adjoint_k(c, k, tapes, cur, nxt);
             if (rc) return rc;
             double* t = cur;
             cur = nxt;
             nxt = t;
+            i -= k;
         }
     }
     for (; i >= 0; --i) {

@@ -212,7 +212,7 @@ struct lbrs_batch2d {
     int fuse;                 // time steps per forward launch (1, or 2 to KMAX_STEPS fused)
     long long pntiles;        // tiles of the fused launches
     int pmax_blocks[KMAX_STEPS + 1];  // resident workgroups of the k-step fused kernel
-    int amax_blocks;          // resident workgroups of the fused adjoint kernel
+    int amax_blocks[KMAX_STEPS + 1];  // resident workgroups of the k-step adjoint kernel
     hipGraph_t graph;
     hipGraphExec_t exec;
     const void* graph_args[7];  // arguments the captured gradient graph was built with
@@ -308,7 +308,8 @@ int lbrs_batch2d_init(lbrs_batch2d** out, int ndom, const lbrs_params* doms, con
     b->max_blocks = prop.multiProcessorCount * step2d_blocks_per_cu(b->wpb, true, false);
     for (int k = 2; k <= KMAX_STEPS; ++k)
         b->pmax_blocks[k] = prop.multiProcessorCount * step2d_batch_pair_blocks_per_cu(b->wpb, k);
-    b->amax_blocks = prop.multiProcessorCount * b2_adjoint_pair_blocks_per_cu(b->wpb);
+    for (int k = 2; k <= KMAX_STEPS; ++k)
+        b->amax_blocks[k] = prop.multiProcessorCount * b2_adjoint_k_blocks_per_cu(b->wpb, k);
     b->fuse = 1;
     b->doms.resize(ndom);
     long long off = 0, rows = 0, tiles = 0;
@@ -546,20 +547,21 @@ int lbrs_batch2d_window_objective(lbrs_batch2d* b, double* d_J, double* d_fbar) 
 
 // Whole gradient of J_d (each domain's window objective) with respect to U0:
 // reset from U0, forward with checkpoints every `segment` steps, objective,
-// Two adjoint steps of every domain (fused launch): fbar^{n+2} -> fbar^n with
-// U^{n+1} (Ua) and U^n (Ub).
-static int b2_adjoint_pair_step(lbrs_batch2d* b, const double* Ua, const double* Ub,
-                                const double* gn, double* g) {
+// k adjoint steps of every domain (fused launch, k <= the fusion the tile
+// list was planned for): fbar^{n+k} -> fbar^n with tapes[s] = U^{n+k-1-s}.
+static int b2_adjoint_k_step(lbrs_batch2d* b, int k, const double* const* tapes,
+                             const double* gn, double* g) {
     Batch2DAdjPairArgs a;
     a.doms = b->d_doms;
     a.ndom = b->ndom;
     a.pntiles = b->pntiles;
     a.total = b->total;
-    a.Ua = Ua;
-    a.Ub = Ub;
+    a.k = k;
+    for (int s = 0; s < KMAX_STEPS; ++s) a.tape[s] = s < k ? tapes[s] : nullptr;
     a.gn = gn;
     a.g = g;
-    return ok(launch_b2_adjoint_pair(a, b->wpb, b->amax_blocks, b->stream)) ? LBRS_OK : LBRS_E_HIP;
+    return ok(launch_b2_adjoint_k(a, b->wpb, b->amax_blocks[k], b->stream)) ? LBRS_OK
+                                                                            : LBRS_E_HIP;
 }
 
 // backward sweep (recompute each segment with a tape, reverse adjoint steps),
@@ -598,12 +600,17 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
     // adjoint steps back through tape slots len-1 .. 0 (cur and nxt swap)
     auto reverse_steps = [&](int len) -> int {
         int i = len - 1;
-        if (b->fuse >= 2) {  // two adjoint steps per launch: tapes i (U^{n+1}) and i-1 (U^n)
-            for (; i >= 1; i -= 2) {
-                int r = b2_adjoint_pair_step(b, d_tape + i * ucount, d_tape + (i - 1) * ucount,
-                                             cur, nxt);
+        if (b->fuse >= 2) {
+            // launches of fuse adjoint steps (tapes i, i-1, ...), then one of
+            // the remaining steps (two or more)
+            while (i >= 1) {
+                const int k = i + 1 < b->fuse ? i + 1 : b->fuse;
+                const double* tapes[KMAX_STEPS];
+                for (int s = 0; s < k; ++s) tapes[s] = d_tape + (long long)(i - s) * ucount;
+                int r = b2_adjoint_k_step(b, k, tapes, cur, nxt);
                 if (r) return r;
                 std::swap(cur, nxt);
+                i -= k;
             }
         }
         for (; i >= 0; --i) {

@@ -218,8 +218,9 @@ struct AdjArgs {
     const DevState* st;  // the fixed lattice speed is read from st->lam_fixed
 };
 
-// Two adjoint steps per launch (periodic D2Q4): fbar^n from fbar^{n+2}, with
-// U^{n+1} and U^n from the tape; tiles as in Pair2DArgs.
+// k adjoint steps per launch (periodic D2Q4): fbar^n from fbar^{n+k}, with
+// U^{n+k-1} .. U^n from the tape; tiles as in Pair2DArgs (strips of at most
+// 64 - 2k columns).
 struct AdjPairArgs {
     long long plane;
     long long ps, rs;       // population layout
@@ -227,9 +228,10 @@ struct AdjPairArgs {
     int strip, nstrips, nseg, ntiles;
     double gamma, omega;
     const DevState* st;     // the fixed lattice speed is read from st->lam_fixed
-    const double* Ua;       // U^{n+1} [4][ny][nx]
-    const double* Ub;       // U^n
-    const double* gn;       // fbar^{n+2}
+    int k;                  // adjoint steps of the launch (2 .. KMAX_STEPS)
+    const double* tape[KMAX_STEPS];  // tape[s] = U^{n+k-1-s} [4][ny][nx], the moments
+                                     // step s+1 is taken at
+    const double* gn;       // fbar^{n+k}
     double* g;              // fbar^n
 };
 
@@ -385,21 +387,21 @@ hipError_t launch_adjoint_step(const AdjArgs& a, const double* Un, const double*
                                hipStream_t s);
 hipError_t launch_adjoint_init(const AdjArgs& a, const double* fb0, const double* U0, double* Ub,
                                hipStream_t s);
-hipError_t launch_adjoint_pair(const AdjPairArgs& a, int wpb, int max_blocks, hipStream_t s);
-int adjoint_pair_blocks_per_cu(int wpb);
+hipError_t launch_adjoint_k(const AdjPairArgs& a, int wpb, int max_blocks, hipStream_t s);
+int adjoint_k_blocks_per_cu(int wpb, int k);
 // Two adjoint steps of every domain of a 2D batch (tiles of the fused launches).
 struct Batch2DAdjPairArgs {
     const Domain2D* doms;
     int ndom;
     long long pntiles;
     long long total;        // cells of all domains (plane of the tapes)
-    const double* Ua;       // U^{n+1} [4][total]
-    const double* Ub;       // U^n
-    const double* gn;       // fbar^{n+2}
+    int k;                  // adjoint steps of the launch (2 .. KMAX_STEPS)
+    const double* tape[KMAX_STEPS];  // tape[s] = U^{n+k-1-s} [4][total]
+    const double* gn;       // fbar^{n+k}
     double* g;              // fbar^n
 };
-hipError_t launch_b2_adjoint_pair(const Batch2DAdjPairArgs& a, int wpb, int max_blocks,
-                                  hipStream_t s);
-int b2_adjoint_pair_blocks_per_cu(int wpb);
+hipError_t launch_b2_adjoint_k(const Batch2DAdjPairArgs& a, int wpb, int max_blocks,
+                               hipStream_t s);
+int b2_adjoint_k_blocks_per_cu(int wpb, int k);
 
 }  // namespace lbrs

@@ -40,6 +40,7 @@ EXPORTS = (
     "lbrs_batch2d_get_state", "lbrs_batch2d_destroy", "lbrs_body_codes", "lbrs_strerror",
     "lbrs_destroy", "lbrs_set_fusion", "lbrs_batch2d_set_fusion", "lbrs_adjoint_step2",
     "lbrs_step_tape2", "lbrs_forward_taped", "lbrs_backward_taped", "lbrs_cfl_max",
+    "lbrs_step_tapes", "lbrs_adjoint_steps",
     "lbrs_run_noalloc", "lbrs_pair_stats",
 )
 
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH, require_gpu: bool = True):
         "lbrs_batch2d_set_fusion": (i, [vp, i]),
         "lbrs_adjoint_step2": (i, [vp, vp, vp, vp, vp]),
         "lbrs_step_tape2": (i, [vp, vp, vp]),
+        "lbrs_step_tapes": (i, [vp, i, vp]),
+        "lbrs_adjoint_steps": (i, [vp, i, vp, vp, vp]),
         "lbrs_forward_taped": (i, [vp, i, vp]),
         "lbrs_backward_taped": (i, [vp, i, vp, vp, vp]),
         "lbrs_batch_query": (i, [i, P, i, ctypes.POINTER(ll), szp]),
@@ -328,6 +331,15 @@ def lbrs_adjoint_step(ctx, Utape, fbar_next, fbar):
 
 def lbrs_step_tape2(ctx, Utape_n, Utape_n1):
     _check(load_library().lbrs_step_tape2(ctx, _dptr(Utape_n), _dptr(Utape_n1)), "lbrs_step_tape2")
+
+
+def lbrs_step_tapes(ctx, k, Utape):
+    _check(load_library().lbrs_step_tapes(ctx, int(k), _dptr(Utape)), "lbrs_step_tapes")
+
+
+def lbrs_adjoint_steps(ctx, k, Utape, fbar_next, fbar):
+    _check(load_library().lbrs_adjoint_steps(ctx, int(k), _dptr(Utape), _dptr(fbar_next),
+                                             _dptr(fbar)), "lbrs_adjoint_steps")
 
 
 def lbrs_adjoint_step2(ctx, Utape_n1, Utape_n, fbar_next2, fbar):

@@ -222,6 +222,56 @@ def test_adjoint_step2_equals_two_steps(layout, n):
     sim.close()
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("n", [48, 130])
+def test_adjoint_steps_equals_single_steps(layout, n, k):
+    """lbrs_adjoint_steps (k reverse steps per launch) against k calls of
+    lbrs_adjoint_step on the same tapes and random fbar, ragged strips and
+    segments included; tapes from lbrs_step_tapes against k taped single
+    steps."""
+    w = wl.fourier_modes(n, seed=5)
+    sim = lbrs.Sim(lbrs.LBRS_D2Q4, n, n, gamma=w.gamma, omega=1.3, cfl=w.cfl, bc=(1, 1, 1, 1),
+                   lambda_mode=lbrs.LBRS_LAMBDA_FROZEN_INIT, layout=layout)
+    sim.init_primitive(w.W)
+    f0 = sim.get_f()
+    st0 = sim.state()
+    tapes = torch.empty((k, 4, n, n), dtype=torch.float64, device="cuda")
+    for s in range(k):
+        lbrs.lbrs_step_tape(sim.ctx, tapes[s])
+    f_single = sim.get_f()
+    # the same k taped steps in one fused launch
+    sim.set_f(f0, st0["t"], st0["nsteps"])
+    tk = torch.full_like(tapes, float("nan"))
+    lbrs.lbrs_step_tapes(sim.ctx, k, tk)
+    dt = float((tk - tapes).abs().max())
+    df = float((sim.get_f() - f_single).abs().max())
+    report("step tapes", k=k, n=n, layout=layout, tape_diff=dt, f_diff=df)
+    assert sim.state()["nsteps"] == k
+    assert dt <= 1e-12 * float(tapes.abs().max()) and df <= 1e-12 * float(f_single.abs().max())
+    rng = np.random.default_rng(4 + k)
+    g = torch.from_numpy(rng.standard_normal(16 * n * n)).cuda()
+    ref = g.clone()
+    nxt = torch.empty_like(g)
+    for s in reversed(range(k)):
+        lbrs.lbrs_adjoint_step(sim.ctx, tapes[s], ref, nxt)
+        ref, nxt = nxt, ref
+    h0 = torch.empty_like(g)
+    for tile in [(0, 4), (0, 8), (3, 2), (0, 1)]:
+        sim.set_tile(*tile)
+        h0.fill_(float("nan"))
+        lbrs.lbrs_adjoint_steps(sim.ctx, k, tapes, g, h0)
+        diff = float((h0 - ref).abs().max())
+        report("adjoint steps", k=k, n=n, layout=layout, tile=tile, max_abs=diff,
+               bitwise=bool(torch.equal(h0, ref)))
+        assert diff <= 1e-12 * float(ref.abs().max())
+    with pytest.raises(lbrs.LBRSError):
+        lbrs.lbrs_adjoint_steps(sim.ctx, k, tapes, g, g)
+    with pytest.raises(lbrs.LBRSError):
+        lbrs.lbrs_adjoint_steps(sim.ctx, 5, tapes, g, h0)
+    sim.close()
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("n", [70, 130])
 def test_step_tape2_equals_two_taped_steps(layout, n):
