@@ -50,7 +50,8 @@ class GradientSpec:
     omega: float = 1.0
     cfl: float = 0.5
     layout: int = lbrs.LBRS_LAYOUT_ROWS
-    segment: int | None = None  # checkpoint spacing; default ceil(sqrt(T))
+    segment: int | None = None  # checkpoint spacing; default ceil(sqrt(T)), rounded up to a
+                                # multiple of the steps per launch
     lam: float | None = None    # frozen lattice speed; set by prepare()
     tile: tuple | None = None   # (rows_per_tile, waves_per_block, alternate) of the step kernel
     fuse: int = 1               # steps per launch of the plain forward steps (1 to 4)
@@ -62,7 +63,10 @@ class GradientSpec:
 
     @property
     def seg(self) -> int:
-        return self.segment or max(1, math.ceil(math.sqrt(self.steps)))
+        if self.segment:
+            return self.segment
+        f = max(1, self.fuse)
+        return min(self.steps, math.ceil(math.ceil(math.sqrt(self.steps)) / f) * f)
 
 
 class GradientRunner:
@@ -108,15 +112,26 @@ class GradientRunner:
                     raise
                 self.store_all = False  # automatic choice: fall back to checkpoints
                 torch.cuda.empty_cache()
+        self._seg = None
         if not self.store_all:
-            nck = math.ceil(spec.steps / spec.seg)
-            self.ckpt = torch.empty(nck * fcount, dtype=torch.float64, device=dev)
-            self.tape = torch.empty(spec.seg * 4 * n * n, dtype=torch.float64, device=dev)
+            self._alloc_segments()
         self.fbar = torch.empty(fcount, dtype=torch.float64, device=dev)
         self.work = torch.empty(fcount, dtype=torch.float64, device=dev)
         self.U0 = torch.empty((4, n, n), dtype=torch.float64, device=dev)
         self.J = torch.zeros(1, dtype=torch.float64, device=dev)
         self.win = window_range(n, *spec.window)
+
+    def _alloc_segments(self):
+        """Checkpoints and the segment tape for the spec's segment length."""
+        spec, n = self.spec, self.spec.n
+        if self._seg == spec.seg:
+            return
+        dev = self.sim.device
+        self.ckpt = self.tape = None
+        nck = math.ceil(spec.steps / spec.seg)
+        self.ckpt = torch.empty(nck * 16 * n * n, dtype=torch.float64, device=dev)
+        self.tape = torch.empty(spec.seg * 4 * n * n, dtype=torch.float64, device=dev)
+        self._seg = spec.seg
 
     def forward(self, rho0: torch.Tensor, keep: bool = True) -> torch.Tensor:
         s, sim = self.spec, self.sim
@@ -154,6 +169,8 @@ class GradientRunner:
         best = autotune.tune(self.sim, steps=steps, use_cache=False)
         self.spec.tile = (best["rows"], best["wpb"], best["alt"])
         self.spec.fuse = best["fuse"]
+        if not self.store_all:
+            self._alloc_segments()  # the default segment follows the steps per launch
         return best
 
     def close(self):
