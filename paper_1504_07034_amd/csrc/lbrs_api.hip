@@ -831,7 +831,8 @@ int lbrs_step_tapes(lbrs_ctx* c, int k, double* d_Utape) {
 
 // Reverse adjoint steps over tape slots len-1 .. 0 (slot i = U^{n0+i}), from
 // fbar in cur; cur and nxt swap after every launch, so cur ends holding
-// fbar^{n0}.  Fused contexts take two steps per launch (tapes i and i-1).
+// fbar^{n0}.  Fused contexts take up to k = fuse steps per launch (tapes i,
+// i-1, .., i-k+1).
 static int reverse_sweep(lbrs_ctx* c, int len, const double* d_tape, double*& cur, double*& nxt) {
     const long long ucount = (long long)c->K * c->plane;
     int i = len - 1;

@@ -408,7 +408,7 @@ int lbrs_batch2d_set_fusion(lbrs_batch2d* b, int steps_per_launch) {
     if (!b || steps_per_launch < 1 || steps_per_launch > KMAX_STEPS) return LBRS_E_INVAL;
     if (steps_per_launch != b->fuse) {
         // the fused launches' strips for this many steps (every fused
-        // kernel, the taped and adjoint pairs too, walks this tile list),
+        // kernel, the taped and adjoint ones too, walks this tile list),
         // into the device table (whose lattice speeds the device computed)
         const size_t bytes = sizeof(Domain2D) * b->ndom;
         if (!ok(hipStreamSynchronize(b->stream)) ||

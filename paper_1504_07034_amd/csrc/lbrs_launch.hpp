@@ -106,7 +106,7 @@ enum : int {
     PST_PRED_HIT,         // predicted guesses that stood
     PST_PRED_MISS,        // predicted guesses rolled back
     PST_EVALUATED,        // cells whose bound the prediction kernel evaluated
-    PST_PRED_NONE,        // pairs with candidates but no prediction (overflow, none)
+    PST_PRED_NONE,        // launches with candidates but no prediction (overflow, none)
     PST_LISTED,           // candidates the launches listed
     PST_OVERFLOW,         // launches whose candidates overflowed the list
     PST_STEPS3,           // of PST_PAIRS: three-step launches

@@ -1,43 +1,45 @@
-// Two fused LBRS steps per launch for the 2D Euler equations (D2Q4, gfx950).
+// Fused LBRS launches of up to four steps for the 2D Euler equations (D2Q4,
+// gfx950).
 //
 // The single-step kernel reads f^n and writes f^{n+1} once per step: 256 B of
 // HBM traffic per cell and step, which bounds it.  Here a wavefront feeds
-// every row of f^{n+1} it has just streamed straight into a second collision
-// and streaming, so f^n is read once and f^{n+2} written once: 128 B per cell
-// and step.  Both steps are the scheme of Sec. II.D unchanged (moments, the
-// folded equilibria, relaxation, exact diagonal hops, Sec. II.E walls,
-// transmissive and periodic sides); nothing but the order of the work differs.
+// every row of f^{n+1} it has just streamed straight into the next collision
+// and streaming, k times, so f^n is read once and f^{n+k} written once: 256/k
+// B per cell and step.  Every step is the scheme of Sec. II.D unchanged
+// (moments, the folded equilibria, relaxation, exact diagonal hops, Sec. II.E
+// walls, transmissive and periodic sides); nothing but the order of the work
+// differs.
 //
-// Lanes and rows.  Lane l holds column x0 - 2 + l.  The first step is valid
-// on lanes 1..62, the second on lanes 2..61, so a strip has <= 60 output
-// columns.  A tile's first step computes rows y0-1 .. y1 of f^{n+1} (one halo
-// row on each side, from f^n rows y0-2 .. y1+1), the second rows y0 .. y1-1 of
-// f^{n+2}.  Register pipelines: the upward hops of the last two rows of each
-// step, and the next row of f^n in flight.  At a clamped (transmissive or
-// wall) side the second step must pull from the edge cell of f^{n+1} itself,
-// not from a ghost row or column that the first step would make up: there
-// the edge column's values are copied into the halo lane, and at a clamped
-// bottom or top the edge row's hops are reused (selects, no extra rows).
+// Lanes and rows.  Lane l holds column x0 - k + l; step s (0-based) is valid
+// on lanes s+1 .. 62-s, so a strip has <= 64 - 2k output columns.  A tile
+// reads rows y0-k .. y1+k-1 of f^n; step s completes rows from y0-k+1+s on,
+// the last step rows y0 .. y1-1 of f^{n+k}.  Pipelines: the upward hops of
+// the last two rows of each step (the older one in LDS for three or more
+// steps), and the next row of f^n in flight.  Between steps every
+// intermediate state obeys the side rules: beyond a clamped (transmissive or
+// wall) side the next step pulls from the edge cell of that state itself
+// (the edge column's values copied into the halo lane, the edge row's hops
+// reused), in every strip and segment whose lanes or rows reach the side.
 //
-// Lattice speed of the second step.  With a fixed speed it is known.  With
-// the per-step speed it is the global bound over f^{n+1}, which no workgroup
-// has before the launch ends.  The launch then takes lambda*_{n+1} equal to
-// lambda*_n, reduces the true bound of its f^{n+1} on the side, and leaves
-// its result tentative.  The next launch checks the guess: equal bit for bit
-// (and the first step admissible) means the two steps are exactly those of
-// two single steps, and it continues from f^{n+2}; otherwise f^n, still
-// intact in the other buffer, is current again, and that launch repeats the
-// pair with the now known lambda*_{n+1} (or one step when the first step was
-// non-physical).  Where the bound keeps changing, guessing wastes a pass per
-// two steps; a saturating count of how often the checked bound repeated
-// (0..3, one up for a repeat, one down for a change) decides: at 0 a launch
-// first reduces the bound of f^{n+1} alone (reading f^n, storing nothing) and
-// the next launch takes the two steps with it; above 0 it guesses.  Every
-// workgroup of a launch takes the same decisions from the same slots, so no
-// grid barrier is needed.  The last launch of a call never leaves a
-// tentative result, so every other call sees an ordinary time state.
+// Lattice speeds of the later steps.  With a fixed speed they are known.
+// With the per-step speed each is the global bound over the state before it,
+// which no workgroup has before the launch ends.  The launch then guesses
+// them (the predictions the launch before left, else the current bound while
+// it keeps repeating), reduces the true bound of every intermediate state on
+// the side, and leaves its result tentative.  The next launch checks every
+// guess: all equal bit for bit (and the states admissible) means the k steps
+// are exactly those of k single steps, and it continues from f^{n+k};
+// otherwise f^n, still intact in the other buffer, is current again, and
+// that launch redoes the steps with the bounds now known (up to the first
+// wrong guess; up to a non-physical state).  Where nothing can be guessed a
+// launch first reduces the bound of f^{n+1} alone.  Every workgroup of a
+// launch takes the same decisions from the same slots, so no grid barrier is
+// needed.  The last launch of a call never leaves a tentative result, so
+// every other call sees an ordinary time state.  The predictions: after each
+// launch, one small kernel per predicted step evaluates the exact bound of
+// the next states on patches around the cells where the bound peaks.
 //
-// Also here: the taped form (U^n and U^{n+1} stored for the gradients'
+// Also here: the taped form (U of every step's input for the gradients'
 // recompute) and the 2D batch's form over all domains (fixed speeds).
 #include "lbrs_launch.hpp"
 #include "lbrs_rowops.hpp"
