@@ -454,7 +454,9 @@ def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None, fuse=4):
     from paper_1504_07034_amd import workloads as wl
 
     ws = ws or wl.domain_batch(128, seed=0, steps=steps)
-    seg = max(1, round(2 * math.sqrt(steps)))  # minimises 128*ceil(T/s) + 32*s bytes per cell
+    # near the minimum of 128*ceil(T/s) + 32*s bytes per cell (s = 2 sqrt(T)),
+    # a multiple of the steps per launch
+    seg = max(fuse, round(2 * math.sqrt(steps) / fuse) * fuse)
     nck = math.ceil(steps / seg)
     per_cell = 8 * (16 * (nck + 4) + 4 * (seg + 2))  # ckpt, f0 f1 fbar work, tape, U0 Ubar0
 
@@ -586,7 +588,7 @@ def batched_grad_2d(steps=1000, subset=16, mem_frac=0.6, ws=None, fuse=4):
     rel = float(np.max(np.abs(np.asarray(J_s) - J_b) / np.abs(np.asarray(J_s))))
     lups = total_cells * steps
     return {"domains": len(ws), "cells": int(total_cells), "steps": steps, "segment": seg,
-            "forward_steps_per_launch": fuse, "waves": wave_info, "ms": round(total_ms, 1),
+            "steps_per_launch": fuse, "waves": wave_info, "ms": round(total_ms, 1),
             "forward_equiv_MLUPS": round(lups / total_ms / 1e3, 1),
             "whole_tape": {"ms": round(ms_w, 1), "waves": len(info_w),
                            "bytes_per_cell": per_cell_w,

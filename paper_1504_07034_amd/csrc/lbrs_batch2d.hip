@@ -399,7 +399,7 @@ static Batch2DArgs b2_args(const lbrs_batch2d* b, double* tape) {
     a.f1 = b->f1;
     a.cur = b->cur;
     a.tape = tape;
-    a.tape2 = nullptr;
+    for (int i = 0; i < KMAX_STEPS; ++i) a.ktape[i] = nullptr;
     a.status = b->d_status;
     return a;
 }
@@ -580,15 +580,19 @@ static int b2_gradient_enqueue(lbrs_batch2d* b, const double* d_U0, int nsteps, 
     // len steps from the current state, U^{n+i} to tape slot i
     auto taped_steps = [&](int len) -> int {
         int i = 0;
-        if (b->fuse >= 2) {  // two steps per launch, both inputs taped
-            for (; i + 1 < len; i += 2) {
-                Batch2DArgs a = b2_args(b, d_tape + i * ucount);
-                a.tape2 = d_tape + (i + 1) * ucount;
-                if (!ok(launch_step2d_batch_pair(a, b->wpb, true, 2, b->pmax_blocks[2],
+        if (b->fuse >= 2) {
+            // launches of fuse steps, every step's input taped, then one of
+            // the remaining steps (two or more)
+            while (i + 1 < len) {
+                const int k = len - i < b->fuse ? len - i : b->fuse;
+                Batch2DArgs a = b2_args(b, nullptr);
+                for (int s = 0; s < k; ++s) a.ktape[s] = d_tape + (long long)(i + s) * ucount;
+                if (!ok(launch_step2d_batch_pair(a, b->wpb, true, k, b->pmax_blocks[k],
                                                  b->stream)))
                     return LBRS_E_HIP;
                 b->cur ^= 1;
-                b->nsteps += 2;
+                b->nsteps += k;
+                i += k;
             }
         }
         for (; i < len; ++i) {

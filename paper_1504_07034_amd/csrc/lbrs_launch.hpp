@@ -321,7 +321,7 @@ struct Batch2DArgs {
     double* f1;
     int cur;               // buffer holding f^n (host parity)
     double* tape;          // [4][total] or null
-    double* tape2;         // fused taped launches: U^{n+1} ([4][total])
+    double* ktape[KMAX_STEPS];  // fused taped launches: U^{n+s} of step s+1 ([4][total])
     unsigned* status;      // per domain
 };
 

@@ -997,11 +997,10 @@ __global__ __launch_bounds__(64) void pair_predict_kernel(Pair2DArgs a, int leve
 // tile list, numbered domain by domain (each domain's strip count a multiple
 // of the waves per workgroup, so a workgroup's waves share a domain and a
 // row segment; strips of at most 64 - 2K columns); a non-physical state
-// after any of the K steps sets the domain's status.  The taped form takes
-// two steps.
+// after any of the K steps sets the domain's status.  TAPE: U of every
+// step's input to a.ktape[s].
 template <int WPB, bool TAPE, int K>
 __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
-    static_assert(!TAPE || K == 2, "the taped form takes two steps");
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long total_waves = (long long)gridDim.x * WPB;
@@ -1031,10 +1030,9 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
         g.omega = d.omega;
         g.gamma = d.gamma;
         for (int s = 0; s < 4; ++s) g.bc[s] = d.bc[s];
-        g.tape[0] = TAPE ? a.tape + d.coff : nullptr;
-        g.tape[1] = TAPE ? a.tape2 + d.coff : nullptr;
 #pragma unroll
-        for (int i = 2; i < KMAX_STEPS; ++i) g.tape[i] = nullptr;
+        for (int i = 0; i < KMAX_STEPS; ++i)
+            g.tape[i] = TAPE && i < K ? a.ktape[i] + d.coff : nullptr;
         g.tape_ps = a.total;
         const int local = (int)(tile - d.ptile0);
         const int strip = local % d.pnstrips;
@@ -1194,7 +1192,7 @@ static hipError_t launch_batch_pair_wk(const Batch2DArgs& a, bool tape, int max_
     long long nblocks = (a.pntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
     if (tape)
-        hipLaunchKernelGGL((step2d_batch_pair<WPB, true, 2>), dim3((unsigned)nblocks),
+        hipLaunchKernelGGL((step2d_batch_pair<WPB, true, K>), dim3((unsigned)nblocks),
                            dim3(64 * WPB), 0, s, a);
     else
         hipLaunchKernelGGL((step2d_batch_pair<WPB, false, K>), dim3((unsigned)nblocks),
@@ -1206,10 +1204,10 @@ static hipError_t launch_batch_pair_wk(const Batch2DArgs& a, bool tape, int max_
 template <int WPB>
 static hipError_t launch_batch_pair_w(const Batch2DArgs& a, bool tape, int k, int max_blocks,
                                       hipStream_t s) {
-    if (tape || k == 2) return launch_batch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
+    if (k == 2) return launch_batch_pair_wk<WPB, 2>(a, tape, max_blocks, s);
     if constexpr (WPB <= 8) {
-        if (k == 3) return launch_batch_pair_wk<WPB, 3>(a, false, max_blocks, s);
-        if (k == 4) return launch_batch_pair_wk<WPB, 4>(a, false, max_blocks, s);
+        if (k == 3) return launch_batch_pair_wk<WPB, 3>(a, tape, max_blocks, s);
+        if (k == 4) return launch_batch_pair_wk<WPB, 4>(a, tape, max_blocks, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1222,17 +1220,20 @@ static int batch_occupancy() {
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-// Resident workgroups per CU of the k-step form (k = 2: the plain and the
-// taped form, whichever fits fewer).
+// Resident workgroups per CU of the k-step forms (the plain and the taped
+// one, whichever fits fewer).
+template <int WPB, int K>
+static int batch_pair_blocks_k() {
+    const int n = batch_occupancy<WPB, false, K>(), m = batch_occupancy<WPB, true, K>();
+    return n < m ? n : m;
+}
+
 template <int WPB>
 static int batch_pair_blocks_w(int k) {
-    if (k == 2) {
-        const int n = batch_occupancy<WPB, false, 2>(), m = batch_occupancy<WPB, true, 2>();
-        return n < m ? n : m;
-    }
+    if (k == 2) return batch_pair_blocks_k<WPB, 2>();
     if constexpr (WPB <= 8) {
-        if (k == 3) return batch_occupancy<WPB, false, 3>();
-        if (k == 4) return batch_occupancy<WPB, false, 4>();
+        if (k == 3) return batch_pair_blocks_k<WPB, 3>();
+        if (k == 4) return batch_pair_blocks_k<WPB, 4>();
     }
     return 1;
 }
