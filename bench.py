@@ -40,7 +40,7 @@ SINGLE_SOURCES = ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 # did work (per-step lattice speeds: one launch per step, of which those past
 # the steps done exit at once, moving nothing).
 PAIR_TRAFFIC_BYTES = {"4,8": 4.464e9, "2,8": 4.430e9}
-PAIR_TRAFFIC_SOURCE_HASH = "ee022fbdb436e8ee"
+PAIR_TRAFFIC_SOURCE_HASH = "ef6ba20669c149e0"
 PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 
 
