@@ -955,7 +955,8 @@ def main():
     st = sim.state()
     assert st["rc"] == 0 and st["nsteps"] == mid, st
     f_mid, t_mid = sim.get_f(), st["t"]
-    print(f"bench: whole run {n_total} steps; window from step {mid} (t = {t_mid:.5f})",
+    whole = f" ({first['ms_per_step']} ms/step, {first['MLUPS']} MLUPS)" if first else ""
+    print(f"bench: whole run {n_total} steps{whole}; window from step {mid} (t = {t_mid:.5f})",
           file=sys.stderr, flush=True)
 
     if args.rows < 0:  # autotune the launch shape from the window's start (untimed)
@@ -1004,8 +1005,9 @@ def main():
         """The kernel's own algorithmic bytes: 256 B per lattice update for a
         single step (16 FP64 populations in, 16 out), 256/k B for k fused
         steps (f^n in and f^{n+k} out per k updates: the states between never
-        leave the registers); per launch: the launches the window enqueued (a
-        call of K steps enqueues K launches of the step kernel either way)."""
+        leave the registers); per launch: the step-kernel launches the window
+        enqueued (a call of K single steps enqueues K; a fused call counts its
+        own, those that found the work done included)."""
         bpl = BYTES_PER_LUP / sh["fuse"]
         cells = n * n
         alg = bpl * cells * done
@@ -1032,6 +1034,10 @@ def main():
                 active = lc["pairs"] + lc["rejected"] + lc["bound_only"] + lc["single"]
                 r["active_launches"] = active
                 r["avg_active_launch_ms"] = round(ms / max(active, 1), 5)
+                launches = max(lc["enqueued"], 1)
+                r["launches"] = launches
+                r["avg_launch_ms"] = round(ms / launches, 5)
+                r["alg_bytes_per_launch"] = round(alg / launches)
                 r["traffic"] = traffic_bytes(sh, args.layout, active / launches)
             else:
                 r["traffic"] = None

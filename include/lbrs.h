@@ -226,7 +226,9 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
  * (PER_STEP mode clips the last dt).  With lbrs_set_fusion(c, k), k = 2 to 4
  * (2D Euler), the steps run up to k per launch with the same results (see
  * there).
- * Asynchronous. */
+ * Asynchronous, except with fused launches and PER_STEP speeds on a stream
+ * that is not being captured: the call then waits for the stream (see
+ * lbrs_set_fusion). */
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
 
 /* Wait for the stream and report the current time, completed step count,
@@ -239,7 +241,7 @@ int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda,
                    unsigned* status, long long* fail_step);
 
 /* Counters of the fused launches since lbrs_init (lbrs_set_fusion(c, k > 1)),
- * into counts[0 .. n-1] (n <= 13; missing ones 0): [0] launches of two or
+ * into counts[0 .. n-1] (n <= 14; missing ones 0): [0] launches of two or
  * more steps whose result stood, [1] such launches rolled back (a guessed
  * bound that was wrong), [2] launches that only reduced the bound of f^{n+1},
  * [3] one-step launches, [4] predictions of the next launch's bounds made,
@@ -248,7 +250,9 @@ int lbrs_get_state(lbrs_ctx* c, double* t, long long* nsteps, double* lambda,
  * candidates but left no prediction (too many, none, or a non-physical
  * state), [9] candidates listed, [10] launches whose candidates overflowed
  * the list, [11] of [0], the three-step ones, [12] of [0], the four-step
- * ones (so the steps taken are 2 [0] + [11] + 2 [12] + [3]).  With per-step
+ * ones (so the steps taken are 2 [0] + [11] + 2 [12] + [3]), [13] fused
+ * step launches enqueued (counted on the host; those that found the work
+ * done and exited at once included).  With per-step
  * lattice speeds a fused launch guesses the bounds of the states after its
  * first steps (the predictions when the launch before left them, else the
  * current bound while it keeps repeating) and the next launch checks every
@@ -417,9 +421,16 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * count, every lattice speed, the status, fail_step, the reported state after
  * each lbrs_step call and the populations are those of single steps, bit for
  * bit.  lbrs_step(c, max_steps, t_end) then enqueues a one-thread set-up
- * kernel and up to max_steps launches (with a fixed speed max_steps/k + 1),
- * of which the ones beyond the work done exit at once; with PER_STEP speeds
- * each launch is followed by the prediction kernel (one cooperative launch).
+ * kernel and, with a fixed speed, (max_steps - 2)/k + 2 launches; with
+ * PER_STEP speeds each launch is followed by the prediction kernels (one per
+ * guessed step), and a launch whose guess was wrong does no step, so the
+ * call enqueues rounds of about max_steps/k + 2 launches (each round with
+ * its own set-up for the steps left), waits for the stream after each and
+ * reads how far the run got, until max_steps steps are done, t_end is
+ * reached or a state is non-physical -- usually one round.  On a stream
+ * being captured it instead enqueues max_steps launches (enough whatever
+ * the guesses do) and does not wait.  Launches beyond the work done exit
+ * at once.
  * The shape set by lbrs_set_tile applies (strips of at most 64 - 2k columns;
  * automatic segments of at least 4 rows; 16 waves per workgroup run as 12,
  * as 8 with k >= 3 or PER_STEP speeds; alternate is ignored).
@@ -580,9 +591,12 @@ void lbrs_batch2d_destroy(lbrs_batch2d* b);
  * d_U0, the two population buffers (lbrs_query_sizes' f_bytes each), the
  * output d_U [K][ny][nx] and optionally d_state (5 device doubles: t,
  * completed steps, lattice speed of the last step, status, first
- * non-physical step or -1).  Asynchronous on hip_stream.  Every call on one
- * GPU shares that GPU's array: calls that overlap on one GPU (different
- * streams, threads) race; calls in one stream are ordered.  Parameters as
+ * non-physical step or -1).  Asynchronous on hip_stream (with PER_STEP
+ * speeds and steps_per_launch > 1 it enqueues the max_steps launches that
+ * suffice whatever the guesses, never the rounds of lbrs_step).  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams, threads) race; calls in one stream are ordered.
+ * Parameters as
  * lbrs_init, except that solid bodies (whose node codes would need a staging
  * buffer and more scratch than the array holds) are rejected: LBRS_E_INVAL.
  * LBRS_E_HIP if the array's device address cannot be found. */

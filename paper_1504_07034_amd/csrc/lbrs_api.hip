@@ -32,6 +32,8 @@ struct lbrs_ctx {
     int sbpc[17];        // resident scalar-step workgroups per CU, by waves per block
     unsigned short* codes;  // body node codes in the scratch area (null: no body)
     int fuse;            // 2D Euler: time steps per launch (1, or 2 to 4 fused)
+    bool rounds;         // fused PER_STEP calls may wait between rounds of launches
+    long long pair_enq;  // fused step launches enqueued since init (idle ones included)
     PairState* pst;      // record of the fused launches (scratch area, behind the time state)
     PredCand* cand;      // candidate list of the per-step prediction (scratch area), or null
     int pbpc[3][KMAX_STEPS + 1][17];  // resident fused-kernel workgroups per CU, by (plain,
@@ -194,6 +196,7 @@ static int ctx_setup(lbrs_ctx* c, const lbrs_params* p, const double* d_U0, doub
     c->pst = (PairState*)((char*)d_scratch + pair_offset());
     c->cand = fusable(p) ? (PredCand*)((char*)d_scratch + cand_offset()) : nullptr;
     c->fuse = 1;
+    c->rounds = true;
     c->stream = (hipStream_t)hip_stream;
     c->launches = 0;
     c->rows_per_tile = 0;
@@ -495,6 +498,27 @@ static Step1DArgs step1d_args(const lbrs_ctx* c, double t_end, int max_steps) {
     return a;
 }
 
+// One call's worth of fused launches: the set-up kernel (the call stops at
+// max_steps more steps) and nl launches, each followed by its prediction
+// launches with per-step speeds; the last one leaves an ordinary time state.
+static int step_fused(lbrs_ctx* c, int max_steps, double t_end, int nl) {
+    Pair2DArgs a = pair_args(c, t_end);
+    hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), max_steps,
+                                       c->stream);
+    if (e != hipSuccess) return LBRS_E_HIP;
+    const int mb = pair_max_blocks(c, false, a.kmax);
+    for (int s = 0; s < nl; ++s) {
+        a.launch = c->launches;
+        a.last = s == nl - 1;
+        e = launch_step2d_pair(a, pair_wpb(c, false, a.kmax), false, mb, c->stream);
+        ++c->pair_enq;
+        if (e == hipSuccess && a.cand) e = launch_pair_predict(a, c->stream);
+        if (e != hipSuccess) return LBRS_E_HIP;
+        ++c->launches;
+    }
+    return LBRS_OK;
+}
+
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
     if (!c || max_steps < 0 || isnan(t_end)) return LBRS_E_INVAL;
     if (max_steps == 0) return LBRS_OK;
@@ -514,25 +538,34 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         // Launches needed.  Per-step speeds: a launch advances at least one
         // step, except a bound-only pass or one whose guess is rejected, and
         // the launch after either of those advances at least two, so
-        // max_steps launches suffice.  Fixed speeds: every launch but the
-        // last advances kmax steps (a check that rolls back ends the run with
-        // a non-physical state) and the last one at least one.
-        Pair2DArgs a = pair_args(c, t_end);
-        const int nl = a.lam_mode == LAM_PER_STEP ? max_steps
-                                                  : (max_steps + a.kmax - 2) / a.kmax + 1;
-        hipError_t e = launch_pair_prepare(c->pst, c->st, (int)(c->launches & 1), max_steps,
-                                           c->stream);
-        if (e != hipSuccess) return LBRS_E_HIP;
-        const int mb = pair_max_blocks(c, false, a.kmax);
-        for (int s = 0; s < nl; ++s) {
-            a.launch = c->launches;
-            a.last = s == nl - 1;
-            e = launch_step2d_pair(a, pair_wpb(c, false, a.kmax), false, mb, c->stream);
-            // with per-step speeds, the prediction of the bound the next
-            // launch's second step needs
-            if (e == hipSuccess && a.cand) e = launch_pair_predict(a, c->stream);
-            if (e != hipSuccess) return LBRS_E_HIP;
-            ++c->launches;
+        // max_steps launches always suffice -- but most of them usually find
+        // the work done.  So, unless the stream is being captured, the call
+        // enqueues rounds of about max_steps/kmax launches (each round a
+        // call of its own for the steps left) and reads after each how far
+        // the run got.  Fixed speeds: every launch but the last advances
+        // kmax steps (a check that rolls back ends the run with a
+        // non-physical state) and the last one at least one.
+        const bool per_step = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess) return LBRS_E_HIP;
+        if (!per_step || !c->rounds || cs != hipStreamCaptureStatusNone) {
+            const int k = c->fuse;
+            return step_fused(c, max_steps, t_end, per_step ? max_steps : (max_steps + k - 2) / k + 1);
+        }
+        int left = max_steps;
+        while (left > 0) {
+            const int rc = step_fused(c, left, t_end, (left + c->fuse - 1) / c->fuse + 2);
+            if (rc) return rc;
+            if (hipStreamSynchronize(c->stream) != hipSuccess) return LBRS_E_HIP;
+            DevState h;
+            long long n_limit = 0;
+            if (hipMemcpy(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(&n_limit, &c->pst->n_limit, sizeof(n_limit), hipMemcpyDeviceToHost) !=
+                    hipSuccess)
+                return LBRS_E_HIP;
+            const Slot& s = h.s[c->launches & 1];
+            if (h.status || !(s.t < t_end) || s.n >= n_limit) break;
+            left = (int)(n_limit - s.n);
         }
         return LBRS_OK;
     }
@@ -596,7 +629,8 @@ int lbrs_pair_stats(lbrs_ctx* c, long long* counts, int n) {
     unsigned long long h[PST_COUNT];
     if (hipMemcpy(h, c->pst->stat, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
         return LBRS_E_HIP;
-    for (int i = 0; i < n; ++i) counts[i] = i < PST_COUNT ? (long long)h[i] : 0;
+    for (int i = 0; i < n; ++i)
+        counts[i] = i < PST_COUNT ? (long long)h[i] : i == PST_COUNT ? c->pair_enq : 0;
     return LBRS_OK;
 }
 
@@ -775,6 +809,7 @@ static int step_tape_fused(lbrs_ctx* c, int len, double* d_tape) {
             a.tape[i] = d_tape + (slot < len ? slot : len - 1) * ucount;
         }
         e = launch_step2d_pair(a, pair_wpb(c, true, k), true, mb, c->stream);
+        ++c->pair_enq;
         if (e != hipSuccess) return LBRS_E_HIP;
         ++c->launches;
     }
@@ -798,6 +833,7 @@ int lbrs_step_tape2(lbrs_ctx* c, double* d_Utape_n, double* d_Utape_n1) {
         a.launch = c->launches;
         a.last = k == 1;
         e = launch_step2d_pair(a, pair_wpb(c, true, 2), true, mb, c->stream);
+        ++c->pair_enq;
         if (e != hipSuccess) return LBRS_E_HIP;
         ++c->launches;
     }
@@ -823,6 +859,7 @@ int lbrs_step_tapes(lbrs_ctx* c, int k, double* d_Utape) {
         a.launch = c->launches;
         a.last = j == 1;
         e = launch_step2d_pair(a, pair_wpb(c, true, k), true, mb, c->stream);
+        ++c->pair_enq;
         if (e != hipSuccess) return LBRS_E_HIP;
         ++c->launches;
     }
@@ -992,6 +1029,7 @@ int lbrs_run_noalloc(const lbrs_params* p, const double* d_U0, double* d_f0, dou
     lbrs_ctx c;  // on the stack: nothing is allocated
     int rc = ctx_setup(&c, p, d_U0, d_f0, d_f1, sp, hip_stream, false);
     if (rc) return rc;
+    c.rounds = false;  // one enqueue, no waits
     if (steps_per_launch >= 2 && (rc = lbrs_set_fusion(&c, steps_per_launch))) return rc;
     if ((rc = lbrs_step(&c, max_steps, t_end))) return rc;
     if ((rc = lbrs_moments(&c, d_U))) return rc;

@@ -521,7 +521,7 @@ class Sim:
 
     PAIR_STATS = ("pairs", "rejected", "bound_only", "single", "predicted", "pred_hit",
                   "pred_miss", "evaluated", "pred_none", "listed", "overflow", "steps3",
-                  "steps4")
+                  "steps4", "enqueued")
 
     def pair_stats(self) -> dict:
         """Counters of the fused launches since init (lbrs_pair_stats)."""

@@ -169,6 +169,9 @@ def test_riemann_to_end_large(n, fuse):
         assert steps == ref.nsteps
         assert stats["steps3"] == 0 or fuse >= 3
         assert stats["steps4"] == 0 or fuse >= 4
+        # launches that did work are among those enqueued
+        active = stats["pairs"] + stats["rejected"] + stats["bound_only"] + stats["single"]
+        assert active <= stats["enqueued"]
 
 
 @pytest.mark.parametrize("sides", [(1, 1, 1, 1), (1, 1, 0, 0), (0, 0, 1, 1)])
