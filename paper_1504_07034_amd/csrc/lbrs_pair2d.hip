@@ -265,11 +265,17 @@ __device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, in
         }
     };
 
+    // Lockstep with the workgroup's neighbouring strips (equal trip counts
+    // and the same rows, so every wave meets the same barriers): a barrier
+    // before every row, or every second row with four steps per launch, where
+    // the longer rows make the looser lockstep faster while the strips still
+    // share the halo columns' reads in cache (with no barrier at all the
+    // reads from HBM triple).
+    constexpr int ROW_SYNC = K >= 4 ? 2 : 1;
     double cur[16], nxt[16], Uc[4];
     load_row(nxt, g.fin, g.ps, g.rs, map_index(y0 - K, ny, py), xl);
     for (int r = y0 - K; r <= y1 + K - 1; ++r) {
-        // lockstep with the workgroup's neighbouring strips (equal trip counts)
-        if (WPB > 1) __builtin_amdgcn_s_barrier();
+        if (WPB > 1 && (r & (ROW_SYNC - 1)) == 0) __builtin_amdgcn_s_barrier();
 #pragma unroll
         for (int p = 0; p < 16; ++p) cur[p] = nxt[p];
         // row r+1 in flight while row r is computed
