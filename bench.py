@@ -39,8 +39,8 @@ SINGLE_SOURCES = ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 # the window's figure is that times the share of the enqueued launches that
 # did work (per-step lattice speeds: one launch per step, of which those past
 # the steps done exit at once, moving nothing).
-PAIR_TRAFFIC_BYTES = {"4,8": 4.474e9, "2,8": 4.431e9}
-PAIR_TRAFFIC_SOURCE_HASH = "ce933863a43904a3"
+PAIR_TRAFFIC_BYTES = {"4,8": 4.486e9, "2,8": 4.429e9}
+PAIR_TRAFFIC_SOURCE_HASH = "1e6e5c123254d3a9"
 PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 
 

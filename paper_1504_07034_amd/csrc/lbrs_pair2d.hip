@@ -163,8 +163,9 @@ __device__ inline void tape_row(double* tape, long long tape_ps, int nx, int j, 
 // tile's cells of f^{n+s+1}; TAPE stores U^{n+s} of every step's input;
 // CAND lists candidates from the last step's output (see PredCand).  One
 // copy of the step code serves every row and step of a kernel's path, so
-// all cells round alike.
-template <int WPB, int K, bool TAPE, bool CAND = false, bool LPB = false>
+// all cells round alike.  EARLY: a wave sends the next row's loads before it
+// waits at the workgroup barrier (else after).
+template <int WPB, int K, bool TAPE, bool CAND = false, bool LPB = false, bool EARLY = true>
 __device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, int y1, int lane,
                                         double (&lm)[KMAX_STEPS], bool (&bad)[KMAX_STEPS],
                                         bool store = true, double* pbl = nullptr) {
@@ -267,19 +268,24 @@ __device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, in
 
     // Lockstep with the workgroup's neighbouring strips (equal trip counts
     // and the same rows, so every wave meets the same barriers): a barrier
-    // before every row, or every second row with four steps per launch, where
+    // at every row, or every second row with four steps per launch, where
     // the longer rows make the looser lockstep faster while the strips still
     // share the halo columns' reads in cache (with no barrier at all the
-    // reads from HBM triple).
+    // reads from HBM triple).  The barrier carries no memory order (the
+    // waves exchange nothing), so a wave's next-row loads can go out before
+    // it waits there: faster for every form measured but the batch's three
+    // steps, which passes EARLY = false.
     constexpr int ROW_SYNC = K >= 4 ? 2 : 1;
     double cur[16], nxt[16], Uc[4];
     load_row(nxt, g.fin, g.ps, g.rs, map_index(y0 - K, ny, py), xl);
     for (int r = y0 - K; r <= y1 + K - 1; ++r) {
-        if (WPB > 1 && (r & (ROW_SYNC - 1)) == 0) __builtin_amdgcn_s_barrier();
+        const bool sync = WPB > 1 && (r & (ROW_SYNC - 1)) == 0;
+        if (!EARLY && sync) __builtin_amdgcn_s_barrier();
 #pragma unroll
         for (int p = 0; p < 16; ++p) cur[p] = nxt[p];
         // row r+1 in flight while row r is computed
         load_row(nxt, g.fin, g.ps, g.rs, map_index(r + 1, ny, py), xl);
+        if (EARLY && sync) __builtin_amdgcn_s_barrier();
         moments_d2q4(cur, Uc);
         if (TAPE) tape_row(g.tape[0], g.tape_ps, nx, r, y0, y1, voff, Uc);  // U^n of row r
 #pragma unroll
@@ -1052,7 +1058,7 @@ __global__ __launch_bounds__(64 * WPB) void step2d_batch_pair(Batch2DArgs a) {
             lm[i] = 0.0;
             bad[i] = false;
         }
-        march_k<WPB, K, TAPE, false, LPB>(g, strip, y0, y1, lane, lm, bad, true, pbl);
+        march_k<WPB, K, TAPE, false, LPB, K != 3>(g, strip, y0, y1, lane, lm, bad, true, pbl);
         bool any_bad = false;
 #pragma unroll
         for (int i = 0; i < K; ++i) any_bad = any_bad || bad[i];
