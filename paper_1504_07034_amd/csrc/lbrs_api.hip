@@ -539,10 +539,12 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         // step, except a bound-only pass or one whose guess is rejected, and
         // the launch after either of those advances at least two, so
         // max_steps launches always suffice -- but most of them usually find
-        // the work done.  So, unless the stream is being captured, the call
+        // the work done.  So, unless the stream is being captured or the
+        // context may not wait (the no-allocation entry point), the call
         // enqueues rounds of about max_steps/kmax launches (each round a
-        // call of its own for the steps left) and reads after each how far
-        // the run got.  Fixed speeds: every launch but the last advances
+        // call of its own for the steps left; at least three launches, so
+        // every round advances) and reads after each how far the run got.
+        // Fixed speeds: every launch but the last advances
         // kmax steps (a check that rolls back ends the run with a
         // non-physical state) and the last one at least one.
         const bool per_step = c->P.lambda_mode == LBRS_LAMBDA_PER_STEP;
