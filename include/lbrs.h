@@ -228,7 +228,9 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
  * there).
  * Asynchronous, except with fused launches and PER_STEP speeds on a stream
  * that is not being captured: the call then waits for the stream (see
- * lbrs_set_fusion). */
+ * lbrs_set_fusion).  A graph captured around single-step calls replays
+ * consistently when max_steps is a multiple of six (one launch per step; see
+ * lbrs_set_fusion for fused calls). */
 int lbrs_step(lbrs_ctx* c, int max_steps, double t_end);
 
 /* Wait for the stream and report the current time, completed step count,
@@ -429,8 +431,13 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * reads how far the run got, until max_steps steps are done, t_end is
  * reached or a state is non-physical -- usually one round.  On a stream
  * being captured it instead enqueues max_steps launches (enough whatever
- * the guesses do) and does not wait.  Launches beyond the work done exit
- * at once.
+ * the guesses do; with a fixed speed those above), rounded up to a multiple
+ * of six, and does not wait: the time state rotates its slots with the
+ * launch count modulo six, so the captured graph can be replayed any number
+ * of times, each replay continuing the run by up to max_steps steps from
+ * where the last one left it, and the context's calls between replays see
+ * the state the last replay left.  Launches beyond the work done exit at
+ * once.
  * The shape set by lbrs_set_tile applies (strips of at most 64 - 2k columns;
  * automatic segments of at least 4 rows; 16 waves per workgroup run as 12,
  * as 8 with k >= 3 or PER_STEP speeds; alternate is ignored).

@@ -552,7 +552,14 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
         if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess) return LBRS_E_HIP;
         if (!per_step || !c->rounds || cs != hipStreamCaptureStatusNone) {
             const int k = c->fuse;
-            return step_fused(c, max_steps, t_end, per_step ? max_steps : (max_steps + k - 2) / k + 1);
+            int nl = per_step ? max_steps : (max_steps + k - 2) / k + 1;
+            // A graph replays the launches with the launch numbers they were
+            // captured with, and the time state and reductions rotate their
+            // slots with the launch number modulo six: a multiple of six
+            // launches leaves the slots where the call found them, so every
+            // replay continues from the state the last one left.
+            if (cs != hipStreamCaptureStatusNone) nl = (nl + 5) / 6 * 6;
+            return step_fused(c, max_steps, t_end, nl);
         }
         int left = max_steps;
         while (left > 0) {

@@ -250,6 +250,56 @@ def test_step_counts_per_call(chunks, lam_mode, fuse):
     assert max_abs(U, ref.U) <= TOL
 
 
+@pytest.mark.parametrize("lam_mode", [0, 1])
+@FUSE
+def test_fused_calls_replayed_from_a_graph(lam_mode, fuse):
+    """A fused lbrs_step call captured in a HIP graph (torch.cuda.graph on the
+    context's own stream) enqueues its launches without waiting, rounded up
+    to a multiple of six, so each replay continues the run by the call's
+    steps from where the last one left it.  One eager call first, then the
+    capture (which runs nothing: the state stays at the eager call's), then
+    three replays with eager work and synchronisation between them, each
+    against the same calls made eagerly on another context: step count,
+    time, lattice speed and U bit for bit, and the last one against the
+    oracle."""
+    w = _riemann_rect(130, 90)
+    first, k = 3, 7
+    ref = _fused(w, omega=1.2, lam_mode=lam_mode, fuse=fuse)
+    ref.step(first)
+    want = []
+    for _ in range(3):
+        ref.step(k)
+        want.append((ref.state(), ref.moments().cpu().numpy()))
+    ref.close()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        sim = _fused(w, omega=1.2, lam_mode=lam_mode, fuse=fuse)
+        sim.step(first)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            sim.step(k)
+        torch.cuda.synchronize()
+        st = sim.state()
+        assert st["rc"] == 0 and st["nsteps"] == first
+        for i in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            st = sim.state()
+            U = sim.moments().cpu().numpy()
+            torch.cuda.synchronize()
+            ws, wU = want[i]
+            assert st["rc"] == 0 and st["nsteps"] == ws["nsteps"] == first + (i + 1) * k
+            assert st["t"] == ws["t"] and st["lambda"] == ws["lambda"]
+            assert max_abs(U, wU) == 0.0, i
+        sim.close()
+    P = oracle_problem(w, omega=1.2, lam_mode=lam_mode)
+    o = oracle.run(P, oracle.prim_to_cons(P, w.W), max_steps=first + 3 * k)
+    assert o.nsteps == first + 3 * k
+    assert st["t"] == pytest.approx(o.t, rel=1e-12, abs=0)
+    assert max_abs(U, o.U) <= TOL
+
+
 @FUSE
 def test_lattice_speed_sequence(fuse):
     """After every call (of 3 to 14 steps) the reported lattice speed and time
