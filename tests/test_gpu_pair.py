@@ -251,19 +251,19 @@ def test_step_counts_per_call(chunks, lam_mode, fuse):
 
 
 @pytest.mark.parametrize("lam_mode", [0, 1])
-@FUSE
+@pytest.mark.parametrize("fuse", [1, 2, 3, 4])
 def test_fused_calls_replayed_from_a_graph(lam_mode, fuse):
     """A fused lbrs_step call captured in a HIP graph (torch.cuda.graph on the
     context's own stream) enqueues its launches without waiting, rounded up
     to a multiple of six, so each replay continues the run by the call's
-    steps from where the last one left it.  One eager call first, then the
-    capture (which runs nothing: the state stays at the eager call's), then
-    three replays with eager work and synchronisation between them, each
-    against the same calls made eagerly on another context: step count,
-    time, lattice speed and U bit for bit, and the last one against the
-    oracle."""
+    steps from where the last one left it (single steps: a call of six, one
+    launch each).  One eager call first, then the capture (which runs
+    nothing: the state stays at the eager call's), then three replays with
+    eager work and synchronisation between them, each against the same calls
+    made eagerly on another context: step count, time, lattice speed and U
+    bit for bit, and the last one against the oracle."""
     w = _riemann_rect(130, 90)
-    first, k = 3, 7
+    first, k = 3, (6 if fuse == 1 else 7)
     ref = _fused(w, omega=1.2, lam_mode=lam_mode, fuse=fuse)
     ref.step(first)
     want = []
