@@ -423,7 +423,8 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * count, every lattice speed, the status, fail_step, the reported state after
  * each lbrs_step call and the populations are those of single steps, bit for
  * bit.  lbrs_step(c, max_steps, t_end) then enqueues a one-thread set-up
- * kernel and, with a fixed speed, (max_steps - 2)/k + 2 launches; with
+ * kernel and, with a fixed speed, (max_steps + k - 2)/k + 1 launches
+ * (integer division); with
  * PER_STEP speeds each launch is followed by the prediction kernels (one per
  * guessed step), and a launch whose guess was wrong does no step, so the
  * call enqueues rounds of about max_steps/k + 2 launches (each round with
