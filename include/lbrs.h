@@ -427,10 +427,10 @@ int lbrs_set_tile(lbrs_ctx* c, int rows_per_tile, int waves_per_block, int alter
  * (integer division); with
  * PER_STEP speeds each launch is followed by the prediction kernels (one per
  * guessed step), and a launch whose guess was wrong does no step, so the
- * call enqueues rounds of about max_steps/k + 2 launches (each round with
- * its own set-up for the steps left), waits for the stream after each and
- * reads how far the run got, until max_steps steps are done, t_end is
- * reached or a state is non-physical -- usually one round.  On a stream
+ * call enqueues rounds of about max_steps/k + 2 launches, at most 512 (each
+ * round with its own set-up for the steps left), waits for the stream after
+ * each and reads how far the run got, until max_steps steps are done, t_end
+ * is reached or a state is non-physical -- usually one round.  On a stream
  * being captured it instead enqueues max_steps launches (enough whatever
  * the guesses do; with a fixed speed those above), rounded up to a multiple
  * of six, and does not wait: the time state rotates its slots with the

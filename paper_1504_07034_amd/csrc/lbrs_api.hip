@@ -561,9 +561,13 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
             if (cs != hipStreamCaptureStatusNone) nl = (nl + 5) / 6 * 6;
             return step_fused(c, max_steps, t_end, nl);
         }
+        // at most ROUND_MAX launches a round, so that a call of far more
+        // steps than t_end leaves enqueues few launches past the work
+        constexpr int ROUND_MAX = 512;
         int left = max_steps;
         while (left > 0) {
-            const int rc = step_fused(c, left, t_end, (left + c->fuse - 1) / c->fuse + 2);
+            const int want = (left + c->fuse - 1) / c->fuse + 2;
+            const int rc = step_fused(c, left, t_end, want < ROUND_MAX ? want : ROUND_MAX);
             if (rc) return rc;
             if (hipStreamSynchronize(c->stream) != hipSuccess) return LBRS_E_HIP;
             DevState h;

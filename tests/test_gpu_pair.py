@@ -250,6 +250,27 @@ def test_step_counts_per_call(chunks, lam_mode, fuse):
     assert max_abs(U, ref.U) <= TOL
 
 
+@FUSE
+def test_call_far_past_t_end(fuse):
+    """A call of far more steps than the run to t_end takes (100000 against a
+    few dozen) stops at t_end with the oracle's state, and enqueues at most
+    one round of 512 launches beyond those that did work."""
+    w = _riemann_rect(130, 90)
+    P = oracle_problem(w)
+    ref = _oracle_run(P, w, t_end=w.t_end)
+    assert ref.status == 0 and ref.t == w.t_end
+    sim = _fused(w, fuse=fuse)
+    sim.step(100000, w.t_end)
+    st = sim.state()
+    stats = sim.pair_stats()
+    U = sim.moments().cpu().numpy()
+    sim.close()
+    assert st["rc"] == 0 and st["nsteps"] == ref.nsteps and st["t"] == ref.t
+    assert max_abs(U, ref.U) <= TOL
+    active = stats["pairs"] + stats["rejected"] + stats["bound_only"] + stats["single"]
+    assert active <= stats["enqueued"] <= active + 512, stats
+
+
 @pytest.mark.parametrize("lam_mode", [0, 1])
 @pytest.mark.parametrize("fuse", [1, 2, 3, 4])
 def test_fused_calls_replayed_from_a_graph(lam_mode, fuse):
