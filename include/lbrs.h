@@ -16,7 +16,9 @@
  * --------------------------------
  *  * All arithmetic is IEEE FP64.  All large buffers are DEVICE pointers that
  *    the caller allocates and owns; the library borrows them until
- *    lbrs_destroy().  The library allocates only its small host-side context.
+ *    lbrs_destroy().  The library allocates only its small host-side context
+ *    (with, for a context whose fused calls read state back, a pinned host
+ *    buffer of under 1 KiB; see lbrs_init).
  *  * Layouts (C order, x fastest):
  *      U  (conserved)  : K planes [K][ny][nx]; K = 3 in 1D (rho, rho u, rho E),
  *                        K = 4 in 2D (rho, rho u, rho v, rho E), K = 1 for a
@@ -37,8 +39,9 @@
  *  * Grid: cell-centred, dx = (x1-x0)/nx, dy = (y1-y0)/ny; 2D requires
  *    dx == dy (the D2Q4 populations hop along cell diagonals).
  *  * Every call that enqueues work does so on the context's HIP stream and
- *    returns without synchronising, except lbrs_get_state() which waits for
- *    the stream.
+ *    returns without synchronising, except those whose description says
+ *    that they wait for the stream (lbrs_get_state(), the counters and
+ *    reports, fused PER_STEP lbrs_step() calls, a body's lbrs_init(), ...).
  *  * Return codes: LBRS_OK (0) or a negative lbrs_status; lbrs_strerror()
  *    names them.  An invalid argument is rejected before anything is
  *    enqueued.  A non-physical state (rho <= 0, p <= 0 or a non-finite value;
@@ -213,7 +216,10 @@ int lbrs_prim_to_cons(const lbrs_params* p, const double* d_W, double* d_U, void
  * next lbrs_get_state() with step index 0.  With a body (p->solid) the node
  * codes are built on the host, copied into d_scratch and the stream is
  * synchronised before the call returns (an inadmissible mask: LBRS_E_INVAL,
- * nothing enqueued). */
+ * nothing enqueued).  A 2D Euler context with PER_STEP speeds and no body or
+ * DIRICHLET side also gets a pinned host buffer of under 1 KiB (hipHostMalloc)
+ * through which fused calls read the state back between their rounds of
+ * launches (see lbrs_set_fusion); lbrs_destroy frees it. */
 int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* d_f0,
               double* d_f1, void* d_scratch, void* hip_stream);
 
@@ -613,6 +619,10 @@ int lbrs_run_noalloc(const lbrs_params* p, const double* d_U0, double* d_f0, dou
                      double* d_state, void* hip_stream);
 
 const char* lbrs_strerror(int code);
+
+/* Free the context (and its pinned host buffer, if lbrs_init made one); the
+ * caller's device buffers stay the caller's.  Work enqueued on its stream
+ * should have finished. */
 void lbrs_destroy(lbrs_ctx* c);
 
 #ifdef __cplusplus

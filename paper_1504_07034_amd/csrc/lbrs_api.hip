@@ -2,6 +2,7 @@
 // the context, and the launch sequence of every call.  No call allocates
 // device memory; all large buffers are the caller's.
 #include <math.h>
+#include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -34,6 +35,8 @@ struct lbrs_ctx {
     int fuse;            // 2D Euler: time steps per launch (1, or 2 to 4 fused)
     bool rounds;         // fused PER_STEP calls may wait between rounds of launches
     long long pair_enq;  // fused step launches enqueued since init (idle ones included)
+    void* hst;           // pinned host copy of the time state and the call's step limit
+                         // (fused PER_STEP rounds), or null
     PairState* pst;      // record of the fused launches (scratch area, behind the time state)
     PredCand* cand;      // candidate list of the per-step prediction (scratch area), or null
     int pbpc[3][KMAX_STEPS + 1][17];  // resident fused-kernel workgroups per CU, by (plain,
@@ -75,6 +78,10 @@ static bool fusable(const lbrs_params* p) {
     for (int s = 0; s < 4; ++s)
         if (p->bc[s] == LBRS_BC_DIRICHLET) return false;
     return true;
+}
+// The time state and the record's step limit, contiguous in the scratch area.
+static size_t round_state_bytes() {
+    return pair_offset() + offsetof(PairState, n_limit) + sizeof(long long);
 }
 static size_t codes_offset(const lbrs_params* p) {
     return cand_offset() + (fusable(p) ? round256(sizeof(PredCand) * (size_t)PRED_CAP) : 0);
@@ -254,6 +261,11 @@ int lbrs_init(lbrs_ctx** out, const lbrs_params* p, const double* d_U0, double* 
         free(c);
         return rc;
     }
+    // the rounds of fused PER_STEP calls read the time state and the step
+    // limit back through one pinned copy (else two blocking ones)
+    if (fusable(p) && p->lambda_mode == LBRS_LAMBDA_PER_STEP &&
+        hipHostMalloc(&c->hst, round_state_bytes(), hipHostMallocDefault) != hipSuccess)
+        c->hst = nullptr;
     *out = c;
     return LBRS_OK;
 }
@@ -569,13 +581,23 @@ int lbrs_step(lbrs_ctx* c, int max_steps, double t_end) {
             const int want = (left + c->fuse - 1) / c->fuse + 2;
             const int rc = step_fused(c, left, t_end, want < ROUND_MAX ? want : ROUND_MAX);
             if (rc) return rc;
-            if (hipStreamSynchronize(c->stream) != hipSuccess) return LBRS_E_HIP;
             DevState h;
             long long n_limit = 0;
-            if (hipMemcpy(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(&n_limit, &c->pst->n_limit, sizeof(n_limit), hipMemcpyDeviceToHost) !=
-                    hipSuccess)
+            if (c->hst) {
+                // one copy behind the round's last kernel, then one wait
+                if (hipMemcpyAsync(c->hst, c->st, round_state_bytes(), hipMemcpyDeviceToHost,
+                                   c->stream) != hipSuccess ||
+                    hipStreamSynchronize(c->stream) != hipSuccess)
+                    return LBRS_E_HIP;
+                memcpy(&h, c->hst, sizeof(DevState));
+                memcpy(&n_limit, (const char*)c->hst + pair_offset() + offsetof(PairState, n_limit),
+                       sizeof(n_limit));
+            } else if (hipStreamSynchronize(c->stream) != hipSuccess ||
+                       hipMemcpy(&h, c->st, sizeof(DevState), hipMemcpyDeviceToHost) != hipSuccess ||
+                       hipMemcpy(&n_limit, &c->pst->n_limit, sizeof(n_limit),
+                                 hipMemcpyDeviceToHost) != hipSuccess) {
                 return LBRS_E_HIP;
+            }
             const Slot& s = h.s[c->launches & 1];
             if (h.status || !(s.t < t_end) || s.n >= n_limit) break;
             left = (int)(n_limit - s.n);
@@ -1064,6 +1086,9 @@ const char* lbrs_strerror(int code) {
     }
 }
 
-void lbrs_destroy(lbrs_ctx* c) { free(c); }
+void lbrs_destroy(lbrs_ctx* c) {
+    if (c && c->hst) (void)hipHostFree(c->hst);
+    free(c);
+}
 
 }  // extern "C"
