@@ -31,16 +31,16 @@ METRIC = "MLUPS + % HBM roofline: plain vs batched vs adjoint step, 1 MI355X"
 # (automatic row segments, row-interleaved layout), valid for the kernel code
 # they were taken on (profiles/step2d_d2q4_riemann4096.md); null once the code
 # changes or for a shape not profiled.
-TRAFFIC_BYTES = {"16,0": 4.431e9}
-TRAFFIC_SOURCE_HASH = "905b216eb87675aa"
+TRAFFIC_BYTES = {"16,0": 4.430e9}
+TRAFFIC_SOURCE_HASH = "c1666d2a85a1b74c"
 SINGLE_SOURCES = ("lbrs_step2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 # The same for the fused multi-step kernel, by "steps_per_launch,waves_per_block":
 # HBM bytes per launch that does work (profiles/step2d_pair_riemann4096.md);
 # the window's figure is that times the share of the enqueued launches that
 # did work (per-step lattice speeds: one launch per step, of which those past
 # the steps done exit at once, moving nothing).
-PAIR_TRAFFIC_BYTES = {"4,8": 4.486e9, "2,8": 4.429e9}
-PAIR_TRAFFIC_SOURCE_HASH = "1e6e5c123254d3a9"
+PAIR_TRAFFIC_BYTES = {"4,8": 4.498e9, "2,8": 4.428e9}
+PAIR_TRAFFIC_SOURCE_HASH = "317c0476b9c364cb"
 PAIR_SOURCES = ("lbrs_pair2d.hip", "lbrs_device.hpp", "lbrs_rowops.hpp")
 
 

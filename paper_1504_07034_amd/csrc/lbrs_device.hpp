@@ -216,12 +216,17 @@ __device__ inline void moments_d2q4(const double f[16], double U[4]) {
 // Local bound max(|u+v|, |u+v +- sqrt2 a|, |u-v|, |u-v -+ sqrt2 a|), which for
 // a >= 0 is max(|u+v|, |u-v|) + sqrt2 a exactly.  Returns false (and 0) for a
 // non-physical state.
+// An admissible state: positive density and pressure, every value finite.
+__device__ inline bool admissible_d2q4(const double U[4], const Euler2& e) {
+    return (U[0] > 0.0) && (e.p > 0.0) && isfinite(U[0]) && isfinite(U[1]) && isfinite(U[2]) &&
+           isfinite(U[3]) && isfinite(e.p);
+}
+
 __device__ inline bool bound_d2q4(const double U[4], double gamma, double* lam) {
 #pragma clang fp contract(off)
     double gm1 = gamma - 1.0;
     Euler2 e = euler2(U, gm1);
-    bool ok = (U[0] > 0.0) && (e.p > 0.0) && isfinite(U[0]) && isfinite(U[1]) &&
-              isfinite(U[2]) && isfinite(U[3]) && isfinite(e.p);
+    bool ok = admissible_d2q4(U, e);
     double a = sqrt(gamma * e.p / U[0]);
     double l = fma_rn(1.4142135623730951, a, fmax(fabs(e.u + e.v), fabs(e.u - e.v)));
     *lam = ok ? l : 0.0;

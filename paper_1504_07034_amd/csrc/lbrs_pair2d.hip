@@ -364,7 +364,16 @@ __device__ __forceinline__ void march_k(const PairGeom& g, int strip, int y0, in
             double U1[4], l1;
             moments_d2q4(gq, U1);
             const bool own = out_lane && o >= y0 && o < y1;
-            const bool ok = bound_d2q4(U1, g.gamma, &l1);
+            // the bounds are needed with per-step speeds only, which always
+            // run the form that lists candidates; the others test
+            // admissibility alone (no square root, one division fewer)
+            bool ok;
+            if constexpr (CAND) {
+                ok = bound_d2q4(U1, g.gamma, &l1);
+            } else {
+                ok = admissible_d2q4(U1, euler2(U1, gm1));
+                l1 = 0.0;
+            }
             bad[st] |= own && !ok;
             lm[st] = fmax(lm[st], own ? l1 : 0.0);
             if (st == K - 1) {
@@ -1129,7 +1138,9 @@ static hipError_t launch_pair_wk(const Pair2DArgs& a, bool tape, int max_blocks,
     int nblocks = (a.ntiles + WPB - 1) / WPB;
     if (max_blocks > 0 && nblocks > max_blocks) nblocks = max_blocks;
     // per-step speeds with a candidate list: the form that lists candidates
+    // (the only form that reduces the bounds per-step speeds need)
     const bool cand = a.cand != nullptr && a.lam_mode == LAM_PER_STEP && !tape;
+    if (a.lam_mode == LAM_PER_STEP && !cand) return hipErrorInvalidValue;
     if (cand)
         hipLaunchKernelGGL((step2d_pair<WPB, false, true, KM>), dim3(nblocks), dim3(64 * WPB), 0, s,
                            a);
